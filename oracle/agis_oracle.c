@@ -1,0 +1,720 @@
+/*
+ * AGIS CPU oracle -- TEST INFRASTRUCTURE ONLY (see agis_oracle.h).
+ *
+ * Plain double-precision C, one formula per paper equation, in the order the
+ * paper gives them.  No blocking, fusion or algebraic short-cuts beyond what
+ * the equations state; loops over independent sources / segments may run in
+ * parallel (results do not depend on the thread count).
+ *
+ * Citations name sections, equation labels and algorithms of Lindegren et
+ * al. (2012), "The astrometric core solution for the Gaia mission".
+ */
+#include "agis_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define M_ORDER 4
+
+/* ========================================================================
+ * Appendix A.1, quaternion algebra: product (eq:quatmult), conjugate
+ * (eq:quatconj), inverse (eq:quatinv).  Quaternions are {x, y, z, w}.
+ * ====================================================================== */
+void orc_qmul(const double a[4], const double b[4], double out[4]) {
+    double r[4];
+    r[0] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+    r[1] = -a[0] * b[2] + a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+    r[2] = a[0] * b[1] - a[1] * b[0] + a[2] * b[3] + a[3] * b[2];
+    r[3] = -a[0] * b[0] - a[1] * b[1] - a[2] * b[2] + a[3] * b[3];
+    memcpy(out, r, sizeof r);
+}
+
+void orc_qconj(const double a[4], double out[4]) {
+    out[0] = -a[0]; out[1] = -a[1]; out[2] = -a[2]; out[3] = a[3];
+}
+
+void orc_qinv(const double a[4], double out[4]) {
+    double n2 = a[0] * a[0] + a[1] * a[1] + a[2] * a[2] + a[3] * a[3];
+    out[0] = -a[0] / n2; out[1] = -a[1] / n2; out[2] = -a[2] / n2; out[3] = a[3] / n2;
+}
+
+/* Frame rotation (eq:quatframerot): {out, 0} = q^-1 {v, 0} q. */
+void orc_frame_rotate(const double q[4], const double v[3], double out[3]) {
+    double qi[4], vq[4] = {v[0], v[1], v[2], 0.0}, t[4], r[4];
+    orc_qinv(q, qi);
+    orc_qmul(qi, vq, t);
+    orc_qmul(t, q, r);
+    out[0] = r[0]; out[1] = r[1]; out[2] = r[2];
+}
+
+/* Vector rotation (eq:quatvecrot): {out, 0} = q {v, 0} q^-1. */
+void orc_vector_rotate(const double q[4], const double v[3], double out[3]) {
+    double qi[4], vq[4] = {v[0], v[1], v[2], 0.0}, t[4], r[4];
+    orc_qinv(q, qi);
+    orc_qmul(q, vq, t);
+    orc_qmul(t, qi, r);
+    out[0] = r[0]; out[1] = r[1]; out[2] = r[2];
+}
+
+/* Attitude matrix from a unit quaternion (eq:quat2mat), row-major. */
+void orc_quat2mat(const double q[4], double A[9]) {
+    double x = q[0], y = q[1], z = q[2], w = q[3];
+    A[0] = 1.0 - 2.0 * (y * y + z * z); A[1] = 2.0 * (x * y + z * w);       A[2] = 2.0 * (x * z - y * w);
+    A[3] = 2.0 * (x * y - z * w);       A[4] = 1.0 - 2.0 * (x * x + z * z); A[5] = 2.0 * (y * z + x * w);
+    A[6] = 2.0 * (x * z + y * w);       A[7] = 2.0 * (y * z - x * w);       A[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+/* Rotation quaternion Q(phi) of a rotation vector (eq:qrot). */
+void orc_qrot(const double phi[3], double out[4]) {
+    double ang = sqrt(phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2]);
+    if (ang > 0.0) {
+        double s = sin(0.5 * ang);
+        out[0] = phi[0] / ang * s; out[1] = phi[1] / ang * s; out[2] = phi[2] / ang * s;
+        out[3] = cos(0.5 * ang);
+    } else {
+        out[0] = 0.0; out[1] = 0.0; out[2] = 0.0; out[3] = 1.0;
+    }
+}
+
+/* ========================================================================
+ * Appendix B: left index (tau_l <= t < tau_{l+1}, restricted to the spline
+ * interval [tau_{M-1}, tau_N]; t = tau_N belongs to the last interval) and
+ * de Boor's Algorithm B1 for the M = 4 non-zero B-splines.
+ * ====================================================================== */
+int64_t orc_left_index(const double* knots, int64_t n_knots, double t) {
+    int64_t N = n_knots - M_ORDER;
+    int64_t lo = M_ORDER - 1, hi = N - 1;       /* answer in [lo, hi] */
+    if (t >= knots[N]) return N - 1;
+    if (t <= knots[lo]) return lo;
+    while (lo < hi) {                            /* largest l with tau_l <= t */
+        int64_t mid = (lo + hi + 1) / 2;
+        if (knots[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+void orc_bspline(const double* knots, int64_t ell, double t, double b[4]) {
+    double Rv[M_ORDER], Lv[M_ORDER];
+    b[0] = 1.0;
+    for (int i = 0; i <= M_ORDER - 2; ++i) {
+        Rv[i] = knots[ell + i + 1] - t;
+        Lv[i] = t - knots[ell - i];
+        double s = 0.0;
+        for (int j = 0; j <= i; ++j) {
+            double u = b[j] / (Rv[j] + Lv[i - j]);
+            b[j] = s + Rv[j] * u;
+            s = Lv[i - j] * u;
+        }
+        b[i + 1] = s;
+    }
+}
+
+/* ========================================================================
+ * Appendix C: Algorithms C1 (modified Cholesky for semidefinite matrices,
+ * with rank-defect count d), C2 and C3.  Dense row-major storage.
+ * ====================================================================== */
+int orc_chol_c1(double* U, int n) {
+    int d = 0;
+    for (int j = 0; j < n; ++j) {
+        for (int i = 0; i <= j; ++i) {
+            double s = 0.0;
+            for (int k = 0; k < i; ++k) s += U[k * n + i] * U[k * n + j];
+            if (i < j) {
+                if (U[i * n + i] > 0.0) U[i * n + j] = (U[i * n + j] - s) / U[i * n + i];
+                else U[i * n + j] = 0.0;
+            } else {
+                if (U[j * n + j] - s > 0.0) U[j * n + j] = sqrt(U[j * n + j] - s);
+                else { U[j * n + j] = 0.0; d += 1; }
+            }
+        }
+        for (int i = j + 1; i < n; ++i) U[i * n + j] = 0.0;
+    }
+    return d;
+}
+
+void orc_chol_c2(const double* U, int n, double* y) {
+    for (int i = 0; i < n; ++i) {
+        if (U[i * n + i] > 0.0) {
+            double s = 0.0;
+            for (int k = 0; k < i; ++k) s += U[k * n + i] * y[k];
+            y[i] = (y[i] - s) / U[i * n + i];
+        } else {
+            y[i] = 0.0;
+        }
+    }
+}
+
+void orc_chol_c3(const double* U, int n, double* x) {
+    for (int i = n - 1; i >= 0; --i) {
+        if (U[i * n + i] > 0.0) {
+            double s = 0.0;
+            for (int k = i + 1; k < n; ++k) s += U[i * n + k] * x[k];
+            x[i] = (x[i] - s) / U[i * n + i];
+        } else {
+            x[i] = 0.0;
+        }
+    }
+}
+
+/* The same three algorithms restricted to a band envelope of half-width hb
+ * (Appendix C.2 remark: the factor keeps the envelope, no fill-in). */
+#define UBX(j, jj) UB[(int64_t)(j) * (hb + 1) + ((jj) - (j))]
+int orc_band_c1(double* UB, int n, int hb) {
+    int d = 0;
+    for (int j = 0; j < n; ++j) {
+        int k0 = j - hb > 0 ? j - hb : 0;
+        for (int i = k0; i <= j; ++i) {
+            double s = 0.0;
+            for (int k = k0; k < i; ++k) s += UBX(k, i) * UBX(k, j);
+            if (i < j) {
+                if (UBX(i, i) > 0.0) UBX(i, j) = (UBX(i, j) - s) / UBX(i, i);
+                else UBX(i, j) = 0.0;
+            } else {
+                if (UBX(j, j) - s > 0.0) UBX(j, j) = sqrt(UBX(j, j) - s);
+                else { UBX(j, j) = 0.0; d += 1; }
+            }
+        }
+    }
+    return d;
+}
+
+void orc_band_c2(const double* UB, int n, int hb, double* y) {
+    for (int i = 0; i < n; ++i) {
+        if (UBX(i, i) > 0.0) {
+            int k0 = i - hb > 0 ? i - hb : 0;
+            double s = 0.0;
+            for (int k = k0; k < i; ++k) s += UBX(k, i) * y[k];
+            y[i] = (y[i] - s) / UBX(i, i);
+        } else {
+            y[i] = 0.0;
+        }
+    }
+}
+
+void orc_band_c3(const double* UB, int n, int hb, double* x) {
+    for (int i = n - 1; i >= 0; --i) {
+        if (UBX(i, i) > 0.0) {
+            int k1 = i + hb < n - 1 ? i + hb : n - 1;
+            double s = 0.0;
+            for (int k = i + 1; k <= k1; ++k) s += UBX(i, k) * x[k];
+            x[i] = (x[i] - s) / UBX(i, i);
+        } else {
+            x[i] = 0.0;
+        }
+    }
+}
+#undef UBX
+
+/* ========================================================================
+ * Sect. 3.2: normal triad of a source (eq:normal-triad).
+ * ====================================================================== */
+void orc_normal_triad(double alpha, double delta, double p[3], double q[3], double r[3]) {
+    double sa = sin(alpha), ca = cos(alpha), sd = sin(delta), cd = cos(delta);
+    p[0] = -sa;      p[1] = ca;       p[2] = 0.0;
+    q[0] = -sd * ca; q[1] = -sd * sa; q[2] = cd;
+    r[0] = cd * ca;  r[1] = cd * sa;  r[2] = sd;
+}
+
+/* Barycentric position [AU] and velocity [AU/s] of the observer: the
+ * synthetic world's circular orbit in the ecliptic, rotated to the
+ * equatorial frame (auxiliary data of eq:astro). */
+void orc_ephemeris(const orc_world_t* w, double t, double b[3], double v[3]) {
+    double L = w->eph_L0 + w->eph_Lrate * t;
+    double ce = cos(w->eps_obl), se = sin(w->eps_obl);
+    double be[3] = {w->eph_radius_au * cos(L), w->eph_radius_au * sin(L), 0.0};
+    double ve[3] = {-w->eph_radius_au * w->eph_Lrate * sin(L), w->eph_radius_au * w->eph_Lrate * cos(L), 0.0};
+    b[0] = be[0]; b[1] = ce * be[1] - se * be[2]; b[2] = se * be[1] + ce * be[2];
+    v[0] = ve[0]; v[1] = ce * ve[1] - se * ve[2]; v[2] = se * ve[1] + ce * ve[2];
+}
+
+static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* Everything the model computes for one observation. */
+typedef struct {
+    int64_t ell;
+    double B[4];
+    double qraw[4], D, q[4];
+    double p[3], qv[3], r[3];
+    double bG[3], vG[3], vc[3];
+    double tau;                 /* (t_B - t_ep) in years */
+    double ubar[3], u[3], Su[3];
+    double phi, zeta, eta, R;
+    int f;
+} orc_fwd_t;
+
+/* Sect. 3.2-3.5: the computed AL field angle and the residual. */
+static void forward_one(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st,
+                        int64_t l, orc_fwd_t* o) {
+    const double t = obs->t[l];
+    const double* s = st->s + 5 * (int64_t)obs->src[l];
+    /* eq:qspline with Algorithm B1 */
+    o->ell = orc_left_index(w->knots, w->n_knots, t);
+    orc_bspline(w->knots, o->ell, t, o->B);
+    for (int c = 0; c < 4; ++c) o->qraw[c] = 0.0;
+    for (int k = 0; k < M_ORDER; ++k) {
+        const double* an = st->a + 4 * (o->ell - M_ORDER + 1 + k);
+        for (int c = 0; c < 4; ++c) o->qraw[c] += an[c] * o->B[k];
+    }
+    double n2 = o->qraw[0] * o->qraw[0] + o->qraw[1] * o->qraw[1] + o->qraw[2] * o->qraw[2] + o->qraw[3] * o->qraw[3];
+    o->D = 1.0 - n2;                                   /* eq:Dl */
+    double nq = sqrt(n2);
+    for (int c = 0; c < 4; ++c) o->q[c] = o->qraw[c] / nq;
+    /* eq:normal-triad, eq:roemer, eq:astro-standard (mu_r = 0) */
+    orc_normal_triad(s[0], s[1], o->p, o->qv, o->r);
+    orc_ephemeris(w, t, o->bG, o->vG);
+    double tB = t + dot3(o->r, o->bG) * w->au_m / w->c_mps;
+    o->tau = (tB - w->t_ep) / w->year_s;
+    double ub[3];
+    for (int k = 0; k < 3; ++k)
+        ub[k] = o->r[k] + o->tau * (o->p[k] * s[3] + o->qv[k] * s[4]) - s[2] * o->bG[k];
+    double nub = sqrt(dot3(ub, ub));
+    for (int k = 0; k < 3; ++k) o->ubar[k] = ub[k] / nub;
+    /* eq:classAberr */
+    for (int k = 0; k < 3; ++k) o->vc[k] = o->vG[k] * w->au_m / w->c_mps;
+    double uu[3];
+    for (int k = 0; k < 3; ++k) uu[k] = o->ubar[k] + o->vc[k];
+    double nu = sqrt(dot3(uu, uu));
+    for (int k = 0; k < 3; ++k) o->u[k] = uu[k] / nu;
+    /* eq:srsprop, eq:srsprop1, eq:srspropeta */
+    orc_frame_rotate(o->q, o->u, o->Su);
+    o->phi = atan2(o->Su[1], o->Su[0]);
+    o->zeta = atan2(o->Su[2], sqrt(o->Su[0] * o->Su[0] + o->Su[1] * o->Su[1]));
+    o->f = o->phi >= 0.0 ? 1 : -1;
+    o->eta = o->phi - o->f * 0.5 * w->gamma_c;
+    /* eq:resAL with the generic calibration model (eq:generic1) */
+    o->R = obs->eta_obs[l] + st->c[obs->cell[l]] - o->eta;
+}
+
+/* Sect. 5.1.3: design row -dR_AL/ds for (alpha*, delta, parallax, mu_alpha*,
+ * mu_delta): eq:ubardiff, eq:duds, eq:srspropdiff, eq:srspqr,
+ * eq:srsprop1diffsol. */
+static void source_partials(const orc_fwd_t* o, double A[5]) {
+    double dub[5][3];
+    for (int k = 0; k < 3; ++k) {
+        double Ib = o->bG[k] - o->r[k] * dot3(o->r, o->bG);
+        dub[0][k] = o->p[k];
+        dub[1][k] = o->qv[k];
+        dub[2][k] = -Ib;
+        dub[3][k] = o->p[k] * o->tau;
+        dub[4][k] = o->qv[k] * o->tau;
+    }
+    double ubv = dot3(o->ubar, o->vc);
+    double sp = sin(o->phi), cp = cos(o->phi), sz = sin(o->zeta), cz = cos(o->zeta);
+    double m[3] = {-sp, cp, 0.0};
+    (void)sz;
+    for (int j = 0; j < 5; ++j) {
+        double du[3];
+        double vd = dot3(o->vc, dub[j]);
+        for (int k = 0; k < 3; ++k) du[k] = (1.0 - ubv) * dub[j][k] - o->ubar[k] * vd;
+        double dSu[3];
+        orc_frame_rotate(o->q, du, dSu);
+        A[j] = dot3(m, dSu) / cz;
+    }
+}
+
+/* Sect. 5.2.3: dR_AL/dq = -(eq:dfadq) = 2 sec(zeta) q {S'n, 0}. */
+static void attitude_partial(const orc_fwd_t* o, double g[4]) {
+    double sp = sin(o->phi), cp = cos(o->phi), sz = sin(o->zeta), cz = cos(o->zeta);
+    double nq[4] = {-sz * cp, -sz * sp, cz, 0.0};
+    double t[4];
+    orc_qmul(o->q, nq, t);
+    for (int c = 0; c < 4; ++c) g[c] = 2.0 / cz * t[c];
+}
+
+void orc_observe(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st,
+                 int64_t i0, int64_t i1,
+                 double* eta, double* phi, double* zeta, int8_t* f, double* R,
+                 double* dsrc, double* dq, double* bspl, int64_t* ell, double* qraw, double* D) {
+#pragma omp parallel for schedule(static)
+    for (int64_t l = i0; l < i1; ++l) {
+        orc_fwd_t o;
+        forward_one(w, obs, st, l, &o);
+        if (eta) eta[l] = o.eta;
+        if (phi) phi[l] = o.phi;
+        if (zeta) zeta[l] = o.zeta;
+        if (f) f[l] = (int8_t)o.f;
+        if (R) R[l] = o.R;
+        if (dsrc) source_partials(&o, dsrc + 5 * l);
+        if (dq) attitude_partial(&o, dq + 4 * l);
+        if (bspl) for (int k = 0; k < 4; ++k) bspl[4 * l + k] = o.B[k];
+        if (ell) ell[l] = o.ell;
+        if (qraw) for (int k = 0; k < 4; ++k) qraw[4 * l + k] = o.qraw[k];
+        if (D) D[l] = o.D;
+    }
+}
+
+/* Statistical weight W_l = w_l / (sigma_l^2 + eps_l^2) (eq:Jfunc) with
+ * w_l = 1 and eps_l = 0 (plain weighted least squares). */
+static double weight(const orc_obs_t* obs, int64_t l) {
+    double s = (double)obs->sigma[l];
+    return 1.0 / (s * s);
+}
+
+/* Observations grouped by source, each group in input order (stable). */
+static void group_by_source(const orc_obs_t* obs, int64_t n_src, int64_t** off_out, int64_t** idx_out) {
+    int64_t* off = (int64_t*)calloc((size_t)n_src + 1, sizeof(int64_t));
+    int64_t* idx = (int64_t*)malloc(sizeof(int64_t) * (size_t)(obs->n > 0 ? obs->n : 1));
+    for (int64_t l = 0; l < obs->n; ++l) off[obs->src[l] + 1] += 1;
+    for (int64_t i = 0; i < n_src; ++i) off[i + 1] += off[i];
+    int64_t* pos = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_src > 0 ? n_src : 1));
+    for (int64_t i = 0; i < n_src; ++i) pos[i] = off[i];
+    for (int64_t l = 0; l < obs->n; ++l) idx[pos[obs->src[l]]++] = l;
+    free(pos);
+    *off_out = off;
+    *idx_out = idx;
+}
+
+/* ========================================================================
+ * Sect. 5.1: source update.  For each source: eq:normS / eq:normSmat with
+ * the design matrix eq:designS and h = R (eq:designSrhs), solved by
+ * Algorithms C1-C3; Q_i from eq:Qi; alpha updated through d_1 = dalpha cos
+ * delta (footnote to eq:ubardiff).
+ * ====================================================================== */
+void orc_source_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st,
+                       double* d_out, double* Q_out, int32_t* defect_out) {
+    int64_t *off, *idx;
+    group_by_source(obs, st->n_src, &off, &idx);
+#pragma omp parallel
+    {
+        int64_t cap = 0;
+        double *Ab = NULL, *hb = NULL, *Wb = NULL;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < st->n_src; ++i) {
+            int64_t ni = off[i + 1] - off[i];
+            if (ni > cap) {
+                cap = ni;
+                Ab = (double*)realloc(Ab, sizeof(double) * 5 * cap);
+                hb = (double*)realloc(hb, sizeof(double) * cap);
+                Wb = (double*)realloc(Wb, sizeof(double) * cap);
+            }
+            double N[25] = {0}, b[5] = {0};
+            for (int64_t k = 0; k < ni; ++k) {
+                int64_t l = idx[off[i] + k];
+                orc_fwd_t o;
+                forward_one(w, obs, st, l, &o);
+                double* A = Ab + 5 * k;
+                source_partials(&o, A);
+                hb[k] = o.R;
+                Wb[k] = weight(obs, l);
+                for (int r = 0; r < 5; ++r) {
+                    for (int c = 0; c < 5; ++c) N[5 * r + c] += A[r] * Wb[k] * A[c];
+                    b[r] += A[r] * Wb[k] * hb[k];
+                }
+            }
+            int def = orc_chol_c1(N, 5);
+            orc_chol_c2(N, 5, b);
+            orc_chol_c3(N, 5, b);
+            double Q = 0.0;
+            for (int64_t k = 0; k < ni; ++k) {
+                double Rk = hb[k];
+                for (int c = 0; c < 5; ++c) Rk -= Ab[5 * k + c] * b[c];
+                Q += Rk * Wb[k] * Rk;
+            }
+            double* s = st->s + 5 * i;
+            double cosd = cos(s[1]);
+            s[0] += b[0] / cosd;
+            s[1] += b[1];
+            s[2] += b[2];
+            s[3] += b[3];
+            s[4] += b[4];
+            if (d_out) for (int c = 0; c < 5; ++c) d_out[5 * i + c] = b[c];
+            if (Q_out) Q_out[i] = Q;
+            if (defect_out) defect_out[i] = def;
+        }
+        free(Ab); free(hb); free(Wb);
+    }
+    free(off);
+    free(idx);
+}
+
+/* ========================================================================
+ * Sect. 5.2: attitude update.  Normal equations eq:normAmod (with the
+ * regularisation eq:Dl, eq:JfuncMod, eq:dDldan), the partials eq:dfadq times
+ * B_n, and the overlapping segmentation of Sect. 5.2.2: segment K uses the
+ * data in [tau_{x_K - L}, tau_{x_{K+1} + L}) and supplies the updates for
+ * x_K - 1 <= n <= x_{K+1} - 2 (M = 4).  Each segment is solved with
+ * Algorithms C1-C3 on the band envelope.
+ * ====================================================================== */
+int64_t orc_num_segments(const orc_world_t* w) {
+    int64_t K = w->n_knots - 2 * M_ORDER + 1;    /* number of knot intervals N - 3 */
+    return (K + w->seg_len - 1) / w->seg_len;
+}
+
+typedef struct {
+    int64_t lo, hi;              /* knot indices bounding the data interval */
+    int64_t n_lo, n_hi;          /* coefficient range of the segment system */
+    int64_t keep_lo, keep_hi;    /* coefficient range whose updates are kept */
+    int last;
+} seg_t;
+
+static void segment_bounds(const orc_world_t* w, int64_t K, seg_t* s) {
+    int64_t N = w->n_knots - M_ORDER;
+    int64_t nseg = orc_num_segments(w);
+    int64_t x0 = (M_ORDER - 1) + K * (int64_t)w->seg_len;          /* x_K */
+    int64_t x1 = K + 1 < nseg ? x0 + w->seg_len : N;                /* x_{K+1} */
+    s->lo = K == 0 ? M_ORDER - 1 : x0 - w->seg_overlap;
+    s->hi = K + 1 < nseg ? x1 + w->seg_overlap : N;
+    if (s->lo < M_ORDER - 1) s->lo = M_ORDER - 1;
+    if (s->hi > N) s->hi = N;
+    s->n_lo = s->lo - (M_ORDER - 1);
+    s->n_hi = s->hi - 1;
+    s->keep_lo = K == 0 ? 0 : x0 - M_ORDER / 2 + 1;
+    s->keep_hi = K + 1 < nseg ? x1 - M_ORDER / 2 : N - 1;
+    s->last = K + 1 == nseg;
+}
+
+typedef struct { double t; int64_t l; } tl_t;
+static int cmp_tl(const void* a, const void* b) {
+    const tl_t* x = (const tl_t*)a;
+    const tl_t* y = (const tl_t*)b;
+    if (x->t < y->t) return -1;
+    if (x->t > y->t) return 1;
+    return x->l < y->l ? -1 : (x->l > y->l ? 1 : 0);
+}
+
+static tl_t* time_order(const orc_obs_t* obs) {
+    tl_t* o = (tl_t*)malloc(sizeof(tl_t) * (size_t)(obs->n > 0 ? obs->n : 1));
+    for (int64_t l = 0; l < obs->n; ++l) { o[l].t = obs->t[l]; o[l].l = l; }
+    qsort(o, (size_t)obs->n, sizeof(tl_t), cmp_tl);
+    return o;
+}
+
+static int64_t first_at_or_after(const tl_t* o, int64_t n, double t) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (o[mid].t < t) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+static int64_t solve_segment(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st,
+                             const tl_t* order, const seg_t* sg, double* d) {
+    const int hb = 4 * M_ORDER - 1;
+    int64_t ncoef = sg->n_hi - sg->n_lo + 1;
+    int n = (int)(4 * ncoef);
+    double* UB = (double*)calloc((size_t)n * (hb + 1), sizeof(double));
+    double* y = (double*)calloc((size_t)n, sizeof(double));
+    const double lam2 = w->lambda_reg * w->lambda_reg;
+    double t_lo = w->knots[sg->lo], t_hi = w->knots[sg->hi];
+    int64_t first = first_at_or_after(order, obs->n, t_lo);
+    for (int64_t k = first; k < obs->n; ++k) {
+        double t = order[k].t;
+        if (sg->last ? (t > t_hi) : (t >= t_hi)) break;
+        int64_t l = order[k].l;
+        orc_fwd_t o;
+        forward_one(w, obs, st, l, &o);
+        double g[4];
+        attitude_partial(&o, g);
+        double W = weight(obs, l);
+        for (int kn = 0; kn < M_ORDER; ++kn) {
+            int64_t nb = o.ell - (M_ORDER - 1) + kn - sg->n_lo;
+            for (int km = 0; km < M_ORDER; ++km) {
+                int64_t mb = o.ell - (M_ORDER - 1) + km - sg->n_lo;
+                if (mb < nb) continue;
+                for (int r = 0; r < 4; ++r) {
+                    for (int c = 0; c < 4; ++c) {
+                        int64_t i = 4 * nb + r, j = 4 * mb + c;
+                        if (j < i) continue;
+                        double dRR = o.B[kn] * g[r] * o.B[km] * g[c];
+                        double dDD = (-2.0 * o.qraw[r] * o.B[kn]) * (-2.0 * o.qraw[c] * o.B[km]);
+                        UB[i * (hb + 1) + (j - i)] += (dRR + lam2 * dDD) * W;
+                    }
+                }
+            }
+            for (int r = 0; r < 4; ++r) {
+                double dR = o.B[kn] * g[r];
+                double dD = -2.0 * o.qraw[r] * o.B[kn];
+                y[4 * nb + r] -= (dR * o.R + lam2 * dD * o.D) * W;
+            }
+        }
+    }
+    int64_t def = orc_band_c1(UB, n, hb);
+    orc_band_c2(UB, n, hb, y);
+    orc_band_c3(UB, n, hb, y);
+    for (int64_t nn = sg->keep_lo; nn <= sg->keep_hi; ++nn)
+        for (int c = 0; c < 4; ++c) d[4 * nn + c] = y[4 * (nn - sg->n_lo) + c];
+    free(UB);
+    free(y);
+    return def;
+}
+
+static int64_t attitude_solve(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, double* d) {
+    tl_t* order = time_order(obs);
+    int64_t nseg = orc_num_segments(w);
+    int64_t def = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : def)
+    for (int64_t K = 0; K < nseg; ++K) {
+        seg_t sg;
+        segment_bounds(w, K, &sg);
+        def += solve_segment(w, obs, st, order, &sg, d);
+    }
+    free(order);
+    return def;
+}
+
+int64_t orc_attitude_segment(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st,
+                             int64_t K, double* d, int64_t* keep_lo, int64_t* keep_hi) {
+    tl_t* order = time_order(obs);
+    seg_t sg;
+    segment_bounds(w, K, &sg);
+    int64_t def = solve_segment(w, obs, st, order, &sg, d);
+    if (keep_lo) *keep_lo = sg.keep_lo;
+    if (keep_hi) *keep_hi = sg.keep_hi;
+    free(order);
+    return def;
+}
+
+int64_t orc_attitude_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st, double* d_out) {
+    double* d = (double*)calloc((size_t)(4 * st->n_att), sizeof(double));
+    int64_t def = attitude_solve(w, obs, st, d);
+    for (int64_t k = 0; k < 4 * st->n_att; ++k) st->a[k] += d[k];
+    if (d_out) memcpy(d_out, d, sizeof(double) * (size_t)(4 * st->n_att));
+    free(d);
+    return def;
+}
+
+/* ========================================================================
+ * Sect. 5.3: calibration update.  One effect with Phi = 1 per cell
+ * (eq:generic2, eq:pdC), so N_cc is diagonal (eq:normC); each 1x1 system
+ * goes through C1-C3; then the constraint projection eq:calCon with one
+ * constraint per day, c_P + c_F = 0 (eq:cc1 for this model).
+ * ====================================================================== */
+static void calibration_solve(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, double* d) {
+    double* Nc = (double*)calloc((size_t)st->n_cells, sizeof(double));
+    double* bc = (double*)calloc((size_t)st->n_cells, sizeof(double));
+    for (int64_t l = 0; l < obs->n; ++l) {
+        orc_fwd_t o;
+        forward_one(w, obs, st, l, &o);
+        double W = weight(obs, l);
+        int32_t c = obs->cell[l];
+        Nc[c] += 1.0 * W * 1.0;
+        bc[c] -= 1.0 * o.R * W;
+    }
+    for (int64_t c = 0; c < st->n_cells; ++c) {
+        double U = Nc[c], x = bc[c];
+        orc_chol_c1(&U, 1);
+        orc_chol_c2(&U, 1, &x);
+        orc_chol_c3(&U, 1, &x);
+        d[c] = x;
+    }
+    /* C = one column per day with ones at (2j, 2j+1); columns orthogonal,
+     * C'C = 2 I */
+    for (int64_t j = 0; 2 * j + 1 < st->n_cells; ++j) {
+        double ctd = d[2 * j] + d[2 * j + 1];
+        double z = ctd / 2.0;
+        d[2 * j] -= z;
+        d[2 * j + 1] -= z;
+    }
+    free(Nc);
+    free(bc);
+}
+
+void orc_calibration_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st, double* d_out) {
+    double* d = (double*)calloc((size_t)st->n_cells, sizeof(double));
+    calibration_solve(w, obs, st, d);
+    for (int64_t c = 0; c < st->n_cells; ++c) st->c[c] += d[c];
+    if (d_out) memcpy(d_out, d, sizeof(double) * (size_t)st->n_cells);
+    free(d);
+}
+
+/* Sect. 4.5 (practical scheme): S with a^k, c^k; then A and C both with
+ * s^{k+1}, a^k, c^k (the S[AC] variant of eq:precondS(CAG) without G). */
+void orc_iterate_sac(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st) {
+    orc_source_update(w, obs, st, NULL, NULL, NULL);
+    double* da = (double*)calloc((size_t)(4 * st->n_att), sizeof(double));
+    double* dc = (double*)calloc((size_t)st->n_cells, sizeof(double));
+    attitude_solve(w, obs, st, da);
+    calibration_solve(w, obs, st, dc);
+    for (int64_t k = 0; k < 4 * st->n_att; ++k) st->a[k] += da[k];
+    for (int64_t c = 0; c < st->n_cells; ++c) st->c[c] += dc[c];
+    free(da);
+    free(dc);
+}
+
+/* ========================================================================
+ * Sect. 6.1: frame rotator.
+ * Fit: unweighted least squares of eq:cond-mu3 over all sources taken as
+ * S_PM, comparison epoch t = t_ep, with the position differences of
+ * eq:fr-Delta1 (t_P = t_ep); normal equations solved by C1-C3.
+ * Apply: the five rigorous steps of Sect. 6.1.2 for every source and
+ * eq:fr-q4 with eq:RF4 for every attitude coefficient.
+ * ====================================================================== */
+void orc_frame_fit(const orc_world_t* w, const orc_state_t* st, const double* s_ref, double eps_omega[6]) {
+    double N[36] = {0}, b[6] = {0};
+    double tau = (w->t_ep - w->t_fr) / w->year_s;
+    for (int64_t i = 0; i < st->n_src; ++i) {
+        const double* s = st->s + 5 * i;
+        const double* h = s_ref + 5 * i;
+        double pt[3], qt[3], rt[3], ph[3], qh[3], rh[3];
+        orc_normal_triad(s[0], s[1], pt, qt, rt);
+        orc_normal_triad(h[0], h[1], ph, qh, rh);
+        double dr[3] = {rt[0] - rh[0], rt[1] - rh[1], rt[2] - rh[2]};
+        double rows[4][6], rhs[4];
+        for (int k = 0; k < 3; ++k) {
+            rows[0][k] = 0.0;        rows[0][3 + k] = qt[k];
+            rows[1][k] = 0.0;        rows[1][3 + k] = -pt[k];
+            rows[2][k] = qt[k];      rows[2][3 + k] = tau * qt[k];
+            rows[3][k] = -pt[k];     rows[3][3 + k] = -tau * pt[k];
+        }
+        rhs[0] = s[3] - h[3];
+        rhs[1] = s[4] - h[4];
+        rhs[2] = dot3(pt, dr);
+        rhs[3] = dot3(qt, dr);
+        for (int e = 0; e < 4; ++e) {
+            for (int r = 0; r < 6; ++r) {
+                for (int c = 0; c < 6; ++c) N[6 * r + c] += rows[e][r] * rows[e][c];
+                b[r] += rows[e][r] * rhs[e];
+            }
+        }
+    }
+    orc_chol_c1(N, 6);
+    orc_chol_c2(N, 6, b);
+    orc_chol_c3(N, 6, b);
+    memcpy(eps_omega, b, sizeof b);
+}
+
+/* f(t) = Q[(t - t_fr) omega] Q(eps)  (eq:fr1) */
+static void frame_quat(const orc_world_t* w, const double eo[6], double t, double f[4]) {
+    double dt = (t - w->t_fr) / w->year_s;
+    double wv[3] = {dt * eo[3], dt * eo[4], dt * eo[5]};
+    double qw[4], qe[4];
+    orc_qrot(wv, qw);
+    orc_qrot(eo, qe);
+    orc_qmul(qw, qe, f);
+}
+
+void orc_frame_apply(const orc_world_t* w, orc_state_t* st, const double eo[6]) {
+    double f[4], fi[4];
+    frame_quat(w, eo, w->t_ep, f);                                  /* step 1 */
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < st->n_src; ++i) {
+        double* s = st->s + 5 * i;
+        double pt[3], qt[3], rt[3];
+        orc_normal_triad(s[0], s[1], pt, qt, rt);                   /* step 2 */
+        double rC[3], mut[3], muC[3];
+        orc_frame_rotate(f, rt, rC);                                /* step 3, eq:fr-r */
+        double wxr[3] = {eo[4] * rt[2] - eo[5] * rt[1], eo[5] * rt[0] - eo[3] * rt[2], eo[3] * rt[1] - eo[4] * rt[0]};
+        for (int k = 0; k < 3; ++k) mut[k] = pt[k] * s[3] + qt[k] * s[4] - wxr[k];   /* eq:mu-agis */
+        orc_frame_rotate(f, mut, muC);                              /* eq:fr-mu */
+        double alpha = atan2(rC[1], rC[0]);                         /* step 4, eq:fr-ad */
+        double delta = atan2(rC[2], sqrt(rC[0] * rC[0] + rC[1] * rC[1]));
+        double p[3], q[3], r[3];
+        orc_normal_triad(alpha, delta, p, q, r);
+        s[0] = alpha;
+        s[1] = delta;
+        s[3] = dot3(p, muC);                                        /* step 5, eq:fr-mu-icrs */
+        s[4] = dot3(q, muC);
+    }
+    (void)fi;
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < st->n_att; ++n) {
+        double tbar = 0.5 * (w->knots[n] + w->knots[n + M_ORDER]);  /* eq:RF4 */
+        double fn[4], fni[4], r[4];
+        frame_quat(w, eo, tbar, fn);
+        orc_qinv(fn, fni);
+        orc_qmul(fni, st->a + 4 * n, r);                            /* eq:fr-q4 */
+        memcpy(st->a + 4 * n, r, sizeof r);
+    }
+}

@@ -1,0 +1,118 @@
+/*
+ * AGIS CPU oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, double-precision implementation of the source (S), attitude
+ * (A) and calibration (C) updating blocks and the frame rotator of the
+ * astrometric core solution (Lindegren et al. 2012, arXiv:1112.4139), written
+ * from the paper's equations and algorithms in their order.  It exists to
+ * check the GPU library; only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load it.  It shares no code, header or
+ * table with the GPU library.
+ *
+ * Units: t in seconds from the reference epoch; angles in radians; proper
+ * motions and frame spin in radians per Julian year; ephemeris in AU.
+ */
+#ifndef AGIS_ORACLE_H
+#define AGIS_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int64_t n_knots;          /* N + M, M = 4 */
+    const double* knots;      /* non-decreasing knot sequence tau_0..tau_{N+3} */
+    double gamma_c;           /* conventional basic angle [rad] */
+    double t_ep;              /* reference epoch of the astrometric parameters [s] */
+    double t_fr;              /* frame rotator epoch [s] */
+    double lambda_reg;        /* attitude regularisation lambda */
+    int32_t seg_len;          /* attitude segment length [knot intervals] */
+    int32_t seg_overlap;      /* L: half overlap [knot intervals] */
+    double eph_radius_au;     /* circular barycentric orbit radius [AU] */
+    double eph_L0;            /* orbital longitude at t = 0 [rad] */
+    double eph_Lrate;         /* orbital angular rate [rad/s] */
+    double eps_obl;           /* ecliptic obliquity [rad] */
+    double au_m;              /* astronomical unit [m] */
+    double c_mps;             /* speed of light [m/s] */
+    double year_s;            /* Julian year [s] */
+} orc_world_t;
+
+typedef struct {
+    int64_t n;
+    const double* t;          /* observation time [s] */
+    const double* eta_obs;    /* observed AL field angle without calibration [rad] */
+    const float* sigma;       /* formal AL uncertainty [rad] */
+    const int32_t* src;       /* source index */
+    const int8_t* fov;        /* +1 preceding, -1 following */
+    const int32_t* cell;      /* calibration cell */
+} orc_obs_t;
+
+typedef struct {
+    int64_t n_src, n_att, n_cells;
+    double* s;                /* [n_src][5] alpha, delta, parallax, pm_alpha*, pm_delta */
+    double* a;                /* [n_att][4] x, y, z, w */
+    double* c;                /* [n_cells] */
+} orc_state_t;
+
+/* --- Appendix A: quaternions -------------------------------------------- */
+void orc_qmul(const double a[4], const double b[4], double out[4]);
+void orc_qconj(const double a[4], double out[4]);
+void orc_qinv(const double a[4], double out[4]);
+void orc_frame_rotate(const double q[4], const double v[3], double out[3]);
+void orc_vector_rotate(const double q[4], const double v[3], double out[3]);
+void orc_quat2mat(const double q[4], double A[9]);
+void orc_qrot(const double phi[3], double out[4]);
+
+/* --- Appendix B: B-splines ---------------------------------------------- */
+int64_t orc_left_index(const double* knots, int64_t n_knots, double t);
+void orc_bspline(const double* knots, int64_t ell, double t, double b[4]);
+
+/* --- Appendix C: modified Cholesky (dense, row-major n x n) --------------- */
+int orc_chol_c1(double* U, int n);
+void orc_chol_c2(const double* U, int n, double* y);
+void orc_chol_c3(const double* U, int n, double* x);
+/* band storage: UB[j*(hb+1) + k] is element (j, j+k), 0 <= k <= hb */
+int orc_band_c1(double* UB, int n, int hb);
+void orc_band_c2(const double* UB, int n, int hb, double* y);
+void orc_band_c3(const double* UB, int n, int hb, double* x);
+
+/* --- Sect. 3: observation model ------------------------------------------ */
+/* Per observation: computed field angle eta, instrument angles phi, zeta,
+ * field index f, residual R (with calibration), design row -dR/ds (5),
+ * dR/dq (4), B-spline values (4) and left index, unnormalised attitude
+ * quaternion (4) and D = 1 - |sum a_n B_n|^2.  Any output pointer may be NULL. */
+void orc_observe(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st,
+                 int64_t i0, int64_t i1,
+                 double* eta, double* phi, double* zeta, int8_t* f, double* R,
+                 double* dsrc, double* dq, double* bspl, int64_t* ell, double* qraw, double* D);
+void orc_ephemeris(const orc_world_t* w, double t, double b[3], double v[3]);
+void orc_normal_triad(double alpha, double delta, double p[3], double q[3], double r[3]);
+
+/* --- Sect. 5: update blocks ----------------------------------------------- */
+/* S block for all sources; updates st->s in place.  Optional outputs:
+ * d[n_src][5] updates, Q[n_src] = R'WR after the solve, defect[n_src]. */
+void orc_source_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st,
+                       double* d, double* Q, int32_t* defect);
+/* A block (all segments); residuals from the current state.  d[n_att][4]
+ * receives the applied update (may be NULL); returns the summed defect. */
+int64_t orc_attitude_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st, double* d);
+/* One segment K only: solve and return the kept updates in d[n_att][4]
+ * (entries outside the kept range are left untouched); no state change. */
+int64_t orc_attitude_segment(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st,
+                             int64_t K, double* d, int64_t* keep_lo, int64_t* keep_hi);
+int64_t orc_num_segments(const orc_world_t* w);
+/* C block; d[n_cells] receives the applied update (may be NULL). */
+void orc_calibration_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st, double* d);
+/* S[AC]: S, then A and C from the same post-S residuals. */
+void orc_iterate_sac(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st);
+
+/* --- Sect. 6.1: frame rotator --------------------------------------------- */
+/* eps_omega = (eps_X, eps_Y, eps_Z [rad], omega_X, omega_Y, omega_Z [rad/yr]) */
+void orc_frame_fit(const orc_world_t* w, const orc_state_t* st, const double* s_ref, double eps_omega[6]);
+void orc_frame_apply(const orc_world_t* w, orc_state_t* st, const double eps_omega[6]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
