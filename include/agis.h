@@ -1,0 +1,205 @@
+/*
+ * libagis -- the per-iteration source (S), attitude (A) and calibration (C)
+ * updating blocks and the frame rotator of the Gaia astrometric core
+ * solution (Lindegren et al. 2012, "The astrometric core solution for the
+ * Gaia mission", arXiv:1112.4139), on one AMD Instinct MI355X (gfx950).
+ *
+ * C ABI: plain pointers and sizes.  Every call returns AGIS_OK (0) or a
+ * negative error code; agis_last_error() then describes the failure.  No C++
+ * exception crosses the interface.  A context owns all device memory it
+ * allocates; caller buffers are only read or written during the call.  One
+ * context must not be used from two host threads at once.  Rank deficiency
+ * of a block system is not an error: it is counted (Algorithm C1's defect d)
+ * in the statistics.
+ *
+ * Units: times in seconds from the reference epoch of the astrometric
+ * parameters; angles in radians; proper motions and the frame spin in radians
+ * per Julian year (year_s seconds); the observer ephemeris in astronomical
+ * units (a circular barycentric orbit, see agis_config_t).
+ *
+ * Pointers marked "where" are host memory when where == AGIS_HOST and device
+ * memory of the context's GPU when where == AGIS_DEVICE (for instance the
+ * data pointer of a torch tensor on that device; the copy is ordered on the
+ * context's stream).
+ */
+#ifndef AGIS_H
+#define AGIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AGIS_VERSION 100
+
+enum {
+    AGIS_OK = 0,
+    AGIS_E_INVALID_ARG = -1, /* null pointer, bad enum, bad size */
+    AGIS_E_SHAPE = -2,       /* sizes inconsistent with the configuration */
+    AGIS_E_RANGE = -3,       /* index or time outside its valid range */
+    AGIS_E_DEVICE = -4,      /* HIP runtime error */
+    AGIS_E_OOM = -5,         /* device allocation failed */
+    AGIS_E_NUMERIC = -6,     /* non-finite value detected */
+    AGIS_E_STATE = -7        /* call out of order (e.g. update before load) */
+};
+
+enum { AGIS_HOST = 0, AGIS_DEVICE = 1 };
+enum { AGIS_FP64 = 0, AGIS_MIXED = 1 };
+
+typedef struct agis_ctx agis_ctx_t;
+
+/*
+ * Method constants and the synthetic world's auxiliary data.
+ *   knots      : B-spline knot sequence tau_0..tau_{N+3} for cubic splines
+ *                (order M = 4, Sect. 3.3 and Appendix B), non-decreasing,
+ *                copied at create.  Observation times must lie in
+ *                [tau_3, tau_N].
+ *   gamma_c    : conventional basic angle Gamma_c (eq:srspropeta).
+ *   t_ep, t_fr : reference epoch of the astrometric parameters (eq:uniform)
+ *                and frame rotator epoch (eq:fr1) [s].
+ *   lambda_reg : attitude regularisation lambda (eq:JfuncMod).
+ *   seg_len, seg_overlap : attitude segments of seg_len knot intervals with
+ *                L = seg_overlap intervals on each side (Sect. 5.2.2).
+ *   eph_*      : observer ephemeris b_G(t) = R_x(eps_obl) eph_radius_au
+ *                (cos L, sin L, 0), L = eph_L0 + eph_Lrate t, and its time
+ *                derivative v_G (the auxiliary data of eq:astro).
+ *   au_m, c_mps, year_s : astronomical unit [m], speed of light [m/s],
+ *                Julian year [s].
+ *   precision  : AGIS_FP64 or AGIS_MIXED (FP32 partials and normal-matrix
+ *                accumulation with compensated sums; FP64 elsewhere).
+ *   device     : HIP device ordinal; stream: hipStream_t or NULL (the
+ *                context then creates its own default-priority stream).
+ */
+typedef struct {
+    int64_t n_knots;
+    const double* knots;
+    double gamma_c;
+    double t_ep, t_fr;
+    double lambda_reg;
+    int32_t seg_len, seg_overlap;
+    double eph_radius_au, eph_L0, eph_Lrate, eps_obl;
+    double au_m, c_mps, year_s;
+    int32_t precision;
+    int32_t device;
+    void* stream;
+} agis_config_t;
+
+/*
+ * One AL observation record per element (Sect. 3.5, eq:synth/eq:resAL), SoA:
+ *   t       [n] observation time [s]
+ *   eta_obs [n] observed AL field angle of the fiducial line, without the
+ *               calibration term [rad]; the model value is eta_obs + c_cell
+ *   sigma   [n] formal AL standard uncertainty [rad], float32, > 0
+ *   src     [n] source index in [0, n_src)
+ *   fov     [n] field of view: +1 preceding, -1 following
+ *   cell    [n] calibration cell in [0, n_cells); cells are grouped in
+ *               constraint pairs (2j, 2j+1) with c_2j + c_2j+1 = 0
+ *               (eq:calCon); within one knot interval all observations of
+ *               one field of view must share a cell, and each cell must cover
+ *               a contiguous run of knot intervals (AGIS_E_SHAPE otherwise)
+ */
+typedef struct {
+    int64_t n;
+    const double* t;
+    const double* eta_obs;
+    const float* sigma;
+    const int32_t* src;
+    const int8_t* fov;
+    const int32_t* cell;
+} agis_obs_soa_t;
+
+typedef struct {
+    int64_t n_obs;           /* observations used */
+    int64_t n_units;         /* sources / coefficients / cells updated */
+    int64_t defect;          /* summed rank-defect count of Algorithm C1 */
+    double rms_update[5];    /* RMS of the update per component: sources
+                                (alpha*, delta, parallax, mu_alpha*, mu_delta);
+                                attitude (x, y, z, w); calibration (value) */
+    double max_update[5];
+    double chi2;             /* sum of W R^2 after the S solve (eq:Qi summed) */
+    double ms;               /* device time of the block [ms] */
+} agis_block_stats_t;
+
+typedef struct {
+    agis_block_stats_t s, a, c;
+    double eps_omega[6];     /* frame rotator parameters applied (0 if none) */
+    double ms;               /* device time of the whole iteration [ms] */
+} agis_iter_stats_t;
+
+int agis_version(void);
+
+/* Create a context on cfg->device; copies *cfg and the knots. */
+int agis_create(const agis_config_t* cfg, agis_ctx_t** out);
+void agis_destroy(agis_ctx_t* ctx);
+/* Message of the last failed call on ctx (owned by ctx, valid until its
+ * next call); with ctx == NULL, the last agis_create failure. */
+const char* agis_last_error(const agis_ctx_t* ctx);
+
+/* Observation store (Sect. 3.5 observation records).  Validates every
+ * index and time, then builds the two device orders the blocks stream:
+ * by (source, time) for S and by time for A and C, with left indices
+ * (tau_l <= t < tau_{l+1}; t = tau_N in the last interval), source and knot
+ * interval offsets.  n_src and n_cells fix the parameter vector sizes. */
+int agis_load_observations(agis_ctx_t* ctx, const agis_obs_soa_t* obs, int64_t n_src, int64_t n_cells,
+                           int where);
+
+/* Parameters.  Sources [n][5] (alpha, delta, parallax, pm_alpha*, pm_delta);
+ * attitude [N][4] B-spline coefficients (x, y, z, w) of eq:qspline;
+ * calibration [n_cells]. */
+int agis_set_sources(agis_ctx_t* ctx, int64_t n, const double* s5, int where);
+int agis_get_sources(agis_ctx_t* ctx, int64_t n, double* s5, int where);
+int agis_set_attitude(agis_ctx_t* ctx, int64_t n, const double* a4, int where);
+int agis_get_attitude(agis_ctx_t* ctx, int64_t n, double* a4, int where);
+int agis_set_calibration(agis_ctx_t* ctx, int64_t n, const double* c, int where);
+int agis_get_calibration(agis_ctx_t* ctx, int64_t n, double* c, int where);
+
+/* S block (Sect. 5.1): per source, eq:normS with the design matrix of
+ * eq:designS at the current (s, a, c), solved by Algorithms C1-C3;
+ * alpha is updated by d_1 / cos(delta). */
+int agis_source_update(agis_ctx_t* ctx, agis_block_stats_t* st);
+/* A block (Sect. 5.2): regularised band normal equations eq:normAmod per
+ * overlapping segment, Algorithms C1-C3 on the band, updates kept by the
+ * selection rule of Sect. 5.2.2. */
+int agis_attitude_update(agis_ctx_t* ctx, agis_block_stats_t* st);
+/* C block (Sect. 5.3): per-cell normal equations eq:normC (Phi = 1), then
+ * the constraint projection eq:calCon. */
+int agis_calibration_update(agis_ctx_t* ctx, agis_block_stats_t* st);
+/* A and C together from one pass of residuals at the current parameters
+ * (the bracketed pair of the S[ACG] scheme, Sect. 4.5, without G). */
+int agis_attitude_calibration_update(agis_ctx_t* ctx, agis_block_stats_t* st_a, agis_block_stats_t* st_c);
+
+/* Frame rotator (Sect. 6.1).  The reference catalogue s_ref [n_src][5]
+ * defines the S_PM comparison of eq:cond-mu3 at t = t_ep (eq:fr-Delta1).
+ * frame_fit solves the unweighted least squares for eps_omega = (eps_X,
+ * eps_Y, eps_Z [rad], omega_X, omega_Y, omega_Z [rad/yr]); frame_apply
+ * transforms all sources rigorously (Sect. 6.1.2) and all attitude
+ * coefficients by eq:fr-q4. */
+int agis_set_frame_reference(agis_ctx_t* ctx, int64_t n, const double* s_ref5, int where);
+int agis_frame_fit(agis_ctx_t* ctx, double eps_omega[6]);
+int agis_frame_apply(agis_ctx_t* ctx, const double eps_omega[6]);
+
+/* n_iter simple iterations S[AC] (Sect. 4.5), each followed by the frame
+ * rotator when a reference is set.  per_iter may be NULL or hold n_iter
+ * entries. */
+int agis_iterate(agis_ctx_t* ctx, int32_t n_iter, agis_iter_stats_t* per_iter);
+
+/* Residuals R_l (eq:resAL) at the current parameters, in the input order of
+ * agis_load_observations. */
+int agis_residuals(agis_ctx_t* ctx, double* R, int where);
+
+/* Sizes of the loaded problem (any pointer may be NULL). */
+int agis_problem_size(const agis_ctx_t* ctx, int64_t* n_obs, int64_t* n_src, int64_t* n_att, int64_t* n_cells,
+                      int64_t* n_segments);
+
+/* Device time [ms] of the last launch of each hot kernel, measured with
+ * HIP events on the context stream: [0] source update, [1] attitude and
+ * calibration accumulation, [2] band solve, [3] calibration solve,
+ * [4] frame rotator. */
+int agis_kernel_times(const agis_ctx_t* ctx, double ms[5]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

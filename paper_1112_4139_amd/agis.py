@@ -1,0 +1,286 @@
+"""ctypes binding of libagis (include/agis.h): argument marshalling only.
+
+Every function below has the name of the C entry point it calls and only
+converts arguments: NumPy arrays are passed as host pointers (AGIS_HOST),
+torch tensors on the GPU as device pointers (AGIS_DEVICE).  All computation
+happens in the library's HIP kernels; if the library is missing the import
+fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libagis.so")
+
+AGIS_OK = 0
+AGIS_HOST, AGIS_DEVICE = 0, 1
+AGIS_FP64, AGIS_MIXED = 0, 1
+ERRORS = {-1: "E_INVALID_ARG", -2: "E_SHAPE", -3: "E_RANGE", -4: "E_DEVICE", -5: "E_OOM", -6: "E_NUMERIC",
+          -7: "E_STATE"}
+
+P = ctypes.POINTER
+c_d, c_i64, c_i32, c_i8, c_f = ctypes.c_double, ctypes.c_int64, ctypes.c_int32, ctypes.c_int8, ctypes.c_float
+
+
+class agis_config_t(ctypes.Structure):
+    _fields_ = [("n_knots", c_i64), ("knots", P(c_d)), ("gamma_c", c_d), ("t_ep", c_d), ("t_fr", c_d),
+                ("lambda_reg", c_d), ("seg_len", c_i32), ("seg_overlap", c_i32), ("eph_radius_au", c_d),
+                ("eph_L0", c_d), ("eph_Lrate", c_d), ("eps_obl", c_d), ("au_m", c_d), ("c_mps", c_d),
+                ("year_s", c_d), ("precision", c_i32), ("device", c_i32), ("stream", ctypes.c_void_p)]
+
+
+class agis_obs_soa_t(ctypes.Structure):
+    _fields_ = [("n", c_i64), ("t", ctypes.c_void_p), ("eta_obs", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
+                ("src", ctypes.c_void_p), ("fov", ctypes.c_void_p), ("cell", ctypes.c_void_p)]
+
+
+class agis_block_stats_t(ctypes.Structure):
+    _fields_ = [("n_obs", c_i64), ("n_units", c_i64), ("defect", c_i64), ("rms_update", c_d * 5),
+                ("max_update", c_d * 5), ("chi2", c_d), ("ms", c_d)]
+
+    def as_dict(self):
+        return dict(n_obs=self.n_obs, n_units=self.n_units, defect=self.defect, rms_update=list(self.rms_update),
+                    max_update=list(self.max_update), chi2=self.chi2, ms=self.ms)
+
+
+class agis_iter_stats_t(ctypes.Structure):
+    _fields_ = [("s", agis_block_stats_t), ("a", agis_block_stats_t), ("c", agis_block_stats_t),
+                ("eps_omega", c_d * 6), ("ms", c_d)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libagis.so not built at {LIB_PATH}; run __graft_entry__.build()")
+_lib = ctypes.CDLL(LIB_PATH)
+_vp = ctypes.c_void_p
+_ctx_p = ctypes.c_void_p
+_sig = {
+    "agis_version": ([], ctypes.c_int),
+    "agis_create": ([P(agis_config_t), P(_ctx_p)], ctypes.c_int),
+    "agis_destroy": ([_ctx_p], None),
+    "agis_last_error": ([_ctx_p], ctypes.c_char_p),
+    "agis_load_observations": ([_ctx_p, P(agis_obs_soa_t), c_i64, c_i64, ctypes.c_int], ctypes.c_int),
+    "agis_set_sources": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
+    "agis_get_sources": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
+    "agis_set_attitude": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
+    "agis_get_attitude": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
+    "agis_set_calibration": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
+    "agis_get_calibration": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
+    "agis_source_update": ([_ctx_p, P(agis_block_stats_t)], ctypes.c_int),
+    "agis_attitude_update": ([_ctx_p, P(agis_block_stats_t)], ctypes.c_int),
+    "agis_calibration_update": ([_ctx_p, P(agis_block_stats_t)], ctypes.c_int),
+    "agis_attitude_calibration_update": ([_ctx_p, P(agis_block_stats_t), P(agis_block_stats_t)], ctypes.c_int),
+    "agis_set_frame_reference": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
+    "agis_frame_fit": ([_ctx_p, P(c_d)], ctypes.c_int),
+    "agis_frame_apply": ([_ctx_p, P(c_d)], ctypes.c_int),
+    "agis_iterate": ([_ctx_p, c_i32, P(agis_iter_stats_t)], ctypes.c_int),
+    "agis_residuals": ([_ctx_p, _vp, ctypes.c_int], ctypes.c_int),
+    "agis_problem_size": ([_ctx_p, P(c_i64), P(c_i64), P(c_i64), P(c_i64), P(c_i64)], ctypes.c_int),
+    "agis_kernel_times": ([_ctx_p, P(c_d)], ctypes.c_int),
+}
+for _name, (_args, _res) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+EXPORTS = tuple(_sig)
+
+
+class AgisError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(rc, ctx):
+    if rc != AGIS_OK:
+        raise AgisError(rc, (_lib.agis_last_error(ctx) or b"").decode())
+
+
+def _ptr(x, dtype):
+    """(pointer, where, keepalive) for a NumPy array or a torch tensor."""
+    try:
+        import torch
+        if isinstance(x, torch.Tensor):
+            want = {np.float64: torch.float64, np.float32: torch.float32, np.int32: torch.int32,
+                    np.int8: torch.int8}[dtype]
+            if x.dtype != want or not x.is_contiguous():
+                raise TypeError(f"tensor must be contiguous {want}")
+            return ctypes.c_void_p(x.data_ptr()), (AGIS_DEVICE if x.is_cuda else AGIS_HOST), x
+    except ImportError:
+        pass
+    a = np.ascontiguousarray(x, dtype=dtype)
+    return a.ctypes.data_as(ctypes.c_void_p), AGIS_HOST, a
+
+
+def agis_version() -> int:
+    return _lib.agis_version()
+
+
+def agis_create(consts: dict, knots, precision=AGIS_FP64, device=0, stream=None):
+    k = np.ascontiguousarray(knots, dtype=np.float64)
+    cfg = agis_config_t(n_knots=k.size, knots=k.ctypes.data_as(P(c_d)), gamma_c=consts["gamma_c"],
+                        t_ep=consts["t_ep"], t_fr=consts["t_fr"], lambda_reg=consts["lambda_reg"],
+                        seg_len=int(consts["seg_len"]), seg_overlap=int(consts["seg_overlap"]),
+                        eph_radius_au=consts["eph_radius_au"], eph_L0=consts["eph_L0"],
+                        eph_Lrate=consts["eph_Lrate"], eps_obl=consts["eps_obl"], au_m=consts["au_m"],
+                        c_mps=consts["c_mps"], year_s=consts["year_s"], precision=precision, device=device,
+                        stream=stream)
+    ctx = _ctx_p()
+    rc = _lib.agis_create(ctypes.byref(cfg), ctypes.byref(ctx))
+    _check(rc, None)
+    return ctx
+
+
+def agis_destroy(ctx):
+    _lib.agis_destroy(ctx)
+
+
+def agis_last_error(ctx) -> str:
+    return (_lib.agis_last_error(ctx) or b"").decode()
+
+
+def agis_load_observations(ctx, t, eta_obs, sigma, src, fov, cell, n_src, n_cells):
+    cols = [_ptr(t, np.float64), _ptr(eta_obs, np.float64), _ptr(sigma, np.float32), _ptr(src, np.int32),
+            _ptr(fov, np.int8), _ptr(cell, np.int32)]
+    wheres = {w for _, w, _ in cols}
+    if len(wheres) != 1:
+        raise ValueError("observation columns must all be host arrays or all device tensors")
+    n = len(cols[-1][2])
+    obs = agis_obs_soa_t(n, *[p for p, _, _ in cols])
+    _check(_lib.agis_load_observations(ctx, ctypes.byref(obs), int(n_src), int(n_cells), wheres.pop()), ctx)
+
+
+def _set(fn, ctx, n, x):
+    p, where, keep = _ptr(x, np.float64)
+    _check(fn(ctx, int(n), p, where), ctx)
+
+
+def _get(fn, ctx, n, width, out=None):
+    if out is None:
+        out = np.empty((n, width) if width > 1 else n, dtype=np.float64)
+    p, where, keep = _ptr(out, np.float64)
+    _check(fn(ctx, int(n), p, where), ctx)
+    return out
+
+
+def agis_set_sources(ctx, s5):
+    _set(_lib.agis_set_sources, ctx, len(s5), s5)
+
+
+def agis_get_sources(ctx, n, out=None):
+    return _get(_lib.agis_get_sources, ctx, n, 5, out)
+
+
+def agis_set_attitude(ctx, a4):
+    _set(_lib.agis_set_attitude, ctx, len(a4), a4)
+
+
+def agis_get_attitude(ctx, n, out=None):
+    return _get(_lib.agis_get_attitude, ctx, n, 4, out)
+
+
+def agis_set_calibration(ctx, c):
+    _set(_lib.agis_set_calibration, ctx, len(c), c)
+
+
+def agis_get_calibration(ctx, n, out=None):
+    return _get(_lib.agis_get_calibration, ctx, n, 1, out)
+
+
+def agis_source_update(ctx):
+    st = agis_block_stats_t()
+    _check(_lib.agis_source_update(ctx, ctypes.byref(st)), ctx)
+    return st.as_dict()
+
+
+def agis_attitude_update(ctx):
+    st = agis_block_stats_t()
+    _check(_lib.agis_attitude_update(ctx, ctypes.byref(st)), ctx)
+    return st.as_dict()
+
+
+def agis_calibration_update(ctx):
+    st = agis_block_stats_t()
+    _check(_lib.agis_calibration_update(ctx, ctypes.byref(st)), ctx)
+    return st.as_dict()
+
+
+def agis_attitude_calibration_update(ctx):
+    sa, sc = agis_block_stats_t(), agis_block_stats_t()
+    _check(_lib.agis_attitude_calibration_update(ctx, ctypes.byref(sa), ctypes.byref(sc)), ctx)
+    return sa.as_dict(), sc.as_dict()
+
+
+def agis_set_frame_reference(ctx, s_ref):
+    if s_ref is None:
+        n = ctypes.c_int64()
+        _lib.agis_problem_size(ctx, None, ctypes.byref(n), None, None, None)
+        _check(_lib.agis_set_frame_reference(ctx, n.value, None, AGIS_HOST), ctx)
+        return
+    _set(_lib.agis_set_frame_reference, ctx, len(s_ref), s_ref)
+
+
+def agis_frame_fit(ctx):
+    eo = (c_d * 6)()
+    _check(_lib.agis_frame_fit(ctx, eo), ctx)
+    return np.array(eo[:])
+
+
+def agis_frame_apply(ctx, eps_omega):
+    eo = (c_d * 6)(*[float(x) for x in eps_omega])
+    _check(_lib.agis_frame_apply(ctx, eo), ctx)
+
+
+def agis_iterate(ctx, n_iter, stats=True):
+    if stats:
+        arr = (agis_iter_stats_t * max(int(n_iter), 1))()
+        _check(_lib.agis_iterate(ctx, int(n_iter), arr), ctx)
+        return [dict(s=x.s.as_dict(), a=x.a.as_dict(), c=x.c.as_dict(), eps_omega=list(x.eps_omega), ms=x.ms)
+                for x in arr[:n_iter]]
+    _check(_lib.agis_iterate(ctx, int(n_iter), None), ctx)
+    return None
+
+
+def agis_residuals(ctx, out=None):
+    if out is None:
+        n = ctypes.c_int64()
+        _lib.agis_problem_size(ctx, ctypes.byref(n), None, None, None, None)
+        out = np.empty(n.value, dtype=np.float64)
+    p, where, keep = _ptr(out, np.float64)
+    _check(_lib.agis_residuals(ctx, p, where), ctx)
+    return out
+
+
+def agis_problem_size(ctx):
+    v = [ctypes.c_int64() for _ in range(5)]
+    _check(_lib.agis_problem_size(ctx, *[ctypes.byref(x) for x in v]), ctx)
+    return dict(zip(["n_obs", "n_src", "n_att", "n_cells", "n_segments"], [x.value for x in v]))
+
+
+def agis_kernel_times(ctx):
+    ms = (c_d * 5)()
+    _check(_lib.agis_kernel_times(ctx, ms), ctx)
+    return dict(zip(["source_update", "ac_pass", "band_solve", "calib_solve", "frame"], ms[:]))
+
+
+class Solver:
+    """Owns one context; the problem is described by a synth.World-like
+    object (consts, knots, observation columns, parameter arrays)."""
+
+    def __init__(self, consts, knots, precision=AGIS_FP64, device=0, stream=None):
+        self.ctx = agis_create(consts, knots, precision, device, stream)
+
+    def close(self):
+        if self.ctx is not None:
+            agis_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

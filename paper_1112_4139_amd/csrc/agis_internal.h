@@ -1,0 +1,127 @@
+// Internal context of libagis and the kernel launchers shared by the host
+// API (capi.hip) and the kernels (kernels.hip, store.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/agis.h"
+#include "model.h"
+
+namespace agis {
+
+// Per-segment description of the attitude band systems (Sect. 5.2.2).
+struct SegDesc {
+    int64_t n_lo, n_hi;        // coefficient range of the segment system
+    int64_t keep_lo, keep_hi;  // coefficients whose updates this segment supplies
+    int64_t u_off;             // offset (in rows of 16) of its factor storage
+};
+
+// Number of sums per knot interval produced by the A/C pass: 10 block pairs
+// (n <= m among the four B-splines) x 10 unique entries of the symmetric 4x4
+// block, then 4 x 4 right-hand-side entries.
+constexpr int IV_PAIRS = 10;
+constexpr int IV_SUMS = IV_PAIRS * 10 + 16;
+// calibration partial sums per interval: (sum W, sum W R) for fov +1 and -1
+constexpr int IV_CAL = 4;
+
+struct Timers {
+    hipEvent_t ev[10][2];
+    bool valid[10];
+};
+
+}  // namespace agis
+
+struct agis_ctx {
+    agis_config_t cfg;
+    std::string err;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    agis::DevConsts k;
+
+    // knots
+    int64_t n_knots = 0, N = 0, K = 0;   // N coefficients, K = N - 3 intervals
+    std::vector<double> h_knots;
+    double* knots = nullptr;
+
+    // observation store
+    bool loaded = false;
+    int64_t n_obs = 0, n_src = 0, n_cells = 0;
+    // by (source, time)
+    double* s_t = nullptr;
+    double* s_eta = nullptr;
+    float* s_sig = nullptr;
+    int32_t* s_cell = nullptr;
+    int32_t* s_ell = nullptr;
+    int64_t* src_off = nullptr;          // [n_src + 1]
+    // by time
+    double* t_t = nullptr;
+    double* t_eta = nullptr;
+    float* t_sig = nullptr;
+    int32_t* t_cellfov = nullptr;         // cell * 2 + (fov < 0)
+    int32_t* t_src = nullptr;
+    int32_t* t_perm = nullptr;           // input index of each time-ordered observation
+    int64_t* iv_off = nullptr;           // [K + 1]
+    int32_t* iv_cell = nullptr;          // [K][2] cell of the fov +1 / -1 observations (-1: none)
+    int32_t* cell_iv = nullptr;          // [n_cells][2] interval range [lo, hi) of each cell
+
+    // parameters
+    double* s = nullptr;                 // [n_src][5]
+    double* a = nullptr;                 // [N][4]
+    double* c = nullptr;                 // [n_cells]
+    agis::SrcPrep* prep = nullptr;       // [n_src]
+    double* s_ref = nullptr;             // [n_src][5] frame reference (optional)
+    bool have_ref = false;
+
+    // work arrays
+    double* ds = nullptr;                // [n_src][5] last source update
+    double* qsrc = nullptr;              // [n_src] Q_i after the S solve
+    int32_t* sdef = nullptr;             // [n_src] defect per source
+    double* iv_sums = nullptr;           // [K][IV_SUMS]
+    double* iv_cal = nullptr;            // [K][IV_CAL]
+    double* da = nullptr;                // [N][4]
+    double* dc = nullptr;                // [n_cells]
+    int32_t* seg_def = nullptr;          // [n_seg]
+    std::vector<agis::SegDesc> h_segs;
+    agis::SegDesc* segs = nullptr;
+    double* ufac = nullptr;              // factor rows: [sum_seg 4*(n_hi-n_lo+1)][16]
+    double* yfac = nullptr;              // forward-substituted right-hand sides
+    int64_t ufac_rows = 0;
+    double* red = nullptr;               // reduction scratch
+    int64_t red_len = 0;
+    double* eo = nullptr;                // [8] frame rotator parameters on device
+    double* stat = nullptr;              // statistics scratch
+
+    agis::Timers tm;
+    double last_ms[5] = {0, 0, 0, 0, 0};
+};
+
+namespace agis {
+
+int set_error(agis_ctx* ctx, int code, const std::string& msg);
+int hip_check(agis_ctx* ctx, hipError_t e, const char* what);
+
+// store.hip
+int build_store(agis_ctx* ctx, const agis_obs_soa_t* obs, int where);
+
+// kernels.hip
+void launch_prep_sources(agis_ctx* ctx);
+void launch_source_update(agis_ctx* ctx);
+void launch_ac_pass(agis_ctx* ctx);
+void launch_band_solve(agis_ctx* ctx);
+void launch_calib_solve(agis_ctx* ctx);
+void launch_apply_attitude(agis_ctx* ctx);
+void launch_apply_calibration(agis_ctx* ctx);
+void launch_frame_fit(agis_ctx* ctx);
+void launch_frame_apply(agis_ctx* ctx);
+void launch_residuals(agis_ctx* ctx, double* R_input_order);
+// statistics over n rows of width w (rms and max per column, col < 5);
+// out[0..4] = rms, out[5..9] = max, out[10] = scalar sum of extra (or 0)
+void launch_stats(agis_ctx* ctx, const double* x, int64_t n, int w, const double* extra, const int32_t* iextra,
+                  double* out);
+
+}  // namespace agis

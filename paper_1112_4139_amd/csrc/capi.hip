@@ -1,0 +1,646 @@
+// C ABI of libagis (include/agis.h): context, parameters, update blocks,
+// frame rotator and the simple-iteration driver.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "agis_internal.h"
+
+namespace agis {
+
+int set_error(agis_ctx* ctx, int code, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+int hip_check(agis_ctx* ctx, hipError_t e, const char* what) {
+    if (e == hipSuccess) return AGIS_OK;
+    return set_error(ctx, e == hipErrorOutOfMemory ? AGIS_E_OOM : AGIS_E_DEVICE,
+                     std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace agis
+
+using namespace agis;
+
+static std::string g_create_error;
+
+#define HIPCHK(expr)                                            \
+    do {                                                        \
+        int rc_ = hip_check(ctx, (expr), #expr);                \
+        if (rc_ != AGIS_OK) return rc_;                         \
+    } while (0)
+
+#define CHECK_CTX()                                                              \
+    do {                                                                         \
+        if (!ctx) return AGIS_E_INVALID_ARG;                                     \
+        ctx->err.clear();                                                        \
+        int rc_ = hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");     \
+        if (rc_ != AGIS_OK) return rc_;                                          \
+    } while (0)
+
+#define REQUIRE_LOADED()                                                                        \
+    do {                                                                                        \
+        if (!ctx->loaded) return set_error(ctx, AGIS_E_STATE, "observations not loaded");       \
+    } while (0)
+
+template <typename T>
+static int dalloc(agis_ctx* ctx, T** p, size_t n, const char* what) {
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return set_error(ctx, AGIS_E_OOM, std::string("device allocation failed: ") + what);
+    }
+    return AGIS_OK;
+}
+
+#define ALLOC(p, n, what)                                       \
+    do {                                                        \
+        int rc_ = dalloc(ctx, &(p), (size_t)(n), what);         \
+        if (rc_ != AGIS_OK) return rc_;                         \
+    } while (0)
+
+template <typename T>
+static void dfree(T*& p) {
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+static void free_store(agis_ctx* ctx) {
+    dfree(ctx->s_t);
+    dfree(ctx->s_eta);
+    dfree(ctx->s_sig);
+    dfree(ctx->s_cell);
+    dfree(ctx->s_ell);
+    dfree(ctx->src_off);
+    dfree(ctx->t_t);
+    dfree(ctx->t_eta);
+    dfree(ctx->t_sig);
+    dfree(ctx->t_cellfov);
+    dfree(ctx->t_src);
+    dfree(ctx->t_perm);
+    dfree(ctx->iv_off);
+    dfree(ctx->iv_cell);
+    dfree(ctx->cell_iv);
+    dfree(ctx->s);
+    dfree(ctx->c);
+    dfree(ctx->prep);
+    dfree(ctx->s_ref);
+    dfree(ctx->ds);
+    dfree(ctx->qsrc);
+    dfree(ctx->sdef);
+    dfree(ctx->dc);
+    ctx->loaded = false;
+    ctx->have_ref = false;
+}
+
+static int copy_in(agis_ctx* ctx, void* dst, const void* src, size_t bytes, int where) {
+    if (where != AGIS_HOST && where != AGIS_DEVICE) return set_error(ctx, AGIS_E_INVALID_ARG, "bad 'where'");
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, where == AGIS_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                          ctx->stream));
+    if (where == AGIS_HOST) HIPCHK(hipStreamSynchronize(ctx->stream));
+    return AGIS_OK;
+}
+
+static int copy_out(agis_ctx* ctx, void* dst, const void* src, size_t bytes, int where) {
+    if (where != AGIS_HOST && where != AGIS_DEVICE) return set_error(ctx, AGIS_E_INVALID_ARG, "bad 'where'");
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, where == AGIS_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return AGIS_OK;
+}
+
+extern "C" int agis_version(void) { return AGIS_VERSION; }
+
+extern "C" const char* agis_last_error(const agis_ctx_t* ctx) {
+    if (!ctx) return g_create_error.c_str();
+    return ctx->err.c_str();
+}
+
+// Segments of Sect. 5.2.2: segment K uses the knot intervals of
+// [tau_{x_K - L}, tau_{x_{K+1} + L}) and supplies the updates of
+// x_K - 1 <= n <= x_{K+1} - 2 (M = 4); x_K = 3 + K * seg_len.
+static void build_segments(agis_ctx* ctx) {
+    const int64_t N = ctx->N, K = ctx->K;
+    const int64_t S = ctx->cfg.seg_len, L = ctx->cfg.seg_overlap;
+    const int64_t nseg = (K + S - 1) / S;
+    ctx->h_segs.clear();
+    int64_t off = 0;
+    for (int64_t s = 0; s < nseg; ++s) {
+        const int64_t x0 = 3 + s * S;
+        const int64_t x1 = s + 1 < nseg ? x0 + S : N;
+        int64_t lo = s == 0 ? 3 : x0 - L;
+        int64_t hi = s + 1 < nseg ? x1 + L : N;
+        lo = std::max<int64_t>(lo, 3);
+        hi = std::min<int64_t>(hi, N);
+        SegDesc d;
+        d.n_lo = lo - 3;
+        d.n_hi = hi - 1;
+        d.keep_lo = s == 0 ? 0 : x0 - 1;
+        d.keep_hi = s + 1 < nseg ? x1 - 2 : N - 1;
+        d.u_off = off;
+        off += 4 * (d.n_hi - d.n_lo + 1);
+        ctx->h_segs.push_back(d);
+    }
+    ctx->ufac_rows = off;
+}
+
+extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
+    g_create_error.clear();
+    if (!cfg || !out) {
+        g_create_error = "null argument";
+        return AGIS_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    if (cfg->n_knots < 8 || !cfg->knots) {
+        g_create_error = "need at least 8 knots (order 4, one interval)";
+        return AGIS_E_SHAPE;
+    }
+    for (int64_t i = 1; i < cfg->n_knots; ++i) {
+        if (!(cfg->knots[i] >= cfg->knots[i - 1])) {
+            g_create_error = "knot sequence must be non-decreasing and finite";
+            return AGIS_E_INVALID_ARG;
+        }
+    }
+    if (!(cfg->knots[cfg->n_knots - 4] > cfg->knots[3])) {
+        g_create_error = "empty spline interval";
+        return AGIS_E_SHAPE;
+    }
+    if (cfg->seg_len < 1 || cfg->seg_overlap < 0) {
+        g_create_error = "seg_len must be >= 1 and seg_overlap >= 0";
+        return AGIS_E_INVALID_ARG;
+    }
+    if (cfg->precision != AGIS_FP64 && cfg->precision != AGIS_MIXED) {
+        g_create_error = "precision must be AGIS_FP64 or AGIS_MIXED";
+        return AGIS_E_INVALID_ARG;
+    }
+    if (cfg->precision == AGIS_MIXED) {
+        g_create_error = "AGIS_MIXED is not available in this build";
+        return AGIS_E_INVALID_ARG;
+    }
+    if (!(cfg->year_s > 0) || !(cfg->c_mps > 0) || !(cfg->au_m > 0)) {
+        g_create_error = "year_s, c_mps and au_m must be positive";
+        return AGIS_E_INVALID_ARG;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) {
+        g_create_error = "no such HIP device";
+        return AGIS_E_DEVICE;
+    }
+    agis_ctx* ctx = new (std::nothrow) agis_ctx();
+    if (!ctx) {
+        g_create_error = "out of host memory";
+        return AGIS_E_OOM;
+    }
+    ctx->cfg = *cfg;
+    ctx->cfg.knots = nullptr;
+    ctx->device = cfg->device;
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+        g_create_error = "hipSetDevice failed";
+        delete ctx;
+        return AGIS_E_DEVICE;
+    }
+    if (cfg->stream) {
+        ctx->stream = (hipStream_t)cfg->stream;
+    } else {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            g_create_error = "hipStreamCreate failed";
+            delete ctx;
+            return AGIS_E_DEVICE;
+        }
+        ctx->own_stream = true;
+    }
+    ctx->n_knots = cfg->n_knots;
+    ctx->N = cfg->n_knots - 4;
+    ctx->K = ctx->N - 3;
+    ctx->h_knots.assign(cfg->knots, cfg->knots + cfg->n_knots);
+    DevConsts& k = ctx->k;
+    k.gamma_half = 0.5 * cfg->gamma_c;
+    k.t_ep = cfg->t_ep;
+    k.t_fr = cfg->t_fr;
+    k.inv_year = 1.0 / cfg->year_s;
+    k.year_s = cfg->year_s;
+    k.au_c = cfg->au_m / cfg->c_mps;
+    k.lam2 = cfg->lambda_reg * cfg->lambda_reg;
+    k.eph_r = cfg->eph_radius_au;
+    k.eph_L0 = cfg->eph_L0;
+    k.eph_Lrate = cfg->eph_Lrate;
+    k.cos_obl = std::cos(cfg->eps_obl);
+    k.sin_obl = std::sin(cfg->eps_obl);
+    build_segments(ctx);
+    int rc = AGIS_OK;
+    auto fail = [&](int code) {
+        g_create_error = ctx->err;
+        agis_destroy(ctx);
+        return code;
+    };
+    if ((rc = dalloc(ctx, &ctx->knots, ctx->n_knots, "knots")) != AGIS_OK) return fail(rc);
+    if ((rc = dalloc(ctx, &ctx->a, 4 * ctx->N, "attitude")) != AGIS_OK) return fail(rc);
+    if ((rc = dalloc(ctx, &ctx->da, 4 * ctx->N, "attitude update")) != AGIS_OK) return fail(rc);
+    if ((rc = dalloc(ctx, &ctx->iv_sums, (size_t)IV_SUMS * ctx->K, "interval sums")) != AGIS_OK) return fail(rc);
+    if ((rc = dalloc(ctx, &ctx->iv_cal, (size_t)IV_CAL * ctx->K, "interval calibration sums")) != AGIS_OK)
+        return fail(rc);
+    if ((rc = dalloc(ctx, &ctx->segs, ctx->h_segs.size(), "segments")) != AGIS_OK) return fail(rc);
+    if ((rc = dalloc(ctx, &ctx->seg_def, ctx->h_segs.size(), "segment defects")) != AGIS_OK) return fail(rc);
+    if ((rc = dalloc(ctx, &ctx->ufac, (size_t)16 * ctx->ufac_rows, "band factor")) != AGIS_OK) return fail(rc);
+    if ((rc = dalloc(ctx, &ctx->yfac, (size_t)ctx->ufac_rows, "band rhs")) != AGIS_OK) return fail(rc);
+    ctx->red_len = 1 << 16;
+    if ((rc = dalloc(ctx, &ctx->red, ctx->red_len, "reduction scratch")) != AGIS_OK) return fail(rc);
+    if ((rc = dalloc(ctx, &ctx->eo, 8, "frame parameters")) != AGIS_OK) return fail(rc);
+    if ((rc = dalloc(ctx, &ctx->stat, 64, "statistics")) != AGIS_OK) return fail(rc);
+    if (hipMemcpy(ctx->knots, cfg->knots, ctx->n_knots * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ctx->segs, ctx->h_segs.data(), ctx->h_segs.size() * sizeof(SegDesc), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemset(ctx->da, 0, 4 * ctx->N * sizeof(double)) != hipSuccess ||
+        hipMemset(ctx->eo, 0, 8 * sizeof(double)) != hipSuccess) {
+        ctx->err = "initial copies failed";
+        return fail(AGIS_E_DEVICE);
+    }
+    for (int e = 0; e < 10; ++e) {
+        ctx->tm.valid[e] = false;
+        if (hipEventCreate(&ctx->tm.ev[e][0]) != hipSuccess || hipEventCreate(&ctx->tm.ev[e][1]) != hipSuccess) {
+            ctx->err = "hipEventCreate failed";
+            return fail(AGIS_E_DEVICE);
+        }
+    }
+    *out = ctx;
+    return AGIS_OK;
+}
+
+extern "C" void agis_destroy(agis_ctx_t* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    free_store(ctx);
+    dfree(ctx->knots);
+    dfree(ctx->a);
+    dfree(ctx->da);
+    dfree(ctx->iv_sums);
+    dfree(ctx->iv_cal);
+    dfree(ctx->segs);
+    dfree(ctx->seg_def);
+    dfree(ctx->ufac);
+    dfree(ctx->yfac);
+    dfree(ctx->red);
+    dfree(ctx->eo);
+    dfree(ctx->stat);
+    for (int e = 0; e < 10; ++e) {
+        if (ctx->tm.ev[e][0]) (void)hipEventDestroy(ctx->tm.ev[e][0]);
+        if (ctx->tm.ev[e][1]) (void)hipEventDestroy(ctx->tm.ev[e][1]);
+    }
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+extern "C" int agis_load_observations(agis_ctx_t* ctx, const agis_obs_soa_t* obs, int64_t n_src, int64_t n_cells,
+                                      int where) {
+    CHECK_CTX();
+    if (!obs || n_src < 0 || n_cells < 0 || obs->n < 0) return set_error(ctx, AGIS_E_INVALID_ARG, "bad arguments");
+    if (obs->n > 0 && (!obs->t || !obs->eta_obs || !obs->sigma || !obs->src || !obs->fov || !obs->cell))
+        return set_error(ctx, AGIS_E_INVALID_ARG, "null observation column");
+    if (obs->n >= (int64_t)1 << 31) return set_error(ctx, AGIS_E_SHAPE, "at most 2^31 - 1 observations");
+    if (where != AGIS_HOST && where != AGIS_DEVICE) return set_error(ctx, AGIS_E_INVALID_ARG, "bad 'where'");
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    free_store(ctx);
+    ctx->n_obs = obs->n;
+    ctx->n_src = n_src;
+    ctx->n_cells = n_cells;
+    ALLOC(ctx->s, 5 * n_src, "sources");
+    ALLOC(ctx->c, n_cells, "calibration");
+    ALLOC(ctx->prep, n_src, "source prep");
+    ALLOC(ctx->ds, 5 * n_src, "source updates");
+    ALLOC(ctx->qsrc, n_src, "source chi2");
+    ALLOC(ctx->sdef, n_src, "source defects");
+    ALLOC(ctx->dc, n_cells, "calibration updates");
+    HIPCHK(hipMemsetAsync(ctx->s, 0, 5 * std::max<int64_t>(n_src, 1) * sizeof(double), ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->c, 0, std::max<int64_t>(n_cells, 1) * sizeof(double), ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->dc, 0, std::max<int64_t>(n_cells, 1) * sizeof(double), ctx->stream));
+    int rc = build_store(ctx, obs, where);
+    if (rc != AGIS_OK) {
+        std::string keep = ctx->err;
+        free_store(ctx);
+        ctx->err = keep;
+        return rc;
+    }
+    launch_prep_sources(ctx);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->loaded = true;
+    return AGIS_OK;
+}
+
+static int check_finite_host(agis_ctx* ctx, const double* x, int64_t n, int where) {
+    if (where != AGIS_HOST) return AGIS_OK;
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(x[i])) return set_error(ctx, AGIS_E_NUMERIC, "non-finite parameter value");
+    return AGIS_OK;
+}
+
+extern "C" int agis_set_sources(agis_ctx_t* ctx, int64_t n, const double* s5, int where) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    if (n != ctx->n_src || (!s5 && n > 0)) return set_error(ctx, AGIS_E_SHAPE, "source count mismatch");
+    int rc = check_finite_host(ctx, s5, 5 * n, where);
+    if (rc) return rc;
+    rc = copy_in(ctx, ctx->s, s5, 5 * n * sizeof(double), where);
+    if (rc) return rc;
+    launch_prep_sources(ctx);
+    HIPCHK(hipGetLastError());
+    return AGIS_OK;
+}
+
+extern "C" int agis_get_sources(agis_ctx_t* ctx, int64_t n, double* s5, int where) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    if (n != ctx->n_src || (!s5 && n > 0)) return set_error(ctx, AGIS_E_SHAPE, "source count mismatch");
+    return copy_out(ctx, s5, ctx->s, 5 * n * sizeof(double), where);
+}
+
+extern "C" int agis_set_attitude(agis_ctx_t* ctx, int64_t n, const double* a4, int where) {
+    CHECK_CTX();
+    if (n != ctx->N || !a4) return set_error(ctx, AGIS_E_SHAPE, "attitude coefficient count must be n_knots - 4");
+    int rc = check_finite_host(ctx, a4, 4 * n, where);
+    if (rc) return rc;
+    return copy_in(ctx, ctx->a, a4, 4 * n * sizeof(double), where);
+}
+
+extern "C" int agis_get_attitude(agis_ctx_t* ctx, int64_t n, double* a4, int where) {
+    CHECK_CTX();
+    if (n != ctx->N || !a4) return set_error(ctx, AGIS_E_SHAPE, "attitude coefficient count must be n_knots - 4");
+    return copy_out(ctx, a4, ctx->a, 4 * n * sizeof(double), where);
+}
+
+extern "C" int agis_set_calibration(agis_ctx_t* ctx, int64_t n, const double* c, int where) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    if (n != ctx->n_cells || (!c && n > 0)) return set_error(ctx, AGIS_E_SHAPE, "cell count mismatch");
+    int rc = check_finite_host(ctx, c, n, where);
+    if (rc) return rc;
+    return copy_in(ctx, ctx->c, c, n * sizeof(double), where);
+}
+
+extern "C" int agis_get_calibration(agis_ctx_t* ctx, int64_t n, double* c, int where) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    if (n != ctx->n_cells || (!c && n > 0)) return set_error(ctx, AGIS_E_SHAPE, "cell count mismatch");
+    return copy_out(ctx, c, ctx->c, n * sizeof(double), where);
+}
+
+// --- timing and statistics helpers -----------------------------------------
+enum { T_S = 0, T_AC = 1, T_BAND = 2, T_CAL = 3, T_FRAME = 4, T_ITER = 5 };
+
+static void tstart(agis_ctx* ctx, int e) { (void)hipEventRecord(ctx->tm.ev[e][0], ctx->stream); }
+static void tstop(agis_ctx* ctx, int e) {
+    (void)hipEventRecord(ctx->tm.ev[e][1], ctx->stream);
+    ctx->tm.valid[e] = true;
+}
+static double tget(agis_ctx* ctx, int e) {
+    if (!ctx->tm.valid[e]) return 0.0;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, ctx->tm.ev[e][0], ctx->tm.ev[e][1]) != hipSuccess) return 0.0;
+    return (double)ms;
+}
+
+static int fill_stats(agis_ctx* ctx, agis_block_stats_t* st, const double* x, int64_t n, int w,
+                      const double* extra, const int32_t* iextra, int64_t n_obs, int64_t n_units) {
+    if (!st) return AGIS_OK;
+    launch_stats(ctx, x, n, w, extra, iextra, ctx->stat);
+    HIPCHK(hipGetLastError());
+    double h[12];
+    HIPCHK(hipMemcpyAsync(h, ctx->stat, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    std::memset(st, 0, sizeof(*st));
+    for (int e = 0; e < 5; ++e) {
+        st->rms_update[e] = h[e];
+        st->max_update[e] = h[5 + e];
+    }
+    st->chi2 = h[10];
+    st->defect = (int64_t)std::llround(h[11]);
+    st->n_obs = n_obs;
+    st->n_units = n_units;
+    return AGIS_OK;
+}
+
+static int run_source(agis_ctx* ctx) {
+    tstart(ctx, T_S);
+    launch_source_update(ctx);
+    HIPCHK(hipGetLastError());
+    tstop(ctx, T_S);
+    return AGIS_OK;
+}
+
+// A/C accumulation pass followed by the requested solves.  The A update is
+// applied only after the C solve has read the interval sums, so both blocks
+// see the same parameters (S[AC]).
+static int run_ac(agis_ctx* ctx, bool do_a, bool do_c) {
+    tstart(ctx, T_AC);
+    launch_ac_pass(ctx);
+    HIPCHK(hipGetLastError());
+    tstop(ctx, T_AC);
+    if (do_a) {
+        tstart(ctx, T_BAND);
+        launch_band_solve(ctx);
+        HIPCHK(hipGetLastError());
+        tstop(ctx, T_BAND);
+    }
+    if (do_c) {
+        tstart(ctx, T_CAL);
+        launch_calib_solve(ctx);
+        HIPCHK(hipGetLastError());
+        tstop(ctx, T_CAL);
+    }
+    if (do_a) launch_apply_attitude(ctx);
+    if (do_c) launch_apply_calibration(ctx);
+    HIPCHK(hipGetLastError());
+    return AGIS_OK;
+}
+
+static int stats_s(agis_ctx* ctx, agis_block_stats_t* st) {
+    if (!st) return AGIS_OK;
+    int rc = fill_stats(ctx, st, ctx->ds, ctx->n_src, 5, ctx->qsrc, ctx->sdef, ctx->n_obs, ctx->n_src);
+    if (rc == AGIS_OK) st->ms = tget(ctx, T_S);
+    return rc;
+}
+static int stats_a(agis_ctx* ctx, agis_block_stats_t* st) {
+    if (!st) return AGIS_OK;
+    int rc = fill_stats(ctx, st, ctx->da, ctx->N, 4, nullptr, nullptr, ctx->n_obs, ctx->N);
+    if (rc) return rc;
+    // summed rank-defect count over the segments
+    agis_block_stats_t tmp;
+    rc = fill_stats(ctx, &tmp, nullptr, (int64_t)ctx->h_segs.size(), 0, nullptr, ctx->seg_def, 0, 0);
+    if (rc) return rc;
+    st->defect = tmp.defect;
+    st->ms = tget(ctx, T_AC) + tget(ctx, T_BAND);
+    return AGIS_OK;
+}
+static int stats_c(agis_ctx* ctx, agis_block_stats_t* st) {
+    if (!st) return AGIS_OK;
+    int rc = fill_stats(ctx, st, ctx->dc, ctx->n_cells, 1, nullptr, nullptr, ctx->n_obs, ctx->n_cells);
+    if (rc == AGIS_OK) st->ms = tget(ctx, T_CAL);
+    return rc;
+}
+
+extern "C" int agis_source_update(agis_ctx_t* ctx, agis_block_stats_t* st) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    int rc = run_source(ctx);
+    if (rc) return rc;
+    rc = stats_s(ctx, st);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return AGIS_OK;
+}
+
+extern "C" int agis_attitude_update(agis_ctx_t* ctx, agis_block_stats_t* st) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    int rc = run_ac(ctx, true, false);
+    if (rc) return rc;
+    rc = stats_a(ctx, st);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return AGIS_OK;
+}
+
+extern "C" int agis_calibration_update(agis_ctx_t* ctx, agis_block_stats_t* st) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    int rc = run_ac(ctx, false, true);
+    if (rc) return rc;
+    rc = stats_c(ctx, st);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return AGIS_OK;
+}
+
+extern "C" int agis_attitude_calibration_update(agis_ctx_t* ctx, agis_block_stats_t* st_a, agis_block_stats_t* st_c) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    int rc = run_ac(ctx, true, true);
+    if (rc) return rc;
+    if ((rc = stats_a(ctx, st_a))) return rc;
+    if ((rc = stats_c(ctx, st_c))) return rc;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return AGIS_OK;
+}
+
+extern "C" int agis_set_frame_reference(agis_ctx_t* ctx, int64_t n, const double* s_ref5, int where) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    if (n != ctx->n_src) return set_error(ctx, AGIS_E_SHAPE, "reference catalogue size must equal n_src");
+    if (!s_ref5) {
+        ctx->have_ref = false;
+        return AGIS_OK;
+    }
+    int rc = check_finite_host(ctx, s_ref5, 5 * n, where);
+    if (rc) return rc;
+    if (!ctx->s_ref) ALLOC(ctx->s_ref, 5 * std::max<int64_t>(n, 1), "frame reference");
+    rc = copy_in(ctx, ctx->s_ref, s_ref5, 5 * n * sizeof(double), where);
+    if (rc) return rc;
+    ctx->have_ref = true;
+    return AGIS_OK;
+}
+
+extern "C" int agis_frame_fit(agis_ctx_t* ctx, double eps_omega[6]) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    if (!ctx->have_ref) return set_error(ctx, AGIS_E_STATE, "no frame reference set");
+    launch_frame_fit(ctx);
+    HIPCHK(hipGetLastError());
+    if (eps_omega) {
+        HIPCHK(hipMemcpyAsync(eps_omega, ctx->eo, 6 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return AGIS_OK;
+}
+
+extern "C" int agis_frame_apply(agis_ctx_t* ctx, const double eps_omega[6]) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    if (!eps_omega) return set_error(ctx, AGIS_E_INVALID_ARG, "null eps_omega");
+    for (int e = 0; e < 6; ++e)
+        if (!std::isfinite(eps_omega[e])) return set_error(ctx, AGIS_E_NUMERIC, "non-finite frame parameter");
+    HIPCHK(hipMemcpyAsync(ctx->eo, eps_omega, 6 * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    launch_frame_apply(ctx);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return AGIS_OK;
+}
+
+extern "C" int agis_iterate(agis_ctx_t* ctx, int32_t n_iter, agis_iter_stats_t* per_iter) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    if (n_iter < 0) return set_error(ctx, AGIS_E_INVALID_ARG, "n_iter < 0");
+    for (int32_t it = 0; it < n_iter; ++it) {
+        agis_iter_stats_t* st = per_iter ? per_iter + it : nullptr;
+        tstart(ctx, T_ITER);
+        int rc = run_source(ctx);
+        if (rc) return rc;
+        if (st && (rc = stats_s(ctx, &st->s))) return rc;
+        rc = run_ac(ctx, true, true);
+        if (rc) return rc;
+        if (st && (rc = stats_a(ctx, &st->a))) return rc;
+        if (st && (rc = stats_c(ctx, &st->c))) return rc;
+        if (ctx->have_ref) {
+            tstart(ctx, T_FRAME);
+            launch_frame_fit(ctx);
+            launch_frame_apply(ctx);
+            HIPCHK(hipGetLastError());
+            tstop(ctx, T_FRAME);
+        }
+        tstop(ctx, T_ITER);
+        if (st) {
+            if (ctx->have_ref) {
+                HIPCHK(hipMemcpyAsync(st->eps_omega, ctx->eo, 6 * sizeof(double), hipMemcpyDeviceToHost,
+                                      ctx->stream));
+            } else {
+                std::memset(st->eps_omega, 0, sizeof st->eps_omega);
+            }
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            st->ms = tget(ctx, T_ITER);
+        }
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->last_ms[0] = tget(ctx, T_S);
+    ctx->last_ms[1] = tget(ctx, T_AC);
+    ctx->last_ms[2] = tget(ctx, T_BAND);
+    ctx->last_ms[3] = tget(ctx, T_CAL);
+    ctx->last_ms[4] = tget(ctx, T_FRAME);
+    return AGIS_OK;
+}
+
+extern "C" int agis_residuals(agis_ctx_t* ctx, double* R, int where) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    if (!R && ctx->n_obs > 0) return set_error(ctx, AGIS_E_INVALID_ARG, "null R");
+    if (where != AGIS_HOST && where != AGIS_DEVICE) return set_error(ctx, AGIS_E_INVALID_ARG, "bad 'where'");
+    double* dR = R;
+    if (where == AGIS_HOST) ALLOC(dR, ctx->n_obs, "residuals");
+    launch_residuals(ctx, dR);
+    int rc = hip_check(ctx, hipGetLastError(), "residual kernel");
+    if (rc == AGIS_OK && where == AGIS_HOST)
+        rc = hip_check(ctx, hipMemcpyAsync(R, dR, ctx->n_obs * sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+                       "copy residuals");
+    if (rc == AGIS_OK) rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync");
+    if (where == AGIS_HOST) (void)hipFree(dR);
+    return rc;
+}
+
+extern "C" int agis_problem_size(const agis_ctx_t* ctx, int64_t* n_obs, int64_t* n_src, int64_t* n_att,
+                                 int64_t* n_cells, int64_t* n_segments) {
+    if (!ctx) return AGIS_E_INVALID_ARG;
+    if (n_obs) *n_obs = ctx->n_obs;
+    if (n_src) *n_src = ctx->n_src;
+    if (n_att) *n_att = ctx->N;
+    if (n_cells) *n_cells = ctx->n_cells;
+    if (n_segments) *n_segments = (int64_t)ctx->h_segs.size();
+    return AGIS_OK;
+}
+
+extern "C" int agis_kernel_times(const agis_ctx_t* ctx, double ms[5]) {
+    if (!ctx || !ms) return AGIS_E_INVALID_ARG;
+    for (int e = 0; e < 5; ++e) ms[e] = ctx->last_ms[e];
+    return AGIS_OK;
+}

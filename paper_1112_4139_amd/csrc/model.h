@@ -1,0 +1,282 @@
+// Device-side observation model of the astrometric core solution for one
+// along-scan observation: proper direction (Sect. 3.2), attitude quaternion
+// from the cubic B-spline (Sect. 3.3, Appendix B), instrument angles and
+// field angle (eq:srsprop1, eq:srspropeta), residual (eq:resAL), and the
+// partial derivatives used by the S and A blocks (Sect. 5.1.3, 5.2.3-5.2.4).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace agis {
+
+// Per-run constants, passed by value to every kernel.
+struct DevConsts {
+    double gamma_half;   // Gamma_c / 2
+    double t_ep;         // reference epoch [s]
+    double inv_year;     // 1 / year [1/s]
+    double au_c;         // light time for one astronomical unit [s]
+    double lam2;         // lambda^2 of the attitude regularisation
+    double eph_r, eph_L0, eph_Lrate, cos_obl, sin_obl;
+    double t_fr;
+    double year_s;
+};
+
+// Source data gathered per observation by the time-ordered pass: barycentric
+// direction r at t_ep, proper-motion vector p mu_a* + q mu_d, parallax.
+struct SrcPrep {
+    double r[3];
+    double mu[3];
+    double plx;
+    double pad;
+};
+
+__device__ __forceinline__ double dot3(const double* a, const double* b) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// Barycentric position [AU] and velocity [AU/s] of the observer on the
+// circular orbit of the synthetic world.
+__device__ __forceinline__ void ephemeris(const DevConsts& k, double t, double b[3], double v[3]) {
+    double sL, cL;
+    sincos(k.eph_L0 + k.eph_Lrate * t, &sL, &cL);
+    double bx = k.eph_r * cL, by = k.eph_r * sL;
+    b[0] = bx;
+    b[1] = k.cos_obl * by;
+    b[2] = k.sin_obl * by;
+    double w = k.eph_r * k.eph_Lrate;
+    double vx = -w * sL, vy = w * cL;
+    v[0] = vx;
+    v[1] = k.cos_obl * vy;
+    v[2] = k.sin_obl * vy;
+}
+
+// The four non-zero cubic B-splines B_{l-3..l}(t) by de Boor's recurrence
+// (Algorithm B1, M = 4); kn points at tau_{l-2}, so kn[0..5] = tau_{l-2..l+3}.
+__device__ __forceinline__ void bspline4(const double* __restrict__ kn, double t, double B[4]) {
+    // R_i = tau_{l+i+1} - t ; L_i = t - tau_{l-i}
+    const double R0 = kn[3] - t, R1 = kn[4] - t, R2 = kn[5] - t;
+    const double L0 = t - kn[2], L1 = t - kn[1], L2 = t - kn[0];
+    double b0 = 1.0, b1, b2, b3, s, u;
+    // i = 0
+    u = b0 / (R0 + L0);
+    b0 = R0 * u;
+    b1 = L0 * u;
+    // i = 1
+    u = b0 / (R0 + L1);
+    b0 = R0 * u;
+    s = L1 * u;
+    u = b1 / (R1 + L0);
+    b1 = s + R1 * u;
+    b2 = L0 * u;
+    // i = 2
+    u = b0 / (R0 + L2);
+    b0 = R0 * u;
+    s = L2 * u;
+    u = b1 / (R1 + L1);
+    b1 = s + R1 * u;
+    s = L1 * u;
+    u = b2 / (R2 + L0);
+    b2 = s + R2 * u;
+    b3 = L0 * u;
+    B[0] = b0;
+    B[1] = b1;
+    B[2] = b2;
+    B[3] = b3;
+}
+
+// Attitude matrix A = S'C of a unit quaternion (eq:quat2mat), row-major.
+__device__ __forceinline__ void quat2mat(const double q[4], double A[9]) {
+    const double x = q[0], y = q[1], z = q[2], w = q[3];
+    A[0] = 1.0 - 2.0 * (y * y + z * z);
+    A[1] = 2.0 * (x * y + z * w);
+    A[2] = 2.0 * (x * z - y * w);
+    A[3] = 2.0 * (x * y - z * w);
+    A[4] = 1.0 - 2.0 * (x * x + z * z);
+    A[5] = 2.0 * (y * z + x * w);
+    A[6] = 2.0 * (x * z + y * w);
+    A[7] = 2.0 * (y * z - x * w);
+    A[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// Everything one observation contributes; filled by observe().
+struct ObsEval {
+    double R;          // residual eta_obs + c - eta
+    double ubar[3];    // coordinate direction <r + tau mu - plx b>
+    double vc[3];      // v_G / c
+    double b[3];       // observer position [AU]
+    double tau;        // (t_B - t_ep) [yr]
+    double Su[3];      // proper direction in the SRS
+    double rho;        // sqrt(Su_x^2 + Su_y^2) = cos(zeta)
+    double q[4];       // normalised attitude quaternion
+    double qraw[4];    // sum a_n B_n (not normalised)
+    double D;          // 1 - |qraw|^2 (eq:Dl)
+    double B[4];       // B_{l-3..l}(t)
+    double A[9];       // attitude matrix
+};
+
+// Observation model (eq:roemer, eq:astro-standard, eq:classAberr,
+// eq:qspline, eq:srsprop, eq:srsprop1, eq:srspropeta, eq:resAL).
+// a4: the four coefficients a_{l-3..l} (x,y,z,w each); kn: tau_{l-2..l+3}.
+__device__ __forceinline__ void observe(const DevConsts& k, double t, double eta_obs, double cal, const double r[3],
+                                        const double mu[3], double plx, const double* __restrict__ a4,
+                                        const double* __restrict__ kn, ObsEval& o) {
+    double v[3];
+    ephemeris(k, t, o.b, v);
+    const double tB = t + dot3(r, o.b) * k.au_c;
+    o.tau = (tB - k.t_ep) * k.inv_year;
+    double ub[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ub[c] = r[c] + o.tau * mu[c] - plx * o.b[c];
+    const double iub = 1.0 / sqrt(dot3(ub, ub));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        o.ubar[c] = ub[c] * iub;
+        o.vc[c] = v[c] * k.au_c;
+    }
+    double uu[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) uu[c] = o.ubar[c] + o.vc[c];
+    const double iuu = 1.0 / sqrt(dot3(uu, uu));
+    double u[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[c] = uu[c] * iuu;
+
+    bspline4(kn, t, o.B);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        o.qraw[c] = a4[c] * o.B[0] + a4[4 + c] * o.B[1] + a4[8 + c] * o.B[2] + a4[12 + c] * o.B[3];
+    const double n2 = o.qraw[0] * o.qraw[0] + o.qraw[1] * o.qraw[1] + o.qraw[2] * o.qraw[2] + o.qraw[3] * o.qraw[3];
+    o.D = 1.0 - n2;
+    const double iq = 1.0 / sqrt(n2);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) o.q[c] = o.qraw[c] * iq;
+    quat2mat(o.q, o.A);
+    o.Su[0] = o.A[0] * u[0] + o.A[1] * u[1] + o.A[2] * u[2];
+    o.Su[1] = o.A[3] * u[0] + o.A[4] * u[1] + o.A[5] * u[2];
+    o.Su[2] = o.A[6] * u[0] + o.A[7] * u[1] + o.A[8] * u[2];
+    o.rho = sqrt(o.Su[0] * o.Su[0] + o.Su[1] * o.Su[1]);
+    const double phi = atan2(o.Su[1], o.Su[0]);
+    const double eta = phi >= 0.0 ? phi - k.gamma_half : phi + k.gamma_half;
+    o.R = eta_obs + cal - eta;
+}
+
+// Design row -dR/ds for (alpha*, delta, parallax, mu_a*, mu_d):
+// eq:ubardiff, eq:duds, eq:srspropdiff with eq:srsprop1diffsol; the AL unit
+// vector m of eq:srspqr is taken back to celestial coordinates once.
+__device__ __forceinline__ void source_partials(const ObsEval& o, const double p[3], const double q[3],
+                                                const double r[3], double Ad[5]) {
+    const double inv_rho = 1.0 / o.rho;
+    const double ms0 = -o.Su[1] * inv_rho, ms1 = o.Su[0] * inv_rho;   // (-sin phi, cos phi, 0)
+    double m[3];
+    m[0] = o.A[0] * ms0 + o.A[3] * ms1;
+    m[1] = o.A[1] * ms0 + o.A[4] * ms1;
+    m[2] = o.A[2] * ms0 + o.A[5] * ms1;
+    const double f = 1.0 - dot3(o.ubar, o.vc);
+    const double mu_ = dot3(m, o.ubar);
+    const double rb = dot3(r, o.b);
+    double dpl[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dpl[c] = -(o.b[c] - r[c] * rb);
+    const double secz = inv_rho;
+    const double a0 = (f * dot3(m, p) - mu_ * dot3(o.vc, p)) * secz;
+    const double a1 = (f * dot3(m, q) - mu_ * dot3(o.vc, q)) * secz;
+    Ad[0] = a0;
+    Ad[1] = a1;
+    Ad[2] = (f * dot3(m, dpl) - mu_ * dot3(o.vc, dpl)) * secz;
+    Ad[3] = a0 * o.tau;
+    Ad[4] = a1 * o.tau;
+}
+
+// dR/dq = 2 sec(zeta) q {S'n, 0} (eq:dfadq), n of eq:srspqr.
+__device__ __forceinline__ void attitude_partial(const ObsEval& o, double g[4]) {
+    const double inv_rho = 1.0 / o.rho;
+    const double sz = o.Su[2];
+    const double n0 = -sz * o.Su[0] * inv_rho, n1 = -sz * o.Su[1] * inv_rho, n2 = o.rho;
+    const double* q = o.q;
+    // {q_v, q_w} {n, 0} = {q_w n + q_v x n, -q_v . n}
+    const double s = 2.0 * inv_rho;
+    g[0] = s * (q[3] * n0 + q[1] * n2 - q[2] * n1);
+    g[1] = s * (q[3] * n1 + q[2] * n0 - q[0] * n2);
+    g[2] = s * (q[3] * n2 + q[0] * n1 - q[1] * n0);
+    g[3] = s * (-(q[0] * n0 + q[1] * n1 + q[2] * n2));
+}
+
+// Modified Cholesky for a small dense symmetric system (Algorithms C1-C3
+// of Appendix C: zero pivots are skipped and counted, no pivoting).
+// U holds the upper triangle row-major n x n on entry; x the right-hand
+// side; returns the rank-defect count.
+template <int NN>
+__device__ __forceinline__ int small_chol_solve(double U[NN * NN], double x[NN]) {
+    int d = 0;
+#pragma unroll
+    for (int j = 0; j < NN; ++j) {
+#pragma unroll
+        for (int i = 0; i <= j; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < i; ++kk) s += U[kk * NN + i] * U[kk * NN + j];
+            if (i < j) {
+                U[i * NN + j] = U[i * NN + i] > 0.0 ? (U[i * NN + j] - s) / U[i * NN + i] : 0.0;
+            } else {
+                const double piv = U[j * NN + j] - s;
+                if (piv > 0.0) {
+                    U[j * NN + j] = sqrt(piv);
+                } else {
+                    U[j * NN + j] = 0.0;
+                    ++d;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NN; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < i; ++kk) s += U[kk * NN + i] * x[kk];
+        x[i] = U[i * NN + i] > 0.0 ? (x[i] - s) / U[i * NN + i] : 0.0;
+    }
+#pragma unroll
+    for (int i = NN - 1; i >= 0; --i) {
+        double s = 0.0;
+#pragma unroll
+        for (int kk = i + 1; kk < NN; ++kk) s += U[i * NN + kk] * x[kk];
+        x[i] = U[i * NN + i] > 0.0 ? (x[i] - s) / U[i * NN + i] : 0.0;
+    }
+    return d;
+}
+
+// Rotation quaternion Q(phi) of a rotation vector (eq:qrot).
+__device__ __forceinline__ void qrot(const double phi[3], double out[4]) {
+    const double ang = sqrt(phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2]);
+    if (ang > 0.0) {
+        double s, c;
+        sincos(0.5 * ang, &s, &c);
+        out[0] = phi[0] / ang * s;
+        out[1] = phi[1] / ang * s;
+        out[2] = phi[2] / ang * s;
+        out[3] = c;
+    } else {
+        out[0] = 0.0;
+        out[1] = 0.0;
+        out[2] = 0.0;
+        out[3] = 1.0;
+    }
+}
+
+// Hamilton product {x, y, z, w} (eq:quatmult).
+__device__ __forceinline__ void qmul(const double a[4], const double b[4], double o[4]) {
+    o[0] = a[3] * b[0] + a[0] * b[3] + a[1] * b[2] - a[2] * b[1];
+    o[1] = a[3] * b[1] - a[0] * b[2] + a[1] * b[3] + a[2] * b[0];
+    o[2] = a[3] * b[2] + a[0] * b[1] - a[1] * b[0] + a[2] * b[3];
+    o[3] = a[3] * b[3] - a[0] * b[0] - a[1] * b[1] - a[2] * b[2];
+}
+
+// Sum over the 64 lanes of a wavefront (butterfly; every lane gets the sum).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+}  // namespace agis

@@ -160,18 +160,34 @@ void syn_nominal_quat(const syn_law_t* w, int64_t n, const double* t, double* q)
  * Writes at most cap transits (times and fov +1 = preceding, -1 = following)
  * and returns the number found.
  */
-static int64_t transits_one(const syn_law_t* w, const double r_equ[3], double t0, double t1,
-                            double* tt, int8_t* ff, int64_t cap) {
+typedef struct {
+    int64_t nrev;
+    double* z;                 /* [nrev][3] spin axis at mid-revolution */
+} rev_table_t;
+
+static void rev_table_build(const syn_law_t* w, double t0, double t1, rev_table_t* tab) {
+    const double P = 2.0 * M_PI / w->wspin;
+    tab->nrev = (int64_t)ceil((t1 - t0) / P) + 1;
+    tab->z = (double*)malloc(sizeof(double) * 3 * (size_t)tab->nrev);
+    for (int64_t k = 0; k < tab->nrev; ++k) {
+        double e1[3], e2[3];
+        spin_frame(w, t0 + ((double)k + 0.5) * P, tab->z + 3 * k, e1, e2);
+    }
+}
+
+static int64_t transits_one(const syn_law_t* w, const rev_table_t* tab, const double r_equ[3], double t0,
+                            double t1, double* tt, int8_t* ff, int64_t cap) {
     double r[3];
     equ_to_ecl(w->eps_obl, r_equ, r);
     const double P = 2.0 * M_PI / w->wspin;
-    const double margin = sin(w->zeta_max) + 0.05;
+    /* the spin axis moves by less than 0.012 rad in half a revolution */
+    const double margin = sin(w->zeta_max) + 0.015 * (2.0 * M_PI / w->wspin) / 21600.0;
     int64_t nfound = 0;
-    double tk = t0;
-    for (int64_t k = 0; tk < t1; ++k, tk = t0 + (double)k * P) {
+    for (int64_t k = 0; k < tab->nrev; ++k) {
+        const double tk = t0 + (double)k * P;
+        if (tk >= t1) break;
+        if (fabs(dot3(r, tab->z + 3 * k)) > margin) continue;
         double z[3], e1[3], e2[3];
-        spin_frame(w, tk + 0.5 * P, z, e1, e2);
-        if (fabs(dot3(r, z)) > margin) continue;
         for (int fi = 0; fi < 2; ++fi) {
             int f = fi == 0 ? +1 : -1;
             /* initial guess within [tk, tk+P) */
@@ -179,7 +195,7 @@ static int64_t transits_one(const syn_law_t* w, const double r_equ[3], double t0
             double psi = atan2(dot3(r, e2), dot3(r, e1));
             double Om = w->Omega0 + w->wspin * tk;
             double t = tk + wrap_2pi(psi - f * 0.5 * w->gamma - Om) / w->wspin;
-            for (int it = 0; it < 4; ++it) {
+            for (int it = 0; it < 3; ++it) {
                 spin_frame(w, t, z, e1, e2);
                 psi = atan2(dot3(r, e2), dot3(r, e1));
                 Om = w->Omega0 + w->wspin * t;
@@ -211,15 +227,18 @@ static void sort_transits(double* t, int8_t* f, int64_t n) {
  */
 void syn_count_transits(const syn_law_t* w, int64_t nsrc, const double* ra, const double* dec,
                         double t0, double t1, int64_t* counts) {
+    rev_table_t tab;
+    rev_table_build(w, t0, t1, &tab);
 #pragma omp parallel
     {
         double tt[4096]; int8_t ff[4096];
 #pragma omp for schedule(dynamic, 256)
         for (int64_t i = 0; i < nsrc; ++i) {
             double r[3] = {cos(dec[i]) * cos(ra[i]), cos(dec[i]) * sin(ra[i]), sin(dec[i])};
-            counts[i] = transits_one(w, r, t0, t1, tt, ff, 4096);
+            counts[i] = transits_one(w, &tab, r, t0, t1, tt, ff, 4096);
         }
     }
+    free(tab.z);
 }
 
 /*
@@ -228,12 +247,15 @@ void syn_count_transits(const syn_law_t* w, int64_t nsrc, const double* ra, cons
  */
 void syn_fill_transits(const syn_law_t* w, int64_t nsrc, const double* ra, const double* dec,
                        double t0, double t1, const int64_t* offsets, double* t_out, int8_t* f_out) {
+    rev_table_t tab;
+    rev_table_build(w, t0, t1, &tab);
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < nsrc; ++i) {
         double r[3] = {cos(dec[i]) * cos(ra[i]), cos(dec[i]) * sin(ra[i]), sin(dec[i])};
         int64_t cap = offsets[i + 1] - offsets[i];
-        int64_t n = transits_one(w, r, t0, t1, t_out + offsets[i], f_out + offsets[i], cap);
+        int64_t n = transits_one(w, &tab, r, t0, t1, t_out + offsets[i], f_out + offsets[i], cap);
         (void)n;
         sort_transits(t_out + offsets[i], f_out + offsets[i], cap);
     }
+    free(tab.z);
 }
