@@ -88,7 +88,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="gaia1")
     ap.add_argument("--seg-len", type=int, default=None)
-    ap.add_argument("--cpu-frac", type=float, default=0.01)
+    ap.add_argument("--cpu-frac", type=float, default=0.2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

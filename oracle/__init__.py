@@ -80,7 +80,7 @@ def lib():
                                   P(c_d), P(c_d), P(c_d), P(c_d), P(c_i64), P(c_d), P(c_d)]
         L.orc_ephemeris.argtypes = [P(World), c_d, P(c_d), P(c_d)]
         L.orc_normal_triad.argtypes = [c_d, c_d, P(c_d), P(c_d), P(c_d)]
-        L.orc_source_update.argtypes = [P(World), P(Obs), P(State), P(c_d), P(c_d), P(c_i32)]
+        L.orc_source_update.argtypes = [P(World), P(Obs), P(State), P(c_d), P(c_d), P(c_i32), P(c_d)]
         L.orc_attitude_update.argtypes = [P(World), P(Obs), P(State), P(c_d)]
         L.orc_attitude_update.restype = c_i64
         L.orc_attitude_segment.argtypes = [P(World), P(Obs), P(State), c_i64, P(c_d), P(c_i64), P(c_i64)]
@@ -88,8 +88,8 @@ def lib():
         L.orc_num_segments.argtypes = [P(World)]
         L.orc_num_segments.restype = c_i64
         L.orc_calibration_update.argtypes = [P(World), P(Obs), P(State), P(c_d)]
-        L.orc_iterate_sac.argtypes = [P(World), P(Obs), P(State)]
-        L.orc_frame_fit.argtypes = [P(World), P(State), P(c_d), P(c_d)]
+        L.orc_iterate_sac.argtypes = [P(World), P(Obs), P(State), P(c_d)]
+        L.orc_frame_fit.argtypes = [P(World), P(State), P(c_d), P(c_d), P(c_d)]
         L.orc_frame_apply.argtypes = [P(World), P(State), P(c_d)]
         _lib = L
     return _lib
@@ -259,8 +259,9 @@ class Problem:
     def source_update(self):
         ns = self.s.shape[0]
         d, Q, de = np.zeros((ns, 5)), np.zeros(ns), np.zeros(ns, np.int32)
+        self.var = np.zeros((ns, 5))
         lib().orc_source_update(ctypes.byref(self.world), ctypes.byref(self.obs), ctypes.byref(self.state),
-                                _p(d, c_d), _p(Q, c_d), _p(de, c_i32))
+                                _p(d, c_d), _p(Q, c_d), _p(de, c_i32), _p(self.var, c_d))
         return d, Q, de
 
     def attitude_update(self):
@@ -286,12 +287,18 @@ class Problem:
         return d
 
     def iterate_sac(self):
-        lib().orc_iterate_sac(ctypes.byref(self.world), ctypes.byref(self.obs), ctypes.byref(self.state))
+        self.var = np.zeros((self.s.shape[0], 5))
+        lib().orc_iterate_sac(ctypes.byref(self.world), ctypes.byref(self.obs), ctypes.byref(self.state),
+                              _p(self.var, c_d))
 
-    def frame_fit(self, s_ref):
+    def frame_fit(self, s_ref, weighted=True):
+        """Frame rotator fit; weighted by the variances of the last S update
+        (unit weights before any, or with weighted=False)."""
         s_ref = np.ascontiguousarray(s_ref, dtype=np.float64)
         eo = np.zeros(6)
-        lib().orc_frame_fit(ctypes.byref(self.world), ctypes.byref(self.state), _p(s_ref, c_d), _p(eo, c_d))
+        var = getattr(self, "var", None) if weighted else None
+        lib().orc_frame_fit(ctypes.byref(self.world), ctypes.byref(self.state), _p(s_ref, c_d), _p(var, c_d),
+                            _p(eo, c_d))
         return eo
 
     def frame_apply(self, eo):

@@ -372,7 +372,7 @@ static void group_by_source(const orc_obs_t* obs, int64_t n_src, int64_t** off_o
  * delta (footnote to eq:ubardiff).
  * ====================================================================== */
 void orc_source_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st,
-                       double* d_out, double* Q_out, int32_t* defect_out) {
+                       double* d_out, double* Q_out, int32_t* defect_out, double* var_out) {
     int64_t *off, *idx;
     group_by_source(obs, st->n_src, &off, &idx);
 #pragma omp parallel
@@ -405,6 +405,17 @@ void orc_source_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* 
             int def = orc_chol_c1(N, 5);
             orc_chol_c2(N, 5, b);
             orc_chol_c3(N, 5, b);
+            if (var_out) {
+                /* diagonal of the inverse: C2 and C3 on the unit vectors
+                 * (Appendix C.2) */
+                for (int kk = 0; kk < 5; ++kk) {
+                    double e[5] = {0, 0, 0, 0, 0};
+                    e[kk] = 1.0;
+                    orc_chol_c2(N, 5, e);
+                    orc_chol_c3(N, 5, e);
+                    var_out[5 * i + kk] = def > 0 ? 0.0 : e[kk];
+                }
+            }
             double Q = 0.0;
             for (int64_t k = 0; k < ni; ++k) {
                 double Rk = hb[k];
@@ -621,8 +632,8 @@ void orc_calibration_update(const orc_world_t* w, const orc_obs_t* obs, orc_stat
 
 /* Sect. 4.5 (practical scheme): S with a^k, c^k; then A and C both with
  * s^{k+1}, a^k, c^k (the S[AC] variant of eq:precondS(CAG) without G). */
-void orc_iterate_sac(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st) {
-    orc_source_update(w, obs, st, NULL, NULL, NULL);
+void orc_iterate_sac(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st, double* var) {
+    orc_source_update(w, obs, st, NULL, NULL, NULL, var);
     double* da = (double*)calloc((size_t)(4 * st->n_att), sizeof(double));
     double* dc = (double*)calloc((size_t)st->n_cells, sizeof(double));
     attitude_solve(w, obs, st, da);
@@ -641,7 +652,8 @@ void orc_iterate_sac(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st
  * Apply: the five rigorous steps of Sect. 6.1.2 for every source and
  * eq:fr-q4 with eq:RF4 for every attitude coefficient.
  * ====================================================================== */
-void orc_frame_fit(const orc_world_t* w, const orc_state_t* st, const double* s_ref, double eps_omega[6]) {
+void orc_frame_fit(const orc_world_t* w, const orc_state_t* st, const double* s_ref, const double* var,
+                   double eps_omega[6]) {
     double N[36] = {0}, b[6] = {0};
     double tau = (w->t_ep - w->t_fr) / w->year_s;
     for (int64_t i = 0; i < st->n_src; ++i) {
@@ -662,10 +674,19 @@ void orc_frame_fit(const orc_world_t* w, const orc_state_t* st, const double* s_
         rhs[1] = s[4] - h[4];
         rhs[2] = dot3(pt, dr);
         rhs[3] = dot3(qt, dr);
+        /* weights: inverse variances of mu_a*, mu_d, alpha*, delta */
+        const int vidx[4] = {3, 4, 0, 1};
+        double wt[4] = {1.0, 1.0, 1.0, 1.0};
+        if (var) {
+            for (int e = 0; e < 4; ++e) {
+                double v = var[5 * i + vidx[e]];
+                wt[e] = (v > 0.0 && isfinite(v)) ? 1.0 / v : 0.0;
+            }
+        }
         for (int e = 0; e < 4; ++e) {
             for (int r = 0; r < 6; ++r) {
-                for (int c = 0; c < 6; ++c) N[6 * r + c] += rows[e][r] * rows[e][c];
-                b[r] += rows[e][r] * rhs[e];
+                for (int c = 0; c < 6; ++c) N[6 * r + c] += rows[e][r] * wt[e] * rows[e][c];
+                b[r] += rows[e][r] * wt[e] * rhs[e];
             }
         }
     }

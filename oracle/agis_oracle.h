@@ -91,9 +91,11 @@ void orc_normal_triad(double alpha, double delta, double p[3], double q[3], doub
 
 /* --- Sect. 5: update blocks ----------------------------------------------- */
 /* S block for all sources; updates st->s in place.  Optional outputs:
- * d[n_src][5] updates, Q[n_src] = R'WR after the solve, defect[n_src]. */
+ * d[n_src][5] updates, Q[n_src] = R'WR after the solve, defect[n_src],
+ * var[n_src][5] the diagonal of the inverse normal matrix (first-order
+ * variances, Sect. 5.1.1 / eq:cov). */
 void orc_source_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st,
-                       double* d, double* Q, int32_t* defect);
+                       double* d, double* Q, int32_t* defect, double* var);
 /* A block (all segments); residuals from the current state.  d[n_att][4]
  * receives the applied update (may be NULL); returns the summed defect. */
 int64_t orc_attitude_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st, double* d);
@@ -105,11 +107,15 @@ int64_t orc_num_segments(const orc_world_t* w);
 /* C block; d[n_cells] receives the applied update (may be NULL). */
 void orc_calibration_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st, double* d);
 /* S[AC]: S, then A and C from the same post-S residuals. */
-void orc_iterate_sac(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st);
+void orc_iterate_sac(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st, double* var);
 
 /* --- Sect. 6.1: frame rotator --------------------------------------------- */
-/* eps_omega = (eps_X, eps_Y, eps_Z [rad], omega_X, omega_Y, omega_Z [rad/yr]) */
-void orc_frame_fit(const orc_world_t* w, const orc_state_t* st, const double* s_ref, double eps_omega[6]);
+/* eps_omega = (eps_X, eps_Y, eps_Z [rad], omega_X, omega_Y, omega_Z [rad/yr]).
+ * var[n_src][5] (may be NULL: unit weights) weights each condition equation
+ * by the inverse variance of its parameter; a source with a zero or
+ * non-finite variance gets zero weight. */
+void orc_frame_fit(const orc_world_t* w, const orc_state_t* st, const double* s_ref, const double* var,
+                   double eps_omega[6]);
 void orc_frame_apply(const orc_world_t* w, orc_state_t* st, const double eps_omega[6]);
 
 #ifdef __cplusplus

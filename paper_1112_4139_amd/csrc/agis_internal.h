@@ -81,6 +81,7 @@ struct agis_ctx {
     double* ds = nullptr;                // [n_src][5] last source update
     double* qsrc = nullptr;              // [n_src] Q_i after the S solve
     int32_t* sdef = nullptr;             // [n_src] defect per source
+    double* svar = nullptr;              // [n_src][5] variances of the last S update (1 before any)
     double* iv_sums = nullptr;           // [K][IV_SUMS]
     double* iv_cal = nullptr;            // [K][IV_CAL]
     double* da = nullptr;                // [N][4]
@@ -95,6 +96,10 @@ struct agis_ctx {
     int64_t red_len = 0;
     double* eo = nullptr;                // [8] frame rotator parameters on device
     double* stat = nullptr;              // statistics scratch
+
+    // lanes per source (S block) and per knot interval (A/C pass)
+    int s_group = 16;
+    int ac_group = 8;
 
     agis::Timers tm;
     double last_ms[5] = {0, 0, 0, 0, 0};

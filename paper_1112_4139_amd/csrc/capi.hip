@@ -2,6 +2,7 @@
 // frame rotator and the simple-iteration driver.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -91,6 +92,7 @@ static void free_store(agis_ctx* ctx) {
     dfree(ctx->ds);
     dfree(ctx->qsrc);
     dfree(ctx->sdef);
+    dfree(ctx->svar);
     dfree(ctx->dc);
     ctx->loaded = false;
     ctx->have_ref = false;
@@ -230,6 +232,8 @@ extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
     k.cos_obl = std::cos(cfg->eps_obl);
     k.sin_obl = std::sin(cfg->eps_obl);
     build_segments(ctx);
+    if (const char* e = std::getenv("AGIS_S_GROUP")) ctx->s_group = std::atoi(e);
+    if (const char* e = std::getenv("AGIS_AC_GROUP")) ctx->ac_group = std::atoi(e);
     int rc = AGIS_OK;
     auto fail = [&](int code) {
         g_create_error = ctx->err;
@@ -313,10 +317,18 @@ extern "C" int agis_load_observations(agis_ctx_t* ctx, const agis_obs_soa_t* obs
     ALLOC(ctx->ds, 5 * n_src, "source updates");
     ALLOC(ctx->qsrc, n_src, "source chi2");
     ALLOC(ctx->sdef, n_src, "source defects");
+    ALLOC(ctx->svar, 5 * n_src, "source variances");
     ALLOC(ctx->dc, n_cells, "calibration updates");
     HIPCHK(hipMemsetAsync(ctx->s, 0, 5 * std::max<int64_t>(n_src, 1) * sizeof(double), ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->c, 0, std::max<int64_t>(n_cells, 1) * sizeof(double), ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->dc, 0, std::max<int64_t>(n_cells, 1) * sizeof(double), ctx->stream));
+    {
+        // unit weights for the frame fit until the first S update
+        std::vector<double> ones(5 * std::max<int64_t>(n_src, 1), 1.0);
+        HIPCHK(hipMemcpyAsync(ctx->svar, ones.data(), ones.size() * sizeof(double), hipMemcpyHostToDevice,
+                              ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
     int rc = build_store(ctx, obs, where);
     if (rc != AGIS_OK) {
         std::string keep = ctx->err;

@@ -1,15 +1,6 @@
-// Hot-path kernels of the S, A and C updating blocks and the frame rotator.
+// Kernels of the C block, the frame rotator, residuals and statistics (the
+// source update, the A/C accumulation pass and the band solve are in hot.hip).
 //
-//   k_source_update  one wavefront per source: model + design row per
-//                    observation (Sect. 5.1.3), eq:normS sums in registers,
-//                    wave butterfly reduction, 5x5 Algorithms C1-C3, update
-//   k_ac_pass        one wavefront per knot interval over the time-ordered
-//                    stream: model at s^(k+1), a^(k), c^(k); per-interval sums
-//                    of the eq:normAmod blocks and of the C block (eq:normC)
-//   k_band_solve     one wavefront per attitude segment (Sect. 5.2.2):
-//                    right-looking modified band Cholesky (Algorithm C1 with
-//                    C2 folded in) over a sliding 16-wide window in LDS, then
-//                    C3; keeps the segment's selected coefficients
 //   k_calib_solve    per constraint pair: eq:normC solve and eq:calCon
 //   frame rotator    eq:cond-mu3 normal equations (two-stage reduction),
 //                    6x6 solve, rigorous source transform, eq:fr-q4
@@ -47,318 +38,6 @@ __global__ __launch_bounds__(256) void k_prep_sources(int64_t n_src, const doubl
         o.pad = 0.0;
         prep[i] = o;
     }
-}
-
-// S block (Sect. 5.1): one wavefront per source.
-__global__ __launch_bounds__(256) void k_source_update(DevConsts k, int64_t n_src, const int64_t* __restrict__ off,
-                                                       const double* __restrict__ ot, const double* __restrict__ oeta,
-                                                       const float* __restrict__ osig,
-                                                       const int32_t* __restrict__ ocell,
-                                                       const int32_t* __restrict__ oell,
-                                                       const double* __restrict__ knots, const double* __restrict__ a,
-                                                       const double* __restrict__ c, double* __restrict__ s,
-                                                       SrcPrep* __restrict__ prep, double* __restrict__ ds,
-                                                       double* __restrict__ qsrc, int32_t* __restrict__ sdef) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
-    if (i >= n_src) return;                      // uniform across the wavefront
-    double* si = s + 5 * i;
-    const double alpha = si[0], delta = si[1], plx = si[2], pma = si[3], pmd = si[4];
-    double sa, ca, sd, cd;
-    sincos(alpha, &sa, &ca);
-    sincos(delta, &sd, &cd);
-    const double p[3] = {-sa, ca, 0.0};
-    const double q[3] = {-sd * ca, -sd * sa, cd};
-    const double r[3] = {cd * ca, cd * sa, sd};
-    double mu[3];
-    for (int cc = 0; cc < 3; ++cc) mu[cc] = p[cc] * pma + q[cc] * pmd;
-
-    double acc[21];
-#pragma unroll
-    for (int e = 0; e < 21; ++e) acc[e] = 0.0;
-    const int64_t l0 = off[i], l1 = off[i + 1];
-    for (int64_t l = l0 + lane; l < l1; l += WAVE) {
-        const int32_t ell = oell[l];
-        const double t = ot[l];
-        ObsEval o;
-        observe(k, t, oeta[l], c[ocell[l] >> 1], r, mu, plx, a + 4 * (ell - 3), knots + (ell - 2), o);
-        double A[5];
-        source_partials(o, p, q, r, A);
-        const double sg = (double)osig[l];
-        const double W = 1.0 / (sg * sg);
-        int e = 0;
-#pragma unroll
-        for (int rr = 0; rr < 5; ++rr) {
-            const double wa = W * A[rr];
-#pragma unroll
-            for (int cc = rr; cc < 5; ++cc) acc[e++] += wa * A[cc];
-        }
-#pragma unroll
-        for (int rr = 0; rr < 5; ++rr) acc[15 + rr] += W * A[rr] * o.R;
-        acc[20] += W * o.R * o.R;
-    }
-#pragma unroll
-    for (int e = 0; e < 21; ++e) acc[e] = wave_sum(acc[e]);
-    if (lane == 0) {
-        double U[25], N[25], x[5];
-        int e = 0;
-        for (int rr = 0; rr < 5; ++rr)
-            for (int cc = rr; cc < 5; ++cc) {
-                U[rr * 5 + cc] = acc[e];
-                N[rr * 5 + cc] = acc[e];
-                N[cc * 5 + rr] = acc[e];
-                ++e;
-            }
-        for (int rr = 0; rr < 5; ++rr) x[rr] = acc[15 + rr];
-        const int d = small_chol_solve<5>(U, x);
-        // Q_i = h'Wh - 2 d'b + d'N d (eq:Qi)
-        double dNd = 0.0, db = 0.0;
-        for (int rr = 0; rr < 5; ++rr) {
-            double t = 0.0;
-            for (int cc = 0; cc < 5; ++cc) t += N[rr * 5 + cc] * x[cc];
-            dNd += x[rr] * t;
-            db += x[rr] * acc[15 + rr];
-        }
-        qsrc[i] = acc[20] - 2.0 * db + dNd;
-        sdef[i] = d;
-        for (int rr = 0; rr < 5; ++rr) ds[5 * i + rr] = x[rr];
-        const double na = alpha + x[0] / cd, nd = delta + x[1];
-        const double npl = plx + x[2], npa = pma + x[3], npd = pmd + x[4];
-        si[0] = na;
-        si[1] = nd;
-        si[2] = npl;
-        si[3] = npa;
-        si[4] = npd;
-        double sa2, ca2, sd2, cd2;
-        sincos(na, &sa2, &ca2);
-        sincos(nd, &sd2, &cd2);
-        SrcPrep o;
-        const double p2[3] = {-sa2, ca2, 0.0};
-        const double q2[3] = {-sd2 * ca2, -sd2 * sa2, cd2};
-        o.r[0] = cd2 * ca2;
-        o.r[1] = cd2 * sa2;
-        o.r[2] = sd2;
-        for (int cc = 0; cc < 3; ++cc) o.mu[cc] = p2[cc] * npa + q2[cc] * npd;
-        o.plx = npl;
-        o.pad = 0.0;
-        prep[i] = o;
-    }
-}
-
-// --------------------------------------------------------- A and C pass
-// One wavefront per knot interval j (left index j + 3).  Output per
-// interval: sums[p*10 + e] = sum_l W B_n B_m M_e with M = g g' + 4 lambda^2
-// q~ q~' (pair p = (n, m), entry e = (r, c), r <= c), and sums[100 + 4n + r]
-// = - sum_l W B_n (g_r R - 2 lambda^2 q~_r D); cal = (sum W, sum W R) per fov.
-__global__ __launch_bounds__(256) void k_ac_pass(DevConsts k, int64_t K, const int64_t* __restrict__ iv_off,
-                                                 const double* __restrict__ ot, const double* __restrict__ oeta,
-                                                 const float* __restrict__ osig,
-                                                 const int32_t* __restrict__ ocellfov,
-                                                 const int32_t* __restrict__ osrc, const SrcPrep* __restrict__ prep,
-                                                 const double* __restrict__ knots, const double* __restrict__ a,
-                                                 const double* __restrict__ c, double* __restrict__ iv_sums,
-                                                 double* __restrict__ iv_cal) {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t j = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
-    if (j >= K) return;
-    double a4[16], kn[6];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) a4[e] = a[4 * j + e];
-#pragma unroll
-    for (int e = 0; e < 6; ++e) kn[e] = knots[j + 1 + e];
-    double accP[IV_PAIRS * 10];
-    double accR[16];
-    double accC[IV_CAL];
-#pragma unroll
-    for (int e = 0; e < IV_PAIRS * 10; ++e) accP[e] = 0.0;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) accR[e] = 0.0;
-#pragma unroll
-    for (int e = 0; e < IV_CAL; ++e) accC[e] = 0.0;
-    const double lam2 = k.lam2;
-    const int64_t l0 = iv_off[j], l1 = iv_off[j + 1];
-    for (int64_t l = l0 + lane; l < l1; l += WAVE) {
-        const int32_t cf = ocellfov[l];
-        const SrcPrep sp = prep[osrc[l]];
-        ObsEval o;
-        observe(k, ot[l], oeta[l], c[cf >> 1], sp.r, sp.mu, sp.plx, a4, kn, o);
-        double g[4];
-        attitude_partial(o, g);
-        const double sg = (double)osig[l];
-        const double W = 1.0 / (sg * sg);
-        double M[10], rv[4];
-        int e = 0;
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-            for (int cc = rr; cc < 4; ++cc)
-                M[e++] = W * (g[rr] * g[cc] + 4.0 * lam2 * o.qraw[rr] * o.qraw[cc]);
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) rv[rr] = -W * (g[rr] * o.R - 2.0 * lam2 * o.qraw[rr] * o.D);
-        int p = 0;
-#pragma unroll
-        for (int n = 0; n < 4; ++n)
-#pragma unroll
-            for (int m = n; m < 4; ++m) {
-                const double bb = o.B[n] * o.B[m];
-#pragma unroll
-                for (int ee = 0; ee < 10; ++ee) accP[p * 10 + ee] += bb * M[ee];
-                ++p;
-            }
-#pragma unroll
-        for (int n = 0; n < 4; ++n)
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) accR[n * 4 + rr] += o.B[n] * rv[rr];
-        const int f = cf & 1;
-        const double wr = W * o.R;
-        accC[2 * f] += W;
-        accC[2 * f + 1] += wr;
-    }
-    double* out = iv_sums + j * IV_SUMS;
-#pragma unroll
-    for (int e = 0; e < IV_PAIRS * 10; ++e) {
-        const double v = wave_sum(accP[e]);
-        if (lane == (e & (WAVE - 1))) out[e] = v;
-    }
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const double v = wave_sum(accR[e]);
-        if (lane == ((100 + e) & (WAVE - 1))) out[100 + e] = v;
-    }
-#pragma unroll
-    for (int e = 0; e < IV_CAL; ++e) {
-        const double v = wave_sum(accC[e]);
-        if (lane == e) iv_cal[j * IV_CAL + e] = v;
-    }
-}
-
-// ------------------------------------------------------------ band solve
-// Entry (i, kk) of a segment's band normal matrix (i <= kk <= i + 15, both
-// segment-relative scalar indices) assembled from the per-interval sums.
-__device__ __forceinline__ double band_entry(const double* __restrict__ iv_sums, int64_t n_lo, int64_t nb, int64_t i,
-                                             int64_t kk) {
-    const int64_t bi = i >> 2, bk = kk >> 2;
-    const int r = (int)(i & 3), cc = (int)(kk & 3);
-    const int rr = r < cc ? r : cc, c2 = r < cc ? cc : r;
-    const int e = tri4(rr, c2);
-    int64_t jlo = bk - 3 > 0 ? bk - 3 : 0;
-    int64_t jhi = bi < nb - 4 ? bi : nb - 4;
-    double s = 0.0;
-    for (int64_t j = jlo; j <= jhi; ++j) {
-        const int p = tri4((int)(bi - j), (int)(bk - j));
-        s += iv_sums[(n_lo + j) * IV_SUMS + p * 10 + e];
-    }
-    return s;
-}
-
-__device__ __forceinline__ double band_rhs(const double* __restrict__ iv_sums, int64_t n_lo, int64_t nb, int64_t i) {
-    const int64_t bi = i >> 2;
-    const int r = (int)(i & 3);
-    int64_t jlo = bi - 3 > 0 ? bi - 3 : 0;
-    int64_t jhi = bi < nb - 4 ? bi : nb - 4;
-    double s = 0.0;
-    for (int64_t j = jlo; j <= jhi; ++j) s += iv_sums[(n_lo + j) * IV_SUMS + 100 + (bi - j) * 4 + r];
-    return s;
-}
-
-__global__ __launch_bounds__(64) void k_band_solve(int64_t nseg, const SegDesc* __restrict__ segs,
-                                                   const double* __restrict__ iv_sums, double* __restrict__ ufac,
-                                                   double* __restrict__ yfac, double* __restrict__ da,
-                                                   int32_t* __restrict__ seg_def) {
-    __shared__ double Wn[16][17];     // window: row slot i & 15, column slot kk & 15, column 16 = rhs
-    __shared__ double Ur[17];
-    __shared__ double X[16];
-    const int lane = threadIdx.x;
-    const int64_t sgi = blockIdx.x;
-    if (sgi >= nseg) return;
-    const SegDesc d = segs[sgi];
-    const int64_t nb = d.n_hi - d.n_lo + 1;
-    const int64_t nu = 4 * nb;
-    double* U = ufac + d.u_off * 16;
-    double* Y = yfac + d.u_off;
-    // initial window: rows 0..15, columns up to 15
-    for (int idx = lane; idx < 16 * 17; idx += 64) {
-        const int row = idx / 17, col = idx % 17;
-        double v = 0.0;
-        if (row < nu) {
-            if (col == 16) v = band_rhs(iv_sums, d.n_lo, nb, row);
-            else if (col >= row && col < nu) v = band_entry(iv_sums, d.n_lo, nb, row, col);
-        }
-        Wn[row][col] = v;
-    }
-    __syncthreads();
-    int defect = 0;
-    // trailing-update work items: 120 pairs (dj, dk), 1 <= dj <= dk <= 15,
-    // then 15 right-hand-side items
-    for (int64_t i = 0; i < nu; ++i) {
-        const int si = (int)(i & 15);
-        const double piv = Wn[si][si];
-        const bool ok = piv > 0.0;
-        const double u = ok ? sqrt(piv) : 0.0;
-        const double inv = ok ? 1.0 / u : 0.0;
-        if (!ok) ++defect;
-        if (lane < 16) {
-            const int64_t kk = i + lane;
-            double v = 0.0;
-            if (kk < nu) v = lane == 0 ? u : Wn[si][kk & 15] * inv;
-            U[i * 16 + lane] = v;
-            Ur[lane] = v;
-        } else if (lane == 16) {
-            const double y = Wn[si][16] * inv;
-            Y[i] = y;
-            Ur[16] = y;
-        }
-        __syncthreads();
-        for (int w = lane; w < 135; w += 64) {
-            if (w < 120) {
-                // decode w -> (dj, dk)
-                int dj = 1, rem = w;
-                while (rem >= 16 - dj) {
-                    rem -= 16 - dj;
-                    ++dj;
-                }
-                const int dk = dj + rem;
-                const int64_t jj = i + dj, kk = i + dk;
-                if (kk < nu) Wn[jj & 15][kk & 15] -= Ur[dj] * Ur[dk];
-            } else {
-                const int dj = w - 119;
-                const int64_t jj = i + dj;
-                if (jj < nu) Wn[jj & 15][16] -= Ur[dj] * Ur[16];
-            }
-        }
-        __syncthreads();
-        const int64_t kn = i + 16;
-        if (kn < nu) {
-            if (lane < 16) {
-                const int64_t jj = kn - 15 + lane;
-                Wn[jj & 15][kn & 15] = band_entry(iv_sums, d.n_lo, nb, jj, kn);
-            } else if (lane == 16) {
-                Wn[kn & 15][16] = band_rhs(iv_sums, d.n_lo, nb, kn);
-            }
-        }
-        __syncthreads();
-    }
-    // back substitution (Algorithm C3) over the band rows
-    if (lane < 16) X[lane] = 0.0;
-    __syncthreads();
-    for (int64_t i = nu - 1; i >= 0; --i) {
-        double v = 0.0;
-        if (lane >= 1 && lane < 16) {
-            const int64_t kk = i + lane;
-            if (kk < nu) v = U[i * 16 + lane] * X[kk & 15];
-        }
-        v = wave_sum(v);
-        __syncthreads();
-        if (lane == 0) {
-            const double uii = U[i * 16];
-            const double xi = uii > 0.0 ? (Y[i] - v) / uii : 0.0;
-            X[i & 15] = xi;
-            const int64_t n = d.n_lo + (i >> 2);
-            if (n >= d.keep_lo && n <= d.keep_hi) da[4 * n + (i & 3)] = xi;
-        }
-        __syncthreads();
-    }
-    if (lane == 0) seg_def[sgi] = defect;
 }
 
 __global__ void k_apply_add(int64_t n, double* __restrict__ x, const double* __restrict__ dx) {
@@ -426,8 +105,11 @@ __global__ __launch_bounds__(256) void k_calib_solve(int64_t n_cells, const int3
 constexpr int FR_BLOCKS = 512;
 constexpr int FR_VALS = 27;   // 21 upper entries of the 6x6 matrix + 6 rhs
 
+// Weighted by the inverse variances of the last S update (eq:cond-mu3 rows
+// for mu_a*, mu_d, alpha*, delta); zero or non-finite variance: zero weight.
 __global__ __launch_bounds__(256) void k_frame_fit_partial(DevConsts k, int64_t n_src, const double* __restrict__ s,
                                                            const double* __restrict__ sref,
+                                                           const double* __restrict__ svar,
                                                            double* __restrict__ part) {
     __shared__ double red[256];
     double acc[FR_VALS];
@@ -462,15 +144,20 @@ __global__ __launch_bounds__(256) void k_frame_fit_partial(DevConsts k, int64_t 
         rhs[1] = x[4] - h[4];
         rhs[2] = dot3(pt, dr);
         rhs[3] = dot3(qt, dr);
+        const double* vi = svar + 5 * i;
+        const double vv[4] = {vi[3], vi[4], vi[0], vi[1]};
 #pragma unroll
         for (int eq = 0; eq < 4; ++eq) {
+            const double wt = (vv[eq] > 0.0 && isfinite(vv[eq])) ? 1.0 / vv[eq] : 0.0;
             int e = 0;
 #pragma unroll
-            for (int r = 0; r < 6; ++r)
+            for (int r = 0; r < 6; ++r) {
+                const double rw = rows[eq][r] * wt;
 #pragma unroll
-                for (int cc = r; cc < 6; ++cc) acc[e++] += rows[eq][r] * rows[eq][cc];
+                for (int cc = r; cc < 6; ++cc) acc[e++] += rw * rows[eq][cc];
+            }
 #pragma unroll
-            for (int r = 0; r < 6; ++r) acc[21 + r] += rows[eq][r] * rhs[eq];
+            for (int r = 0; r < 6; ++r) acc[21 + r] += rows[eq][r] * wt * rhs[eq];
         }
     }
     for (int e = 0; e < FR_VALS; ++e) {
@@ -667,26 +354,8 @@ void launch_prep_sources(agis_ctx* ctx) {
     k_prep_sources<<<grid_for(ctx->n_src), 256, 0, ctx->stream>>>(ctx->n_src, ctx->s, ctx->prep);
 }
 
-void launch_source_update(agis_ctx* ctx) {
-    if (ctx->n_src == 0) return;
-    k_source_update<<<waves_grid(ctx->n_src, 4), 256, 0, ctx->stream>>>(
-        ctx->k, ctx->n_src, ctx->src_off, ctx->s_t, ctx->s_eta, ctx->s_sig, ctx->s_cell, ctx->s_ell, ctx->knots,
-        ctx->a, ctx->c, ctx->s, ctx->prep, ctx->ds, ctx->qsrc, ctx->sdef);
-}
 
-void launch_ac_pass(agis_ctx* ctx) {
-    if (ctx->K == 0) return;
-    k_ac_pass<<<waves_grid(ctx->K, 4), 256, 0, ctx->stream>>>(ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta,
-                                                               ctx->t_sig, ctx->t_cellfov, ctx->t_src, ctx->prep,
-                                                               ctx->knots, ctx->a, ctx->c, ctx->iv_sums, ctx->iv_cal);
-}
 
-void launch_band_solve(agis_ctx* ctx) {
-    const int64_t nseg = (int64_t)ctx->h_segs.size();
-    if (nseg == 0) return;
-    k_band_solve<<<(unsigned)nseg, 64, 0, ctx->stream>>>(nseg, ctx->segs, ctx->iv_sums, ctx->ufac, ctx->yfac, ctx->da,
-                                                        ctx->seg_def);
-}
 
 void launch_apply_attitude(agis_ctx* ctx) {
     k_apply_add<<<grid_for(4 * ctx->N), 256, 0, ctx->stream>>>(4 * ctx->N, ctx->a, ctx->da);
@@ -704,7 +373,8 @@ void launch_apply_calibration(agis_ctx* ctx) {
 }
 
 void launch_frame_fit(agis_ctx* ctx) {
-    k_frame_fit_partial<<<FR_BLOCKS, 256, 0, ctx->stream>>>(ctx->k, ctx->n_src, ctx->s, ctx->s_ref, ctx->red);
+    k_frame_fit_partial<<<FR_BLOCKS, 256, 0, ctx->stream>>>(ctx->k, ctx->n_src, ctx->s, ctx->s_ref, ctx->svar,
+                                                            ctx->red);
     k_frame_fit_final<<<1, 64, 0, ctx->stream>>>(ctx->red, ctx->eo);
 }
 

@@ -204,10 +204,10 @@ __device__ __forceinline__ void attitude_partial(const ObsEval& o, double g[4]) 
 
 // Modified Cholesky for a small dense symmetric system (Algorithms C1-C3
 // of Appendix C: zero pivots are skipped and counted, no pivoting).
-// U holds the upper triangle row-major n x n on entry; x the right-hand
-// side; returns the rank-defect count.
+// small_chol_factor: U holds the upper triangle row-major n x n on entry and
+// the factor on exit; returns the rank-defect count.
 template <int NN>
-__device__ __forceinline__ int small_chol_solve(double U[NN * NN], double x[NN]) {
+__device__ __forceinline__ int small_chol_factor(double U[NN * NN]) {
     int d = 0;
 #pragma unroll
     for (int j = 0; j < NN; ++j) {
@@ -229,6 +229,12 @@ __device__ __forceinline__ int small_chol_solve(double U[NN * NN], double x[NN])
             }
         }
     }
+    return d;
+}
+
+// Algorithms C2 and C3 with the factor of small_chol_factor.
+template <int NN>
+__device__ __forceinline__ void small_chol_subst(const double U[NN * NN], double x[NN]) {
 #pragma unroll
     for (int i = 0; i < NN; ++i) {
         double s = 0.0;
@@ -243,6 +249,12 @@ __device__ __forceinline__ int small_chol_solve(double U[NN * NN], double x[NN])
         for (int kk = i + 1; kk < NN; ++kk) s += U[i * NN + kk] * x[kk];
         x[i] = U[i * NN + i] > 0.0 ? (x[i] - s) / U[i * NN + i] : 0.0;
     }
+}
+
+template <int NN>
+__device__ __forceinline__ int small_chol_solve(double U[NN * NN], double x[NN]) {
+    const int d = small_chol_factor<NN>(U);
+    small_chol_subst<NN>(U, x);
     return d;
 }
 

@@ -234,7 +234,9 @@ def make_world(spec: WorldSpec, law: dict | None = None) -> World:
     N = knots.shape[0] - 4
 
     rng = np.random.default_rng(spec.seed_truth)
-    n = spec.n_src
+    # with a primary-source selection, draw extra candidates and keep the
+    # first n_src that pass it
+    n = spec.n_src if spec.min_transits <= 0 else int(spec.n_src * 1.5) + 64
     ra = rng.uniform(0.0, 2.0 * np.pi, n)
     if spec.dec_band is None:
         sd = rng.uniform(-1.0, 1.0, n)
@@ -275,8 +277,12 @@ def make_world(spec: WorldSpec, law: dict | None = None) -> World:
     off, tt, ff = find_transits(law, ra, dec, t_beg, t_end)
     ntr = np.diff(off)
     if spec.min_transits > 0:
-        # primary-source selection: keep only well-observed stars
+        # primary-source selection: keep only well-observed stars (the
+        # first n_src candidates with at least min_transits transits)
         ok = ntr >= spec.min_transits
+        if ok.sum() < spec.n_src:
+            raise RuntimeError("not enough candidate sources pass the transit selection")
+        ok &= np.cumsum(ok) <= spec.n_src
         keep_tr = np.repeat(ok, ntr)
         tt, ff = tt[keep_tr], ff[keep_tr]
         ntr = ntr[ok]

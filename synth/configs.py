@@ -26,7 +26,8 @@ def mini_law() -> dict:
     return law
 
 
-# name -> (law factory, WorldSpec)
+# name -> (law factory, WorldSpec).  Attitude segments are 240 knot
+# intervals with L = 12 on each side.
 WORKLOADS = {
     # 20 000 stars, 1 yr, one AL observation per transit (~343k obs),
     # 1200 s knots (~105k attitude unknowns), 732 cells; the tiny workload
@@ -39,10 +40,10 @@ WORKLOADS = {
                                    seg_len=100, seg_overlap=12, lambda_reg=1e-2)),
     # 1M stars, 1 yr, 9 AF observations per transit (~160M obs), 30 s knots
     "gaia1": (gaia_law, WorldSpec(n_src=1_000_000, years=1.0, knot_dt=30.0, ccd_per_transit=9,
-                                  seg_len=2880, seg_overlap=12, lambda_reg=1e-2)),
+                                  seg_len=240, seg_overlap=12, lambda_reg=1e-2)),
     # 2M stars, 5 yr, 9 AF observations per transit (~1.6G obs), 1% outliers
     "gaia5": (gaia_law, WorldSpec(n_src=2_000_000, years=5.0, knot_dt=30.0, ccd_per_transit=9,
-                                  seg_len=2880, seg_overlap=12, lambda_reg=1e-2, outlier_frac=0.01)),
+                                  seg_len=240, seg_overlap=12, lambda_reg=1e-2, outlier_frac=0.01)),
 }
 
 
