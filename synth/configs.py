@@ -27,20 +27,23 @@ def mini_law() -> dict:
 
 
 # name -> (law factory, WorldSpec).  Attitude segments are 240 knot
-# intervals with L = 12 on each side.
+# intervals with L = 12 on each side.  Primary sources (Sect. 6.2) must admit
+# a five-parameter solution: the 1-year workloads keep stars with at least
+# six transits (a star seen on fewer occasions has a singular or nearly
+# singular 5x5 system).
 WORKLOADS = {
     # 20 000 stars, 1 yr, one AL observation per transit (~343k obs),
     # 1200 s knots (~105k attitude unknowns), 732 cells; the tiny workload
     "tiny": (mini_law, WorldSpec(n_src=20000, years=1.0, knot_dt=1200.0, ccd_per_transit=1,
-                                 seg_len=240, seg_overlap=12, lambda_reg=1e-2)),
+                                 seg_len=240, seg_overlap=12, lambda_reg=1e-2, min_transits=6)),
     # small parity cases (seconds on one CPU core)
     "small": (mini_law, WorldSpec(n_src=4000, years=1.0, knot_dt=1200.0, ccd_per_transit=1,
-                                  seg_len=240, seg_overlap=12, lambda_reg=1e-2)),
+                                  seg_len=240, seg_overlap=12, lambda_reg=1e-2, min_transits=6)),
     "small9": (mini_law, WorldSpec(n_src=3000, years=0.5, knot_dt=1200.0, ccd_per_transit=9,
                                    seg_len=100, seg_overlap=12, lambda_reg=1e-2)),
     # 1M stars, 1 yr, 9 AF observations per transit (~160M obs), 30 s knots
     "gaia1": (gaia_law, WorldSpec(n_src=1_000_000, years=1.0, knot_dt=30.0, ccd_per_transit=9,
-                                  seg_len=240, seg_overlap=12, lambda_reg=1e-2)),
+                                  seg_len=240, seg_overlap=12, lambda_reg=1e-2, min_transits=6)),
     # 2M stars, 5 yr, 9 AF observations per transit (~1.6G obs), 1% outliers
     "gaia5": (gaia_law, WorldSpec(n_src=2_000_000, years=5.0, knot_dt=30.0, ccd_per_transit=9,
                                   seg_len=240, seg_overlap=12, lambda_reg=1e-2, outlier_frac=0.01)),

@@ -49,7 +49,7 @@ def src_diff_uas(s_ref, s):
     return ds / UAS
 
 
-def floor_tolerance(oracle_lib, world, eta, run, n_draws=2, ulp_noise=3e-16, factor=4.0):
+def floor_tolerance(oracle_lib, world, eta, run, n_draws=3, ulp_noise=3e-16, factor=8.0):
     """Per-parameter tolerance: max(1e-3 uas, factor x the oracle's own
     response to a ~3-ulp perturbation of every residual).
 
