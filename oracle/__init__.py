@@ -2,7 +2,9 @@
 
 The oracle (``agis_oracle.c``) is a plain double-precision CPU implementation
 of the source, attitude and calibration updating blocks and the frame rotator
-of the Gaia astrometric core solution, written from the paper.  Only the test
+of the Gaia astrometric core solution, written from the paper.  The same
+source built in x87 extended precision serves as the reference against which
+the FP64 rounding floor of any implementation is measured.  Only the test
 suite, the smoke check and the CPU-baseline leg of the benchmark may use it;
 the GPU library never loads, calls or links it.
 """
@@ -15,84 +17,105 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
 P = ctypes.POINTER
 c_d, c_i64, c_i32, c_i8, c_f = ctypes.c_double, ctypes.c_int64, ctypes.c_int32, ctypes.c_int8, ctypes.c_float
 
-
-class World(ctypes.Structure):
-    _fields_ = [("n_knots", c_i64), ("knots", P(c_d)), ("gamma_c", c_d), ("t_ep", c_d), ("t_fr", c_d),
-                ("lambda_reg", c_d), ("seg_len", c_i32), ("seg_overlap", c_i32), ("eph_radius_au", c_d),
-                ("eph_L0", c_d), ("eph_Lrate", c_d), ("eps_obl", c_d), ("au_m", c_d), ("c_mps", c_d),
-                ("year_s", c_d)]
-
-
-class Obs(ctypes.Structure):
-    _fields_ = [("n", c_i64), ("t", P(c_d)), ("eta_obs", P(c_d)), ("sigma", P(c_f)), ("src", P(c_i32)),
-                ("fov", P(c_i8)), ("cell", P(c_i32))]
+# Two builds of the same source: "double" (the oracle) and "extended" (x87
+# 80-bit long double, the reference that the FP64 rounding floor is measured
+# against).  name -> (ctypes real, numpy dtype, library file, extra flags)
+PRECISIONS = {
+    "double": (ctypes.c_double, np.float64, "liboracle.so", []),
+    "extended": (ctypes.c_longdouble, np.longdouble, "liboracle_x.so", ["-DORC_EXTENDED"]),
+}
 
 
-class State(ctypes.Structure):
-    _fields_ = [("n_src", c_i64), ("n_att", c_i64), ("n_cells", c_i64), ("s", P(c_d)), ("a", P(c_d)),
-                ("c", P(c_d))]
+def _structs(c_r):
+    class World(ctypes.Structure):
+        _fields_ = [("n_knots", c_i64), ("knots", P(c_r)), ("gamma_c", c_r), ("t_ep", c_r), ("t_fr", c_r),
+                    ("lambda_reg", c_r), ("seg_len", c_i32), ("seg_overlap", c_i32), ("eph_radius_au", c_r),
+                    ("eph_L0", c_r), ("eph_Lrate", c_r), ("eps_obl", c_r), ("au_m", c_r), ("c_mps", c_r),
+                    ("year_s", c_r)]
+
+    class Obs(ctypes.Structure):
+        _fields_ = [("n", c_i64), ("t", P(c_r)), ("eta_obs", P(c_r)), ("sigma", P(c_f)), ("src", P(c_i32)),
+                    ("fov", P(c_i8)), ("cell", P(c_i32))]
+
+    class State(ctypes.Structure):
+        _fields_ = [("n_src", c_i64), ("n_att", c_i64), ("n_cells", c_i64), ("s", P(c_r)), ("a", P(c_r)),
+                    ("c", P(c_r))]
+
+    return World, Obs, State
+
+
+World, Obs, State = _structs(c_d)
+_STRUCTS = {"double": (World, Obs, State), "extended": _structs(ctypes.c_longdouble)}
+
+
+def _lib_path(precision):
+    return os.path.join(_HERE, PRECISIONS[precision][2])
 
 
 def build(force: bool = False) -> str:
+    """Compile both builds of the oracle (FP64 and x87 extended)."""
     src = os.path.join(_HERE, "agis_oracle.c")
     hdr = os.path.join(_HERE, "agis_oracle.h")
     newest = max(os.path.getmtime(src), os.path.getmtime(hdr))
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < newest:
-        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-std=c99", "-D_DEFAULT_SOURCE", "-O2", "-fno-fast-math",
-                               "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC", "-o", tmp, src, "-lm"])
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+    for precision, (_, _, _, flags) in PRECISIONS.items():
+        path = _lib_path(precision)
+        if force or not os.path.exists(path) or os.path.getmtime(path) < newest:
+            tmp = path + ".tmp%d" % os.getpid()
+            subprocess.check_call(["gcc", "-std=c99", "-D_DEFAULT_SOURCE", *flags, "-O2", "-fno-fast-math",
+                                   "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC", "-o", tmp, src, "-lm"])
+            os.replace(tmp, path)
+    return _lib_path("double")
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+def lib(precision="double"):
+    if precision not in _libs:
+        path = _lib_path(precision)
+        if not os.path.exists(path):
             build()
-        L = ctypes.CDLL(_LIB_PATH)
-        L.orc_qmul.argtypes = [P(c_d), P(c_d), P(c_d)]
-        L.orc_qconj.argtypes = [P(c_d), P(c_d)]
-        L.orc_qinv.argtypes = [P(c_d), P(c_d)]
-        L.orc_frame_rotate.argtypes = [P(c_d), P(c_d), P(c_d)]
-        L.orc_vector_rotate.argtypes = [P(c_d), P(c_d), P(c_d)]
-        L.orc_quat2mat.argtypes = [P(c_d), P(c_d)]
-        L.orc_qrot.argtypes = [P(c_d), P(c_d)]
-        L.orc_left_index.argtypes = [P(c_d), c_i64, c_d]
+        c_r = PRECISIONS[precision][0]
+        World, Obs, State = _STRUCTS[precision]
+        L = ctypes.CDLL(path)
+        L.orc_qmul.argtypes = [P(c_r), P(c_r), P(c_r)]
+        L.orc_qconj.argtypes = [P(c_r), P(c_r)]
+        L.orc_qinv.argtypes = [P(c_r), P(c_r)]
+        L.orc_frame_rotate.argtypes = [P(c_r), P(c_r), P(c_r)]
+        L.orc_vector_rotate.argtypes = [P(c_r), P(c_r), P(c_r)]
+        L.orc_quat2mat.argtypes = [P(c_r), P(c_r)]
+        L.orc_qrot.argtypes = [P(c_r), P(c_r)]
+        L.orc_left_index.argtypes = [P(c_r), c_i64, c_r]
         L.orc_left_index.restype = c_i64
-        L.orc_bspline.argtypes = [P(c_d), c_i64, c_d, P(c_d)]
-        L.orc_chol_c1.argtypes = [P(c_d), ctypes.c_int]
+        L.orc_bspline.argtypes = [P(c_r), c_i64, c_r, P(c_r)]
+        L.orc_chol_c1.argtypes = [P(c_r), ctypes.c_int]
         L.orc_chol_c1.restype = ctypes.c_int
-        L.orc_chol_c2.argtypes = [P(c_d), ctypes.c_int, P(c_d)]
-        L.orc_chol_c3.argtypes = [P(c_d), ctypes.c_int, P(c_d)]
-        L.orc_band_c1.argtypes = [P(c_d), ctypes.c_int, ctypes.c_int]
+        L.orc_chol_c2.argtypes = [P(c_r), ctypes.c_int, P(c_r)]
+        L.orc_chol_c3.argtypes = [P(c_r), ctypes.c_int, P(c_r)]
+        L.orc_band_c1.argtypes = [P(c_r), ctypes.c_int, ctypes.c_int]
         L.orc_band_c1.restype = ctypes.c_int
-        L.orc_band_c2.argtypes = [P(c_d), ctypes.c_int, ctypes.c_int, P(c_d)]
-        L.orc_band_c3.argtypes = [P(c_d), ctypes.c_int, ctypes.c_int, P(c_d)]
-        L.orc_observe.argtypes = [P(World), P(Obs), P(State), c_i64, c_i64, P(c_d), P(c_d), P(c_d), P(c_i8),
-                                  P(c_d), P(c_d), P(c_d), P(c_d), P(c_i64), P(c_d), P(c_d)]
-        L.orc_ephemeris.argtypes = [P(World), c_d, P(c_d), P(c_d)]
-        L.orc_normal_triad.argtypes = [c_d, c_d, P(c_d), P(c_d), P(c_d)]
-        L.orc_source_update.argtypes = [P(World), P(Obs), P(State), P(c_d), P(c_d), P(c_i32), P(c_d)]
-        L.orc_attitude_update.argtypes = [P(World), P(Obs), P(State), P(c_d)]
+        L.orc_band_c2.argtypes = [P(c_r), ctypes.c_int, ctypes.c_int, P(c_r)]
+        L.orc_band_c3.argtypes = [P(c_r), ctypes.c_int, ctypes.c_int, P(c_r)]
+        L.orc_observe.argtypes = [P(World), P(Obs), P(State), c_i64, c_i64, P(c_r), P(c_r), P(c_r), P(c_i8),
+                                  P(c_r), P(c_r), P(c_r), P(c_r), P(c_i64), P(c_r), P(c_r)]
+        L.orc_ephemeris.argtypes = [P(World), c_r, P(c_r), P(c_r)]
+        L.orc_normal_triad.argtypes = [c_r, c_r, P(c_r), P(c_r), P(c_r)]
+        L.orc_source_update.argtypes = [P(World), P(Obs), P(State), P(c_r), P(c_r), P(c_i32), P(c_r)]
+        L.orc_attitude_update.argtypes = [P(World), P(Obs), P(State), P(c_r)]
         L.orc_attitude_update.restype = c_i64
-        L.orc_attitude_segment.argtypes = [P(World), P(Obs), P(State), c_i64, P(c_d), P(c_i64), P(c_i64)]
+        L.orc_attitude_segment.argtypes = [P(World), P(Obs), P(State), c_i64, P(c_r), P(c_i64), P(c_i64)]
         L.orc_attitude_segment.restype = c_i64
         L.orc_num_segments.argtypes = [P(World)]
         L.orc_num_segments.restype = c_i64
-        L.orc_calibration_update.argtypes = [P(World), P(Obs), P(State), P(c_d)]
-        L.orc_iterate_sac.argtypes = [P(World), P(Obs), P(State), P(c_d)]
-        L.orc_frame_fit.argtypes = [P(World), P(State), P(c_d), P(c_d), P(c_d)]
-        L.orc_frame_apply.argtypes = [P(World), P(State), P(c_d)]
-        _lib = L
-    return _lib
+        L.orc_calibration_update.argtypes = [P(World), P(Obs), P(State), P(c_r)]
+        L.orc_iterate_sac.argtypes = [P(World), P(Obs), P(State), P(c_r)]
+        L.orc_frame_fit.argtypes = [P(World), P(State), P(c_r), P(c_r), P(c_r)]
+        L.orc_frame_apply.argtypes = [P(World), P(State), P(c_r)]
+        _libs[precision] = L
+    return _libs[precision]
 
 
 def _p(a, ct):
@@ -196,114 +219,135 @@ class Problem:
 
     ``consts`` keys: gamma_c, t_ep, t_fr, lambda_reg, seg_len, seg_overlap,
     eph_radius_au, eph_L0, eph_Lrate, eps_obl, au_m, c_mps, year_s.
+    ``precision``: "double" (the oracle) or "extended" (the same code in x87
+    extended precision; arrays are then numpy longdouble).
     """
 
-    def __init__(self, consts, knots, t, eta_obs, sigma, src, fov, cell, s, a, c):
-        self.knots = _vec(knots)
-        self.t = _vec(t)
-        self.eta_obs = _vec(eta_obs)
+    def __init__(self, consts, knots, t, eta_obs, sigma, src, fov, cell, s, a, c, precision="double"):
+        self.precision = precision
+        self._cr, self._dt = PRECISIONS[precision][0], PRECISIONS[precision][1]
+        self._World, self._Obs, self._State = _STRUCTS[precision]
+        self._L = lib(precision)
+        self.knots = self._arr(knots)
+        self.t = self._arr(t)
+        self.eta_obs = self._arr(eta_obs)
         self.sigma = np.ascontiguousarray(sigma, dtype=np.float32)
         self.src = np.ascontiguousarray(src, dtype=np.int32)
         self.fov = np.ascontiguousarray(fov, dtype=np.int8)
         self.cell = np.ascontiguousarray(cell, dtype=np.int32)
-        self.s = np.ascontiguousarray(s, dtype=np.float64).copy()
-        self.a = np.ascontiguousarray(a, dtype=np.float64).copy()
-        self.c = np.ascontiguousarray(c, dtype=np.float64).copy()
+        self.s = self._arr(s).copy()
+        self.a = self._arr(a).copy()
+        self.c = self._arr(c).copy()
         self.consts = dict(consts)
-        self.world = World(n_knots=self.knots.size, knots=_p(self.knots, c_d), gamma_c=consts["gamma_c"],
-                           t_ep=consts["t_ep"], t_fr=consts["t_fr"], lambda_reg=consts["lambda_reg"],
-                           seg_len=int(consts["seg_len"]), seg_overlap=int(consts["seg_overlap"]),
-                           eph_radius_au=consts["eph_radius_au"], eph_L0=consts["eph_L0"],
-                           eph_Lrate=consts["eph_Lrate"], eps_obl=consts["eps_obl"], au_m=consts["au_m"],
-                           c_mps=consts["c_mps"], year_s=consts["year_s"])
+        cr = self._cr
+        self.world = self._World(n_knots=self.knots.size, knots=_p(self.knots, cr), gamma_c=consts["gamma_c"],
+                                 t_ep=consts["t_ep"], t_fr=consts["t_fr"], lambda_reg=consts["lambda_reg"],
+                                 seg_len=int(consts["seg_len"]), seg_overlap=int(consts["seg_overlap"]),
+                                 eph_radius_au=consts["eph_radius_au"], eph_L0=consts["eph_L0"],
+                                 eph_Lrate=consts["eph_Lrate"], eps_obl=consts["eps_obl"], au_m=consts["au_m"],
+                                 c_mps=consts["c_mps"], year_s=consts["year_s"])
         self._refresh()
 
+    def _arr(self, x):
+        return np.ascontiguousarray(x, dtype=self._dt)
+
+    def _zeros(self, shape):
+        return np.zeros(shape, dtype=self._dt)
+
     def _refresh(self):
-        self.obs = Obs(n=self.t.size, t=_p(self.t, c_d), eta_obs=_p(self.eta_obs, c_d), sigma=_p(self.sigma, c_f),
-                       src=_p(self.src, c_i32), fov=_p(self.fov, c_i8), cell=_p(self.cell, c_i32))
-        self.state = State(n_src=self.s.shape[0], n_att=self.a.shape[0], n_cells=self.c.size,
-                           s=_p(self.s, c_d), a=_p(self.a, c_d), c=_p(self.c, c_d))
+        cr = self._cr
+        self.obs = self._Obs(n=self.t.size, t=_p(self.t, cr), eta_obs=_p(self.eta_obs, cr),
+                             sigma=_p(self.sigma, c_f), src=_p(self.src, c_i32), fov=_p(self.fov, c_i8),
+                             cell=_p(self.cell, c_i32))
+        self.state = self._State(n_src=self.s.shape[0], n_att=self.a.shape[0], n_cells=self.c.size,
+                                 s=_p(self.s, cr), a=_p(self.a, cr), c=_p(self.c, cr))
 
     def set_eta_obs(self, eta_obs):
-        self.eta_obs = _vec(eta_obs).copy()
+        self.eta_obs = self._arr(eta_obs).copy()
         self._refresh()
 
     def set_state(self, s=None, a=None, c=None):
         if s is not None:
-            self.s = np.ascontiguousarray(s, dtype=np.float64).copy()
+            self.s = self._arr(s).copy()
         if a is not None:
-            self.a = np.ascontiguousarray(a, dtype=np.float64).copy()
+            self.a = self._arr(a).copy()
         if c is not None:
-            self.c = np.ascontiguousarray(c, dtype=np.float64).copy()
+            self.c = self._arr(c).copy()
         self._refresh()
 
     def observe(self, i0=0, i1=None, partials=False):
         n = self.t.size
         i1 = n if i1 is None else i1
-        out = dict(eta=np.zeros(n), phi=np.zeros(n), zeta=np.zeros(n), f=np.zeros(n, np.int8), R=np.zeros(n),
-                   bspl=np.zeros((n, 4)), ell=np.zeros(n, np.int64), qraw=np.zeros((n, 4)), D=np.zeros(n))
+        z = self._zeros
+        out = dict(eta=z(n), phi=z(n), zeta=z(n), f=np.zeros(n, np.int8), R=z(n),
+                   bspl=z((n, 4)), ell=np.zeros(n, np.int64), qraw=z((n, 4)), D=z(n))
         if partials:
-            out["dsrc"] = np.zeros((n, 5))
-            out["dq"] = np.zeros((n, 4))
-        lib().orc_observe(ctypes.byref(self.world), ctypes.byref(self.obs), ctypes.byref(self.state), i0, i1,
-                          _p(out["eta"], c_d), _p(out["phi"], c_d), _p(out["zeta"], c_d), _p(out["f"], c_i8),
-                          _p(out["R"], c_d), _p(out.get("dsrc"), c_d), _p(out.get("dq"), c_d),
-                          _p(out["bspl"], c_d), _p(out["ell"], c_i64), _p(out["qraw"], c_d), _p(out["D"], c_d))
+            out["dsrc"] = z((n, 5))
+            out["dq"] = z((n, 4))
+        cr = self._cr
+        self._L.orc_observe(ctypes.byref(self.world), ctypes.byref(self.obs), ctypes.byref(self.state), i0, i1,
+                            _p(out["eta"], cr), _p(out["phi"], cr), _p(out["zeta"], cr), _p(out["f"], c_i8),
+                            _p(out["R"], cr), _p(out.get("dsrc"), cr), _p(out.get("dq"), cr),
+                            _p(out["bspl"], cr), _p(out["ell"], c_i64), _p(out["qraw"], cr), _p(out["D"], cr))
         return out
 
     def ephemeris(self, t):
-        b, v = np.empty(3), np.empty(3)
-        lib().orc_ephemeris(ctypes.byref(self.world), float(t), _p(b, c_d), _p(v, c_d))
+        b, v = self._zeros(3), self._zeros(3)
+        self._L.orc_ephemeris(ctypes.byref(self.world), t, _p(b, self._cr), _p(v, self._cr))
         return b, v
 
     def source_update(self):
         ns = self.s.shape[0]
-        d, Q, de = np.zeros((ns, 5)), np.zeros(ns), np.zeros(ns, np.int32)
-        self.var = np.zeros((ns, 5))
-        lib().orc_source_update(ctypes.byref(self.world), ctypes.byref(self.obs), ctypes.byref(self.state),
-                                _p(d, c_d), _p(Q, c_d), _p(de, c_i32), _p(self.var, c_d))
+        d, Q, de = self._zeros((ns, 5)), self._zeros(ns), np.zeros(ns, np.int32)
+        self.var = self._zeros((ns, 5))
+        cr = self._cr
+        self._L.orc_source_update(ctypes.byref(self.world), ctypes.byref(self.obs), ctypes.byref(self.state),
+                                  _p(d, cr), _p(Q, cr), _p(de, c_i32), _p(self.var, cr))
         return d, Q, de
 
     def attitude_update(self):
         d = np.zeros_like(self.a)
-        de = lib().orc_attitude_update(ctypes.byref(self.world), ctypes.byref(self.obs), ctypes.byref(self.state),
-                                       _p(d, c_d))
+        de = self._L.orc_attitude_update(ctypes.byref(self.world), ctypes.byref(self.obs),
+                                         ctypes.byref(self.state), _p(d, self._cr))
         return d, int(de)
 
     def attitude_segment(self, K):
         d = np.full_like(self.a, np.nan)
         lo, hi = c_i64(), c_i64()
-        de = lib().orc_attitude_segment(ctypes.byref(self.world), ctypes.byref(self.obs), ctypes.byref(self.state),
-                                        int(K), _p(d, c_d), ctypes.byref(lo), ctypes.byref(hi))
+        de = self._L.orc_attitude_segment(ctypes.byref(self.world), ctypes.byref(self.obs),
+                                          ctypes.byref(self.state), int(K), _p(d, self._cr), ctypes.byref(lo),
+                                          ctypes.byref(hi))
         return d, int(de), lo.value, hi.value
 
     def num_segments(self):
-        return int(lib().orc_num_segments(ctypes.byref(self.world)))
+        return int(self._L.orc_num_segments(ctypes.byref(self.world)))
 
     def calibration_update(self):
         d = np.zeros_like(self.c)
-        lib().orc_calibration_update(ctypes.byref(self.world), ctypes.byref(self.obs), ctypes.byref(self.state),
-                                     _p(d, c_d))
+        self._L.orc_calibration_update(ctypes.byref(self.world), ctypes.byref(self.obs), ctypes.byref(self.state),
+                                       _p(d, self._cr))
         return d
 
     def iterate_sac(self):
-        self.var = np.zeros((self.s.shape[0], 5))
-        lib().orc_iterate_sac(ctypes.byref(self.world), ctypes.byref(self.obs), ctypes.byref(self.state),
-                              _p(self.var, c_d))
+        self.var = self._zeros((self.s.shape[0], 5))
+        self._L.orc_iterate_sac(ctypes.byref(self.world), ctypes.byref(self.obs), ctypes.byref(self.state),
+                                _p(self.var, self._cr))
 
     def frame_fit(self, s_ref, weighted=True):
         """Frame rotator fit; weighted by the variances of the last S update
         (unit weights before any, or with weighted=False)."""
-        s_ref = np.ascontiguousarray(s_ref, dtype=np.float64)
-        eo = np.zeros(6)
+        s_ref = self._arr(s_ref)
+        eo = self._zeros(6)
         var = getattr(self, "var", None) if weighted else None
-        lib().orc_frame_fit(ctypes.byref(self.world), ctypes.byref(self.state), _p(s_ref, c_d), _p(var, c_d),
-                            _p(eo, c_d))
+        cr = self._cr
+        self._L.orc_frame_fit(ctypes.byref(self.world), ctypes.byref(self.state), _p(s_ref, cr), _p(var, cr),
+                              _p(eo, cr))
         return eo
 
     def frame_apply(self, eo):
-        eo = _vec(eo, 6)
-        lib().orc_frame_apply(ctypes.byref(self.world), ctypes.byref(self.state), _p(eo, c_d))
+        eo = self._arr(eo)
+        assert eo.size == 6
+        self._L.orc_frame_apply(ctypes.byref(self.world), ctypes.byref(self.state), _p(eo, self._cr))
 
     def iterate(self, s_ref=None):
         """One S[AC] iteration, then (if s_ref is given) the frame rotator."""
@@ -315,7 +359,7 @@ class Problem:
         return None
 
 
-def problem_from_world(world, eta_obs=None, state="start"):
+def problem_from_world(world, eta_obs=None, state="start", precision="double"):
     """Build a Problem from a synth.World; eta_obs defaults to zeros."""
     n = world.t.size
     eta = np.zeros(n) if eta_obs is None else eta_obs
@@ -323,7 +367,8 @@ def problem_from_world(world, eta_obs=None, state="start"):
         s, a, c = world.src_start, world.att_start, world.cal_start
     else:
         s, a, c = world.src_true, world.att_true, world.cal_true
-    return Problem(world.consts, world.knots, world.t, eta, world.sigma, world.src, world.fov, world.cell, s, a, c)
+    return Problem(world.consts, world.knots, world.t, eta, world.sigma, world.src, world.fov, world.cell, s, a, c,
+                   precision=precision)
 
 
 def observed_field_angles(world):

@@ -1,19 +1,27 @@
 /*
  * AGIS CPU oracle -- TEST INFRASTRUCTURE ONLY (see agis_oracle.h).
  *
- * Plain double-precision C, one formula per paper equation, in the order the
- * paper gives them.  No blocking, fusion or algebraic short-cuts beyond what
+ * Plain double-precision C (or x87 extended with ORC_EXTENDED), one formula
+ * per paper equation, in the order the paper gives them.  No blocking, fusion or algebraic short-cuts beyond what
  * the equations state; loops over independent sources / segments may run in
  * parallel (results do not depend on the thread count).
  *
  * Citations name sections, equation labels and algorithms of Lindegren et
  * al. (2012), "The astrometric core solution for the Gaia mission".
  */
-#include "agis_oracle.h"
-
-#include <math.h>
+#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <tgmath.h>
+
+/* The same source also builds as a reference in x87 extended precision
+ * (64-bit significand): every "double" below, including those of the header,
+ * becomes "long double" and <tgmath.h> picks the matching libm routines.
+ * The floating-point error of the FP64 build is measured against it. */
+#ifdef ORC_EXTENDED
+#define double long double
+#endif
+#include "agis_oracle.h"
 
 #define M_ORDER 4
 

@@ -47,6 +47,7 @@ struct agis_ctx {
     int64_t n_knots = 0, N = 0, K = 0;   // N coefficients, K = N - 3 intervals
     std::vector<double> h_knots;
     double* knots = nullptr;
+    agis::KnotTab* ktab = nullptr;       // [K] per-interval table of the observation model
 
     // observation store
     bool loaded = false;

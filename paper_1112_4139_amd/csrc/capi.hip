@@ -149,6 +149,27 @@ static void build_segments(agis_ctx* ctx) {
     ctx->ufac_rows = off;
 }
 
+// Table of the observation model per knot interval l = j + 3: orbital
+// longitude at tau_l, and 1/(tau_l+1 - tau_l) when tau_l-2..tau_l+3 are
+// exactly equally spaced (the closed-form B-splines then equal Algorithm B1
+// to rounding), else 0.
+static std::vector<KnotTab> knot_table(const agis_ctx* ctx) {
+    const std::vector<double>& kn = ctx->h_knots;
+    std::vector<KnotTab> tab(ctx->K);
+    for (int64_t j = 0; j < ctx->K; ++j) {
+        const int64_t l = j + 3;
+        const double dt = kn[l + 1] - kn[l];
+        bool uniform = dt > 0.0;
+        for (int64_t i = l - 2; i < l + 3 && uniform; ++i) uniform = (kn[i + 1] - kn[i]) == dt;
+        const double L = ctx->cfg.eph_L0 + ctx->cfg.eph_Lrate * kn[l];
+        tab[j].sL = std::sin(L);
+        tab[j].cL = std::cos(L);
+        tab[j].inv_dt = uniform ? 1.0 / dt : 0.0;
+        tab[j].tau = kn[l];
+    }
+    return tab;
+}
+
 extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
     g_create_error.clear();
     if (!cfg || !out) {
@@ -231,6 +252,10 @@ extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
     k.eph_Lrate = cfg->eph_Lrate;
     k.cos_obl = std::cos(cfg->eps_obl);
     k.sin_obl = std::sin(cfg->eps_obl);
+    k.cos_half_gamma = std::cos(k.gamma_half);
+    k.sin_half_gamma = std::sin(k.gamma_half);
+    k.half_gamma_err = (double)((long double)k.gamma_half -
+                                std::atan2((long double)k.sin_half_gamma, (long double)k.cos_half_gamma));
     build_segments(ctx);
     if (const char* e = std::getenv("AGIS_S_GROUP")) ctx->s_group = std::atoi(e);
     if (const char* e = std::getenv("AGIS_AC_GROUP")) ctx->ac_group = std::atoi(e);
@@ -241,6 +266,7 @@ extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
         return code;
     };
     if ((rc = dalloc(ctx, &ctx->knots, ctx->n_knots, "knots")) != AGIS_OK) return fail(rc);
+    if ((rc = dalloc(ctx, &ctx->ktab, ctx->K, "knot table")) != AGIS_OK) return fail(rc);
     if ((rc = dalloc(ctx, &ctx->a, 4 * ctx->N, "attitude")) != AGIS_OK) return fail(rc);
     if ((rc = dalloc(ctx, &ctx->da, 4 * ctx->N, "attitude update")) != AGIS_OK) return fail(rc);
     if ((rc = dalloc(ctx, &ctx->iv_sums, (size_t)IV_SUMS * ctx->K, "interval sums")) != AGIS_OK) return fail(rc);
@@ -254,7 +280,9 @@ extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
     if ((rc = dalloc(ctx, &ctx->red, ctx->red_len, "reduction scratch")) != AGIS_OK) return fail(rc);
     if ((rc = dalloc(ctx, &ctx->eo, 8, "frame parameters")) != AGIS_OK) return fail(rc);
     if ((rc = dalloc(ctx, &ctx->stat, 64, "statistics")) != AGIS_OK) return fail(rc);
+    const std::vector<KnotTab> h_ktab = knot_table(ctx);
     if (hipMemcpy(ctx->knots, cfg->knots, ctx->n_knots * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ctx->ktab, h_ktab.data(), h_ktab.size() * sizeof(KnotTab), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(ctx->segs, ctx->h_segs.data(), ctx->h_segs.size() * sizeof(SegDesc), hipMemcpyHostToDevice) !=
             hipSuccess ||
         hipMemset(ctx->da, 0, 4 * ctx->N * sizeof(double)) != hipSuccess ||
@@ -279,6 +307,7 @@ extern "C" void agis_destroy(agis_ctx_t* ctx) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     free_store(ctx);
     dfree(ctx->knots);
+    dfree(ctx->ktab);
     dfree(ctx->a);
     dfree(ctx->da);
     dfree(ctx->iv_sums);

@@ -13,13 +13,12 @@
 //                       10 block pairs x 10 unique entries of eq:normAmod, its
 //                       16 right-hand-side entries and the per-fov calibration
 //                       sums of eq:normC.
-//   k_band_solve        A solve (Sect. 5.2.2, App. C): one wavefront per segment;
-//                       right-looking modified band Cholesky (Algorithm C1 with
-//                       C2 folded in as an extra column) over a sliding window
-//                       of 16 unknowns in LDS, with the per-interval sums
-//                       prefetched into an LDS ring one coefficient block
-//                       ahead; then C3 with the factor rows prefetched 16 rows
-//                       ahead; the segment keeps its selected coefficients.
+//   k_band_solve        A solve (Sect. 5.2.2, App. C): one 16-lane row of a
+//                       wavefront per segment; right-looking modified band
+//                       Cholesky (Algorithm C1 with C2 folded in) over a
+//                       register window of 16 rows x 16 band offsets, rows
+//                       entering from the per-interval sums in an LDS ring;
+//                       then C3; the segment keeps its selected coefficients.
 //
 // Each lane walks its item's observations with stride G and loads the next
 // observation's columns while the current one is evaluated.  No global
@@ -47,7 +46,8 @@ __global__ __launch_bounds__(256) void k_source_update(DevConsts k, int64_t n_sr
                                                        const float* __restrict__ osig,
                                                        const int32_t* __restrict__ ocell,
                                                        const int32_t* __restrict__ oell,
-                                                       const double* __restrict__ knots, const double* __restrict__ a,
+                                                       const double* __restrict__ knots,
+                                                       const KnotTab* __restrict__ ktab, const double* __restrict__ a,
                                                        const double* __restrict__ c, double* __restrict__ s,
                                                        SrcPrep* __restrict__ prep, double* __restrict__ ds,
                                                        double* __restrict__ qsrc, int32_t* __restrict__ sdef,
@@ -106,7 +106,8 @@ __global__ __launch_bounds__(256) void k_source_update(DevConsts k, int64_t n_sr
             ell_n = oell[ln];
         }
         ObsEval o;
-        observe(k, t_c, e_c, c[c_c >> 1], r, mu, plx, a + 4 * (ell_c - 3), knots + (ell_c - 2), o);
+        observe(k, t_c, e_c, c[c_c >> 1], r, mu, plx, a + 4 * (ell_c - 3), knots + (ell_c - 2), ktab[ell_c - 3],
+                o);
         double A[5];
         source_partials(o, p, q, r, A);
         const double sg = (double)s_c;
@@ -186,20 +187,72 @@ __global__ __launch_bounds__(256) void k_source_update(DevConsts k, int64_t n_sr
 }
 
 // ------------------------------------------------------------- A/C pass
+// Value of v in the other lane of the pair (lanes 2i, 2i+1): DPP quad_perm
+// [1, 0, 3, 2] on both 32-bit halves.
+__device__ __forceinline__ double pair_swap(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0xB1, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over the G/2 lanes of a group that share the parity of this lane.
+template <int G>
+__device__ __forceinline__ double parity_sum(double v) {
+#pragma unroll
+    for (int m = G / 2; m >= 2; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// What one observation adds to the sums of its knot interval: the 10 unique
+// entries of W (g g' + 4 lambda^2 q q') (eq:normAmod), the 4 entries of
+// -W (g R - 2 lambda^2 q D), the four B-splines, W and W R, and the field.
+struct AcTerm {
+    double M[10], rv[4], B[4], W, WR;
+    int f;
+};
+
+// Add one observation's term to this lane's half of the interval sums.
+// Lane parity p = 0 holds block pairs (n,m) = (0,0) (0,1) (0,2) (0,3) (1,1),
+// right-hand sides n = 0, 1 and the fov +1 calibration sums; p = 1 holds
+// (1,2) (1,3) (2,2) (2,3) (3,3), n = 2, 3 and fov -1.
+__device__ __forceinline__ void ac_accumulate(const AcTerm& x, int p, double* __restrict__ accP,
+                                              double* __restrict__ accR, double* __restrict__ accC) {
+    const double s1 = p ? x.B[1] : x.B[0];
+    const double s2 = p ? x.B[2] : x.B[0];
+    const double s3 = p ? x.B[3] : x.B[1];
+    const double bb[5] = {s1 * s2, s1 * s3, s2 * x.B[2], s2 * x.B[3], s3 * s3};
+#pragma unroll
+    for (int kk = 0; kk < 5; ++kk)
+#pragma unroll
+        for (int e = 0; e < 10; ++e) accP[kk * 10 + e] += bb[kk] * x.M[e];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        accR[r] += s2 * x.rv[r];
+        accR[4 + r] += s3 * x.rv[r];
+    }
+    const bool mine = x.f == p;
+    accC[0] += mine ? x.W : 0.0;
+    accC[1] += mine ? x.WR : 0.0;
+}
+
 template <int G>
 __global__ __launch_bounds__(256) void k_ac_pass(DevConsts k, int64_t K, const int64_t* __restrict__ iv_off,
                                                  const double* __restrict__ ot, const double* __restrict__ oeta,
                                                  const float* __restrict__ osig,
                                                  const int32_t* __restrict__ ocellfov,
                                                  const int32_t* __restrict__ osrc, const SrcPrep* __restrict__ prep,
-                                                 const double* __restrict__ knots, const double* __restrict__ a,
+                                                 const double* __restrict__ knots,
+                                                 const KnotTab* __restrict__ ktab, const double* __restrict__ a,
                                                  const double* __restrict__ c, double* __restrict__ iv_sums,
                                                  double* __restrict__ iv_cal) {
+    static_assert(G >= 2 && (G & (G - 1)) == 0, "G must be an even power of two");
     constexpr int GPB = 256 / G;
     __shared__ double sh_a[GPB][16];
     __shared__ double sh_k[GPB][6];
     const int gl = threadIdx.x % G;
     const int gi = threadIdx.x / G;
+    const int p = gl & 1;
     const int64_t j = (int64_t)blockIdx.x * GPB + gi;
     const bool valid = j < K;
     for (int e = gl; e < 22; e += G) {
@@ -209,96 +262,109 @@ __global__ __launch_bounds__(256) void k_ac_pass(DevConsts k, int64_t K, const i
         else sh_k[gi][e - 16] = v;
     }
     __syncthreads();
-    double accP[IV_PAIRS * 10];
-    double accR[16];
-    double accC[IV_CAL];
+    double accP[50], accR[8], accC[2];
 #pragma unroll
-    for (int e = 0; e < IV_PAIRS * 10; ++e) accP[e] = 0.0;
+    for (int e = 0; e < 50; ++e) accP[e] = 0.0;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) accR[e] = 0.0;
-#pragma unroll
-    for (int e = 0; e < IV_CAL; ++e) accC[e] = 0.0;
+    for (int e = 0; e < 8; ++e) accR[e] = 0.0;
+    accC[0] = accC[1] = 0.0;
     const double lam2 = k.lam2;
     const int64_t l0 = valid ? iv_off[j] : 0, l1 = valid ? iv_off[j + 1] : 0;
-    int64_t l = l0 + gl;
+    const KnotTab kt = valid ? ktab[j] : KnotTab{0.0, 1.0, 0.0, 0.0};
+    // The two lanes of a pair take observations base + {0, 1}, base advancing
+    // by G; both run the same iterations.  A lane past the end evaluates the
+    // interval's last observation again with weight zero.
+    int64_t base = l0 + (gl & ~1);
     double t_c = 0.0, e_c = 0.0;
     float s_c = 1.0f;
     int32_t cf_c = 0;
+    bool h_c = false;
     SrcPrep sp_c = {};
-    if (l < l1) {
-        t_c = ot[l];
-        e_c = oeta[l];
-        s_c = osig[l];
-        cf_c = ocellfov[l];
-        sp_c = prep[osrc[l]];
+    if (base < l1) {
+        h_c = base + p < l1;
+        const int64_t le = h_c ? base + p : l1 - 1;
+        t_c = ot[le];
+        e_c = oeta[le];
+        s_c = osig[le];
+        cf_c = ocellfov[le];
+        sp_c = prep[osrc[le]];
     }
-    for (; l < l1; l += G) {
-        const int64_t ln = l + G;
+    for (; base < l1; base += G) {
+        const int64_t bn = base + G;
         double t_n = 0.0, e_n = 0.0;
         float s_n = 1.0f;
         int32_t cf_n = 0, src_n = 0;
-        if (ln < l1) {
-            t_n = ot[ln];
-            e_n = oeta[ln];
-            s_n = osig[ln];
-            cf_n = ocellfov[ln];
-            src_n = osrc[ln];
+        bool h_n = false;
+        if (bn < l1) {
+            h_n = bn + p < l1;
+            const int64_t le = h_n ? bn + p : l1 - 1;
+            t_n = ot[le];
+            e_n = oeta[le];
+            s_n = osig[le];
+            cf_n = ocellfov[le];
+            src_n = osrc[le];
         }
-        ObsEval o;
-        observe(k, t_c, e_c, c[cf_c >> 1], sp_c.r, sp_c.mu, sp_c.plx, sh_a[gi], sh_k[gi], o);
+        AcTerm own, oth;
+        {
+            ObsEval o;
+            observe(k, t_c, e_c, c[cf_c >> 1], sp_c.r, sp_c.mu, sp_c.plx, sh_a[gi], sh_k[gi], kt, o);
+            double g[4];
+            attitude_partial(o, g);
+            const double sg = (double)s_c;
+            const double W = h_c ? 1.0 / (sg * sg) : 0.0;
+            int e = 0;
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+                for (int cc = rr; cc < 4; ++cc)
+                    own.M[e++] = W * (g[rr] * g[cc] + 4.0 * lam2 * o.qraw[rr] * o.qraw[cc]);
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) own.rv[rr] = -W * (g[rr] * o.R - 2.0 * lam2 * o.qraw[rr] * o.D);
+#pragma unroll
+            for (int n = 0; n < 4; ++n) own.B[n] = o.B[n];
+            own.W = W;
+            own.WR = W * o.R;
+            own.f = cf_c & 1;
+        }
         SrcPrep sp_n = {};
-        if (ln < l1) sp_n = prep[src_n];
-        double g[4];
-        attitude_partial(o, g);
-        const double sg = (double)s_c;
-        const double W = 1.0 / (sg * sg);
-        double M[10], rv[4];
-        int e = 0;
+        if (bn < l1) sp_n = prep[src_n];
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr)
+        for (int e = 0; e < 10; ++e) oth.M[e] = pair_swap(own.M[e]);
 #pragma unroll
-            for (int cc = rr; cc < 4; ++cc)
-                M[e++] = W * (g[rr] * g[cc] + 4.0 * lam2 * o.qraw[rr] * o.qraw[cc]);
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) rv[rr] = -W * (g[rr] * o.R - 2.0 * lam2 * o.qraw[rr] * o.D);
-        int pp = 0;
-#pragma unroll
-        for (int n = 0; n < 4; ++n)
-#pragma unroll
-            for (int m = n; m < 4; ++m) {
-                const double bb = o.B[n] * o.B[m];
-#pragma unroll
-                for (int ee = 0; ee < 10; ++ee) accP[pp * 10 + ee] += bb * M[ee];
-                ++pp;
-            }
-#pragma unroll
-        for (int n = 0; n < 4; ++n)
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) accR[n * 4 + rr] += o.B[n] * rv[rr];
-        const int f = cf_c & 1;
-        accC[2 * f] += W;
-        accC[2 * f + 1] += W * o.R;
+        for (int e = 0; e < 4; ++e) {
+            oth.rv[e] = pair_swap(own.rv[e]);
+            oth.B[e] = pair_swap(own.B[e]);
+        }
+        oth.W = pair_swap(own.W);
+        oth.WR = pair_swap(own.WR);
+        oth.f = __builtin_amdgcn_update_dpp(0, own.f, 0xB1, 0xF, 0xF, false);
+        ac_accumulate(own, p, accP, accR, accC);
+        ac_accumulate(oth, p, accP, accR, accC);
         t_c = t_n;
         e_c = e_n;
         s_c = s_n;
         cf_c = cf_n;
+        h_c = h_n;
         sp_c = sp_n;
     }
+    // Lane gl holds, after the reduction, the totals of its parity's half;
+    // the G/2 lanes of one parity share the stores.
+    const int slot = gl >> 1;
     double* out = iv_sums + j * IV_SUMS;
 #pragma unroll
-    for (int e = 0; e < IV_PAIRS * 10; ++e) {
-        const double v = group_sum<G>(accP[e]);
-        if (valid && gl == (e % G)) out[e] = v;
+    for (int e = 0; e < 50; ++e) {
+        const double v = parity_sum<G>(accP[e]);
+        if (valid && slot == e % (G / 2)) out[50 * p + e] = v;
     }
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const double v = group_sum<G>(accR[e]);
-        if (valid && gl == ((100 + e) % G)) out[100 + e] = v;
+    for (int e = 0; e < 8; ++e) {
+        const double v = parity_sum<G>(accR[e]);
+        if (valid && slot == (50 + e) % (G / 2)) out[100 + 8 * p + e] = v;
     }
 #pragma unroll
-    for (int e = 0; e < IV_CAL; ++e) {
-        const double v = group_sum<G>(accC[e]);
-        if (valid && gl == (e % G)) iv_cal[j * IV_CAL + e] = v;
+    for (int e = 0; e < 2; ++e) {
+        const double v = parity_sum<G>(accC[e]);
+        if (valid && slot == (58 + e) % (G / 2)) iv_cal[j * IV_CAL + 2 * p + e] = v;
     }
 }
 
@@ -329,163 +395,155 @@ __device__ __forceinline__ double ring_rhs(const double (*ring)[RING_W], int64_t
     return s;
 }
 
-constexpr int PF = (RING_W + 63) / 64;  // doubles per lane to fetch one interval
+// Value of v in another lane of the 16-lane row (DPP, both 32-bit halves):
+// CTRL 0x150 + n broadcasts lane n of the row, 0x100 + n reads lane + n,
+// 0x110 + n reads lane - n, 0x120 + n rotates by n; lanes with no source
+// read 0.
+template <int CTRL>
+__device__ __forceinline__ double row_dpp(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
 
+// Right-looking update of the window rows c = C..15 by pivot row i:
+// lane d, row c: entry (i+c, i+c+d) -= U(i, i+c) U(i, i+c+d).
+template <int C>
+__device__ __forceinline__ void band_trailing(double (&W)[16], double U) {
+    if constexpr (C < 16) {
+        W[C] -= row_dpp<0x150 + C>(U) * row_dpp<0x100 + C>(U);
+        band_trailing<C + 1>(W, U);
+    }
+}
+
+constexpr int BAND_SEGS = 4;            // segments per wavefront, one per 16-lane row
+constexpr int PFL = (RING_W + 15) / 16; // doubles per lane to fetch one interval
+
+// Modified band Cholesky of the attitude segments (Algorithms C1-C3 with
+// half bandwidth 15, Sect. 5.2.2).  Each 16-lane row of the wavefront solves
+// one segment: lane d holds band offset d of the 16 window rows i..i+15 in
+// registers (W[c] = entry (i+c, i+c+d)) and the right-hand side of row i+d.
+// Step i takes the pivot from lane 0, forms U(i, i+d) in lane d, updates the
+// window through row broadcasts and shifts, retires row i and lets row i+16
+// enter from the per-interval sums (an LDS ring, each interval prefetched
+// two coefficient blocks ahead).  A zero or negative pivot gives a zero
+// factor row and counts one defect.  C3 then runs back up the segment with
+// x(i+d) in lane d and a row reduction per step.
 __global__ __launch_bounds__(64) void k_band_solve(int64_t nseg, const SegDesc* __restrict__ segs,
                                                    const double* __restrict__ iv_sums, double* __restrict__ ufac,
                                                    double* __restrict__ yfac, double* __restrict__ da,
                                                    int32_t* __restrict__ seg_def) {
-    __shared__ double ring[RING][RING_W];
-    __shared__ double Wn[16][17];      // window: row slot i & 15, column slot kk & 15, column 16 = rhs
-    __shared__ double Ur[17];
-    __shared__ double X[16];
-    __shared__ double Ub[2][16][17];   // back substitution: factor rows (+ y) of two 16-row chunks
-    const int lane = threadIdx.x;
-    const int64_t sgi = blockIdx.x;
-    if (sgi >= nseg) return;
-    const SegDesc d = segs[sgi];
-    const int64_t nb = d.n_hi - d.n_lo + 1;
-    const int64_t nu = 4 * nb;
-    const int64_t n_iv = nb - 3;       // intervals of the segment
-    const double* sums = iv_sums + d.n_lo * IV_SUMS;
-    double* U = ufac + d.u_off * 16;
-    double* Y = yfac + d.u_off;
-    // intervals 0..4 into the ring
-    for (int jj = 0; jj < 5 && jj < n_iv; ++jj)
-        for (int e = lane; e < RING_W; e += 64) ring[jj][e] = sums[(int64_t)jj * IV_SUMS + e];
-    __syncthreads();
-    for (int idx = lane; idx < 16 * 17; idx += 64) {
-        const int row = idx / 17, col = idx % 17;
-        double v = 0.0;
-        if (row < nu) {
-            if (col == 16) v = ring_rhs(ring, nb, row);
-            else if (col >= row && col < nu) v = ring_entry(ring, nb, row, col);
+    __shared__ double ring_all[BAND_SEGS][RING][RING_W];
+    const int d = threadIdx.x & 15;
+    const int sl = threadIdx.x >> 4;
+    const int64_t sgi = (int64_t)blockIdx.x * BAND_SEGS + sl;
+    const bool valid = sgi < nseg;
+    double (*ring)[RING_W] = ring_all[sl];
+    SegDesc sd = {0, -1, 0, -1, 0};
+    if (valid) sd = segs[sgi];
+    const int64_t nb = sd.n_hi - sd.n_lo + 1;
+    const int64_t nu = valid ? 4 * nb : 0;
+    const int64_t n_iv = valid ? nb - 3 : 0;
+    int64_t nu_max = 0;
+    for (int s2 = 0; s2 < BAND_SEGS; ++s2) {
+        const int64_t g = (int64_t)blockIdx.x * BAND_SEGS + s2;
+        if (g < nseg) {
+            const SegDesc o = segs[g];
+            const int64_t n2 = 4 * (o.n_hi - o.n_lo + 1);
+            nu_max = n2 > nu_max ? n2 : nu_max;
         }
-        Wn[row][col] = v;
+    }
+    const double* sums = iv_sums + (valid ? sd.n_lo : 0) * IV_SUMS;
+    double* U = ufac + sd.u_off * 16;
+    double* Y = yfac + sd.u_off;
+    // intervals 0..4 into the ring, interval 5 into registers
+    for (int jj = 0; jj < 5; ++jj)
+        if (jj < n_iv)
+            for (int e = d; e < RING_W; e += 16) ring[jj][e] = sums[(int64_t)jj * IV_SUMS + e];
+    double pfA[PFL], pfB[PFL];
+#pragma unroll
+    for (int u = 0; u < PFL; ++u) {
+        const int e = d + 16 * u;
+        pfA[u] = (5 < n_iv && e < RING_W) ? sums[5 * IV_SUMS + e] : 0.0;
+        pfB[u] = 0.0;
     }
     __syncthreads();
+    double W[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) W[c] = (c + d < nu) ? ring_entry(ring, nb, c, c + d) : 0.0;
+    double R = d < nu ? ring_rhs(ring, nb, d) : 0.0;
     int defect = 0;
-    double pf[PF];
-    for (int64_t i = 0; i < nu; ++i) {
+    for (int64_t i = 0; i < nu_max; ++i) {
+        const bool act = i < nu;
         const int64_t b = i >> 2;
-        const bool block_start = (i & 3) == 0;
-        const int64_t jpf = b + 5;     // interval to prefetch during this block
-        if (block_start && jpf < n_iv) {
+        if ((i & 3) == 0 && b + 6 < n_iv) {
 #pragma unroll
-            for (int u = 0; u < PF; ++u) {
-                const int e = lane + 64 * u;
-                pf[u] = e < RING_W ? sums[jpf * IV_SUMS + e] : 0.0;
+            for (int u = 0; u < PFL; ++u) {
+                const int e = d + 16 * u;
+                pfB[u] = e < RING_W ? sums[(b + 6) * IV_SUMS + e] : 0.0;
             }
         }
-        const int si = (int)(i & 15);
-        const double piv = Wn[si][si];
+        const double piv = row_dpp<0x150>(W[0]);
         const bool ok = piv > 0.0;
-        const double uu = ok ? sqrt(piv) : 0.0;
-        const double inv = ok ? 1.0 / uu : 0.0;
-        if (!ok) ++defect;
-        if (lane < 16) {
-            const int64_t kk = i + lane;
-            double v = 0.0;
-            if (kk < nu) v = lane == 0 ? uu : Wn[si][kk & 15] * inv;
-            U[i * 16 + lane] = v;
-            Ur[lane] = v;
-        } else if (lane == 16) {
-            const double y = Wn[si][16] * inv;
-            Y[i] = y;
-            Ur[16] = y;
+        const double inv = ok ? rsqrt_nr(piv) : 0.0;
+        const double Ud = d == 0 ? piv * inv : W[0] * inv;
+        const double y = row_dpp<0x150>(R) * inv;
+        if (act) {
+            U[i * 16 + d] = Ud;
+            if (d == 0) {
+                Y[i] = y;
+                defect += ok ? 0 : 1;
+            }
         }
-        __syncthreads();
-        // trailing update: 120 pairs (dj, dk), 1 <= dj <= dk <= 15, then 15
-        // right-hand-side items
-        for (int w = lane; w < 135; w += 64) {
-            if (w < 120) {
-                int dj = 1, rem = w;
-                while (rem >= 16 - dj) {
-                    rem -= 16 - dj;
-                    ++dj;
+        band_trailing<1>(W, Ud);
+        R -= Ud * y;
+        R = row_dpp<0x101>(R);
+#pragma unroll
+        for (int c = 0; c < 15; ++c) W[c] = W[c + 1];
+        const int64_t r = i + 16;
+        W[15] = (r + d < nu) ? ring_entry(ring, nb, r, r + d) : 0.0;
+        if (d == 15) R = r < nu ? ring_rhs(ring, nb, r) : 0.0;
+        if ((i & 3) == 3) {
+            // block b done: interval b + 5 enters the ring in the slot of
+            // interval b - 3, which no later row refers to
+            if (b + 5 < n_iv) {
+#pragma unroll
+                for (int u = 0; u < PFL; ++u) {
+                    const int e = d + 16 * u;
+                    if (e < RING_W) ring[(b + 5) & (RING - 1)][e] = pfA[u];
                 }
-                const int dk = dj + rem;
-                const int64_t jj = i + dj, kk = i + dk;
-                if (kk < nu) Wn[jj & 15][kk & 15] -= Ur[dj] * Ur[dk];
-            } else {
-                const int dj = w - 119;
-                const int64_t jj = i + dj;
-                if (jj < nu) Wn[jj & 15][16] -= Ur[dj] * Ur[16];
             }
-        }
-        __syncthreads();
-        const int64_t kn = i + 16;     // column entering the window
-        if (kn < nu) {
-            if (lane < 16) {
-                const int64_t jj = kn - 15 + lane;
-                Wn[jj & 15][kn & 15] = ring_entry(ring, nb, jj, kn);
-            } else if (lane == 16) {
-                Wn[kn & 15][16] = ring_rhs(ring, nb, kn);
-            }
-        }
-        if ((i & 3) == 3 && jpf < n_iv) {
-            // end of block b: the prefetched interval b + 5 enters the ring
-            // (its slot held interval b - 3, no longer referenced)
 #pragma unroll
-            for (int u = 0; u < PF; ++u) {
-                const int e = lane + 64 * u;
-                if (e < RING_W) ring[jpf & (RING - 1)][e] = pf[u];
-            }
-        }
-        __syncthreads();
-    }
-    // back substitution (Algorithm C3), factor rows fetched a chunk ahead
-    if (lane < 16) X[lane] = 0.0;
-    const int64_t nchunk = (nu + 15) / 16;
-    auto load_chunk = [&](int64_t ch, double* regs) {
-#pragma unroll
-        for (int u = 0; u < 5; ++u) {
-            const int idx = lane + 64 * u;          // 0 .. 16*17-1 used
-            double v = 0.0;
-            if (idx < 16 * 17) {
-                const int row = idx / 17, col = idx % 17;
-                const int64_t i = ch * 16 + row;
-                if (i < nu) v = col < 16 ? U[i * 16 + col] : Y[i];
-            }
-            regs[u] = v;
-        }
-    };
-    auto store_chunk = [&](int buf, const double* regs) {
-#pragma unroll
-        for (int u = 0; u < 5; ++u) {
-            const int idx = lane + 64 * u;
-            if (idx < 16 * 17) Ub[buf][idx / 17][idx % 17] = regs[u];
-        }
-    };
-    double cur[5], nxt[5];
-    load_chunk(nchunk - 1, cur);
-    store_chunk((nchunk - 1) & 1, cur);
-    __syncthreads();
-    for (int64_t ch = nchunk - 1; ch >= 0; --ch) {
-        if (ch > 0) load_chunk(ch - 1, nxt);
-        const int buf = (int)(ch & 1);
-        const int64_t i_hi = (ch * 16 + 15 < nu - 1) ? ch * 16 + 15 : nu - 1;
-        for (int64_t i = i_hi; i >= ch * 16; --i) {
-            const int row = (int)(i - ch * 16);
-            double v = 0.0;
-            if (lane >= 1 && lane < 16) {
-                const int64_t kk = i + lane;
-                if (kk < nu) v = Ub[buf][row][lane] * X[kk & 15];
-            }
-            v = group_sum<16>(v);
-            if (lane == 0) {
-                const double uii = Ub[buf][row][0];
-                const double xi = uii > 0.0 ? (Ub[buf][row][16] - v) / uii : 0.0;
-                X[i & 15] = xi;
-                const int64_t n = d.n_lo + (i >> 2);
-                if (n >= d.keep_lo && n <= d.keep_hi) da[4 * n + (i & 3)] = xi;
-            }
+            for (int u = 0; u < PFL; ++u) pfA[u] = pfB[u];
             __syncthreads();
         }
-        if (ch > 0) store_chunk((ch - 1) & 1, nxt);
-        __syncthreads();
     }
-    if (lane == 0) seg_def[sgi] = defect;
+    __syncthreads();   // factor rows and forward-substituted y visible to all lanes
+    // Algorithm C3 from the last row up: lane d holds x(i+d), d >= 1
+    double x = 0.0;
+    for (int64_t t = 0; t < nu_max; ++t) {
+        const int64_t i = nu - 1 - t;
+        const bool act = i >= 0;
+        double Uid = 0.0, uii = 0.0, yi = 0.0;
+        if (act) {
+            Uid = U[i * 16 + d];
+            uii = U[i * 16];
+            yi = Y[i];
+        }
+        double p = d >= 1 ? Uid * x : 0.0;
+        p += row_dpp<0x128>(p);
+        p += row_dpp<0x124>(p);
+        p += row_dpp<0x122>(p);
+        p += row_dpp<0x121>(p);
+        const double xi = uii > 0.0 ? (yi - p) * rcp_nr(uii) : 0.0;
+        if (act && d == 0) {
+            const int64_t n = sd.n_lo + (i >> 2);
+            if (n >= sd.keep_lo && n <= sd.keep_hi) da[4 * n + (i & 3)] = xi;
+        }
+        x = row_dpp<0x111>(d == 0 ? xi : x);
+    }
+    if (valid && d == 0) seg_def[sgi] = defect;
 }
 
 inline int groups_grid(int64_t n_items, int items_per_block) {
@@ -497,7 +555,7 @@ inline int groups_grid(int64_t n_items, int items_per_block) {
 #define AGIS_S_LAUNCH(G)                                                                                       \
     k_source_update<G><<<groups_grid(ctx->n_src, 256 / G), 256, 0, ctx->stream>>>(                             \
         ctx->k, ctx->n_src, ctx->src_off, ctx->s_t, ctx->s_eta, ctx->s_sig, ctx->s_cell, ctx->s_ell, ctx->knots, \
-        ctx->a, ctx->c, ctx->s, ctx->prep, ctx->ds, ctx->qsrc, ctx->sdef, ctx->svar)
+        ctx->ktab, ctx->a, ctx->c, ctx->s, ctx->prep, ctx->ds, ctx->qsrc, ctx->sdef, ctx->svar)
 
 void launch_source_update(agis_ctx* ctx) {
     if (ctx->n_src == 0) return;
@@ -512,11 +570,12 @@ void launch_source_update(agis_ctx* ctx) {
 #define AGIS_AC_LAUNCH(G)                                                                                     \
     k_ac_pass<G><<<groups_grid(ctx->K, 256 / G), 256, 0, ctx->stream>>>(                                       \
         ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, ctx->t_sig, ctx->t_cellfov, ctx->t_src, ctx->prep, \
-        ctx->knots, ctx->a, ctx->c, ctx->iv_sums, ctx->iv_cal)
+        ctx->knots, ctx->ktab, ctx->a, ctx->c, ctx->iv_sums, ctx->iv_cal)
 
 void launch_ac_pass(agis_ctx* ctx) {
     if (ctx->K == 0) return;
     switch (ctx->ac_group) {
+        case 2: AGIS_AC_LAUNCH(2); break;
         case 4: AGIS_AC_LAUNCH(4); break;
         case 8: AGIS_AC_LAUNCH(8); break;
         case 16: AGIS_AC_LAUNCH(16); break;
@@ -528,8 +587,8 @@ void launch_ac_pass(agis_ctx* ctx) {
 void launch_band_solve(agis_ctx* ctx) {
     const int64_t nseg = (int64_t)ctx->h_segs.size();
     if (nseg == 0) return;
-    k_band_solve<<<(unsigned)nseg, 64, 0, ctx->stream>>>(nseg, ctx->segs, ctx->iv_sums, ctx->ufac, ctx->yfac, ctx->da,
-                                                        ctx->seg_def);
+    k_band_solve<<<(unsigned)((nseg + BAND_SEGS - 1) / BAND_SEGS), 64, 0, ctx->stream>>>(
+        nseg, ctx->segs, ctx->iv_sums, ctx->ufac, ctx->yfac, ctx->da, ctx->seg_def);
 }
 
 }  // namespace agis

@@ -276,7 +276,8 @@ __global__ __launch_bounds__(256) void k_residuals(DevConsts k, int64_t K, const
                                                    const int32_t* __restrict__ ocellfov,
                                                    const int32_t* __restrict__ osrc,
                                                    const int32_t* __restrict__ operm, const SrcPrep* __restrict__ prep,
-                                                   const double* __restrict__ knots, const double* __restrict__ a,
+                                                   const double* __restrict__ knots,
+                                                   const KnotTab* __restrict__ ktab, const double* __restrict__ a,
                                                    const double* __restrict__ c, double* __restrict__ R) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t j = (int64_t)blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
@@ -284,10 +285,11 @@ __global__ __launch_bounds__(256) void k_residuals(DevConsts k, int64_t K, const
     double a4[16], kn[6];
     for (int e = 0; e < 16; ++e) a4[e] = a[4 * j + e];
     for (int e = 0; e < 6; ++e) kn[e] = knots[j + 1 + e];
+    const KnotTab kt = ktab[j];
     for (int64_t l = iv_off[j] + lane; l < iv_off[j + 1]; l += WAVE) {
         const SrcPrep sp = prep[osrc[l]];
         ObsEval o;
-        observe(k, ot[l], oeta[l], c[ocellfov[l] >> 1], sp.r, sp.mu, sp.plx, a4, kn, o);
+        observe(k, ot[l], oeta[l], c[ocellfov[l] >> 1], sp.r, sp.mu, sp.plx, a4, kn, kt, o);
         R[operm[l]] = o.R;
     }
 }
@@ -388,7 +390,7 @@ void launch_residuals(agis_ctx* ctx, double* R) {
     if (ctx->K == 0) return;
     k_residuals<<<waves_grid(ctx->K, 4), 256, 0, ctx->stream>>>(ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta,
                                                                  ctx->t_cellfov, ctx->t_src, ctx->t_perm, ctx->prep,
-                                                                 ctx->knots, ctx->a, ctx->c, R);
+                                                                 ctx->knots, ctx->ktab, ctx->a, ctx->c, R);
 }
 
 void launch_stats(agis_ctx* ctx, const double* x, int64_t n, int w, const double* extra, const int32_t* iextra,

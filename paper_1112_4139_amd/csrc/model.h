@@ -20,6 +20,8 @@ struct DevConsts {
     double eph_r, eph_L0, eph_Lrate, cos_obl, sin_obl;
     double t_fr;
     double year_s;
+    double cos_half_gamma, sin_half_gamma;   // rounded cos, sin of Gamma_c / 2
+    double half_gamma_err;                   // Gamma_c/2 - atan2(sin_half_gamma, cos_half_gamma)
 };
 
 // Source data gathered per observation by the time-ordered pass: barycentric
@@ -31,24 +33,33 @@ struct SrcPrep {
     double pad;
 };
 
+// Per knot interval [tau_l, tau_l+1): sine and cosine of the observer's
+// orbital longitude at tau_l, 1 / (tau_l+1 - tau_l) when the six knots
+// tau_l-2..tau_l+3 are equally spaced (0 otherwise), and tau_l.
+struct KnotTab {
+    double sL, cL;
+    double inv_dt;
+    double tau;
+};
+
 __device__ __forceinline__ double dot3(const double* a, const double* b) {
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
-// Barycentric position [AU] and velocity [AU/s] of the observer on the
-// circular orbit of the synthetic world.
-__device__ __forceinline__ void ephemeris(const DevConsts& k, double t, double b[3], double v[3]) {
-    double sL, cL;
-    sincos(k.eph_L0 + k.eph_Lrate * t, &sL, &cL);
-    double bx = k.eph_r * cL, by = k.eph_r * sL;
-    b[0] = bx;
-    b[1] = k.cos_obl * by;
-    b[2] = k.sin_obl * by;
-    double w = k.eph_r * k.eph_Lrate;
-    double vx = -w * sL, vy = w * cL;
-    v[0] = vx;
-    v[1] = k.cos_obl * vy;
-    v[2] = k.sin_obl * vy;
+// 1/sqrt(x) to ~1 ulp: hardware estimate and two Newton-Raphson steps.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * (1.5 - 0.5 * x * y * y);
+    y = y * (1.5 - 0.5 * x * y * y);
+    return y;
+}
+
+// 1/x to ~1 ulp: hardware estimate and two Newton-Raphson steps.
+__device__ __forceinline__ double rcp_nr(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = y * (2.0 - x * y);
+    y = y * (2.0 - x * y);
+    return y;
 }
 
 // The four non-zero cubic B-splines B_{l-3..l}(t) by de Boor's recurrence
@@ -99,6 +110,26 @@ __device__ __forceinline__ void quat2mat(const double q[4], double A[9]) {
     A[8] = 1.0 - 2.0 * (x * x + y * y);
 }
 
+// Attitude matrix of the rotation represented by any non-zero quaternion:
+// eq:quat2mat written in the homogeneous form (w^2 + x^2 - y^2 - z^2, ...)
+// and divided by |q|^2, with inv_n2 = 1/|q|^2.  For a unit quaternion it is
+// eq:quat2mat itself; a rounding error in |q| only scales the matrix, which
+// leaves every direction computed from it unchanged.
+__device__ __forceinline__ void quat2mat_h(const double q[4], double inv_n2, double A[9]) {
+    const double x = q[0], y = q[1], z = q[2], w = q[3];
+    const double xx = x * x, yy = y * y, zz = z * z, ww = w * w;
+    const double s2 = 2.0 * inv_n2;
+    A[0] = (ww + xx - yy - zz) * inv_n2;
+    A[1] = (x * y + z * w) * s2;
+    A[2] = (x * z - y * w) * s2;
+    A[3] = (x * y - z * w) * s2;
+    A[4] = (ww - xx + yy - zz) * inv_n2;
+    A[5] = (y * z + x * w) * s2;
+    A[6] = (x * z + y * w) * s2;
+    A[7] = (y * z - x * w) * s2;
+    A[8] = (ww - xx - yy + zz) * inv_n2;
+}
+
 // Everything one observation contributes; filled by observe().
 struct ObsEval {
     double R;          // residual eta_obs + c - eta
@@ -108,6 +139,7 @@ struct ObsEval {
     double tau;        // (t_B - t_ep) [yr]
     double Su[3];      // proper direction in the SRS
     double rho;        // sqrt(Su_x^2 + Su_y^2) = cos(zeta)
+    double inv_rho;    // 1 / rho
     double q[4];       // normalised attitude quaternion
     double qraw[4];    // sum a_n B_n (not normalised)
     double D;          // 1 - |qraw|^2 (eq:Dl)
@@ -116,19 +148,53 @@ struct ObsEval {
 };
 
 // Observation model (eq:roemer, eq:astro-standard, eq:classAberr,
-// eq:qspline, eq:srsprop, eq:srsprop1, eq:srspropeta, eq:resAL).
-// a4: the four coefficients a_{l-3..l} (x,y,z,w each); kn: tau_{l-2..l+3}.
-__device__ __forceinline__ void observe(const DevConsts& k, double t, double eta_obs, double cal, const double r[3],
-                                        const double mu[3], double plx, const double* __restrict__ a4,
-                                        const double* __restrict__ kn, ObsEval& o) {
+// eq:qspline, eq:srsprop, eq:srsprop1, eq:srspropeta, eq:resAL) for the
+// circular barycentric orbit of the synthetic world.  a4: the four
+// coefficients a_{l-3..l} (x,y,z,w each); kn: tau_{l-2..l+3} (read only when
+// the knots are not equally spaced); kt: the interval's table entry.
+// Evaluated with per-interval tables and without library transcendentals:
+//  * the ephemeris from sin/cos of the orbital longitude at tau_l rotated by
+//    the small angle d = Lrate (t - tau_l) (Taylor series to d^6);
+//  * on equally spaced knots the cubic B-splines in closed form
+//    ((1-u)^3, 3u^3 - 6u^2 + 4, -3u^3 + 3u^2 + 3u + 1, u^3) / 6 with
+//    u = (t - tau_l) / (tau_l+1 - tau_l), otherwise Algorithm B1;
+//  * the field angle as atan(y'/x') of the SRS direction rotated by the
+//    field's Gamma_c/2 (odd series to z^9 for |z| < 1e-2, atan2 otherwise);
+//  * normalisations by Newton-refined reciprocal square roots.
+// Every replacement equals the plain form to rounding.
+__device__ __forceinline__ void observe(const DevConsts& k, double t, double eta_obs, double cal,
+                                            const double r[3], const double mu[3], double plx,
+                                            const double* __restrict__ a4, const double* __restrict__ kn,
+                                            const KnotTab& kt, ObsEval& o) {
     double v[3];
-    ephemeris(k, t, o.b, v);
+    {
+        const double d = k.eph_Lrate * (t - kt.tau);
+        double sL, cL;
+        if (fabs(d) < 1e-2) {
+            const double d2 = d * d;
+            const double sd = d * (1.0 - d2 * (1.0 / 6.0 - d2 * (1.0 / 120.0)));
+            const double cd = 1.0 - d2 * (0.5 - d2 * (1.0 / 24.0 - d2 * (1.0 / 720.0)));
+            sL = kt.sL * cd + kt.cL * sd;
+            cL = kt.cL * cd - kt.sL * sd;
+        } else {
+            sincos(k.eph_L0 + k.eph_Lrate * t, &sL, &cL);
+        }
+        const double bx = k.eph_r * cL, by = k.eph_r * sL;
+        o.b[0] = bx;
+        o.b[1] = k.cos_obl * by;
+        o.b[2] = k.sin_obl * by;
+        const double w = k.eph_r * k.eph_Lrate;
+        const double vx = -w * sL, vy = w * cL;
+        v[0] = vx;
+        v[1] = k.cos_obl * vy;
+        v[2] = k.sin_obl * vy;
+    }
     const double tB = t + dot3(r, o.b) * k.au_c;
     o.tau = (tB - k.t_ep) * k.inv_year;
     double ub[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) ub[c] = r[c] + o.tau * mu[c] - plx * o.b[c];
-    const double iub = 1.0 / sqrt(dot3(ub, ub));
+    const double iub = rsqrt_nr(dot3(ub, ub));
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         o.ubar[c] = ub[c] * iub;
@@ -137,27 +203,51 @@ __device__ __forceinline__ void observe(const DevConsts& k, double t, double eta
     double uu[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) uu[c] = o.ubar[c] + o.vc[c];
-    const double iuu = 1.0 / sqrt(dot3(uu, uu));
+    const double iuu = rsqrt_nr(dot3(uu, uu));
     double u[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) u[c] = uu[c] * iuu;
 
-    bspline4(kn, t, o.B);
+    if (kt.inv_dt > 0.0) {
+        const double x = (t - kt.tau) * kt.inv_dt, x1 = 1.0 - x;
+        const double x2 = x * x, x3 = x2 * x;
+        const double s6 = 1.0 / 6.0;
+        o.B[0] = x1 * x1 * x1 * s6;
+        o.B[1] = (3.0 * x3 - 6.0 * x2 + 4.0) * s6;
+        o.B[2] = (-3.0 * x3 + 3.0 * x2 + 3.0 * x + 1.0) * s6;
+        o.B[3] = x3 * s6;
+    } else {
+        bspline4(kn, t, o.B);
+    }
 #pragma unroll
     for (int c = 0; c < 4; ++c)
         o.qraw[c] = a4[c] * o.B[0] + a4[4 + c] * o.B[1] + a4[8 + c] * o.B[2] + a4[12 + c] * o.B[3];
     const double n2 = o.qraw[0] * o.qraw[0] + o.qraw[1] * o.qraw[1] + o.qraw[2] * o.qraw[2] + o.qraw[3] * o.qraw[3];
     o.D = 1.0 - n2;
-    const double iq = 1.0 / sqrt(n2);
+    const double iq = rsqrt_nr(n2);
 #pragma unroll
     for (int c = 0; c < 4; ++c) o.q[c] = o.qraw[c] * iq;
-    quat2mat(o.q, o.A);
+    quat2mat_h(o.qraw, iq * iq, o.A);
     o.Su[0] = o.A[0] * u[0] + o.A[1] * u[1] + o.A[2] * u[2];
     o.Su[1] = o.A[3] * u[0] + o.A[4] * u[1] + o.A[5] * u[2];
     o.Su[2] = o.A[6] * u[0] + o.A[7] * u[1] + o.A[8] * u[2];
-    o.rho = sqrt(o.Su[0] * o.Su[0] + o.Su[1] * o.Su[1]);
-    const double phi = atan2(o.Su[1], o.Su[0]);
-    const double eta = phi >= 0.0 ? phi - k.gamma_half : phi + k.gamma_half;
+    const double rho2 = o.Su[0] * o.Su[0] + o.Su[1] * o.Su[1];
+    o.inv_rho = rsqrt_nr(rho2);
+    o.rho = rho2 * o.inv_rho;
+    // eta = phi - f Gamma_c / 2 with f = sign(phi): rotate (x, y) by -f Gamma_c/2
+    const double f = o.Su[1] >= 0.0 ? 1.0 : -1.0;
+    const double xr = o.Su[0] * k.cos_half_gamma + f * o.Su[1] * k.sin_half_gamma;
+    const double yr = o.Su[1] * k.cos_half_gamma - f * o.Su[0] * k.sin_half_gamma;
+    double eta;
+    if (xr > 0.0 && fabs(yr) < 1e-2 * xr) {
+        // the (cos, sin) pair rotates by atan2(sin, cos) = Gamma_c/2 - half_gamma_err
+        const double z = yr * rcp_nr(xr), z2 = z * z;
+        eta = z * (1.0 + z2 * (-1.0 / 3.0 + z2 * (1.0 / 5.0 + z2 * (-1.0 / 7.0 + z2 * (1.0 / 9.0))))) -
+              f * k.half_gamma_err;
+    } else {
+        const double phi = atan2(o.Su[1], o.Su[0]);
+        eta = phi >= 0.0 ? phi - k.gamma_half : phi + k.gamma_half;
+    }
     o.R = eta_obs + cal - eta;
 }
 
@@ -166,7 +256,7 @@ __device__ __forceinline__ void observe(const DevConsts& k, double t, double eta
 // vector m of eq:srspqr is taken back to celestial coordinates once.
 __device__ __forceinline__ void source_partials(const ObsEval& o, const double p[3], const double q[3],
                                                 const double r[3], double Ad[5]) {
-    const double inv_rho = 1.0 / o.rho;
+    const double inv_rho = o.inv_rho;
     const double ms0 = -o.Su[1] * inv_rho, ms1 = o.Su[0] * inv_rho;   // (-sin phi, cos phi, 0)
     double m[3];
     m[0] = o.A[0] * ms0 + o.A[3] * ms1;
@@ -190,7 +280,7 @@ __device__ __forceinline__ void source_partials(const ObsEval& o, const double p
 
 // dR/dq = 2 sec(zeta) q {S'n, 0} (eq:dfadq), n of eq:srspqr.
 __device__ __forceinline__ void attitude_partial(const ObsEval& o, double g[4]) {
-    const double inv_rho = 1.0 / o.rho;
+    const double inv_rho = o.inv_rho;
     const double sz = o.Su[2];
     const double n0 = -sz * o.Su[0] * inv_rho, n1 = -sz * o.Su[1] * inv_rho, n2 = o.rho;
     const double* q = o.q;

@@ -1,14 +1,17 @@
 """Parity of the HIP library (through its C ABI) with the CPU oracle.
 
 Same seeded inputs on both sides; the observed field angles come from the
-oracle's observation model at the true parameters.  Tolerance: 1e-3 uas per
-parameter in FP64 (attitude compared as rotations, eq:diffrot2-3, since the
-coefficients' scale is unobservable).  Sources whose 5x5 system is singular
+oracle's observation model at the true parameters.  Updated parameters are
+compared with the oracle built in extended precision: each within
+max(1e-3 uas, its FP64 rounding floor), and per component no less accurate
+than the FP64 oracle itself (attitude compared as rotations,
+eq:diffrot2-3, since the coefficients' scale is unobservable).  Sources whose 5x5 system is singular
 (too few observations) are compared through their defect flag only, because
 "any valid solution" is acceptable there (Appendix C.3).
 """
 import numpy as np
 import pytest
+from scipy.ndimage import maximum_filter1d
 
 import synth
 import synth.configs as C
@@ -49,36 +52,68 @@ def src_diff_uas(s_ref, s):
     return ds / UAS
 
 
-def floor_tolerance(oracle_lib, world, eta, run, n_draws=3, ulp_noise=3e-16, factor=8.0):
-    """Per-parameter tolerance: max(1e-3 uas, factor x the oracle's own
-    response to a ~3-ulp perturbation of every residual).
+def fp64_floor(oracle_lib, world, eta, run, n_draws=3, ulp_noise=3e-16, factor=8.0, factor_ref=4.0):
+    """Reference result X, FP64 oracle result O and per-parameter tolerances.
 
-    Two correct FP64 implementations of the observation model differ in R by
-    a few ulp of the field angle (~3e-16 rad); where a parameter amplifies
-    that (few observations, the weakly determined across-scan attitude axes),
-    the FP64 floor exceeds 1e-3 uas.  run(problem) -> (s, a, c)."""
-    base = run(oracle_lib.problem_from_world(world, eta, state="start"))
-    sens_s = np.zeros_like(base[0])
-    sens_a = np.zeros((base[1].shape[0], 3))
-    sens_c = np.zeros_like(base[2])
+    X is the oracle built in x87 extended precision (64-bit significand): the
+    exact answer to ~1e-19 relative.  An FP64 implementation cannot do better
+    than the FP64 rounding floor of each parameter, estimated two ways: the
+    FP64 oracle's own deviation |O - X|, and the oracle's response to a
+    3e-16 rad (a few ulp of the field angle) perturbation of every residual,
+    the largest over n_draws draws.  Where a parameter amplifies rounding
+    (few observations, the weakly determined across-scan attitude axes) that
+    floor exceeds 1e-3 uas; for attitude coefficients |O - X| is taken as
+    its largest value over the neighbouring coefficients.
+    run(problem) -> (s, a, c)."""
+    X = [np.asarray(v, np.float64) for v in run(oracle_lib.problem_from_world(world, eta, "start", "extended"))]
+    O = run(oracle_lib.problem_from_world(world, eta, state="start"))
+    sens = [np.zeros_like(src_diff_uas(O[0], O[0])), np.zeros((O[1].shape[0], 3)), np.zeros_like(O[2])]
     for k in range(n_draws):
         rng = np.random.default_rng(100 + k)
         out = run(oracle_lib.problem_from_world(world, eta + rng.normal(0, ulp_noise, eta.shape), state="start"))
-        sens_s = np.maximum(sens_s, np.abs(src_diff_uas(base[0], out[0])))
-        sens_a = np.maximum(sens_a, np.abs(rot_diff_uas(base[1], out[1])))
-        sens_c = np.maximum(sens_c, np.abs(out[2] - base[2]) / UAS)
-    tol = (np.maximum(TOL_UAS, factor * sens_s), np.maximum(TOL_UAS, factor * sens_a),
-           np.maximum(TOL_UAS, factor * sens_c))
-    return base, tol
+        for i, f in enumerate(DIFFS):
+            sens[i] = np.maximum(sens[i], np.abs(f(O[i], out[i])))
+    ref = [np.abs(f(X[i], O[i])) for i, f in enumerate(DIFFS)]
+    # the floor of an attitude coefficient is set by the conditioning of the
+    # local band system, which varies slowly along the mission: take the
+    # largest FP64 deviation among the 16 coefficients on either side
+    ref[1] = maximum_filter1d(ref[1], size=33, axis=0, mode="nearest")
+    tol = [np.maximum(TOL_UAS, np.maximum(factor * sens[i], factor_ref * ref[i])) for i in range(3)]
+    return X, O, tol
+
+
+def cal_diff_uas(c_ref, c):
+    return (c - c_ref) / UAS
+
+
+DIFFS = (src_diff_uas, rot_diff_uas, cal_diff_uas)
+
+
+def check_floor(name, X, O, G, tol, which, mask=None, rms_factor=2.0):
+    """GPU result G against the extended-precision reference X: every
+    parameter within its FP64-floor tolerance, and per component an RMS error
+    no larger than rms_factor x that of the FP64 oracle O."""
+    f = DIFFS[which]
+    dg, do = f(X, G), f(X, O)
+    if mask is not None:
+        dg, do, tol = dg[mask], do[mask], tol[mask]
+    report(f"{name} (GPU - ext)", dg, tol)
+    report(f"{name} (FP64 oracle - ext)", do, tol)
+    assert np.all(np.abs(dg) <= tol)
+    rms_g = np.sqrt(np.mean(dg * dg, axis=0))
+    rms_o = np.sqrt(np.mean(do * do, axis=0))
+    assert np.all(rms_g <= rms_factor * rms_o + 1e-5), (rms_g, rms_o)
+    return dg
 
 
 def report(name, diff, tol):
     within = float(np.mean(np.abs(diff) <= TOL_UAS))
     ratio = np.abs(diff) / tol
     worst = np.unravel_index(np.argmax(ratio), ratio.shape)
-    print(f"{name}: max {np.abs(diff).max():.2e} uas, {100 * within:.2f}% within 1e-3 uas, "
-          f"worst diff/tol {ratio.max():.2f} at {tuple(int(x) for x in worst)} "
-          f"(diff {np.abs(diff)[worst]:.2e}, tol {tol[worst]:.2e})")
+    rms = np.sqrt(np.mean(diff * diff, axis=0))
+    print(f"{name}: max {np.abs(diff).max():.2e} uas, rms {np.array2string(np.atleast_1d(rms), precision=2)}, "
+          f"{100 * within:.2f}% within 1e-3 uas, worst diff/tol {ratio.max():.2f} at "
+          f"{tuple(int(x) for x in worst)} (diff {np.abs(diff)[worst]:.2e}, tol {tol[worst]:.2e})")
 
 
 class Pair:
@@ -131,7 +166,12 @@ def test_residuals_match(agis_mod, small, oracle_lib):
     p = Pair(agis_mod, oracle_lib, w, eta)
     Rg = agis_mod.agis_residuals(p.ctx)
     Ro = p.pr.observe()["R"]
-    assert np.abs(Rg - Ro).max() / UAS < TOL_UAS
+    d = Rg - Ro
+    print(f"residuals: max |diff| {np.abs(d).max():.2e} rad, rms {np.sqrt(np.mean(d * d)):.2e} rad")
+    assert np.abs(d).max() / UAS < TOL_UAS
+    # the premise of fp64_floor: the two models differ by rounding only,
+    # well inside the 3e-16 rad noise it propagates through the oracle
+    assert np.sqrt(np.mean(d * d)) < 1.5e-16
     p.close()
 
 
@@ -149,16 +189,15 @@ def test_source_update_parity(agis_mod, oracle_lib, world, request):
         run.defect = de
         return pr.s.copy(), pr.a.copy(), pr.c.copy()
 
-    (s_o, _, _), (tol_s, _, _) = floor_tolerance(oracle_lib, w, eta, run)
+    X, O, tol = fp64_floor(oracle_lib, w, eta, run)
+    run(oracle_lib.problem_from_world(w, eta, state="start"))
+    good = run.defect == 0          # singular sources: any valid solution (App. C.3)
     p = Pair(agis_mod, oracle_lib, w, eta)
     st = agis_mod.agis_source_update(p.ctx)
-    s_g, _, _ = p.gpu_state()
-    good = run.defect == 0              # singular sources: any valid solution (App. C.3)
+    G = p.gpu_state()
     assert good.mean() > 0.95
-    diff = src_diff_uas(s_o, s_g)
-    report(f"S update [{world}]", diff[good], tol_s[good])
-    assert np.all(np.abs(diff[good]) <= tol_s[good])
-    assert np.mean(np.abs(diff[good]) <= TOL_UAS) > 0.95
+    dg = check_floor(f"S update [{world}]", X[0], O[0], G[0], tol[0], 0, mask=good)
+    assert np.mean(np.abs(dg) <= TOL_UAS) > 0.95
     assert st["n_units"] == w.src_true.shape[0]
     p.close()
 
@@ -172,21 +211,17 @@ def test_attitude_calibration_update_parity(agis_mod, oracle_lib, world, request
         pr.iterate_sac()
         return pr.s.copy(), pr.a.copy(), pr.c.copy()
 
-    (s_o, a_o, c_o), (tol_s, tol_a, tol_c) = floor_tolerance(oracle_lib, w, eta, run)
+    X, O, tol = fp64_floor(oracle_lib, w, eta, run)
     p = Pair(agis_mod, oracle_lib, w, eta)
     agis_mod.agis_source_update(p.ctx)
     st_a, st_c = agis_mod.agis_attitude_calibration_update(p.ctx)
-    s_g, a_g, c_g = p.gpu_state()
-    rd = rot_diff_uas(a_o, a_g)
-    report("A update rotation", rd, tol_a)
-    assert np.all(np.abs(rd) <= tol_a)
+    G = p.gpu_state()
+    rd = check_floor("A update rotation", X[1], O[1], G[1], tol[1], 1)
     assert np.mean(np.abs(rd[:, 2]) <= TOL_UAS) > 0.99        # along-scan axis
-    scale = np.abs(np.linalg.norm(a_g, axis=1) / np.linalg.norm(a_o, axis=1) - 1)
+    scale = np.abs(np.linalg.norm(G[1], axis=1) / np.linalg.norm(O[1], axis=1) - 1)
     assert scale.max() < 1e-10
-    dc = (c_g - c_o) / UAS
-    report("C update", dc, tol_c)
-    assert np.all(np.abs(dc) <= tol_c)
-    assert np.all(np.abs(c_g[0::2] + c_g[1::2]) < 1e-18)
+    check_floor("C update", X[2], O[2], G[2], tol[2], 2)
+    assert np.all(np.abs(G[2][0::2] + G[2][1::2]) < 1e-18)
     p.close()
 
 
@@ -215,20 +250,14 @@ def test_iterations_with_frame_rotator_parity(agis_mod, tiny, oracle_lib):
             pr.iterate(s_ref=w.src_true)
         return pr.s.copy(), pr.a.copy(), pr.c.copy()
 
-    (s_o, a_o, c_o), (tol_s, tol_a, tol_c) = floor_tolerance(oracle_lib, w, eta, run)
+    X, O, tol = fp64_floor(oracle_lib, w, eta, run)
     p = Pair(agis_mod, oracle_lib, w, eta)
     agis_mod.agis_set_frame_reference(p.ctx, w.src_true)
     stats = agis_mod.agis_iterate(p.ctx, n_it)
-    s_g, a_g, c_g = p.gpu_state()
-    ds = src_diff_uas(s_o, s_g)
-    rd = rot_diff_uas(a_o, a_g)
-    dc = (c_g - c_o) / UAS
-    report("3 iterations: sources", ds, tol_s)
-    report("3 iterations: attitude", rd, tol_a)
-    report("3 iterations: calibration", dc, tol_c)
-    assert np.all(np.abs(ds) <= tol_s)
-    assert np.all(np.abs(rd) <= tol_a)
-    assert np.all(np.abs(dc) <= tol_c)
+    G = p.gpu_state()
+    check_floor("3 iterations: sources", X[0], O[0], G[0], tol[0], 0)
+    check_floor("3 iterations: attitude", X[1], O[1], G[1], tol[1], 1)
+    check_floor("3 iterations: calibration", X[2], O[2], G[2], tol[2], 2)
     assert len(stats) == n_it and all(np.isfinite(x["ms"]) for x in stats)
     p.close()
 
@@ -261,19 +290,17 @@ def test_data_gap_natural_break(agis_mod, oracle_lib):
         pr.iterate_sac()
         return pr.s.copy(), pr.a.copy(), pr.c.copy()
 
-    (s_o, a_o, c_o), (tol_s, tol_a, tol_c) = floor_tolerance(oracle_lib, w, eta, run)
+    X, O, tol = fp64_floor(oracle_lib, w, eta, run)
     p = Pair(agis_mod, oracle_lib, w, eta)
     agis_mod.agis_source_update(p.ctx)
     st_a, st_c = agis_mod.agis_attitude_calibration_update(p.ctx)
     assert st_a["defect"] > 0
-    _, a_g, _ = p.gpu_state()
-    assert np.all(np.isfinite(a_g))
+    G = p.gpu_state()
+    assert np.all(np.isfinite(G[1]))
     # coefficients whose support lies entirely inside the gap get no update
     inside = np.arange(500 + 3, 512 - 3)
-    np.testing.assert_array_equal(a_g[inside], w.att_start[inside])
-    rd = rot_diff_uas(a_o, a_g)
-    report("A update with a data gap", rd, tol_a)
-    assert np.all(np.abs(rd) <= tol_a)
+    np.testing.assert_array_equal(G[1][inside], w.att_start[inside])
+    check_floor("A update with a data gap", X[1], O[1], G[1], tol[1], 1)
     p.close()
 
 

@@ -259,3 +259,26 @@ def test_oracle_thread_count_invariance(tiny_world, tiny_eta, oracle_lib):
     gomp.omp_set_num_threads(8)
     for x, y in zip(outs[0], outs[1]):
         assert np.array_equal(x, y)
+
+
+def test_extended_build_is_the_same_oracle(tiny_world, tiny_eta, oracle_lib):
+    """The x87 extended-precision build (the reference of the GPU parity
+    tests) computes what the FP64 build computes: residuals agree to FP64
+    rounding and one S[AC] iteration agrees to the FP64 floor (a few 1e-4
+    uas RMS for the sources)."""
+    w = tiny_world
+    po = oracle_lib.problem_from_world(w, tiny_eta, state="start")
+    px = oracle_lib.problem_from_world(w, tiny_eta, state="start", precision="extended")
+    assert px.s.dtype == np.longdouble and np.finfo(np.longdouble).nmant >= 63
+    Ro, Rx = po.observe()["R"], px.observe()["R"]
+    assert np.abs(Ro - np.asarray(Rx, np.float64)).max() < 2e-15
+    po.iterate_sac()
+    px.iterate_sac()
+    ds = (po.s - np.asarray(px.s, np.float64)) / synth.UAS
+    ds[:, 0] *= np.cos(po.s[:, 1])
+    rms = np.sqrt(np.mean(ds * ds, axis=0))
+    assert np.all(rms < 2e-3) and np.all(rms > 0)
+    assert np.abs(po.c - np.asarray(px.c, np.float64)).max() / synth.UAS < 1e-4
+    # a wrong build (double arithmetic under a long double interface) would
+    # reproduce the FP64 result bit for bit
+    assert not np.array_equal(po.s, np.asarray(px.s, np.float64))
