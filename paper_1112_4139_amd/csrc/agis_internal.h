@@ -98,9 +98,8 @@ struct agis_ctx {
     double* eo = nullptr;                // [8] frame rotator parameters on device
     double* stat = nullptr;              // statistics scratch
 
-    // lanes per source (S block) and per knot interval (A/C pass)
+    // lanes per source in the S block
     int s_group = 16;
-    int ac_group = 8;
 
     agis::Timers tm;
     double last_ms[5] = {0, 0, 0, 0, 0};

@@ -258,7 +258,6 @@ extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
                                 std::atan2((long double)k.sin_half_gamma, (long double)k.cos_half_gamma));
     build_segments(ctx);
     if (const char* e = std::getenv("AGIS_S_GROUP")) ctx->s_group = std::atoi(e);
-    if (const char* e = std::getenv("AGIS_AC_GROUP")) ctx->ac_group = std::atoi(e);
     int rc = AGIS_OK;
     auto fail = [&](int code) {
         g_create_error = ctx->err;

@@ -7,12 +7,12 @@
 //                       over the G lanes reduces them; one lane per source
 //                       runs Algorithms C1-C3 on the 5x5 system and applies
 //                       the update.
-//   k_ac_pass<G>        A/C accumulation (Sect. 5.2.1, 5.2.4, 5.3).  G lanes per
-//                       knot interval stream the time-ordered store at
-//                       (s^(k+1), a^(k), c^(k)); per interval they produce the
-//                       10 block pairs x 10 unique entries of eq:normAmod, its
-//                       16 right-hand-side entries and the per-fov calibration
-//                       sums of eq:normC.
+//   k_ac_pass           A/C accumulation (Sect. 5.2.1, 5.2.4, 5.3).  One
+//                       wavefront per knot interval streams the time-ordered
+//                       store at (s^(k+1), a^(k), c^(k)) and sums, on the FP64
+//                       matrix cores, the 10 block pairs x 10 unique entries
+//                       of eq:normAmod, its 16 right-hand-side entries and the
+//                       per-fov calibration sums of eq:normC.
 //   k_band_solve        A solve (Sect. 5.2.2, App. C): one 16-lane row of a
 //                       wavefront per segment; right-looking modified band
 //                       Cholesky (Algorithm C1 with C2 folded in) over a
@@ -187,159 +187,127 @@ __global__ __launch_bounds__(256) void k_source_update(DevConsts k, int64_t n_sr
 }
 
 // ------------------------------------------------------------- A/C pass
-// Value of v in the other lane of the pair (lanes 2i, 2i+1): DPP quad_perm
-// [1, 0, 3, 2] on both 32-bit halves.
-__device__ __forceinline__ double pair_swap(double v) {
-    const uint64_t b = __builtin_bit_cast(uint64_t, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0xB1, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0xB1, 0xF, 0xF, false);
-    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
+typedef double double4_t __attribute__((ext_vector_type(4)));
 
-// Sum over the G/2 lanes of a group that share the parity of this lane.
-template <int G>
-__device__ __forceinline__ double parity_sum(double v) {
-#pragma unroll
-    for (int m = G / 2; m >= 2; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
-}
+constexpr int AC_WAVES = 2;             // wavefronts per block, one knot interval each
+constexpr int AC_XS = 33;               // LDS row stride (doubles) of the transposition buffer
 
-// What one observation adds to the sums of its knot interval: the 10 unique
-// entries of W (g g' + 4 lambda^2 q q') (eq:normAmod), the 4 entries of
-// -W (g R - 2 lambda^2 q D), the four B-splines, W and W R, and the field.
-struct AcTerm {
-    double M[10], rv[4], B[4], W, WR;
-    int f;
-};
-
-// Add one observation's term to this lane's half of the interval sums.
-// Lane parity p = 0 holds block pairs (n,m) = (0,0) (0,1) (0,2) (0,3) (1,1),
-// right-hand sides n = 0, 1 and the fov +1 calibration sums; p = 1 holds
-// (1,2) (1,3) (2,2) (2,3) (3,3), n = 2, 3 and fov -1.
-__device__ __forceinline__ void ac_accumulate(const AcTerm& x, int p, double* __restrict__ accP,
-                                              double* __restrict__ accR, double* __restrict__ accC) {
-    const double s1 = p ? x.B[1] : x.B[0];
-    const double s2 = p ? x.B[2] : x.B[0];
-    const double s3 = p ? x.B[3] : x.B[1];
-    const double bb[5] = {s1 * s2, s1 * s3, s2 * x.B[2], s2 * x.B[3], s3 * s3};
-#pragma unroll
-    for (int kk = 0; kk < 5; ++kk)
-#pragma unroll
-        for (int e = 0; e < 10; ++e) accP[kk * 10 + e] += bb[kk] * x.M[e];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        accR[r] += s2 * x.rv[r];
-        accR[4 + r] += s3 * x.rv[r];
-    }
-    const bool mine = x.f == p;
-    accC[0] += mine ? x.W : 0.0;
-    accC[1] += mine ? x.WR : 0.0;
-}
-
-template <int G>
-__global__ __launch_bounds__(256) void k_ac_pass(DevConsts k, int64_t K, const int64_t* __restrict__ iv_off,
-                                                 const double* __restrict__ ot, const double* __restrict__ oeta,
-                                                 const float* __restrict__ osig,
-                                                 const int32_t* __restrict__ ocellfov,
-                                                 const int32_t* __restrict__ osrc, const SrcPrep* __restrict__ prep,
-                                                 const double* __restrict__ knots,
-                                                 const KnotTab* __restrict__ ktab, const double* __restrict__ a,
-                                                 const double* __restrict__ c, double* __restrict__ iv_sums,
-                                                 double* __restrict__ iv_cal) {
-    static_assert(G >= 2 && (G & (G - 1)) == 0, "G must be an even power of two");
-    constexpr int GPB = 256 / G;
-    __shared__ double sh_a[GPB][16];
-    __shared__ double sh_k[GPB][6];
-    const int gl = threadIdx.x % G;
-    const int gi = threadIdx.x / G;
-    const int p = gl & 1;
-    const int64_t j = (int64_t)blockIdx.x * GPB + gi;
+// A/C accumulation as a matrix product on the FP64 matrix cores.  Every
+// observation of knot interval j gives two 16-vectors
+//   a = (B_n B_m for the 10 pairs n <= m, B_0..B_3, [fov +1], [fov -1])
+//   b = (10 unique entries of W (g g' + 4 lambda^2 q q'),
+//        -W (g R - 2 lambda^2 q D) (4), W, W R)
+// and the interval's sums are blocks of C = sum over observations of a b'
+// (16 x 16): pairs x entries (eq:normAmod), B_n x right-hand side, and
+// fov x (W, W R) for eq:normC.  One wavefront takes 64 observations at a
+// time (one per lane), writes (a, b) to LDS and feeds them to 16
+// v_mfma_f64_16x16x4 steps, four observations each.
+__global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t K, const int64_t* __restrict__ iv_off,
+                                                           const double* __restrict__ ot,
+                                                           const double* __restrict__ oeta,
+                                                           const float* __restrict__ osig,
+                                                           const int32_t* __restrict__ ocellfov,
+                                                           const int32_t* __restrict__ osrc,
+                                                           const SrcPrep* __restrict__ prep,
+                                                           const double* __restrict__ knots,
+                                                           const KnotTab* __restrict__ ktab,
+                                                           const double* __restrict__ a,
+                                                           const double* __restrict__ c,
+                                                           double* __restrict__ iv_sums,
+                                                           double* __restrict__ iv_cal) {
+    __shared__ double xb[AC_WAVES][64][AC_XS];
+    __shared__ double sh_a[AC_WAVES][16];
+    __shared__ double sh_k[AC_WAVES][6];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.x * AC_WAVES + wv;
     const bool valid = j < K;
-    for (int e = gl; e < 22; e += G) {
+    if (lane < 22) {
         double v = 0.0;
-        if (valid) v = e < 16 ? a[4 * j + e] : knots[j + 1 + (e - 16)];
-        if (e < 16) sh_a[gi][e] = v;
-        else sh_k[gi][e - 16] = v;
+        if (valid) v = lane < 16 ? a[4 * j + lane] : knots[j + 1 + (lane - 16)];
+        if (lane < 16) sh_a[wv][lane] = v;
+        else sh_k[wv][lane - 16] = v;
     }
     __syncthreads();
-    double accP[50], accR[8], accC[2];
-#pragma unroll
-    for (int e = 0; e < 50; ++e) accP[e] = 0.0;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) accR[e] = 0.0;
-    accC[0] = accC[1] = 0.0;
     const double lam2 = k.lam2;
     const int64_t l0 = valid ? iv_off[j] : 0, l1 = valid ? iv_off[j + 1] : 0;
     const KnotTab kt = valid ? ktab[j] : KnotTab{0.0, 1.0, 0.0, 0.0};
-    // The two lanes of a pair take observations base + {0, 1}, base advancing
-    // by G; both run the same iterations.  A lane past the end evaluates the
-    // interval's last observation again with weight zero.
-    int64_t base = l0 + (gl & ~1);
+    double (*xw)[AC_XS] = xb[wv];
+    const int ri = lane & 15, rk = lane >> 4;
+    double4_t C = {0.0, 0.0, 0.0, 0.0};
+    // lanes past the end evaluate the interval's last observation again with
+    // weight zero
+    int64_t base = l0;
     double t_c = 0.0, e_c = 0.0;
     float s_c = 1.0f;
     int32_t cf_c = 0;
     bool h_c = false;
     SrcPrep sp_c = {};
     if (base < l1) {
-        h_c = base + p < l1;
-        const int64_t le = h_c ? base + p : l1 - 1;
+        h_c = base + lane < l1;
+        const int64_t le = h_c ? base + lane : l1 - 1;
         t_c = ot[le];
         e_c = oeta[le];
         s_c = osig[le];
         cf_c = ocellfov[le];
         sp_c = prep[osrc[le]];
     }
-    for (; base < l1; base += G) {
-        const int64_t bn = base + G;
+    for (; base < l1; base += 64) {
+        const int64_t bn = base + 64;
         double t_n = 0.0, e_n = 0.0;
         float s_n = 1.0f;
         int32_t cf_n = 0, src_n = 0;
         bool h_n = false;
         if (bn < l1) {
-            h_n = bn + p < l1;
-            const int64_t le = h_n ? bn + p : l1 - 1;
+            h_n = bn + lane < l1;
+            const int64_t le = h_n ? bn + lane : l1 - 1;
             t_n = ot[le];
             e_n = oeta[le];
             s_n = osig[le];
             cf_n = ocellfov[le];
             src_n = osrc[le];
         }
-        AcTerm own, oth;
         {
             ObsEval o;
-            observe(k, t_c, e_c, c[cf_c >> 1], sp_c.r, sp_c.mu, sp_c.plx, sh_a[gi], sh_k[gi], kt, o);
+            observe(k, t_c, e_c, c[cf_c >> 1], sp_c.r, sp_c.mu, sp_c.plx, sh_a[wv], sh_k[wv], kt, o);
             double g[4];
             attitude_partial(o, g);
             const double sg = (double)s_c;
-            const double W = h_c ? 1.0 / (sg * sg) : 0.0;
+            const double W = h_c ? rcp_nr(sg * sg) : 0.0;
+            double* row = xw[lane];
             int e = 0;
+#pragma unroll
+            for (int n = 0; n < 4; ++n)
+#pragma unroll
+                for (int m = n; m < 4; ++m) row[e++] = o.B[n] * o.B[m];
+#pragma unroll
+            for (int n = 0; n < 4; ++n) row[10 + n] = o.B[n];
+            const int f = cf_c & 1;
+            row[14] = f == 0 ? 1.0 : 0.0;
+            row[15] = f == 1 ? 1.0 : 0.0;
+            e = 0;
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
                 for (int cc = rr; cc < 4; ++cc)
-                    own.M[e++] = W * (g[rr] * g[cc] + 4.0 * lam2 * o.qraw[rr] * o.qraw[cc]);
+                    row[16 + e++] = W * (g[rr] * g[cc] + 4.0 * lam2 * o.qraw[rr] * o.qraw[cc]);
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) own.rv[rr] = -W * (g[rr] * o.R - 2.0 * lam2 * o.qraw[rr] * o.D);
-#pragma unroll
-            for (int n = 0; n < 4; ++n) own.B[n] = o.B[n];
-            own.W = W;
-            own.WR = W * o.R;
-            own.f = cf_c & 1;
+            for (int rr = 0; rr < 4; ++rr) row[26 + rr] = -W * (g[rr] * o.R - 2.0 * lam2 * o.qraw[rr] * o.D);
+            row[30] = W;
+            row[31] = W * o.R;
         }
         SrcPrep sp_n = {};
         if (bn < l1) sp_n = prep[src_n];
+        // the wavefront's LDS operations complete in order: the rows just
+        // written are read back below by other lanes of the same wavefront
+        __asm__ volatile("" ::: "memory");
 #pragma unroll
-        for (int e = 0; e < 10; ++e) oth.M[e] = pair_swap(own.M[e]);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            oth.rv[e] = pair_swap(own.rv[e]);
-            oth.B[e] = pair_swap(own.B[e]);
+        for (int kk = 0; kk < 16; ++kk) {
+            const double av = xw[4 * kk + rk][ri];
+            const double bv = xw[4 * kk + rk][16 + ri];
+            C = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, C, 0, 0, 0);
         }
-        oth.W = pair_swap(own.W);
-        oth.WR = pair_swap(own.WR);
-        oth.f = __builtin_amdgcn_update_dpp(0, own.f, 0xB1, 0xF, 0xF, false);
-        ac_accumulate(own, p, accP, accR, accC);
-        ac_accumulate(oth, p, accP, accR, accC);
+        __asm__ volatile("" ::: "memory");
         t_c = t_n;
         e_c = e_n;
         s_c = s_n;
@@ -347,24 +315,15 @@ __global__ __launch_bounds__(256) void k_ac_pass(DevConsts k, int64_t K, const i
         h_c = h_n;
         sp_c = sp_n;
     }
-    // Lane gl holds, after the reduction, the totals of its parity's half;
-    // the G/2 lanes of one parity share the stores.
-    const int slot = gl >> 1;
+    if (!valid) return;
+    // lane l holds C[4 v + l / 16][l % 16], v = 0..3
     double* out = iv_sums + j * IV_SUMS;
 #pragma unroll
-    for (int e = 0; e < 50; ++e) {
-        const double v = parity_sum<G>(accP[e]);
-        if (valid && slot == e % (G / 2)) out[50 * p + e] = v;
-    }
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const double v = parity_sum<G>(accR[e]);
-        if (valid && slot == (50 + e) % (G / 2)) out[100 + 8 * p + e] = v;
-    }
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        const double v = parity_sum<G>(accC[e]);
-        if (valid && slot == (58 + e) % (G / 2)) iv_cal[j * IV_CAL + 2 * p + e] = v;
+    for (int v = 0; v < 4; ++v) {
+        const int i = 4 * v + rk, jj = ri;
+        if (i < 10 && jj < 10) out[i * 10 + jj] = C[v];
+        else if (i >= 10 && i < 14 && jj >= 10 && jj < 14) out[100 + (i - 10) * 4 + (jj - 10)] = C[v];
+        else if (i >= 14 && jj >= 14) iv_cal[j * IV_CAL + (i - 14) * 2 + (jj - 14)] = C[v];
     }
 }
 
@@ -473,6 +432,9 @@ __global__ __launch_bounds__(64) void k_band_solve(int64_t nseg, const SegDesc* 
 #pragma unroll
     for (int c = 0; c < 16; ++c) W[c] = (c + d < nu) ? ring_entry(ring, nb, c, c + d) : 0.0;
     double R = d < nu ? ring_rhs(ring, nb, d) : 0.0;
+    // row i + 16 (entering after step i) is read from the ring one step early
+    double nW = (16 + d < nu) ? ring_entry(ring, nb, 16, 16 + d) : 0.0;
+    double nR = (d == 15 && 16 < nu) ? ring_rhs(ring, nb, 16) : 0.0;
     int defect = 0;
     for (int64_t i = 0; i < nu_max; ++i) {
         const bool act = i < nu;
@@ -489,6 +451,13 @@ __global__ __launch_bounds__(64) void k_band_solve(int64_t nseg, const SegDesc* 
         const double inv = ok ? rsqrt_nr(piv) : 0.0;
         const double Ud = d == 0 ? piv * inv : W[0] * inv;
         const double y = row_dpp<0x150>(R) * inv;
+        band_trailing<1>(W, Ud);
+        R -= Ud * y;
+        R = row_dpp<0x101>(R);
+        if (d == 15) R = nR;
+#pragma unroll
+        for (int c = 0; c < 15; ++c) W[c] = W[c + 1];
+        W[15] = nW;
         if (act) {
             U[i * 16 + d] = Ud;
             if (d == 0) {
@@ -496,17 +465,13 @@ __global__ __launch_bounds__(64) void k_band_solve(int64_t nseg, const SegDesc* 
                 defect += ok ? 0 : 1;
             }
         }
-        band_trailing<1>(W, Ud);
-        R -= Ud * y;
-        R = row_dpp<0x101>(R);
-#pragma unroll
-        for (int c = 0; c < 15; ++c) W[c] = W[c + 1];
-        const int64_t r = i + 16;
-        W[15] = (r + d < nu) ? ring_entry(ring, nb, r, r + d) : 0.0;
-        if (d == 15) R = r < nu ? ring_rhs(ring, nb, r) : 0.0;
-        if ((i & 3) == 3) {
-            // block b done: interval b + 5 enters the ring in the slot of
-            // interval b - 3, which no later row refers to
+        const int64_t r = i + 17;
+        nW = (r + d < nu) ? ring_entry(ring, nb, r, r + d) : 0.0;
+        nR = (d == 15 && r < nu) ? ring_rhs(ring, nb, r) : 0.0;
+        if ((i & 3) == 2) {
+            // interval b + 5 (first read for row 4b + 20, at step 4b + 3)
+            // enters the ring in the slot of interval b - 3, which no row
+            // after 4b + 3 refers to
             if (b + 5 < n_iv) {
 #pragma unroll
                 for (int u = 0; u < PFL; ++u) {
@@ -520,28 +485,47 @@ __global__ __launch_bounds__(64) void k_band_solve(int64_t nseg, const SegDesc* 
         }
     }
     __syncthreads();   // factor rows and forward-substituted y visible to all lanes
-    // Algorithm C3 from the last row up: lane d holds x(i+d), d >= 1
+    // Algorithm C3 from the last row up: lane d holds x(i+d), d >= 1.  Rows
+    // are read 16 at a time, one chunk ahead of their use.
     double x = 0.0;
-    for (int64_t t = 0; t < nu_max; ++t) {
-        const int64_t i = nu - 1 - t;
-        const bool act = i >= 0;
-        double Uid = 0.0, uii = 0.0, yi = 0.0;
-        if (act) {
-            Uid = U[i * 16 + d];
-            uii = U[i * 16];
-            yi = Y[i];
+    double cU[16], cu[16], cy[16];
+    auto load_rows = [&](int64_t t0, double* lU, double* lu, double* ly) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int64_t i = nu - 1 - (t0 + k);
+            lU[k] = lu[k] = ly[k] = 0.0;
+            if (i >= 0) {
+                lU[k] = U[i * 16 + d];
+                lu[k] = U[i * 16];
+                ly[k] = Y[i];
+            }
         }
-        double p = d >= 1 ? Uid * x : 0.0;
-        p += row_dpp<0x128>(p);
-        p += row_dpp<0x124>(p);
-        p += row_dpp<0x122>(p);
-        p += row_dpp<0x121>(p);
-        const double xi = uii > 0.0 ? (yi - p) * rcp_nr(uii) : 0.0;
-        if (act && d == 0) {
-            const int64_t n = sd.n_lo + (i >> 2);
-            if (n >= sd.keep_lo && n <= sd.keep_hi) da[4 * n + (i & 3)] = xi;
+    };
+    load_rows(0, cU, cu, cy);
+    for (int64_t t0 = 0; t0 < nu_max; t0 += 16) {
+        double nU[16], nu_[16], ny[16];
+        load_rows(t0 + 16, nU, nu_, ny);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int64_t i = nu - 1 - (t0 + k);
+            double p = d >= 1 ? cU[k] * x : 0.0;
+            p += row_dpp<0x128>(p);
+            p += row_dpp<0x124>(p);
+            p += row_dpp<0x122>(p);
+            p += row_dpp<0x121>(p);
+            const double xi = cu[k] > 0.0 ? (cy[k] - p) * rcp_nr(cu[k]) : 0.0;
+            if (i >= 0 && d == 0) {
+                const int64_t n = sd.n_lo + (i >> 2);
+                if (n >= sd.keep_lo && n <= sd.keep_hi) da[4 * n + (i & 3)] = xi;
+            }
+            x = row_dpp<0x111>(d == 0 ? xi : x);
         }
-        x = row_dpp<0x111>(d == 0 ? xi : x);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            cU[k] = nU[k];
+            cu[k] = nu_[k];
+            cy[k] = ny[k];
+        }
     }
     if (valid && d == 0) seg_def[sgi] = defect;
 }
@@ -567,21 +551,11 @@ void launch_source_update(agis_ctx* ctx) {
     }
 }
 
-#define AGIS_AC_LAUNCH(G)                                                                                     \
-    k_ac_pass<G><<<groups_grid(ctx->K, 256 / G), 256, 0, ctx->stream>>>(                                       \
-        ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, ctx->t_sig, ctx->t_cellfov, ctx->t_src, ctx->prep, \
-        ctx->knots, ctx->ktab, ctx->a, ctx->c, ctx->iv_sums, ctx->iv_cal)
-
 void launch_ac_pass(agis_ctx* ctx) {
     if (ctx->K == 0) return;
-    switch (ctx->ac_group) {
-        case 2: AGIS_AC_LAUNCH(2); break;
-        case 4: AGIS_AC_LAUNCH(4); break;
-        case 8: AGIS_AC_LAUNCH(8); break;
-        case 16: AGIS_AC_LAUNCH(16); break;
-        case 32: AGIS_AC_LAUNCH(32); break;
-        default: AGIS_AC_LAUNCH(64); break;
-    }
+    k_ac_pass<<<(unsigned)((ctx->K + AC_WAVES - 1) / AC_WAVES), 64 * AC_WAVES, 0, ctx->stream>>>(
+        ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, ctx->t_sig, ctx->t_cellfov, ctx->t_src, ctx->prep,
+        ctx->knots, ctx->ktab, ctx->a, ctx->c, ctx->iv_sums, ctx->iv_cal);
 }
 
 void launch_band_solve(agis_ctx* ctx) {
