@@ -41,7 +41,7 @@ __device__ __forceinline__ double group_sum(double v) {
 
 // ------------------------------------------------------------------ S block
 template <int G>
-__global__ __launch_bounds__(256) void k_source_update(DevConsts k, int64_t n_src, const int64_t* __restrict__ off,
+__global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n_src, const int64_t* __restrict__ off,
                                                        const double* __restrict__ ot, const double* __restrict__ oeta,
                                                        const float* __restrict__ osig,
                                                        const int32_t* __restrict__ ocell,
@@ -82,23 +82,35 @@ __global__ __launch_bounds__(256) void k_source_update(DevConsts k, int64_t n_sr
 #pragma unroll
     for (int e = 0; e < 21; ++e) acc[e] = 0.0;
     int64_t l = l0 + gl;
-    // current and next observation columns (software prefetch)
-    double t_c = 0.0, e_c = 0.0;
+    // Current observation: columns, and the gathered attitude coefficients,
+    // interval table entry and calibration of its cell.  The next
+    // observation's columns load at the top of an iteration, its gathers
+    // after the current observation has been evaluated.
+    double t_c = 0.0, e_c = 0.0, cal_c = 0.0;
     float s_c = 1.0f;
-    int32_t c_c = 0, ell_c = 3;
+    int32_t ell_c = 3;
+    double a_c[16];
+    KnotTab kt_c = {0.0, 1.0, 0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < 16; ++e) a_c[e] = 0.0;
     if (l < l1) {
         t_c = ot[l];
         e_c = oeta[l];
         s_c = osig[l];
-        c_c = ocell[l];
         ell_c = oell[l];
+        cal_c = c[ocell[l] >> 1];
+        const double* a4 = a + 4 * (ell_c - 3);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) a_c[e] = a4[e];
+        kt_c = ktab[ell_c - 3];
     }
     for (; l < l1; l += G) {
         const int64_t ln = l + G;
+        const bool more = ln < l1;
         double t_n = 0.0, e_n = 0.0;
         float s_n = 1.0f;
         int32_t c_n = 0, ell_n = 3;
-        if (ln < l1) {
+        if (more) {
             t_n = ot[ln];
             e_n = oeta[ln];
             s_n = osig[ln];
@@ -106,12 +118,11 @@ __global__ __launch_bounds__(256) void k_source_update(DevConsts k, int64_t n_sr
             ell_n = oell[ln];
         }
         ObsEval o;
-        observe(k, t_c, e_c, c[c_c >> 1], r, mu, plx, a + 4 * (ell_c - 3), knots + (ell_c - 2), ktab[ell_c - 3],
-                o);
+        observe(k, t_c, e_c, cal_c, r, mu, plx, a_c, knots + (ell_c - 2), kt_c, o);
         double A[5];
         source_partials(o, p, q, r, A);
         const double sg = (double)s_c;
-        const double W = 1.0 / (sg * sg);
+        const double W = rcp_nr(sg * sg);
         int e = 0;
 #pragma unroll
         for (int rr = 0; rr < 5; ++rr) {
@@ -125,8 +136,14 @@ __global__ __launch_bounds__(256) void k_source_update(DevConsts k, int64_t n_sr
         t_c = t_n;
         e_c = e_n;
         s_c = s_n;
-        c_c = c_n;
         ell_c = ell_n;
+        if (more) {
+            cal_c = c[c_n >> 1];
+            const double* a4 = a + 4 * (ell_n - 3);
+#pragma unroll
+            for (int e2 = 0; e2 < 16; ++e2) a_c[e2] = a4[e2];
+            kt_c = ktab[ell_n - 3];
+        }
     }
 #pragma unroll
     for (int e = 0; e < 21; ++e) acc[e] = group_sum<G>(acc[e]);
