@@ -31,13 +31,54 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-# Algorithmic per-unit figures of the two observation passes:
-# bytes each pass must move and FP64 operations it must execute.
+# Algorithmic per-unit figures of the two observation passes (FP64 flops,
+# an add, multiply or divide counting 1 and a fused multiply-add 2; bytes
+# each pass must move).  The flop counts follow the formulas of the
+# observation model as the kernels evaluate them:
+#   model (ephemeris, proper direction, aberration, B-splines, attitude,
+#   SRS direction, field angle, residual)                          226
+#   A/C: attitude partials 29, normal-equation terms 83, the 120 interval
+#        sums 240                                                  352
+#   S:   source partials 72, weight 2, the 21 source sums 58        132
+AC_FLOPS_PER_OBS = 226.0 + 352.0
+S_FLOPS_PER_OBS = 226.0 + 132.0
+S_FLOPS_PER_SOURCE = 400.0     # 5x5 modified Cholesky, variances, update
 AC_BYTES_PER_OBS = 28.0        # t 8, eta 8, sigma 4, cell+fov 4, source 4
 AC_BYTES_PER_INTERVAL = 8.0 * (116 + 4) + 8.0 + 4 * 8.0   # sums out, offset, coefficient in
 AC_BYTES_PER_SOURCE = 56.0     # r, mu vector, parallax of s^(k+1)
 S_BYTES_PER_OBS = 28.0         # t 8, eta 8, sigma 4, cell+fov 4, left index 4
 S_BYTES_PER_SOURCE = 40.0 + 40.0 + 64.0 + 40.0 + 8.0 + 4.0 + 8.0   # s in/out, prep, d, Q, defect, offset
+
+KERNEL_SOURCES = ("paper_1112_4139_amd/csrc/hot.hip", "paper_1112_4139_amd/csrc/model.h")
+PMC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_gaia1.txt")
+KERNEL_SYMBOL = {"ac_pass": "k_ac_pass", "source_update": "k_source_update"}
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of kernel from the committed rocprofv3 PMC
+    summary (FETCH_SIZE + WRITE_SIZE scaled by a copy-kernel calibration),
+    or None when no summary exists or the kernels changed since."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    vals = {}
+    with open(PMC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha1") != kernel_source_hash():
+        return None
+    key = KERNEL_SYMBOL[kernel] + " hbm_bytes_per_launch"
+    return float(vals[key]) if key in vals else None
 
 
 def workload_description(name, w):
@@ -90,6 +131,9 @@ def main():
     ap.add_argument("--seg-len", type=int, default=None)
     ap.add_argument("--cpu-frac", type=float, default=0.2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after the timed steps, run one plain device copy of this many MiB (the reference "
+                         "kernel for scaling HBM counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of this path "
@@ -147,20 +191,36 @@ def main():
     value = w.n_obs / (elapsed / args.steps)
     kavg = {k: float(np.mean(v)) for k, v in kt.items()}
     log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, kernels {kavg}")
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {n * 8} bytes read, {n * 8} bytes written")
+        agis.agis_destroy(ctx)
+        return
     st = agis.agis_iterate(ctx, 1, stats=True)[0]
     log(f"last iteration stats: S rms {st['s']['rms_update']} A defect {st['a']['defect']}")
 
-    # dominant kernel and its roofline
+    # dominant kernel and its roofline: both observation passes are bound by
+    # FP64 arithmetic (their algorithmic HBM traffic needs ~10% of 8 TB/s)
     K = w.n_att - 3
     dom = max(("ac_pass", "source_update"), key=lambda k: kavg[k])
     if dom == "ac_pass":
+        alg_flops = AC_FLOPS_PER_OBS * w.n_obs
         alg_bytes = AC_BYTES_PER_OBS * w.n_obs + AC_BYTES_PER_INTERVAL * K + AC_BYTES_PER_SOURCE * n_src
     else:
+        alg_flops = S_FLOPS_PER_OBS * w.n_obs + S_FLOPS_PER_SOURCE * n_src
         alg_bytes = S_BYTES_PER_OBS * w.n_obs + S_BYTES_PER_SOURCE * n_src + 32.0 * w.n_att
-    gbs = alg_bytes / (kavg[dom] * 1e-3) / 1e9
-    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                "alg_bytes_per_launch": alg_bytes, "avg_ms": kavg[dom]}
+    sec = kavg[dom] * 1e-3
+    tfs = alg_flops / sec / 1e12
+    roofline = {"kernel": dom, "bound": "alu", "achieved": round(tfs, 2), "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(tfs / FP64_PEAK_TFLOPS, 4), "traffic": measured_traffic(dom),
+                "alg_flops_per_launch": alg_flops, "alg_bytes_per_launch": alg_bytes,
+                "alg_hbm_GBs": round(alg_bytes / sec / 1e9, 1),
+                "alg_hbm_frac": round(alg_bytes / sec / 1e9 / HBM_PEAK_GBS, 4), "avg_ms": kavg[dom]}
 
     cpu = None
     if not args.no_cpu_baseline:
