@@ -34,7 +34,7 @@ def _structs(c_r):
         _fields_ = [("n_knots", c_i64), ("knots", P(c_r)), ("gamma_c", c_r), ("t_ep", c_r), ("t_fr", c_r),
                     ("lambda_reg", c_r), ("seg_len", c_i32), ("seg_overlap", c_i32), ("eph_radius_au", c_r),
                     ("eph_L0", c_r), ("eph_Lrate", c_r), ("eps_obl", c_r), ("au_m", c_r), ("c_mps", c_r),
-                    ("year_s", c_r)]
+                    ("year_s", c_r), ("robust", c_i32), ("eps_bucket", c_i32)]
 
     class Obs(ctypes.Structure):
         _fields_ = [("n", c_i64), ("t", P(c_r)), ("eta_obs", P(c_r)), ("sigma", P(c_f)), ("src", P(c_i32)),
@@ -42,7 +42,7 @@ def _structs(c_r):
 
     class State(ctypes.Structure):
         _fields_ = [("n_src", c_i64), ("n_att", c_i64), ("n_cells", c_i64), ("s", P(c_r)), ("a", P(c_r)),
-                    ("c", P(c_r))]
+                    ("c", P(c_r)), ("n_buckets", c_i64), ("eps_a2", P(c_r))]
 
     return World, Obs, State
 
@@ -114,6 +114,11 @@ def lib(precision="double"):
         L.orc_iterate_sac.argtypes = [P(World), P(Obs), P(State), P(c_r)]
         L.orc_frame_fit.argtypes = [P(World), P(State), P(c_r), P(c_r), P(c_r)]
         L.orc_frame_apply.argtypes = [P(World), P(State), P(c_r)]
+        L.orc_weight_function.argtypes = [c_r]
+        L.orc_weight_function.restype = c_r
+        L.orc_quantile.argtypes = [P(c_r), c_i64, c_r]
+        L.orc_quantile.restype = c_r
+        L.orc_excess_attitude_noise.argtypes = [P(World), P(Obs), P(State)]
         _libs[precision] = L
     return _libs[precision]
 
@@ -207,6 +212,17 @@ def band_solve(UB, b, hb):
     return U, x, d
 
 
+def weight_function(z):
+    """Downweighting function w(z) of eq:dw."""
+    return float(lib().orc_weight_function(float(z)))
+
+
+def quantile(x, p):
+    """p-quantile, linear interpolation at (n - 1) p (type 7)."""
+    x = _vec(x)
+    return float(lib().orc_quantile(_p(x, c_d), x.size, float(p)))
+
+
 def normal_triad(alpha, delta):
     p, q, r = np.empty(3), np.empty(3), np.empty(3)
     lib().orc_normal_triad(float(alpha), float(delta), _p(p, c_d), _p(q, c_d), _p(r, c_d))
@@ -218,7 +234,9 @@ class Problem:
     """Holds the world constants, observations and a mutable state (s, a, c).
 
     ``consts`` keys: gamma_c, t_ep, t_fr, lambda_reg, seg_len, seg_overlap,
-    eph_radius_au, eph_L0, eph_Lrate, eps_obl, au_m, c_mps, year_s.
+    eph_radius_au, eph_L0, eph_Lrate, eps_obl, au_m, c_mps, year_s, and for
+    the robust mode robust (0/1), eps_bucket (knot intervals per bucket) and
+    eps_a_init (initial excess attitude noise [rad]).
     ``precision``: "double" (the oracle) or "extended" (the same code in x87
     extended precision; arrays are then numpy longdouble).
     """
@@ -245,7 +263,14 @@ class Problem:
                                  seg_len=int(consts["seg_len"]), seg_overlap=int(consts["seg_overlap"]),
                                  eph_radius_au=consts["eph_radius_au"], eph_L0=consts["eph_L0"],
                                  eph_Lrate=consts["eph_Lrate"], eps_obl=consts["eps_obl"], au_m=consts["au_m"],
-                                 c_mps=consts["c_mps"], year_s=consts["year_s"])
+                                 c_mps=consts["c_mps"], year_s=consts["year_s"],
+                                 robust=int(consts.get("robust", 0)), eps_bucket=int(consts.get("eps_bucket", 8)))
+        n_iv = self.knots.size - 7
+        if self.world.robust:
+            nb = (n_iv + self.world.eps_bucket - 1) // self.world.eps_bucket
+            self.eps_a2 = self._arr(np.full(nb, float(consts.get("eps_a_init", 0.0)) ** 2))
+        else:
+            self.eps_a2 = self._zeros(0)
         self._refresh()
 
     def _arr(self, x):
@@ -260,13 +285,17 @@ class Problem:
                              sigma=_p(self.sigma, c_f), src=_p(self.src, c_i32), fov=_p(self.fov, c_i8),
                              cell=_p(self.cell, c_i32))
         self.state = self._State(n_src=self.s.shape[0], n_att=self.a.shape[0], n_cells=self.c.size,
-                                 s=_p(self.s, cr), a=_p(self.a, cr), c=_p(self.c, cr))
+                                 s=_p(self.s, cr), a=_p(self.a, cr), c=_p(self.c, cr),
+                                 n_buckets=self.eps_a2.size, eps_a2=_p(self.eps_a2, cr))
 
     def set_eta_obs(self, eta_obs):
         self.eta_obs = self._arr(eta_obs).copy()
         self._refresh()
 
-    def set_state(self, s=None, a=None, c=None):
+    def set_state(self, s=None, a=None, c=None, eps_a2=None):
+        if eps_a2 is not None:
+            assert np.size(eps_a2) == self.eps_a2.size
+            self.eps_a2 = self._arr(eps_a2).copy()
         if s is not None:
             self.s = self._arr(s).copy()
         if a is not None:
@@ -321,6 +350,12 @@ class Problem:
 
     def num_segments(self):
         return int(self._L.orc_num_segments(ctypes.byref(self.world)))
+
+    def excess_attitude_noise(self):
+        """Re-estimate eps_a^2 per bucket from the residuals at the current state."""
+        self._L.orc_excess_attitude_noise(ctypes.byref(self.world), ctypes.byref(self.obs),
+                                          ctypes.byref(self.state))
+        return self.eps_a2.copy()
 
     def calibration_update(self):
         d = np.zeros_like(self.c)

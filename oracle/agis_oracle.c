@@ -352,13 +352,6 @@ void orc_observe(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* 
     }
 }
 
-/* Statistical weight W_l = w_l / (sigma_l^2 + eps_l^2) (eq:Jfunc) with
- * w_l = 1 and eps_l = 0 (plain weighted least squares). */
-static double weight(const orc_obs_t* obs, int64_t l) {
-    double s = (double)obs->sigma[l];
-    return 1.0 / (s * s);
-}
-
 /* Observations grouped by source, each group in input order (stable). */
 static void group_by_source(const orc_obs_t* obs, int64_t n_src, int64_t** off_out, int64_t** idx_out) {
     int64_t* off = (int64_t*)calloc((size_t)n_src + 1, sizeof(int64_t));
@@ -374,11 +367,99 @@ static void group_by_source(const orc_obs_t* obs, int64_t n_src, int64_t** off_o
 }
 
 /* ========================================================================
+ * Sect. 5.1.2 and 5.2.5: robust weighting.
+ * ====================================================================== */
+/* eq:dw: 1 up to |z| = 2, a cubic in t = |z| - 2 up to 3, exp(-|z|/3) beyond. */
+double orc_weight_function(double z) {
+    double a = fabs(z);
+    if (a <= 2.0) return 1.0;
+    if (a < 3.0) {
+        double t = a - 2.0;
+        return 1.0 - 1.773735 * t * t + 1.141615 * t * t * t;
+    }
+    return exp(-a / 3.0);
+}
+
+static int cmp_real(const void* a, const void* b) {
+    double x = *(const double*)a, y = *(const double*)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+double orc_quantile(const double* x, int64_t n, double p) {
+    if (n <= 0) return 0.0;
+    double* y = (double*)malloc(sizeof(double) * (size_t)n);
+    memcpy(y, x, sizeof(double) * (size_t)n);
+    qsort(y, (size_t)n, sizeof(double), cmp_real);
+    double h = (double)(n - 1) * p;
+    int64_t j = (int64_t)floor(h);
+    double q = j + 1 < n ? y[j] + (h - (double)j) * (y[j + 1] - y[j]) : y[n - 1];
+    free(y);
+    return q;
+}
+
+/* Knot interval of an observation (left index l, interval l - 3) and its
+ * excess-noise bucket. */
+static int64_t bucket_of(const orc_world_t* w, int64_t ell) { return (ell - (M_ORDER - 1)) / w->eps_bucket; }
+
+/* sigma~_l^2 = sigma_l^2 + eps_a^2(t_l) (eq:W with eps_i = 0). */
+static double sigma_tilde2(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, int64_t l,
+                           int64_t ell) {
+    double s = (double)obs->sigma[l];
+    double v = s * s;
+    if (w->robust) v += st->eps_a2[bucket_of(w, ell)];
+    return v;
+}
+
+/* Statistical weight W_l = w_l / sigma~_l^2 (eq:W, eq:wl) for the attitude
+ * and calibration updates: w_l from the residual R_l of the pass and the
+ * latest excess attitude noise (Sect. 5.2.5); w_l = 1 when not robust. */
+static double weight(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, int64_t l,
+                     const orc_fwd_t* o) {
+    double v = sigma_tilde2(w, obs, st, l, o->ell);
+    double wl = w->robust ? orc_weight_function(o->R / sqrt(v)) : 1.0;
+    return wl / v;
+}
+
+void orc_excess_attitude_noise(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st) {
+    if (!w->robust || st->n_buckets <= 0) return;
+    int64_t nb = st->n_buckets;
+    int64_t* cnt = (int64_t*)calloc((size_t)nb + 1, sizeof(int64_t));
+    int64_t* bk = (int64_t*)malloc(sizeof(int64_t) * (size_t)(obs->n > 0 ? obs->n : 1));
+    double* v = (double*)malloc(sizeof(double) * (size_t)(obs->n > 0 ? obs->n : 1));
+    double* x = (double*)malloc(sizeof(double) * (size_t)(obs->n > 0 ? obs->n : 1));
+#pragma omp parallel for schedule(static)
+    for (int64_t l = 0; l < obs->n; ++l) {
+        orc_fwd_t o;
+        forward_one(w, obs, st, l, &o);
+        double s = (double)obs->sigma[l];
+        bk[l] = bucket_of(w, o.ell);
+        v[l] = o.R * o.R - s * s;
+    }
+    for (int64_t l = 0; l < obs->n; ++l) cnt[bk[l] + 1] += 1;
+    for (int64_t j = 0; j < nb; ++j) cnt[j + 1] += cnt[j];
+    int64_t* pos = (int64_t*)malloc(sizeof(int64_t) * (size_t)nb);
+    for (int64_t j = 0; j < nb; ++j) pos[j] = cnt[j];
+    for (int64_t l = 0; l < obs->n; ++l) x[pos[bk[l]]++] = v[l];
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t j = 0; j < nb; ++j) {
+        double q = orc_quantile(x + cnt[j], cnt[j + 1] - cnt[j], 0.68);
+        st->eps_a2[j] = q > 0.0 ? q : 0.0;
+    }
+    free(cnt); free(bk); free(v); free(x); free(pos);
+}
+
+/* ========================================================================
  * Sect. 5.1: source update.  For each source: eq:normS / eq:normSmat with
  * the design matrix eq:designS and h = R (eq:designSrhs), solved by
  * Algorithms C1-C3; Q_i from eq:Qi; alpha updated through d_1 = dalpha cos
  * delta (footnote to eq:ubardiff).
+ * Robust (Sect. 5.1.2, inner iteration with eps_i = 0): initial downweights
+ * w_l = w(h_l / varsigma_i), varsigma_i half the intersextile range of the
+ * h_l; then four solves, the weights after each of the first three set to
+ * w(R_l / sigma~_l) from the updated residuals R_l = h_l - A_l d.
  * ====================================================================== */
+#define ORC_INNER_SOLVES 4
+
 void orc_source_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st,
                        double* d_out, double* Q_out, int32_t* defect_out, double* var_out) {
     int64_t *off, *idx;
@@ -386,7 +467,7 @@ void orc_source_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* 
 #pragma omp parallel
     {
         int64_t cap = 0;
-        double *Ab = NULL, *hb = NULL, *Wb = NULL;
+        double *Ab = NULL, *hb = NULL, *Vb = NULL, *wb = NULL;
 #pragma omp for schedule(dynamic, 64)
         for (int64_t i = 0; i < st->n_src; ++i) {
             int64_t ni = off[i + 1] - off[i];
@@ -394,25 +475,48 @@ void orc_source_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* 
                 cap = ni;
                 Ab = (double*)realloc(Ab, sizeof(double) * 5 * cap);
                 hb = (double*)realloc(hb, sizeof(double) * cap);
-                Wb = (double*)realloc(Wb, sizeof(double) * cap);
+                Vb = (double*)realloc(Vb, sizeof(double) * cap);
+                wb = (double*)realloc(wb, sizeof(double) * cap);
             }
-            double N[25] = {0}, b[5] = {0};
             for (int64_t k = 0; k < ni; ++k) {
                 int64_t l = idx[off[i] + k];
                 orc_fwd_t o;
                 forward_one(w, obs, st, l, &o);
-                double* A = Ab + 5 * k;
-                source_partials(&o, A);
+                source_partials(&o, Ab + 5 * k);
                 hb[k] = o.R;
-                Wb[k] = weight(obs, l);
-                for (int r = 0; r < 5; ++r) {
-                    for (int c = 0; c < 5; ++c) N[5 * r + c] += A[r] * Wb[k] * A[c];
-                    b[r] += A[r] * Wb[k] * hb[k];
-                }
+                Vb[k] = sigma_tilde2(w, obs, st, l, o.ell);
+                wb[k] = 1.0;
             }
-            int def = orc_chol_c1(N, 5);
-            orc_chol_c2(N, 5, b);
-            orc_chol_c3(N, 5, b);
+            int n_solve = 1;
+            if (w->robust) {
+                n_solve = ORC_INNER_SOLVES;
+                double vs = 0.5 * (orc_quantile(hb, ni, 5.0 / 6.0) - orc_quantile(hb, ni, 1.0 / 6.0));
+                for (int64_t k = 0; k < ni; ++k) wb[k] = vs > 0.0 ? orc_weight_function(hb[k] / vs) : 1.0;
+            }
+            double N[25], b[5];
+            int def = 0;
+            for (int it = 0; it < n_solve; ++it) {
+                if (it > 0) {
+                    for (int64_t k = 0; k < ni; ++k) {
+                        double Rk = hb[k];
+                        for (int c = 0; c < 5; ++c) Rk -= Ab[5 * k + c] * b[c];
+                        wb[k] = orc_weight_function(Rk / sqrt(Vb[k]));
+                    }
+                }
+                for (int e = 0; e < 25; ++e) N[e] = 0.0;
+                for (int e = 0; e < 5; ++e) b[e] = 0.0;
+                for (int64_t k = 0; k < ni; ++k) {
+                    const double* A = Ab + 5 * k;
+                    double W = wb[k] / Vb[k];
+                    for (int r = 0; r < 5; ++r) {
+                        for (int c = 0; c < 5; ++c) N[5 * r + c] += A[r] * W * A[c];
+                        b[r] += A[r] * W * hb[k];
+                    }
+                }
+                def = orc_chol_c1(N, 5);
+                orc_chol_c2(N, 5, b);
+                orc_chol_c3(N, 5, b);
+            }
             if (var_out) {
                 /* diagonal of the inverse: C2 and C3 on the unit vectors
                  * (Appendix C.2) */
@@ -428,7 +532,7 @@ void orc_source_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* 
             for (int64_t k = 0; k < ni; ++k) {
                 double Rk = hb[k];
                 for (int c = 0; c < 5; ++c) Rk -= Ab[5 * k + c] * b[c];
-                Q += Rk * Wb[k] * Rk;
+                Q += Rk * (wb[k] / Vb[k]) * Rk;
             }
             double* s = st->s + 5 * i;
             double cosd = cos(s[1]);
@@ -441,7 +545,7 @@ void orc_source_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* 
             if (Q_out) Q_out[i] = Q;
             if (defect_out) defect_out[i] = def;
         }
-        free(Ab); free(hb); free(Wb);
+        free(Ab); free(hb); free(Vb); free(wb);
     }
     free(off);
     free(idx);
@@ -526,7 +630,7 @@ static int64_t solve_segment(const orc_world_t* w, const orc_obs_t* obs, const o
         forward_one(w, obs, st, l, &o);
         double g[4];
         attitude_partial(&o, g);
-        double W = weight(obs, l);
+        double W = weight(w, obs, st, l, &o);
         for (int kn = 0; kn < M_ORDER; ++kn) {
             int64_t nb = o.ell - (M_ORDER - 1) + kn - sg->n_lo;
             for (int km = 0; km < M_ORDER; ++km) {
@@ -606,7 +710,7 @@ static void calibration_solve(const orc_world_t* w, const orc_obs_t* obs, const 
     for (int64_t l = 0; l < obs->n; ++l) {
         orc_fwd_t o;
         forward_one(w, obs, st, l, &o);
-        double W = weight(obs, l);
+        double W = weight(w, obs, st, l, &o);
         int32_t c = obs->cell[l];
         Nc[c] += 1.0 * W * 1.0;
         bc[c] -= 1.0 * o.R * W;
@@ -639,9 +743,12 @@ void orc_calibration_update(const orc_world_t* w, const orc_obs_t* obs, orc_stat
 }
 
 /* Sect. 4.5 (practical scheme): S with a^k, c^k; then A and C both with
- * s^{k+1}, a^k, c^k (the S[AC] variant of eq:precondS(CAG) without G). */
+ * s^{k+1}, a^k, c^k (the S[AC] variant of eq:precondS(CAG) without G).
+ * Robust: the excess attitude noise is re-estimated from the residuals after
+ * the source update and used by the A and C weights (Sect. 5.2.5). */
 void orc_iterate_sac(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st, double* var) {
     orc_source_update(w, obs, st, NULL, NULL, NULL, var);
+    orc_excess_attitude_noise(w, obs, st);
     double* da = (double*)calloc((size_t)(4 * st->n_att), sizeof(double));
     double* dc = (double*)calloc((size_t)st->n_cells, sizeof(double));
     attitude_solve(w, obs, st, da);
@@ -654,9 +761,11 @@ void orc_iterate_sac(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st
 
 /* ========================================================================
  * Sect. 6.1: frame rotator.
- * Fit: unweighted least squares of eq:cond-mu3 over all sources taken as
- * S_PM, comparison epoch t = t_ep, with the position differences of
- * eq:fr-Delta1 (t_P = t_ep); normal equations solved by C1-C3.
+ * Fit: least squares of eq:cond-mu3 over all sources taken as S_PM,
+ * comparison epoch t = t_ep, with the position differences of eq:fr-Delta1
+ * (t_P = t_ep), each equation weighted by the inverse variance of its
+ * parameter (unit weights without variances); normal equations solved by
+ * C1-C3.
  * Apply: the five rigorous steps of Sect. 6.1.2 for every source and
  * eq:fr-q4 with eq:RF4 for every attitude coefficient.
  * ====================================================================== */

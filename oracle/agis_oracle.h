@@ -36,6 +36,8 @@ typedef struct {
     double au_m;              /* astronomical unit [m] */
     double c_mps;             /* speed of light [m/s] */
     double year_s;            /* Julian year [s] */
+    int32_t robust;           /* 0: w_l = 1, eps = 0; 1: downweighting and excess attitude noise */
+    int32_t eps_bucket;       /* knot intervals per excess-attitude-noise bucket (robust) */
 } orc_world_t;
 
 typedef struct {
@@ -53,6 +55,8 @@ typedef struct {
     double* s;                /* [n_src][5] alpha, delta, parallax, pm_alpha*, pm_delta */
     double* a;                /* [n_att][4] x, y, z, w */
     double* c;                /* [n_cells] */
+    int64_t n_buckets;        /* ceil((N - 3) / eps_bucket) when robust, else 0 */
+    double* eps_a2;           /* [n_buckets] excess attitude variance eps_a^2 [rad^2] */
 } orc_state_t;
 
 /* --- Appendix A: quaternions -------------------------------------------- */
@@ -89,11 +93,26 @@ void orc_observe(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* 
 void orc_ephemeris(const orc_world_t* w, double t, double b[3], double v[3]);
 void orc_normal_triad(double alpha, double delta, double p[3], double q[3], double r[3]);
 
+/* --- Sect. 5.1.2, 5.2.5: robust weighting ------------------------------------ */
+/* Downweighting function w(z) (eq:dw). */
+double orc_weight_function(double z);
+/* p-quantile of x[0..n-1] by linear interpolation between order statistics
+ * at (n - 1) p (Hyndman-Fan type 7); n = 0 gives 0.  x is not modified. */
+double orc_quantile(const double* x, int64_t n, double p);
+/* Excess attitude noise (eq e09) per bucket from the residuals at the
+ * current state: eps_a2[j] = max(0, F_0.68(R_l^2 - sigma_l^2)) over the
+ * observations of bucket j (knot intervals [j B, (j + 1) B)); 0 for an empty
+ * bucket.  Needs robust = 1. */
+void orc_excess_attitude_noise(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st);
+
 /* --- Sect. 5: update blocks ----------------------------------------------- */
 /* S block for all sources; updates st->s in place.  Optional outputs:
  * d[n_src][5] updates, Q[n_src] = R'WR after the solve, defect[n_src],
  * var[n_src][5] the diagonal of the inverse normal matrix (first-order
- * variances, Sect. 5.1.1 / eq:cov). */
+ * variances, Sect. 5.1.1 / eq:cov).  With robust = 1 each source runs the
+ * inner iteration of Sect. 5.1.2 (initial downweights from half the
+ * intersextile range of its residuals, then four solves with the weights
+ * re-derived from the updated residuals; excess source noise 0). */
 void orc_source_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st,
                        double* d, double* Q, int32_t* defect, double* var);
 /* A block (all segments); residuals from the current state.  d[n_att][4]

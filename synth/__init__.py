@@ -106,6 +106,9 @@ class WorldSpec:
     seed_outlier: int = 3
     dec_band: tuple | None = None     # optional (dec_min, dec_max) [rad] to concentrate stars
     min_transits: int = 0             # keep only stars with at least this many transits
+    robust: bool = False              # downweighting and excess attitude noise in the solvers
+    eps_bucket: int = 8               # knot intervals per excess-attitude-noise bucket
+    eps_a_init: float = 50.0 * MAS    # excess attitude noise assumed before the first attitude update
 
 
 @dataclass
@@ -337,7 +340,8 @@ def make_world(spec: WorldSpec, law: dict | None = None) -> World:
         gamma_c=law["gamma"], t_ep=0.0, t_fr=0.0, lambda_reg=spec.lambda_reg,
         seg_len=spec.seg_len, seg_overlap=spec.seg_overlap,
         eph_radius_au=1.01, eph_L0=law["L0"], eph_Lrate=law["Lrate"], eps_obl=law["eps_obl"],
-        au_m=AU_M, c_mps=C_MPS, year_s=YEAR, t_beg=t_beg, t_end=t_end, law=law)
+        au_m=AU_M, c_mps=C_MPS, year_s=YEAR, t_beg=t_beg, t_end=t_end, law=law,
+        robust=int(spec.robust), eps_bucket=spec.eps_bucket, eps_a_init=spec.eps_a_init)
     return World(spec=spec, consts=consts, knots=knots, src_true=src_true, att_true=att_true,
                  cal_true=cal_true, src_start=src_start, att_start=att_start, cal_start=cal_start,
                  t=np.ascontiguousarray(t_obs), src=np.ascontiguousarray(src_idx),

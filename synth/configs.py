@@ -44,9 +44,18 @@ WORKLOADS = {
     # 1M stars, 1 yr, 9 AF observations per transit (~160M obs), 30 s knots
     "gaia1": (gaia_law, WorldSpec(n_src=1_000_000, years=1.0, knot_dt=30.0, ccd_per_transit=9,
                                   seg_len=240, seg_overlap=12, lambda_reg=1e-2, min_transits=6)),
-    # 2M stars, 5 yr, 9 AF observations per transit (~1.6G obs), 1% outliers
+    # 2M stars, 5 yr, 9 AF observations per transit (~1.6G obs), 1% outliers,
+    # robust solvers (downweighting, excess attitude noise in 8-interval buckets)
     "gaia5": (gaia_law, WorldSpec(n_src=2_000_000, years=5.0, knot_dt=30.0, ccd_per_transit=9,
-                                  seg_len=240, seg_overlap=12, lambda_reg=1e-2, outlier_frac=0.01)),
+                                  seg_len=240, seg_overlap=12, lambda_reg=1e-2, outlier_frac=0.01,
+                                  robust=True)),
+    # robust parity cases: the tiny and small worlds with 1% outliers
+    "tiny_robust": (mini_law, WorldSpec(n_src=20000, years=1.0, knot_dt=1200.0, ccd_per_transit=1,
+                                        seg_len=240, seg_overlap=12, lambda_reg=1e-2, min_transits=6,
+                                        outlier_frac=0.01, robust=True)),
+    "small_robust": (mini_law, WorldSpec(n_src=4000, years=1.0, knot_dt=1200.0, ccd_per_transit=1,
+                                         seg_len=240, seg_overlap=12, lambda_reg=1e-2, min_transits=6,
+                                         outlier_frac=0.01, robust=True)),
 }
 
 
