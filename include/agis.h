@@ -71,6 +71,17 @@ typedef struct agis_ctx agis_ctx_t;
  *                accumulation with compensated sums; FP64 elsewhere).
  *   device     : HIP device ordinal; stream: hipStream_t or NULL (the
  *                context then creates its own default-priority stream).
+ *   robust     : 0 = statistical weights W = 1/sigma^2; 1 = robust weighting
+ *                (Sect. 5.1.2, 5.2.5): W = w(z)/sigma~^2 with the downweighting
+ *                function w of eq:dw and sigma~^2 = sigma^2 + eps_a^2(t); the
+ *                source update runs the inner iteration (initial downweights
+ *                from half the intersextile range of the source's residuals,
+ *                then four solves; excess source noise 0); the excess
+ *                attitude noise eps_a (eq e09, 68th percentile of R^2 -
+ *                sigma^2) is re-estimated per bucket after every source
+ *                update and used by the attitude and calibration weights.
+ *   eps_bucket : knot intervals per eps_a bucket (robust only, >= 1).
+ *   eps_a_init : eps_a of every bucket before the first estimate [rad].
  */
 typedef struct {
     int64_t n_knots;
@@ -84,6 +95,9 @@ typedef struct {
     int32_t precision;
     int32_t device;
     void* stream;
+    int32_t robust;
+    int32_t eps_bucket;
+    double eps_a_init;
 } agis_config_t;
 
 /*
@@ -196,8 +210,20 @@ int agis_problem_size(const agis_ctx_t* ctx, int64_t* n_obs, int64_t* n_src, int
 /* Device time [ms] of the last launch of each hot kernel, measured with
  * HIP events on the context stream: [0] source update, [1] attitude and
  * calibration accumulation, [2] band solve, [3] calibration solve,
- * [4] frame rotator. */
+ * [4] frame rotator.  In the robust mode [0] covers the three kernels of
+ * the source inner iteration and [1] the residual pass, the eps_a
+ * estimate and the accumulation. */
 int agis_kernel_times(const agis_ctx_t* ctx, double ms[5]);
+
+/* Excess attitude noise (robust mode): eps_a^2 [rad^2] of each bucket of
+ * eps_bucket knot intervals, n = ceil((N - 3) / eps_bucket).  Set before an
+ * update to impose values; read after one to inspect the estimate.
+ * AGIS_E_STATE when the context is not robust; AGIS_E_SHAPE when n differs. */
+int agis_set_excess_noise(agis_ctx_t* ctx, int64_t n, const double* eps_a2, int where);
+int agis_get_excess_noise(agis_ctx_t* ctx, int64_t n, double* eps_a2, int where);
+/* Re-estimate eps_a^2 per bucket from the residuals at the current
+ * parameters (eq e09), as the iteration does after the source update. */
+int agis_excess_noise_update(agis_ctx_t* ctx);
 
 #ifdef __cplusplus
 }

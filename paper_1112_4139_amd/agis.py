@@ -30,7 +30,8 @@ class agis_config_t(ctypes.Structure):
     _fields_ = [("n_knots", c_i64), ("knots", P(c_d)), ("gamma_c", c_d), ("t_ep", c_d), ("t_fr", c_d),
                 ("lambda_reg", c_d), ("seg_len", c_i32), ("seg_overlap", c_i32), ("eph_radius_au", c_d),
                 ("eph_L0", c_d), ("eph_Lrate", c_d), ("eps_obl", c_d), ("au_m", c_d), ("c_mps", c_d),
-                ("year_s", c_d), ("precision", c_i32), ("device", c_i32), ("stream", ctypes.c_void_p)]
+                ("year_s", c_d), ("precision", c_i32), ("device", c_i32), ("stream", ctypes.c_void_p),
+                ("robust", c_i32), ("eps_bucket", c_i32), ("eps_a_init", c_d)]
 
 
 class agis_obs_soa_t(ctypes.Structure):
@@ -80,6 +81,9 @@ _sig = {
     "agis_residuals": ([_ctx_p, _vp, ctypes.c_int], ctypes.c_int),
     "agis_problem_size": ([_ctx_p, P(c_i64), P(c_i64), P(c_i64), P(c_i64), P(c_i64)], ctypes.c_int),
     "agis_kernel_times": ([_ctx_p, P(c_d)], ctypes.c_int),
+    "agis_set_excess_noise": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
+    "agis_get_excess_noise": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
+    "agis_excess_noise_update": ([_ctx_p], ctypes.c_int),
 }
 for _name, (_args, _res) in _sig.items():
     _f = getattr(_lib, _name)
@@ -128,7 +132,9 @@ def agis_create(consts: dict, knots, precision=AGIS_FP64, device=0, stream=None)
                         eph_radius_au=consts["eph_radius_au"], eph_L0=consts["eph_L0"],
                         eph_Lrate=consts["eph_Lrate"], eps_obl=consts["eps_obl"], au_m=consts["au_m"],
                         c_mps=consts["c_mps"], year_s=consts["year_s"], precision=precision, device=device,
-                        stream=stream)
+                        stream=stream, robust=int(consts.get("robust", 0)),
+                        eps_bucket=int(consts.get("eps_bucket", 8)),
+                        eps_a_init=float(consts.get("eps_a_init", 0.0)))
     ctx = _ctx_p()
     rc = _lib.agis_create(ctypes.byref(cfg), ctypes.byref(ctx))
     _check(rc, None)
@@ -253,6 +259,18 @@ def agis_residuals(ctx, out=None):
     p, where, keep = _ptr(out, np.float64)
     _check(_lib.agis_residuals(ctx, p, where), ctx)
     return out
+
+
+def agis_set_excess_noise(ctx, eps_a2):
+    _set(_lib.agis_set_excess_noise, ctx, len(eps_a2), eps_a2)
+
+
+def agis_get_excess_noise(ctx, n, out=None):
+    return _get(_lib.agis_get_excess_noise, ctx, n, 1, out)
+
+
+def agis_excess_noise_update(ctx):
+    _check(_lib.agis_excess_noise_update(ctx), ctx)
 
 
 def agis_problem_size(ctx):

@@ -98,6 +98,14 @@ struct agis_ctx {
     double* eo = nullptr;                // [8] frame rotator parameters on device
     double* stat = nullptr;              // statistics scratch
 
+    // robust mode: excess attitude noise per bucket, per-source varsigma,
+    // and the seven by-source columns of the inner iteration (the first one
+    // also holds R^2 - sigma^2 in time order for the eps_a estimate)
+    int64_t n_buckets = 0;
+    double* eps_a2 = nullptr;            // [n_buckets]
+    double* vs = nullptr;                // [n_src]
+    double* rcol = nullptr;              // [7][n_obs]
+
     // lanes per source in the S block
     int s_group = 16;
 
@@ -116,6 +124,9 @@ int build_store(agis_ctx* ctx, const agis_obs_soa_t* obs, int where);
 // kernels.hip
 void launch_prep_sources(agis_ctx* ctx);
 void launch_source_update(agis_ctx* ctx);
+// robust.hip
+void launch_source_update_robust(agis_ctx* ctx);
+void launch_excess_noise(agis_ctx* ctx);
 void launch_ac_pass(agis_ctx* ctx);
 void launch_band_solve(agis_ctx* ctx);
 void launch_calib_solve(agis_ctx* ctx);

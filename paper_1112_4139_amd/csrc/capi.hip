@@ -94,6 +94,8 @@ static void free_store(agis_ctx* ctx) {
     dfree(ctx->sdef);
     dfree(ctx->svar);
     dfree(ctx->dc);
+    dfree(ctx->vs);
+    dfree(ctx->rcol);
     ctx->loaded = false;
     ctx->have_ref = false;
 }
@@ -199,6 +201,11 @@ extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
         g_create_error = "precision must be AGIS_FP64 or AGIS_MIXED";
         return AGIS_E_INVALID_ARG;
     }
+    if ((cfg->robust != 0 && cfg->robust != 1) || (cfg->robust && cfg->eps_bucket < 1) ||
+        !(std::isfinite(cfg->eps_a_init) && cfg->eps_a_init >= 0.0)) {
+        g_create_error = "robust must be 0 or 1, eps_bucket >= 1 and eps_a_init finite and >= 0";
+        return AGIS_E_INVALID_ARG;
+    }
     if (cfg->precision == AGIS_MIXED) {
         g_create_error = "AGIS_MIXED is not available in this build";
         return AGIS_E_INVALID_ARG;
@@ -257,6 +264,9 @@ extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
     k.half_gamma_err = (double)((long double)k.gamma_half -
                                 std::atan2((long double)k.sin_half_gamma, (long double)k.cos_half_gamma));
     build_segments(ctx);
+    if (cfg->robust) {
+        ctx->n_buckets = (ctx->K + cfg->eps_bucket - 1) / cfg->eps_bucket;
+    }
     if (const char* e = std::getenv("AGIS_S_GROUP")) ctx->s_group = std::atoi(e);
     int rc = AGIS_OK;
     auto fail = [&](int code) {
@@ -279,6 +289,14 @@ extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
     if ((rc = dalloc(ctx, &ctx->red, ctx->red_len, "reduction scratch")) != AGIS_OK) return fail(rc);
     if ((rc = dalloc(ctx, &ctx->eo, 8, "frame parameters")) != AGIS_OK) return fail(rc);
     if ((rc = dalloc(ctx, &ctx->stat, 64, "statistics")) != AGIS_OK) return fail(rc);
+    if (ctx->n_buckets > 0) {
+        if ((rc = dalloc(ctx, &ctx->eps_a2, ctx->n_buckets, "excess attitude noise")) != AGIS_OK) return fail(rc);
+        const std::vector<double> e0(ctx->n_buckets, cfg->eps_a_init * cfg->eps_a_init);
+        if (hipMemcpy(ctx->eps_a2, e0.data(), e0.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+            ctx->err = "initial copies failed";
+            return fail(AGIS_E_DEVICE);
+        }
+    }
     const std::vector<KnotTab> h_ktab = knot_table(ctx);
     if (hipMemcpy(ctx->knots, cfg->knots, ctx->n_knots * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(ctx->ktab, h_ktab.data(), h_ktab.size() * sizeof(KnotTab), hipMemcpyHostToDevice) != hipSuccess ||
@@ -318,6 +336,7 @@ extern "C" void agis_destroy(agis_ctx_t* ctx) {
     dfree(ctx->red);
     dfree(ctx->eo);
     dfree(ctx->stat);
+    dfree(ctx->eps_a2);
     for (int e = 0; e < 10; ++e) {
         if (ctx->tm.ev[e][0]) (void)hipEventDestroy(ctx->tm.ev[e][0]);
         if (ctx->tm.ev[e][1]) (void)hipEventDestroy(ctx->tm.ev[e][1]);
@@ -363,6 +382,12 @@ extern "C" int agis_load_observations(agis_ctx_t* ctx, const agis_obs_soa_t* obs
         free_store(ctx);
         ctx->err = keep;
         return rc;
+    }
+    if (ctx->cfg.robust) {
+        // the inner iteration's by-source columns (A, h, sigma~^2), also
+        // used for R^2 - sigma^2 by the excess-noise estimate
+        ALLOC(ctx->vs, n_src, "source varsigma");
+        ALLOC(ctx->rcol, 7 * std::max<int64_t>(ctx->n_obs, 1), "robust columns");
     }
     launch_prep_sources(ctx);
     HIPCHK(hipGetLastError());
@@ -465,7 +490,8 @@ static int fill_stats(agis_ctx* ctx, agis_block_stats_t* st, const double* x, in
 
 static int run_source(agis_ctx* ctx) {
     tstart(ctx, T_S);
-    launch_source_update(ctx);
+    if (ctx->cfg.robust) launch_source_update_robust(ctx);
+    else launch_source_update(ctx);
     HIPCHK(hipGetLastError());
     tstop(ctx, T_S);
     return AGIS_OK;
@@ -474,8 +500,9 @@ static int run_source(agis_ctx* ctx) {
 // A/C accumulation pass followed by the requested solves.  The A update is
 // applied only after the C solve has read the interval sums, so both blocks
 // see the same parameters (S[AC]).
-static int run_ac(agis_ctx* ctx, bool do_a, bool do_c) {
+static int run_ac(agis_ctx* ctx, bool do_a, bool do_c, bool eps_update = false) {
     tstart(ctx, T_AC);
+    if (eps_update && ctx->cfg.robust) launch_excess_noise(ctx);
     launch_ac_pass(ctx);
     HIPCHK(hipGetLastError());
     tstop(ctx, T_AC);
@@ -619,7 +646,8 @@ extern "C" int agis_iterate(agis_ctx_t* ctx, int32_t n_iter, agis_iter_stats_t* 
         int rc = run_source(ctx);
         if (rc) return rc;
         if (st && (rc = stats_s(ctx, &st->s))) return rc;
-        rc = run_ac(ctx, true, true);
+        // robust: eps_a from the residuals after the source update (Sect. 5.2.5)
+        rc = run_ac(ctx, true, true, true);
         if (rc) return rc;
         if (st && (rc = stats_a(ctx, &st->a))) return rc;
         if (st && (rc = stats_c(ctx, &st->c))) return rc;
@@ -648,6 +676,32 @@ extern "C" int agis_iterate(agis_ctx_t* ctx, int32_t n_iter, agis_iter_stats_t* 
     ctx->last_ms[2] = tget(ctx, T_BAND);
     ctx->last_ms[3] = tget(ctx, T_CAL);
     ctx->last_ms[4] = tget(ctx, T_FRAME);
+    return AGIS_OK;
+}
+
+extern "C" int agis_set_excess_noise(agis_ctx_t* ctx, int64_t n, const double* eps_a2, int where) {
+    CHECK_CTX();
+    if (!ctx->cfg.robust) return set_error(ctx, AGIS_E_STATE, "the context is not robust");
+    if (n != ctx->n_buckets || !eps_a2) return set_error(ctx, AGIS_E_SHAPE, "bucket count mismatch");
+    int rc = check_finite_host(ctx, eps_a2, n, where);
+    if (rc) return rc;
+    return copy_in(ctx, ctx->eps_a2, eps_a2, n * sizeof(double), where);
+}
+
+extern "C" int agis_get_excess_noise(agis_ctx_t* ctx, int64_t n, double* eps_a2, int where) {
+    CHECK_CTX();
+    if (!ctx->cfg.robust) return set_error(ctx, AGIS_E_STATE, "the context is not robust");
+    if (n != ctx->n_buckets || !eps_a2) return set_error(ctx, AGIS_E_SHAPE, "bucket count mismatch");
+    return copy_out(ctx, eps_a2, ctx->eps_a2, n * sizeof(double), where);
+}
+
+extern "C" int agis_excess_noise_update(agis_ctx_t* ctx) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    if (!ctx->cfg.robust) return set_error(ctx, AGIS_E_STATE, "the context is not robust");
+    launch_excess_noise(ctx);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
     return AGIS_OK;
 }
 

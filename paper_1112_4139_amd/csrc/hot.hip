@@ -24,6 +24,7 @@
 // observation's columns while the current one is evaluated.  No global
 // atomics; all sums have a fixed order.
 #include "agis_internal.h"
+#include "source_block.h"
 
 namespace agis {
 
@@ -32,12 +33,6 @@ namespace {
 // pair index of (n, m), 0 <= n <= m <= 3 (also the entry index of (r, c))
 __host__ __device__ __forceinline__ int tri4(int n, int m) { return n * 4 - (n * (n - 1)) / 2 + (m - n); }
 
-template <int G>
-__device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-    for (int m = G / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
-}
 
 // ------------------------------------------------------------------ S block
 template <int G>
@@ -148,59 +143,7 @@ __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n
 #pragma unroll
     for (int e = 0; e < 21; ++e) acc[e] = group_sum<G>(acc[e]);
     if (!valid || gl != 0) return;
-    double U[25], N[25], x[5];
-    int e = 0;
-    for (int rr = 0; rr < 5; ++rr)
-        for (int cc = rr; cc < 5; ++cc) {
-            U[rr * 5 + cc] = acc[e];
-            N[rr * 5 + cc] = acc[e];
-            N[cc * 5 + rr] = acc[e];
-            ++e;
-        }
-    for (int rr = 0; rr < 5; ++rr) x[rr] = acc[15 + rr];
-    const int d = small_chol_factor<5>(U);
-    small_chol_subst<5>(U, x);
-    // diagonal of the inverse normal matrix, the first-order variances of
-    // the five parameters (Sect. 5.1.1): C2 and C3 on the unit vectors
-#pragma unroll
-    for (int kk = 0; kk < 5; ++kk) {
-        double ev[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        ev[kk] = 1.0;
-        small_chol_subst<5>(U, ev);
-        svar[5 * i + kk] = d > 0 ? 0.0 : ev[kk];
-    }
-    // Q_i = h'Wh - 2 d'b + d'N d (eq:Qi)
-    double dNd = 0.0, db = 0.0;
-    for (int rr = 0; rr < 5; ++rr) {
-        double t = 0.0;
-        for (int cc = 0; cc < 5; ++cc) t += N[rr * 5 + cc] * x[cc];
-        dNd += x[rr] * t;
-        db += x[rr] * acc[15 + rr];
-    }
-    qsrc[i] = acc[20] - 2.0 * db + dNd;
-    sdef[i] = d;
-    for (int rr = 0; rr < 5; ++rr) ds[5 * i + rr] = x[rr];
-    const double na = alpha + x[0] / cd, nd = delta + x[1];
-    const double npl = plx + x[2], npa = pma + x[3], npd = pmd + x[4];
-    double* si = s + 5 * i;
-    si[0] = na;
-    si[1] = nd;
-    si[2] = npl;
-    si[3] = npa;
-    si[4] = npd;
-    double sa2, ca2, sd2, cd2;
-    sincos(na, &sa2, &ca2);
-    sincos(nd, &sd2, &cd2);
-    SrcPrep pr;
-    const double p2[3] = {-sa2, ca2, 0.0};
-    const double q2[3] = {-sd2 * ca2, -sd2 * sa2, cd2};
-    pr.r[0] = cd2 * ca2;
-    pr.r[1] = cd2 * sa2;
-    pr.r[2] = sd2;
-    for (int cc = 0; cc < 3; ++cc) pr.mu[cc] = p2[cc] * npa + q2[cc] * npd;
-    pr.plx = npl;
-    pr.pad = 0.0;
-    prep[i] = pr;
+    source_finish(acc, i, alpha, delta, plx, pma, pmd, cd, s, prep, ds, qsrc, sdef, svar);
 }
 
 // ------------------------------------------------------------- A/C pass
@@ -230,7 +173,8 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
                                                            const KnotTab* __restrict__ ktab,
                                                            const double* __restrict__ a,
                                                            const double* __restrict__ c,
-                                                           double* __restrict__ iv_sums,
+                                                           const double* __restrict__ eps_a2, int eps_bucket,
+                                                           int robust, double* __restrict__ iv_sums,
                                                            double* __restrict__ iv_cal) {
     __shared__ double xb[AC_WAVES][64][AC_XS];
     __shared__ double sh_a[AC_WAVES][16];
@@ -249,6 +193,8 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
     const double lam2 = k.lam2;
     const int64_t l0 = valid ? iv_off[j] : 0, l1 = valid ? iv_off[j + 1] : 0;
     const KnotTab kt = valid ? ktab[j] : KnotTab{0.0, 1.0, 0.0, 0.0};
+    // robust: sigma~^2 = sigma^2 + eps_a^2 of the interval's bucket (eq:W)
+    const double eps2 = (valid && robust) ? eps_a2[j / eps_bucket] : 0.0;
     double (*xw)[AC_XS] = xb[wv];
     const int ri = lane & 15, rk = lane >> 4;
     double4_t C = {0.0, 0.0, 0.0, 0.0};
@@ -290,7 +236,13 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
             double g[4];
             attitude_partial(o, g);
             const double sg = (double)s_c;
-            const double W = h_c ? rcp_nr(sg * sg) : 0.0;
+            double W;
+            if (robust) {
+                const double s2 = sg * sg + eps2;
+                W = h_c ? down_weight(o.R / sqrt(s2)) / s2 : 0.0;
+            } else {
+                W = h_c ? rcp_nr(sg * sg) : 0.0;
+            }
             double* row = xw[lane];
             int e = 0;
 #pragma unroll
@@ -572,7 +524,8 @@ void launch_ac_pass(agis_ctx* ctx) {
     if (ctx->K == 0) return;
     k_ac_pass<<<(unsigned)((ctx->K + AC_WAVES - 1) / AC_WAVES), 64 * AC_WAVES, 0, ctx->stream>>>(
         ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, ctx->t_sig, ctx->t_cellfov, ctx->t_src, ctx->prep,
-        ctx->knots, ctx->ktab, ctx->a, ctx->c, ctx->iv_sums, ctx->iv_cal);
+        ctx->knots, ctx->ktab, ctx->a, ctx->c, ctx->eps_a2, ctx->cfg.eps_bucket, ctx->cfg.robust, ctx->iv_sums,
+        ctx->iv_cal);
 }
 
 void launch_band_solve(agis_ctx* ctx) {
