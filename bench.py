@@ -88,6 +88,7 @@ def workload_description(name, w):
             "years": sp.years, "obs_per_transit": sp.ccd_per_transit, "knot_interval_s": sp.knot_dt,
             "attitude_coefficients": int(w.n_att), "cells": int(w.n_cells), "segment_intervals": sp.seg_len,
             "overlap_L": sp.seg_overlap, "lambda": sp.lambda_reg, "sigma_uas": 100.0,
+            "outlier_frac": sp.outlier_frac, "robust": bool(sp.robust),
             "law": "Gaia-like: spin 60 arcsec/s, precession 63 d, aspect 45 deg, basic angle 106.5 deg"}
 
 
@@ -151,7 +152,7 @@ def main():
     torch.cuda.set_device(0)
     over = {} if args.seg_len is None else {"seg_len": args.seg_len}
     t0 = time.time()
-    w = C.make(args.workload, **over)
+    w = C.make(args.workload, progress=log, **over)
     log(f"workload {args.workload}: {w.src_true.shape[0]} sources, {w.n_obs} obs, {w.n_att} coefficients "
         f"({time.time() - t0:.1f} s)")
 
@@ -167,6 +168,9 @@ def main():
     R = agis.agis_residuals(ctx)                   # = c_true - eta_true
     eta_obs = -R + w.eps
     del R, zeros
+    if args.no_cpu_baseline:
+        w.eps = w.eta_nominal = None           # not needed any more
+    log("observed field angles computed")
     agis.agis_load_observations(ctx, w.t, eta_obs, w.sigma, w.src, w.fov, w.cell, n_src, w.n_cells)
     agis.agis_set_sources(ctx, w.src_start)
     agis.agis_set_attitude(ctx, w.att_start)

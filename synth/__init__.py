@@ -228,8 +228,10 @@ def _sign_continuous_fast(q: np.ndarray) -> np.ndarray:
     return np.where(flips[:, None] == 1, -q, q)
 
 
-def make_world(spec: WorldSpec, law: dict | None = None) -> World:
-    """Generate one seeded synthetic workload (no observed field angles)."""
+def make_world(spec: WorldSpec, law: dict | None = None, progress=None) -> World:
+    """Generate one seeded synthetic workload (no observed field angles).
+    progress(message), if given, is called at each stage."""
+    say = progress if progress is not None else (lambda m: None)
     law = dict(default_law() if law is None else law)
     T = spec.years * YEAR
     t_beg, t_end = -0.5 * T, 0.5 * T
@@ -277,7 +279,9 @@ def make_world(spec: WorldSpec, law: dict | None = None) -> World:
     cal_true[1::2] = -g
 
     # transits and per-CCD observation times
+    say(f"transit search: {n} stars, {spec.years} yr")
     off, tt, ff = find_transits(law, ra, dec, t_beg, t_end)
+    say(f"{tt.shape[0]} transits")
     ntr = np.diff(off)
     if spec.min_transits > 0:
         # primary-source selection: keep only well-observed stars (the
@@ -312,6 +316,7 @@ def make_world(spec: WorldSpec, law: dict | None = None) -> World:
     cell = (2 * day + (fov == -1)).astype(np.int32)
     sigma = np.full(t_obs.shape[0], spec.sigma_al, dtype=np.float32)
 
+    say(f"{t_obs.shape[0]} observations; noise and start values")
     rng_n = np.random.default_rng(spec.seed_noise)
     if spec.noise:
         eps = rng_n.standard_normal(t_obs.shape[0]) * sigma.astype(np.float64)

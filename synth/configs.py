@@ -66,7 +66,7 @@ def workload(name: str, **overrides):
     return law_f(), dataclasses.replace(spec, **overrides)
 
 
-def make(name: str, **overrides):
+def make(name: str, progress=None, **overrides):
     from . import make_world
     law, spec = workload(name, **overrides)
-    return make_world(spec, law)
+    return make_world(spec, law, progress=progress)
