@@ -67,8 +67,13 @@ typedef struct agis_ctx agis_ctx_t;
  *                derivative v_G (the auxiliary data of eq:astro).
  *   au_m, c_mps, year_s : astronomical unit [m], speed of light [m/s],
  *                Julian year [s].
- *   precision  : AGIS_FP64 or AGIS_MIXED (FP32 partials and normal-matrix
- *                accumulation with compensated sums; FP64 elsewhere).
+ *   precision  : AGIS_FP64 or AGIS_MIXED.  MIXED keeps the observation
+ *                model and residuals, the 5x5 and band Cholesky, the
+ *                calibration solve and the frame rotator in FP64; the partials
+ *                and the normal-equation sums of the S block and the A/C pass
+ *                are single precision with compensated (Kahan) sums (in the
+ *                A/C pass per 64-observation chunk of matrix-core sums).  The
+ *                robust source inner iteration always runs in FP64.
  *   device     : HIP device ordinal; stream: hipStream_t or NULL (the
  *                context then creates its own default-priority stream).
  *   robust     : 0 = statistical weights W = 1/sigma^2; 1 = robust weighting

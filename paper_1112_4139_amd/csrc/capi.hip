@@ -206,10 +206,6 @@ extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
         g_create_error = "robust must be 0 or 1, eps_bucket >= 1 and eps_a_init finite and >= 0";
         return AGIS_E_INVALID_ARG;
     }
-    if (cfg->precision == AGIS_MIXED) {
-        g_create_error = "AGIS_MIXED is not available in this build";
-        return AGIS_E_INVALID_ARG;
-    }
     if (!(cfg->year_s > 0) || !(cfg->c_mps > 0) || !(cfg->au_m > 0)) {
         g_create_error = "year_s, c_mps and au_m must be positive";
         return AGIS_E_INVALID_ARG;

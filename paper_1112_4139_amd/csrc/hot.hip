@@ -23,6 +23,8 @@
 // Each lane walks its item's observations with stride G and loads the next
 // observation's columns while the current one is evaluated.  No global
 // atomics; all sums have a fixed order.
+#include <type_traits>
+
 #include "agis_internal.h"
 #include "source_block.h"
 
@@ -35,7 +37,15 @@ __host__ __device__ __forceinline__ int tri4(int n, int m) { return n * 4 - (n *
 
 
 // ------------------------------------------------------------------ S block
-template <int G>
+// Compensated (Kahan) single-precision running sum: s + (-c) carries the sum.
+__device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+template <int G, bool MIXED>
 __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n_src, const int64_t* __restrict__ off,
                                                        const double* __restrict__ ot, const double* __restrict__ oeta,
                                                        const float* __restrict__ osig,
@@ -76,6 +86,10 @@ __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n
     double acc[21];
 #pragma unroll
     for (int e = 0; e < 21; ++e) acc[e] = 0.0;
+    // mixed precision: single-precision partials and sums with compensation
+    float fs[MIXED ? 21 : 1], fc[MIXED ? 21 : 1];
+#pragma unroll
+    for (int e = 0; e < (MIXED ? 21 : 1); ++e) fs[e] = fc[e] = 0.0f;
     int64_t l = l0 + gl;
     // Current observation: columns, and the gathered attitude coefficients,
     // interval table entry and calibration of its cell.  The next
@@ -118,16 +132,36 @@ __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n
         source_partials(o, p, q, r, A);
         const double sg = (double)s_c;
         const double W = rcp_nr(sg * sg);
-        int e = 0;
+        if constexpr (MIXED) {
+            float Af[5];
 #pragma unroll
-        for (int rr = 0; rr < 5; ++rr) {
-            const double wa = W * A[rr];
+            for (int rr = 0; rr < 5; ++rr) Af[rr] = (float)A[rr];
+            const float Wf = (float)W, Rf = (float)o.R;
+            int e = 0;
 #pragma unroll
-            for (int cc = rr; cc < 5; ++cc) acc[e++] += wa * A[cc];
+            for (int rr = 0; rr < 5; ++rr) {
+                const float wa = Wf * Af[rr];
+#pragma unroll
+                for (int cc = rr; cc < 5; ++cc) {
+                    kahan_add(fs[e], fc[e], wa * Af[cc]);
+                    ++e;
+                }
+            }
+#pragma unroll
+            for (int rr = 0; rr < 5; ++rr) kahan_add(fs[15 + rr], fc[15 + rr], Wf * Af[rr] * Rf);
+            kahan_add(fs[20], fc[20], Wf * Rf * Rf);
+        } else {
+            int e = 0;
+#pragma unroll
+            for (int rr = 0; rr < 5; ++rr) {
+                const double wa = W * A[rr];
+#pragma unroll
+                for (int cc = rr; cc < 5; ++cc) acc[e++] += wa * A[cc];
+            }
+#pragma unroll
+            for (int rr = 0; rr < 5; ++rr) acc[15 + rr] += W * A[rr] * o.R;
+            acc[20] += W * o.R * o.R;
         }
-#pragma unroll
-        for (int rr = 0; rr < 5; ++rr) acc[15 + rr] += W * A[rr] * o.R;
-        acc[20] += W * o.R * o.R;
         t_c = t_n;
         e_c = e_n;
         s_c = s_n;
@@ -140,6 +174,10 @@ __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n
             kt_c = ktab[ell_n - 3];
         }
     }
+    if constexpr (MIXED) {
+#pragma unroll
+        for (int e = 0; e < 21; ++e) acc[e] = (double)fs[e] - (double)fc[e];
+    }
 #pragma unroll
     for (int e = 0; e < 21; ++e) acc[e] = group_sum<G>(acc[e]);
     if (!valid || gl != 0) return;
@@ -148,6 +186,7 @@ __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n
 
 // ------------------------------------------------------------- A/C pass
 typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
 
 constexpr int AC_WAVES = 2;             // wavefronts per block, one knot interval each
 constexpr int AC_XS = 33;               // LDS row stride (doubles) of the transposition buffer
@@ -162,6 +201,12 @@ constexpr int AC_XS = 33;               // LDS row stride (doubles) of the trans
 // fov x (W, W R) for eq:normC.  One wavefront takes 64 observations at a
 // time (one per lane), writes (a, b) to LDS and feeds them to 16
 // v_mfma_f64_16x16x4 steps, four observations each.
+//
+// Mixed precision (MIXED): the model stays FP64; a and b are formed in FP32
+// from single-precision partials, each 64-observation chunk is summed by
+// v_mfma_f32_16x16x4 and the chunk sums enter compensated (Kahan) FP32
+// running sums, converted to FP64 for the band solve.
+template <bool MIXED>
 __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t K, const int64_t* __restrict__ iv_off,
                                                            const double* __restrict__ ot,
                                                            const double* __restrict__ oeta,
@@ -176,7 +221,8 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
                                                            const double* __restrict__ eps_a2, int eps_bucket,
                                                            int robust, double* __restrict__ iv_sums,
                                                            double* __restrict__ iv_cal) {
-    __shared__ double xb[AC_WAVES][64][AC_XS];
+    using XT = typename std::conditional<MIXED, float, double>::type;
+    __shared__ XT xb[AC_WAVES][64][AC_XS];
     __shared__ double sh_a[AC_WAVES][16];
     __shared__ double sh_k[AC_WAVES][6];
     const int lane = threadIdx.x & 63;
@@ -195,9 +241,10 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
     const KnotTab kt = valid ? ktab[j] : KnotTab{0.0, 1.0, 0.0, 0.0};
     // robust: sigma~^2 = sigma^2 + eps_a^2 of the interval's bucket (eq:W)
     const double eps2 = (valid && robust) ? eps_a2[j / eps_bucket] : 0.0;
-    double (*xw)[AC_XS] = xb[wv];
+    XT (*xw)[AC_XS] = xb[wv];
     const int ri = lane & 15, rk = lane >> 4;
     double4_t C = {0.0, 0.0, 0.0, 0.0};
+    float4_t Cs = {0.0f, 0.0f, 0.0f, 0.0f}, Cc = {0.0f, 0.0f, 0.0f, 0.0f};
     // lanes past the end evaluate the interval's last observation again with
     // weight zero
     int64_t base = l0;
@@ -243,38 +290,84 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
             } else {
                 W = h_c ? rcp_nr(sg * sg) : 0.0;
             }
-            double* row = xw[lane];
-            int e = 0;
-#pragma unroll
-            for (int n = 0; n < 4; ++n)
-#pragma unroll
-                for (int m = n; m < 4; ++m) row[e++] = o.B[n] * o.B[m];
-#pragma unroll
-            for (int n = 0; n < 4; ++n) row[10 + n] = o.B[n];
+            XT* row = xw[lane];
             const int f = cf_c & 1;
-            row[14] = f == 0 ? 1.0 : 0.0;
-            row[15] = f == 1 ? 1.0 : 0.0;
-            e = 0;
+            if constexpr (MIXED) {
+                float B[4], gf[4], qf[4];
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr)
+                for (int n = 0; n < 4; ++n) {
+                    B[n] = (float)o.B[n];
+                    gf[n] = (float)g[n];
+                    qf[n] = (float)o.qraw[n];
+                }
+                const float Wf = (float)W, Rf = (float)o.R, Df = (float)o.D, l2 = (float)lam2;
+                int e = 0;
 #pragma unroll
-                for (int cc = rr; cc < 4; ++cc)
-                    row[16 + e++] = W * (g[rr] * g[cc] + 4.0 * lam2 * o.qraw[rr] * o.qraw[cc]);
+                for (int n = 0; n < 4; ++n)
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) row[26 + rr] = -W * (g[rr] * o.R - 2.0 * lam2 * o.qraw[rr] * o.D);
-            row[30] = W;
-            row[31] = W * o.R;
+                    for (int m = n; m < 4; ++m) row[e++] = B[n] * B[m];
+#pragma unroll
+                for (int n = 0; n < 4; ++n) row[10 + n] = B[n];
+                row[14] = f == 0 ? 1.0f : 0.0f;
+                row[15] = f == 1 ? 1.0f : 0.0f;
+                e = 0;
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+                    for (int cc = rr; cc < 4; ++cc) row[16 + e++] = Wf * (gf[rr] * gf[cc] + 4.0f * l2 * qf[rr] * qf[cc]);
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) row[26 + rr] = -Wf * (gf[rr] * Rf - 2.0f * l2 * qf[rr] * Df);
+                row[30] = Wf;
+                row[31] = Wf * Rf;
+            } else {
+                int e = 0;
+#pragma unroll
+                for (int n = 0; n < 4; ++n)
+#pragma unroll
+                    for (int m = n; m < 4; ++m) row[e++] = o.B[n] * o.B[m];
+#pragma unroll
+                for (int n = 0; n < 4; ++n) row[10 + n] = o.B[n];
+                row[14] = f == 0 ? 1.0 : 0.0;
+                row[15] = f == 1 ? 1.0 : 0.0;
+                e = 0;
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+                    for (int cc = rr; cc < 4; ++cc)
+                        row[16 + e++] = W * (g[rr] * g[cc] + 4.0 * lam2 * o.qraw[rr] * o.qraw[cc]);
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) row[26 + rr] = -W * (g[rr] * o.R - 2.0 * lam2 * o.qraw[rr] * o.D);
+                row[30] = W;
+                row[31] = W * o.R;
+            }
         }
         SrcPrep sp_n = {};
         if (bn < l1) sp_n = prep[src_n];
         // the wavefront's LDS operations complete in order: the rows just
         // written are read back below by other lanes of the same wavefront
         __asm__ volatile("" ::: "memory");
+        if constexpr (MIXED) {
+            float4_t Ck = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            const double av = xw[4 * kk + rk][ri];
-            const double bv = xw[4 * kk + rk][16 + ri];
-            C = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, C, 0, 0, 0);
+            for (int kk = 0; kk < 16; ++kk) {
+                const float av = xw[4 * kk + rk][ri];
+                const float bv = xw[4 * kk + rk][16 + ri];
+                Ck = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, Ck, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                float sv = Cs[v], cv = Cc[v];
+                kahan_add(sv, cv, Ck[v]);
+                Cs[v] = sv;
+                Cc[v] = cv;
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) {
+                const double av = xw[4 * kk + rk][ri];
+                const double bv = xw[4 * kk + rk][16 + ri];
+                C = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, C, 0, 0, 0);
+            }
         }
         __asm__ volatile("" ::: "memory");
         t_c = t_n;
@@ -285,11 +378,16 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
         sp_c = sp_n;
     }
     if (!valid) return;
-    // lane l holds C[4 v + l / 16][l % 16], v = 0..3
+    if constexpr (MIXED) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) C[v] = (double)Cs[v] - (double)Cc[v];
+    }
+    // lane l holds C[4 v + l / 16][l % 16] (FP64 product) or
+    // C[4 (l / 16) + v][l % 16] (FP32 product), v = 0..3
     double* out = iv_sums + j * IV_SUMS;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        const int i = 4 * v + rk, jj = ri;
+        const int i = MIXED ? 4 * rk + v : 4 * v + rk, jj = ri;
         if (i < 10 && jj < 10) out[i * 10 + jj] = C[v];
         else if (i >= 10 && i < 14 && jj >= 10 && jj < 14) out[100 + (i - 10) * 4 + (jj - 10)] = C[v];
         else if (i >= 14 && jj >= 14) iv_cal[j * IV_CAL + (i - 14) * 2 + (jj - 14)] = C[v];
@@ -506,7 +604,8 @@ inline int groups_grid(int64_t n_items, int items_per_block) {
 }  // namespace
 
 #define AGIS_S_LAUNCH(G)                                                                                       \
-    k_source_update<G><<<groups_grid(ctx->n_src, 256 / G), 256, 0, ctx->stream>>>(                             \
+    (ctx->cfg.precision == AGIS_MIXED ? k_source_update<G, true> : k_source_update<G, false>)                  \
+        <<<groups_grid(ctx->n_src, 256 / G), 256, 0, ctx->stream>>>(                                           \
         ctx->k, ctx->n_src, ctx->src_off, ctx->s_t, ctx->s_eta, ctx->s_sig, ctx->s_cell, ctx->s_ell, ctx->knots, \
         ctx->ktab, ctx->a, ctx->c, ctx->s, ctx->prep, ctx->ds, ctx->qsrc, ctx->sdef, ctx->svar)
 
@@ -522,7 +621,8 @@ void launch_source_update(agis_ctx* ctx) {
 
 void launch_ac_pass(agis_ctx* ctx) {
     if (ctx->K == 0) return;
-    k_ac_pass<<<(unsigned)((ctx->K + AC_WAVES - 1) / AC_WAVES), 64 * AC_WAVES, 0, ctx->stream>>>(
+    (ctx->cfg.precision == AGIS_MIXED ? k_ac_pass<true> : k_ac_pass<false>)
+        <<<(unsigned)((ctx->K + AC_WAVES - 1) / AC_WAVES), 64 * AC_WAVES, 0, ctx->stream>>>(
         ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, ctx->t_sig, ctx->t_cellfov, ctx->t_src, ctx->prep,
         ctx->knots, ctx->ktab, ctx->a, ctx->c, ctx->eps_a2, ctx->cfg.eps_bucket, ctx->cfg.robust, ctx->iv_sums,
         ctx->iv_cal);
