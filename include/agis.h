@@ -186,7 +186,7 @@ int agis_attitude_update(agis_ctx_t* ctx, agis_block_stats_t* st);
  * the constraint projection eq:calCon. */
 int agis_calibration_update(agis_ctx_t* ctx, agis_block_stats_t* st);
 /* A and C together from one pass of residuals at the current parameters
- * (the bracketed pair of the S[ACG] scheme, Sect. 4.5, without G). */
+ * (the bracketed pair of the S[ACG] scheme, Sect. 4.6, without G). */
 int agis_attitude_calibration_update(agis_ctx_t* ctx, agis_block_stats_t* st_a, agis_block_stats_t* st_c);
 
 /* Frame rotator (Sect. 6.1).  The reference catalogue s_ref [n_src][5]
@@ -199,7 +199,7 @@ int agis_set_frame_reference(agis_ctx_t* ctx, int64_t n, const double* s_ref5, i
 int agis_frame_fit(agis_ctx_t* ctx, double eps_omega[6]);
 int agis_frame_apply(agis_ctx_t* ctx, const double eps_omega[6]);
 
-/* n_iter simple iterations S[AC] (Sect. 4.5), each followed by the frame
+/* n_iter simple iterations S[AC] (Sect. 4.5, 4.6), each followed by the frame
  * rotator when a reference is set.  per_iter may be NULL or hold n_iter
  * entries. */
 int agis_iterate(agis_ctx_t* ctx, int32_t n_iter, agis_iter_stats_t* per_iter);
@@ -229,6 +229,67 @@ int agis_get_excess_noise(agis_ctx_t* ctx, int64_t n, double* eps_a2, int where)
 /* Re-estimate eps_a^2 per bucket from the residuals at the current
  * parameters (eq e09), as the iteration does after the source update. */
 int agis_excess_noise_update(agis_ctx_t* ctx);
+
+/*
+ * Learned extrapolation of the simple iteration (an extension of the paper's
+ * method: it generalises the accelerated simple iteration of Sect. 4.7,
+ * whose premise is that the updates decay geometrically along the slowest
+ * eigenvectors of the iteration).  Two MLPs, which = 0 for sources and 1 for
+ * attitude coefficients, map per unit the last four recorded updates u_k
+ * (newest first), normalised by their RMS s, and two descriptors (sources:
+ * log(n_obs + 1)/5 and the sine of the ecliptic latitude; coefficients: sine
+ * and cosine of twice the coefficient's angle about its z axis) to four
+ * mixing coefficients c; the candidate is x + sum_k c_k u_k, a step inside
+ * the span of the unit's recent updates (sources: alpha moves by the mixed
+ * d alpha* over cos delta).
+ * Inputs F = 22 / 18 (the first 20 / 16 are the normalised updates, newest
+ * first, components d alpha*, d delta, d parallax, d mu_alpha*, d mu_delta /
+ * d a_x, d a_y, d a_z, d a_w), outputs O = 4, two hidden layers of 64 with
+ * tanh.  Weights [F*64 W1][64 b1][64*64 W2][64 b2][O*64 W3][O b3]
+ * (row-major, row = output unit) in FP32; the forward and backward passes
+ * use them rounded to BF16 with FP32 accumulation.  Training targets T have
+ * NC = 5 / 4 columns: the displacement to learn in units of s.
+ */
+/* Start a history: the current parameters become the anchor. */
+int agis_learned_reset(agis_ctx_t* ctx);
+/* Record (current - anchor) as the newest update; the current parameters
+ * become the anchor.  A "record" may follow any number of iterations. */
+int agis_learned_record(agis_ctx_t* ctx);
+/* Features X [n][F] and scales s [n] of every unit from the last four
+ * recorded updates (AGIS_E_STATE with fewer than four). */
+int agis_learned_features(agis_ctx_t* ctx, int32_t which, int64_t n, float* X, float* scale, int where);
+/* Weights: Glorot-uniform from a SplitMix64 stream (biases 0), set, get. */
+int agis_mlp_init(agis_ctx_t* ctx, int32_t which, uint64_t seed);
+int agis_mlp_set_weights(agis_ctx_t* ctx, int32_t which, int64_t n, const float* w, int where);
+int agis_mlp_get_weights(agis_ctx_t* ctx, int32_t which, int64_t n, float* w, int where);
+/* Y [n][4] = MLP(X [n][F]), the mixing coefficients. */
+int agis_mlp_forward(agis_ctx_t* ctx, int32_t which, int64_t n, const float* X, float* Y, int where);
+/* Gradient of L = sum_i |yhat_i - T_i|^2 / (2 n), yhat_i[c] = sum_k
+ * MLP(X_i)[k] X_i[k NC + c] (T [n][NC]), with respect to the weights
+ * (grad [NW], same layout) and L, at the current weights. */
+int agis_mlp_gradient(agis_ctx_t* ctx, int32_t which, int64_t n, const float* X, const float* T, float* grad,
+                      float* loss, int where);
+/* steps Adam steps (beta 0.9, 0.999, eps 1e-8, rate lr) on minibatches of
+ * `batch` samples drawn from (X, T) by a counter-based hash of (seed, step);
+ * loss_out (host, may be NULL) receives each step's minibatch loss. */
+int agis_mlp_train(agis_ctx_t* ctx, int32_t which, int64_t n, const float* X, const float* T, int where,
+                   int32_t steps, int32_t batch, float lr, uint64_t seed, float* loss_out);
+/* sum over observations of R^2 / sigma^2 at the current parameters. */
+int agis_chi2(agis_ctx_t* ctx, double* q);
+/* Ungated: x <- x + s MLP(features) for sources and coefficients, then a new
+ * history starts from x.  AGIS_E_STATE with fewer than four records. */
+int agis_learned_apply(agis_ctx_t* ctx);
+/* Gated learned step, two S[AC] iterations: from the current state x0 one
+ * plain iteration gives x1, and one iteration from the candidate x0 + s y
+ * gives c1.  The one iteration damps what the MLP gets wrong along the
+ * well-determined directions, along which sum W R^2 is steep.  c1 is kept
+ * (the history restarts from it) when q_cand = sum W R^2 (c1), with W the
+ * plain weight 1 / sigma^2, is below q_plain = sum W R^2 (x1); otherwise the
+ * state becomes x1 and the history goes on, its next record spanning one
+ * iteration more.  Sources, attitude, calibration and, when robust, the
+ * excess attitude noise are saved and restored on the device.
+ * AGIS_E_STATE with fewer than four records. */
+int agis_learned_step(agis_ctx_t* ctx, double* q_plain, double* q_cand, int32_t* accepted);
 
 #ifdef __cplusplus
 }

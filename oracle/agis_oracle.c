@@ -742,7 +742,7 @@ void orc_calibration_update(const orc_world_t* w, const orc_obs_t* obs, orc_stat
     free(d);
 }
 
-/* Sect. 4.5 (practical scheme): S with a^k, c^k; then A and C both with
+/* Sect. 4.6 (order of the blocks): S with a^k, c^k; then A and C both with
  * s^{k+1}, a^k, c^k (the S[AC] variant of eq:precondS(CAG) without G).
  * Robust: the excess attitude noise is re-estimated from the residuals after
  * the source update and used by the A and C weights (Sect. 5.2.5). */

@@ -84,6 +84,19 @@ _sig = {
     "agis_set_excess_noise": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
     "agis_get_excess_noise": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
     "agis_excess_noise_update": ([_ctx_p], ctypes.c_int),
+    "agis_learned_reset": ([_ctx_p], ctypes.c_int),
+    "agis_learned_record": ([_ctx_p], ctypes.c_int),
+    "agis_learned_features": ([_ctx_p, c_i32, c_i64, _vp, _vp, ctypes.c_int], ctypes.c_int),
+    "agis_mlp_init": ([_ctx_p, c_i32, ctypes.c_uint64], ctypes.c_int),
+    "agis_mlp_set_weights": ([_ctx_p, c_i32, c_i64, _vp, ctypes.c_int], ctypes.c_int),
+    "agis_mlp_get_weights": ([_ctx_p, c_i32, c_i64, _vp, ctypes.c_int], ctypes.c_int),
+    "agis_mlp_forward": ([_ctx_p, c_i32, c_i64, _vp, _vp, ctypes.c_int], ctypes.c_int),
+    "agis_mlp_gradient": ([_ctx_p, c_i32, c_i64, _vp, _vp, _vp, P(ctypes.c_float), ctypes.c_int], ctypes.c_int),
+    "agis_mlp_train": ([_ctx_p, c_i32, c_i64, _vp, _vp, ctypes.c_int, c_i32, c_i32, ctypes.c_float, ctypes.c_uint64,
+                        _vp], ctypes.c_int),
+    "agis_chi2": ([_ctx_p, P(c_d)], ctypes.c_int),
+    "agis_learned_apply": ([_ctx_p], ctypes.c_int),
+    "agis_learned_step": ([_ctx_p, P(c_d), P(c_d), P(c_i32)], ctypes.c_int),
 }
 for _name, (_args, _res) in _sig.items():
     _f = getattr(_lib, _name)
@@ -271,6 +284,94 @@ def agis_get_excess_noise(ctx, n, out=None):
 
 def agis_excess_noise_update(ctx):
     _check(_lib.agis_excess_noise_update(ctx), ctx)
+
+
+MLP_IN = (22, 18)
+MLP_OUT = (4, 4)           # mixing coefficients of the four recorded updates
+MLP_NT = (5, 4)            # target columns: update components
+MLP_NW = tuple(64 * f + 64 + 64 * 64 + 64 + o * 64 + o for f, o in zip(MLP_IN, MLP_OUT))
+
+
+def _fptr(x):
+    return _ptr(x, np.float32)
+
+
+def agis_learned_reset(ctx):
+    _check(_lib.agis_learned_reset(ctx), ctx)
+
+
+def agis_learned_record(ctx):
+    _check(_lib.agis_learned_record(ctx), ctx)
+
+
+def agis_learned_features(ctx, which):
+    sz = agis_problem_size(ctx)
+    n = sz["n_src"] if which == 0 else sz["n_att"]
+    X = np.empty((n, MLP_IN[which]), np.float32)
+    sc = np.empty(n, np.float32)
+    _check(_lib.agis_learned_features(ctx, int(which), n, X.ctypes.data_as(ctypes.c_void_p),
+                                      sc.ctypes.data_as(ctypes.c_void_p), AGIS_HOST), ctx)
+    return X, sc
+
+
+def agis_mlp_init(ctx, which, seed):
+    _check(_lib.agis_mlp_init(ctx, int(which), int(seed)), ctx)
+
+
+def agis_mlp_set_weights(ctx, which, w):
+    p, where, keep = _fptr(w)
+    _check(_lib.agis_mlp_set_weights(ctx, int(which), MLP_NW[which], p, where), ctx)
+
+
+def agis_mlp_get_weights(ctx, which):
+    w = np.empty(MLP_NW[which], np.float32)
+    _check(_lib.agis_mlp_get_weights(ctx, int(which), w.size, w.ctypes.data_as(ctypes.c_void_p), AGIS_HOST), ctx)
+    return w
+
+
+def agis_mlp_forward(ctx, which, X):
+    X = np.ascontiguousarray(X, np.float32)
+    Y = np.empty((X.shape[0], MLP_OUT[which]), np.float32)
+    _check(_lib.agis_mlp_forward(ctx, int(which), X.shape[0], X.ctypes.data_as(ctypes.c_void_p),
+                                 Y.ctypes.data_as(ctypes.c_void_p), AGIS_HOST), ctx)
+    return Y
+
+
+def agis_mlp_gradient(ctx, which, X, T):
+    X = np.ascontiguousarray(X, np.float32)
+    T = np.ascontiguousarray(T, np.float32)
+    g = np.empty(MLP_NW[which], np.float32)
+    loss = ctypes.c_float()
+    _check(_lib.agis_mlp_gradient(ctx, int(which), X.shape[0], X.ctypes.data_as(ctypes.c_void_p),
+                                  T.ctypes.data_as(ctypes.c_void_p), g.ctypes.data_as(ctypes.c_void_p),
+                                  ctypes.byref(loss), AGIS_HOST), ctx)
+    return g, loss.value
+
+
+def agis_mlp_train(ctx, which, X, T, steps, batch, lr, seed=0):
+    X = np.ascontiguousarray(X, np.float32)
+    T = np.ascontiguousarray(T, np.float32)
+    losses = np.empty(max(int(steps), 1), np.float32)
+    _check(_lib.agis_mlp_train(ctx, int(which), X.shape[0], X.ctypes.data_as(ctypes.c_void_p),
+                               T.ctypes.data_as(ctypes.c_void_p), AGIS_HOST, int(steps), int(batch), float(lr),
+                               int(seed), losses.ctypes.data_as(ctypes.c_void_p)), ctx)
+    return losses[:steps]
+
+
+def agis_chi2(ctx):
+    q = c_d()
+    _check(_lib.agis_chi2(ctx, ctypes.byref(q)), ctx)
+    return q.value
+
+
+def agis_learned_apply(ctx):
+    _check(_lib.agis_learned_apply(ctx), ctx)
+
+
+def agis_learned_step(ctx):
+    qp, qc, acc = c_d(), c_d(), c_i32()
+    _check(_lib.agis_learned_step(ctx, ctypes.byref(qp), ctypes.byref(qc), ctypes.byref(acc)), ctx)
+    return dict(q_plain=qp.value, q_candidate=qc.value, accepted=bool(acc.value))
 
 
 def agis_problem_size(ctx):

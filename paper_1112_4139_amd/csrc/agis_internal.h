@@ -106,6 +106,30 @@ struct agis_ctx {
     double* vs = nullptr;                // [n_src]
     double* rcol = nullptr;              // [7][n_obs]
 
+    // learned extrapolation: update histories (rings of four), MLP weights
+    // (FP32 master, BF16-rounded copy, Adam moments, gradient + loss) for
+    // the source [0] and attitude-coefficient [1] networks, work buffers
+    double* lh_anchor_s = nullptr;       // [n_src][5]
+    double* lh_ring_s = nullptr;         // [4][n_src][5]
+    double* lh_anchor_a = nullptr;       // [N][4]
+    double* lh_ring_a = nullptr;         // [4][N][4]
+    int lh_count = 0;
+    float* mlp_w[2] = {nullptr, nullptr};
+    float* mlp_wb[2] = {nullptr, nullptr};
+    float* mlp_m1[2] = {nullptr, nullptr};
+    float* mlp_m2[2] = {nullptr, nullptr};
+    float* mlp_g[2] = {nullptr, nullptr};
+    int mlp_t[2] = {0, 0};
+    float* lf_X[2] = {nullptr, nullptr};
+    float* lf_scale[2] = {nullptr, nullptr};
+    float* lf_Y[2] = {nullptr, nullptr};
+    double* bk_s[2] = {};                // state backups of the gated learned step
+    double* bk_a[2] = {};
+    double* bk_c[2] = {};
+    double* bk_e[2] = {};
+    double* chi2_part = nullptr;         // [ceil(K / 64)]
+    double* chi2_out = nullptr;          // [2]
+
     // lanes per source in the S block
     int s_group = 16;
 
@@ -124,6 +148,23 @@ int build_store(agis_ctx* ctx, const agis_obs_soa_t* obs, int where);
 // kernels.hip
 void launch_prep_sources(agis_ctx* ctx);
 void launch_source_update(agis_ctx* ctx);
+// learned.hip
+int mlp_num_weights(int which);
+int mlp_num_inputs(int which);
+int mlp_num_outputs(int which);
+int mlp_num_targets(int which);
+void launch_hist_record(agis_ctx* ctx, int slot);
+void launch_hist_anchor(agis_ctx* ctx);
+void launch_features(agis_ctx* ctx, int which, float* X, float* scale);
+void launch_mlp_forward(agis_ctx* ctx, int which, int64_t n, const float* X, float* Y);
+void launch_mlp_grad(agis_ctx* ctx, int which, int64_t nb, const int64_t* idx, const float* X, const float* T,
+                     float* part);
+void launch_batch_idx(agis_ctx* ctx, int64_t nb, int64_t n, uint64_t seed, uint64_t step, int64_t* idx);
+void launch_adam(agis_ctx* ctx, int which, float lr, int t);
+void launch_round_weights(agis_ctx* ctx, int which);
+void launch_apply_candidate(agis_ctx* ctx, const float* Cs, const float* Ca);
+void launch_copy(agis_ctx* ctx, int64_t n, const double* src, double* dst);
+void launch_chi2(agis_ctx* ctx, double* part, double* out);
 // robust.hip
 void launch_source_update_robust(agis_ctx* ctx);
 void launch_excess_noise(agis_ctx* ctx);

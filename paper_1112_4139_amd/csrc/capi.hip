@@ -96,6 +96,24 @@ static void free_store(agis_ctx* ctx) {
     dfree(ctx->dc);
     dfree(ctx->vs);
     dfree(ctx->rcol);
+    dfree(ctx->lh_anchor_s);
+    dfree(ctx->lh_ring_s);
+    dfree(ctx->lh_anchor_a);
+    dfree(ctx->lh_ring_a);
+    for (int w = 0; w < 2; ++w) {
+        dfree(ctx->lf_X[w]);
+        dfree(ctx->lf_scale[w]);
+        dfree(ctx->lf_Y[w]);
+    }
+    for (int k = 0; k < 2; ++k) {
+        dfree(ctx->bk_s[k]);
+        dfree(ctx->bk_a[k]);
+        dfree(ctx->bk_c[k]);
+        dfree(ctx->bk_e[k]);
+    }
+    dfree(ctx->chi2_part);
+    dfree(ctx->chi2_out);
+    ctx->lh_count = 0;
     ctx->loaded = false;
     ctx->have_ref = false;
 }
@@ -285,6 +303,21 @@ extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
     if ((rc = dalloc(ctx, &ctx->red, ctx->red_len, "reduction scratch")) != AGIS_OK) return fail(rc);
     if ((rc = dalloc(ctx, &ctx->eo, 8, "frame parameters")) != AGIS_OK) return fail(rc);
     if ((rc = dalloc(ctx, &ctx->stat, 64, "statistics")) != AGIS_OK) return fail(rc);
+    for (int w = 0; w < 2; ++w) {
+        const int nw = mlp_num_weights(w);
+        if ((rc = dalloc(ctx, &ctx->mlp_w[w], nw, "mlp weights")) != AGIS_OK) return fail(rc);
+        if ((rc = dalloc(ctx, &ctx->mlp_wb[w], nw, "mlp weights")) != AGIS_OK) return fail(rc);
+        if ((rc = dalloc(ctx, &ctx->mlp_m1[w], nw, "mlp moments")) != AGIS_OK) return fail(rc);
+        if ((rc = dalloc(ctx, &ctx->mlp_m2[w], nw, "mlp moments")) != AGIS_OK) return fail(rc);
+        if ((rc = dalloc(ctx, &ctx->mlp_g[w], nw + 1, "mlp gradient")) != AGIS_OK) return fail(rc);
+        if (hipMemset(ctx->mlp_w[w], 0, nw * sizeof(float)) != hipSuccess ||
+            hipMemset(ctx->mlp_wb[w], 0, nw * sizeof(float)) != hipSuccess ||
+            hipMemset(ctx->mlp_m1[w], 0, nw * sizeof(float)) != hipSuccess ||
+            hipMemset(ctx->mlp_m2[w], 0, nw * sizeof(float)) != hipSuccess) {
+            ctx->err = "initial copies failed";
+            return fail(AGIS_E_DEVICE);
+        }
+    }
     if (ctx->n_buckets > 0) {
         if ((rc = dalloc(ctx, &ctx->eps_a2, ctx->n_buckets, "excess attitude noise")) != AGIS_OK) return fail(rc);
         const std::vector<double> e0(ctx->n_buckets, cfg->eps_a_init * cfg->eps_a_init);
@@ -333,6 +366,13 @@ extern "C" void agis_destroy(agis_ctx_t* ctx) {
     dfree(ctx->eo);
     dfree(ctx->stat);
     dfree(ctx->eps_a2);
+    for (int w = 0; w < 2; ++w) {
+        dfree(ctx->mlp_w[w]);
+        dfree(ctx->mlp_wb[w]);
+        dfree(ctx->mlp_m1[w]);
+        dfree(ctx->mlp_m2[w]);
+        dfree(ctx->mlp_g[w]);
+    }
     for (int e = 0; e < 10; ++e) {
         if (ctx->tm.ev[e][0]) (void)hipEventDestroy(ctx->tm.ev[e][0]);
         if (ctx->tm.ev[e][1]) (void)hipEventDestroy(ctx->tm.ev[e][1]);
@@ -632,39 +672,46 @@ extern "C" int agis_frame_apply(agis_ctx_t* ctx, const double eps_omega[6]) {
     return AGIS_OK;
 }
 
+// One S[AC] iteration followed by the frame rotation (Sect. 4.6, 6.1);
+// st (may be null) receives the block statistics.
+static int iterate_once(agis_ctx* ctx, agis_iter_stats_t* st) {
+    tstart(ctx, T_ITER);
+    int rc = run_source(ctx);
+    if (rc) return rc;
+    if (st && (rc = stats_s(ctx, &st->s))) return rc;
+    // robust: eps_a from the residuals after the source update (Sect. 5.2.5)
+    rc = run_ac(ctx, true, true, true);
+    if (rc) return rc;
+    if (st && (rc = stats_a(ctx, &st->a))) return rc;
+    if (st && (rc = stats_c(ctx, &st->c))) return rc;
+    if (ctx->have_ref) {
+        tstart(ctx, T_FRAME);
+        launch_frame_fit(ctx);
+        launch_frame_apply(ctx);
+        HIPCHK(hipGetLastError());
+        tstop(ctx, T_FRAME);
+    }
+    tstop(ctx, T_ITER);
+    if (st) {
+        if (ctx->have_ref) {
+            HIPCHK(hipMemcpyAsync(st->eps_omega, ctx->eo, 6 * sizeof(double), hipMemcpyDeviceToHost,
+                                  ctx->stream));
+        } else {
+            std::memset(st->eps_omega, 0, sizeof st->eps_omega);
+        }
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        st->ms = tget(ctx, T_ITER);
+    }
+    return AGIS_OK;
+}
+
 extern "C" int agis_iterate(agis_ctx_t* ctx, int32_t n_iter, agis_iter_stats_t* per_iter) {
     CHECK_CTX();
     REQUIRE_LOADED();
     if (n_iter < 0) return set_error(ctx, AGIS_E_INVALID_ARG, "n_iter < 0");
     for (int32_t it = 0; it < n_iter; ++it) {
-        agis_iter_stats_t* st = per_iter ? per_iter + it : nullptr;
-        tstart(ctx, T_ITER);
-        int rc = run_source(ctx);
+        int rc = iterate_once(ctx, per_iter ? per_iter + it : nullptr);
         if (rc) return rc;
-        if (st && (rc = stats_s(ctx, &st->s))) return rc;
-        // robust: eps_a from the residuals after the source update (Sect. 5.2.5)
-        rc = run_ac(ctx, true, true, true);
-        if (rc) return rc;
-        if (st && (rc = stats_a(ctx, &st->a))) return rc;
-        if (st && (rc = stats_c(ctx, &st->c))) return rc;
-        if (ctx->have_ref) {
-            tstart(ctx, T_FRAME);
-            launch_frame_fit(ctx);
-            launch_frame_apply(ctx);
-            HIPCHK(hipGetLastError());
-            tstop(ctx, T_FRAME);
-        }
-        tstop(ctx, T_ITER);
-        if (st) {
-            if (ctx->have_ref) {
-                HIPCHK(hipMemcpyAsync(st->eps_omega, ctx->eo, 6 * sizeof(double), hipMemcpyDeviceToHost,
-                                      ctx->stream));
-            } else {
-                std::memset(st->eps_omega, 0, sizeof st->eps_omega);
-            }
-            HIPCHK(hipStreamSynchronize(ctx->stream));
-            st->ms = tget(ctx, T_ITER);
-        }
     }
     HIPCHK(hipStreamSynchronize(ctx->stream));
     ctx->last_ms[0] = tget(ctx, T_S);
@@ -698,6 +745,329 @@ extern "C" int agis_excess_noise_update(agis_ctx_t* ctx) {
     launch_excess_noise(ctx);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    return AGIS_OK;
+}
+
+
+// --------------------------------------------------- learned extrapolation
+static int learned_alloc(agis_ctx* ctx) {
+    if (ctx->lh_ring_s) return AGIS_OK;
+    const int64_t ns = std::max<int64_t>(ctx->n_src, 1), na = std::max<int64_t>(ctx->N, 1);
+    ALLOC(ctx->lh_anchor_s, 5 * ns, "history anchor");
+    ALLOC(ctx->lh_ring_s, 4 * 5 * ns, "update history");
+    ALLOC(ctx->lh_anchor_a, 4 * na, "history anchor");
+    ALLOC(ctx->lh_ring_a, 4 * 4 * na, "update history");
+    for (int w = 0; w < 2; ++w) {
+        const int64_t n = w == 0 ? ns : na;
+        ALLOC(ctx->lf_X[w], n * mlp_num_inputs(w), "features");
+        ALLOC(ctx->lf_scale[w], n, "feature scales");
+        ALLOC(ctx->lf_Y[w], n * mlp_num_outputs(w), "mlp outputs");
+    }
+    for (int k = 0; k < 2; ++k) {
+        ALLOC(ctx->bk_s[k], 5 * ns, "candidate backup");
+        ALLOC(ctx->bk_a[k], 4 * na, "candidate backup");
+        ALLOC(ctx->bk_c[k], std::max<int64_t>(ctx->n_cells, 1), "candidate backup");
+        ALLOC(ctx->bk_e[k], std::max<int64_t>(ctx->n_buckets, 1), "candidate backup");
+    }
+    ALLOC(ctx->chi2_part, std::max<int64_t>((ctx->K + 63) / 64, 1), "chi2 partials");
+    ALLOC(ctx->chi2_out, 2, "chi2");
+    return AGIS_OK;
+}
+
+static int check_which(agis_ctx* ctx, int32_t which) {
+    if (which != 0 && which != 1) return set_error(ctx, AGIS_E_INVALID_ARG, "which must be 0 (sources) or 1 (knots)");
+    return AGIS_OK;
+}
+
+extern "C" int agis_learned_reset(agis_ctx_t* ctx) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    int rc = learned_alloc(ctx);
+    if (rc) return rc;
+    launch_hist_anchor(ctx);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->lh_count = 0;
+    return AGIS_OK;
+}
+
+extern "C" int agis_learned_record(agis_ctx_t* ctx) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    if (!ctx->lh_ring_s) return set_error(ctx, AGIS_E_STATE, "agis_learned_reset first");
+    launch_hist_record(ctx, ctx->lh_count % 4);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ++ctx->lh_count;
+    return AGIS_OK;
+}
+
+extern "C" int agis_learned_features(agis_ctx_t* ctx, int32_t which, int64_t n, float* X, float* scale, int where) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    int rc = check_which(ctx, which);
+    if (rc) return rc;
+    if (ctx->lh_count < 4) return set_error(ctx, AGIS_E_STATE, "fewer than four recorded updates");
+    const int64_t nu = which == 0 ? ctx->n_src : ctx->N;
+    if (n != nu || !X || !scale) return set_error(ctx, AGIS_E_SHAPE, "unit count mismatch");
+    launch_features(ctx, which, ctx->lf_X[which], ctx->lf_scale[which]);
+    HIPCHK(hipGetLastError());
+    rc = copy_out(ctx, X, ctx->lf_X[which], n * mlp_num_inputs(which) * sizeof(float), where);
+    if (rc) return rc;
+    return copy_out(ctx, scale, ctx->lf_scale[which], n * sizeof(float), where);
+}
+
+extern "C" int agis_mlp_init(agis_ctx_t* ctx, int32_t which, uint64_t seed) {
+    CHECK_CTX();
+    int rc = check_which(ctx, which);
+    if (rc) return rc;
+    const int F = mlp_num_inputs(which), O = mlp_num_outputs(which), H = 64;
+    const int nw = mlp_num_weights(which);
+    std::vector<float> w(nw, 0.0f);
+    // uniform +-sqrt(6 / (fan_in + fan_out)) weights from a SplitMix64
+    // stream, zero biases
+    uint64_t st = seed;
+    auto next = [&]() {
+        uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return (double)((z ^ (z >> 31)) >> 11) * (1.0 / 9007199254740992.0);
+    };
+    auto fill = [&](int off, int rows, int cols) {
+        const double a = std::sqrt(6.0 / (rows + cols));
+        for (int e = 0; e < rows * cols; ++e) w[off + e] = (float)((2.0 * next() - 1.0) * a);
+    };
+    fill(0, H, F);
+    fill(H * F + H, H, H);
+    fill(H * F + H + H * H + H, O, H);
+    HIPCHK(hipMemcpy(ctx->mlp_w[which], w.data(), nw * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(ctx->mlp_m1[which], 0, nw * sizeof(float)));
+    HIPCHK(hipMemset(ctx->mlp_m2[which], 0, nw * sizeof(float)));
+    ctx->mlp_t[which] = 0;
+    launch_round_weights(ctx, which);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return AGIS_OK;
+}
+
+extern "C" int agis_mlp_set_weights(agis_ctx_t* ctx, int32_t which, int64_t n, const float* w, int where) {
+    CHECK_CTX();
+    int rc = check_which(ctx, which);
+    if (rc) return rc;
+    if (n != mlp_num_weights(which) || !w) return set_error(ctx, AGIS_E_SHAPE, "weight count mismatch");
+    rc = copy_in(ctx, ctx->mlp_w[which], w, n * sizeof(float), where);
+    if (rc) return rc;
+    HIPCHK(hipMemsetAsync(ctx->mlp_m1[which], 0, n * sizeof(float), ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->mlp_m2[which], 0, n * sizeof(float), ctx->stream));
+    ctx->mlp_t[which] = 0;
+    launch_round_weights(ctx, which);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return AGIS_OK;
+}
+
+extern "C" int agis_mlp_get_weights(agis_ctx_t* ctx, int32_t which, int64_t n, float* w, int where) {
+    CHECK_CTX();
+    int rc = check_which(ctx, which);
+    if (rc) return rc;
+    if (n != mlp_num_weights(which) || !w) return set_error(ctx, AGIS_E_SHAPE, "weight count mismatch");
+    return copy_out(ctx, w, ctx->mlp_w[which], n * sizeof(float), where);
+}
+
+// device copies of caller arrays (host) or the caller's device pointers
+struct DevIn {
+    std::vector<void*> own;
+    ~DevIn() {
+        for (void* p : own) (void)hipFree(p);
+    }
+};
+
+static int dev_input(agis_ctx* ctx, DevIn& keep, const float* src, int64_t n, int where, const float** out) {
+    if (where == AGIS_DEVICE) {
+        *out = src;
+        return AGIS_OK;
+    }
+    float* d = nullptr;
+    int rc = dalloc(ctx, &d, (size_t)std::max<int64_t>(n, 1), "staging");
+    if (rc) return rc;
+    keep.own.push_back(d);
+    HIPCHK(hipMemcpyAsync(d, src, n * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+    *out = d;
+    return AGIS_OK;
+}
+
+extern "C" int agis_mlp_forward(agis_ctx_t* ctx, int32_t which, int64_t n, const float* X, float* Y, int where) {
+    CHECK_CTX();
+    int rc = check_which(ctx, which);
+    if (rc) return rc;
+    if (n < 0 || (n > 0 && (!X || !Y))) return set_error(ctx, AGIS_E_INVALID_ARG, "bad arrays");
+    if (where != AGIS_HOST && where != AGIS_DEVICE) return set_error(ctx, AGIS_E_INVALID_ARG, "bad 'where'");
+    DevIn keep;
+    const float* dX = nullptr;
+    if ((rc = dev_input(ctx, keep, X, n * mlp_num_inputs(which), where, &dX))) return rc;
+    float* dY = Y;
+    if (where == AGIS_HOST) {
+        if ((rc = dalloc(ctx, &dY, (size_t)std::max<int64_t>(n * mlp_num_outputs(which), 1), "staging"))) return rc;
+        keep.own.push_back(dY);
+    }
+    launch_mlp_forward(ctx, which, n, dX, dY);
+    HIPCHK(hipGetLastError());
+    if (where == AGIS_HOST)
+        HIPCHK(hipMemcpyAsync(Y, dY, n * mlp_num_outputs(which) * sizeof(float), hipMemcpyDeviceToHost,
+                              ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return AGIS_OK;
+}
+
+extern "C" int agis_mlp_gradient(agis_ctx_t* ctx, int32_t which, int64_t n, const float* X, const float* T,
+                                 float* grad, float* loss, int where) {
+    CHECK_CTX();
+    int rc = check_which(ctx, which);
+    if (rc) return rc;
+    if (n <= 0 || !X || !T || !grad || !loss) return set_error(ctx, AGIS_E_INVALID_ARG, "bad arrays");
+    if (where != AGIS_HOST && where != AGIS_DEVICE) return set_error(ctx, AGIS_E_INVALID_ARG, "bad 'where'");
+    DevIn keep;
+    const float *dX = nullptr, *dT = nullptr;
+    if ((rc = dev_input(ctx, keep, X, n * mlp_num_inputs(which), where, &dX))) return rc;
+    if ((rc = dev_input(ctx, keep, T, n * mlp_num_targets(which), where, &dT))) return rc;
+    const int nw = mlp_num_weights(which);
+    float* part = nullptr;
+    if ((rc = dalloc(ctx, &part, (size_t)((n + 127) / 128) * (nw + 1), "gradient partials"))) return rc;
+    keep.own.push_back(part);
+    launch_mlp_grad(ctx, which, n, nullptr, dX, dT, part);
+    HIPCHK(hipGetLastError());
+    std::vector<float> g(nw + 1);
+    HIPCHK(hipMemcpyAsync(g.data(), ctx->mlp_g[which], (nw + 1) * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (where == AGIS_HOST) {
+        std::memcpy(grad, g.data(), nw * sizeof(float));
+    } else {
+        HIPCHK(hipMemcpy(grad, ctx->mlp_g[which], nw * sizeof(float), hipMemcpyDeviceToDevice));
+    }
+    *loss = g[nw];
+    return AGIS_OK;
+}
+
+extern "C" int agis_mlp_train(agis_ctx_t* ctx, int32_t which, int64_t n, const float* X, const float* T, int where,
+                              int32_t steps, int32_t batch, float lr, uint64_t seed, float* loss_out) {
+    CHECK_CTX();
+    int rc = check_which(ctx, which);
+    if (rc) return rc;
+    if (n <= 0 || !X || !T || steps < 0 || batch < 1 || !(lr > 0.0f))
+        return set_error(ctx, AGIS_E_INVALID_ARG, "bad training arguments");
+    if (where != AGIS_HOST && where != AGIS_DEVICE) return set_error(ctx, AGIS_E_INVALID_ARG, "bad 'where'");
+    DevIn keep;
+    const float *dX = nullptr, *dT = nullptr;
+    if ((rc = dev_input(ctx, keep, X, n * mlp_num_inputs(which), where, &dX))) return rc;
+    if ((rc = dev_input(ctx, keep, T, n * mlp_num_targets(which), where, &dT))) return rc;
+    const int nw = mlp_num_weights(which);
+    float* part = nullptr;
+    int64_t* idx = nullptr;
+    if ((rc = dalloc(ctx, &part, (size_t)((batch + 127) / 128) * (nw + 1), "gradient partials"))) return rc;
+    keep.own.push_back(part);
+    if ((rc = dalloc(ctx, &idx, (size_t)batch, "minibatch"))) return rc;
+    keep.own.push_back(idx);
+    for (int32_t it = 0; it < steps; ++it) {
+        launch_batch_idx(ctx, batch, n, seed, (uint64_t)(ctx->mlp_t[which] + 1), idx);
+        launch_mlp_grad(ctx, which, batch, idx, dX, dT, part);
+        ++ctx->mlp_t[which];
+        launch_adam(ctx, which, lr, ctx->mlp_t[which]);
+        if (loss_out)
+            HIPCHK(hipMemcpyAsync(loss_out + it, ctx->mlp_g[which] + nw, sizeof(float), hipMemcpyDeviceToHost,
+                                  ctx->stream));
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return AGIS_OK;
+}
+
+extern "C" int agis_chi2(agis_ctx_t* ctx, double* q) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    if (!q) return set_error(ctx, AGIS_E_INVALID_ARG, "null q");
+    int rc = learned_alloc(ctx);
+    if (rc) return rc;
+    launch_chi2(ctx, ctx->chi2_part, ctx->chi2_out);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(q, ctx->chi2_out, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return AGIS_OK;
+}
+
+// Iteration state (sources, attitude, calibration and, when robust, the
+// excess attitude noise) to and from backup slot k.
+static void save_state(agis_ctx* ctx, int k) {
+    launch_copy(ctx, 5 * ctx->n_src, ctx->s, ctx->bk_s[k]);
+    launch_copy(ctx, 4 * ctx->N, ctx->a, ctx->bk_a[k]);
+    launch_copy(ctx, ctx->n_cells, ctx->c, ctx->bk_c[k]);
+    if (ctx->cfg.robust) launch_copy(ctx, ctx->n_buckets, ctx->eps_a2, ctx->bk_e[k]);
+}
+
+static void restore_state(agis_ctx* ctx, int k) {
+    launch_copy(ctx, 5 * ctx->n_src, ctx->bk_s[k], ctx->s);
+    launch_copy(ctx, 4 * ctx->N, ctx->bk_a[k], ctx->a);
+    launch_copy(ctx, ctx->n_cells, ctx->bk_c[k], ctx->c);
+    if (ctx->cfg.robust) launch_copy(ctx, ctx->n_buckets, ctx->bk_e[k], ctx->eps_a2);
+    launch_prep_sources(ctx);
+}
+
+// x <- x + sum_k c_k u_k, c = MLP(features), for sources and attitude
+// coefficients.
+static void apply_candidate(agis_ctx* ctx) {
+    for (int w = 0; w < 2; ++w) {
+        launch_features(ctx, w, ctx->lf_X[w], ctx->lf_scale[w]);
+        launch_mlp_forward(ctx, w, w == 0 ? ctx->n_src : ctx->N, ctx->lf_X[w], ctx->lf_Y[w]);
+    }
+    launch_apply_candidate(ctx, ctx->lf_Y[0], ctx->lf_Y[1]);
+    launch_prep_sources(ctx);
+}
+
+extern "C" int agis_learned_apply(agis_ctx_t* ctx) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    if (!ctx->lh_ring_s || ctx->lh_count < 4) return set_error(ctx, AGIS_E_STATE, "fewer than four recorded updates");
+    apply_candidate(ctx);
+    launch_hist_anchor(ctx);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->lh_count = 0;
+    return AGIS_OK;
+}
+
+extern "C" int agis_learned_step(agis_ctx_t* ctx, double* q_plain, double* q_cand, int32_t* accepted) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    if (!ctx->lh_ring_s || ctx->lh_count < 4) return set_error(ctx, AGIS_E_STATE, "fewer than four recorded updates");
+    // plain: x0 -> x1 by one iteration
+    save_state(ctx, 0);
+    int rc = iterate_once(ctx, nullptr);
+    if (rc) return rc;
+    launch_chi2(ctx, ctx->chi2_part, ctx->chi2_out);
+    save_state(ctx, 1);
+    // candidate: x0 + s y, then one iteration
+    restore_state(ctx, 0);
+    apply_candidate(ctx);
+    if ((rc = iterate_once(ctx, nullptr))) return rc;
+    launch_chi2(ctx, ctx->chi2_part, ctx->chi2_out + 1);
+    HIPCHK(hipGetLastError());
+    double q[2];
+    HIPCHK(hipMemcpyAsync(q, ctx->chi2_out, sizeof q, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    const bool acc = std::isfinite(q[1]) && q[1] < q[0];
+    if (acc) {
+        // the trajectory restarts from the candidate: new history
+        launch_hist_anchor(ctx);
+        ctx->lh_count = 0;
+    } else {
+        // the plain trajectory goes on from x1 (the history keeps its
+        // anchor, so the next record spans one iteration more)
+        restore_state(ctx, 1);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (q_plain) *q_plain = q[0];
+    if (q_cand) *q_cand = q[1];
+    if (accepted) *accepted = acc ? 1 : 0;
     return AGIS_OK;
 }
 

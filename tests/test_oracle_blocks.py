@@ -211,7 +211,7 @@ def test_frame_rotator_round_trip_and_null_space(tiny_world, tiny_eta, oracle_li
 
 
 def test_first_iteration_independent_of_source_start(tiny_world, tiny_eta, oracle_lib):
-    """Footnote to Sect. 4.4: with the S block first, x^(1) does not depend
+    """Footnote in Sect. 4.5: with the S block first, x^(1) does not depend
     on s^(0) (to second order in the start offsets)."""
     w = tiny_world
     pa = oracle_lib.problem_from_world(w, tiny_eta, state="start")
