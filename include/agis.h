@@ -250,7 +250,8 @@ int agis_excess_noise_update(agis_ctx_t* ctx);
  * use them rounded to BF16 with FP32 accumulation.  Training targets T have
  * NC = 5 / 4 columns: the displacement to learn in units of s.
  */
-/* Start a history: the current parameters become the anchor. */
+/* Start a history: the current parameters (sources, attitude, calibration)
+ * become the anchor. */
 int agis_learned_reset(agis_ctx_t* ctx);
 /* Record (current - anchor) as the newest update; the current parameters
  * become the anchor.  A "record" may follow any number of iterations. */
@@ -290,6 +291,22 @@ int agis_learned_apply(agis_ctx_t* ctx);
  * excess attitude noise are saved and restored on the device.
  * AGIS_E_STATE with fewer than four records. */
 int agis_learned_step(agis_ctx_t* ctx, double* q_plain, double* q_cand, int32_t* accepted);
+
+/*
+ * Accelerated simple iteration (Sect. 4.7): when successive updates shrink
+ * by a nearly constant ratio lambda, the updates still to come sum to
+ * lambda / (1 - lambda) times the newest one.  Over the recorded history
+ * (agis_learned_reset / agis_learned_record, a record every m iterations),
+ * lambda is the least-squares ratio sum u1 u2 / sum u2^2 of the newest (u1)
+ * to the previous (u2) parallax update over the sources 0, stride,
+ * 2 stride, ... (parallaxes do not change with the frame orientation),
+ * clamped to [0, lambda_max]; sources, attitude and calibration then move
+ * by f = lambda / (1 - lambda) times their newest update (alpha by the
+ * update in alpha* over cos delta) and a new history starts.  No step
+ * (f = 0, history kept) when lambda <= 0.  stride >= 1, 0 <= lambda_max < 1
+ * (else AGIS_E_INVALID_ARG); AGIS_E_STATE with fewer than two records.
+ */
+int agis_asi_step(agis_ctx_t* ctx, int32_t stride, double lambda_max, double* lambda, double* factor);
 
 #ifdef __cplusplus
 }

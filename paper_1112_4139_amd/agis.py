@@ -96,6 +96,7 @@ _sig = {
                         _vp], ctypes.c_int),
     "agis_chi2": ([_ctx_p, P(c_d)], ctypes.c_int),
     "agis_learned_apply": ([_ctx_p], ctypes.c_int),
+    "agis_asi_step": ([_ctx_p, ctypes.c_int32, c_d, P(c_d), P(c_d)], ctypes.c_int),
     "agis_learned_step": ([_ctx_p, P(c_d), P(c_d), P(c_i32)], ctypes.c_int),
 }
 for _name, (_args, _res) in _sig.items():
@@ -366,6 +367,12 @@ def agis_chi2(ctx):
 
 def agis_learned_apply(ctx):
     _check(_lib.agis_learned_apply(ctx), ctx)
+
+
+def agis_asi_step(ctx, stride=1, lambda_max=0.99):
+    lam, f = c_d(), c_d()
+    _check(_lib.agis_asi_step(ctx, int(stride), float(lambda_max), ctypes.byref(lam), ctypes.byref(f)), ctx)
+    return dict(lam=lam.value, factor=f.value)
 
 
 def agis_learned_step(ctx):

@@ -113,6 +113,10 @@ struct agis_ctx {
     double* lh_ring_s = nullptr;         // [4][n_src][5]
     double* lh_anchor_a = nullptr;       // [N][4]
     double* lh_ring_a = nullptr;         // [4][N][4]
+    double* lh_anchor_c = nullptr;       // [n_cells]
+    double* lh_ring_c = nullptr;         // [4][n_cells]
+    double* asi_part = nullptr;          // accelerated iteration: block sums, result
+    double* asi_out = nullptr;
     int lh_count = 0;
     float* mlp_w[2] = {nullptr, nullptr};
     float* mlp_wb[2] = {nullptr, nullptr};
@@ -155,6 +159,8 @@ int mlp_num_outputs(int which);
 int mlp_num_targets(int which);
 void launch_hist_record(agis_ctx* ctx, int slot);
 void launch_hist_anchor(agis_ctx* ctx);
+void launch_asi_sums(agis_ctx* ctx, int stride, double* part, double* out);
+void launch_asi_apply(agis_ctx* ctx, double f);
 void launch_features(agis_ctx* ctx, int which, float* X, float* scale);
 void launch_mlp_forward(agis_ctx* ctx, int which, int64_t n, const float* X, float* Y);
 void launch_mlp_grad(agis_ctx* ctx, int which, int64_t nb, const int64_t* idx, const float* X, const float* T,

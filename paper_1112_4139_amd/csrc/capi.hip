@@ -100,6 +100,10 @@ static void free_store(agis_ctx* ctx) {
     dfree(ctx->lh_ring_s);
     dfree(ctx->lh_anchor_a);
     dfree(ctx->lh_ring_a);
+    dfree(ctx->lh_anchor_c);
+    dfree(ctx->lh_ring_c);
+    dfree(ctx->asi_part);
+    dfree(ctx->asi_out);
     for (int w = 0; w < 2; ++w) {
         dfree(ctx->lf_X[w]);
         dfree(ctx->lf_scale[w]);
@@ -757,6 +761,11 @@ static int learned_alloc(agis_ctx* ctx) {
     ALLOC(ctx->lh_ring_s, 4 * 5 * ns, "update history");
     ALLOC(ctx->lh_anchor_a, 4 * na, "history anchor");
     ALLOC(ctx->lh_ring_a, 4 * 4 * na, "update history");
+    const int64_t nc = std::max<int64_t>(ctx->n_cells, 1);
+    ALLOC(ctx->lh_anchor_c, nc, "history anchor");
+    ALLOC(ctx->lh_ring_c, 4 * nc, "update history");
+    ALLOC(ctx->asi_part, 2 * ((ns + 255) / 256), "accelerated iteration sums");
+    ALLOC(ctx->asi_out, 2, "accelerated iteration sums");
     for (int w = 0; w < 2; ++w) {
         const int64_t n = w == 0 ? ns : na;
         ALLOC(ctx->lf_X[w], n * mlp_num_inputs(w), "features");
@@ -1031,6 +1040,35 @@ extern "C" int agis_learned_apply(agis_ctx_t* ctx) {
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(ctx->stream));
     ctx->lh_count = 0;
+    return AGIS_OK;
+}
+
+extern "C" int agis_asi_step(agis_ctx_t* ctx, int32_t stride, double lambda_max, double* lambda, double* factor) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    if (stride < 1 || !(lambda_max >= 0.0 && lambda_max < 1.0))
+        return set_error(ctx, AGIS_E_INVALID_ARG, "stride >= 1 and 0 <= lambda_max < 1");
+    if (!ctx->lh_ring_s || ctx->lh_count < 2) return set_error(ctx, AGIS_E_STATE, "fewer than two recorded updates");
+    launch_asi_sums(ctx, stride, ctx->asi_part, ctx->asi_out);
+    HIPCHK(hipGetLastError());
+    double sums[2];
+    HIPCHK(hipMemcpyAsync(sums, ctx->asi_out, sizeof sums, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    // least-squares ratio of the newest to the previous parallax updates
+    double lam = sums[1] > 0.0 ? sums[0] / sums[1] : 0.0;
+    if (!std::isfinite(lam) || lam < 0.0) lam = 0.0;
+    lam = std::min(lam, lambda_max);
+    const double f = lam / (1.0 - lam);
+    if (f > 0.0) {
+        launch_asi_apply(ctx, f);
+        launch_prep_sources(ctx);
+        launch_hist_anchor(ctx);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        ctx->lh_count = 0;
+    }
+    if (lambda) *lambda = lam;
+    if (factor) *factor = f;
     return AGIS_OK;
 }
 

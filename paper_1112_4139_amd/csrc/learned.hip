@@ -353,6 +353,67 @@ __global__ void k_apply_att(int64_t n, const float* __restrict__ C, const double
     }
 }
 
+// ------------------------------------------------- accelerated iteration
+// Sums over the sources i = 0, stride, 2 stride, ... of u1 u2 and u2 u2,
+// u1 and u2 the parallax updates of the newest and the previous record;
+// block b takes subset entries [256 b, 256 (b + 1)) and writes part[2 b],
+// part[2 b + 1] (fixed order: wave sums, then the four waves in order).
+__global__ __launch_bounds__(256) void k_asi_partial(int64_t n, int stride, const double* __restrict__ ring, int count,
+                                                     double* __restrict__ part) {
+    __shared__ double red[2][4];
+    const int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x;
+    const int64_t i = e * stride;
+    double xy = 0.0, yy = 0.0;
+    if (i < n) {
+        const double u1 = ring[(int64_t)ring_slot(count, 0) * 5 * n + 5 * i + 2];
+        const double u2 = ring[(int64_t)ring_slot(count, 1) * 5 * n + 5 * i + 2];
+        xy = u1 * u2;
+        yy = u2 * u2;
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        xy += __shfl_xor(xy, m, 64);
+        yy += __shfl_xor(yy, m, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = xy;
+        red[1][threadIdx.x >> 6] = yy;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+        part[2 * blockIdx.x + 1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+    }
+}
+
+__global__ void k_sum_partial2(int64_t nb, const double* __restrict__ part, double* __restrict__ out) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double a = 0.0, b = 0.0;
+    for (int64_t q = 0; q < nb; ++q) {
+        a += part[2 * q];
+        b += part[2 * q + 1];
+    }
+    out[0] = a;
+    out[1] = b;
+}
+
+// x <- x + f u1 (u1 the newest recorded update)
+__global__ void k_asi_apply_src(int64_t n, const double* __restrict__ ring, int count, double f,
+                                double* __restrict__ s) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double* u = ring + (int64_t)ring_slot(count, 0) * 5 * n + 5 * i;
+        double* x = s + 5 * i;
+        x[0] += f * u[0] / cos(x[1]);        // d alpha* -> d alpha
+        for (int c = 1; c < 5; ++c) x[c] += f * u[c];
+    }
+}
+
+__global__ void k_asi_apply_vec(int64_t n, const double* __restrict__ ring, int count, double f,
+                                double* __restrict__ v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v[i] += f * ring[(int64_t)ring_slot(count, 0) * n + i];
+}
+
 // sum of W R^2 over the observations of knot intervals [b * 64, (b + 1) * 64)
 __global__ __launch_bounds__(64) void k_chi2_partial(DevConsts k, int64_t K, const int64_t* __restrict__ iv_off,
                                                      const double* __restrict__ ot, const double* __restrict__ oeta,
@@ -408,11 +469,32 @@ void launch_hist_record(agis_ctx* ctx, int slot) {
                                                                         ctx->lh_ring_s, slot);
     k_hist_record_att<<<blocks_for(4 * ctx->N), 256, 0, ctx->stream>>>(4 * ctx->N, ctx->a, ctx->lh_anchor_a,
                                                                         ctx->lh_ring_a, slot);
+    if (ctx->n_cells > 0)
+        k_hist_record_att<<<blocks_for(ctx->n_cells), 256, 0, ctx->stream>>>(ctx->n_cells, ctx->c, ctx->lh_anchor_c,
+                                                                              ctx->lh_ring_c, slot);
 }
 
 void launch_hist_anchor(agis_ctx* ctx) {
     k_copy<<<blocks_for(5 * ctx->n_src), 256, 0, ctx->stream>>>(5 * ctx->n_src, ctx->s, ctx->lh_anchor_s);
     k_copy<<<blocks_for(4 * ctx->N), 256, 0, ctx->stream>>>(4 * ctx->N, ctx->a, ctx->lh_anchor_a);
+    k_copy<<<blocks_for(ctx->n_cells), 256, 0, ctx->stream>>>(ctx->n_cells, ctx->c, ctx->lh_anchor_c);
+}
+
+void launch_asi_sums(agis_ctx* ctx, int stride, double* part, double* out) {
+    const int64_t n_sub = (ctx->n_src + stride - 1) / stride;
+    const int64_t nb = std::max<int64_t>((n_sub + 255) / 256, 1);
+    k_asi_partial<<<(unsigned)nb, 256, 0, ctx->stream>>>(ctx->n_src, stride, ctx->lh_ring_s, ctx->lh_count, part);
+    k_sum_partial2<<<1, 64, 0, ctx->stream>>>(nb, part, out);
+}
+
+void launch_asi_apply(agis_ctx* ctx, double f) {
+    k_asi_apply_src<<<blocks_for(ctx->n_src), 256, 0, ctx->stream>>>(ctx->n_src, ctx->lh_ring_s, ctx->lh_count, f,
+                                                                      ctx->s);
+    k_asi_apply_vec<<<blocks_for(4 * ctx->N), 256, 0, ctx->stream>>>(4 * ctx->N, ctx->lh_ring_a, ctx->lh_count, f,
+                                                                      ctx->a);
+    if (ctx->n_cells > 0)
+        k_asi_apply_vec<<<blocks_for(ctx->n_cells), 256, 0, ctx->stream>>>(ctx->n_cells, ctx->lh_ring_c,
+                                                                            ctx->lh_count, f, ctx->c);
 }
 
 void launch_features(agis_ctx* ctx, int which, float* X, float* scale) {

@@ -119,12 +119,17 @@ def collect(ctx, w, m, n_macro, horizon, every=1):
     return data
 
 
-def solve(ctx, w, m, n_iter, ref, learned, tol=1.0, log=None):
-    """Iterate in blocks of m iterations (plain, or each block followed by the
-    gated learned step once the history holds four records) until the
-    disagreement with ref drops below tol uas; returns the S[AC] iterations
-    (the gate's two included), the wall time of the library calls, the
-    accept/reject counts and the median q_cand / q_plain of the gate."""
+def solve(ctx, w, m, n_iter, ref, mode, tol=1.0, log=None, asi_stride=16, asi_lambda_max=0.99):
+    """Iterate in blocks of m iterations until the disagreement with ref
+    drops below tol uas.  mode "plain": the simple iteration alone; "asi":
+    after each block from the third record of a history on, the accelerated
+    step of Sect. 4.7 (factor lambda / (1 - lambda) on the newest update);
+    "learned": after each block from the fourth record on, the gated learned
+    step.  Returns the S[AC] iterations (the gate's two included), the wall
+    time of the library calls, the accept/reject counts (asi: steps taken
+    and skipped) and the median q_cand / q_plain of the gate, or the median
+    lambda of the accelerated steps."""
+    learned = mode == "learned"
     agis.agis_learned_reset(ctx)
     acc = rej = 0
     it = 0
@@ -139,6 +144,14 @@ def solve(ctx, w, m, n_iter, ref, learned, tol=1.0, log=None):
         agis.agis_learned_record(ctx)
         count += 1
         it += m
+        if mode == "asi" and count >= 3:
+            r = agis.agis_asi_step(ctx, asi_stride, asi_lambda_max)
+            ratios.append(r["lam"])
+            if r["factor"] > 0:
+                acc += 1
+                count = 0
+            else:
+                rej += 1
         if learned and count >= 4:
             r = agis.agis_learned_step(ctx)
             it += 2
@@ -152,11 +165,11 @@ def solve(ctx, w, m, n_iter, ref, learned, tol=1.0, log=None):
         blocks += 1
         dis = disagreement(state(ctx, w), ref)
         if log and blocks % 20 == 0:
-            log(f"{'learned' if learned else 'plain'} it {it}: disagreement {dis:.3f} uas, "
+            log(f"{mode} it {it}: disagreement {dis:.3f} uas, "
                 f"accepted {acc} rejected {rej}")
     return dict(iterations=it if dis <= tol else None, seconds=t_gpu, accepted=acc, rejected=rej,
                 disagreement=dis, chi2=agis.agis_chi2(ctx),
-                median_q_ratio=float(np.median(ratios)) if ratios else None)
+                median_ratio=float(np.median(ratios)) if ratios else None)
 
 
 def main(argv=None):
@@ -173,6 +186,7 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--max-iter", type=int, default=160000)
     ap.add_argument("--tol", type=float, default=1.0)
+    ap.add_argument("--modes", default="plain,asi,learned", help="solves to compare (plain, asi, learned)")
     args = ap.parse_args(argv)
 
     def log(msg):
@@ -217,11 +231,11 @@ def main(argv=None):
     chi2_ref = agis.agis_chi2(ctx)
     agis.agis_destroy(ctx)
     out = {}
-    for mode in ("plain", "learned"):
+    for mode in args.modes.split(","):
         w, ctx = problem(args.world, args.eval_seed)
         for which in (0, 1):
             agis.agis_mlp_set_weights(ctx, which, weights[which])
-        out[mode] = solve(ctx, w, args.m, args.max_iter, ref, mode == "learned", tol=args.tol, log=log)
+        out[mode] = solve(ctx, w, args.m, args.max_iter, ref, mode, tol=args.tol, log=log)
         log(f"{mode}: {out[mode]}")
         agis.agis_destroy(ctx)
     print(json.dumps({"world": args.world, "train_seeds": args.train_seeds, "eval_seed": args.eval_seed,

@@ -257,3 +257,44 @@ def test_linear_extrapolation_is_accepted(agis_mod, tiny):
         assert np.array_equal(x, y)
     agis_mod.agis_destroy(ctx)
     agis_mod.agis_destroy(twin)
+
+
+@pytest.mark.parametrize("stride,lambda_max", [(1, 0.99), (7, 0.99), (3, 0.5)])
+def test_asi_step(agis_mod, tiny, stride, lambda_max):
+    """Accelerated step: lambda is the least-squares ratio of the two newest
+    parallax updates over every stride-th source (clamped), and sources,
+    attitude and calibration move by lambda / (1 - lambda) times their
+    newest update; a new history starts."""
+    w, eta = tiny
+    ctx = _ctx(agis_mod, w, eta)
+    agis_mod.agis_iterate(ctx, 200, stats=False)
+    agis_mod.agis_learned_reset(ctx)
+    prev = _state(agis_mod, ctx, w)
+    ups = []
+    for r in range(3):
+        agis_mod.agis_iterate(ctx, 10, stats=False)
+        agis_mod.agis_learned_record(ctx)
+        cur = _state(agis_mod, ctx, w)
+        d = [cur[0] - prev[0], cur[1] - prev[1], cur[2] - prev[2]]
+        d[0][:, 0] *= np.cos(cur[0][:, 1])
+        ups.append(d)
+        prev = cur
+    u1, u2 = ups[-1][0][::stride, 2], ups[-2][0][::stride, 2]
+    lam = min(max(np.sum(u1 * u2) / np.sum(u2 * u2), 0.0), lambda_max)
+    f = lam / (1 - lam)
+    s0, a0, c0 = prev
+    r = agis_mod.agis_asi_step(ctx, stride, lambda_max)
+    print(r, "host lambda", lam)
+    assert abs(r["lam"] - lam) <= 1e-12 and abs(r["factor"] - f) <= 1e-12 * f
+    assert f > 0
+    s1, a1, c1 = _state(agis_mod, ctx, w)
+    ds = r["factor"] * ups[-1][0]
+    ds[:, 0] /= np.cos(s0[:, 1])
+    assert np.all(np.abs(s1 - (s0 + ds)) <= 2 * np.spacing(np.abs(s0)) + 1e-12 * np.abs(ds))
+    for x1, x0, u in ((a1, a0, ups[-1][1]), (c1, c0, ups[-1][2])):
+        assert np.all(np.abs(x1 - (x0 + r["factor"] * u)) <= 2 * np.spacing(np.abs(x0)) + 1e-12 * np.abs(u) * f)
+    with pytest.raises(RuntimeError):                  # new history: fewer than two records
+        agis_mod.agis_asi_step(ctx, stride, lambda_max)
+    with pytest.raises(RuntimeError):                  # invalid stride
+        agis_mod.agis_asi_step(ctx, 0, 0.9)
+    agis_mod.agis_destroy(ctx)
