@@ -395,7 +395,12 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
 }
 
 // ------------------------------------------------------------ band solve
-constexpr int RING = 8;                 // intervals held in LDS
+// Intervals held in LDS per segment.  The row read at step i (row i + 17)
+// needs the intervals (i+17)/4 - 3 .. (i+17)/4, and interval b + 5 enters at
+// the end of step 4b + 2, after that step's read, into the slot of interval
+// b, which no later row needs; the start needs intervals 0..4.  Five slots
+// keep four segments per block within 18.6 KB of LDS (eight blocks per CU).
+constexpr int RING = 5;
 constexpr int RING_W = IV_SUMS;         // doubles per interval
 
 // Entry (i, kk) (segment-relative scalar indices, i <= kk <= i + 15) of the
@@ -407,7 +412,8 @@ __device__ __forceinline__ double ring_entry(const double (*ring)[RING_W], int64
     const int64_t jlo = bk - 3 > 0 ? bk - 3 : 0;
     const int64_t jhi = bi < nb - 4 ? bi : nb - 4;
     double s = 0.0;
-    for (int64_t j = jlo; j <= jhi; ++j) s += ring[j & (RING - 1)][tri4((int)(bi - j), (int)(bk - j)) * 10 + e];
+    for (int64_t j = jlo, sl = jlo % RING; j <= jhi; ++j, sl = sl + 1 == RING ? 0 : sl + 1)
+        s += ring[sl][tri4((int)(bi - j), (int)(bk - j)) * 10 + e];
     return s;
 }
 
@@ -417,7 +423,8 @@ __device__ __forceinline__ double ring_rhs(const double (*ring)[RING_W], int64_t
     const int64_t jlo = bi - 3 > 0 ? bi - 3 : 0;
     const int64_t jhi = bi < nb - 4 ? bi : nb - 4;
     double s = 0.0;
-    for (int64_t j = jlo; j <= jhi; ++j) s += ring[j & (RING - 1)][100 + (bi - j) * 4 + r];
+    for (int64_t j = jlo, sl = jlo % RING; j <= jhi; ++j, sl = sl + 1 == RING ? 0 : sl + 1)
+        s += ring[sl][100 + (bi - j) * 4 + r];
     return s;
 }
 
@@ -443,7 +450,7 @@ __device__ __forceinline__ void band_trailing(double (&W)[16], double U) {
     }
 }
 
-constexpr int BAND_SEGS = 4;            // segments per wavefront, one per 16-lane row
+constexpr int BAND_SEGS = 4;            // segments per block (one wavefront), one per 16-lane row
 constexpr int PFL = (RING_W + 15) / 16; // doubles per lane to fetch one interval
 
 // Modified band Cholesky of the attitude segments (Algorithms C1-C3 with
@@ -456,7 +463,7 @@ constexpr int PFL = (RING_W + 15) / 16; // doubles per lane to fetch one interva
 // two coefficient blocks ahead).  A zero or negative pivot gives a zero
 // factor row and counts one defect.  C3 then runs back up the segment with
 // x(i+d) in lane d and a row reduction per step.
-__global__ __launch_bounds__(64) void k_band_solve(int64_t nseg, const SegDesc* __restrict__ segs,
+__global__ __launch_bounds__(16 * BAND_SEGS) void k_band_solve(int64_t nseg, const SegDesc* __restrict__ segs,
                                                    const double* __restrict__ iv_sums, double* __restrict__ ufac,
                                                    double* __restrict__ yfac, double* __restrict__ da,
                                                    int32_t* __restrict__ seg_def) {
@@ -537,13 +544,13 @@ __global__ __launch_bounds__(64) void k_band_solve(int64_t nseg, const SegDesc* 
         nR = (d == 15 && r < nu) ? ring_rhs(ring, nb, r) : 0.0;
         if ((i & 3) == 2) {
             // interval b + 5 (first read for row 4b + 20, at step 4b + 3)
-            // enters the ring in the slot of interval b - 3, which no row
-            // after 4b + 3 refers to
+            // enters the ring in the slot of interval b, which no row read
+            // from step 4b + 3 on refers to
             if (b + 5 < n_iv) {
 #pragma unroll
                 for (int u = 0; u < PFL; ++u) {
                     const int e = d + 16 * u;
-                    if (e < RING_W) ring[(b + 5) & (RING - 1)][e] = pfA[u];
+                    if (e < RING_W) ring[(int)(b + 5) % RING][e] = pfA[u];
                 }
             }
 #pragma unroll
@@ -631,7 +638,7 @@ void launch_ac_pass(agis_ctx* ctx) {
 void launch_band_solve(agis_ctx* ctx) {
     const int64_t nseg = (int64_t)ctx->h_segs.size();
     if (nseg == 0) return;
-    k_band_solve<<<(unsigned)((nseg + BAND_SEGS - 1) / BAND_SEGS), 64, 0, ctx->stream>>>(
+    k_band_solve<<<(unsigned)((nseg + BAND_SEGS - 1) / BAND_SEGS), 16 * BAND_SEGS, 0, ctx->stream>>>(
         nseg, ctx->segs, ctx->iv_sums, ctx->ufac, ctx->yfac, ctx->da, ctx->seg_def);
 }
 

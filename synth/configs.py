@@ -41,9 +41,11 @@ WORKLOADS = {
                                   seg_len=240, seg_overlap=12, lambda_reg=1e-2, min_transits=6)),
     "small9": (mini_law, WorldSpec(n_src=3000, years=0.5, knot_dt=1200.0, ccd_per_transit=9,
                                    seg_len=100, seg_overlap=12, lambda_reg=1e-2)),
-    # 1M stars, 1 yr, 9 AF observations per transit (~160M obs), 30 s knots
+    # 1M stars, 1 yr, 9 AF observations per transit (~160M obs), 30 s knots;
+    # segments of 130 intervals: 8,092 band systems, four per wavefront, all
+    # resident on the chip at once
     "gaia1": (gaia_law, WorldSpec(n_src=1_000_000, years=1.0, knot_dt=30.0, ccd_per_transit=9,
-                                  seg_len=240, seg_overlap=12, lambda_reg=1e-2, min_transits=6)),
+                                  seg_len=130, seg_overlap=12, lambda_reg=1e-2, min_transits=6)),
     # 2M stars, 5 yr, 9 AF observations per transit (~1.6G obs), 1% outliers,
     # robust solvers (downweighting, excess attitude noise in 8-interval buckets)
     "gaia5": (gaia_law, WorldSpec(n_src=2_000_000, years=5.0, knot_dt=30.0, ccd_per_transit=9,
