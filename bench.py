@@ -63,11 +63,12 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload, precision):
     """HBM bytes per launch of kernel from the committed rocprofv3 PMC
     summary (FETCH_SIZE + WRITE_SIZE scaled by a copy-kernel calibration),
-    or None when no summary exists or the kernels changed since."""
-    if not os.path.exists(PMC_FILE):
+    taken on the FP64 gaia1 workload; None for another workload or
+    precision, when no summary exists or when the kernels changed since."""
+    if workload != "gaia1" or precision != "fp64" or not os.path.exists(PMC_FILE):
         return None
     vals = {}
     with open(PMC_FILE) as fh:
@@ -222,8 +223,9 @@ def main():
         alg_bytes = S_BYTES_PER_OBS * w.n_obs + S_BYTES_PER_SOURCE * n_src + 32.0 * w.n_att
     sec = kavg[dom] * 1e-3
     tfs = alg_flops / sec / 1e12
+    traffic = measured_traffic(dom, args.workload, args.precision)
     roofline = {"kernel": dom, "bound": "alu", "achieved": round(tfs, 2), "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(tfs / FP64_PEAK_TFLOPS, 4), "traffic": measured_traffic(dom),
+                "unit": "TFLOP/s", "frac": round(tfs / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
                 "alg_flops_per_launch": alg_flops, "alg_bytes_per_launch": alg_bytes,
                 "alg_hbm_GBs": round(alg_bytes / sec / 1e9, 1),
                 "alg_hbm_frac": round(alg_bytes / sec / 1e9 / HBM_PEAK_GBS, 4), "avg_ms": kavg[dom]}

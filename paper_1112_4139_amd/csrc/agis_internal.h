@@ -136,6 +136,8 @@ struct agis_ctx {
 
     // lanes per source in the S block
     int s_group = 16;
+    int64_t select_reg_limit = INT64_MAX;   // robust quantiles: register-held keys up to this count
+    int64_t select_reg_min_mean = 256;      // ... in the register kernel from this mean set size
 
     agis::Timers tm;
     double last_ms[5] = {0, 0, 0, 0, 0};

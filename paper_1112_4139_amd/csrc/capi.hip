@@ -286,6 +286,8 @@ extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
         ctx->n_buckets = (ctx->K + cfg->eps_bucket - 1) / cfg->eps_bucket;
     }
     if (const char* e = std::getenv("AGIS_S_GROUP")) ctx->s_group = std::atoi(e);
+    if (const char* e = std::getenv("AGIS_SELECT_REG_LIMIT")) ctx->select_reg_limit = std::atoll(e);
+    if (const char* e = std::getenv("AGIS_SELECT_REG_MIN_MEAN")) ctx->select_reg_min_mean = std::atoll(e);
     int rc = AGIS_OK;
     auto fail = [&](int code) {
         g_create_error = ctx->err;

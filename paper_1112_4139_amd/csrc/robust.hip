@@ -16,9 +16,11 @@
 //                   eps_a^2 = max(0, 68th percentile of R^2 - sigma^2) (eq e09).
 //
 // Quantiles are the type-7 interpolation between two exact order statistics;
-// each order statistic is found by eight 8-bit radix-selection passes over an
-// order-preserving integer image of the doubles, with the digit histogram in
-// LDS (integer counts: the result does not depend on the order of the adds).
+// the lower one is found by eight 8-bit radix-selection passes over an
+// order-preserving integer image of the doubles (held in registers, up to
+// 2,048 per block), with the digit histogram in LDS (integer counts: the
+// result does not depend on the order of the adds); the upper one by a count
+// and a minimum over the same keys.
 #include "agis_internal.h"
 #include "source_block.h"
 
@@ -37,7 +39,49 @@ __device__ __forceinline__ double key_value(uint64_t k) {
     return __builtin_bit_cast(double, u);
 }
 
-// k-th smallest (0-based, k < n) of v[0..n) by the whole 64-thread block.
+// One radix step of the selection of the k-th smallest key: from the
+// 256-bin histogram of the current digit, the digit holding rank k and the
+// number of keys in the lower digits (every lane receives both).
+__device__ __forceinline__ void radix_digit(const uint32_t* hist, int64_t k, int& digit_out, uint32_t& below_out) {
+    const int lane = threadIdx.x;
+    // lane owns digits 4 lane .. 4 lane + 3
+    const uint32_t c0 = hist[4 * lane], c1 = hist[4 * lane + 1], c2 = hist[4 * lane + 2];
+    const uint32_t c3 = hist[4 * lane + 3];
+    const uint32_t tot = c0 + c1 + c2 + c3;
+    uint32_t inc = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    const uint32_t exc = inc - tot;
+    const bool mine = (int64_t)exc <= k && k < (int64_t)inc;
+    int digit = 0;
+    uint32_t below = exc;
+    if (mine) {
+        const uint32_t r = (uint32_t)(k - (int64_t)exc);
+        if (r < c0) {
+            digit = 0;
+        } else if (r < c0 + c1) {
+            digit = 1;
+            below += c0;
+        } else if (r < c0 + c1 + c2) {
+            digit = 2;
+            below += c0 + c1;
+        } else {
+            digit = 3;
+            below += c0 + c1 + c2;
+        }
+        digit += 4 * lane;
+    }
+    const uint64_t bal = __ballot(mine);
+    const int src = __ffsll((unsigned long long)bal) - 1;
+    digit_out = __shfl(digit, src, 64);
+    below_out = __shfl(below, src, 64);
+}
+
+// k-th smallest (0-based, k < n) of v[0..n) by the whole 64-thread block,
+// reading v on every pass (any n).
 __device__ double block_select(const double* __restrict__ v, int64_t n, int64_t k, uint32_t* hist) {
     const int lane = threadIdx.x;
     uint64_t prefix = 0, mask = 0;
@@ -49,40 +93,9 @@ __device__ double block_select(const double* __restrict__ v, int64_t n, int64_t 
             if ((kk & mask) == prefix) atomicAdd(&hist[(kk >> shift) & 255u], 1u);
         }
         __syncthreads();
-        // lane owns digits 4 lane .. 4 lane + 3
-        const uint32_t c0 = hist[4 * lane], c1 = hist[4 * lane + 1], c2 = hist[4 * lane + 2];
-        const uint32_t c3 = hist[4 * lane + 3];
-        const uint32_t tot = c0 + c1 + c2 + c3;
-        uint32_t inc = tot;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += y;
-        }
-        const uint32_t exc = inc - tot;
-        const bool mine = (int64_t)exc <= k && k < (int64_t)inc;
-        int digit = 0;
-        uint32_t below = exc;
-        if (mine) {
-            const uint32_t r = (uint32_t)(k - (int64_t)exc);
-            if (r < c0) {
-                digit = 0;
-            } else if (r < c0 + c1) {
-                digit = 1;
-                below += c0;
-            } else if (r < c0 + c1 + c2) {
-                digit = 2;
-                below += c0 + c1;
-            } else {
-                digit = 3;
-                below += c0 + c1 + c2;
-            }
-            digit += 4 * lane;
-        }
-        const uint64_t bal = __ballot(mine);
-        const int src = __ffsll((unsigned long long)bal) - 1;
-        digit = __shfl(digit, src, 64);
-        below = __shfl(below, src, 64);
+        int digit;
+        uint32_t below;
+        radix_digit(hist, k, digit, below);
         prefix |= (uint64_t)digit << shift;
         mask |= 0xFFull << shift;
         k -= (int64_t)below;
@@ -101,6 +114,84 @@ __device__ double block_quantile7(const double* __restrict__ v, int64_t n, doubl
     if (j + 1 >= n) return xj;
     const double xj1 = block_select(v, n, j + 1, hist);
     return xj + (h - (double)j) * (xj1 - xj);
+}
+
+// Keys held in registers: key r of lane l is element l + 64 r (n <= 64 KR).
+constexpr int KR = 32;
+
+__device__ __forceinline__ void load_keys(const double* __restrict__ v, int64_t n, uint64_t (&kr)[KR]) {
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < KR; ++r) kr[r] = lane + 64 * r < n ? order_key(v[lane + 64 * r]) : ~0ull;
+}
+
+// k-th smallest key of the n register-held keys.  Where every active lane
+// of a slot has the same digit (the leading digits of values of one sign
+// and magnitude), one lane adds their count: LDS atomics to one address
+// from all lanes would serialise.
+__device__ uint64_t reg_select(const uint64_t (&kr)[KR], int64_t n, int64_t k, uint32_t* hist) {
+    const int lane = threadIdx.x;
+    const int nr = (int)((n + 63) / 64);
+    uint64_t prefix = 0, mask = 0;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        for (int b = lane; b < 256; b += 64) hist[b] = 0u;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < KR; ++r) {
+            if (r < nr && lane + 64 * r < n && (kr[r] & mask) == prefix) {
+                // the active lanes only: the first one's digit, and who shares it
+                const uint32_t dg = (uint32_t)(kr[r] >> shift) & 255u;
+                const uint32_t d0 = __builtin_amdgcn_readfirstlane(dg);
+                const uint64_t am = __ballot(true);
+                const uint64_t same = __ballot(dg == d0);
+                if (same == am) {
+                    if (lane == __ffsll((unsigned long long)am) - 1) atomicAdd(&hist[d0], (uint32_t)__popcll(am));
+                } else {
+                    atomicAdd(&hist[dg], 1u);
+                }
+            }
+        }
+        __syncthreads();
+        int digit;
+        uint32_t below;
+        radix_digit(hist, k, digit, below);
+        prefix |= (uint64_t)digit << shift;
+        mask |= 0xFFull << shift;
+        k -= (int64_t)below;
+        __syncthreads();
+    }
+    return prefix;
+}
+
+// Type-7 p-quantile of the n register-held keys: the order statistic j by
+// selection, j + 1 as the same key if more than j + 1 keys are <= it, else
+// as the smallest key above it.
+__device__ double reg_quantile7(const uint64_t (&kr)[KR], int64_t n, double p, uint32_t* hist) {
+    if (n <= 0) return 0.0;
+    const int lane = threadIdx.x;
+    const double h = (double)(n - 1) * p;
+    const int64_t j = (int64_t)floor(h);
+    const uint64_t kj = reg_select(kr, n, j, hist);
+    const double xj = key_value(kj);
+    if (j + 1 >= n) return xj;
+    uint32_t cle = 0;
+    uint64_t mn = ~0ull;
+#pragma unroll
+    for (int r = 0; r < KR; ++r) {
+        if (lane + 64 * r < n) {
+            cle += kr[r] <= kj ? 1u : 0u;
+            if (kr[r] > kj && kr[r] < mn) mn = kr[r];
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        cle += __shfl_xor(cle, o, 64);
+        const uint32_t lo = __shfl_xor((uint32_t)mn, o, 64), hi = __shfl_xor((uint32_t)(mn >> 32), o, 64);
+        const uint64_t other = ((uint64_t)hi << 32) | lo;
+        mn = other < mn ? other : mn;
+    }
+    const uint64_t kj1 = (int64_t)cle >= j + 2 ? kj : mn;
+    return xj + (h - (double)j) * (key_value(kj1) - xj);
 }
 
 // ------------------------------------------------------------- S, pass 0
@@ -146,14 +237,26 @@ __global__ __launch_bounds__(256, 2) void k_s_rows(DevConsts k, int64_t n_src, c
 }
 
 // ------------------------------------------------ S, initial downweights
+// REG: keys of sets up to reg_limit in registers (fewer wavefronts per SIMD,
+// pays for large sets); otherwise re-read on every pass (small sets).
+template <bool REG>
 __global__ __launch_bounds__(64) void k_s_sigma(int64_t n_src, const int64_t* __restrict__ off,
-                                                const double* __restrict__ h, double* __restrict__ vs) {
+                                                const double* __restrict__ h, double* __restrict__ vs,
+                                                int64_t reg_limit) {
     __shared__ uint32_t hist[256];
     const int64_t i = blockIdx.x;
     if (i >= n_src) return;
     const int64_t l0 = off[i], n = off[i + 1] - l0;
-    const double q5 = block_quantile7(h + l0, n, 5.0 / 6.0, hist);
-    const double q1 = block_quantile7(h + l0, n, 1.0 / 6.0, hist);
+    double q5, q1;
+    if (REG && n <= reg_limit) {
+        uint64_t kr[KR];
+        load_keys(h + l0, n, kr);
+        q5 = reg_quantile7(kr, n, 5.0 / 6.0, hist);
+        q1 = reg_quantile7(kr, n, 1.0 / 6.0, hist);
+    } else {
+        q5 = block_quantile7(h + l0, n, 5.0 / 6.0, hist);
+        q1 = block_quantile7(h + l0, n, 1.0 / 6.0, hist);
+    }
     if (threadIdx.x == 0) vs[i] = 0.5 * (q5 - q1);
 }
 
@@ -254,17 +357,41 @@ __global__ __launch_bounds__(64) void k_ac_resid(DevConsts k, int64_t K, const i
     }
 }
 
+template <bool REG>
 __global__ __launch_bounds__(64) void k_bucket_eps(int64_t n_buckets, int64_t K, int eps_bucket,
                                                    const int64_t* __restrict__ iv_off, const double* __restrict__ v,
-                                                   double* __restrict__ eps_a2) {
+                                                   double* __restrict__ eps_a2, int64_t reg_limit) {
     __shared__ uint32_t hist[256];
     const int64_t b = blockIdx.x;
     if (b >= n_buckets) return;
     const int64_t j0 = b * eps_bucket;
     const int64_t j1 = j0 + eps_bucket < K ? j0 + eps_bucket : K;
     const int64_t l0 = iv_off[j0], n = iv_off[j1] - l0;
-    const double q = block_quantile7(v + l0, n, 0.68, hist);
+    double q;
+    if (REG && n <= reg_limit) {
+        uint64_t kr[KR];
+        load_keys(v + l0, n, kr);
+        q = reg_quantile7(kr, n, 0.68, hist);
+    } else {
+        q = block_quantile7(v + l0, n, 0.68, hist);
+    }
     if (threadIdx.x == 0) eps_a2[b] = q > 0.0 ? q : 0.0;
+}
+
+// Largest set whose keys go to registers; larger sets (or all, with the
+// context's limit at 0) are read from memory on every radix pass.
+inline int64_t select_reg_limit(const agis_ctx* ctx) {
+    return ctx->select_reg_limit < 64 * KR ? ctx->select_reg_limit : 64 * KR;
+}
+
+// The register kernel pays for mean set sizes from ~256 up to about three
+// quarters of its capacity (measured: sets of ~160 run faster in the lean
+// kernel, ~800 and ~1,200 in the register one; at ~2,400 most sets exceed the
+// capacity and re-read their values with fewer wavefronts per SIMD).
+inline bool select_in_registers(const agis_ctx* ctx, int64_t n_values, int64_t n_sets) {
+    const int64_t lim = select_reg_limit(ctx);
+    return lim > 0 && n_sets > 0 && n_values >= ctx->select_reg_min_mean * n_sets &&
+           (ctx->select_reg_min_mean == 0 || 4 * n_values <= 3 * lim * n_sets);
 }
 
 inline unsigned groups_grid(int64_t n_items, int items_per_block) {
@@ -290,8 +417,9 @@ void launch_source_update_robust(agis_ctx* ctx) {
         case 32: AGIS_ROWS_LAUNCH(32); break;
         default: AGIS_ROWS_LAUNCH(64); break;
     }
-    k_s_sigma<<<(unsigned)ctx->n_src, 64, 0, ctx->stream>>>(ctx->n_src, ctx->src_off, ctx->rcol + 5 * ctx->n_obs,
-                                                             ctx->vs);
+    (select_in_registers(ctx, ctx->n_obs, ctx->n_src) ? k_s_sigma<true> : k_s_sigma<false>)
+        <<<(unsigned)ctx->n_src, 64, 0, ctx->stream>>>(ctx->n_src, ctx->src_off, ctx->rcol + 5 * ctx->n_obs, ctx->vs,
+                                                       select_reg_limit(ctx));
     switch (ctx->s_group) {
         case 8: AGIS_IRLS_LAUNCH(8); break;
         case 16: AGIS_IRLS_LAUNCH(16); break;
@@ -305,8 +433,9 @@ void launch_excess_noise(agis_ctx* ctx) {
     k_ac_resid<<<(unsigned)ctx->K, 64, 0, ctx->stream>>>(ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, ctx->t_sig,
                                                          ctx->t_cellfov, ctx->t_src, ctx->prep, ctx->knots, ctx->ktab,
                                                          ctx->a, ctx->c, ctx->rcol);
-    k_bucket_eps<<<(unsigned)ctx->n_buckets, 64, 0, ctx->stream>>>(ctx->n_buckets, ctx->K, ctx->cfg.eps_bucket,
-                                                                   ctx->iv_off, ctx->rcol, ctx->eps_a2);
+    (select_in_registers(ctx, ctx->n_obs, ctx->n_buckets) ? k_bucket_eps<true> : k_bucket_eps<false>)
+        <<<(unsigned)ctx->n_buckets, 64, 0, ctx->stream>>>(ctx->n_buckets, ctx->K, ctx->cfg.eps_bucket, ctx->iv_off,
+                                                           ctx->rcol, ctx->eps_a2, select_reg_limit(ctx));
 }
 
 }  // namespace agis

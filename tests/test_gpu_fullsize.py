@@ -32,7 +32,7 @@ def subworld(w, idx):
     sub = types.SimpleNamespace(**{k: v for k, v in vars(w).items() if k not in OBS_FIELDS})
     for k in OBS_FIELDS:
         setattr(sub, k, getattr(w, k)[idx])
-    sub.n_obs = idx.size
+    sub.n_obs, sub.n_att, sub.n_cells = idx.size, w.n_att, w.n_cells
     return sub
 
 

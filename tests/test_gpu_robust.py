@@ -3,6 +3,8 @@ oracle: excess attitude noise per bucket, the source inner iteration, and
 iterations with robust attitude and calibration weights, on the tiny world
 with 1% gross outliers (noise N(0, 50 mas)).  Same criterion as the plain
 parity tests: the extended-precision oracle is the reference."""
+import types
+
 import numpy as np
 import pytest
 
@@ -107,3 +109,42 @@ def test_robust_mode_calls(agis_mod, oracle_lib, tiny_robust):
     agis_mod.agis_set_excess_noise(ctx, np.full(nb, 1e-20))
     assert np.all(agis_mod.agis_get_excess_noise(ctx, nb) == 1e-20)
     agis_mod.agis_destroy(ctx)
+
+
+@pytest.mark.parametrize("eps_bucket", [8, 100, 200])
+def test_quantile_paths_agree(agis_mod, oracle_lib, tiny_robust, eps_bucket, monkeypatch):
+    """The exact quantiles from register-held keys (sets up to 2,048, in the
+    register kernel) and from keys re-read on every radix pass (larger sets,
+    and every set in the lean kernel) are the same numbers: with the default
+    kernel choice, the lean kernel forced everywhere and the register kernel
+    forced everywhere, the robust S update and the excess noise agree bit
+    for bit, and the noise agrees with the oracle.
+    Buckets of 8, 100 and 200 intervals hold ~100, ~1,300 and ~2,600
+    observations (the last beyond the register capacity)."""
+    w, eta = tiny_robust
+    consts = dict(w.consts)
+    consts["eps_bucket"] = eps_bucket
+    wb = types.SimpleNamespace(**{**vars(w), "consts": consts, "n_cells": w.n_cells, "n_att": w.n_att,
+                                  "n_obs": w.n_obs})
+    out = []
+    # default choice; the lean kernel everywhere; the register kernel everywhere
+    for env in ({}, {"AGIS_SELECT_REG_LIMIT": "0"}, {"AGIS_SELECT_REG_MIN_MEAN": "0"}):
+        for k in ("AGIS_SELECT_REG_LIMIT", "AGIS_SELECT_REG_MIN_MEAN"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        p = Pair(agis_mod, oracle_lib, wb, eta, state="truth")
+        agis_mod.agis_excess_noise_update(p.ctx)
+        e_g = agis_mod.agis_get_excess_noise(p.ctx, p.pr.eps_a2.size)
+        agis_mod.agis_set_sources(p.ctx, w.src_start)
+        agis_mod.agis_source_update(p.ctx)
+        out.append((e_g, p.gpu_state()[0]))
+        if not env:
+            e_o = p.pr.excess_attitude_noise()
+        p.close()
+    for k in ("AGIS_SELECT_REG_LIMIT", "AGIS_SELECT_REG_MIN_MEAN"):
+        monkeypatch.delenv(k, raising=False)
+    print(f"eps_bucket {eps_bucket}: {e_o.size} buckets; max |eps^2 GPU - oracle| {np.abs(out[0][0] - e_o).max():.2e}")
+    for o in out[1:]:
+        assert np.array_equal(out[0][0], o[0]) and np.array_equal(out[0][1], o[1])
+    assert np.all(np.abs(out[0][0] - e_o) <= 2e-24)
