@@ -104,7 +104,7 @@ struct agis_ctx {
     int64_t n_buckets = 0;
     double* eps_a2 = nullptr;            // [n_buckets]
     double* vs = nullptr;                // [n_src]
-    double* rcol = nullptr;              // [7][n_obs]
+    double* rcol = nullptr;              // [6][n_obs]
 
     // learned extrapolation: update histories (rings of four), MLP weights
     // (FP32 master, BF16-rounded copy, Adam moments, gradient + loss) for

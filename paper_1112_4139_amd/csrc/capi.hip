@@ -429,7 +429,7 @@ extern "C" int agis_load_observations(agis_ctx_t* ctx, const agis_obs_soa_t* obs
         // the inner iteration's by-source columns (A, h, sigma~^2), also
         // used for R^2 - sigma^2 by the excess-noise estimate
         ALLOC(ctx->vs, n_src, "source varsigma");
-        ALLOC(ctx->rcol, 7 * std::max<int64_t>(ctx->n_obs, 1), "robust columns");
+        ALLOC(ctx->rcol, 6 * std::max<int64_t>(ctx->n_obs, 1), "robust columns");
     }
     launch_prep_sources(ctx);
     HIPCHK(hipGetLastError());

@@ -2,8 +2,10 @@
 //
 //   k_s_rows<G>     S block, pass 0: G lanes per source evaluate the model at
 //                   the current parameters and store, per observation (by-source
-//                   order), the design row -dR/ds (5), h = R and
-//                   sigma~^2 = sigma^2 + eps_a^2(t) as seven columns in HBM.
+//                   order), the design row -dR/ds (its alpha*, delta and
+//                   parallax entries, and tau, the proper-motion entries
+//                   being the first two times tau), h = R and
+//                   sigma~^2 = sigma^2 + eps_a^2(t) as six columns in HBM.
 //   k_s_sigma       one wavefront per source: half the intersextile range of
 //                   its h (exact order statistics by radix selection).
 //   k_s_irls<G>     the inner iteration from the stored columns: initial
@@ -230,9 +232,10 @@ __global__ __launch_bounds__(256, 2) void k_s_rows(DevConsts k, int64_t n_src, c
         double A[5];
         source_partials(o, p, q, r, A);
 #pragma unroll
-        for (int e = 0; e < 5; ++e) col[e * n_obs + l] = A[e];
-        col[5 * n_obs + l] = o.R;
-        col[6 * n_obs + l] = sg * sg + eps_a2[(ell - 3) / eps_bucket];
+        for (int e = 0; e < 3; ++e) col[e * n_obs + l] = A[e];
+        col[3 * n_obs + l] = o.tau;              // A[3] = A[0] tau, A[4] = A[1] tau
+        col[4 * n_obs + l] = o.R;
+        col[5 * n_obs + l] = sg * sg + eps_a2[(ell - 3) / eps_bucket];
     }
 }
 
@@ -285,8 +288,11 @@ __global__ __launch_bounds__(256) void k_s_irls(int64_t n_src, const int64_t* __
         for (int64_t l = l0 + gl; l < l1; l += G) {
             double A[5];
 #pragma unroll
-            for (int e = 0; e < 5; ++e) A[e] = col[e * n_obs + l];
-            const double h = col[5 * n_obs + l], s2 = col[6 * n_obs + l];
+            for (int e = 0; e < 3; ++e) A[e] = col[e * n_obs + l];
+            const double tau = col[3 * n_obs + l];
+            A[3] = A[0] * tau;                   // as the design row forms them
+            A[4] = A[1] * tau;
+            const double h = col[4 * n_obs + l], s2 = col[5 * n_obs + l];
             double wl;
             if (it == 0) {
                 wl = vsi > 0.0 ? down_weight(h / vsi) : 1.0;
@@ -418,7 +424,7 @@ void launch_source_update_robust(agis_ctx* ctx) {
         default: AGIS_ROWS_LAUNCH(64); break;
     }
     (select_in_registers(ctx, ctx->n_obs, ctx->n_src) ? k_s_sigma<true> : k_s_sigma<false>)
-        <<<(unsigned)ctx->n_src, 64, 0, ctx->stream>>>(ctx->n_src, ctx->src_off, ctx->rcol + 5 * ctx->n_obs, ctx->vs,
+        <<<(unsigned)ctx->n_src, 64, 0, ctx->stream>>>(ctx->n_src, ctx->src_off, ctx->rcol + 4 * ctx->n_obs, ctx->vs,
                                                        select_reg_limit(ctx));
     switch (ctx->s_group) {
         case 8: AGIS_IRLS_LAUNCH(8); break;
