@@ -298,3 +298,51 @@ def test_asi_step(agis_mod, tiny, stride, lambda_max):
     with pytest.raises(RuntimeError):                  # invalid stride
         agis_mod.agis_asi_step(ctx, 0, 0.9)
     agis_mod.agis_destroy(ctx)
+
+
+def test_learned_solve_beats_plain(agis_mod):
+    """Train both networks on one plain trajectory of the tiny world (seed
+    1), then iterate seed 0 with and without the gated learned step for the
+    same number of S[AC] iterations (the gate's included): the learned
+    iterate has the lower sum W R^2, i.e. it is closer to the solution in the
+    norm of the normal matrix, and the gate kept some of its candidates."""
+    from paper_1112_4139_amd import learned
+
+    m, horizon = 50, 20
+    w1, ctx1 = learned.problem("tiny", 1)
+    data = learned.collect(ctx1, w1, m, 60, horizon)
+    for which in (0, 1):
+        X, T = data[which]
+        agis_mod.agis_mlp_init(ctx1, which, 5 + which)
+        loss = np.concatenate([agis_mod.agis_mlp_train(ctx1, which, X, T, n, 1024, lr, seed=3 + which)
+                               for n, lr in ((2000, 1e-3), (1000, 2.5e-4))])
+        print(f"net {which}: {X.shape[0]} samples, loss {loss[:20].mean():.3g} -> {loss[-100:].mean():.3g}")
+        assert loss[-100:].mean() < 0.3 * loss[:20].mean()
+    weights = [agis_mod.agis_mlp_get_weights(ctx1, which) for which in (0, 1)]
+    agis_mod.agis_destroy(ctx1)
+    chi2 = {}
+    for mode in ("learned", "plain"):
+        w0, ctx = learned.problem("tiny", 0)
+        for which in (0, 1):
+            agis_mod.agis_mlp_set_weights(ctx, which, weights[which])
+        agis_mod.agis_learned_reset(ctx)
+        it, count, acc = 0, 0, 0
+        if mode == "learned":
+            while it < 4000:
+                agis_mod.agis_iterate(ctx, m, stats=False)
+                agis_mod.agis_learned_record(ctx)
+                it, count = it + m, count + 1
+                if count >= 4:
+                    r = agis_mod.agis_learned_step(ctx)
+                    it += 2
+                    if r["accepted"]:
+                        acc, count = acc + 1, 0
+        else:
+            # as many S[AC] iterations as the learned run took
+            it = chi2["learned"][1]
+            agis_mod.agis_iterate(ctx, it, stats=False)
+        chi2[mode] = (agis_mod.agis_chi2(ctx), it, acc)
+        agis_mod.agis_destroy(ctx)
+    print(chi2)
+    assert chi2["learned"][2] > 0
+    assert chi2["learned"][0] < chi2["plain"][0]
