@@ -203,6 +203,12 @@ int agis_frame_apply(agis_ctx_t* ctx, const double eps_omega[6]);
  * rotator when a reference is set.  per_iter may be NULL or hold n_iter
  * entries. */
 int agis_iterate(agis_ctx_t* ctx, int32_t n_iter, agis_iter_stats_t* per_iter);
+/* The same n_iter iterations replayed from a HIP graph of one iteration
+ * (captured on the first call, and again after agis_load_observations or
+ * agis_set_frame_reference); the results equal agis_iterate's bit for bit.
+ * Saves the per-kernel launch cost where the kernels are short; records no
+ * per-block times (agis_kernel_times keeps those of the last agis_iterate). */
+int agis_iterate_graph(agis_ctx_t* ctx, int32_t n_iter);
 
 /* Residuals R_l (eq:resAL) at the current parameters, in the input order of
  * agis_load_observations. */

@@ -141,6 +141,12 @@ struct agis_ctx {
 
     agis::Timers tm;
     double last_ms[5] = {0, 0, 0, 0, 0};
+    bool timing = true;                      // per-block HIP events (off inside a graph capture)
+
+    // one captured iteration; rebuilt when gen (bumped by every call that
+    // changes what the kernels are launched with) differs from graph_gen
+    hipGraphExec_t graph_exec = nullptr;
+    uint64_t gen = 1, graph_gen = 0;
 };
 
 namespace agis {

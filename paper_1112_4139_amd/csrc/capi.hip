@@ -120,6 +120,7 @@ static void free_store(agis_ctx* ctx) {
     ctx->lh_count = 0;
     ctx->loaded = false;
     ctx->have_ref = false;
+    ++ctx->gen;
 }
 
 static int copy_in(agis_ctx* ctx, void* dst, const void* src, size_t bytes, int where) {
@@ -357,6 +358,7 @@ extern "C" void agis_destroy(agis_ctx_t* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     free_store(ctx);
     dfree(ctx->knots);
     dfree(ctx->ktab);
@@ -498,8 +500,11 @@ extern "C" int agis_get_calibration(agis_ctx_t* ctx, int64_t n, double* c, int w
 // --- timing and statistics helpers -----------------------------------------
 enum { T_S = 0, T_AC = 1, T_BAND = 2, T_CAL = 3, T_FRAME = 4, T_ITER = 5 };
 
-static void tstart(agis_ctx* ctx, int e) { (void)hipEventRecord(ctx->tm.ev[e][0], ctx->stream); }
+static void tstart(agis_ctx* ctx, int e) {
+    if (ctx->timing) (void)hipEventRecord(ctx->tm.ev[e][0], ctx->stream);
+}
 static void tstop(agis_ctx* ctx, int e) {
+    if (!ctx->timing) return;
     (void)hipEventRecord(ctx->tm.ev[e][1], ctx->stream);
     ctx->tm.valid[e] = true;
 }
@@ -639,6 +644,7 @@ extern "C" int agis_set_frame_reference(agis_ctx_t* ctx, int64_t n, const double
     CHECK_CTX();
     REQUIRE_LOADED();
     if (n != ctx->n_src) return set_error(ctx, AGIS_E_SHAPE, "reference catalogue size must equal n_src");
+    ++ctx->gen;
     if (!s_ref5) {
         ctx->have_ref = false;
         return AGIS_OK;
@@ -725,6 +731,39 @@ extern "C" int agis_iterate(agis_ctx_t* ctx, int32_t n_iter, agis_iter_stats_t* 
     ctx->last_ms[2] = tget(ctx, T_BAND);
     ctx->last_ms[3] = tget(ctx, T_CAL);
     ctx->last_ms[4] = tget(ctx, T_FRAME);
+    return AGIS_OK;
+}
+
+extern "C" int agis_iterate_graph(agis_ctx_t* ctx, int32_t n_iter) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    if (n_iter < 0) return set_error(ctx, AGIS_E_INVALID_ARG, "n_iter < 0");
+    if (!ctx->graph_exec || ctx->graph_gen != ctx->gen) {
+        if (ctx->graph_exec) {
+            HIPCHK(hipGraphExecDestroy(ctx->graph_exec));
+            ctx->graph_exec = nullptr;
+        }
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        ctx->timing = false;
+        const int rc = iterate_once(ctx, nullptr);
+        ctx->timing = true;
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(ctx->stream, &g);
+        if (rc != AGIS_OK || ec != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc != AGIS_OK ? rc : hip_check(ctx, ec, "end of graph capture");
+        }
+        const hipError_t ei = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            ctx->graph_exec = nullptr;
+            return hip_check(ctx, ei, "graph instantiation");
+        }
+        ctx->graph_gen = ctx->gen;
+    }
+    for (int32_t it = 0; it < n_iter; ++it) HIPCHK(hipGraphLaunch(ctx->graph_exec, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
     return AGIS_OK;
 }
 

@@ -1,0 +1,109 @@
+"""The graph-captured iteration (agis_iterate_graph) against the eager one
+(agis_iterate): the same kernels on the same stream, so the iterates agree
+bit for bit, also when graph replays and eager iterations alternate, after
+the captured configuration changes (frame reference cleared, observations
+reloaded: the graph is captured again), and in the robust mode."""
+import time
+
+import numpy as np
+import pytest
+
+import synth.configs as C
+from test_gpu_parity import agis_mod  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(agis, w, eta):
+    ctx = agis.agis_create(w.consts, w.knots)
+    agis.agis_load_observations(ctx, w.t, eta, w.sigma, w.src, w.fov, w.cell, w.src_true.shape[0], w.n_cells)
+    agis.agis_set_sources(ctx, w.src_start)
+    agis.agis_set_attitude(ctx, w.att_start)
+    agis.agis_set_calibration(ctx, w.cal_start)
+    agis.agis_set_frame_reference(ctx, w.src_true)
+    return ctx
+
+
+def _state(agis, ctx, w, robust=False):
+    out = [agis.agis_get_sources(ctx, w.src_true.shape[0]), agis.agis_get_attitude(ctx, w.n_att),
+           agis.agis_get_calibration(ctx, w.n_cells)]
+    if robust:
+        nb = (w.knots.size - 7 + int(w.consts["eps_bucket"]) - 1) // int(w.consts["eps_bucket"])
+        out.append(agis.agis_get_excess_noise(ctx, nb))
+    return out
+
+
+def _same(x, y):
+    return all(np.array_equal(a, b) for a, b in zip(x, y))
+
+
+@pytest.fixture(scope="module")
+def tiny(oracle_lib):
+    w = C.make("tiny")
+    return w, oracle_lib.observed_field_angles(w)
+
+
+def test_graph_equals_eager(agis_mod, tiny):
+    w, eta = tiny
+    e, g = _ctx(agis_mod, w, eta), _ctx(agis_mod, w, eta)
+    agis_mod.agis_iterate(e, 6, stats=False)
+    agis_mod.agis_iterate_graph(g, 3)
+    agis_mod.agis_iterate(g, 1, stats=False)             # eager work between replays
+    agis_mod.agis_iterate_graph(g, 2)
+    assert _same(_state(agis_mod, e, w), _state(agis_mod, g, w))
+    # without the frame rotator (captured again)
+    for c in (e, g):
+        agis_mod.agis_set_frame_reference(c, None)
+    agis_mod.agis_iterate(e, 2, stats=False)
+    agis_mod.agis_iterate_graph(g, 2)
+    assert _same(_state(agis_mod, e, w), _state(agis_mod, g, w))
+    # observations reloaded (new buffers; sources and calibration start from
+    # zero, so set again): captured again
+    s0, a0, c0 = _state(agis_mod, e, w)
+    for c in (e, g):
+        agis_mod.agis_load_observations(c, w.t, eta, w.sigma, w.src, w.fov, w.cell, w.src_true.shape[0],
+                                        w.n_cells)
+        agis_mod.agis_set_sources(c, s0)
+        agis_mod.agis_set_attitude(c, a0)
+        agis_mod.agis_set_calibration(c, c0)
+        agis_mod.agis_set_frame_reference(c, w.src_true)
+    agis_mod.agis_iterate(e, 2, stats=False)
+    agis_mod.agis_iterate_graph(g, 2)
+    assert _same(_state(agis_mod, e, w), _state(agis_mod, g, w))
+    agis_mod.agis_iterate_graph(g, 0)
+    with pytest.raises(RuntimeError):
+        agis_mod.agis_iterate_graph(g, -1)
+    agis_mod.agis_destroy(e)
+    agis_mod.agis_destroy(g)
+
+
+def test_graph_equals_eager_robust(agis_mod, oracle_lib):
+    w = C.make("tiny_robust")
+    eta = oracle_lib.observed_field_angles(w)
+    e, g = _ctx(agis_mod, w, eta), _ctx(agis_mod, w, eta)
+    agis_mod.agis_iterate(e, 4, stats=False)
+    agis_mod.agis_iterate_graph(g, 2)
+    agis_mod.agis_iterate(g, 1, stats=False)
+    agis_mod.agis_iterate_graph(g, 1)
+    assert _same(_state(agis_mod, e, w, True), _state(agis_mod, g, w, True))
+    agis_mod.agis_destroy(e)
+    agis_mod.agis_destroy(g)
+
+
+def test_graph_timing(agis_mod, tiny):
+    """Per-iteration wall time of the two paths on the tiny world (short
+    kernels): reported; the graph must not be slower than the eager path."""
+    w, eta = tiny
+    ctx = _ctx(agis_mod, w, eta)
+    agis_mod.agis_iterate(ctx, 5, stats=False)
+    agis_mod.agis_iterate_graph(ctx, 5)
+    n = 200
+    t0 = time.perf_counter()
+    agis_mod.agis_iterate(ctx, n, stats=False)
+    t_e = (time.perf_counter() - t0) / n
+    t0 = time.perf_counter()
+    agis_mod.agis_iterate_graph(ctx, n)
+    t_g = (time.perf_counter() - t0) / n
+    print(f"tiny world: eager {1e3 * t_e:.3f} ms, graph {1e3 * t_g:.3f} ms per iteration")
+    assert t_g <= 1.1 * t_e
+    agis_mod.agis_destroy(ctx)
