@@ -182,6 +182,8 @@ def main():
     sz = agis.agis_problem_size(ctx)
     log(f"store built: {sz}")
 
+    s_group = agis.agis_autotune(ctx)
+    log(f"autotuned: {s_group} lanes per source")
     for i in range(args.warmup):
         agis.agis_iterate(ctx, 1, stats=False)
     torch.cuda.synchronize()
@@ -239,7 +241,8 @@ def main():
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None,
            "dtype": "f64" if args.precision == "fp64" else "f64 model, f32 partials and sums", "data": "synthetic",
-           "config": workload_description(args.workload, w), "kernel_ms": kavg, "roofline": roofline,
+           "config": {**workload_description(args.workload, w), "lanes_per_source": s_group},
+           "kernel_ms": kavg, "roofline": roofline,
            "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
     agis.agis_destroy(ctx)

@@ -209,6 +209,12 @@ int agis_iterate(agis_ctx_t* ctx, int32_t n_iter, agis_iter_stats_t* per_iter);
  * Saves the per-kernel launch cost where the kernels are short; records no
  * per-block times (agis_kernel_times keeps those of the last agis_iterate). */
 int agis_iterate_graph(agis_ctx_t* ctx, int32_t n_iter);
+/* Times the source update with 8, 16 and 32 lanes per source on the loaded
+ * problem (twice each, from the current state, restored bit for bit
+ * afterwards: sources, their derived data and variances) and keeps the
+ * fastest; *s_group (may be NULL) receives it.  The default, 16, is the best
+ * for ~160 observations per source. */
+int agis_autotune(agis_ctx_t* ctx, int32_t* s_group);
 
 /* Residuals R_l (eq:resAL) at the current parameters, in the input order of
  * agis_load_observations. */

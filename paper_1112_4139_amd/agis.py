@@ -79,6 +79,7 @@ _sig = {
     "agis_frame_apply": ([_ctx_p, P(c_d)], ctypes.c_int),
     "agis_iterate": ([_ctx_p, c_i32, P(agis_iter_stats_t)], ctypes.c_int),
     "agis_iterate_graph": ([_ctx_p, ctypes.c_int32], ctypes.c_int),
+    "agis_autotune": ([_ctx_p, P(c_i32)], ctypes.c_int),
     "agis_residuals": ([_ctx_p, _vp, ctypes.c_int], ctypes.c_int),
     "agis_problem_size": ([_ctx_p, P(c_i64), P(c_i64), P(c_i64), P(c_i64), P(c_i64)], ctypes.c_int),
     "agis_kernel_times": ([_ctx_p, P(c_d)], ctypes.c_int),
@@ -268,6 +269,12 @@ def agis_iterate(ctx, n_iter, stats=True):
 
 def agis_iterate_graph(ctx, n_iter):
     _check(_lib.agis_iterate_graph(ctx, int(n_iter)), ctx)
+
+
+def agis_autotune(ctx):
+    g = c_i32()
+    _check(_lib.agis_autotune(ctx, ctypes.byref(g)), ctx)
+    return g.value
 
 
 def agis_residuals(ctx, out=None):

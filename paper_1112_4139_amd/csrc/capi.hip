@@ -734,6 +734,73 @@ extern "C" int agis_iterate(agis_ctx_t* ctx, int32_t n_iter, agis_iter_stats_t* 
     return AGIS_OK;
 }
 
+extern "C" int agis_autotune(agis_ctx_t* ctx, int32_t* s_group) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    if (ctx->n_src > 0) {
+        const int64_t ns = ctx->n_src;
+        double *bs = nullptr, *bv = nullptr;
+        agis::SrcPrep* bp = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        int rc = AGIS_OK;
+        auto release = [&]() {
+            if (bs) (void)hipFree(bs);
+            if (bv) (void)hipFree(bv);
+            if (bp) (void)hipFree(bp);
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        };
+        auto restore = [&]() -> hipError_t {
+            hipError_t e = hipMemcpyAsync(ctx->s, bs, 5 * ns * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(ctx->svar, bv, 5 * ns * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(ctx->prep, bp, ns * sizeof(agis::SrcPrep), hipMemcpyDeviceToDevice, ctx->stream);
+            return e;
+        };
+        if ((rc = dalloc(ctx, &bs, 5 * ns, "tuning backup")) || (rc = dalloc(ctx, &bv, 5 * ns, "tuning backup")) ||
+            (rc = dalloc(ctx, &bp, ns, "tuning backup"))) {
+            release();
+            return rc;
+        }
+        hipError_t e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        if (e == hipSuccess) e = hipMemcpyAsync(bs, ctx->s, 5 * ns * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(bv, ctx->svar, 5 * ns * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(bp, ctx->prep, ns * sizeof(agis::SrcPrep), hipMemcpyDeviceToDevice, ctx->stream);
+        // the source update for each group size, twice (the faster run
+        // counts), each from the saved state
+        const int cand[3] = {8, 16, 32};
+        int best = ctx->s_group;
+        float best_ms = 3.0e38f;
+        for (int ci = 0; ci < 3 && e == hipSuccess && rc == AGIS_OK; ++ci) {
+            for (int rep = 0; rep < 2 && e == hipSuccess && rc == AGIS_OK; ++rep) {
+                ctx->s_group = cand[ci];
+                e = restore();
+                if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+                if (e == hipSuccess) rc = run_source(ctx);
+                if (e == hipSuccess && rc == AGIS_OK) e = hipEventRecord(e1, ctx->stream);
+                if (e == hipSuccess && rc == AGIS_OK) e = hipEventSynchronize(e1);
+                float ms = 0.0f;
+                if (e == hipSuccess && rc == AGIS_OK) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e == hipSuccess && rc == AGIS_OK && ms < best_ms) {
+                    best_ms = ms;
+                    best = cand[ci];
+                }
+            }
+        }
+        ctx->s_group = best;
+        ++ctx->gen;                      // launch shapes changed
+        if (e == hipSuccess) e = restore();
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        release();
+        if (rc != AGIS_OK) return rc;
+        if (e != hipSuccess) return hip_check(ctx, e, "autotuning");
+    }
+    if (s_group) *s_group = ctx->s_group;
+    return AGIS_OK;
+}
+
 extern "C" int agis_iterate_graph(agis_ctx_t* ctx, int32_t n_iter) {
     CHECK_CTX();
     REQUIRE_LOADED();

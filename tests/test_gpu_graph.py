@@ -107,3 +107,29 @@ def test_graph_timing(agis_mod, tiny):
     print(f"tiny world: eager {1e3 * t_e:.3f} ms, graph {1e3 * t_g:.3f} ms per iteration")
     assert t_g <= 1.1 * t_e
     agis_mod.agis_destroy(ctx)
+
+
+def test_autotune_keeps_state(agis_mod, tiny, monkeypatch):
+    """agis_autotune times the S pass per group size from the current state
+    and restores it: every state array is bitwise unchanged, the chosen size
+    is one of the candidates, and a following source update equals that of a
+    context fixed to the chosen size."""
+    w, eta = tiny
+    ctx = _ctx(agis_mod, w, eta)
+    agis_mod.agis_iterate(ctx, 3, stats=False)
+    before = _state(agis_mod, ctx, w)
+    g = agis_mod.agis_autotune(ctx)
+    print(f"autotuned lanes per source: {g}")
+    assert g in (8, 16, 32)
+    assert _same(before, _state(agis_mod, ctx, w))
+    monkeypatch.setenv("AGIS_S_GROUP", str(g))
+    ref = _ctx(agis_mod, w, eta)
+    monkeypatch.delenv("AGIS_S_GROUP")
+    for c in (ctx, ref):
+        agis_mod.agis_set_sources(c, before[0])
+        agis_mod.agis_set_attitude(c, before[1])
+        agis_mod.agis_set_calibration(c, before[2])
+        agis_mod.agis_source_update(c)
+    assert _same(_state(agis_mod, ctx, w), _state(agis_mod, ref, w))
+    agis_mod.agis_destroy(ctx)
+    agis_mod.agis_destroy(ref)
