@@ -59,6 +59,7 @@ struct agis_ctx {
     int32_t* s_cell = nullptr;
     int32_t* s_ell = nullptr;
     int64_t* src_off = nullptr;          // [n_src + 1]
+    int32_t* src_order = nullptr;        // [n_src] S-pass launch order (decreasing observation count)
     // by time
     double* t_t = nullptr;
     double* t_eta = nullptr;

@@ -76,6 +76,7 @@ static void free_store(agis_ctx* ctx) {
     dfree(ctx->s_cell);
     dfree(ctx->s_ell);
     dfree(ctx->src_off);
+    dfree(ctx->src_order);
     dfree(ctx->t_t);
     dfree(ctx->t_eta);
     dfree(ctx->t_sig);
@@ -426,6 +427,24 @@ extern "C" int agis_load_observations(agis_ctx_t* ctx, const agis_obs_soa_t* obs
         free_store(ctx);
         ctx->err = keep;
         return rc;
+    }
+    {
+        // launch order of the sources in the S pass: by decreasing number of
+        // observations, so that the sources sharing a wavefront (and its
+        // loop trip count) have nearly equal counts (ties by index)
+        std::vector<int64_t> h_off(n_src + 1);
+        HIPCHK(hipMemcpyAsync(h_off.data(), ctx->src_off, (n_src + 1) * sizeof(int64_t), hipMemcpyDeviceToHost,
+                              ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        std::vector<int32_t> order(n_src);
+        for (int64_t i = 0; i < n_src; ++i) order[i] = (int32_t)i;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+            return h_off[x + 1] - h_off[x] > h_off[y + 1] - h_off[y];
+        });
+        ALLOC(ctx->src_order, std::max<int64_t>(n_src, 1), "source order");
+        HIPCHK(hipMemcpyAsync(ctx->src_order, order.data(), n_src * sizeof(int32_t), hipMemcpyHostToDevice,
+                              ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
     }
     if (ctx->cfg.robust) {
         // the inner iteration's by-source columns (A, h, sigma~^2), also

@@ -56,11 +56,13 @@ __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n
                                                        const double* __restrict__ c, double* __restrict__ s,
                                                        SrcPrep* __restrict__ prep, double* __restrict__ ds,
                                                        double* __restrict__ qsrc, int32_t* __restrict__ sdef,
-                                                       double* __restrict__ svar) {
+                                                       double* __restrict__ svar, const int32_t* __restrict__ order) {
     constexpr int GPB = 256 / G;
     const int gl = threadIdx.x % G;
-    const int64_t i = (int64_t)blockIdx.x * GPB + threadIdx.x / G;
-    const bool valid = i < n_src;
+    // group k takes the k-th source of the launch order
+    const int64_t kg = (int64_t)blockIdx.x * GPB + threadIdx.x / G;
+    const bool valid = kg < n_src;
+    const int64_t i = valid ? order[kg] : 0;
     double alpha = 0.0, delta = 0.0, plx = 0.0, pma = 0.0, pmd = 0.0;
     int64_t l0 = 0, l1 = 0;
     if (valid) {
@@ -614,7 +616,7 @@ inline int groups_grid(int64_t n_items, int items_per_block) {
     (ctx->cfg.precision == AGIS_MIXED ? k_source_update<G, true> : k_source_update<G, false>)                  \
         <<<groups_grid(ctx->n_src, 256 / G), 256, 0, ctx->stream>>>(                                           \
         ctx->k, ctx->n_src, ctx->src_off, ctx->s_t, ctx->s_eta, ctx->s_sig, ctx->s_cell, ctx->s_ell, ctx->knots, \
-        ctx->ktab, ctx->a, ctx->c, ctx->s, ctx->prep, ctx->ds, ctx->qsrc, ctx->sdef, ctx->svar)
+        ctx->ktab, ctx->a, ctx->c, ctx->s, ctx->prep, ctx->ds, ctx->qsrc, ctx->sdef, ctx->svar, ctx->src_order)
 
 void launch_source_update(agis_ctx* ctx) {
     if (ctx->n_src == 0) return;

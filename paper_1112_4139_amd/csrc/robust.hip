@@ -206,11 +206,13 @@ __global__ __launch_bounds__(256, 2) void k_s_rows(DevConsts k, int64_t n_src, c
                                                    const KnotTab* __restrict__ ktab, const double* __restrict__ a,
                                                    const double* __restrict__ c, const double* __restrict__ s,
                                                    const double* __restrict__ eps_a2, int eps_bucket,
-                                                   double* __restrict__ col, int64_t n_obs) {
+                                                   double* __restrict__ col, int64_t n_obs,
+                                                   const int32_t* __restrict__ order) {
     constexpr int GPB = 256 / G;
     const int gl = threadIdx.x % G;
-    const int64_t i = (int64_t)blockIdx.x * GPB + threadIdx.x / G;
-    if (i >= n_src) return;
+    const int64_t kg = (int64_t)blockIdx.x * GPB + threadIdx.x / G;
+    if (kg >= n_src) return;
+    const int64_t i = order[kg];
     const double* si = s + 5 * i;
     const double alpha = si[0], delta = si[1], plx = si[2], pma = si[3], pmd = si[4];
     double sa, ca, sd, cd;
@@ -245,10 +247,10 @@ __global__ __launch_bounds__(256, 2) void k_s_rows(DevConsts k, int64_t n_src, c
 template <bool REG>
 __global__ __launch_bounds__(64) void k_s_sigma(int64_t n_src, const int64_t* __restrict__ off,
                                                 const double* __restrict__ h, double* __restrict__ vs,
-                                                int64_t reg_limit) {
+                                                int64_t reg_limit, const int32_t* __restrict__ order) {
     __shared__ uint32_t hist[256];
-    const int64_t i = blockIdx.x;
-    if (i >= n_src) return;
+    if ((int64_t)blockIdx.x >= n_src) return;
+    const int64_t i = order[blockIdx.x];         // the largest sets first
     const int64_t l0 = off[i], n = off[i + 1] - l0;
     double q5, q1;
     if (REG && n <= reg_limit) {
@@ -272,12 +274,13 @@ __global__ __launch_bounds__(256) void k_s_irls(int64_t n_src, const int64_t* __
                                                 const double* __restrict__ vs, double* __restrict__ s,
                                                 SrcPrep* __restrict__ prep, double* __restrict__ ds,
                                                 double* __restrict__ qsrc, int32_t* __restrict__ sdef,
-                                                double* __restrict__ svar) {
+                                                double* __restrict__ svar, const int32_t* __restrict__ order) {
     constexpr int GPB = 256 / G;
     const int gl = threadIdx.x % G;
     const int leader = (threadIdx.x & 63) & ~(G - 1);
-    const int64_t i = (int64_t)blockIdx.x * GPB + threadIdx.x / G;
-    const bool valid = i < n_src;
+    const int64_t kg = (int64_t)blockIdx.x * GPB + threadIdx.x / G;
+    const bool valid = kg < n_src;
+    const int64_t i = valid ? order[kg] : 0;
     const int64_t l0 = valid ? off[i] : 0, l1 = valid ? off[i + 1] : 0;
     const double vsi = valid ? vs[i] : 0.0;
     double d[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -409,11 +412,11 @@ inline unsigned groups_grid(int64_t n_items, int items_per_block) {
 #define AGIS_ROWS_LAUNCH(G)                                                                                      \
     k_s_rows<G><<<groups_grid(ctx->n_src, 256 / G), 256, 0, ctx->stream>>>(                                      \
         ctx->k, ctx->n_src, ctx->src_off, ctx->s_t, ctx->s_eta, ctx->s_sig, ctx->s_cell, ctx->s_ell, ctx->knots,   \
-        ctx->ktab, ctx->a, ctx->c, ctx->s, ctx->eps_a2, ctx->cfg.eps_bucket, ctx->rcol, ctx->n_obs)
+        ctx->ktab, ctx->a, ctx->c, ctx->s, ctx->eps_a2, ctx->cfg.eps_bucket, ctx->rcol, ctx->n_obs, ctx->src_order)
 #define AGIS_IRLS_LAUNCH(G)                                                                                      \
     k_s_irls<G><<<groups_grid(ctx->n_src, 256 / G), 256, 0, ctx->stream>>>(                                      \
         ctx->n_src, ctx->src_off, ctx->rcol, ctx->n_obs, ctx->vs, ctx->s, ctx->prep, ctx->ds, ctx->qsrc, ctx->sdef, \
-        ctx->svar)
+        ctx->svar, ctx->src_order)
 
 void launch_source_update_robust(agis_ctx* ctx) {
     if (ctx->n_src == 0) return;
@@ -425,7 +428,7 @@ void launch_source_update_robust(agis_ctx* ctx) {
     }
     (select_in_registers(ctx, ctx->n_obs, ctx->n_src) ? k_s_sigma<true> : k_s_sigma<false>)
         <<<(unsigned)ctx->n_src, 64, 0, ctx->stream>>>(ctx->n_src, ctx->src_off, ctx->rcol + 4 * ctx->n_obs, ctx->vs,
-                                                       select_reg_limit(ctx));
+                                                       select_reg_limit(ctx), ctx->src_order);
     switch (ctx->s_group) {
         case 8: AGIS_IRLS_LAUNCH(8); break;
         case 16: AGIS_IRLS_LAUNCH(16); break;
