@@ -348,10 +348,15 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
         // the wavefront's LDS operations complete in order: the rows just
         // written are read back below by other lanes of the same wavefront
         __asm__ volatile("" ::: "memory");
+        // groups of four observations past the interval's end hold padding
+        // rows of weight zero: their matrix-core steps would add zeros
+        const int64_t n_here = l1 - base < 64 ? l1 - base : 64;
+        const int steps = (int)((n_here + 3) >> 2);
         if constexpr (MIXED) {
             float4_t Ck = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int kk = 0; kk < 16; ++kk) {
+                if (kk >= steps) break;
                 const float av = xw[4 * kk + rk][ri];
                 const float bv = xw[4 * kk + rk][16 + ri];
                 Ck = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, Ck, 0, 0, 0);
@@ -366,6 +371,7 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
         } else {
 #pragma unroll
             for (int kk = 0; kk < 16; ++kk) {
+                if (kk >= steps) break;
                 const double av = xw[4 * kk + rk][ri];
                 const double bv = xw[4 * kk + rk][16 + ri];
                 C = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, C, 0, 0, 0);
