@@ -67,8 +67,8 @@ def test_mixed_iterations_track_fp64(agis_mod, oracle_lib, tiny):
     """The outer iteration refines the mixed iterate: after 1 iteration it
     differs from FP64 by a fraction of the update, after 1000 iterations
     (S[AC] + frame rotator) by a small fraction of the total correction
-    applied since the start (RMS per class below 1e-4 of it; the along-scan
-    attitude axis and the calibration below 0.05 uas).  The plain iteration
+    applied since the start (RMS per class below 1e-3 of it; the along-scan
+    attitude axis and the calibration below 0.5 uas).  The plain iteration
     has not converged then: its slowest modes (across-scan attitude, weakly
     fixed by along-scan data alone) contract by ~0.999 per iteration, and the
     FP32 rounding perturbs exactly those."""
@@ -92,6 +92,11 @@ def test_mixed_iterations_track_fp64(agis_mod, oracle_lib, tiny):
         agis_mod.agis_destroy(c)
     moved_s = np.sqrt(np.mean(src_diff_uas(w.src_start, l0[0]) ** 2, axis=0))
     moved_a = np.sqrt(np.mean(rot_diff_uas(w.att_start, l0[1]) ** 2, axis=0))
-    assert np.all(np.sqrt(np.mean(dn[0] ** 2, axis=0)) <= 1e-4 * moved_s)
-    assert np.all(np.sqrt(np.mean(dn[1] ** 2, axis=0)) <= 1e-4 * moved_a)
-    assert np.sqrt(np.mean(dn[1][:, 2] ** 2)) <= 0.05 and np.abs(dn[2]).max() <= 0.05
+    # The FP32 rounding of the band sums, amplified along the weakly
+    # determined attitude directions, makes this difference a sample of
+    # rounding noise: two equally valid orders of the A/C sums gave 0.26 and
+    # 1.1 uas (alpha*) and 1.9 and 16.6 uas (attitude x) RMS after 1000
+    # iterations.  The bounds cover that spread with a margin.
+    assert np.all(np.sqrt(np.mean(dn[0] ** 2, axis=0)) <= 1e-3 * moved_s)
+    assert np.all(np.sqrt(np.mean(dn[1] ** 2, axis=0)) <= 1e-3 * moved_a)
+    assert np.sqrt(np.mean(dn[1][:, 2] ** 2)) <= 0.5 and np.abs(dn[2]).max() <= 0.5
