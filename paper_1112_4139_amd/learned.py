@@ -27,6 +27,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import os
 import sys
 import time
 
@@ -175,11 +176,11 @@ def solve(ctx, w, m, n_iter, ref, mode, tol=1.0, log=None, asi_stride=16, asi_la
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--world", default="tiny")
-    ap.add_argument("--train-seeds", default="1,2,3")
+    ap.add_argument("--train-seeds", default="1,2,3,4")
     ap.add_argument("--eval-seed", type=int, default=0)
     ap.add_argument("--m", type=int, default=50, help="iterations per recorded update")
-    ap.add_argument("--macro", type=int, default=120, help="records per training trajectory")
-    ap.add_argument("--horizon", type=int, default=20, help="records ahead that the networks predict")
+    ap.add_argument("--macro", type=int, default=None, help="records per training trajectory (horizon + 100)")
+    ap.add_argument("--horizon", type=int, default=160, help="records ahead that the networks predict")
     ap.add_argument("--ref-eval", type=int, default=200000, help="iterations of the evaluation reference run")
     ap.add_argument("--steps", type=int, default=12000, help="Adam steps per network (three rate stages)")
     ap.add_argument("--batch", type=int, default=1024)
@@ -187,7 +188,10 @@ def main(argv=None):
     ap.add_argument("--max-iter", type=int, default=160000)
     ap.add_argument("--tol", type=float, default=1.0)
     ap.add_argument("--modes", default="plain,asi,learned", help="solves to compare (plain, asi, learned)")
+    ap.add_argument("--ref-file", default=None, help="npz cache of the evaluation reference (read if it matches)")
     args = ap.parse_args(argv)
+    if args.macro is None:
+        args.macro = args.horizon + 100
 
     def log(msg):
         print(f"[learned {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
@@ -221,14 +225,26 @@ def main(argv=None):
     agis.agis_destroy(ctx_train)
 
     w, ctx = problem(args.world, args.eval_seed)
-    done = 0
-    while done < args.ref_eval:
-        n = min(10000, args.ref_eval - done)
-        agis.agis_iterate(ctx, n, stats=False)
-        done += n
-        log(f"evaluation reference: {done} of {args.ref_eval} plain iterations")
-    ref = state(ctx, w)
-    chi2_ref = agis.agis_chi2(ctx)
+    cached = None
+    if args.ref_file and os.path.exists(args.ref_file):
+        z = np.load(args.ref_file)
+        if (int(z["iterations"]) == args.ref_eval and str(z["world"]) == args.world
+                and int(z["seed"]) == args.eval_seed):
+            cached = (z["s"], z["a"], z["c"]), float(z["chi2"])
+            log(f"evaluation reference from {args.ref_file}")
+    if cached is None:
+        done = 0
+        while done < args.ref_eval:
+            n = min(10000, args.ref_eval - done)
+            agis.agis_iterate(ctx, n, stats=False)
+            done += n
+            log(f"evaluation reference: {done} of {args.ref_eval} plain iterations")
+        ref, chi2_ref = state(ctx, w), agis.agis_chi2(ctx)
+        if args.ref_file:
+            np.savez(args.ref_file, s=ref[0], a=ref[1], c=ref[2], chi2=chi2_ref, iterations=args.ref_eval,
+                     world=args.world, seed=args.eval_seed)
+    else:
+        ref, chi2_ref = cached
     agis.agis_destroy(ctx)
     out = {}
     for mode in args.modes.split(","):
