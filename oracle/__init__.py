@@ -112,6 +112,7 @@ def lib(precision="double"):
         L.orc_num_segments.restype = c_i64
         L.orc_calibration_update.argtypes = [P(World), P(Obs), P(State), P(c_r)]
         L.orc_iterate_sac.argtypes = [P(World), P(Obs), P(State), P(c_r)]
+        L.orc_normal_rhs.argtypes = [P(World), P(Obs), P(State), P(c_r), P(c_r), P(c_r)]
         L.orc_frame_fit.argtypes = [P(World), P(State), P(c_r), P(c_r), P(c_r)]
         L.orc_frame_apply.argtypes = [P(World), P(State), P(c_r)]
         L.orc_weight_function.argtypes = [c_r]
@@ -362,6 +363,15 @@ class Problem:
         self._L.orc_calibration_update(ctypes.byref(self.world), ctypes.byref(self.obs), ctypes.byref(self.state),
                                        _p(d, self._cr))
         return d
+
+    def normal_rhs(self):
+        """Right-hand sides of the S, A and C normal equations at the current
+        state: (rs [n_src][5], ra [n_att][4], rc [n_cells])."""
+        rs, ra, rc = self._zeros(self.s.shape), self._zeros(self.a.shape), self._zeros(self.c.shape)
+        cr = self._cr
+        self._L.orc_normal_rhs(ctypes.byref(self.world), ctypes.byref(self.obs), ctypes.byref(self.state),
+                               _p(rs, cr), _p(ra, cr), _p(rc, cr))
+        return rs, ra, rc
 
     def iterate_sac(self):
         self.var = self._zeros((self.s.shape[0], 5))

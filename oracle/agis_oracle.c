@@ -760,6 +760,42 @@ void orc_iterate_sac(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st
 }
 
 /* ========================================================================
+ * Right-hand sides of the three normal-equation blocks at the current state
+ * (eq:normS, eq:normAmod with the regularisation of eq:JfuncMod, eq:normC),
+ * summed over all observations: the vector b - N x of the linearised
+ * problem that the conjugate-gradient scheme of Sect. 4.7 works with.
+ * rs: [n_src][5] sum A' W R with A the design row -dR/ds; ra: [n_att][4]
+ * -sum (dR/da R + lambda^2 dD/da D) W; rc: [n_cells] -sum R W.  Not robust:
+ * W = 1 / sigma^2 in all three, as in the block solves.
+ * ====================================================================== */
+void orc_normal_rhs(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, double* rs, double* ra,
+                    double* rc) {
+    const double lam2 = w->lambda_reg * w->lambda_reg;
+    memset(rs, 0, sizeof(double) * (size_t)(5 * st->n_src));
+    memset(ra, 0, sizeof(double) * (size_t)(4 * st->n_att));
+    memset(rc, 0, sizeof(double) * (size_t)st->n_cells);
+    for (int64_t l = 0; l < obs->n; ++l) {
+        orc_fwd_t o;
+        forward_one(w, obs, st, l, &o);
+        double W = weight(w, obs, st, l, &o);
+        double A[5], g[4];
+        source_partials(&o, A);
+        attitude_partial(&o, g);
+        double* bs = rs + 5 * (int64_t)obs->src[l];
+        for (int k = 0; k < 5; ++k) bs[k] += A[k] * W * o.R;
+        for (int kn = 0; kn < M_ORDER; ++kn) {
+            double* bn = ra + 4 * (o.ell - (M_ORDER - 1) + kn);
+            for (int r = 0; r < 4; ++r) {
+                double dR = o.B[kn] * g[r];
+                double dD = -2.0 * o.qraw[r] * o.B[kn];
+                bn[r] -= (dR * o.R + lam2 * dD * o.D) * W;
+            }
+        }
+        rc[obs->cell[l]] -= 1.0 * o.R * W;
+    }
+}
+
+/* ========================================================================
  * Sect. 6.1: frame rotator.
  * Fit: least squares of eq:cond-mu3 over all sources taken as S_PM,
  * comparison epoch t = t_ep, with the position differences of eq:fr-Delta1

@@ -128,6 +128,11 @@ void orc_calibration_update(const orc_world_t* w, const orc_obs_t* obs, orc_stat
 /* S[AC]: S, then A and C from the same post-S residuals. */
 void orc_iterate_sac(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st, double* var);
 
+/* Right-hand sides b - N x of the S, A and C normal equations at the current
+ * state, summed over all observations (no robust weighting). */
+void orc_normal_rhs(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, double* rs, double* ra,
+                    double* rc);
+
 /* --- Sect. 6.1: frame rotator --------------------------------------------- */
 /* eps_omega = (eps_X, eps_Y, eps_Z [rad], omega_X, omega_Y, omega_Z [rad/yr]).
  * var[n_src][5] (may be NULL: unit weights) weights each condition equation

@@ -1,0 +1,114 @@
+"""Preconditioned conjugate gradients for AGIS (Sect. 4.7) on the oracle --
+TEST INFRASTRUCTURE ONLY (tests, smoke check and benchmark baseline).
+
+The paper names conjugate gradients as its baseline scheme and states that
+it uses the same S, A and C block solves as the simple iteration in the role
+of the preconditioner K, but leaves the algorithm to a companion paper.  The
+scheme here is the textbook preconditioned CG (Polak-Ribiere form) for the
+normal equations N x = b of the problem linearised at the current
+parameters, with these definitions:
+
+* unknowns: sources (d alpha*, d delta, d parallax, d mu_alpha*, d mu_delta),
+  attitude coefficients, calibration parameters; a step v moves the state as
+  the block updates do (alpha by v_alpha* / cos delta, the rest additively);
+* r(x): the right-hand sides b - N x of the three blocks at state x
+  (Problem.normal_rhs);
+* z(x) = K^-1 r(x): the S, A and C block updates computed at one and the
+  same state x (block Jacobi: A and C do not see the S update);
+* N p is not formed: for the linear problem r(x + p) = r(x) - N p and
+  z(x + p) = z(x) - K^-1 N p, so one evaluation of (r, z) at the trial point
+  x + p per iteration gives every quantity of the recurrences:
+      alpha = r'z / p'(r - r(x + p))
+      x <- x + alpha p
+      r <- (1 - alpha) r + alpha r(x + p),  z <- (1 - alpha) z + alpha z(x + p)
+      beta = max(0, r'(z - z_old) / r_old'z_old)      (Polak-Ribiere)
+      p <- z + beta p
+* a cycle starts with one evaluation at x itself (r, z, p = z) after the
+  frame rotator, when a frame reference is given, has been applied; it runs
+  `restart` iterations, then the next call starts a new cycle.  A
+  non-positive or non-finite p'N p also starts a new cycle.
+
+Each evaluation costs one pass of every block: the same work as one simple
+iteration.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def step_state(s, a, c, v, f, n_src, n_att):
+    """State moved by f v (v in the unknowns' coordinates)."""
+    vs = v[:5 * n_src].reshape(n_src, 5)
+    s2 = s.copy()
+    s2[:, 0] = s[:, 0] + f * vs[:, 0] / np.cos(s[:, 1])
+    s2[:, 1:] = s[:, 1:] + f * vs[:, 1:]
+    a2 = a + f * v[5 * n_src:5 * n_src + 4 * n_att].reshape(n_att, 4)
+    c2 = c + f * v[5 * n_src + 4 * n_att:]
+    return s2, a2, c2
+
+
+def evaluate(pr):
+    """(r, z) at the problem's current state, which is left unchanged."""
+    s, a, c = pr.s.copy(), pr.a.copy(), pr.c.copy()
+    rs, ra, rc = pr.normal_rhs()
+    zs, _, _ = pr.source_update()
+    pr.set_state(s=s)
+    za, _ = pr.attitude_update()
+    pr.set_state(a=a)
+    zc = pr.calibration_update()
+    pr.set_state(c=c)
+    return np.concatenate([rs.ravel(), ra.ravel(), rc]), np.concatenate([zs.ravel(), za.ravel(), zc])
+
+
+class CG:
+    """Iteration state of the scheme; run() advances the Problem's state."""
+
+    def __init__(self, pr, restart=40, s_ref=None):
+        self.pr, self.restart, self.s_ref = pr, int(restart), s_ref
+        self.k = 0                     # iterations done in the current cycle (0: a cycle starts next)
+        self.r = self.z = self.p = None
+        self.rho = 0.0
+        self.alpha = self.beta = 0.0
+        self.n_eval = 0
+
+    def _dims(self):
+        return self.pr.s.shape[0], self.pr.a.shape[0]
+
+    def step(self):
+        """One evaluation: the start of a cycle or one CG iteration."""
+        pr = self.pr
+        ns, na = self._dims()
+        self.n_eval += 1
+        if self.k == 0:
+            if self.s_ref is not None:
+                pr.frame_apply(pr.frame_fit(self.s_ref))
+            self.r, self.z = evaluate(pr)
+            self.p = self.z.copy()
+            self.rho = self.r @ self.z
+            self.alpha = self.beta = 0.0
+            self.k = 1 if self.restart > 0 else 0
+            return
+        x = (pr.s.copy(), pr.a.copy(), pr.c.copy())
+        pr.set_state(*step_state(*x, self.p, 1.0, ns, na))
+        ry, zy = evaluate(pr)
+        pq = self.p @ (self.r - ry)
+        if not (np.isfinite(pq) and pq > 0.0):
+            pr.set_state(*x)
+            self.k = 0
+            self.alpha = self.beta = 0.0
+            return
+        alpha = self.rho / pq
+        pr.set_state(*step_state(*x, self.p, alpha, ns, na))
+        r = (1.0 - alpha) * self.r + alpha * ry
+        z = (1.0 - alpha) * self.z + alpha * zy
+        rho = r @ z
+        beta = (rho - r @ self.z) / self.rho if self.rho != 0.0 else 0.0
+        beta = max(beta, 0.0)
+        self.p = z + beta * self.p
+        self.r, self.z, self.rho = r, z, rho
+        self.alpha, self.beta = alpha, beta
+        self.k = self.k + 1 if self.k < self.restart else 0
+
+    def run(self, n_eval):
+        for _ in range(int(n_eval)):
+            self.step()
