@@ -113,6 +113,8 @@ def lib(precision="double"):
         L.orc_calibration_update.argtypes = [P(World), P(Obs), P(State), P(c_r)]
         L.orc_iterate_sac.argtypes = [P(World), P(Obs), P(State), P(c_r)]
         L.orc_normal_rhs.argtypes = [P(World), P(Obs), P(State), P(c_r), P(c_r), P(c_r)]
+        L.orc_normal_quadratic.argtypes = [P(World), P(Obs), P(State), P(c_r)]
+        L.orc_normal_quadratic.restype = c_r
         L.orc_frame_fit.argtypes = [P(World), P(State), P(c_r), P(c_r), P(c_r)]
         L.orc_frame_apply.argtypes = [P(World), P(State), P(c_r)]
         L.orc_weight_function.argtypes = [c_r]
@@ -372,6 +374,14 @@ class Problem:
         self._L.orc_normal_rhs(ctypes.byref(self.world), ctypes.byref(self.obs), ctypes.byref(self.state),
                                _p(rs, cr), _p(ra, cr), _p(rc, cr))
         return rs, ra, rc
+
+    def normal_quadratic(self, v):
+        """v' N v for the normal matrix of the three blocks at the current
+        state (v: sources, then attitude, then calibration unknowns)."""
+        v = self._arr(v)
+        assert v.size == 5 * self.s.shape[0] + 4 * self.a.shape[0] + self.c.size
+        return self._L.orc_normal_quadratic(ctypes.byref(self.world), ctypes.byref(self.obs),
+                                            ctypes.byref(self.state), _p(v, self._cr))
 
     def iterate_sac(self):
         self.var = self._zeros((self.s.shape[0], 5))

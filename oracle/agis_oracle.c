@@ -795,6 +795,38 @@ void orc_normal_rhs(const orc_world_t* w, const orc_obs_t* obs, const orc_state_
     }
 }
 
+/* The quadratic form v' N v of the normal matrix of the three blocks at the
+ * current state: sum over the observations of W (J_R v)^2 + lambda^2 W
+ * (J_D v)^2, with J_R v = -A . v_src + sum_n B_n dR/dq . v_att(n) + v_cal
+ * (A the design row -dR/ds) and J_D v = sum_n -2 q~ B_n . v_att(n).
+ * v: [n_src][5], then [n_att][4], then [n_cells]. */
+double orc_normal_quadratic(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, const double* v) {
+    const double lam2 = w->lambda_reg * w->lambda_reg;
+    const double* va = v + 5 * st->n_src;
+    const double* vc = va + 4 * st->n_att;
+    double sum = 0.0;
+    for (int64_t l = 0; l < obs->n; ++l) {
+        orc_fwd_t o;
+        forward_one(w, obs, st, l, &o);
+        double W = weight(w, obs, st, l, &o);
+        double A[5], g[4];
+        source_partials(&o, A);
+        attitude_partial(&o, g);
+        const double* vs = v + 5 * (int64_t)obs->src[l];
+        double jr = vc[obs->cell[l]], jd = 0.0;
+        for (int k = 0; k < 5; ++k) jr -= A[k] * vs[k];
+        for (int kn = 0; kn < M_ORDER; ++kn) {
+            const double* vn = va + 4 * (o.ell - (M_ORDER - 1) + kn);
+            for (int r = 0; r < 4; ++r) {
+                jr += o.B[kn] * g[r] * vn[r];
+                jd += -2.0 * o.qraw[r] * o.B[kn] * vn[r];
+            }
+        }
+        sum += W * jr * jr + lam2 * W * jd * jd;
+    }
+    return sum;
+}
+
 /* ========================================================================
  * Sect. 6.1: frame rotator.
  * Fit: least squares of eq:cond-mu3 over all sources taken as S_PM,

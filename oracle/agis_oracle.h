@@ -133,6 +133,10 @@ void orc_iterate_sac(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st
 void orc_normal_rhs(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, double* rs, double* ra,
                     double* rc);
 
+/* v' N v for the normal matrix of the S, A and C blocks at the current state;
+ * v holds the source, then the attitude, then the calibration unknowns. */
+double orc_normal_quadratic(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, const double* v);
+
 /* --- Sect. 6.1: frame rotator --------------------------------------------- */
 /* eps_omega = (eps_X, eps_Y, eps_Z [rad], omega_X, omega_Y, omega_Z [rad/yr]).
  * var[n_src][5] (may be NULL: unit weights) weights each condition equation

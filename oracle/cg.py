@@ -15,21 +15,22 @@ parameters, with these definitions:
   (Problem.normal_rhs);
 * z(x) = K^-1 r(x): the S, A and C block updates computed at one and the
   same state x (block Jacobi: A and C do not see the S update);
-* N p is not formed: for the linear problem r(x + p) = r(x) - N p and
-  z(x + p) = z(x) - K^-1 N p, so one evaluation of (r, z) at the trial point
-  x + p per iteration gives every quantity of the recurrences:
-      alpha = r'z / p'(r - r(x + p))
-      x <- x + alpha p
-      r <- (1 - alpha) r + alpha r(x + p),  z <- (1 - alpha) z + alpha z(x + p)
+* p'N p: the quadratic form of the normal matrix at the current state
+  (Problem.normal_quadratic), the one product with N the recurrences need;
+* an iteration:
+      alpha = r'z / p'N p,  x <- x + alpha p,  (r, z) <- (r(x), z(x))
       beta = max(0, r'(z - z_old) / r_old'z_old)      (Polak-Ribiere)
       p <- z + beta p
-* a cycle starts with one evaluation at x itself (r, z, p = z) after the
-  frame rotator, when a frame reference is given, has been applied; it runs
-  `restart` iterations, then the next call starts a new cycle.  A
-  non-positive or non-finite p'N p also starts a new cycle.
+  r and z are evaluated at each new iterate rather than updated by
+  recurrences, so the model's slight non-linearity and rounding do not
+  accumulate in them;
+* a cycle starts with the frame rotator, when a frame reference is given,
+  and one evaluation at x (r, z, p = z); it runs `restart` iterations, then
+  the next step starts a new cycle.  A non-positive or non-finite p'N p
+  leaves x unchanged and starts a new cycle.
 
-Each evaluation costs one pass of every block: the same work as one simple
-iteration.
+An iteration costs one pass of every block (as one simple iteration does)
+plus one pass over the observations for p'N p.
 """
 from __future__ import annotations
 
@@ -61,7 +62,8 @@ def evaluate(pr):
 
 
 class CG:
-    """Iteration state of the scheme; run() advances the Problem's state."""
+    """Iteration state of the scheme; step() and run() advance the Problem's
+    state."""
 
     def __init__(self, pr, restart=40, s_ref=None):
         self.pr, self.restart, self.s_ref = pr, int(restart), s_ref
@@ -69,16 +71,11 @@ class CG:
         self.r = self.z = self.p = None
         self.rho = 0.0
         self.alpha = self.beta = 0.0
-        self.n_eval = 0
-
-    def _dims(self):
-        return self.pr.s.shape[0], self.pr.a.shape[0]
 
     def step(self):
-        """One evaluation: the start of a cycle or one CG iteration."""
+        """The start of a cycle or one CG iteration (one evaluation each)."""
         pr = self.pr
-        ns, na = self._dims()
-        self.n_eval += 1
+        ns, na = pr.s.shape[0], pr.a.shape[0]
         if self.k == 0:
             if self.s_ref is not None:
                 pr.frame_apply(pr.frame_fit(self.s_ref))
@@ -86,21 +83,16 @@ class CG:
             self.p = self.z.copy()
             self.rho = self.r @ self.z
             self.alpha = self.beta = 0.0
-            self.k = 1 if self.restart > 0 else 0
+            self.k = 1
             return
-        x = (pr.s.copy(), pr.a.copy(), pr.c.copy())
-        pr.set_state(*step_state(*x, self.p, 1.0, ns, na))
-        ry, zy = evaluate(pr)
-        pq = self.p @ (self.r - ry)
-        if not (np.isfinite(pq) and pq > 0.0):
-            pr.set_state(*x)
+        pnp = pr.normal_quadratic(self.p)
+        if not (np.isfinite(pnp) and pnp > 0.0):
             self.k = 0
             self.alpha = self.beta = 0.0
             return
-        alpha = self.rho / pq
-        pr.set_state(*step_state(*x, self.p, alpha, ns, na))
-        r = (1.0 - alpha) * self.r + alpha * ry
-        z = (1.0 - alpha) * self.z + alpha * zy
+        alpha = self.rho / pnp
+        pr.set_state(*step_state(pr.s, pr.a, pr.c, self.p, alpha, ns, na))
+        r, z = evaluate(pr)
         rho = r @ z
         beta = (rho - r @ self.z) / self.rho if self.rho != 0.0 else 0.0
         beta = max(beta, 0.0)
@@ -109,6 +101,6 @@ class CG:
         self.alpha, self.beta = alpha, beta
         self.k = self.k + 1 if self.k < self.restart else 0
 
-    def run(self, n_eval):
-        for _ in range(int(n_eval)):
+    def run(self, n):
+        for _ in range(int(n)):
             self.step()
