@@ -147,6 +147,16 @@ typedef struct {
     double ms;               /* device time of the whole iteration [ms] */
 } agis_iter_stats_t;
 
+/* One step of the conjugate-gradient scheme (agis_cg_iterate). */
+typedef struct {
+    double alpha;            /* step length taken (0 at the start of a cycle or on breakdown) */
+    double beta;             /* coefficient of the previous direction in the new one */
+    double rho;              /* r'z after the step */
+    int32_t cycle_start;     /* 1: this evaluation started a cycle (frame rotator, r, z, p = z at x) */
+    int32_t breakdown;       /* 1: p'N p <= 0 or not finite; no move, the next step starts a cycle */
+    double ms;               /* device time of the step [ms] */
+} agis_cg_stats_t;
+
 int agis_version(void);
 
 /* Create a context on cfg->device; copies *cfg and the knots. */
@@ -319,6 +329,41 @@ int agis_learned_step(agis_ctx_t* ctx, double* q_plain, double* q_cand, int32_t*
  * (else AGIS_E_INVALID_ARG); AGIS_E_STATE with fewer than two records.
  */
 int agis_asi_step(agis_ctx_t* ctx, int32_t stride, double lambda_max, double* lambda, double* factor);
+
+/*
+ * Conjugate gradients (Sect. 4.7: the paper's baseline scheme, built on the
+ * same S, A and C block solves as the simple iteration).  Preconditioned CG
+ * in the Polak-Ribiere form for the normal equations linearised at the
+ * current parameters, with these definitions:
+ *   unknowns: per source (d alpha*, d delta, d parallax, d mu_alpha*,
+ *     d mu_delta), per attitude coefficient its 4 components, per cell its
+ *     calibration; a step v moves alpha by v_alpha* / cos delta and every
+ *     other parameter additively;
+ *   r(x): the right-hand sides b - N x of eq:normS, eq:normAmod (with the
+ *     regularisation) and eq:normC at state x;
+ *   z(x) = K^-1 r(x): the S, A (overlapping segments) and C (with eq:calCon)
+ *     block updates, all three computed at the same state x (block Jacobi);
+ *   p'N p: the quadratic form of the normal matrix at the current state,
+ *     summed over the observations (weights 1 / sigma^2, the regularisation
+ *     terms with lambda^2);
+ *   an iteration: alpha = r'z / p'N p, x <- x + alpha p, r and z evaluated
+ *     at the new x, beta = max(0, r'(z - z_old) / r_old'z_old),
+ *     p <- z + beta p.
+ * A cycle starts with the frame rotator (when a frame reference is set) and
+ * one evaluation at x itself (r, z, p = z); it runs `restart` iterations.
+ * Each call performs n_eval steps (cycle starts and iterations alike; an
+ * iteration costs one pass of the three blocks, like one simple iteration,
+ * plus one pass over the observations for p'N p) and keeps the CG vectors
+ * for the next call; any other call that changes the parameters or the
+ * problem (set_*, loads, updates, iterations, frame application,
+ * accelerated or learned steps) makes the next step start a new cycle.  A
+ * non-positive or non-finite p'N p leaves x unchanged and ends the cycle.
+ * per_eval (optional, n_eval entries) receives the statistics of each step.
+ * restart >= 1 and n_eval >= 0 (else AGIS_E_INVALID_ARG); AGIS_E_STATE in
+ * the robust mode, whose observation weights change with the residuals (the
+ * paper switches between the simple iteration and CG for that reason).
+ */
+int agis_cg_iterate(agis_ctx_t* ctx, int32_t n_eval, int32_t restart, agis_cg_stats_t* per_eval);
 
 #ifdef __cplusplus
 }

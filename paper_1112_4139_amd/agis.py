@@ -53,6 +53,11 @@ class agis_iter_stats_t(ctypes.Structure):
                 ("eps_omega", c_d * 6), ("ms", c_d)]
 
 
+class agis_cg_stats_t(ctypes.Structure):
+    _fields_ = [("alpha", c_d), ("beta", c_d), ("rho", c_d), ("cycle_start", c_i32), ("breakdown", c_i32),
+                ("ms", c_d)]
+
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libagis.so not built at {LIB_PATH}; run __graft_entry__.build()")
 _lib = ctypes.CDLL(LIB_PATH)
@@ -99,6 +104,7 @@ _sig = {
     "agis_chi2": ([_ctx_p, P(c_d)], ctypes.c_int),
     "agis_learned_apply": ([_ctx_p], ctypes.c_int),
     "agis_asi_step": ([_ctx_p, ctypes.c_int32, c_d, P(c_d), P(c_d)], ctypes.c_int),
+    "agis_cg_iterate": ([_ctx_p, c_i32, c_i32, P(agis_cg_stats_t)], ctypes.c_int),
     "agis_learned_step": ([_ctx_p, P(c_d), P(c_d), P(c_i32)], ctypes.c_int),
 }
 for _name, (_args, _res) in _sig.items():
@@ -385,6 +391,18 @@ def agis_asi_step(ctx, stride=1, lambda_max=0.99):
     lam, f = c_d(), c_d()
     _check(_lib.agis_asi_step(ctx, int(stride), float(lambda_max), ctypes.byref(lam), ctypes.byref(f)), ctx)
     return dict(lam=lam.value, factor=f.value)
+
+
+def agis_cg_iterate(ctx, n_eval, restart=40, stats=True):
+    """n_eval evaluations of the conjugate-gradient scheme; per evaluation a
+    dict (alpha, beta, rho, cycle_start, breakdown, ms) when stats."""
+    if stats:
+        arr = (agis_cg_stats_t * max(int(n_eval), 1))()
+        _check(_lib.agis_cg_iterate(ctx, int(n_eval), int(restart), arr), ctx)
+        return [dict(alpha=x.alpha, beta=x.beta, rho=x.rho, cycle_start=x.cycle_start, breakdown=x.breakdown,
+                     ms=x.ms) for x in arr[:n_eval]]
+    _check(_lib.agis_cg_iterate(ctx, int(n_eval), int(restart), None), ctx)
+    return None
 
 
 def agis_learned_step(ctx):

@@ -135,6 +135,23 @@ struct agis_ctx {
     double* chi2_part = nullptr;         // [ceil(K / 64)]
     double* chi2_out = nullptr;          // [2]
 
+    // conjugate gradients (cg.hip): vectors over all unknowns, sources
+    // [n_src][5], then attitude [N][4], then calibration [n_cells]
+    double* rhs_s_out = nullptr;         // S pass: right-hand sides written here when set
+    double* cg_r = nullptr;              // b - N x at the current iterate
+    double* cg_z = nullptr;              // K^-1 r
+    double* cg_p = nullptr;              // search direction
+    double* cg_ry = nullptr;             // r and z at the new iterate (swapped with cg_r, cg_z)
+    double* cg_zy = nullptr;
+    double* cg_sy = nullptr;             // sources of the point being evaluated
+    double* cg_part = nullptr;           // reduction partials [CG_BLOCKS][2] and of p'N p
+    double* cg_qpart = nullptr;
+    double* cg_out = nullptr;            // results [2]
+    int cg_k = 0;                        // iterations done in the current cycle (0: a cycle starts)
+    double cg_rho = 0.0;                 // r'z
+    uint64_t cg_ver = 0;                 // state version the CG vectors belong to
+    uint64_t xver = 1;                   // bumped by every call that changes the state outside CG
+
     // lanes per source in the S block
     int s_group = 16;
     int64_t select_reg_limit = INT64_MAX;   // robust quantiles: register-held keys up to this count
@@ -180,12 +197,21 @@ void launch_round_weights(agis_ctx* ctx, int which);
 void launch_apply_candidate(agis_ctx* ctx, const float* Cs, const float* Ca);
 void launch_copy(agis_ctx* ctx, int64_t n, const double* src, double* dst);
 void launch_chi2(agis_ctx* ctx, double* part, double* out);
+// cg.hip
+int64_t cg_size(const agis_ctx* ctx);
+void launch_cg_gather(agis_ctx* ctx, double* r, double* z);
+void launch_cg_step_state(agis_ctx* ctx, const double* v, double f);
+void launch_cg_dot(agis_ctx* ctx, const double* a, const double* b, const double* c, double* out);
+void launch_cg_dot2(agis_ctx* ctx, const double* a, const double* b1, const double* b2, double* out);
+int64_t cg_quad_blocks(const agis_ctx* ctx);
+void launch_cg_quad(agis_ctx* ctx, const double* p, double* part, double* out);
+void launch_cg_direction(agis_ctx* ctx, double beta);
 // robust.hip
 void launch_source_update_robust(agis_ctx* ctx);
 void launch_excess_noise(agis_ctx* ctx);
 void launch_ac_pass(agis_ctx* ctx);
 void launch_band_solve(agis_ctx* ctx);
-void launch_calib_solve(agis_ctx* ctx);
+void launch_calib_solve(agis_ctx* ctx, double* rc = nullptr);   // rc: optional right-hand sides
 void launch_apply_attitude(agis_ctx* ctx);
 void launch_apply_calibration(agis_ctx* ctx);
 void launch_frame_fit(agis_ctx* ctx);

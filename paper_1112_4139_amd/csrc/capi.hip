@@ -118,6 +118,10 @@ static void free_store(agis_ctx* ctx) {
     }
     dfree(ctx->chi2_part);
     dfree(ctx->chi2_out);
+    for (double** v : {&ctx->cg_r, &ctx->cg_z, &ctx->cg_p, &ctx->cg_ry, &ctx->cg_zy, &ctx->cg_sy, &ctx->cg_part,
+                       &ctx->cg_qpart, &ctx->cg_out})
+        dfree(*v);
+    ctx->cg_k = 0;
     ctx->lh_count = 0;
     ctx->loaded = false;
     ctx->have_ref = false;
@@ -393,6 +397,7 @@ extern "C" void agis_destroy(agis_ctx_t* ctx) {
 extern "C" int agis_load_observations(agis_ctx_t* ctx, const agis_obs_soa_t* obs, int64_t n_src, int64_t n_cells,
                                       int where) {
     CHECK_CTX();
+    ++ctx->xver;
     if (!obs || n_src < 0 || n_cells < 0 || obs->n < 0) return set_error(ctx, AGIS_E_INVALID_ARG, "bad arguments");
     if (obs->n > 0 && (!obs->t || !obs->eta_obs || !obs->sigma || !obs->src || !obs->fov || !obs->cell))
         return set_error(ctx, AGIS_E_INVALID_ARG, "null observation column");
@@ -468,6 +473,7 @@ static int check_finite_host(agis_ctx* ctx, const double* x, int64_t n, int wher
 
 extern "C" int agis_set_sources(agis_ctx_t* ctx, int64_t n, const double* s5, int where) {
     CHECK_CTX();
+    ++ctx->xver;
     REQUIRE_LOADED();
     if (n != ctx->n_src || (!s5 && n > 0)) return set_error(ctx, AGIS_E_SHAPE, "source count mismatch");
     int rc = check_finite_host(ctx, s5, 5 * n, where);
@@ -488,6 +494,7 @@ extern "C" int agis_get_sources(agis_ctx_t* ctx, int64_t n, double* s5, int wher
 
 extern "C" int agis_set_attitude(agis_ctx_t* ctx, int64_t n, const double* a4, int where) {
     CHECK_CTX();
+    ++ctx->xver;
     if (n != ctx->N || !a4) return set_error(ctx, AGIS_E_SHAPE, "attitude coefficient count must be n_knots - 4");
     int rc = check_finite_host(ctx, a4, 4 * n, where);
     if (rc) return rc;
@@ -502,6 +509,7 @@ extern "C" int agis_get_attitude(agis_ctx_t* ctx, int64_t n, double* a4, int whe
 
 extern "C" int agis_set_calibration(agis_ctx_t* ctx, int64_t n, const double* c, int where) {
     CHECK_CTX();
+    ++ctx->xver;
     REQUIRE_LOADED();
     if (n != ctx->n_cells || (!c && n > 0)) return set_error(ctx, AGIS_E_SHAPE, "cell count mismatch");
     int rc = check_finite_host(ctx, c, n, where);
@@ -565,8 +573,10 @@ static int run_source(agis_ctx* ctx) {
 
 // A/C accumulation pass followed by the requested solves.  The A update is
 // applied only after the C solve has read the interval sums, so both blocks
-// see the same parameters (S[AC]).
-static int run_ac(agis_ctx* ctx, bool do_a, bool do_c, bool eps_update = false) {
+// see the same parameters (S[AC]).  apply = false leaves the updates in da
+// and dc; rc (optional) receives the calibration right-hand sides.
+static int run_ac(agis_ctx* ctx, bool do_a, bool do_c, bool eps_update = false, bool apply = true,
+                  double* rc = nullptr) {
     tstart(ctx, T_AC);
     if (eps_update && ctx->cfg.robust) launch_excess_noise(ctx);
     launch_ac_pass(ctx);
@@ -580,12 +590,12 @@ static int run_ac(agis_ctx* ctx, bool do_a, bool do_c, bool eps_update = false) 
     }
     if (do_c) {
         tstart(ctx, T_CAL);
-        launch_calib_solve(ctx);
+        launch_calib_solve(ctx, rc);
         HIPCHK(hipGetLastError());
         tstop(ctx, T_CAL);
     }
-    if (do_a) launch_apply_attitude(ctx);
-    if (do_c) launch_apply_calibration(ctx);
+    if (do_a && apply) launch_apply_attitude(ctx);
+    if (do_c && apply) launch_apply_calibration(ctx);
     HIPCHK(hipGetLastError());
     return AGIS_OK;
 }
@@ -617,6 +627,7 @@ static int stats_c(agis_ctx* ctx, agis_block_stats_t* st) {
 
 extern "C" int agis_source_update(agis_ctx_t* ctx, agis_block_stats_t* st) {
     CHECK_CTX();
+    ++ctx->xver;
     REQUIRE_LOADED();
     int rc = run_source(ctx);
     if (rc) return rc;
@@ -628,6 +639,7 @@ extern "C" int agis_source_update(agis_ctx_t* ctx, agis_block_stats_t* st) {
 
 extern "C" int agis_attitude_update(agis_ctx_t* ctx, agis_block_stats_t* st) {
     CHECK_CTX();
+    ++ctx->xver;
     REQUIRE_LOADED();
     int rc = run_ac(ctx, true, false);
     if (rc) return rc;
@@ -639,6 +651,7 @@ extern "C" int agis_attitude_update(agis_ctx_t* ctx, agis_block_stats_t* st) {
 
 extern "C" int agis_calibration_update(agis_ctx_t* ctx, agis_block_stats_t* st) {
     CHECK_CTX();
+    ++ctx->xver;
     REQUIRE_LOADED();
     int rc = run_ac(ctx, false, true);
     if (rc) return rc;
@@ -650,6 +663,7 @@ extern "C" int agis_calibration_update(agis_ctx_t* ctx, agis_block_stats_t* st) 
 
 extern "C" int agis_attitude_calibration_update(agis_ctx_t* ctx, agis_block_stats_t* st_a, agis_block_stats_t* st_c) {
     CHECK_CTX();
+    ++ctx->xver;
     REQUIRE_LOADED();
     int rc = run_ac(ctx, true, true);
     if (rc) return rc;
@@ -661,6 +675,7 @@ extern "C" int agis_attitude_calibration_update(agis_ctx_t* ctx, agis_block_stat
 
 extern "C" int agis_set_frame_reference(agis_ctx_t* ctx, int64_t n, const double* s_ref5, int where) {
     CHECK_CTX();
+    ++ctx->xver;
     REQUIRE_LOADED();
     if (n != ctx->n_src) return set_error(ctx, AGIS_E_SHAPE, "reference catalogue size must equal n_src");
     ++ctx->gen;
@@ -692,6 +707,7 @@ extern "C" int agis_frame_fit(agis_ctx_t* ctx, double eps_omega[6]) {
 
 extern "C" int agis_frame_apply(agis_ctx_t* ctx, const double eps_omega[6]) {
     CHECK_CTX();
+    ++ctx->xver;
     REQUIRE_LOADED();
     if (!eps_omega) return set_error(ctx, AGIS_E_INVALID_ARG, "null eps_omega");
     for (int e = 0; e < 6; ++e)
@@ -738,6 +754,7 @@ static int iterate_once(agis_ctx* ctx, agis_iter_stats_t* st) {
 
 extern "C" int agis_iterate(agis_ctx_t* ctx, int32_t n_iter, agis_iter_stats_t* per_iter) {
     CHECK_CTX();
+    ++ctx->xver;
     REQUIRE_LOADED();
     if (n_iter < 0) return set_error(ctx, AGIS_E_INVALID_ARG, "n_iter < 0");
     for (int32_t it = 0; it < n_iter; ++it) {
@@ -822,6 +839,7 @@ extern "C" int agis_autotune(agis_ctx_t* ctx, int32_t* s_group) {
 
 extern "C" int agis_iterate_graph(agis_ctx_t* ctx, int32_t n_iter) {
     CHECK_CTX();
+    ++ctx->xver;
     REQUIRE_LOADED();
     if (n_iter < 0) return set_error(ctx, AGIS_E_INVALID_ARG, "n_iter < 0");
     if (!ctx->graph_exec || ctx->graph_gen != ctx->gen) {
@@ -855,6 +873,7 @@ extern "C" int agis_iterate_graph(agis_ctx_t* ctx, int32_t n_iter) {
 
 extern "C" int agis_set_excess_noise(agis_ctx_t* ctx, int64_t n, const double* eps_a2, int where) {
     CHECK_CTX();
+    ++ctx->xver;
     if (!ctx->cfg.robust) return set_error(ctx, AGIS_E_STATE, "the context is not robust");
     if (n != ctx->n_buckets || !eps_a2) return set_error(ctx, AGIS_E_SHAPE, "bucket count mismatch");
     int rc = check_finite_host(ctx, eps_a2, n, where);
@@ -871,6 +890,7 @@ extern "C" int agis_get_excess_noise(agis_ctx_t* ctx, int64_t n, double* eps_a2,
 
 extern "C" int agis_excess_noise_update(agis_ctx_t* ctx) {
     CHECK_CTX();
+    ++ctx->xver;
     REQUIRE_LOADED();
     if (!ctx->cfg.robust) return set_error(ctx, AGIS_E_STATE, "the context is not robust");
     launch_excess_noise(ctx);
@@ -1160,6 +1180,7 @@ static void apply_candidate(agis_ctx* ctx) {
 
 extern "C" int agis_learned_apply(agis_ctx_t* ctx) {
     CHECK_CTX();
+    ++ctx->xver;
     REQUIRE_LOADED();
     if (!ctx->lh_ring_s || ctx->lh_count < 4) return set_error(ctx, AGIS_E_STATE, "fewer than four recorded updates");
     apply_candidate(ctx);
@@ -1172,6 +1193,7 @@ extern "C" int agis_learned_apply(agis_ctx_t* ctx) {
 
 extern "C" int agis_asi_step(agis_ctx_t* ctx, int32_t stride, double lambda_max, double* lambda, double* factor) {
     CHECK_CTX();
+    ++ctx->xver;
     REQUIRE_LOADED();
     if (stride < 1 || !(lambda_max >= 0.0 && lambda_max < 1.0))
         return set_error(ctx, AGIS_E_INVALID_ARG, "stride >= 1 and 0 <= lambda_max < 1");
@@ -1201,6 +1223,7 @@ extern "C" int agis_asi_step(agis_ctx_t* ctx, int32_t stride, double lambda_max,
 
 extern "C" int agis_learned_step(agis_ctx_t* ctx, double* q_plain, double* q_cand, int32_t* accepted) {
     CHECK_CTX();
+    ++ctx->xver;
     REQUIRE_LOADED();
     if (!ctx->lh_ring_s || ctx->lh_count < 4) return set_error(ctx, AGIS_E_STATE, "fewer than four recorded updates");
     // plain: x0 -> x1 by one iteration
@@ -1233,6 +1256,128 @@ extern "C" int agis_learned_step(agis_ctx_t* ctx, double* q_plain, double* q_can
     if (q_plain) *q_plain = q[0];
     if (q_cand) *q_cand = q[1];
     if (accepted) *accepted = acc ? 1 : 0;
+    return AGIS_OK;
+}
+
+// --- conjugate gradients (Sect. 4.7) ----------------------------------------
+// Preconditioned CG (Polak-Ribiere) for the normal equations linearised at
+// the current state.  K is the block-Jacobi form of the S, A and C blocks
+// (all three at one point); r and z are evaluated at every iterate, and
+// p'N p comes from one pass over the observations.
+
+static int cg_alloc(agis_ctx* ctx) {
+    if (ctx->cg_r) return AGIS_OK;
+    const int64_t n = std::max<int64_t>(cg_size(ctx), 1);
+    for (double** v : {&ctx->cg_r, &ctx->cg_z, &ctx->cg_p, &ctx->cg_ry, &ctx->cg_zy}) ALLOC(*v, n, "cg vectors");
+    ALLOC(ctx->cg_sy, 5 * std::max<int64_t>(ctx->n_src, 1), "cg state");
+    ALLOC(ctx->cg_part, 2 * 1024, "cg partial sums");
+    ALLOC(ctx->cg_qpart, std::max<int64_t>(cg_quad_blocks(ctx), 1), "cg partial sums");
+    ALLOC(ctx->cg_out, 2, "cg sums");
+    return AGIS_OK;
+}
+
+// r and z at the current state, which is left as it was: the S pass writes
+// its right-hand sides into r and its update into ds, then the sources are
+// put back; the A/C pass and the A and C solves run at the same point and
+// their updates stay in da and dc.
+static int cg_evaluate(agis_ctx* ctx, double* r, double* z) {
+    const int64_t ns = ctx->n_src;
+    launch_copy(ctx, 5 * ns, ctx->s, ctx->cg_sy);
+    ctx->rhs_s_out = r;
+    int rc = run_source(ctx);
+    ctx->rhs_s_out = nullptr;
+    if (rc) return rc;
+    launch_copy(ctx, 5 * ns, ctx->cg_sy, ctx->s);
+    launch_prep_sources(ctx);
+    if ((rc = run_ac(ctx, true, true, false, false, r + 5 * ns + 4 * ctx->N))) return rc;
+    launch_cg_gather(ctx, r, z);
+    HIPCHK(hipGetLastError());
+    return AGIS_OK;
+}
+
+static int cg_read(agis_ctx* ctx, double h[2]) {
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(h, ctx->cg_out, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return AGIS_OK;
+}
+
+static int cg_step(agis_ctx* ctx, int32_t restart, agis_cg_stats_t* st) {
+    const int64_t n = cg_size(ctx);
+    double h[2];
+    int rc;
+    agis_cg_stats_t out = {0.0, 0.0, 0.0, 0, 0, 0.0};
+    tstart(ctx, T_ITER);
+    if (ctx->cg_k == 0 || ctx->cg_ver != ctx->xver) {
+        // a cycle starts at x: frame rotator, then r, z and p = z
+        if (ctx->have_ref) {
+            tstart(ctx, T_FRAME);
+            launch_frame_fit(ctx);
+            launch_frame_apply(ctx);
+            HIPCHK(hipGetLastError());
+            tstop(ctx, T_FRAME);
+        }
+        if ((rc = cg_evaluate(ctx, ctx->cg_r, ctx->cg_z))) return rc;
+        launch_copy(ctx, n, ctx->cg_z, ctx->cg_p);
+        launch_cg_dot(ctx, ctx->cg_r, ctx->cg_z, nullptr, ctx->cg_out);
+        if ((rc = cg_read(ctx, h))) return rc;
+        ctx->cg_rho = h[0];
+        ctx->cg_k = 1;
+        out.cycle_start = 1;
+    } else {
+        launch_cg_quad(ctx, ctx->cg_p, ctx->cg_qpart, ctx->cg_out);
+        if ((rc = cg_read(ctx, h))) return rc;
+        const double pnp = h[0];
+        if (!(std::isfinite(pnp) && pnp > 0.0)) {
+            // no descent along p: stay at x, start a new cycle next
+            ctx->cg_k = 0;
+            out.breakdown = 1;
+        } else {
+            const double alpha = ctx->cg_rho / pnp;
+            launch_cg_step_state(ctx, ctx->cg_p, alpha);
+            launch_prep_sources(ctx);
+            if ((rc = cg_evaluate(ctx, ctx->cg_ry, ctx->cg_zy))) return rc;
+            launch_cg_dot2(ctx, ctx->cg_ry, ctx->cg_zy, ctx->cg_z, ctx->cg_out);   // r'z, r'z_old
+            if ((rc = cg_read(ctx, h))) return rc;
+            double beta = ctx->cg_rho != 0.0 ? (h[0] - h[1]) / ctx->cg_rho : 0.0;
+            beta = std::max(beta, 0.0);
+            std::swap(ctx->cg_r, ctx->cg_ry);
+            std::swap(ctx->cg_z, ctx->cg_zy);
+            launch_cg_direction(ctx, beta);
+            HIPCHK(hipGetLastError());
+            ctx->cg_rho = h[0];
+            ctx->cg_k = ctx->cg_k < restart ? ctx->cg_k + 1 : 0;
+            out.alpha = alpha;
+            out.beta = beta;
+        }
+    }
+    tstop(ctx, T_ITER);
+    ctx->cg_ver = ctx->xver;
+    if (st) {
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        out.rho = ctx->cg_rho;
+        out.ms = tget(ctx, T_ITER);
+        *st = out;
+    }
+    return AGIS_OK;
+}
+
+extern "C" int agis_cg_iterate(agis_ctx_t* ctx, int32_t n_eval, int32_t restart, agis_cg_stats_t* per_eval) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    if (n_eval < 0 || restart < 1) return set_error(ctx, AGIS_E_INVALID_ARG, "n_eval >= 0 and restart >= 1");
+    if (ctx->cfg.robust)
+        return set_error(ctx, AGIS_E_STATE, "conjugate gradients need fixed observation weights (not robust)");
+    int rc = cg_alloc(ctx);
+    if (rc) return rc;
+    for (int32_t e = 0; e < n_eval; ++e)
+        if ((rc = cg_step(ctx, restart, per_eval ? per_eval + e : nullptr))) return rc;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->last_ms[0] = tget(ctx, T_S);
+    ctx->last_ms[1] = tget(ctx, T_AC);
+    ctx->last_ms[2] = tget(ctx, T_BAND);
+    ctx->last_ms[3] = tget(ctx, T_CAL);
+    ctx->last_ms[4] = tget(ctx, T_FRAME);
     return AGIS_OK;
 }
 

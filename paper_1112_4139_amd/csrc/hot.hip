@@ -56,7 +56,8 @@ __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n
                                                        const double* __restrict__ c, double* __restrict__ s,
                                                        SrcPrep* __restrict__ prep, double* __restrict__ ds,
                                                        double* __restrict__ qsrc, int32_t* __restrict__ sdef,
-                                                       double* __restrict__ svar, const int32_t* __restrict__ order) {
+                                                       double* __restrict__ svar, const int32_t* __restrict__ order,
+                                                       double* __restrict__ rhs) {
     constexpr int GPB = 256 / G;
     const int gl = threadIdx.x % G;
     // group k takes the k-th source of the launch order
@@ -183,7 +184,7 @@ __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n
 #pragma unroll
     for (int e = 0; e < 21; ++e) acc[e] = group_sum<G>(acc[e]);
     if (!valid || gl != 0) return;
-    source_finish(acc, i, alpha, delta, plx, pma, pmd, cd, s, prep, ds, qsrc, sdef, svar);
+    source_finish(acc, i, alpha, delta, plx, pma, pmd, cd, s, prep, ds, qsrc, sdef, svar, rhs);
 }
 
 // ------------------------------------------------------------- A/C pass
@@ -622,7 +623,8 @@ inline int groups_grid(int64_t n_items, int items_per_block) {
     (ctx->cfg.precision == AGIS_MIXED ? k_source_update<G, true> : k_source_update<G, false>)                  \
         <<<groups_grid(ctx->n_src, 256 / G), 256, 0, ctx->stream>>>(                                           \
         ctx->k, ctx->n_src, ctx->src_off, ctx->s_t, ctx->s_eta, ctx->s_sig, ctx->s_cell, ctx->s_ell, ctx->knots, \
-        ctx->ktab, ctx->a, ctx->c, ctx->s, ctx->prep, ctx->ds, ctx->qsrc, ctx->sdef, ctx->svar, ctx->src_order)
+        ctx->ktab, ctx->a, ctx->c, ctx->s, ctx->prep, ctx->ds, ctx->qsrc, ctx->sdef, ctx->svar, ctx->src_order, \
+        ctx->rhs_s_out)
 
 void launch_source_update(agis_ctx* ctx) {
     if (ctx->n_src == 0) return;

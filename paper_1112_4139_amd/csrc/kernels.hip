@@ -47,11 +47,12 @@ __global__ void k_apply_add(int64_t n, double* __restrict__ x, const double* __r
 
 // ------------------------------------------------------ calibration solve
 // One block per constraint pair (cells 2j, 2j+1): eq:normC with Phi = 1
-// (a 1x1 system per cell, Algorithms C1-C3), then eq:calCon.
+// (a 1x1 system per cell, Algorithms C1-C3), then eq:calCon.  rc
+// (optional) receives each cell's right-hand side -sum W R.
 __global__ __launch_bounds__(256) void k_calib_solve(int64_t n_cells, const int32_t* __restrict__ cell_iv,
                                                      const int32_t* __restrict__ iv_cell,
                                                      const double* __restrict__ iv_cal, double* __restrict__ c,
-                                                     double* __restrict__ dc) {
+                                                     double* __restrict__ dc, double* __restrict__ rc) {
     __shared__ double red[256][2];
     __shared__ double dt[2];
     const int64_t pair = blockIdx.x;
@@ -82,6 +83,7 @@ __global__ __launch_bounds__(256) void k_calib_solve(int64_t n_cells, const int3
         if (threadIdx.x == 0) {
             double U = red[0][0];
             double x = -red[0][1];
+            if (rc && cell < n_cells) rc[cell] = x;
             double Um[1] = {U}, xm[1] = {x};
             small_chol_solve<1>(Um, xm);
             dt[h] = (cell < n_cells) ? xm[0] : 0.0;
@@ -363,11 +365,11 @@ void launch_apply_attitude(agis_ctx* ctx) {
     k_apply_add<<<grid_for(4 * ctx->N), 256, 0, ctx->stream>>>(4 * ctx->N, ctx->a, ctx->da);
 }
 
-void launch_calib_solve(agis_ctx* ctx) {
+void launch_calib_solve(agis_ctx* ctx, double* rc) {
     const int64_t pairs = (ctx->n_cells + 1) / 2;
     if (pairs == 0) return;
     k_calib_solve<<<(unsigned)pairs, 256, 0, ctx->stream>>>(ctx->n_cells, ctx->cell_iv, ctx->iv_cell, ctx->iv_cal,
-                                                           ctx->c, ctx->dc);
+                                                           ctx->c, ctx->dc, rc);
 }
 
 void launch_apply_calibration(agis_ctx* ctx) {

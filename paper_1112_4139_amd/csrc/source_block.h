@@ -11,11 +11,12 @@
 namespace agis {
 
 // acc: the 15 upper-triangle entries of N (row-major), the 5 of b and h'Wh.
+// rhs (optional, [n_src][5]) receives b.
 __device__ __forceinline__ void source_finish(const double acc[21], int64_t i, double alpha, double delta,
                                               double plx, double pma, double pmd, double cd, double* __restrict__ s,
                                               SrcPrep* __restrict__ prep, double* __restrict__ ds,
                                               double* __restrict__ qsrc, int32_t* __restrict__ sdef,
-                                              double* __restrict__ svar) {
+                                              double* __restrict__ svar, double* __restrict__ rhs = nullptr) {
     double U[25], N[25], x[5];
     int e = 0;
     for (int rr = 0; rr < 5; ++rr)
@@ -26,6 +27,8 @@ __device__ __forceinline__ void source_finish(const double acc[21], int64_t i, d
             ++e;
         }
     for (int rr = 0; rr < 5; ++rr) x[rr] = acc[15 + rr];
+    if (rhs)
+        for (int rr = 0; rr < 5; ++rr) rhs[5 * i + rr] = acc[15 + rr];
     const int d = small_chol_factor<5>(U);
     small_chol_subst<5>(U, x);
     // diagonal of the inverse normal matrix, the first-order variances of

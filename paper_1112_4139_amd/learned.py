@@ -120,7 +120,38 @@ def collect(ctx, w, m, n_macro, horizon, every=1):
     return data
 
 
-def solve(ctx, w, m, n_iter, ref, mode, tol=1.0, log=None, asi_stride=16, asi_lambda_max=0.99):
+def solve_cg(ctx, w, n_iter, ref, tol=1.0, log=None, restart=40):
+    """Conjugate gradients (Sect. 4.7) in cycles of restart + 1 evaluations
+    (one at the cycle's start point, then restart iterations), until the
+    disagreement with ref drops below tol uas.  The frame rotator, which CG
+    applies at each cycle start, is applied before each check, as the simple
+    iteration applies it after every iteration.  Returns the evaluations
+    (each one pass of the three blocks, like one S[AC] iteration), the wall
+    time of the library calls, the cycles and breakdowns, and the median
+    step length."""
+    it = 0
+    t_gpu = 0.0
+    alphas = []
+    cycles = breakdowns = 0
+    dis = disagreement(state(ctx, w), ref)
+    while it < n_iter and dis > tol:
+        t0 = time.perf_counter()
+        st = agis.agis_cg_iterate(ctx, restart + 1, restart)
+        agis.agis_frame_apply(ctx, agis.agis_frame_fit(ctx))
+        t_gpu += time.perf_counter() - t0
+        it += restart + 1
+        cycles += 1
+        breakdowns += sum(x["breakdown"] for x in st)
+        alphas += [x["alpha"] for x in st if x["alpha"] > 0]
+        dis = disagreement(state(ctx, w), ref)
+        if log and cycles % 20 == 0:
+            log(f"cg it {it}: disagreement {dis:.3f} uas, breakdowns {breakdowns}")
+    return dict(iterations=it if dis <= tol else None, seconds=t_gpu, cycles=cycles, breakdowns=breakdowns,
+                disagreement=dis, chi2=agis.agis_chi2(ctx),
+                median_alpha=float(np.median(alphas)) if alphas else None)
+
+
+def solve(ctx, w, m, n_iter, ref, mode, tol=1.0, log=None, asi_stride=16, asi_lambda_max=0.99, cg_restart=40):
     """Iterate in blocks of m iterations until the disagreement with ref
     drops below tol uas.  mode "plain": the simple iteration alone; "asi":
     after each block from the third record of a history on, the accelerated
@@ -131,6 +162,8 @@ def solve(ctx, w, m, n_iter, ref, mode, tol=1.0, log=None, asi_stride=16, asi_la
     and skipped) and the median q_cand / q_plain of the gate, or the median
     lambda of the accelerated steps."""
     learned = mode == "learned"
+    if mode == "cg":
+        return solve_cg(ctx, w, n_iter, ref, tol=tol, log=log, restart=cg_restart)
     agis.agis_learned_reset(ctx)
     acc = rej = 0
     it = 0
@@ -187,7 +220,8 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--max-iter", type=int, default=160000)
     ap.add_argument("--tol", type=float, default=1.0)
-    ap.add_argument("--modes", default="plain,asi,learned", help="solves to compare (plain, asi, learned)")
+    ap.add_argument("--modes", default="plain,asi,learned", help="solves to compare (plain, asi, learned, cg)")
+    ap.add_argument("--cg-restart", type=int, default=40, help="CG iterations per cycle")
     ap.add_argument("--ref-file", default=None, help="npz cache of the evaluation reference (read if it matches)")
     args = ap.parse_args(argv)
     if args.macro is None:
@@ -198,7 +232,8 @@ def main(argv=None):
 
     data = [[], []]
     ctx_train = None
-    for seed in [int(x) for x in args.train_seeds.split(",") if x]:
+    train = "learned" in args.modes.split(",")
+    for seed in [int(x) for x in args.train_seeds.split(",") if x and train]:
         w, ctx = problem(args.world, seed)
         d = collect(ctx, w, args.m, args.macro, args.horizon)
         for which in (0, 1):
@@ -209,7 +244,7 @@ def main(argv=None):
         else:
             agis.agis_destroy(ctx)
     weights, losses = [], []
-    for which in (0, 1):
+    for which in (0, 1) if train else ():
         X = np.concatenate([d[0] for d in data[which]])
         T = np.concatenate([d[1] for d in data[which]])
         agis.agis_mlp_init(ctx_train, which, 1234 + which)
@@ -222,7 +257,8 @@ def main(argv=None):
             f"({time.perf_counter() - t0:.1f} s)")
         weights.append(agis.agis_mlp_get_weights(ctx_train, which))
         losses.append((float(loss[:20].mean()), float(loss[-200:].mean())))
-    agis.agis_destroy(ctx_train)
+    if ctx_train is not None:
+        agis.agis_destroy(ctx_train)
 
     w, ctx = problem(args.world, args.eval_seed)
     cached = None
@@ -249,9 +285,10 @@ def main(argv=None):
     out = {}
     for mode in args.modes.split(","):
         w, ctx = problem(args.world, args.eval_seed)
-        for which in (0, 1):
+        for which in range(len(weights)):
             agis.agis_mlp_set_weights(ctx, which, weights[which])
-        out[mode] = solve(ctx, w, args.m, args.max_iter, ref, mode, tol=args.tol, log=log)
+        out[mode] = solve(ctx, w, args.m, args.max_iter, ref, mode, tol=args.tol, log=log,
+                          cg_restart=args.cg_restart)
         log(f"{mode}: {out[mode]}")
         agis.agis_destroy(ctx)
     print(json.dumps({"world": args.world, "train_seeds": args.train_seeds, "eval_seed": args.eval_seed,
