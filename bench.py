@@ -135,6 +135,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="mixed: FP32 partials and compensated FP32 normal-equation sums")
+    ap.add_argument("--scheme", choices=("si", "cg"), default="si",
+                    help="si: one simple S[AC] iteration per step; cg: one conjugate-gradient step per step "
+                         "(cycles of 40 iterations; an iteration is one pass of the blocks plus p'N p)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the timed steps, run one plain device copy of this many MiB (the reference "
                          "kernel for scaling HBM counters) and exit")
@@ -184,14 +187,21 @@ def main():
 
     s_group = agis.agis_autotune(ctx)
     log(f"autotuned: {s_group} lanes per source")
+
+    def step():
+        if args.scheme == "cg":
+            agis.agis_cg_iterate(ctx, 1, 40, stats=False)
+        else:
+            agis.agis_iterate(ctx, 1, stats=False)
+
     for i in range(args.warmup):
-        agis.agis_iterate(ctx, 1, stats=False)
+        step()
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} done")
     kt = {k: [] for k in ("source_update", "ac_pass", "band_solve", "calib_solve", "frame")}
     t_start = time.perf_counter()
     for i in range(args.steps):
-        agis.agis_iterate(ctx, 1, stats=False)
+        step()
         for k, v in agis.agis_kernel_times(ctx).items():
             kt[k].append(v)
     torch.cuda.synchronize()
@@ -241,7 +251,8 @@ def main():
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None,
            "dtype": "f64" if args.precision == "fp64" else "f64 model, f32 partials and sums", "data": "synthetic",
-           "config": {**workload_description(args.workload, w), "lanes_per_source": s_group},
+           "config": {**workload_description(args.workload, w), "lanes_per_source": s_group,
+                      **({"scheme": "conjugate gradients"} if args.scheme == "cg" else {})},
            "kernel_ms": kavg, "roofline": roofline,
            "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
