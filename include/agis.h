@@ -360,10 +360,28 @@ int agis_asi_step(agis_ctx_t* ctx, int32_t stride, double lambda_max, double* la
  * non-positive or non-finite p'N p leaves x unchanged and ends the cycle.
  * per_eval (optional, n_eval entries) receives the statistics of each step.
  * restart >= 1 and n_eval >= 0 (else AGIS_E_INVALID_ARG); AGIS_E_STATE in
- * the robust mode, whose observation weights change with the residuals (the
- * paper switches between the simple iteration and CG for that reason).
+ * the robust mode unless its weights are frozen (agis_freeze_weights):
+ * robust weights change with the residuals, and the paper switches between
+ * the simple iteration and CG for that reason.
  */
 int agis_cg_iterate(agis_ctx_t* ctx, int32_t n_eval, int32_t restart, agis_cg_stats_t* per_eval);
+
+/*
+ * Frozen weights, the switch of the hybrid scheme (Sect. 4.7: the simple
+ * iteration runs while the robust weights still change, then CG, which
+ * needs a fixed normal matrix).  freeze != 0: at the current parameters and
+ * excess attitude noise, every observation's weight of the A/C pass,
+ * W = w(R / sigma~) / sigma~^2 with sigma~^2 = sigma^2 + eps_a^2 (eq:dw,
+ * eq:W), is fixed as sigma_eff = 1 / sqrt(W) (FP32; W = 0 gives the
+ * largest finite float), and from then on the S, A and C blocks, the
+ * iterations and agis_cg_iterate solve the plain weighted least-squares
+ * problem with sigma_eff in place of sigma (no inner iteration, no
+ * excess-noise update).  freeze == 0: back to the robust weighting.
+ * Calling it again re-freezes at the current parameters.  Device memory:
+ * 8 bytes per observation, allocated on the first freeze.  AGIS_E_STATE
+ * when the context is not robust.
+ */
+int agis_freeze_weights(agis_ctx_t* ctx, int32_t freeze);
 
 #ifdef __cplusplus
 }

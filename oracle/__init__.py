@@ -115,6 +115,7 @@ def lib(precision="double"):
         L.orc_normal_rhs.argtypes = [P(World), P(Obs), P(State), P(c_r), P(c_r), P(c_r)]
         L.orc_normal_quadratic.argtypes = [P(World), P(Obs), P(State), P(c_r)]
         L.orc_normal_quadratic.restype = c_r
+        L.orc_frozen_sigma.argtypes = [P(World), P(Obs), P(State), P(c_f)]
         L.orc_frame_fit.argtypes = [P(World), P(State), P(c_r), P(c_r), P(c_r)]
         L.orc_frame_apply.argtypes = [P(World), P(State), P(c_r)]
         L.orc_weight_function.argtypes = [c_r]
@@ -382,6 +383,14 @@ class Problem:
         assert v.size == 5 * self.s.shape[0] + 4 * self.a.shape[0] + self.c.size
         return self._L.orc_normal_quadratic(ctypes.byref(self.world), ctypes.byref(self.obs),
                                             ctypes.byref(self.state), _p(v, self._cr))
+
+    def frozen_sigma(self):
+        """sigma_eff = 1 / sqrt(W) (float32, input order) of every observation
+        at the current state, W the A/C weight."""
+        out = np.zeros(self.t.size, np.float32)
+        self._L.orc_frozen_sigma(ctypes.byref(self.world), ctypes.byref(self.obs), ctypes.byref(self.state),
+                                 _p(out, c_f))
+        return out
 
     def iterate_sac(self):
         self.var = self._zeros((self.s.shape[0], 5))

@@ -9,6 +9,7 @@
  * Citations name sections, equation labels and algorithms of Lindegren et
  * al. (2012), "The astrometric core solution for the Gaia mission".
  */
+#include <float.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -825,6 +826,22 @@ double orc_normal_quadratic(const orc_world_t* w, const orc_obs_t* obs, const or
         sum += W * jr * jr + lam2 * W * jd * jd;
     }
     return sum;
+}
+
+/* Frozen weights (the switch of the hybrid scheme, Sect. 4.7): each
+ * observation's A/C weight W_l at the current state, as sigma_eff =
+ * 1 / sqrt(W_l) rounded to float (W_l = 0: the largest finite float), in
+ * input order.  A problem with these in place of sigma and no robust
+ * weighting is the fixed weighted least-squares problem CG then solves. */
+void orc_frozen_sigma(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, float* sig) {
+    for (int64_t l = 0; l < obs->n; ++l) {
+        orc_fwd_t o;
+        forward_one(w, obs, st, l, &o);
+        double W = weight(w, obs, st, l, &o);
+        float se = W > 0.0 ? (float)(1.0 / sqrt(W)) : FLT_MAX;
+        if (!(se <= FLT_MAX)) se = FLT_MAX;
+        sig[l] = se;
+    }
 }
 
 /* ========================================================================

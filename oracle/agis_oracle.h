@@ -137,6 +137,10 @@ void orc_normal_rhs(const orc_world_t* w, const orc_obs_t* obs, const orc_state_
  * v holds the source, then the attitude, then the calibration unknowns. */
 double orc_normal_quadratic(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, const double* v);
 
+/* Frozen weights: sigma_eff = 1 / sqrt(W_l) (float) of every observation at the
+ * current state, W_l the A/C weight (eq:dw, eq:W); input order. */
+void orc_frozen_sigma(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, float* sig);
+
 /* --- Sect. 6.1: frame rotator --------------------------------------------- */
 /* eps_omega = (eps_X, eps_Y, eps_Z [rad], omega_X, omega_Y, omega_Z [rad/yr]).
  * var[n_src][5] (may be NULL: unit weights) weights each condition equation

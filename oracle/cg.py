@@ -61,6 +61,20 @@ def evaluate(pr):
     return np.concatenate([rs.ravel(), ra.ravel(), rc]), np.concatenate([zs.ravel(), za.ravel(), zc])
 
 
+def freeze(pr):
+    """The switch of the hybrid scheme: a Problem without robust weighting
+    whose sigma is the robust problem's sigma_eff = 1 / sqrt(W) at its
+    current state (the fixed weighted least-squares problem CG solves)."""
+    from oracle import Problem
+    consts = dict(pr.consts)
+    consts["robust"] = 0
+    out = Problem(consts, pr.knots, pr.t, pr.eta_obs, pr.frozen_sigma(), pr.src, pr.fov, pr.cell, pr.s, pr.a,
+                  pr.c, precision=pr.precision)
+    if getattr(pr, "var", None) is not None:
+        out.var = pr.var.copy()        # the frame rotator's weights from the last S update
+    return out
+
+
 class CG:
     """Iteration state of the scheme; step() and run() advance the Problem's
     state."""

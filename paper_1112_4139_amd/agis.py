@@ -105,6 +105,7 @@ _sig = {
     "agis_learned_apply": ([_ctx_p], ctypes.c_int),
     "agis_asi_step": ([_ctx_p, ctypes.c_int32, c_d, P(c_d), P(c_d)], ctypes.c_int),
     "agis_cg_iterate": ([_ctx_p, c_i32, c_i32, P(agis_cg_stats_t)], ctypes.c_int),
+    "agis_freeze_weights": ([_ctx_p, c_i32], ctypes.c_int),
     "agis_learned_step": ([_ctx_p, P(c_d), P(c_d), P(c_i32)], ctypes.c_int),
 }
 for _name, (_args, _res) in _sig.items():
@@ -403,6 +404,10 @@ def agis_cg_iterate(ctx, n_eval, restart=40, stats=True):
                      ms=x.ms) for x in arr[:n_eval]]
     _check(_lib.agis_cg_iterate(ctx, int(n_eval), int(restart), None), ctx)
     return None
+
+
+def agis_freeze_weights(ctx, freeze=True):
+    _check(_lib.agis_freeze_weights(ctx, 1 if freeze else 0), ctx)
 
 
 def agis_learned_step(ctx):

@@ -67,6 +67,13 @@ struct agis_ctx {
     int32_t* t_cellfov = nullptr;         // cell * 2 + (fov < 0)
     int32_t* t_src = nullptr;
     int32_t* t_perm = nullptr;           // input index of each time-ordered observation
+    int32_t* s_from_t = nullptr;         // time-order index of each (source, time)-ordered observation
+    // frozen robust weights: sigma_eff = 1 / sqrt(W) of every observation in
+    // both orders; while frozen, the plain kernels run with these in place
+    // of sigma (one fixed weighted least-squares problem)
+    float* s_sig_eff = nullptr;
+    float* t_sig_eff = nullptr;
+    bool frozen = false;
     int64_t* iv_off = nullptr;           // [K + 1]
     int32_t* iv_cell = nullptr;          // [K][2] cell of the fov +1 / -1 observations (-1: none)
     int32_t* cell_iv = nullptr;          // [n_cells][2] interval range [lo, hi) of each cell
@@ -169,6 +176,12 @@ struct agis_ctx {
 
 namespace agis {
 
+// robust weighting in effect (not while the weights are frozen)
+inline bool robust_now(const agis_ctx* ctx) { return ctx->cfg.robust && !ctx->frozen; }
+// sigma columns the plain kernels read
+inline const float* s_sig_now(const agis_ctx* ctx) { return ctx->frozen ? ctx->s_sig_eff : ctx->s_sig; }
+inline const float* t_sig_now(const agis_ctx* ctx) { return ctx->frozen ? ctx->t_sig_eff : ctx->t_sig; }
+
 int set_error(agis_ctx* ctx, int code, const std::string& msg);
 int hip_check(agis_ctx* ctx, hipError_t e, const char* what);
 
@@ -209,6 +222,7 @@ void launch_cg_direction(agis_ctx* ctx, double beta);
 // robust.hip
 void launch_source_update_robust(agis_ctx* ctx);
 void launch_excess_noise(agis_ctx* ctx);
+void launch_freeze_sigma(agis_ctx* ctx);
 void launch_ac_pass(agis_ctx* ctx);
 void launch_band_solve(agis_ctx* ctx);
 void launch_calib_solve(agis_ctx* ctx, double* rc = nullptr);   // rc: optional right-hand sides

@@ -83,6 +83,10 @@ static void free_store(agis_ctx* ctx) {
     dfree(ctx->t_cellfov);
     dfree(ctx->t_src);
     dfree(ctx->t_perm);
+    dfree(ctx->s_from_t);
+    dfree(ctx->s_sig_eff);
+    dfree(ctx->t_sig_eff);
+    ctx->frozen = false;
     dfree(ctx->iv_off);
     dfree(ctx->iv_cell);
     dfree(ctx->cell_iv);
@@ -564,7 +568,7 @@ static int fill_stats(agis_ctx* ctx, agis_block_stats_t* st, const double* x, in
 
 static int run_source(agis_ctx* ctx) {
     tstart(ctx, T_S);
-    if (ctx->cfg.robust) launch_source_update_robust(ctx);
+    if (robust_now(ctx)) launch_source_update_robust(ctx);
     else launch_source_update(ctx);
     HIPCHK(hipGetLastError());
     tstop(ctx, T_S);
@@ -578,7 +582,7 @@ static int run_source(agis_ctx* ctx) {
 static int run_ac(agis_ctx* ctx, bool do_a, bool do_c, bool eps_update = false, bool apply = true,
                   double* rc = nullptr) {
     tstart(ctx, T_AC);
-    if (eps_update && ctx->cfg.robust) launch_excess_noise(ctx);
+    if (eps_update && robust_now(ctx)) launch_excess_noise(ctx);
     launch_ac_pass(ctx);
     HIPCHK(hipGetLastError());
     tstop(ctx, T_AC);
@@ -1366,8 +1370,9 @@ extern "C" int agis_cg_iterate(agis_ctx_t* ctx, int32_t n_eval, int32_t restart,
     CHECK_CTX();
     REQUIRE_LOADED();
     if (n_eval < 0 || restart < 1) return set_error(ctx, AGIS_E_INVALID_ARG, "n_eval >= 0 and restart >= 1");
-    if (ctx->cfg.robust)
-        return set_error(ctx, AGIS_E_STATE, "conjugate gradients need fixed observation weights (not robust)");
+    if (robust_now(ctx))
+        return set_error(ctx, AGIS_E_STATE,
+                         "conjugate gradients need fixed observation weights (robust mode: freeze them first)");
     int rc = cg_alloc(ctx);
     if (rc) return rc;
     for (int32_t e = 0; e < n_eval; ++e)
@@ -1378,6 +1383,33 @@ extern "C" int agis_cg_iterate(agis_ctx_t* ctx, int32_t n_eval, int32_t restart,
     ctx->last_ms[2] = tget(ctx, T_BAND);
     ctx->last_ms[3] = tget(ctx, T_CAL);
     ctx->last_ms[4] = tget(ctx, T_FRAME);
+    return AGIS_OK;
+}
+
+// Frozen robust weights (the switch of the hybrid scheme, Sect. 4.7): the
+// weights of the A/C pass at the current parameters become fixed, and every
+// block runs the plain weighted least squares with them until thawed.
+extern "C" int agis_freeze_weights(agis_ctx_t* ctx, int32_t freeze) {
+    CHECK_CTX();
+    ++ctx->xver;
+    REQUIRE_LOADED();
+    if (!ctx->cfg.robust) return set_error(ctx, AGIS_E_STATE, "the context is not robust");
+    if (!freeze) {
+        if (ctx->frozen) {
+            ctx->frozen = false;
+            ++ctx->gen;
+        }
+        return AGIS_OK;
+    }
+    if (!ctx->t_sig_eff) {
+        ALLOC(ctx->t_sig_eff, std::max<int64_t>(ctx->n_obs, 1), "frozen sigma");
+        ALLOC(ctx->s_sig_eff, std::max<int64_t>(ctx->n_obs, 1), "frozen sigma");
+    }
+    launch_freeze_sigma(ctx);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->frozen = true;
+    ++ctx->gen;
     return AGIS_OK;
 }
 

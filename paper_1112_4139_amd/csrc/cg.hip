@@ -266,7 +266,7 @@ void launch_cg_quad(agis_ctx* ctx, const double* p, double* part, double* out) {
         k_cg_quad_sum<<<1, CG_THREADS, 0, ctx->stream>>>(0, part, out);
         return;
     }
-    k_cg_quad<<<(unsigned)nb, 64, 0, ctx->stream>>>(ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, ctx->t_sig,
+    k_cg_quad<<<(unsigned)nb, 64, 0, ctx->stream>>>(ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, t_sig_now(ctx),
                                                     ctx->t_cellfov, ctx->t_src, ctx->prep, ctx->knots, ctx->ktab,
                                                     ctx->a, ctx->c, p, ctx->n_src, ctx->N, part);
     k_cg_quad_sum<<<1, CG_THREADS, 0, ctx->stream>>>(nb, part, out);

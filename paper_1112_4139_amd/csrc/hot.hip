@@ -622,7 +622,7 @@ inline int groups_grid(int64_t n_items, int items_per_block) {
 #define AGIS_S_LAUNCH(G)                                                                                       \
     (ctx->cfg.precision == AGIS_MIXED ? k_source_update<G, true> : k_source_update<G, false>)                  \
         <<<groups_grid(ctx->n_src, 256 / G), 256, 0, ctx->stream>>>(                                           \
-        ctx->k, ctx->n_src, ctx->src_off, ctx->s_t, ctx->s_eta, ctx->s_sig, ctx->s_cell, ctx->s_ell, ctx->knots, \
+        ctx->k, ctx->n_src, ctx->src_off, ctx->s_t, ctx->s_eta, s_sig_now(ctx), ctx->s_cell, ctx->s_ell, ctx->knots, \
         ctx->ktab, ctx->a, ctx->c, ctx->s, ctx->prep, ctx->ds, ctx->qsrc, ctx->sdef, ctx->svar, ctx->src_order, \
         ctx->rhs_s_out)
 
@@ -640,8 +640,8 @@ void launch_ac_pass(agis_ctx* ctx) {
     if (ctx->K == 0) return;
     (ctx->cfg.precision == AGIS_MIXED ? k_ac_pass<true> : k_ac_pass<false>)
         <<<(unsigned)((ctx->K + AC_WAVES - 1) / AC_WAVES), 64 * AC_WAVES, 0, ctx->stream>>>(
-        ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, ctx->t_sig, ctx->t_cellfov, ctx->t_src, ctx->prep,
-        ctx->knots, ctx->ktab, ctx->a, ctx->c, ctx->eps_a2, ctx->cfg.eps_bucket, ctx->cfg.robust, ctx->iv_sums,
+        ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, t_sig_now(ctx), ctx->t_cellfov, ctx->t_src, ctx->prep,
+        ctx->knots, ctx->ktab, ctx->a, ctx->c, ctx->eps_a2, ctx->cfg.eps_bucket, robust_now(ctx), ctx->iv_sums,
         ctx->iv_cal);
 }
 

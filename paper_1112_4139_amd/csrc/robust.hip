@@ -23,6 +23,9 @@
 // 2,048 per block), with the digit histogram in LDS (integer counts: the
 // result does not depend on the order of the adds); the upper one by a count
 // and a minimum over the same keys.
+#include <algorithm>
+#include <cfloat>
+
 #include "agis_internal.h"
 #include "source_block.h"
 
@@ -366,6 +369,48 @@ __global__ __launch_bounds__(64) void k_ac_resid(DevConsts k, int64_t K, const i
     }
 }
 
+// Frozen weights: the robust weight of the A/C pass, W = w(R / sigma~) /
+// sigma~^2 with sigma~^2 = sigma^2 + eps_a^2 of the interval's bucket
+// (eq:dw, eq:W), at the current parameters, stored as sigma_eff = 1 / sqrt(W)
+// in FP32 (W = 0: the largest finite float).
+__global__ __launch_bounds__(64) void k_freeze_sigma(DevConsts k, int64_t K, const int64_t* __restrict__ iv_off,
+                                                     const double* __restrict__ ot, const double* __restrict__ oeta,
+                                                     const float* __restrict__ osig,
+                                                     const int32_t* __restrict__ ocellfov,
+                                                     const int32_t* __restrict__ osrc,
+                                                     const SrcPrep* __restrict__ prep,
+                                                     const double* __restrict__ knots,
+                                                     const KnotTab* __restrict__ ktab, const double* __restrict__ a,
+                                                     const double* __restrict__ c,
+                                                     const double* __restrict__ eps_a2, int eps_bucket,
+                                                     float* __restrict__ sig_eff) {
+    const int lane = threadIdx.x;
+    const int64_t j = blockIdx.x;
+    if (j >= K) return;
+    double a4[16], kn[6];
+    for (int e = 0; e < 16; ++e) a4[e] = a[4 * j + e];
+    for (int e = 0; e < 6; ++e) kn[e] = knots[j + 1 + e];
+    const KnotTab kt = ktab[j];
+    const double eps2 = eps_a2[j / eps_bucket];
+    for (int64_t l = iv_off[j] + lane; l < iv_off[j + 1]; l += 64) {
+        const SrcPrep sp = prep[osrc[l]];
+        ObsEval o;
+        observe(k, ot[l], oeta[l], c[ocellfov[l] >> 1], sp.r, sp.mu, sp.plx, a4, kn, kt, o);
+        const double sg = (double)osig[l];
+        const double s2 = sg * sg + eps2;
+        const double W = down_weight(o.R / sqrt(s2)) / s2;
+        float se = W > 0.0 ? (float)(1.0 / sqrt(W)) : FLT_MAX;
+        if (!(se <= FLT_MAX)) se = FLT_MAX;
+        sig_eff[l] = se;
+    }
+}
+
+__global__ void k_gather_f32(int64_t n, const int32_t* __restrict__ from, const float* __restrict__ src,
+                             float* __restrict__ dst) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[from[i]];
+}
+
 template <bool REG>
 __global__ __launch_bounds__(64) void k_bucket_eps(int64_t n_buckets, int64_t K, int eps_bucket,
                                                    const int64_t* __restrict__ iv_off, const double* __restrict__ v,
@@ -434,6 +479,18 @@ void launch_source_update_robust(agis_ctx* ctx) {
         case 16: AGIS_IRLS_LAUNCH(16); break;
         case 32: AGIS_IRLS_LAUNCH(32); break;
         default: AGIS_IRLS_LAUNCH(64); break;
+    }
+}
+
+void launch_freeze_sigma(agis_ctx* ctx) {
+    if (ctx->K > 0)
+        k_freeze_sigma<<<(unsigned)ctx->K, 64, 0, ctx->stream>>>(
+            ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, ctx->t_sig, ctx->t_cellfov, ctx->t_src, ctx->prep,
+            ctx->knots, ctx->ktab, ctx->a, ctx->c, ctx->eps_a2, ctx->cfg.eps_bucket, ctx->t_sig_eff);
+    if (ctx->n_obs > 0) {
+        const int64_t b = std::min<int64_t>((ctx->n_obs + 255) / 256, 65536);
+        k_gather_f32<<<(unsigned)b, 256, 0, ctx->stream>>>(ctx->n_obs, ctx->s_from_t, ctx->t_sig_eff,
+                                                           ctx->s_sig_eff);
     }
 }
 

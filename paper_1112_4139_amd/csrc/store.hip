@@ -288,11 +288,10 @@ int build_store(agis_ctx* ctx, const agis_obs_soa_t* obs, int where) {
 
     // ---- (source, time) order: stable sort of the time order by source ----
     int32_t* src_sorted = nullptr;
-    int32_t* perm_s = nullptr;
     ALLOC(src_sorted, n, "src_sorted");
     tmp.push_back(src_sorted);
-    ALLOC(perm_s, n, "perm_s");
-    tmp.push_back(perm_s);
+    ALLOC(ctx->s_from_t, n, "s_from_t");          // kept: gathers time-ordered columns into source order
+    int32_t* perm_s = ctx->s_from_t;
     int bits = 1;
     while (bits < 31 && (int64_t(1) << bits) < ctx->n_src) ++bits;
     HIPCHK(hipcub::DeviceRadixSort::SortPairs(temp, tb2, ctx->t_src, src_sorted, iota, perm_s, (int)n, 0, bits, st));
