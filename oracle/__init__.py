@@ -42,7 +42,8 @@ def _structs(c_r):
 
     class State(ctypes.Structure):
         _fields_ = [("n_src", c_i64), ("n_att", c_i64), ("n_cells", c_i64), ("s", P(c_r)), ("a", P(c_r)),
-                    ("c", P(c_r)), ("n_buckets", c_i64), ("eps_a2", P(c_r))]
+                    ("c", P(c_r)), ("n_buckets", c_i64), ("eps_a2", P(c_r)), ("src_eps2", P(c_r)),
+                    ("src_D", P(c_r))]
 
     return World, Obs, State
 
@@ -275,6 +276,9 @@ class Problem:
             self.eps_a2 = self._arr(np.full(nb, float(consts.get("eps_a_init", 0.0)) ** 2))
         else:
             self.eps_a2 = self._zeros(0)
+        # robust 2: excess source noise eps_i^2 and its significance D per source
+        self.src_eps2 = self._zeros(self.s.shape[0]) if self.world.robust == 2 else None
+        self.src_D = self._zeros(self.s.shape[0]) if self.world.robust == 2 else None
         self._refresh()
 
     def _arr(self, x):
@@ -290,7 +294,8 @@ class Problem:
                              cell=_p(self.cell, c_i32))
         self.state = self._State(n_src=self.s.shape[0], n_att=self.a.shape[0], n_cells=self.c.size,
                                  s=_p(self.s, cr), a=_p(self.a, cr), c=_p(self.c, cr),
-                                 n_buckets=self.eps_a2.size, eps_a2=_p(self.eps_a2, cr))
+                                 n_buckets=self.eps_a2.size, eps_a2=_p(self.eps_a2, cr),
+                                 src_eps2=_p(self.src_eps2, cr), src_D=_p(self.src_D, cr))
 
     def set_eta_obs(self, eta_obs):
         self.eta_obs = self._arr(eta_obs).copy()

@@ -411,12 +411,19 @@ static double sigma_tilde2(const orc_world_t* w, const orc_obs_t* obs, const orc
     return v;
 }
 
-/* Statistical weight W_l = w_l / sigma~_l^2 (eq:W, eq:wl) for the attitude
- * and calibration updates: w_l from the residual R_l of the pass and the
- * latest excess attitude noise (Sect. 5.2.5); w_l = 1 when not robust. */
+/* eps_i^2 of the observation's source from the last S update (robust 2;
+ * 0 otherwise or before any). */
+static double source_eps2(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, int64_t l) {
+    return (w->robust == 2 && st->src_eps2) ? st->src_eps2[obs->src[l]] : 0.0;
+}
+
+/* Statistical weight W_l = w_l / (sigma~_l^2 + eps_i^2) (eq:W, eq:wl) for
+ * the attitude and calibration updates: w_l from the residual R_l of the
+ * pass, the latest excess attitude noise and (robust 2) the source's excess
+ * noise (Sect. 5.2.5); w_l = 1 when not robust. */
 static double weight(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, int64_t l,
                      const orc_fwd_t* o) {
-    double v = sigma_tilde2(w, obs, st, l, o->ell);
+    double v = sigma_tilde2(w, obs, st, l, o->ell) + source_eps2(w, obs, st, l);
     double wl = w->robust ? orc_weight_function(o->R / sqrt(v)) : 1.0;
     return wl / v;
 }
@@ -434,7 +441,7 @@ void orc_excess_attitude_noise(const orc_world_t* w, const orc_obs_t* obs, orc_s
         forward_one(w, obs, st, l, &o);
         double s = (double)obs->sigma[l];
         bk[l] = bucket_of(w, o.ell);
-        v[l] = o.R * o.R - s * s;
+        v[l] = o.R * o.R - s * s - source_eps2(w, obs, st, l);     /* e09 */
     }
     for (int64_t l = 0; l < obs->n; ++l) cnt[bk[l] + 1] += 1;
     for (int64_t j = 0; j < nb; ++j) cnt[j + 1] += cnt[j];
@@ -454,12 +461,51 @@ void orc_excess_attitude_noise(const orc_world_t* w, const orc_obs_t* obs, orc_s
  * the design matrix eq:designS and h = R (eq:designSrhs), solved by
  * Algorithms C1-C3; Q_i from eq:Qi; alpha updated through d_1 = dalpha cos
  * delta (footnote to eq:ubardiff).
- * Robust (Sect. 5.1.2, inner iteration with eps_i = 0): initial downweights
- * w_l = w(h_l / varsigma_i), varsigma_i half the intersextile range of the
- * h_l; then four solves, the weights after each of the first three set to
- * w(R_l / sigma~_l) from the updated residuals R_l = h_l - A_l d.
+ * Robust (Sect. 5.1.2): initial downweights w_l = w(h_l / varsigma_i),
+ * varsigma_i half the intersextile range of the h_l; then four rounds, the
+ * weights of each after the first set to w(R_l / (sigma~_l^2 + eps_i^2)^1/2)
+ * from the previous round's residuals R_l = h_l - A_l d (eq:wl).  robust 1:
+ * eps_i = 0; robust 2: each round finds eps_i^2 for its weights (eq:epsi).
  * ====================================================================== */
 #define ORC_INNER_SOLVES 4
+#define ORC_EPS_STEPS 3     /* rational steps of eq:epsi (the paper finds 2-3 sufficient) */
+
+/* eq:normS with W_l = w_l / (sigma~_l^2 + y) (eq:W), solved by C1-C3; N
+ * keeps the factor (for the variances), b the solution; returns the defect. */
+static int source_normals_solve(const double* Ab, const double* hb, const double* Vb, const double* wb, int64_t ni,
+                                double y, double N[25], double b[5]) {
+    for (int e = 0; e < 25; ++e) N[e] = 0.0;
+    for (int e = 0; e < 5; ++e) b[e] = 0.0;
+    for (int64_t k = 0; k < ni; ++k) {
+        const double* A = Ab + 5 * k;
+        double W = wb[k] / (Vb[k] + y);
+        for (int r = 0; r < 5; ++r) {
+            for (int c = 0; c < 5; ++c) N[5 * r + c] += A[r] * W * A[c];
+            b[r] += A[r] * W * hb[k];
+        }
+    }
+    int def = orc_chol_c1(N, 5);
+    orc_chol_c2(N, 5, b);
+    orc_chol_c3(N, 5, b);
+    return def;
+}
+
+/* Q(y) = sum W_l R_l^2 of eq:Qi at the solution b, and its derivative
+ * Q'(y) = -sum w_l R_l^2 / (sigma~_l^2 + y)^2 (the solution's own change
+ * does not enter: it minimises Q). */
+static void source_q(const double* Ab, const double* hb, const double* Vb, const double* wb, int64_t ni, double y,
+                     const double b[5], double* Q, double* Qp) {
+    double q = 0.0, qp = 0.0;
+    for (int64_t k = 0; k < ni; ++k) {
+        double Rk = hb[k];
+        for (int c = 0; c < 5; ++c) Rk -= Ab[5 * k + c] * b[c];
+        double v = Vb[k] + y;
+        q += wb[k] / v * Rk * Rk;
+        qp -= wb[k] * Rk * Rk / (v * v);
+    }
+    *Q = q;
+    *Qp = qp;
+}
 
 void orc_source_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st,
                        double* d_out, double* Q_out, int32_t* defect_out, double* var_out) {
@@ -496,28 +542,42 @@ void orc_source_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* 
             }
             double N[25], b[5];
             int def = 0;
+            double y = 0.0, D = 0.0;          /* eps_i^2 and its significance (eq:epsi, eq:D) */
             for (int it = 0; it < n_solve; ++it) {
                 if (it > 0) {
+                    /* eq:wl with the previous round's solution and eps_i */
                     for (int64_t k = 0; k < ni; ++k) {
                         double Rk = hb[k];
                         for (int c = 0; c < 5; ++c) Rk -= Ab[5 * k + c] * b[c];
-                        wb[k] = orc_weight_function(Rk / sqrt(Vb[k]));
+                        wb[k] = orc_weight_function(Rk / sqrt(Vb[k] + y));
                     }
                 }
-                for (int e = 0; e < 25; ++e) N[e] = 0.0;
-                for (int e = 0; e < 5; ++e) b[e] = 0.0;
-                for (int64_t k = 0; k < ni; ++k) {
-                    const double* A = Ab + 5 * k;
-                    double W = wb[k] / Vb[k];
-                    for (int r = 0; r < 5; ++r) {
-                        for (int c = 0; c < 5; ++c) N[5 * r + c] += A[r] * W * A[c];
-                        b[r] += A[r] * W * hb[k];
+                if (w->robust == 2) {
+                    /* Sect. 5.1.2: for these w_l, eps_i^2 = 0 if Q(0) <= nu, else the
+                     * solution of Q(y) = nu by the steps dy = (1 - Q/nu) Q / Q'
+                     * from y = 0 (three of them); nu = n_i - n_out - 5 with n_out
+                     * the observations with w_l < 0.2 */
+                    int64_t nout = 0;
+                    for (int64_t k = 0; k < ni; ++k) nout += wb[k] < 0.2 ? 1 : 0;
+                    double nu = (double)(ni - nout - 5);
+                    y = 0.0;
+                    double Q = 0.0, Qp = 0.0;
+                    for (int step = 0; step <= ORC_EPS_STEPS; ++step) {
+                        if (step > 0) {
+                            if (!(nu > 0.0 && Q > nu && Qp < 0.0)) break;
+                            y += (1.0 - Q / nu) * Q / Qp;
+                            if (y < 0.0) y = 0.0;
+                        }
+                        def = source_normals_solve(Ab, hb, Vb, wb, ni, y, N, b);
+                        source_q(Ab, hb, Vb, wb, ni, y, b, &Q, &Qp);
+                        if (step == 0) D = nu > 0.0 ? (Q - nu) / sqrt(2.0 * nu) : 0.0;
                     }
+                } else {
+                    def = source_normals_solve(Ab, hb, Vb, wb, ni, 0.0, N, b);
                 }
-                def = orc_chol_c1(N, 5);
-                orc_chol_c2(N, 5, b);
-                orc_chol_c3(N, 5, b);
             }
+            if (st->src_eps2) st->src_eps2[i] = y;
+            if (st->src_D) st->src_D[i] = D;
             if (var_out) {
                 /* diagonal of the inverse: C2 and C3 on the unit vectors
                  * (Appendix C.2) */
@@ -533,7 +593,7 @@ void orc_source_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* 
             for (int64_t k = 0; k < ni; ++k) {
                 double Rk = hb[k];
                 for (int c = 0; c < 5; ++c) Rk -= Ab[5 * k + c] * b[c];
-                Q += Rk * (wb[k] / Vb[k]) * Rk;
+                Q += Rk * (wb[k] / (Vb[k] + y)) * Rk;
             }
             double* s = st->s + 5 * i;
             double cosd = cos(s[1]);

@@ -36,7 +36,8 @@ typedef struct {
     double au_m;              /* astronomical unit [m] */
     double c_mps;             /* speed of light [m/s] */
     double year_s;            /* Julian year [s] */
-    int32_t robust;           /* 0: w_l = 1, eps = 0; 1: downweighting and excess attitude noise */
+    int32_t robust;           /* 0: w_l = 1, eps = 0; 1: downweighting and excess attitude noise;
+                                 2: also the excess source noise eps_i of eq:epsi */
     int32_t eps_bucket;       /* knot intervals per excess-attitude-noise bucket (robust) */
 } orc_world_t;
 
@@ -57,6 +58,8 @@ typedef struct {
     double* c;                /* [n_cells] */
     int64_t n_buckets;        /* ceil((N - 3) / eps_bucket) when robust, else 0 */
     double* eps_a2;           /* [n_buckets] excess attitude variance eps_a^2 [rad^2] */
+    double* src_eps2;         /* [n_src] excess source variance eps_i^2 of the last S update (robust 2; may be NULL) */
+    double* src_D;            /* [n_src] its significance D of eq:D (robust 2; may be NULL) */
 } orc_state_t;
 
 /* --- Appendix A: quaternions -------------------------------------------- */
