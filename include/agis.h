@@ -85,6 +85,13 @@ typedef struct agis_ctx agis_ctx_t;
  *                attitude noise eps_a (eq e09, 68th percentile of R^2 -
  *                sigma^2) is re-estimated per bucket after every source
  *                update and used by the attitude and calibration weights.
+ *                2 = as 1 plus the excess source noise eps_i (Sect. 5.1.2):
+ *                each round of the inner iteration fixes its w_l and solves
+ *                Q(eps_i^2) = nu = n_i - n_out - 5 (n_out: w_l < 0.2) by up
+ *                to three rational steps dy = (1 - Q/nu) Q / Q' from 0
+ *                (eq:epsi; 0 when Q(0) <= nu), W_l = w_l / (sigma~_l^2 +
+ *                eps_i^2) (eq:W, eq:wl); eps_i^2 also enters the attitude
+ *                and calibration weights and eq e09 (R^2 - sigma^2 - eps_i^2).
  *   eps_bucket : knot intervals per eps_a bucket (robust only, >= 1).
  *   eps_a_init : eps_a of every bucket before the first estimate [rad].
  */
@@ -251,6 +258,12 @@ int agis_get_excess_noise(agis_ctx_t* ctx, int64_t n, double* eps_a2, int where)
 /* Re-estimate eps_a^2 per bucket from the residuals at the current
  * parameters (eq e09), as the iteration does after the source update. */
 int agis_excess_noise_update(agis_ctx_t* ctx);
+/* Excess source noise (robust mode 2, Sect. 5.1.2) of the last source
+ * update: eps_i^2 [rad^2] and its significance D = (Q(0) - nu) /
+ * (2 nu)^1/2 (eq:D; 0 when nu <= 0) of each of the n = n_src sources; zero
+ * before the first update.  AGIS_E_STATE unless robust mode 2;
+ * AGIS_E_SHAPE when n differs. */
+int agis_get_source_noise(agis_ctx_t* ctx, int64_t n, double* eps_i2, double* D, int where);
 
 /*
  * Learned extrapolation of the simple iteration (an extension of the paper's

@@ -106,6 +106,7 @@ _sig = {
     "agis_asi_step": ([_ctx_p, ctypes.c_int32, c_d, P(c_d), P(c_d)], ctypes.c_int),
     "agis_cg_iterate": ([_ctx_p, c_i32, c_i32, P(agis_cg_stats_t)], ctypes.c_int),
     "agis_freeze_weights": ([_ctx_p, c_i32], ctypes.c_int),
+    "agis_get_source_noise": ([_ctx_p, c_i64, _vp, _vp, ctypes.c_int], ctypes.c_int),
     "agis_learned_step": ([_ctx_p, P(c_d), P(c_d), P(c_i32)], ctypes.c_int),
 }
 for _name, (_args, _res) in _sig.items():
@@ -404,6 +405,13 @@ def agis_cg_iterate(ctx, n_eval, restart=40, stats=True):
                      ms=x.ms) for x in arr[:n_eval]]
     _check(_lib.agis_cg_iterate(ctx, int(n_eval), int(restart), None), ctx)
     return None
+
+
+def agis_get_source_noise(ctx, n):
+    """(eps_i^2, D) per source of the last source update (robust mode 2)."""
+    e, d = np.zeros(n), np.zeros(n)
+    _check(_lib.agis_get_source_noise(ctx, int(n), e.ctypes.data, d.ctypes.data, AGIS_HOST), ctx)
+    return e, d
 
 
 def agis_freeze_weights(ctx, freeze=True):

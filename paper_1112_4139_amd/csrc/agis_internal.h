@@ -112,6 +112,8 @@ struct agis_ctx {
     int64_t n_buckets = 0;
     double* eps_a2 = nullptr;            // [n_buckets]
     double* vs = nullptr;                // [n_src]
+    double* src_eps2 = nullptr;          // [n_src] robust mode 2: excess source noise eps_i^2 of the last S update
+    double* src_D = nullptr;             // [n_src] ... and its significance D
     double* rcol = nullptr;              // [6][n_obs]
 
     // learned extrapolation: update histories (rings of four), MLP weights
@@ -176,8 +178,8 @@ struct agis_ctx {
 
 namespace agis {
 
-// robust weighting in effect (not while the weights are frozen)
-inline bool robust_now(const agis_ctx* ctx) { return ctx->cfg.robust && !ctx->frozen; }
+// robust mode in effect: 0, 1 or 2 (0 while the weights are frozen)
+inline int robust_now(const agis_ctx* ctx) { return ctx->frozen ? 0 : ctx->cfg.robust; }
 // sigma columns the plain kernels read
 inline const float* s_sig_now(const agis_ctx* ctx) { return ctx->frozen ? ctx->s_sig_eff : ctx->s_sig; }
 inline const float* t_sig_now(const agis_ctx* ctx) { return ctx->frozen ? ctx->t_sig_eff : ctx->t_sig; }

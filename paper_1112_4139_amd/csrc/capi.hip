@@ -100,6 +100,8 @@ static void free_store(agis_ctx* ctx) {
     dfree(ctx->svar);
     dfree(ctx->dc);
     dfree(ctx->vs);
+    dfree(ctx->src_eps2);
+    dfree(ctx->src_D);
     dfree(ctx->rcol);
     dfree(ctx->lh_anchor_s);
     dfree(ctx->lh_ring_s);
@@ -233,9 +235,9 @@ extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
         g_create_error = "precision must be AGIS_FP64 or AGIS_MIXED";
         return AGIS_E_INVALID_ARG;
     }
-    if ((cfg->robust != 0 && cfg->robust != 1) || (cfg->robust && cfg->eps_bucket < 1) ||
+    if (cfg->robust < 0 || cfg->robust > 2 || (cfg->robust && cfg->eps_bucket < 1) ||
         !(std::isfinite(cfg->eps_a_init) && cfg->eps_a_init >= 0.0)) {
-        g_create_error = "robust must be 0 or 1, eps_bucket >= 1 and eps_a_init finite and >= 0";
+        g_create_error = "robust must be 0, 1 or 2, eps_bucket >= 1 and eps_a_init finite and >= 0";
         return AGIS_E_INVALID_ARG;
     }
     if (!(cfg->year_s > 0) || !(cfg->c_mps > 0) || !(cfg->au_m > 0)) {
@@ -459,6 +461,12 @@ extern "C" int agis_load_observations(agis_ctx_t* ctx, const agis_obs_soa_t* obs
         // the inner iteration's by-source columns (A, h, sigma~^2), also
         // used for R^2 - sigma^2 by the excess-noise estimate
         ALLOC(ctx->vs, n_src, "source varsigma");
+        if (ctx->cfg.robust == 2) {
+            ALLOC(ctx->src_eps2, std::max<int64_t>(n_src, 1), "excess source noise");
+            ALLOC(ctx->src_D, std::max<int64_t>(n_src, 1), "excess source noise significance");
+            HIPCHK(hipMemsetAsync(ctx->src_eps2, 0, std::max<int64_t>(n_src, 1) * sizeof(double), ctx->stream));
+            HIPCHK(hipMemsetAsync(ctx->src_D, 0, std::max<int64_t>(n_src, 1) * sizeof(double), ctx->stream));
+        }
         ALLOC(ctx->rcol, 6 * std::max<int64_t>(ctx->n_obs, 1), "robust columns");
     }
     launch_prep_sources(ctx);
@@ -883,6 +891,16 @@ extern "C" int agis_set_excess_noise(agis_ctx_t* ctx, int64_t n, const double* e
     int rc = check_finite_host(ctx, eps_a2, n, where);
     if (rc) return rc;
     return copy_in(ctx, ctx->eps_a2, eps_a2, n * sizeof(double), where);
+}
+
+extern "C" int agis_get_source_noise(agis_ctx_t* ctx, int64_t n, double* eps_i2, double* D, int where) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    if (ctx->cfg.robust != 2) return set_error(ctx, AGIS_E_STATE, "excess source noise needs robust mode 2");
+    if (n != ctx->n_src || (n > 0 && (!eps_i2 || !D))) return set_error(ctx, AGIS_E_SHAPE, "source count mismatch");
+    int rc = copy_out(ctx, eps_i2, ctx->src_eps2, n * sizeof(double), where);
+    if (rc) return rc;
+    return copy_out(ctx, D, ctx->src_D, n * sizeof(double), where);
 }
 
 extern "C" int agis_get_excess_noise(agis_ctx_t* ctx, int64_t n, double* eps_a2, int where) {

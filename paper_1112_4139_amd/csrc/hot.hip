@@ -288,7 +288,8 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
             const double sg = (double)s_c;
             double W;
             if (robust) {
-                const double s2 = sg * sg + eps2;
+                // robust mode 2: plus the source's excess noise eps_i^2 (eq:W)
+                const double s2 = sg * sg + eps2 + (robust == 2 ? sp_c.pad : 0.0);
                 W = h_c ? down_weight(o.R / sqrt(s2)) / s2 : 0.0;
             } else {
                 W = h_c ? rcp_nr(sg * sg) : 0.0;

@@ -19,7 +19,9 @@ constexpr int WAVE = 64;
 __device__ __forceinline__ int tri4(int n, int m) { return n * 4 - (n * (n - 1)) / 2 + (m - n); }
 
 // ---------------------------------------------------------------- sources
+// pad carries the source's excess noise eps_i^2 (robust mode 2; else 0)
 __global__ __launch_bounds__(256) void k_prep_sources(int64_t n_src, const double* __restrict__ s,
+                                                      const double* __restrict__ src_eps2,
                                                       SrcPrep* __restrict__ prep) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_src;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -35,7 +37,7 @@ __global__ __launch_bounds__(256) void k_prep_sources(int64_t n_src, const doubl
         o.r[2] = sd;
         for (int c = 0; c < 3; ++c) o.mu[c] = p[c] * si[3] + q[c] * si[4];
         o.plx = si[2];
-        o.pad = 0.0;
+        o.pad = src_eps2 ? src_eps2[i] : 0.0;
         prep[i] = o;
     }
 }
@@ -248,7 +250,7 @@ __global__ __launch_bounds__(256) void k_frame_apply_sources(DevConsts k, int64_
         o.r[2] = sd2;
         for (int m = 0; m < 3; ++m) o.mu[m] = p[m] * pma + q[m] * pmd;
         o.plx = x[2];
-        o.pad = 0.0;
+        o.pad = prep[i].pad;                  // the source's eps_i^2 stays
         prep[i] = o;
     }
 }
@@ -355,7 +357,7 @@ inline int waves_grid(int64_t n_items, int waves_per_block) {
 }  // namespace
 
 void launch_prep_sources(agis_ctx* ctx) {
-    k_prep_sources<<<grid_for(ctx->n_src), 256, 0, ctx->stream>>>(ctx->n_src, ctx->s, ctx->prep);
+    k_prep_sources<<<grid_for(ctx->n_src), 256, 0, ctx->stream>>>(ctx->n_src, ctx->s, ctx->src_eps2, ctx->prep);
 }
 
 

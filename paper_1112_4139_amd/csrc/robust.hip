@@ -344,6 +344,140 @@ __global__ __launch_bounds__(256) void k_s_irls(int64_t n_src, const int64_t* __
     source_finish(acc, i, alpha, delta, plx, pma, pmd, cos(delta), s, prep, ds, qsrc, sdef, svar);
 }
 
+// The inner iteration with the excess source noise (robust mode 2,
+// Sect. 5.1.2): four rounds as in k_s_irls, the weights of a round after the
+// first w(R_l / (sigma~_l^2 + eps_i^2)^1/2) from the previous round's
+// solution and eps_i (eq:wl); within a round, for those w_l, eps_i^2 = y
+// solves Q(y) = nu (eq:epsi) by up to EPS_STEPS rational steps
+// dy = (1 - Q/nu) Q / Q' from y = 0, Q'(y) = -sum w_l R_l^2 / (sigma~_l^2 +
+// y)^2, nu = n_i - n_out - 5 with n_out the observations with w_l < 0.2;
+// each y costs one accumulation and one residual pass.  D of eq:D (from
+// the last round's Q(0)) and eps_i^2 are stored per source.
+constexpr int EPS_STEPS = 3;
+
+template <int G>
+__global__ __launch_bounds__(256) void k_s_irls_eps(int64_t n_src, const int64_t* __restrict__ off,
+                                                    const double* __restrict__ col, int64_t n_obs,
+                                                    const double* __restrict__ vs, double* __restrict__ s,
+                                                    SrcPrep* __restrict__ prep, double* __restrict__ ds,
+                                                    double* __restrict__ qsrc, int32_t* __restrict__ sdef,
+                                                    double* __restrict__ svar, const int32_t* __restrict__ order,
+                                                    double* __restrict__ eps2_out, double* __restrict__ D_out) {
+    constexpr int GPB = 256 / G;
+    const int gl = threadIdx.x % G;
+    const int leader = (threadIdx.x & 63) & ~(G - 1);
+    const int64_t kg = (int64_t)blockIdx.x * GPB + threadIdx.x / G;
+    const bool valid = kg < n_src;
+    const int64_t i = valid ? order[kg] : 0;
+    const int64_t l0 = valid ? off[i] : 0, l1 = valid ? off[i + 1] : 0;
+    const double vsi = valid ? vs[i] : 0.0;
+    double dw[5] = {0.0, 0.0, 0.0, 0.0, 0.0};      // solution the round's weights come from
+    double d[5] = {0.0, 0.0, 0.0, 0.0, 0.0};       // current solution
+    double y = 0.0, D = 0.0;
+    double acc[21];
+    // w_l of the round (it) from dw and the previous round's eps_i^2 (yw)
+    auto weight_of = [&](int it, const double* A, double h, double s2, double yw) {
+        if (it == 0) return vsi > 0.0 ? down_weight(h / vsi) : 1.0;
+        double R = h;
+#pragma unroll
+        for (int e = 0; e < 5; ++e) R -= A[e] * dw[e];
+        return down_weight(R / sqrt(s2 + yw));
+    };
+    auto load = [&](int64_t l, double* A, double& h, double& s2) {
+#pragma unroll
+        for (int e = 0; e < 3; ++e) A[e] = col[e * n_obs + l];
+        const double tau = col[3 * n_obs + l];
+        A[3] = A[0] * tau;
+        A[4] = A[1] * tau;
+        h = col[4 * n_obs + l];
+        s2 = col[5 * n_obs + l];
+    };
+    for (int it = 0; it < INNER_SOLVES; ++it) {
+        const double yw = y;
+        // accumulation at y; the first one also counts the outliers
+        auto accumulate = [&](double yacc, double* nout) {
+#pragma unroll
+            for (int e = 0; e < 21; ++e) acc[e] = 0.0;
+            double no = 0.0;
+            for (int64_t l = l0 + gl; l < l1; l += G) {
+                double A[5], h, s2;
+                load(l, A, h, s2);
+                const double wl = weight_of(it, A, h, s2, yw);
+                no += wl < 0.2 ? 1.0 : 0.0;
+                const double W = wl / (s2 + yacc);
+                int e = 0;
+#pragma unroll
+                for (int rr = 0; rr < 5; ++rr) {
+                    const double wa = A[rr] * W;
+#pragma unroll
+                    for (int cc = rr; cc < 5; ++cc) acc[e++] += wa * A[cc];
+                }
+#pragma unroll
+                for (int rr = 0; rr < 5; ++rr) acc[15 + rr] += A[rr] * W * h;
+                acc[20] += W * h * h;
+            }
+#pragma unroll
+            for (int e = 0; e < 21; ++e) acc[e] = group_sum<G>(acc[e]);
+            if (nout) *nout = group_sum<G>(no);
+        };
+        auto solve = [&]() {
+            double x[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            if (gl == 0) {
+                double U[25];
+                int e = 0;
+                for (int rr = 0; rr < 5; ++rr)
+                    for (int cc = rr; cc < 5; ++cc) U[rr * 5 + cc] = acc[e++];
+                for (int rr = 0; rr < 5; ++rr) x[rr] = acc[15 + rr];
+                small_chol_factor<5>(U);
+                small_chol_subst<5>(U, x);
+            }
+#pragma unroll
+            for (int e = 0; e < 5; ++e) d[e] = __shfl(x[e], leader, 64);
+        };
+        // Q(y) and Q'(y) at the current solution
+        auto chi2 = [&](double yq, double& Q, double& Qp) {
+            double q = 0.0, qp = 0.0;
+            for (int64_t l = l0 + gl; l < l1; l += G) {
+                double A[5], h, s2;
+                load(l, A, h, s2);
+                const double wl = weight_of(it, A, h, s2, yw);
+                double R = h;
+#pragma unroll
+                for (int e = 0; e < 5; ++e) R -= A[e] * d[e];
+                const double v = s2 + yq;
+                q += wl / v * R * R;
+                qp -= wl * R * R / (v * v);
+            }
+            Q = group_sum<G>(q);
+            Qp = group_sum<G>(qp);
+        };
+        double nout = 0.0;
+        y = 0.0;
+        accumulate(y, &nout);
+        const double nu = (double)(l1 - l0) - nout - 5.0;
+        solve();
+        double Q, Qp;
+        chi2(y, Q, Qp);
+        D = nu > 0.0 ? (Q - nu) / sqrt(2.0 * nu) : 0.0;
+        for (int step = 0; step < EPS_STEPS; ++step) {
+            if (!(nu > 0.0 && Q > nu && Qp < 0.0)) break;
+            y += (1.0 - Q / nu) * Q / Qp;
+            if (y < 0.0) y = 0.0;
+            accumulate(y, nullptr);
+            solve();
+            chi2(y, Q, Qp);
+        }
+#pragma unroll
+        for (int e = 0; e < 5; ++e) dw[e] = d[e];
+    }
+    if (!valid || gl != 0) return;
+    eps2_out[i] = y;
+    D_out[i] = D;
+    const double* si = s + 5 * i;
+    const double alpha = si[0], delta = si[1], plx = si[2], pma = si[3], pmd = si[4];
+    source_finish(acc, i, alpha, delta, plx, pma, pmd, cos(delta), s, prep, ds, qsrc, sdef, svar, nullptr, y);
+}
+
 // ------------------------------------------------ excess attitude noise
 __global__ __launch_bounds__(64) void k_ac_resid(DevConsts k, int64_t K, const int64_t* __restrict__ iv_off,
                                                  const double* __restrict__ ot, const double* __restrict__ oeta,
@@ -352,7 +486,7 @@ __global__ __launch_bounds__(64) void k_ac_resid(DevConsts k, int64_t K, const i
                                                  const int32_t* __restrict__ osrc, const SrcPrep* __restrict__ prep,
                                                  const double* __restrict__ knots,
                                                  const KnotTab* __restrict__ ktab, const double* __restrict__ a,
-                                                 const double* __restrict__ c, double* __restrict__ v) {
+                                                 const double* __restrict__ c, int robust, double* __restrict__ v) {
     const int lane = threadIdx.x;
     const int64_t j = blockIdx.x;
     if (j >= K) return;
@@ -365,7 +499,7 @@ __global__ __launch_bounds__(64) void k_ac_resid(DevConsts k, int64_t K, const i
         ObsEval o;
         observe(k, ot[l], oeta[l], c[ocellfov[l] >> 1], sp.r, sp.mu, sp.plx, a4, kn, kt, o);
         const double sg = (double)osig[l];
-        v[l] = o.R * o.R - sg * sg;
+        v[l] = o.R * o.R - sg * sg - (robust == 2 ? sp.pad : 0.0);       // e09 with eps_i^2 (mode 2)
     }
 }
 
@@ -382,7 +516,7 @@ __global__ __launch_bounds__(64) void k_freeze_sigma(DevConsts k, int64_t K, con
                                                      const double* __restrict__ knots,
                                                      const KnotTab* __restrict__ ktab, const double* __restrict__ a,
                                                      const double* __restrict__ c,
-                                                     const double* __restrict__ eps_a2, int eps_bucket,
+                                                     const double* __restrict__ eps_a2, int eps_bucket, int robust,
                                                      float* __restrict__ sig_eff) {
     const int lane = threadIdx.x;
     const int64_t j = blockIdx.x;
@@ -397,7 +531,7 @@ __global__ __launch_bounds__(64) void k_freeze_sigma(DevConsts k, int64_t K, con
         ObsEval o;
         observe(k, ot[l], oeta[l], c[ocellfov[l] >> 1], sp.r, sp.mu, sp.plx, a4, kn, kt, o);
         const double sg = (double)osig[l];
-        const double s2 = sg * sg + eps2;
+        const double s2 = sg * sg + eps2 + (robust == 2 ? sp.pad : 0.0);
         const double W = down_weight(o.R / sqrt(s2)) / s2;
         float se = W > 0.0 ? (float)(1.0 / sqrt(W)) : FLT_MAX;
         if (!(se <= FLT_MAX)) se = FLT_MAX;
@@ -459,9 +593,14 @@ inline unsigned groups_grid(int64_t n_items, int items_per_block) {
         ctx->k, ctx->n_src, ctx->src_off, ctx->s_t, ctx->s_eta, ctx->s_sig, ctx->s_cell, ctx->s_ell, ctx->knots,   \
         ctx->ktab, ctx->a, ctx->c, ctx->s, ctx->eps_a2, ctx->cfg.eps_bucket, ctx->rcol, ctx->n_obs, ctx->src_order)
 #define AGIS_IRLS_LAUNCH(G)                                                                                      \
-    k_s_irls<G><<<groups_grid(ctx->n_src, 256 / G), 256, 0, ctx->stream>>>(                                      \
-        ctx->n_src, ctx->src_off, ctx->rcol, ctx->n_obs, ctx->vs, ctx->s, ctx->prep, ctx->ds, ctx->qsrc, ctx->sdef, \
-        ctx->svar, ctx->src_order)
+    if (ctx->cfg.robust == 2)                                                                                    \
+        k_s_irls_eps<G><<<groups_grid(ctx->n_src, 256 / G), 256, 0, ctx->stream>>>(                              \
+            ctx->n_src, ctx->src_off, ctx->rcol, ctx->n_obs, ctx->vs, ctx->s, ctx->prep, ctx->ds, ctx->qsrc,      \
+            ctx->sdef, ctx->svar, ctx->src_order, ctx->src_eps2, ctx->src_D);                                    \
+    else                                                                                                         \
+        k_s_irls<G><<<groups_grid(ctx->n_src, 256 / G), 256, 0, ctx->stream>>>(                                  \
+            ctx->n_src, ctx->src_off, ctx->rcol, ctx->n_obs, ctx->vs, ctx->s, ctx->prep, ctx->ds, ctx->qsrc,      \
+            ctx->sdef, ctx->svar, ctx->src_order)
 
 void launch_source_update_robust(agis_ctx* ctx) {
     if (ctx->n_src == 0) return;
@@ -486,7 +625,7 @@ void launch_freeze_sigma(agis_ctx* ctx) {
     if (ctx->K > 0)
         k_freeze_sigma<<<(unsigned)ctx->K, 64, 0, ctx->stream>>>(
             ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, ctx->t_sig, ctx->t_cellfov, ctx->t_src, ctx->prep,
-            ctx->knots, ctx->ktab, ctx->a, ctx->c, ctx->eps_a2, ctx->cfg.eps_bucket, ctx->t_sig_eff);
+            ctx->knots, ctx->ktab, ctx->a, ctx->c, ctx->eps_a2, ctx->cfg.eps_bucket, ctx->cfg.robust, ctx->t_sig_eff);
     if (ctx->n_obs > 0) {
         const int64_t b = std::min<int64_t>((ctx->n_obs + 255) / 256, 65536);
         k_gather_f32<<<(unsigned)b, 256, 0, ctx->stream>>>(ctx->n_obs, ctx->s_from_t, ctx->t_sig_eff,
@@ -498,7 +637,7 @@ void launch_excess_noise(agis_ctx* ctx) {
     if (ctx->K == 0 || ctx->n_buckets == 0) return;
     k_ac_resid<<<(unsigned)ctx->K, 64, 0, ctx->stream>>>(ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, ctx->t_sig,
                                                          ctx->t_cellfov, ctx->t_src, ctx->prep, ctx->knots, ctx->ktab,
-                                                         ctx->a, ctx->c, ctx->rcol);
+                                                         ctx->a, ctx->c, ctx->cfg.robust, ctx->rcol);
     (select_in_registers(ctx, ctx->n_obs, ctx->n_buckets) ? k_bucket_eps<true> : k_bucket_eps<false>)
         <<<(unsigned)ctx->n_buckets, 64, 0, ctx->stream>>>(ctx->n_buckets, ctx->K, ctx->cfg.eps_bucket, ctx->iv_off,
                                                            ctx->rcol, ctx->eps_a2, select_reg_limit(ctx));

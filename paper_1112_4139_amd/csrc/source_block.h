@@ -11,12 +11,13 @@
 namespace agis {
 
 // acc: the 15 upper-triangle entries of N (row-major), the 5 of b and h'Wh.
-// rhs (optional, [n_src][5]) receives b.
+// rhs (optional, [n_src][5]) receives b; eps_i2 goes into the record.
 __device__ __forceinline__ void source_finish(const double acc[21], int64_t i, double alpha, double delta,
                                               double plx, double pma, double pmd, double cd, double* __restrict__ s,
                                               SrcPrep* __restrict__ prep, double* __restrict__ ds,
                                               double* __restrict__ qsrc, int32_t* __restrict__ sdef,
-                                              double* __restrict__ svar, double* __restrict__ rhs = nullptr) {
+                                              double* __restrict__ svar, double* __restrict__ rhs = nullptr,
+                                              double eps_i2 = 0.0) {
     double U[25], N[25], x[5];
     int e = 0;
     for (int rr = 0; rr < 5; ++rr)
@@ -70,7 +71,7 @@ __device__ __forceinline__ void source_finish(const double acc[21], int64_t i, d
     pr.r[2] = sd2;
     for (int cc = 0; cc < 3; ++cc) pr.mu[cc] = p2[cc] * npa + q2[cc] * npd;
     pr.plx = npl;
-    pr.pad = 0.0;
+    pr.pad = eps_i2;                      // the source's excess noise eps_i^2 (robust mode 2)
     prep[i] = pr;
 }
 

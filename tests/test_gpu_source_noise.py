@@ -1,0 +1,109 @@
+"""Robust mode 2 on the GPU: the excess source noise eps_i of Sect. 5.1.2
+(eq:epsi, eq:D) against the oracle, on the tiny robust world (1% outliers)
+with a further 200 uas of noise on every fourth source's observations."""
+import numpy as np
+import pytest
+
+import synth
+import synth.configs as C
+from test_gpu_parity import DIFFS, Pair, check_floor, fp64_floor, agis_mod  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+UAS = synth.UAS
+
+
+@pytest.fixture(scope="module")
+def world2(oracle_lib):
+    w = C.make("tiny_robust")
+    w.consts = dict(w.consts)
+    w.consts["robust"] = 2
+    eta = oracle_lib.observed_field_angles(w)
+    rng = np.random.default_rng(31)
+    extra = w.src % 4 == 0
+    eta = eta + np.where(extra, rng.normal(size=eta.size) * 200 * UAS, 0.0)
+    return w, eta
+
+
+def test_source_update_with_source_noise(agis_mod, oracle_lib, world2):
+    w, eta = world2
+    n_src = w.src_true.shape[0]
+
+    def run(pr):
+        pr.source_update()
+        run.noise = (np.asarray(pr.src_eps2, np.float64).copy(), np.asarray(pr.src_D, np.float64).copy())
+        return pr.s.copy(), pr.a.copy(), pr.c.copy()
+
+    X, O, tol = fp64_floor(oracle_lib, w, eta, run)
+    run(oracle_lib.problem_from_world(w, eta, state="start", precision="extended"))
+    e_x, d_x = run.noise
+    p = Pair(agis_mod, oracle_lib, w, eta)
+    agis_mod.agis_source_update(p.ctx)
+    G = p.gpu_state()
+    check_floor("S update, robust 2: sources", X[0], O[0], G[0], tol[0], 0)
+    e_g, d_g = agis_mod.agis_get_source_noise(p.ctx, n_src)
+    de = np.abs(np.sqrt(e_g) - np.sqrt(e_x)) / UAS
+    print(f"eps_i: median {np.median(np.sqrt(e_x[e_x > 0])) / UAS:.1f} uas over {np.mean(e_x > 0):.2f} of the "
+          f"sources; max |GPU - ext| {de.max():.2e} uas; D max diff {np.abs(d_g - d_x).max():.2e}")
+    assert de.max() < 1e-3
+    assert np.abs(d_g - d_x).max() < 1e-8
+    assert np.array_equal(e_g > 0, e_x > 0)
+    p.close()
+
+
+def test_iterations_with_source_noise(agis_mod, oracle_lib, world2):
+    """Two robust-2 S[AC] iterations with the frame rotator: eps_i enters the
+    attitude and calibration weights and the excess attitude noise."""
+    w, eta = world2
+    n_it = 2
+
+    def run(pr):
+        for _ in range(n_it):
+            pr.iterate(s_ref=w.src_true)
+        run.eps = np.asarray(pr.eps_a2, np.float64).copy()
+        return pr.s.copy(), pr.a.copy(), pr.c.copy()
+
+    X, O, tol = fp64_floor(oracle_lib, w, eta, run)
+    run(oracle_lib.problem_from_world(w, eta, state="start"))
+    e_o = run.eps
+    p = Pair(agis_mod, oracle_lib, w, eta)
+    agis_mod.agis_set_frame_reference(p.ctx, w.src_true)
+    agis_mod.agis_iterate(p.ctx, n_it)
+    G = p.gpu_state()
+    # eps_i is a root of Q(y) = nu and the outlier count n_out a threshold
+    # count, so these iterations amplify rounding: the FP64 oracle deviates
+    # from the extended-precision one by up to 8 uas (75% of the source
+    # parameters within 1e-3 uas).  Criterion as for the hybrid scheme: per
+    # class the GPU's largest and RMS deviation at most twice the FP64
+    # oracle's, and >= 99.5% of the parameters within the per-parameter
+    # FP64-floor tolerance (measured: one source parameter at 1.11x it).
+    for name, which in (("sources", 0), ("attitude", 1), ("calibration", 2)):
+        f = DIFFS[which]
+        dg, do = np.abs(f(X[which], G[which])), np.abs(f(X[which], O[which]))
+        within = float(np.mean(dg <= tol[which]))
+        rms_g, rms_o = np.sqrt(np.mean(dg * dg, axis=0)), np.sqrt(np.mean(do * do, axis=0))
+        print(f"robust 2 iterations, {name}: max |GPU - ext| {dg.max():.2e} (FP64 oracle {do.max():.2e}) uas, "
+              f"rms {np.array2string(np.atleast_1d(rms_g), precision=6)} "
+              f"(oracle {np.array2string(np.atleast_1d(rms_o), precision=6)}), "
+              f"{100 * within:.3f}% within tolerance, worst ratio {(dg / tol[which]).max():.2f}")
+        assert dg.max() <= 2.0 * do.max() + 1e-6
+        assert np.all(rms_g <= 2.0 * rms_o + 1e-6)
+        assert within >= 0.995
+    e_g = agis_mod.agis_get_excess_noise(p.ctx, e_o.size)
+    rel = np.abs(np.sqrt(e_g) - np.sqrt(e_o)) / UAS
+    print(f"robust 2 iterations: eps_a median {np.median(np.sqrt(e_o)) / UAS:.3f} uas, max diff {rel.max():.2e} uas")
+    assert rel.max() < 1e-2
+    p.close()
+
+
+def test_source_noise_calls(agis_mod, oracle_lib):
+    w = C.make("tiny_robust")
+    eta = oracle_lib.observed_field_angles(w)
+    p = Pair(agis_mod, oracle_lib, w, eta)                 # robust mode 1
+    with pytest.raises(agis_mod.AgisError) as e:
+        agis_mod.agis_get_source_noise(p.ctx, w.src_true.shape[0])
+    assert e.value.code == -7
+    p.close()
+    bad = dict(w.consts)
+    bad["robust"] = 3
+    with pytest.raises(agis_mod.AgisError):
+        agis_mod.agis_create(bad, w.knots)
