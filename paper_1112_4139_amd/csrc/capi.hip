@@ -923,8 +923,26 @@ extern "C" int agis_excess_noise_update(agis_ctx_t* ctx) {
 
 
 // --------------------------------------------------- learned extrapolation
-static int learned_alloc(agis_ctx* ctx) {
-    if (ctx->lh_ring_s) return AGIS_OK;
+// The buffers of the iteration schemes, all or none: a failed allocation
+// releases what it had allocated.
+static void learned_free(agis_ctx* ctx) {
+    for (double** v : {&ctx->lh_anchor_s, &ctx->lh_ring_s, &ctx->lh_anchor_a, &ctx->lh_ring_a, &ctx->lh_anchor_c,
+                       &ctx->lh_ring_c, &ctx->asi_part, &ctx->asi_out, &ctx->chi2_part, &ctx->chi2_out})
+        dfree(*v);
+    for (int w = 0; w < 2; ++w) {
+        dfree(ctx->lf_X[w]);
+        dfree(ctx->lf_scale[w]);
+        dfree(ctx->lf_Y[w]);
+    }
+    for (int k = 0; k < 2; ++k) {
+        dfree(ctx->bk_s[k]);
+        dfree(ctx->bk_a[k]);
+        dfree(ctx->bk_c[k]);
+        dfree(ctx->bk_e[k]);
+    }
+}
+
+static int learned_alloc_all(agis_ctx* ctx) {
     const int64_t ns = std::max<int64_t>(ctx->n_src, 1), na = std::max<int64_t>(ctx->N, 1);
     ALLOC(ctx->lh_anchor_s, 5 * ns, "history anchor");
     ALLOC(ctx->lh_ring_s, 4 * 5 * ns, "update history");
@@ -950,6 +968,14 @@ static int learned_alloc(agis_ctx* ctx) {
     ALLOC(ctx->chi2_part, std::max<int64_t>((ctx->K + 63) / 64, 1), "chi2 partials");
     ALLOC(ctx->chi2_out, 2, "chi2");
     return AGIS_OK;
+}
+
+static int learned_alloc(agis_ctx* ctx) {
+    if (ctx->chi2_out) return AGIS_OK;           // allocated last: the whole set is there
+    learned_free(ctx);
+    const int rc = learned_alloc_all(ctx);
+    if (rc != AGIS_OK) learned_free(ctx);
+    return rc;
 }
 
 static int check_which(agis_ctx* ctx, int32_t which) {
@@ -1287,14 +1313,16 @@ extern "C" int agis_learned_step(agis_ctx_t* ctx, double* q_plain, double* q_can
 // (all three at one point); r and z are evaluated at every iterate, and
 // p'N p comes from one pass over the observations.
 
+// Each buffer is allocated once; after a failed allocation a later call
+// completes the set.
 static int cg_alloc(agis_ctx* ctx) {
-    if (ctx->cg_r) return AGIS_OK;
     const int64_t n = std::max<int64_t>(cg_size(ctx), 1);
-    for (double** v : {&ctx->cg_r, &ctx->cg_z, &ctx->cg_p, &ctx->cg_ry, &ctx->cg_zy}) ALLOC(*v, n, "cg vectors");
-    ALLOC(ctx->cg_sy, 5 * std::max<int64_t>(ctx->n_src, 1), "cg state");
-    ALLOC(ctx->cg_part, 2 * 1024, "cg partial sums");
-    ALLOC(ctx->cg_qpart, std::max<int64_t>(cg_quad_blocks(ctx), 1), "cg partial sums");
-    ALLOC(ctx->cg_out, 2, "cg sums");
+    for (double** v : {&ctx->cg_r, &ctx->cg_z, &ctx->cg_p, &ctx->cg_ry, &ctx->cg_zy})
+        if (!*v) ALLOC(*v, n, "cg vectors");
+    if (!ctx->cg_sy) ALLOC(ctx->cg_sy, 5 * std::max<int64_t>(ctx->n_src, 1), "cg state");
+    if (!ctx->cg_part) ALLOC(ctx->cg_part, 2 * 1024, "cg partial sums");
+    if (!ctx->cg_qpart) ALLOC(ctx->cg_qpart, std::max<int64_t>(cg_quad_blocks(ctx), 1), "cg partial sums");
+    if (!ctx->cg_out) ALLOC(ctx->cg_out, 2, "cg sums");
     return AGIS_OK;
 }
 
@@ -1419,10 +1447,8 @@ extern "C" int agis_freeze_weights(agis_ctx_t* ctx, int32_t freeze) {
         }
         return AGIS_OK;
     }
-    if (!ctx->t_sig_eff) {
-        ALLOC(ctx->t_sig_eff, std::max<int64_t>(ctx->n_obs, 1), "frozen sigma");
-        ALLOC(ctx->s_sig_eff, std::max<int64_t>(ctx->n_obs, 1), "frozen sigma");
-    }
+    if (!ctx->t_sig_eff) ALLOC(ctx->t_sig_eff, std::max<int64_t>(ctx->n_obs, 1), "frozen sigma");
+    if (!ctx->s_sig_eff) ALLOC(ctx->s_sig_eff, std::max<int64_t>(ctx->n_obs, 1), "frozen sigma");
     launch_freeze_sigma(ctx);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(ctx->stream));
