@@ -206,6 +206,56 @@ def solve(ctx, w, m, n_iter, ref, mode, tol=1.0, log=None, asi_stride=16, asi_la
                 median_ratio=float(np.median(ratios)) if ratios else None)
 
 
+def errors_to_truth(ctx, w):
+    """Per-class RMS error of the current state against the world's true
+    parameters (uas): alpha*, delta, parallax, mu_alpha*, mu_delta, the three
+    attitude axes, calibration."""
+    x = state(ctx, w)
+    ds = x[0] - w.src_true
+    ds[:, 0] = ((ds[:, 0] + np.pi) % (2 * np.pi) - np.pi) * np.cos(w.src_true[:, 1])
+    d = _qmul(w.att_true * np.array([-1, -1, -1, 1.0]), x[1])
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    rot = 2 * d[:, :3] * np.sign(d[:, 3:4])
+    out = list(np.sqrt(np.mean(ds * ds, axis=0))) + list(np.sqrt(np.mean(rot * rot, axis=0)))
+    out.append(np.sqrt(np.mean((x[2] - w.cal_true) ** 2)))
+    return [float(v / UAS) for v in out]
+
+
+def budget_run(world, seed, n, modes, m=50, restart=40, log=None):
+    """Each scheme for the same number of block passes n from the world's
+    start values (with the frame rotator): per-class RMS error to the truth
+    and the wall time of the library calls.  No reference solution is
+    needed, so this runs at any workload size."""
+    out = {}
+    for mode in modes:
+        w, ctx = problem(world, seed)
+        t0 = time.perf_counter()
+        if mode == "plain":
+            agis.agis_iterate(ctx, n, stats=False)
+        elif mode == "cg":
+            agis.agis_cg_iterate(ctx, n, restart, stats=False)
+            agis.agis_frame_apply(ctx, agis.agis_frame_fit(ctx))
+        elif mode == "asi":
+            agis.agis_learned_reset(ctx)
+            count = done = 0
+            while done < n:
+                k = min(m, n - done)
+                agis.agis_iterate(ctx, k, stats=False)
+                done += k
+                agis.agis_learned_record(ctx)
+                count += 1
+                if count >= 3 and agis.agis_asi_step(ctx, 16, 0.99)["factor"] > 0:
+                    count = 0
+        else:
+            raise ValueError(f"budget runs take plain, asi and cg, not {mode}")
+        sec = time.perf_counter() - t0
+        out[mode] = {"evaluations": n, "seconds": sec, "rms_error_uas": errors_to_truth(ctx, w)}
+        if log:
+            log(f"{mode}: {out[mode]}")
+        agis.agis_destroy(ctx)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--world", default="tiny")
@@ -223,12 +273,21 @@ def main(argv=None):
     ap.add_argument("--modes", default="plain,asi,learned", help="solves to compare (plain, asi, learned, cg)")
     ap.add_argument("--cg-restart", type=int, default=40, help="CG iterations per cycle")
     ap.add_argument("--ref-file", default=None, help="npz cache of the evaluation reference (read if it matches)")
+    ap.add_argument("--budget", type=int, default=0,
+                    help="instead of the convergence study: run each of --modes (plain, asi, cg) for this many "
+                         "block passes and report the errors to the truth")
     args = ap.parse_args(argv)
     if args.macro is None:
         args.macro = args.horizon + 100
 
     def log(msg):
         print(f"[learned {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+    if args.budget:
+        out = budget_run(args.world, args.eval_seed, args.budget, args.modes.split(","), m=args.m,
+                         restart=args.cg_restart, log=log)
+        print(json.dumps({"world": args.world, "seed": args.eval_seed, "budget": args.budget, **out}), flush=True)
+        return
 
     data = [[], []]
     ctx_train = None
