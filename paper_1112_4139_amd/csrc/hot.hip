@@ -89,10 +89,13 @@ __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n
     double acc[21];
 #pragma unroll
     for (int e = 0; e < 21; ++e) acc[e] = 0.0;
-    // mixed precision: single-precision partials and sums with compensation
-    float fs[MIXED ? 21 : 1], fc[MIXED ? 21 : 1];
+    // mixed precision: the 15 normal-matrix sums from single-precision
+    // partials with compensation; the right-hand side and h'Wh stay FP64,
+    // so the iteration's fixed point is the FP64 one (the FP32 matrix only
+    // changes the path to it)
+    float fs[MIXED ? 15 : 1], fc[MIXED ? 15 : 1];
 #pragma unroll
-    for (int e = 0; e < (MIXED ? 21 : 1); ++e) fs[e] = fc[e] = 0.0f;
+    for (int e = 0; e < (MIXED ? 15 : 1); ++e) fs[e] = fc[e] = 0.0f;
     int64_t l = l0 + gl;
     // Current observation: columns, and the gathered attitude coefficients,
     // interval table entry and calibration of its cell.  The next
@@ -139,7 +142,7 @@ __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n
             float Af[5];
 #pragma unroll
             for (int rr = 0; rr < 5; ++rr) Af[rr] = (float)A[rr];
-            const float Wf = (float)W, Rf = (float)o.R;
+            const float Wf = (float)W;
             int e = 0;
 #pragma unroll
             for (int rr = 0; rr < 5; ++rr) {
@@ -151,8 +154,8 @@ __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n
                 }
             }
 #pragma unroll
-            for (int rr = 0; rr < 5; ++rr) kahan_add(fs[15 + rr], fc[15 + rr], Wf * Af[rr] * Rf);
-            kahan_add(fs[20], fc[20], Wf * Rf * Rf);
+            for (int rr = 0; rr < 5; ++rr) acc[15 + rr] += W * A[rr] * o.R;
+            acc[20] += W * o.R * o.R;
         } else {
             int e = 0;
 #pragma unroll
@@ -179,7 +182,7 @@ __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n
     }
     if constexpr (MIXED) {
 #pragma unroll
-        for (int e = 0; e < 21; ++e) acc[e] = (double)fs[e] - (double)fc[e];
+        for (int e = 0; e < 15; ++e) acc[e] = (double)fs[e] - (double)fc[e];
     }
 #pragma unroll
     for (int e = 0; e < 21; ++e) acc[e] = group_sum<G>(acc[e]);
@@ -248,6 +251,15 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
     const int ri = lane & 15, rk = lane >> 4;
     double4_t C = {0.0, 0.0, 0.0, 0.0};
     float4_t Cs = {0.0f, 0.0f, 0.0f, 0.0f}, Cc = {0.0f, 0.0f, 0.0f, 0.0f};
+    // mixed precision: the right-hand sides (B_n times the 4 attitude
+    // right-hand sides, and W, WR per field of view) are summed per lane in
+    // FP64 and reduced over the wavefront at the end, so the fixed point of
+    // the iteration is the FP64 one
+    double rb[MIXED ? 16 : 1], cb[MIXED ? 4 : 1];
+#pragma unroll
+    for (int e = 0; e < (MIXED ? 16 : 1); ++e) rb[e] = 0.0;
+#pragma unroll
+    for (int e = 0; e < (MIXED ? 4 : 1); ++e) cb[e] = 0.0;
     // lanes past the end evaluate the interval's last observation again with
     // weight zero
     int64_t base = l0;
@@ -323,6 +335,14 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
                 for (int rr = 0; rr < 4; ++rr) row[26 + rr] = -Wf * (gf[rr] * Rf - 2.0f * l2 * qf[rr] * Df);
                 row[30] = Wf;
                 row[31] = Wf * Rf;
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    const double rhs = -W * (g[rr] * o.R - 2.0 * lam2 * o.qraw[rr] * o.D);
+#pragma unroll
+                    for (int n = 0; n < 4; ++n) rb[4 * n + rr] += o.B[n] * rhs;
+                }
+                cb[2 * f] += W;
+                cb[2 * f + 1] += W * o.R;
             } else {
                 int e = 0;
 #pragma unroll
@@ -391,6 +411,13 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
     if constexpr (MIXED) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) C[v] = (double)Cs[v] - (double)Cc[v];
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) rb[e] += __shfl_xor(rb[e], m, 64);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) cb[e] += __shfl_xor(cb[e], m, 64);
+        }
     }
     // lane l holds C[4 v + l / 16][l % 16] (FP64 product) or
     // C[4 (l / 16) + v][l % 16] (FP32 product), v = 0..3
@@ -399,8 +426,17 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
     for (int v = 0; v < 4; ++v) {
         const int i = MIXED ? 4 * rk + v : 4 * v + rk, jj = ri;
         if (i < 10 && jj < 10) out[i * 10 + jj] = C[v];
-        else if (i >= 10 && i < 14 && jj >= 10 && jj < 14) out[100 + (i - 10) * 4 + (jj - 10)] = C[v];
-        else if (i >= 14 && jj >= 14) iv_cal[j * IV_CAL + (i - 14) * 2 + (jj - 14)] = C[v];
+        else if (!MIXED && i >= 10 && i < 14 && jj >= 10 && jj < 14) out[100 + (i - 10) * 4 + (jj - 10)] = C[v];
+        else if (!MIXED && i >= 14 && jj >= 14) iv_cal[j * IV_CAL + (i - 14) * 2 + (jj - 14)] = C[v];
+    }
+    if constexpr (MIXED) {
+        // every lane holds the reduced FP64 sums; lane e writes entry e
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            if (lane == e) out[100 + e] = rb[e];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (lane == 16 + e) iv_cal[j * IV_CAL + e] = cb[e];
     }
 }
 

@@ -1,5 +1,5 @@
-"""Mixed precision (FP32 partials and compensated FP32 normal-equation sums,
-FP64 elsewhere) against FP64: one source update against the FP64 oracle, and
+"""Mixed precision (FP32 partials and compensated FP32 normal-matrix sums;
+FP64 right-hand sides, model and solves) against FP64: one source update against the FP64 oracle, and
 the iterate after many S[AC] + frame iterations against the FP64 path (itself
 at parity with the oracle).  The error is reported in uas per class."""
 import numpy as np
@@ -59,7 +59,8 @@ def test_mixed_source_update_vs_oracle(agis_mod, oracle_lib, tiny):
     _summary("mixed S update vs FP64 oracle", ds, np.zeros((1, 3)), np.zeros(1))
     rel = np.abs(ds).max(axis=1) / upd
     print(f"error / update: median {np.median(rel):.2e}, 99% {np.percentile(rel, 99):.2e}, max {rel.max():.2e}")
-    assert np.median(rel) < 1e-3 and np.percentile(rel, 99) < 0.05
+    # the right-hand side is summed in FP64 (measured: median 9e-8, 99% 5e-5)
+    assert np.median(rel) < 1e-6 and np.percentile(rel, 99) < 1e-3
     agis_mod.agis_destroy(ctx)
 
 
@@ -92,11 +93,13 @@ def test_mixed_iterations_track_fp64(agis_mod, oracle_lib, tiny):
         agis_mod.agis_destroy(c)
     moved_s = np.sqrt(np.mean(src_diff_uas(w.src_start, l0[0]) ** 2, axis=0))
     moved_a = np.sqrt(np.mean(rot_diff_uas(w.att_start, l0[1]) ** 2, axis=0))
-    # The FP32 rounding of the band sums, amplified along the weakly
-    # determined attitude directions, makes this difference a sample of
-    # rounding noise: two equally valid orders of the A/C sums gave 0.26 and
-    # 1.1 uas (alpha*) and 1.9 and 16.6 uas (attitude x) RMS after 1000
-    # iterations.  The bounds cover that spread with a margin.
+    # The FP32 normal matrices change the path to the common fixed point
+    # (the right-hand sides are FP64), and the slow across-scan modes have
+    # not converged after 1000 iterations: measured 0.26 uas (alpha*) and
+    # 1.8 uas (attitude x) RMS; with FP32 right-hand sides two equally valid
+    # orders of the A/C sums had given 0.26-1.1 and 1.9-16.6 uas.
     assert np.all(np.sqrt(np.mean(dn[0] ** 2, axis=0)) <= 1e-3 * moved_s)
     assert np.all(np.sqrt(np.mean(dn[1] ** 2, axis=0)) <= 1e-3 * moved_a)
-    assert np.sqrt(np.mean(dn[1][:, 2] ** 2)) <= 0.5 and np.abs(dn[2]).max() <= 0.5
+    # along-scan attitude and calibration, which the iteration determines
+    # well, within 0.05 uas (measured 0.007 uas RMS and 0.027 uas max)
+    assert np.sqrt(np.mean(dn[1][:, 2] ** 2)) <= 0.05 and np.abs(dn[2]).max() <= 0.05
