@@ -38,13 +38,13 @@ from . import agis
 UAS = np.pi / 180 / 3600 * 1e-6
 
 
-def problem(name, seed, **over):
+def problem(name, seed, precision=agis.AGIS_FP64, **over):
     """A synthetic world (seeded) and a context at its start values; the
     observed field angles are the library's model at the truth plus the
     world's noise."""
     import synth.configs as C
     w = C.make(name, seed_truth=seed, seed_noise=seed + 100, seed_start=seed + 200, **over)
-    ctx = agis.agis_create(w.consts, w.knots)
+    ctx = agis.agis_create(w.consts, w.knots, precision=precision)
     n_src = w.src_true.shape[0]
     agis.agis_load_observations(ctx, w.t, np.zeros(w.n_obs), w.sigma, w.src, w.fov, w.cell, n_src, w.n_cells)
     agis.agis_set_sources(ctx, w.src_true)
@@ -221,6 +221,37 @@ def errors_to_truth(ctx, w):
     return [float(v / UAS) for v in out]
 
 
+def precision_run(world, seed, n, mode, restart=40, log=None):
+    """The same scheme (plain or cg) for n block passes in FP64 and in mixed
+    precision from the same start: each one's per-class RMS error to the
+    truth and the per-class RMS difference between the two final states
+    (uas), the measure of whether both reach the same fixed point."""
+    states, out = {}, {}
+    for name, prec in (("fp64", agis.AGIS_FP64), ("mixed", agis.AGIS_MIXED)):
+        w, ctx = problem(world, seed, precision=prec)
+        t0 = time.perf_counter()
+        if mode == "cg":
+            agis.agis_cg_iterate(ctx, n, restart, stats=False)
+            agis.agis_frame_apply(ctx, agis.agis_frame_fit(ctx))
+        else:
+            agis.agis_iterate(ctx, n, stats=False)
+        out[name] = {"seconds": time.perf_counter() - t0, "rms_error_uas": errors_to_truth(ctx, w)}
+        states[name] = state(ctx, w)
+        if log:
+            log(f"{mode} {name}: {out[name]}")
+        agis.agis_destroy(ctx)
+    a, b = states["fp64"], states["mixed"]
+    ds = b[0] - a[0]
+    ds[:, 0] = ((ds[:, 0] + np.pi) % (2 * np.pi) - np.pi) * np.cos(a[0][:, 1])
+    d = _qmul(a[1] * np.array([-1, -1, -1, 1.0]), b[1])
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    rot = 2 * d[:, :3] * np.sign(d[:, 3:4])
+    diff = list(np.sqrt(np.mean(ds * ds, axis=0))) + list(np.sqrt(np.mean(rot * rot, axis=0)))
+    diff.append(np.sqrt(np.mean((b[2] - a[2]) ** 2)))
+    out["mixed_minus_fp64_rms_uas"] = [float(v / UAS) for v in diff]
+    return out
+
+
 def budget_run(world, seed, n, modes, m=50, restart=40, log=None):
     """Each scheme for the same number of block passes n from the world's
     start values (with the frame rotator): per-class RMS error to the truth
@@ -273,6 +304,9 @@ def main(argv=None):
     ap.add_argument("--modes", default="plain,asi,learned", help="solves to compare (plain, asi, learned, cg)")
     ap.add_argument("--cg-restart", type=int, default=40, help="CG iterations per cycle")
     ap.add_argument("--ref-file", default=None, help="npz cache of the evaluation reference (read if it matches)")
+    ap.add_argument("--compare-precisions", action="store_true",
+                    help="with --budget: run the (single) mode in FP64 and in mixed precision and report the "
+                         "difference of the final states")
     ap.add_argument("--budget", type=int, default=0,
                     help="instead of the convergence study: run each of --modes (plain, asi, cg) for this many "
                          "block passes and report the errors to the truth")
@@ -283,6 +317,12 @@ def main(argv=None):
     def log(msg):
         print(f"[learned {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
+    if args.budget and args.compare_precisions:
+        out = precision_run(args.world, args.eval_seed, args.budget, args.modes.split(",")[0],
+                            restart=args.cg_restart, log=log)
+        print(json.dumps({"world": args.world, "seed": args.eval_seed, "budget": args.budget,
+                          "mode": args.modes.split(",")[0], **out}), flush=True)
+        return
     if args.budget:
         out = budget_run(args.world, args.eval_seed, args.budget, args.modes.split(","), m=args.m,
                          restart=args.cg_restart, log=log)
