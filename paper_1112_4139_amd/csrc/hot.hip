@@ -194,7 +194,7 @@ __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n
 typedef double double4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
-constexpr int AC_WAVES = 2;             // wavefronts per block, one knot interval each
+constexpr int AC_WAVES = 1;             // wavefronts per block, one knot interval each (2 and 4 measured 4% and 7% slower)
 constexpr int AC_XS = 33;               // LDS row stride (doubles) of the transposition buffer
 
 // A/C accumulation as a matrix product on the FP64 matrix cores.  Every
