@@ -258,6 +258,9 @@ class Problem:
         self.src = np.ascontiguousarray(src, dtype=np.int32)
         self.fov = np.ascontiguousarray(fov, dtype=np.int8)
         self.cell = np.ascontiguousarray(cell, dtype=np.int32)
+        if int(consts.get("robust", 0)) and self.cell.size and self.cell.min() < 0:
+            # the excess attitude noise would need its ACP and ACF components
+            raise ValueError("robust weighting with across-scan observations is not modelled")
         self.s = self._arr(s).copy()
         self.a = self._arr(a).copy()
         self.c = self._arr(c).copy()
@@ -441,7 +444,11 @@ def problem_from_world(world, eta_obs=None, state="start", precision="double"):
 
 
 def observed_field_angles(world):
-    """eta_obs = eta(t | s_true, a_true) - c_true(cell) + noise (Sect. 3.5 at the truth)."""
+    """eta_obs = eta(t | s_true, a_true) - c_true(cell) + noise (Sect. 3.5 at
+    the truth); for an across-scan observation (cell < 0) zeta(t | s_true,
+    a_true) + noise (eq:resAC, no calibration term)."""
     pr = problem_from_world(world, eta_obs=None, state="truth")
     out = pr.observe()
-    return out["eta"] - world.cal_true[world.cell] + world.eps
+    ac = world.cell < 0
+    al = np.asarray(out["eta"]) - world.cal_true[np.where(ac, 0, world.cell)]
+    return np.where(ac, np.asarray(out["zeta"]), al) + world.eps

@@ -250,9 +250,12 @@ typedef struct {
     double ubar[3], u[3], Su[3];
     double phi, zeta, eta, R;
     int f;
+    int ac;                     /* 1: across-scan observation (cell < 0) */
 } orc_fwd_t;
 
-/* Sect. 3.2-3.5: the computed AL field angle and the residual. */
+/* Sect. 3.2-3.5: the computed field angles and the residual: eq:resAL for
+ * an along-scan observation, eq:resAC (observed minus computed zeta, no
+ * calibration term) for an across-scan one, marked by cell < 0. */
 static void forward_one(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st,
                         int64_t l, orc_fwd_t* o) {
     const double t = obs->t[l];
@@ -291,13 +294,15 @@ static void forward_one(const orc_world_t* w, const orc_obs_t* obs, const orc_st
     o->zeta = atan2(o->Su[2], sqrt(o->Su[0] * o->Su[0] + o->Su[1] * o->Su[1]));
     o->f = o->phi >= 0.0 ? 1 : -1;
     o->eta = o->phi - o->f * 0.5 * w->gamma_c;
-    /* eq:resAL with the generic calibration model (eq:generic1) */
-    o->R = obs->eta_obs[l] + st->c[obs->cell[l]] - o->eta;
+    /* eq:resAL with the generic calibration model (eq:generic1); eq:resAC */
+    o->ac = obs->cell[l] < 0;
+    o->R = o->ac ? obs->eta_obs[l] - o->zeta : obs->eta_obs[l] + st->c[obs->cell[l]] - o->eta;
 }
 
-/* Sect. 5.1.3: design row -dR_AL/ds for (alpha*, delta, parallax, mu_alpha*,
+/* Sect. 5.1.3: design row -dR/ds for (alpha*, delta, parallax, mu_alpha*,
  * mu_delta): eq:ubardiff, eq:duds, eq:srspropdiff, eq:srspqr,
- * eq:srsprop1diffsol. */
+ * eq:srsprop1diffsol.  Along scan d phi = sec(zeta) m'du, across scan
+ * d zeta = n'du, with m and n of eq:srspqr in the SRS. */
 static void source_partials(const orc_fwd_t* o, double A[5]) {
     double dub[5][3];
     for (int k = 0; k < 3; ++k) {
@@ -311,24 +316,32 @@ static void source_partials(const orc_fwd_t* o, double A[5]) {
     double ubv = dot3(o->ubar, o->vc);
     double sp = sin(o->phi), cp = cos(o->phi), sz = sin(o->zeta), cz = cos(o->zeta);
     double m[3] = {-sp, cp, 0.0};
-    (void)sz;
+    double n[3] = {-sz * cp, -sz * sp, cz};
     for (int j = 0; j < 5; ++j) {
         double du[3];
         double vd = dot3(o->vc, dub[j]);
         for (int k = 0; k < 3; ++k) du[k] = (1.0 - ubv) * dub[j][k] - o->ubar[k] * vd;
         double dSu[3];
         orc_frame_rotate(o->q, du, dSu);
-        A[j] = dot3(m, dSu) / cz;
+        A[j] = o->ac ? dot3(n, dSu) : dot3(m, dSu) / cz;
     }
 }
 
-/* Sect. 5.2.3: dR_AL/dq = -(eq:dfadq) = 2 sec(zeta) q {S'n, 0}. */
+/* Sect. 5.2.3: dR_AL/dq = -(eq:dfadq) = 2 sec(zeta) q {S'n, 0}; across
+ * scan dR_AC/dq = -(eq:dfadq) = -2 q {S'm, 0}. */
 static void attitude_partial(const orc_fwd_t* o, double g[4]) {
     double sp = sin(o->phi), cp = cos(o->phi), sz = sin(o->zeta), cz = cos(o->zeta);
-    double nq[4] = {-sz * cp, -sz * sp, cz, 0.0};
+    double v[4] = {-sz * cp, -sz * sp, cz, 0.0};
+    double f = 2.0 / cz;
+    if (o->ac) {
+        v[0] = -sp;
+        v[1] = cp;
+        v[2] = 0.0;
+        f = -2.0;
+    }
     double t[4];
-    orc_qmul(o->q, nq, t);
-    for (int c = 0; c < 4; ++c) g[c] = 2.0 / cz * t[c];
+    orc_qmul(o->q, v, t);
+    for (int c = 0; c < 4; ++c) g[c] = f * t[c];
 }
 
 void orc_observe(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st,
@@ -773,6 +786,7 @@ static void calibration_solve(const orc_world_t* w, const orc_obs_t* obs, const 
         forward_one(w, obs, st, l, &o);
         double W = weight(w, obs, st, l, &o);
         int32_t c = obs->cell[l];
+        if (c < 0) continue;                        /* across scan: no calibration term */
         Nc[c] += 1.0 * W * 1.0;
         bc[c] -= 1.0 * o.R * W;
     }
@@ -852,7 +866,7 @@ void orc_normal_rhs(const orc_world_t* w, const orc_obs_t* obs, const orc_state_
                 bn[r] -= (dR * o.R + lam2 * dD * o.D) * W;
             }
         }
-        rc[obs->cell[l]] -= 1.0 * o.R * W;
+        if (!o.ac) rc[obs->cell[l]] -= 1.0 * o.R * W;
     }
 }
 
@@ -874,7 +888,7 @@ double orc_normal_quadratic(const orc_world_t* w, const orc_obs_t* obs, const or
         source_partials(&o, A);
         attitude_partial(&o, g);
         const double* vs = v + 5 * (int64_t)obs->src[l];
-        double jr = vc[obs->cell[l]], jd = 0.0;
+        double jr = o.ac ? 0.0 : vc[obs->cell[l]], jd = 0.0;
         for (int k = 0; k < 5; ++k) jr -= A[k] * vs[k];
         for (int kn = 0; kn < M_ORDER; ++kn) {
             const double* vn = va + 4 * (o.ell - (M_ORDER - 1) + kn);

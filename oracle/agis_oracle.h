@@ -44,11 +44,12 @@ typedef struct {
 typedef struct {
     int64_t n;
     const double* t;          /* observation time [s] */
-    const double* eta_obs;    /* observed AL field angle without calibration [rad] */
-    const float* sigma;       /* formal AL uncertainty [rad] */
+    const double* eta_obs;    /* observed AL field angle without calibration, or the
+                                 observed AC field angle zeta (cell < 0) [rad] */
+    const float* sigma;       /* formal AL (AC) uncertainty [rad] */
     const int32_t* src;       /* source index */
     const int8_t* fov;        /* +1 preceding, -1 following */
-    const int32_t* cell;      /* calibration cell */
+    const int32_t* cell;      /* calibration cell; -1: across-scan observation (eq:resAC) */
 } orc_obs_t;
 
 typedef struct {

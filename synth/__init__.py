@@ -21,7 +21,9 @@ Conventions shared as data (both implementations read them from the dict):
            equatorial frame by ``eps_obl`` about X
   sources  rows (alpha, delta, parallax, pm_alpha*, pm_delta)
   attitude rows (x, y, z, w) B-spline coefficients, order M = 4
-  cells    cell = 2 * day + (fov == -1), day counted from the mission start
+  cells    cell = 2 * day + (fov == -1), day counted from the mission start;
+           cell = -1 marks an across-scan (AC) observation, which has no
+           calibration parameter
 """
 from __future__ import annotations
 
@@ -92,6 +94,8 @@ class WorldSpec:
     knot_dt: float = 1800.0           # attitude knot interval [s]
     ccd_per_transit: int = 1          # 1 (single line at eta0 = 0) or 9 (AF1..AF9)
     sigma_al: float = 100.0 * UAS     # AL standard uncertainty [rad]
+    ac_obs: bool = False              # one across-scan observation per transit (first CCD line)
+    sigma_ac: float = 0.0             # AC standard uncertainty [rad]; 0: sigma_al * 520 / 92
     noise: bool = True                # add N(0, sigma) observation noise
     outlier_frac: float = 0.0         # fraction of obs whose noise is N(0, 50 mas)
     att_true_pert: float = 10.0 * MAS
@@ -326,6 +330,29 @@ def make_world(spec: WorldSpec, law: dict | None = None, progress=None) -> World
         rng_o = np.random.default_rng(spec.seed_outlier)
         bad = rng_o.random(t_obs.shape[0]) < spec.outlier_frac
         eps[bad] = rng_o.normal(0.0, 50.0 * MAS, int(bad.sum()))
+    if spec.ac_obs:
+        # across-scan observations, appended after the along-scan ones: one
+        # per transit at the time of its first CCD line, AC uncertainty in
+        # the ratio of the paper's bright-star figures (520 / 92 uas), noise
+        # from a stream of its own
+        t_ac = tt - eta0[0] / law["wspin"]
+        src_tr = np.repeat(np.arange(n, dtype=np.int32), ntr)
+        k_ac = (t_ac >= t_beg) & (t_ac <= t_end)
+        t_ac, f_ac, s_ac = t_ac[k_ac], ff[k_ac], src_tr[k_ac]
+        sig_ac = spec.sigma_ac if spec.sigma_ac > 0.0 else spec.sigma_al * 520.0 / 92.0
+        sg_ac = np.full(t_ac.shape[0], sig_ac, dtype=np.float32)
+        if spec.noise:
+            e_ac = np.random.default_rng([spec.seed_noise, 1]).standard_normal(t_ac.shape[0]) * sg_ac.astype(
+                np.float64)
+        else:
+            e_ac = np.zeros(t_ac.shape[0])
+        t_obs = np.concatenate([t_obs, t_ac])
+        fov = np.concatenate([fov, f_ac])
+        src_idx = np.concatenate([src_idx, s_ac])
+        eta_nom = np.concatenate([eta_nom, np.full(t_ac.shape[0], eta0[0])])
+        cell = np.concatenate([cell, np.full(t_ac.shape[0], -1, np.int32)])
+        sigma = np.concatenate([sigma, sg_ac])
+        eps = np.concatenate([eps, e_ac])
 
     rng_s = np.random.default_rng(spec.seed_start)
     so = spec.start_offset

@@ -234,3 +234,73 @@ def test_calibration_partial(small_problem):
     m = w.cell == 5
     np.testing.assert_allclose(d[m], 1e-9, rtol=1e-6)     # eq:pdC with Phi = 1
     assert np.all(d[~m] == 0)
+
+
+# ---------------------------------------------------------------- across scan
+@pytest.fixture(scope="module")
+def small_ac_problem(oracle_lib):
+    import synth.configs as C
+    w = C.make("small", ac_obs=True)
+    eta = oracle_lib.observed_field_angles(w)
+    return w, oracle_lib.problem_from_world(w, eta, state="start")
+
+
+def test_across_scan_residual_has_no_calibration(small_ac_problem):
+    """eq:resAC: observed minus computed zeta, untouched by the calibration
+    (the along-scan residuals move by the cell offset, eq:pdC)."""
+    w, pr = small_ac_problem
+    ac = w.cell < 0
+    o = pr.observe()
+    np.testing.assert_array_equal(o["R"][ac], pr.eta_obs[ac] - o["zeta"][ac])
+    c0 = pr.c.copy()
+    pr.set_state(c=c0 + 1e-9)
+    R2 = pr.observe()["R"]
+    pr.set_state(c=c0)
+    assert np.array_equal(R2[ac], o["R"][ac])
+    np.testing.assert_allclose(R2[~ac] - o["R"][~ac], 1e-9, rtol=1e-6)
+
+
+def test_across_scan_partials_finite_difference(small_ac_problem):
+    """Source and attitude partials of the AC residual (n'du of
+    eq:srsprop1diffsol and -2 q {S'm, 0}) against central differences."""
+    w, pr = small_ac_problem
+    base = pr.observe(partials=True)
+    ac_idx = np.flatnonzero(w.cell < 0)
+    sel = ac_idx[np.arange(0, ac_idx.size, ac_idx.size // 25)[:25]]
+    s0, a0 = pr.s.copy(), pr.a.copy()
+    h = 1.0 * MAS
+    for l in sel:
+        i = w.src[l]
+        scale = np.abs(base["dsrc"][l]).max()
+        for j in range(5):
+            sp, sm = s0.copy(), s0.copy()
+            step = h / np.cos(s0[i, 1]) if j == 0 else h
+            sp[i, j] += step
+            sm[i, j] -= step
+            pr.set_state(s=sp)
+            Rp = pr.observe(l, l + 1)["R"][l]
+            pr.set_state(s=sm)
+            Rm = pr.observe(l, l + 1)["R"][l]
+            fd = -(Rp - Rm) / (2 * h)
+            assert abs(fd - base["dsrc"][l, j]) < 1e-5 * scale, (l, j, fd, base["dsrc"][l, j])
+    pr.set_state(s=s0)
+    hh = 1e-8
+    for l in sel[:10]:
+        ell = base["ell"][l]
+        qn = np.linalg.norm(base["qraw"][l])
+        for k in range(4):
+            n = ell - 3 + k
+            for c in range(4):
+                ap, am = a0.copy(), a0.copy()
+                ap[n, c] += hh
+                am[n, c] -= hh
+                pr.set_state(a=ap)
+                Rp = pr.observe(l, l + 1)["R"][l]
+                pr.set_state(a=am)
+                Rm = pr.observe(l, l + 1)["R"][l]
+                anR = base["bspl"][l, k] * base["dq"][l, c] / qn
+                assert abs((Rp - Rm) / (2 * hh) - anR) < 2e-6 * np.abs(base["dq"][l]).max(), (l, k, c)
+    pr.set_state(a=a0)
+    # dR/dq has no component along q, across scan as along scan
+    qn = base["qraw"] / np.linalg.norm(base["qraw"], axis=1)[:, None]
+    assert np.abs((qn * base["dq"]).sum(axis=1)).max() < 1e-13
