@@ -113,18 +113,26 @@ typedef struct {
 } agis_config_t;
 
 /*
- * One AL observation record per element (Sect. 3.5, eq:synth/eq:resAL), SoA:
+ * One observation record per element (Sect. 3.5, eq:synth with eq:resAL or
+ * eq:resAC; the AL and AC components of an observation are separate
+ * records), SoA:
  *   t       [n] observation time [s]
- *   eta_obs [n] observed AL field angle of the fiducial line, without the
- *               calibration term [rad]; the model value is eta_obs + c_cell
- *   sigma   [n] formal AL standard uncertainty [rad], float32, > 0
+ *   eta_obs [n] along scan: observed AL field angle of the fiducial line,
+ *               without the calibration term [rad] (model value eta_obs +
+ *               c_cell); across scan: the observed AC field angle zeta [rad]
+ *   sigma   [n] formal AL or AC standard uncertainty [rad], float32, > 0
  *   src     [n] source index in [0, n_src)
  *   fov     [n] field of view: +1 preceding, -1 following
- *   cell    [n] calibration cell in [0, n_cells); cells are grouped in
+ *   cell    [n] calibration cell in [0, n_cells), or -1 for an across-scan
+ *               observation (no calibration parameter); cells are grouped in
  *               constraint pairs (2j, 2j+1) with c_2j + c_2j+1 = 0
- *               (eq:calCon); within one knot interval all observations of
+ *               (eq:calCon); within one knot interval all AL observations of
  *               one field of view must share a cell, and each cell must cover
- *               a contiguous run of knot intervals (AGIS_E_SHAPE otherwise)
+ *               a contiguous run of knot intervals (AGIS_E_SHAPE otherwise).
+ * Across-scan observations enter the S and A blocks, the residuals, the
+ * chi^2 and conjugate gradients; a context with robust != 0 refuses them
+ * (AGIS_E_INVALID_ARG at load: the excess attitude noise of eq e09 is
+ * estimated for the AL component only).
  */
 typedef struct {
     int64_t n;

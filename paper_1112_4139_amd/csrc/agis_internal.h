@@ -52,6 +52,7 @@ struct agis_ctx {
     // observation store
     bool loaded = false;
     int64_t n_obs = 0, n_src = 0, n_cells = 0;
+    bool has_ac = false;                 // some observation is across scan (input cell -1)
     // by (source, time)
     double* s_t = nullptr;
     double* s_eta = nullptr;
@@ -81,7 +82,7 @@ struct agis_ctx {
     // parameters
     double* s = nullptr;                 // [n_src][5]
     double* a = nullptr;                 // [N][4]
-    double* c = nullptr;                 // [n_cells]
+    double* c = nullptr;                 // [n_cells + 1]; entry n_cells (across scan) stays 0
     agis::SrcPrep* prep = nullptr;       // [n_src]
     double* s_ref = nullptr;             // [n_src][5] frame reference (optional)
     bool have_ref = false;

@@ -293,6 +293,7 @@ extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
     k.sin_half_gamma = std::sin(k.gamma_half);
     k.half_gamma_err = (double)((long double)k.gamma_half -
                                 std::atan2((long double)k.sin_half_gamma, (long double)k.cos_half_gamma));
+    k.ac_cf0 = INT32_MAX;                    // set by agis_load_observations
     build_segments(ctx);
     if (cfg->robust) {
         ctx->n_buckets = (ctx->K + cfg->eps_bucket - 1) / cfg->eps_bucket;
@@ -409,13 +410,15 @@ extern "C" int agis_load_observations(agis_ctx_t* ctx, const agis_obs_soa_t* obs
         return set_error(ctx, AGIS_E_INVALID_ARG, "null observation column");
     if (obs->n >= (int64_t)1 << 31) return set_error(ctx, AGIS_E_SHAPE, "at most 2^31 - 1 observations");
     if (where != AGIS_HOST && where != AGIS_DEVICE) return set_error(ctx, AGIS_E_INVALID_ARG, "bad 'where'");
+    if (n_cells >= (int64_t)1 << 29) return set_error(ctx, AGIS_E_SHAPE, "at most 2^29 - 1 calibration cells");
     HIPCHK(hipStreamSynchronize(ctx->stream));
     free_store(ctx);
     ctx->n_obs = obs->n;
     ctx->n_src = n_src;
     ctx->n_cells = n_cells;
     ALLOC(ctx->s, 5 * n_src, "sources");
-    ALLOC(ctx->c, n_cells, "calibration");
+    ALLOC(ctx->c, n_cells + 1, "calibration");
+    ctx->k.ac_cf0 = (int32_t)(2 * n_cells);
     ALLOC(ctx->prep, n_src, "source prep");
     ALLOC(ctx->ds, 5 * n_src, "source updates");
     ALLOC(ctx->qsrc, n_src, "source chi2");
@@ -423,7 +426,7 @@ extern "C" int agis_load_observations(agis_ctx_t* ctx, const agis_obs_soa_t* obs
     ALLOC(ctx->svar, 5 * n_src, "source variances");
     ALLOC(ctx->dc, n_cells, "calibration updates");
     HIPCHK(hipMemsetAsync(ctx->s, 0, 5 * std::max<int64_t>(n_src, 1) * sizeof(double), ctx->stream));
-    HIPCHK(hipMemsetAsync(ctx->c, 0, std::max<int64_t>(n_cells, 1) * sizeof(double), ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->c, 0, (n_cells + 1) * sizeof(double), ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->dc, 0, std::max<int64_t>(n_cells, 1) * sizeof(double), ctx->stream));
     {
         // unit weights for the frame fit until the first S update

@@ -172,18 +172,21 @@ __global__ __launch_bounds__(64) void k_cg_quad(DevConsts k, int64_t K, const in
         for (int64_t l = iv_off[j] + lane; l < iv_off[j + 1]; l += 64) {
             const int32_t i = osrc[l];
             const SrcPrep sp = prep[i];
-            const int32_t cell = ocellfov[l] >> 1;
+            const int32_t cf = ocellfov[l], cell = cf >> 1;
+            // across scan: pseudo-cell n_cells, no calibration unknown
+            const bool ac = cf >= k.ac_cf0;
             ObsEval o;
-            observe(k, ot[l], oeta[l], c[cell], sp.r, sp.mu, sp.plx, a + 4 * j, knots + (j + 1), kt, o);
+            observe(k, ot[l], oeta[l], c[cell], sp.r, sp.mu, sp.plx, a + 4 * j, knots + (j + 1), kt, o, ac);
             const double cd = sqrt(sp.r[0] * sp.r[0] + sp.r[1] * sp.r[1]);
             const double icd = 1.0 / cd;
             const double pv[3] = {-sp.r[1] * icd, sp.r[0] * icd, 0.0};
             const double qv[3] = {-sp.r[2] * sp.r[0] * icd, -sp.r[2] * sp.r[1] * icd, cd};
             double A[5], g[4];
-            source_partials(o, pv, qv, sp.r, A);
-            attitude_partial(o, g);
+            source_partials(o, pv, qv, sp.r, A, ac);
+            attitude_partial(o, g, ac);
             const double* ps = p + 5 * (int64_t)i;
-            double jr = pc[cell], jd = 0.0;
+            double jr = 0.0, jd = 0.0;
+            if (!ac) jr = pc[cell];
 #pragma unroll
             for (int e = 0; e < 5; ++e) jr -= A[e] * ps[e];
 #pragma unroll

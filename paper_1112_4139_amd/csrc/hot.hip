@@ -45,7 +45,9 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
     s = t;
 }
 
-template <int G, bool MIXED>
+// AC: the observations may include across-scan ones (cell/fov code from
+// k.ac_cf0 on); the along-scan-only instance is the plain pass.
+template <int G, bool MIXED, bool AC>
 __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n_src, const int64_t* __restrict__ off,
                                                        const double* __restrict__ ot, const double* __restrict__ oeta,
                                                        const float* __restrict__ osig,
@@ -104,6 +106,7 @@ __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n
     double t_c = 0.0, e_c = 0.0, cal_c = 0.0;
     float s_c = 1.0f;
     int32_t ell_c = 3;
+    bool ac_c = false;
     double a_c[16];
     KnotTab kt_c = {0.0, 1.0, 0.0, 0.0};
 #pragma unroll
@@ -113,7 +116,9 @@ __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n
         e_c = oeta[l];
         s_c = osig[l];
         ell_c = oell[l];
-        cal_c = c[ocell[l] >> 1];
+        const int32_t cf = ocell[l];
+        cal_c = c[cf >> 1];
+        ac_c = AC && cf >= k.ac_cf0;
         const double* a4 = a + 4 * (ell_c - 3);
 #pragma unroll
         for (int e = 0; e < 16; ++e) a_c[e] = a4[e];
@@ -133,9 +138,9 @@ __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n
             ell_n = oell[ln];
         }
         ObsEval o;
-        observe(k, t_c, e_c, cal_c, r, mu, plx, a_c, knots + (ell_c - 2), kt_c, o);
+        observe(k, t_c, e_c, cal_c, r, mu, plx, a_c, knots + (ell_c - 2), kt_c, o, ac_c);
         double A[5];
-        source_partials(o, p, q, r, A);
+        source_partials(o, p, q, r, A, ac_c);
         const double sg = (double)s_c;
         const double W = rcp_nr(sg * sg);
         if constexpr (MIXED) {
@@ -174,6 +179,7 @@ __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n
         ell_c = ell_n;
         if (more) {
             cal_c = c[c_n >> 1];
+            ac_c = AC && c_n >= k.ac_cf0;
             const double* a4 = a + 4 * (ell_n - 3);
 #pragma unroll
             for (int e2 = 0; e2 < 16; ++e2) a_c[e2] = a4[e2];
@@ -212,7 +218,9 @@ constexpr int AC_XS = 33;               // LDS row stride (doubles) of the trans
 // from single-precision partials, each 64-observation chunk is summed by
 // v_mfma_f32_16x16x4 and the chunk sums enter compensated (Kahan) FP32
 // running sums, converted to FP64 for the band solve.
-template <bool MIXED>
+// AC: across-scan observations present (cell/fov code from k.ac_cf0 on):
+// their rows carry the AC attitude partials and no calibration entries.
+template <bool MIXED, bool AC>
 __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t K, const int64_t* __restrict__ iv_off,
                                                            const double* __restrict__ ot,
                                                            const double* __restrict__ oeta,
@@ -293,10 +301,11 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
             src_n = osrc[le];
         }
         {
+            const bool ac = AC && cf_c >= k.ac_cf0;
             ObsEval o;
-            observe(k, t_c, e_c, c[cf_c >> 1], sp_c.r, sp_c.mu, sp_c.plx, sh_a[wv], sh_k[wv], kt, o);
+            observe(k, t_c, e_c, c[cf_c >> 1], sp_c.r, sp_c.mu, sp_c.plx, sh_a[wv], sh_k[wv], kt, o, ac);
             double g[4];
-            attitude_partial(o, g);
+            attitude_partial(o, g, ac);
             const double sg = (double)s_c;
             double W;
             if (robust) {
@@ -324,8 +333,8 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
                     for (int m = n; m < 4; ++m) row[e++] = B[n] * B[m];
 #pragma unroll
                 for (int n = 0; n < 4; ++n) row[10 + n] = B[n];
-                row[14] = f == 0 ? 1.0f : 0.0f;
-                row[15] = f == 1 ? 1.0f : 0.0f;
+                row[14] = (f == 0 && !ac) ? 1.0f : 0.0f;
+                row[15] = (f == 1 && !ac) ? 1.0f : 0.0f;
                 e = 0;
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr)
@@ -341,8 +350,10 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
 #pragma unroll
                     for (int n = 0; n < 4; ++n) rb[4 * n + rr] += o.B[n] * rhs;
                 }
-                cb[2 * f] += W;
-                cb[2 * f + 1] += W * o.R;
+                if (!ac) {
+                    cb[2 * f] += W;
+                    cb[2 * f + 1] += W * o.R;
+                }
             } else {
                 int e = 0;
 #pragma unroll
@@ -351,8 +362,8 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
                     for (int m = n; m < 4; ++m) row[e++] = o.B[n] * o.B[m];
 #pragma unroll
                 for (int n = 0; n < 4; ++n) row[10 + n] = o.B[n];
-                row[14] = f == 0 ? 1.0 : 0.0;
-                row[15] = f == 1 ? 1.0 : 0.0;
+                row[14] = (f == 0 && !ac) ? 1.0 : 0.0;
+                row[15] = (f == 1 && !ac) ? 1.0 : 0.0;
                 e = 0;
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr)
@@ -657,7 +668,8 @@ inline int groups_grid(int64_t n_items, int items_per_block) {
 }  // namespace
 
 #define AGIS_S_LAUNCH(G)                                                                                       \
-    (ctx->cfg.precision == AGIS_MIXED ? k_source_update<G, true> : k_source_update<G, false>)                  \
+    (ctx->cfg.precision == AGIS_MIXED ? (ctx->has_ac ? k_source_update<G, true, true> : k_source_update<G, true, false>) \
+                                      : (ctx->has_ac ? k_source_update<G, false, true> : k_source_update<G, false, false>)) \
         <<<groups_grid(ctx->n_src, 256 / G), 256, 0, ctx->stream>>>(                                           \
         ctx->k, ctx->n_src, ctx->src_off, ctx->s_t, ctx->s_eta, s_sig_now(ctx), ctx->s_cell, ctx->s_ell, ctx->knots, \
         ctx->ktab, ctx->a, ctx->c, ctx->s, ctx->prep, ctx->ds, ctx->qsrc, ctx->sdef, ctx->svar, ctx->src_order, \
@@ -675,7 +687,8 @@ void launch_source_update(agis_ctx* ctx) {
 
 void launch_ac_pass(agis_ctx* ctx) {
     if (ctx->K == 0) return;
-    (ctx->cfg.precision == AGIS_MIXED ? k_ac_pass<true> : k_ac_pass<false>)
+    (ctx->cfg.precision == AGIS_MIXED ? (ctx->has_ac ? k_ac_pass<true, true> : k_ac_pass<true, false>)
+                                      : (ctx->has_ac ? k_ac_pass<false, true> : k_ac_pass<false, false>))
         <<<(unsigned)((ctx->K + AC_WAVES - 1) / AC_WAVES), 64 * AC_WAVES, 0, ctx->stream>>>(
         ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, t_sig_now(ctx), ctx->t_cellfov, ctx->t_src, ctx->prep,
         ctx->knots, ctx->ktab, ctx->a, ctx->c, ctx->eps_a2, ctx->cfg.eps_bucket, robust_now(ctx), ctx->iv_sums,

@@ -292,8 +292,9 @@ __global__ __launch_bounds__(256) void k_residuals(DevConsts k, int64_t K, const
     const KnotTab kt = ktab[j];
     for (int64_t l = iv_off[j] + lane; l < iv_off[j + 1]; l += WAVE) {
         const SrcPrep sp = prep[osrc[l]];
+        const int32_t cf = ocellfov[l];
         ObsEval o;
-        observe(k, ot[l], oeta[l], c[ocellfov[l] >> 1], sp.r, sp.mu, sp.plx, a4, kn, kt, o);
+        observe(k, ot[l], oeta[l], c[cf >> 1], sp.r, sp.mu, sp.plx, a4, kn, kt, o, cf >= k.ac_cf0);
         R[operm[l]] = o.R;
     }
 }

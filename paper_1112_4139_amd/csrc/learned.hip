@@ -431,8 +431,10 @@ __global__ __launch_bounds__(64) void k_chi2_partial(DevConsts k, int64_t K, con
         const KnotTab kt = ktab[j];
         for (int64_t l = iv_off[j] + lane; l < iv_off[j + 1]; l += 64) {
             const SrcPrep sp = prep[osrc[l]];
+            const int32_t cf = ocellfov[l];
             ObsEval o;
-            observe(k, ot[l], oeta[l], c[ocellfov[l] >> 1], sp.r, sp.mu, sp.plx, a + 4 * j, knots + (j + 1), kt, o);
+            observe(k, ot[l], oeta[l], c[cf >> 1], sp.r, sp.mu, sp.plx, a + 4 * j, knots + (j + 1), kt, o,
+                    cf >= k.ac_cf0);
             const double sg = (double)osig[l];
             acc += o.R * o.R / (sg * sg);
         }

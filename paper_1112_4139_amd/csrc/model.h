@@ -1,8 +1,9 @@
 // Device-side observation model of the astrometric core solution for one
-// along-scan observation: proper direction (Sect. 3.2), attitude quaternion
-// from the cubic B-spline (Sect. 3.3, Appendix B), instrument angles and
-// field angle (eq:srsprop1, eq:srspropeta), residual (eq:resAL), and the
-// partial derivatives used by the S and A blocks (Sect. 5.1.3, 5.2.3-5.2.4).
+// along-scan or across-scan observation: proper direction (Sect. 3.2),
+// attitude quaternion from the cubic B-spline (Sect. 3.3, Appendix B),
+// instrument angles and field angles (eq:srsprop1, eq:srspropeta), residual
+// (eq:resAL, eq:resAC), and the partial derivatives used by the S and A
+// blocks (Sect. 5.1.3, 5.2.3-5.2.4).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,6 +23,7 @@ struct DevConsts {
     double year_s;
     double cos_half_gamma, sin_half_gamma;   // rounded cos, sin of Gamma_c / 2
     double half_gamma_err;                   // Gamma_c/2 - atan2(sin_half_gamma, cos_half_gamma)
+    int32_t ac_cf0;                          // 2 n_cells: cell/fov codes from here on are across scan
 };
 
 // Source data gathered per observation by the time-ordered pass: barycentric
@@ -132,7 +134,7 @@ __device__ __forceinline__ void quat2mat_h(const double q[4], double inv_n2, dou
 
 // Everything one observation contributes; filled by observe().
 struct ObsEval {
-    double R;          // residual eta_obs + c - eta
+    double R;          // residual eta_obs + c - eta (across scan: zeta_obs - zeta)
     double ubar[3];    // coordinate direction <r + tau mu - plx b>
     double vc[3];      // v_G / c
     double b[3];       // observer position [AU]
@@ -161,11 +163,14 @@ struct ObsEval {
 //  * the field angle as atan(y'/x') of the SRS direction rotated by the
 //    field's Gamma_c/2 (odd series to z^9 for |z| < 1e-2, atan2 otherwise);
 //  * normalisations by Newton-refined reciprocal square roots.
-// Every replacement equals the plain form to rounding.
+// Every replacement equals the plain form to rounding.  ac: an across-scan
+// observation; eta_obs then holds the observed zeta, cal is zero and R is
+// zeta_obs - zeta, with zeta = atan(z / rho) (the same odd series for
+// |z / rho| < 1e-2, atan2 otherwise).
 __device__ __forceinline__ void observe(const DevConsts& k, double t, double eta_obs, double cal,
                                             const double r[3], const double mu[3], double plx,
                                             const double* __restrict__ a4, const double* __restrict__ kn,
-                                            const KnotTab& kt, ObsEval& o) {
+                                            const KnotTab& kt, ObsEval& o, bool ac = false) {
     double v[3];
     {
         const double d = k.eph_Lrate * (t - kt.tau);
@@ -234,6 +239,14 @@ __device__ __forceinline__ void observe(const DevConsts& k, double t, double eta
     const double rho2 = o.Su[0] * o.Su[0] + o.Su[1] * o.Su[1];
     o.inv_rho = rsqrt_nr(rho2);
     o.rho = rho2 * o.inv_rho;
+    if (ac) {
+        const double z = o.Su[2] * o.inv_rho, z2 = z * z;
+        const double zeta = fabs(z) < 1e-2
+                                ? z * (1.0 + z2 * (-1.0 / 3.0 + z2 * (1.0 / 5.0 + z2 * (-1.0 / 7.0 + z2 * (1.0 / 9.0)))))
+                                : atan2(o.Su[2], o.rho);
+        o.R = eta_obs - zeta;
+        return;
+    }
     // eta = phi - f Gamma_c / 2 with f = sign(phi): rotate (x, y) by -f Gamma_c/2
     const double f = o.Su[1] >= 0.0 ? 1.0 : -1.0;
     const double xr = o.Su[0] * k.cos_half_gamma + f * o.Su[1] * k.sin_half_gamma;
@@ -253,22 +266,32 @@ __device__ __forceinline__ void observe(const DevConsts& k, double t, double eta
 
 // Design row -dR/ds for (alpha*, delta, parallax, mu_a*, mu_d):
 // eq:ubardiff, eq:duds, eq:srspropdiff with eq:srsprop1diffsol; the AL unit
-// vector m of eq:srspqr is taken back to celestial coordinates once.
+// vector m of eq:srspqr is taken back to celestial coordinates once (across
+// scan the AC unit vector n, and no factor sec(zeta)).
 __device__ __forceinline__ void source_partials(const ObsEval& o, const double p[3], const double q[3],
-                                                const double r[3], double Ad[5]) {
+                                                const double r[3], double Ad[5], bool ac = false) {
     const double inv_rho = o.inv_rho;
-    const double ms0 = -o.Su[1] * inv_rho, ms1 = o.Su[0] * inv_rho;   // (-sin phi, cos phi, 0)
     double m[3];
-    m[0] = o.A[0] * ms0 + o.A[3] * ms1;
-    m[1] = o.A[1] * ms0 + o.A[4] * ms1;
-    m[2] = o.A[2] * ms0 + o.A[5] * ms1;
+    double secz = inv_rho;
+    if (ac) {
+        // n = (-sin zeta cos phi, -sin zeta sin phi, cos zeta)
+        const double ns0 = -o.Su[2] * o.Su[0] * inv_rho, ns1 = -o.Su[2] * o.Su[1] * inv_rho, ns2 = o.rho;
+        m[0] = o.A[0] * ns0 + o.A[3] * ns1 + o.A[6] * ns2;
+        m[1] = o.A[1] * ns0 + o.A[4] * ns1 + o.A[7] * ns2;
+        m[2] = o.A[2] * ns0 + o.A[5] * ns1 + o.A[8] * ns2;
+        secz = 1.0;
+    } else {
+        const double ms0 = -o.Su[1] * inv_rho, ms1 = o.Su[0] * inv_rho;   // (-sin phi, cos phi, 0)
+        m[0] = o.A[0] * ms0 + o.A[3] * ms1;
+        m[1] = o.A[1] * ms0 + o.A[4] * ms1;
+        m[2] = o.A[2] * ms0 + o.A[5] * ms1;
+    }
     const double f = 1.0 - dot3(o.ubar, o.vc);
     const double mu_ = dot3(m, o.ubar);
     const double rb = dot3(r, o.b);
     double dpl[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) dpl[c] = -(o.b[c] - r[c] * rb);
-    const double secz = inv_rho;
     const double a0 = (f * dot3(m, p) - mu_ * dot3(o.vc, p)) * secz;
     const double a1 = (f * dot3(m, q) - mu_ * dot3(o.vc, q)) * secz;
     Ad[0] = a0;
@@ -278,9 +301,19 @@ __device__ __forceinline__ void source_partials(const ObsEval& o, const double p
     Ad[4] = a1 * o.tau;
 }
 
-// dR/dq = 2 sec(zeta) q {S'n, 0} (eq:dfadq), n of eq:srspqr.
-__device__ __forceinline__ void attitude_partial(const ObsEval& o, double g[4]) {
+// dR/dq = 2 sec(zeta) q {S'n, 0} (eq:dfadq), n of eq:srspqr; across scan
+// dR/dq = -2 q {S'm, 0}.
+__device__ __forceinline__ void attitude_partial(const ObsEval& o, double g[4], bool ac = false) {
     const double inv_rho = o.inv_rho;
+    if (ac) {
+        const double m0 = -o.Su[1] * inv_rho, m1 = o.Su[0] * inv_rho;
+        const double* q = o.q;
+        g[0] = -2.0 * (q[3] * m0 - q[2] * m1);
+        g[1] = -2.0 * (q[3] * m1 + q[2] * m0);
+        g[2] = -2.0 * (q[0] * m1 - q[1] * m0);
+        g[3] = -2.0 * (-(q[0] * m0 + q[1] * m1));
+        return;
+    }
     const double sz = o.Su[2];
     const double n0 = -sz * o.Su[0] * inv_rho, n1 = -sz * o.Su[1] * inv_rho, n2 = o.rho;
     const double* q = o.q;

@@ -35,7 +35,8 @@ enum : int {
     BAD_FOV = 4,
     BAD_T = 8,
     BAD_SIGMA = 16,
-    BAD_ETA = 32
+    BAD_ETA = 32,
+    HAS_AC = 128        // not an error: some observation is across scan (cell -1)
 };
 
 __global__ void k_validate(int64_t n, const double* __restrict__ t, const double* __restrict__ eta,
@@ -45,7 +46,8 @@ __global__ void k_validate(int64_t n, const double* __restrict__ t, const double
     int bad = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         if (src[i] < 0 || src[i] >= n_src) bad |= BAD_SRC;
-        if (cell[i] < 0 || cell[i] >= n_cells) bad |= BAD_CELL;
+        if (cell[i] == -1) bad |= HAS_AC;
+        else if (cell[i] < 0 || cell[i] >= n_cells) bad |= BAD_CELL;
         if (fov[i] != 1 && fov[i] != -1) bad |= BAD_FOV;
         const double ti = t[i];
         if (!(ti >= t_lo && ti <= t_hi)) bad |= BAD_T;
@@ -62,10 +64,12 @@ __global__ void k_iota(int64_t n, int32_t* __restrict__ v) {
         v[i] = (int32_t)i;
 }
 
-// Gather the input columns into time order.
+// Gather the input columns into time order.  An across-scan observation
+// (cell -1) takes the pseudo-cell n_cells, whose calibration entry stays
+// zero, so that every pass may read c[cellfov >> 1].
 __global__ void k_gather_time(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ eta,
                               const float* __restrict__ sig, const int32_t* __restrict__ src,
-                              const int8_t* __restrict__ fov, const int32_t* __restrict__ cell,
+                              const int8_t* __restrict__ fov, const int32_t* __restrict__ cell, int32_t n_cells,
                               double* __restrict__ o_eta, float* __restrict__ o_sig, int32_t* __restrict__ o_src,
                               int32_t* __restrict__ o_cellfov) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -73,7 +77,7 @@ __global__ void k_gather_time(int64_t n, const int32_t* __restrict__ perm, const
         o_eta[i] = eta[j];
         o_sig[i] = sig[j];
         o_src[i] = src[j];
-        o_cellfov[i] = cell[j] * 2 + (fov[j] < 0 ? 1 : 0);
+        o_cellfov[i] = (cell[j] < 0 ? n_cells : cell[j]) * 2 + (fov[j] < 0 ? 1 : 0);
     }
 }
 
@@ -146,16 +150,18 @@ __global__ void k_offsets_time(int64_t n, const double* __restrict__ t, const do
     }
 }
 
-// Calibration cell of each field of view within each knot interval; flags
-// intervals whose observations of one field of view span several cells.
+// Calibration cell of each field of view within each knot interval (across-
+// scan observations, pseudo-cell n_cells, have none); flags intervals whose
+// observations of one field of view span several cells.
 __global__ void k_interval_cells(int64_t K, const int64_t* __restrict__ off, const int32_t* __restrict__ cellfov,
-                                 int32_t* __restrict__ iv_cell, int* __restrict__ flags) {
+                                 int32_t n_cells, int32_t* __restrict__ iv_cell, int* __restrict__ flags) {
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < K; j += (int64_t)gridDim.x * blockDim.x) {
         int32_t cp = -1, cf = -1;
         int bad = 0;
         for (int64_t l = off[j]; l < off[j + 1]; ++l) {
             const int32_t cv = cellfov[l];
             const int32_t cell = cv >> 1;
+            if (cell >= n_cells) continue;
             if (cv & 1) {
                 if (cf < 0) cf = cell;
                 else if (cf != cell) bad = 1;
@@ -245,10 +251,17 @@ int build_store(agis_ctx* ctx, const agis_obs_soa_t* obs, int where) {
     int hflags = 0;
     HIPCHK(hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    ctx->has_ac = (hflags & HAS_AC) != 0;
+    hflags &= ~HAS_AC;
+    if (ctx->has_ac && ctx->cfg.robust) {
+        // the excess attitude noise would need its across-scan components
+        return set_error(ctx, AGIS_E_INVALID_ARG,
+                         "robust weighting with across-scan observations (cell -1) is not supported");
+    }
     if (hflags) {
         std::string m = "invalid observations:";
         if (hflags & BAD_SRC) m += " src outside [0, n_src);";
-        if (hflags & BAD_CELL) m += " cell outside [0, n_cells);";
+        if (hflags & BAD_CELL) m += " cell outside [0, n_cells) and not -1;";
         if (hflags & BAD_FOV) m += " fov not +1/-1;";
         if (hflags & BAD_T) m += " t outside [tau_3, tau_N];";
         if (hflags & BAD_SIGMA) m += " sigma not positive and finite;";
@@ -282,7 +295,8 @@ int build_store(agis_ctx* ctx, const agis_obs_soa_t* obs, int where) {
     ALLOC(ctx->t_sig, n, "t_sig");
     ALLOC(ctx->t_src, n, "t_src");
     ALLOC(ctx->t_cellfov, n, "t_cellfov");
-    k_gather_time<<<blocks, 256, 0, st>>>(n, perm_t, eta_in, sig_in, src_in, fov_in, cell_in, ctx->t_eta,
+    k_gather_time<<<blocks, 256, 0, st>>>(n, perm_t, eta_in, sig_in, src_in, fov_in, cell_in, (int32_t)ctx->n_cells,
+                                          ctx->t_eta,
                                           ctx->t_sig, ctx->t_src, ctx->t_cellfov);
     HIPCHK(hipGetLastError());
 
@@ -316,7 +330,8 @@ int build_store(agis_ctx* ctx, const agis_obs_soa_t* obs, int where) {
     HIPCHK(hipGetLastError());
     ALLOC(ctx->iv_cell, 2 * ctx->K, "iv_cell");
     HIPCHK(hipMemsetAsync(flags, 0, sizeof(int), st));
-    k_interval_cells<<<b2, 256, 0, st>>>(ctx->K, ctx->iv_off, ctx->t_cellfov, ctx->iv_cell, flags);
+    k_interval_cells<<<b2, 256, 0, st>>>(ctx->K, ctx->iv_off, ctx->t_cellfov, (int32_t)ctx->n_cells, ctx->iv_cell,
+                                         flags);
     HIPCHK(hipGetLastError());
     std::vector<int32_t> h_ivc(2 * ctx->K);
     HIPCHK(hipMemcpyAsync(h_ivc.data(), ctx->iv_cell, 2 * ctx->K * sizeof(int32_t), hipMemcpyDeviceToHost, st));

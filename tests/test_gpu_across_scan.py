@@ -1,0 +1,188 @@
+"""Across-scan (AC) observations on the GPU (eq:synth, eq:resAC) against the
+oracle: residuals, the S, A and C blocks, simple iterations with the frame
+rotator, the mixed-precision S block and conjugate gradients, on worlds
+with one AC observation per transit (marked by cell = -1) beside the AL
+ones, with the FP64-floor criterion of the other parity tests.  A robust
+context refuses AC observations (the excess attitude noise has no AC
+components here)."""
+import numpy as np
+import pytest
+
+import synth
+import synth.configs as C
+from test_gpu_parity import DIFFS, TOL_UAS, Pair, check_floor, fp64_floor, src_diff_uas, agis_mod  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+UAS = synth.UAS
+
+
+@pytest.fixture(scope="module")
+def small_ac(oracle_lib):
+    w = C.make("small", ac_obs=True)
+    return w, oracle_lib.observed_field_angles(w)
+
+
+@pytest.fixture(scope="module")
+def small9_ac(oracle_lib):
+    # 9 AL observations and one AC observation per transit; primary sources
+    # only (at least six transits), as in the 1-year workloads: without the
+    # selection a half-year world keeps sources seen on two or three
+    # occasions, whose nearly singular 5x5 systems turn the summation order
+    # into errors of up to 1e9 uas in both implementations
+    w = C.make("small9", ac_obs=True, min_transits=6)
+    return w, oracle_lib.observed_field_angles(w)
+
+
+@pytest.fixture(scope="module")
+def tiny_ac(oracle_lib):
+    w = C.make("tiny", ac_obs=True)
+    return w, oracle_lib.observed_field_angles(w)
+
+
+@pytest.mark.parametrize("world", ["small_ac", "small9_ac"])
+def test_ac_residuals_match(agis_mod, oracle_lib, world, request):
+    w, eta = request.getfixturevalue(world)
+    ac = w.cell < 0
+    assert 0 < ac.sum() < w.n_obs
+    p = Pair(agis_mod, oracle_lib, w, eta)
+    Rg = agis_mod.agis_residuals(p.ctx)
+    Ro = p.pr.observe()["R"]
+    d = Rg - Ro
+    print(f"residuals [{world}]: AL max |diff| {np.abs(d[~ac]).max():.2e}, AC max |diff| {np.abs(d[ac]).max():.2e} "
+          f"rad, rms {np.sqrt(np.mean(d * d)):.2e} rad; AC share {ac.mean():.3f}")
+    assert np.abs(d).max() / UAS < TOL_UAS
+    assert np.sqrt(np.mean(d[ac] ** 2)) < 1.5e-16 and np.sqrt(np.mean(d[~ac] ** 2)) < 1.5e-16
+    p.close()
+
+
+@pytest.mark.parametrize("world", ["small_ac", "small9_ac"])
+def test_ac_source_update_parity(agis_mod, oracle_lib, world, request):
+    w, eta = request.getfixturevalue(world)
+
+    def run(pr):
+        _, _, de = pr.source_update()
+        run.defect = de
+        return pr.s.copy(), pr.a.copy(), pr.c.copy()
+
+    X, O, tol = fp64_floor(oracle_lib, w, eta, run)
+    run(oracle_lib.problem_from_world(w, eta, state="start"))
+    good = run.defect == 0
+    p = Pair(agis_mod, oracle_lib, w, eta)
+    agis_mod.agis_source_update(p.ctx)
+    G = p.gpu_state()
+    assert good.mean() > 0.95
+    dg = check_floor(f"S update with AC [{world}]", X[0], O[0], G[0], tol[0], 0, mask=good)
+    assert np.mean(np.abs(dg) <= TOL_UAS) > 0.95
+    p.close()
+
+
+@pytest.mark.parametrize("world", ["tiny_ac"])
+def test_ac_attitude_calibration_update_parity(agis_mod, oracle_lib, world, request):
+    """One S[AC] iteration without the frame rotator: the AC rows enter the
+    attitude normal equations, not the calibration sums.  (The 3,000-source
+    worlds leave knot intervals with a handful of observations, where the
+    attitude is undetermined in both implementations: coefficients off by
+    1e11 uas.)"""
+    w, eta = request.getfixturevalue(world)
+
+    def run(pr):
+        pr.iterate_sac()
+        return pr.s.copy(), pr.a.copy(), pr.c.copy()
+
+    X, O, tol = fp64_floor(oracle_lib, w, eta, run)
+    p = Pair(agis_mod, oracle_lib, w, eta)
+    agis_mod.agis_source_update(p.ctx)
+    agis_mod.agis_attitude_calibration_update(p.ctx)
+    G = p.gpu_state()
+    check_floor(f"A update with AC [{world}]", X[1], O[1], G[1], tol[1], 1)
+    check_floor(f"C update with AC [{world}]", X[2], O[2], G[2], tol[2], 2)
+    assert np.all(np.abs(G[2][0::2] + G[2][1::2]) < 1e-18)
+    p.close()
+
+
+def test_ac_iterations_with_frame_rotator_parity(agis_mod, oracle_lib, tiny_ac):
+    w, eta = tiny_ac
+    n_it = 3
+
+    def run(pr):
+        for _ in range(n_it):
+            pr.iterate(s_ref=w.src_true)
+        return pr.s.copy(), pr.a.copy(), pr.c.copy()
+
+    X, O, tol = fp64_floor(oracle_lib, w, eta, run)
+    p = Pair(agis_mod, oracle_lib, w, eta)
+    agis_mod.agis_set_frame_reference(p.ctx, w.src_true)
+    agis_mod.agis_iterate(p.ctx, n_it, stats=False)
+    G = p.gpu_state()
+    check_floor("3 iterations with AC: sources", X[0], O[0], G[0], tol[0], 0)
+    check_floor("3 iterations with AC: attitude", X[1], O[1], G[1], tol[1], 1)
+    check_floor("3 iterations with AC: calibration", X[2], O[2], G[2], tol[2], 2)
+    p.close()
+
+
+def test_ac_mixed_source_update(agis_mod, oracle_lib, tiny_ac):
+    """Mixed precision with AC rows: as for AL data, the FP32 normal matrix
+    leaves an error that is a small fraction of the update."""
+    w, eta = tiny_ac
+    pr = oracle_lib.problem_from_world(w, eta, state="start")
+    d_o, _, de = pr.source_update()
+    ctx = agis_mod.agis_create(w.consts, w.knots, precision=1)          # mixed
+    agis_mod.agis_load_observations(ctx, w.t, eta, w.sigma, w.src, w.fov, w.cell, w.src_true.shape[0], w.n_cells)
+    agis_mod.agis_set_sources(ctx, w.src_start)
+    agis_mod.agis_set_attitude(ctx, w.att_start)
+    agis_mod.agis_set_calibration(ctx, w.cal_start)
+    agis_mod.agis_source_update(ctx)
+    s_g = agis_mod.agis_get_sources(ctx, w.src_true.shape[0])
+    agis_mod.agis_destroy(ctx)
+    good = de == 0
+    ds = src_diff_uas(pr.s, s_g)[good]
+    upd = np.abs(d_o[good]).max(axis=1) / UAS
+    rel = np.abs(ds).max(axis=1) / upd
+    print(f"mixed S update with AC: error / update median {np.median(rel):.2e}, 99% {np.percentile(rel, 99):.2e}")
+    assert np.median(rel) < 1e-6 and np.percentile(rel, 99) < 1e-3
+
+
+def test_ac_cg_parity(agis_mod, oracle_lib, tiny_ac):
+    """Conjugate gradients (a cycle start and three iterations) with AC
+    rows in r, z and p'N p; the criterion of the AL CG parity test."""
+    from oracle import cg as ocg
+    w, eta = tiny_ac
+    n_eval, restart = 4, 4
+
+    def run(pr):
+        ocg.CG(pr, restart=restart, s_ref=w.src_true).run(n_eval)
+        return pr.s.copy(), pr.a.copy(), pr.c.copy()
+
+    X, O, tol = fp64_floor(oracle_lib, w, eta, run)
+    p = Pair(agis_mod, oracle_lib, w, eta)
+    agis_mod.agis_set_frame_reference(p.ctx, w.src_true)
+    st = agis_mod.agis_cg_iterate(p.ctx, n_eval, restart)
+    assert not any(x["breakdown"] for x in st)
+    G = p.gpu_state()
+    well = np.bincount(w.src, minlength=w.src_true.shape[0]) >= 10
+    check_floor("CG with AC: sources", X[0], O[0], G[0], tol[0], 0, mask=well)
+    check_floor("CG with AC: attitude", X[1], O[1], G[1], tol[1], 1)
+    check_floor("CG with AC: calibration", X[2], O[2], G[2], tol[2], 2)
+    few, few_o = src_diff_uas(X[0], G[0])[~well], src_diff_uas(X[0], O[0])[~well]
+    if few.size:
+        assert np.abs(few).max() <= 2.0 * np.abs(few_o).max() + 1e-6
+    p.close()
+
+
+def test_ac_refused_in_robust_mode(agis_mod, oracle_lib, small_ac):
+    w, eta = small_ac
+    consts = dict(w.consts)
+    consts["robust"] = 1
+    ctx = agis_mod.agis_create(consts, w.knots)
+    with pytest.raises(agis_mod.AgisError) as e:
+        agis_mod.agis_load_observations(ctx, w.t, eta, w.sigma, w.src, w.fov, w.cell, w.src_true.shape[0],
+                                        w.n_cells)
+    assert "across-scan" in str(e.value)
+    bad = w.cell.copy()
+    bad[0] = -2
+    consts["robust"] = 0
+    ctx2 = agis_mod.agis_create(consts, w.knots)
+    with pytest.raises(agis_mod.AgisError):
+        agis_mod.agis_load_observations(ctx2, w.t, eta, w.sigma, w.src, w.fov, bad, w.src_true.shape[0], w.n_cells)
+    agis_mod.agis_destroy(ctx)
+    agis_mod.agis_destroy(ctx2)
