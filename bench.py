@@ -90,6 +90,8 @@ def workload_description(name, w):
             "attitude_coefficients": int(w.n_att), "cells": int(w.n_cells), "segment_intervals": sp.seg_len,
             "overlap_L": sp.seg_overlap, "lambda": sp.lambda_reg, "sigma_uas": 100.0,
             "outlier_frac": sp.outlier_frac, "robust": bool(sp.robust),
+            **({"ac_obs_per_transit": 1, "ac_observations": int((w.cell < 0).sum()),
+                "sigma_ac_uas": round(float(w.sigma[w.cell < 0][0]) / 4.8481368e-12, 1)} if sp.ac_obs else {}),
             "law": "Gaia-like: spin 60 arcsec/s, precession 63 d, aspect 45 deg, basic angle 106.5 deg"}
 
 
@@ -138,6 +140,8 @@ def main():
     ap.add_argument("--scheme", choices=("si", "cg"), default="si",
                     help="si: one simple S[AC] iteration per step; cg: one conjugate-gradient step per step "
                          "(cycles of 40 iterations; an iteration is one pass of the blocks plus p'N p)")
+    ap.add_argument("--ac", action="store_true",
+                    help="add one across-scan observation per transit (cell -1) to the workload")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the timed steps, run one plain device copy of this many MiB (the reference "
                          "kernel for scaling HBM counters) and exit")
@@ -157,6 +161,9 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     over = {} if args.seg_len is None else {"seg_len": args.seg_len}
+    if args.ac:
+        over["ac_obs"] = True
+    wname = args.workload + ("+ac" if args.ac else "")
     t0 = time.time()
     w = C.make(args.workload, progress=log, **over)
     log(f"workload {args.workload}: {w.src_true.shape[0]} sources, {w.n_obs} obs, {w.n_att} coefficients "
@@ -235,7 +242,7 @@ def main():
         alg_bytes = S_BYTES_PER_OBS * w.n_obs + S_BYTES_PER_SOURCE * n_src + 32.0 * w.n_att
     sec = kavg[dom] * 1e-3
     tfs = alg_flops / sec / 1e12
-    traffic = measured_traffic(dom, args.workload, args.precision)
+    traffic = measured_traffic(dom, wname, args.precision)
     roofline = {"kernel": dom, "bound": "alu", "achieved": round(tfs, 2), "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(tfs / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
                 "alg_flops_per_launch": alg_flops, "alg_bytes_per_launch": alg_bytes,
@@ -251,7 +258,7 @@ def main():
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None,
            "dtype": "f64" if args.precision == "fp64" else "f64 model, f32 partials and sums", "data": "synthetic",
-           "config": {**workload_description(args.workload, w), "lanes_per_source": s_group,
+           "config": {**workload_description(wname, w), "lanes_per_source": s_group,
                       **({"scheme": "conjugate gradients"} if args.scheme == "cg" else {})},
            "kernel_ms": kavg, "roofline": roofline,
            "cpu_baseline": cpu}
