@@ -118,3 +118,14 @@ def test_ac_attitude_error_ratio(oracle_lib):
     assert abs(ratio - printed) < 0.1
     assert np.all(rms[True][:2] < rms[False][:2] / 4)
     assert abs(rms[True][2] / rms[False][2] - 1) < 0.1
+
+
+def test_robust_weighting_refuses_ac(oracle_lib, ac_world):
+    """The excess attitude noise is estimated for the AL component only, so a
+    robust problem with AC records is refused rather than mis-weighted."""
+    w, eta = ac_world
+    consts = dict(w.consts)
+    consts["robust"] = 1
+    with pytest.raises(ValueError, match="across-scan"):
+        oracle_lib.Problem(consts, w.knots, w.t, eta, w.sigma, w.src, w.fov, w.cell, w.src_start, w.att_start,
+                           w.cal_start)
