@@ -186,3 +186,33 @@ def test_ac_refused_in_robust_mode(agis_mod, oracle_lib, small_ac):
         agis_mod.agis_load_observations(ctx2, w.t, eta, w.sigma, w.src, w.fov, bad, w.src_true.shape[0], w.n_cells)
     agis_mod.agis_destroy(ctx)
     agis_mod.agis_destroy(ctx2)
+
+
+def test_ac_chi2_matches_oracle(agis_mod, oracle_lib, small9_ac):
+    """The chi-square pass of the learned scheme (sum R^2 / sigma^2) counts
+    the AC records with their own residual and uncertainty."""
+    w, eta = small9_ac
+    p = Pair(agis_mod, oracle_lib, w, eta)
+    q_g = agis_mod.agis_chi2(p.ctx)
+    R = np.asarray(p.pr.observe()["R"], np.float64)
+    sg = w.sigma.astype(np.float64)
+    q_o = float(np.sum((R / sg) ** 2))
+    ac = w.cell < 0
+    print(f"chi2 with AC: GPU {q_g:.15g}, oracle {q_o:.15g} (AC part {np.sum((R[ac] / sg[ac]) ** 2):.6g})")
+    assert abs(q_g - q_o) <= 1e-11 * q_o
+    p.close()
+
+
+def test_ac_graph_replay_is_the_eager_iteration(agis_mod, oracle_lib, small_ac):
+    """The HIP graph of one iteration, captured with the AC instances of the
+    passes, replays bitwise the eager iterates."""
+    w, eta = small_ac
+    a, b = Pair(agis_mod, oracle_lib, w, eta), Pair(agis_mod, oracle_lib, w, eta)
+    for p in (a, b):
+        agis_mod.agis_set_frame_reference(p.ctx, w.src_true)
+    agis_mod.agis_iterate(a.ctx, 3, stats=False)
+    agis_mod.agis_iterate_graph(b.ctx, 3)
+    for x, y in zip(a.gpu_state(), b.gpu_state()):
+        assert np.array_equal(x, y)
+    a.close()
+    b.close()
