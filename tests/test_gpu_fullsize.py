@@ -11,7 +11,9 @@ Sect. 5.2.2); the C update of sampled days (both cells, all observations of
 the day, Sect. 5.3).  The criterion is the one of the small-world parity
 tests: within max(1e-3 uas, the FP64 rounding floor) of the
 extended-precision oracle, and per component no less accurate than the FP64
-oracle.  The observed field angles come from the oracle's model.
+oracle.  The observed field angles come from the oracle's model.  Every
+test runs on gaia1 and on gaia1 with one across-scan record per transit
+(17.9M more records, cell -1).
 """
 import types
 
@@ -36,11 +38,11 @@ def subworld(w, idx):
     return sub
 
 
-@pytest.fixture(scope="module")
-def full(oracle_lib, agis_mod):
-    w = C.make("gaia1")
+@pytest.fixture(scope="module", params=["gaia1", "gaia1+ac"])
+def full(oracle_lib, agis_mod, request):
+    w = C.make("gaia1", ac_obs=request.param.endswith("+ac"))
     eta = oracle_lib.observed_field_angles(w)
-    print(f"gaia1: {w.n_obs} observations, {w.src_true.shape[0]} sources, {w.n_att} coefficients", flush=True)
+    print(f"{request.param}: {w.n_obs} observations, {w.src_true.shape[0]} sources, {w.n_att} coefficients", flush=True)
     ctx = agis_mod.agis_create(w.consts, w.knots)
     agis_mod.agis_load_observations(ctx, w.t, eta, w.sigma, w.src, w.fov, w.cell, w.src_true.shape[0], w.n_cells)
     yield w, eta, ctx
