@@ -90,7 +90,8 @@ def test_fullsize_source_update(agis_mod, oracle_lib, full):
     mask[pick] = True
     mask &= run.defect == 0
     assert mask.sum() > 1900
-    dg = check_floor(f"S update, {pick.size} sampled sources of gaia1 ({idx.size} observations)", X[0], O[0], G,
+    name = "gaia1+ac" if (w.cell < 0).any() else "gaia1"
+    dg = check_floor(f"S update, {pick.size} sampled sources of {name} ({idx.size} observations)", X[0], O[0], G,
                      tol[0], 0, mask=mask)
     assert np.mean(np.abs(dg) <= TOL_UAS) > 0.95
 
