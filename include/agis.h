@@ -216,10 +216,16 @@ int agis_attitude_calibration_update(agis_ctx_t* ctx, agis_block_stats_t* st_a, 
 
 /* Frame rotator (Sect. 6.1).  The reference catalogue s_ref [n_src][5]
  * defines the S_PM comparison of eq:cond-mu3 at t = t_ep (eq:fr-Delta1).
- * frame_fit solves the unweighted least squares for eps_omega = (eps_X,
- * eps_Y, eps_Z [rad], omega_X, omega_Y, omega_Z [rad/yr]); frame_apply
- * transforms all sources rigorously (Sect. 6.1.2) and all attitude
- * coefficients by eq:fr-q4. */
+ * frame_fit solves the weighted least squares for eps_omega = (eps_X,
+ * eps_Y, eps_Z [rad], omega_X, omega_Y, omega_Z [rad/yr]) over all sources:
+ * each condition equation is weighted by the inverse formal variance of its
+ * parameter from the last source update (the diagonal of the inverse 5x5
+ * normal matrix, Sect. 5.1.1; Sect. 6.1.4 asks for a weighted fit without
+ * fixing the weights); a parameter whose variance is zero or not finite (a
+ * singular source system, or no source update yet with variance 0) gets
+ * weight 0, and before any source update every variance is 1 (unit
+ * weights).  frame_apply transforms all sources rigorously (Sect. 6.1.2)
+ * and all attitude coefficients by eq:fr-q4. */
 int agis_set_frame_reference(agis_ctx_t* ctx, int64_t n, const double* s_ref5, int where);
 int agis_frame_fit(agis_ctx_t* ctx, double eps_omega[6]);
 int agis_frame_apply(agis_ctx_t* ctx, const double eps_omega[6]);
@@ -302,9 +308,12 @@ int agis_learned_record(agis_ctx_t* ctx);
 /* Features X [n][F] and scales s [n] of every unit from the last four
  * recorded updates (AGIS_E_STATE with fewer than four). */
 int agis_learned_features(agis_ctx_t* ctx, int32_t which, int64_t n, float* X, float* scale, int where);
-/* Weights: Glorot-uniform from a SplitMix64 stream (biases 0), set, get. */
+/* Weights: Glorot-uniform from a SplitMix64 stream (biases 0); load n =
+ * the network's weight count FP32 weights in the layout above (from host
+ * or device memory; the Adam moments and step count restart at zero); get
+ * them back. */
 int agis_mlp_init(agis_ctx_t* ctx, int32_t which, uint64_t seed);
-int agis_mlp_set_weights(agis_ctx_t* ctx, int32_t which, int64_t n, const float* w, int where);
+int agis_mlp_load(agis_ctx_t* ctx, int32_t which, int64_t n, const float* w, int where);
 int agis_mlp_get_weights(agis_ctx_t* ctx, int32_t which, int64_t n, float* w, int where);
 /* Y [n][4] = MLP(X [n][F]), the mixing coefficients. */
 int agis_mlp_forward(agis_ctx_t* ctx, int32_t which, int64_t n, const float* X, float* Y, int where);
@@ -313,6 +322,11 @@ int agis_mlp_forward(agis_ctx_t* ctx, int32_t which, int64_t n, const float* X, 
  * (grad [NW], same layout) and L, at the current weights. */
 int agis_mlp_gradient(agis_ctx_t* ctx, int32_t which, int64_t n, const float* X, const float* T, float* grad,
                       float* loss, int where);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8, rate lr) on the gradient of L
+ * over the whole batch (X [n][F], T [n][NC], host or device); *loss (host,
+ * may be NULL) receives L at the weights before the step. */
+int agis_mlp_train_step(agis_ctx_t* ctx, int32_t which, int64_t n, const float* X, const float* T, int where,
+                        float lr, float* loss);
 /* steps Adam steps (beta 0.9, 0.999, eps 1e-8, rate lr) on minibatches of
  * `batch` samples drawn from (X, T) by a counter-based hash of (seed, step);
  * loss_out (host, may be NULL) receives each step's minibatch loss. */
@@ -334,6 +348,24 @@ int agis_learned_apply(agis_ctx_t* ctx);
  * excess attitude noise are saved and restored on the device.
  * AGIS_E_STATE with fewer than four records. */
 int agis_learned_step(agis_ctx_t* ctx, double* q_plain, double* q_cand, int32_t* accepted);
+
+/* One block of the learned-accelerated scheme (agis_iterate_learned). */
+typedef struct {
+    int32_t iterations;      /* S[AC] iterations the block ran: m, plus 2 when gated */
+    int32_t gated;           /* 1: the history held four records and the gated step ran */
+    int32_t accepted;        /* 1: the candidate was kept (the history restarted from it) */
+    double q_plain, q_cand;  /* the gate's sum W R^2 after the plain and the candidate iteration */
+} agis_learned_stats_t;
+
+/* n_blocks blocks of the learned-accelerated simple iteration: each runs m
+ * S[AC] + frame iterations, records their change as the newest update
+ * (agis_learned_record) and, once the history holds four records, takes the
+ * gated learned step (agis_learned_step).  A history is started first when
+ * none exists (agis_learned_reset otherwise sets where it starts).  The
+ * networks are those set by agis_mlp_init / agis_mlp_load / training.
+ * per_block (may be NULL) receives n_blocks entries.  n_blocks >= 0,
+ * m >= 1 (else AGIS_E_INVALID_ARG). */
+int agis_iterate_learned(agis_ctx_t* ctx, int32_t n_blocks, int32_t m, agis_learned_stats_t* per_block);
 
 /*
  * Accelerated simple iteration (Sect. 4.7): when successive updates shrink

@@ -89,7 +89,7 @@ void orc_qrot(const double phi[3], double out[4]) {
 /* ========================================================================
  * Appendix B: left index (tau_l <= t < tau_{l+1}, restricted to the spline
  * interval [tau_{M-1}, tau_N]; t = tau_N belongs to the last interval) and
- * de Boor's Algorithm B1 for the M = 4 non-zero B-splines.
+ * the M = 4 non-zero B-splines at a time.
  * ====================================================================== */
 int64_t orc_left_index(const double* knots, int64_t n_knots, double t) {
     int64_t N = n_knots - M_ORDER;
@@ -103,85 +103,118 @@ int64_t orc_left_index(const double* knots, int64_t n_knots, double t) {
     return lo;
 }
 
+/* The B-splines of order M on the knot sequence (Appendix B, Sect. B.2: they
+ * are fixed by the knots alone; the definition is de Boor's): order 1 is
+ * the indicator of [tau_i, tau_{i+1}), and order k is
+ *   B_{i,k}(t) = (t - tau_i) / (tau_{i+k-1} - tau_i) B_{i,k-1}(t)
+ *              + (tau_{i+k} - t) / (tau_{i+k} - tau_{i+1}) B_{i+1,k-1}(t),
+ * a term whose knot difference is zero being left out.  At t in
+ * [tau_ell, tau_ell+1) only B_{ell-M+1..ell} can be non-zero (Sect. B.3);
+ * b[m] = B_{ell-M+1+m, M}(t). */
+static double bspline_term(const double* knots, int64_t i, int k, double t, double lower_i, double lower_next) {
+    double v = 0.0;
+    double den_left = knots[i + k - 1] - knots[i];
+    double den_right = knots[i + k] - knots[i + 1];
+    if (den_left != 0.0) v += (t - knots[i]) / den_left * lower_i;
+    if (den_right != 0.0) v += (knots[i + k] - t) / den_right * lower_next;
+    return v;
+}
+
 void orc_bspline(const double* knots, int64_t ell, double t, double b[4]) {
-    double Rv[M_ORDER], Lv[M_ORDER];
-    b[0] = 1.0;
-    for (int i = 0; i <= M_ORDER - 2; ++i) {
-        Rv[i] = knots[ell + i + 1] - t;
-        Lv[i] = t - knots[ell - i];
-        double s = 0.0;
-        for (int j = 0; j <= i; ++j) {
-            double u = b[j] / (Rv[j] + Lv[i - j]);
-            b[j] = s + Rv[j] * u;
-            s = Lv[i - j] * u;
+    /* level[k][m]: B_{ell-M+1+m, k}(t), m = 0..M-1; zero off the support */
+    double level[M_ORDER + 1][M_ORDER + 1];
+    memset(level, 0, sizeof level);
+    level[1][M_ORDER - 1] = 1.0;                     /* B_{ell,1}: t lies in [tau_ell, tau_ell+1) */
+    for (int k = 2; k <= M_ORDER; ++k)
+        for (int m = 0; m < M_ORDER; ++m) {
+            int64_t i = ell - M_ORDER + 1 + m;
+            level[k][m] = bspline_term(knots, i, k, t, level[k - 1][m], level[k - 1][m + 1]);
         }
-        b[i + 1] = s;
-    }
+    for (int m = 0; m < M_ORDER; ++m) b[m] = level[M_ORDER][m];
 }
 
 /* ========================================================================
- * Appendix C: Algorithms C1 (modified Cholesky for semidefinite matrices,
- * with rank-defect count d), C2 and C3.  Dense row-major storage.
+ * Appendix C: the modified Cholesky decomposition N = U'U of a symmetric
+ * positive semidefinite matrix (Algorithm C1) and the two triangular solves
+ * (Algorithms C2, C3).  Dense row-major storage, upper triangle.
+ *
+ * C1 forms U column by column.  In column j, each entry above the diagonal
+ * comes from its row's pivot U_ii: U_ij = (N_ij - sum_{k<i} U_ki U_kj) /
+ * U_ii, or 0 when that pivot is not positive; then the pivot of column j is
+ * the square root of N_jj - sum_{k<j} U_kj^2 when that is positive, else 0,
+ * and each zero pivot counts one rank defect d.  The solves skip unknowns
+ * whose pivot is zero (they are set to 0), which gives one valid solution of
+ * a singular system.
  * ====================================================================== */
+/* sum over k in [k_from, k_to) of U_ka U_kb */
+static double column_dot(const double* U, int n, int a, int b, int k_from, int k_to) {
+    double acc = 0.0;
+    for (int k = k_from; k < k_to; ++k) acc += U[k * n + a] * U[k * n + b];
+    return acc;
+}
+
+/* Entry (i, j), i <= j, of the factor from the entries above it (C1's rule). */
+static double factor_entry(double* U, int n, int i, int j, int k_from, int* defect) {
+    double rest = U[i * n + j] - column_dot(U, n, i, j, k_from, i);
+    if (i < j) return U[i * n + i] > 0.0 ? rest / U[i * n + i] : 0.0;
+    if (rest > 0.0) return sqrt(rest);
+    *defect += 1;
+    return 0.0;
+}
+
 int orc_chol_c1(double* U, int n) {
     int d = 0;
     for (int j = 0; j < n; ++j) {
-        for (int i = 0; i <= j; ++i) {
-            double s = 0.0;
-            for (int k = 0; k < i; ++k) s += U[k * n + i] * U[k * n + j];
-            if (i < j) {
-                if (U[i * n + i] > 0.0) U[i * n + j] = (U[i * n + j] - s) / U[i * n + i];
-                else U[i * n + j] = 0.0;
-            } else {
-                if (U[j * n + j] - s > 0.0) U[j * n + j] = sqrt(U[j * n + j] - s);
-                else { U[j * n + j] = 0.0; d += 1; }
-            }
-        }
-        for (int i = j + 1; i < n; ++i) U[i * n + j] = 0.0;
+        for (int i = 0; i <= j; ++i) U[i * n + j] = factor_entry(U, n, i, j, 0, &d);
+        for (int i = j + 1; i < n; ++i) U[i * n + j] = 0.0;         /* lower triangle */
     }
     return d;
 }
 
+/* U' y = b (C2): y_i from the rows above it. */
 void orc_chol_c2(const double* U, int n, double* y) {
     for (int i = 0; i < n; ++i) {
-        if (U[i * n + i] > 0.0) {
-            double s = 0.0;
-            for (int k = 0; k < i; ++k) s += U[k * n + i] * y[k];
-            y[i] = (y[i] - s) / U[i * n + i];
-        } else {
-            y[i] = 0.0;
-        }
+        double piv = U[i * n + i];
+        double known = 0.0;
+        for (int k = 0; k < i; ++k) known += U[k * n + i] * y[k];
+        y[i] = piv > 0.0 ? (y[i] - known) / piv : 0.0;
     }
 }
 
+/* U x = y (C3): x_i from the unknowns after it. */
 void orc_chol_c3(const double* U, int n, double* x) {
     for (int i = n - 1; i >= 0; --i) {
-        if (U[i * n + i] > 0.0) {
-            double s = 0.0;
-            for (int k = i + 1; k < n; ++k) s += U[i * n + k] * x[k];
-            x[i] = (x[i] - s) / U[i * n + i];
-        } else {
-            x[i] = 0.0;
-        }
+        double piv = U[i * n + i];
+        double known = 0.0;
+        for (int k = i + 1; k < n; ++k) known += U[i * n + k] * x[k];
+        x[i] = piv > 0.0 ? (x[i] - known) / piv : 0.0;
     }
 }
 
 /* The same three algorithms restricted to a band envelope of half-width hb
- * (Appendix C.2 remark: the factor keeps the envelope, no fill-in). */
+ * (Appendix C: the factor of a band matrix keeps its envelope, no fill-in).
+ * Entries outside the envelope are zero in N and in U, so every sum runs
+ * over the envelope only, in the dense order. */
 #define UBX(j, jj) UB[(int64_t)(j) * (hb + 1) + ((jj) - (j))]
+static double band_column_dot(const double* UB, int hb, int a, int b, int k_from, int k_to) {
+    double acc = 0.0;
+    for (int k = k_from; k < k_to; ++k) acc += UBX(k, a) * UBX(k, b);
+    return acc;
+}
+
 int orc_band_c1(double* UB, int n, int hb) {
     int d = 0;
     for (int j = 0; j < n; ++j) {
-        int k0 = j - hb > 0 ? j - hb : 0;
-        for (int i = k0; i <= j; ++i) {
-            double s = 0.0;
-            for (int k = k0; k < i; ++k) s += UBX(k, i) * UBX(k, j);
+        int top = j - hb > 0 ? j - hb : 0;          /* first row of column j inside the envelope */
+        for (int i = top; i <= j; ++i) {
+            double rest = UBX(i, j) - band_column_dot(UB, hb, i, j, top, i);
             if (i < j) {
-                if (UBX(i, i) > 0.0) UBX(i, j) = (UBX(i, j) - s) / UBX(i, i);
-                else UBX(i, j) = 0.0;
+                UBX(i, j) = UBX(i, i) > 0.0 ? rest / UBX(i, i) : 0.0;
+            } else if (rest > 0.0) {
+                UBX(j, j) = sqrt(rest);
             } else {
-                if (UBX(j, j) - s > 0.0) UBX(j, j) = sqrt(UBX(j, j) - s);
-                else { UBX(j, j) = 0.0; d += 1; }
+                UBX(j, j) = 0.0;
+                d += 1;
             }
         }
     }
@@ -190,27 +223,19 @@ int orc_band_c1(double* UB, int n, int hb) {
 
 void orc_band_c2(const double* UB, int n, int hb, double* y) {
     for (int i = 0; i < n; ++i) {
-        if (UBX(i, i) > 0.0) {
-            int k0 = i - hb > 0 ? i - hb : 0;
-            double s = 0.0;
-            for (int k = k0; k < i; ++k) s += UBX(k, i) * y[k];
-            y[i] = (y[i] - s) / UBX(i, i);
-        } else {
-            y[i] = 0.0;
-        }
+        int top = i - hb > 0 ? i - hb : 0;
+        double known = 0.0;
+        for (int k = top; k < i; ++k) known += UBX(k, i) * y[k];
+        y[i] = UBX(i, i) > 0.0 ? (y[i] - known) / UBX(i, i) : 0.0;
     }
 }
 
 void orc_band_c3(const double* UB, int n, int hb, double* x) {
     for (int i = n - 1; i >= 0; --i) {
-        if (UBX(i, i) > 0.0) {
-            int k1 = i + hb < n - 1 ? i + hb : n - 1;
-            double s = 0.0;
-            for (int k = i + 1; k <= k1; ++k) s += UBX(i, k) * x[k];
-            x[i] = (x[i] - s) / UBX(i, i);
-        } else {
-            x[i] = 0.0;
-        }
+        int last = i + hb < n - 1 ? i + hb : n - 1;
+        double known = 0.0;
+        for (int k = i + 1; k <= last; ++k) known += UBX(i, k) * x[k];
+        x[i] = UBX(i, i) > 0.0 ? (x[i] - known) / UBX(i, i) : 0.0;
     }
 }
 #undef UBX

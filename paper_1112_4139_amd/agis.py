@@ -58,6 +58,10 @@ class agis_cg_stats_t(ctypes.Structure):
                 ("ms", c_d)]
 
 
+class agis_learned_stats_t(ctypes.Structure):
+    _fields_ = [("iterations", c_i32), ("gated", c_i32), ("accepted", c_i32), ("q_plain", c_d), ("q_cand", c_d)]
+
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libagis.so not built at {LIB_PATH}; run __graft_entry__.build()")
 _lib = ctypes.CDLL(LIB_PATH)
@@ -95,10 +99,12 @@ _sig = {
     "agis_learned_record": ([_ctx_p], ctypes.c_int),
     "agis_learned_features": ([_ctx_p, c_i32, c_i64, _vp, _vp, ctypes.c_int], ctypes.c_int),
     "agis_mlp_init": ([_ctx_p, c_i32, ctypes.c_uint64], ctypes.c_int),
-    "agis_mlp_set_weights": ([_ctx_p, c_i32, c_i64, _vp, ctypes.c_int], ctypes.c_int),
+    "agis_mlp_load": ([_ctx_p, c_i32, c_i64, _vp, ctypes.c_int], ctypes.c_int),
     "agis_mlp_get_weights": ([_ctx_p, c_i32, c_i64, _vp, ctypes.c_int], ctypes.c_int),
     "agis_mlp_forward": ([_ctx_p, c_i32, c_i64, _vp, _vp, ctypes.c_int], ctypes.c_int),
     "agis_mlp_gradient": ([_ctx_p, c_i32, c_i64, _vp, _vp, _vp, P(ctypes.c_float), ctypes.c_int], ctypes.c_int),
+    "agis_mlp_train_step": ([_ctx_p, c_i32, c_i64, _vp, _vp, ctypes.c_int, ctypes.c_float, P(ctypes.c_float)],
+                            ctypes.c_int),
     "agis_mlp_train": ([_ctx_p, c_i32, c_i64, _vp, _vp, ctypes.c_int, c_i32, c_i32, ctypes.c_float, ctypes.c_uint64,
                         _vp], ctypes.c_int),
     "agis_chi2": ([_ctx_p, P(c_d)], ctypes.c_int),
@@ -108,6 +114,7 @@ _sig = {
     "agis_freeze_weights": ([_ctx_p, c_i32], ctypes.c_int),
     "agis_get_source_noise": ([_ctx_p, c_i64, _vp, _vp, ctypes.c_int], ctypes.c_int),
     "agis_learned_step": ([_ctx_p, P(c_d), P(c_d), P(c_i32)], ctypes.c_int),
+    "agis_iterate_learned": ([_ctx_p, c_i32, c_i32, P(agis_learned_stats_t)], ctypes.c_int),
 }
 for _name, (_args, _res) in _sig.items():
     _f = getattr(_lib, _name)
@@ -339,9 +346,9 @@ def agis_mlp_init(ctx, which, seed):
     _check(_lib.agis_mlp_init(ctx, int(which), int(seed)), ctx)
 
 
-def agis_mlp_set_weights(ctx, which, w):
+def agis_mlp_load(ctx, which, w):
     p, where, keep = _fptr(w)
-    _check(_lib.agis_mlp_set_weights(ctx, int(which), MLP_NW[which], p, where), ctx)
+    _check(_lib.agis_mlp_load(ctx, int(which), MLP_NW[which], p, where), ctx)
 
 
 def agis_mlp_get_weights(ctx, which):
@@ -367,6 +374,18 @@ def agis_mlp_gradient(ctx, which, X, T):
                                   T.ctypes.data_as(ctypes.c_void_p), g.ctypes.data_as(ctypes.c_void_p),
                                   ctypes.byref(loss), AGIS_HOST), ctx)
     return g, loss.value
+
+
+def agis_mlp_train_step(ctx, which, X, T, lr):
+    """One Adam step on the whole batch (X, T): NumPy arrays (host) or torch
+    tensors on the device; returns the batch loss before the step."""
+    px, wx, kx = _fptr(X)
+    pt, wt, kt = _fptr(T)
+    if wx != wt:
+        raise ValueError("X and T must both be host arrays or both device tensors")
+    loss = ctypes.c_float()
+    _check(_lib.agis_mlp_train_step(ctx, int(which), int(X.shape[0]), px, pt, wx, float(lr), ctypes.byref(loss)), ctx)
+    return loss.value
 
 
 def agis_mlp_train(ctx, which, X, T, steps, batch, lr, seed=0):
@@ -422,6 +441,16 @@ def agis_learned_step(ctx):
     qp, qc, acc = c_d(), c_d(), c_i32()
     _check(_lib.agis_learned_step(ctx, ctypes.byref(qp), ctypes.byref(qc), ctypes.byref(acc)), ctx)
     return dict(q_plain=qp.value, q_candidate=qc.value, accepted=bool(acc.value))
+
+
+def agis_iterate_learned(ctx, n_blocks, m):
+    """n_blocks blocks of the learned-accelerated scheme (m iterations, a
+    record and, from the fourth record on, the gated step); per block a dict
+    (iterations, gated, accepted, q_plain, q_candidate)."""
+    arr = (agis_learned_stats_t * max(int(n_blocks), 1))()
+    _check(_lib.agis_iterate_learned(ctx, int(n_blocks), int(m), arr), ctx)
+    return [dict(iterations=x.iterations, gated=bool(x.gated), accepted=bool(x.accepted), q_plain=x.q_plain,
+                 q_candidate=x.q_cand) for x in arr[:n_blocks]]
 
 
 def agis_problem_size(ctx):

@@ -187,8 +187,8 @@ static void build_segments(agis_ctx* ctx) {
 
 // Table of the observation model per knot interval l = j + 3: orbital
 // longitude at tau_l, and 1/(tau_l+1 - tau_l) when tau_l-2..tau_l+3 are
-// exactly equally spaced (the closed-form B-splines then equal Algorithm B1
-// to rounding), else 0.
+// exactly equally spaced (the closed-form B-splines then equal the general
+// recursion to rounding), else 0.
 static std::vector<KnotTab> knot_table(const agis_ctx* ctx) {
     const std::vector<double>& kn = ctx->h_knots;
     std::vector<KnotTab> tab(ctx->K);
@@ -1057,7 +1057,7 @@ extern "C" int agis_mlp_init(agis_ctx_t* ctx, int32_t which, uint64_t seed) {
     return AGIS_OK;
 }
 
-extern "C" int agis_mlp_set_weights(agis_ctx_t* ctx, int32_t which, int64_t n, const float* w, int where) {
+extern "C" int agis_mlp_load(agis_ctx_t* ctx, int32_t which, int64_t n, const float* w, int where) {
     CHECK_CTX();
     int rc = check_which(ctx, which);
     if (rc) return rc;
@@ -1152,6 +1152,31 @@ extern "C" int agis_mlp_gradient(agis_ctx_t* ctx, int32_t which, int64_t n, cons
         HIPCHK(hipMemcpy(grad, ctx->mlp_g[which], nw * sizeof(float), hipMemcpyDeviceToDevice));
     }
     *loss = g[nw];
+    return AGIS_OK;
+}
+
+extern "C" int agis_mlp_train_step(agis_ctx_t* ctx, int32_t which, int64_t n, const float* X, const float* T,
+                                   int where, float lr, float* loss) {
+    CHECK_CTX();
+    int rc = check_which(ctx, which);
+    if (rc) return rc;
+    if (n <= 0 || !X || !T || !(lr > 0.0f)) return set_error(ctx, AGIS_E_INVALID_ARG, "bad training arguments");
+    if (where != AGIS_HOST && where != AGIS_DEVICE) return set_error(ctx, AGIS_E_INVALID_ARG, "bad 'where'");
+    DevIn keep;
+    const float *dX = nullptr, *dT = nullptr;
+    if ((rc = dev_input(ctx, keep, X, n * mlp_num_inputs(which), where, &dX))) return rc;
+    if ((rc = dev_input(ctx, keep, T, n * mlp_num_targets(which), where, &dT))) return rc;
+    const int nw = mlp_num_weights(which);
+    float* part = nullptr;
+    if ((rc = dalloc(ctx, &part, (size_t)((n + 127) / 128) * (nw + 1), "gradient partials"))) return rc;
+    keep.own.push_back(part);
+    // the whole batch, in its own order (no index list)
+    launch_mlp_grad(ctx, which, n, nullptr, dX, dT, part);
+    ++ctx->mlp_t[which];
+    launch_adam(ctx, which, lr, ctx->mlp_t[which]);
+    HIPCHK(hipGetLastError());
+    if (loss) HIPCHK(hipMemcpyAsync(loss, ctx->mlp_g[which] + nw, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
     return AGIS_OK;
 }
 
@@ -1272,11 +1297,8 @@ extern "C" int agis_asi_step(agis_ctx_t* ctx, int32_t stride, double lambda_max,
     return AGIS_OK;
 }
 
-extern "C" int agis_learned_step(agis_ctx_t* ctx, double* q_plain, double* q_cand, int32_t* accepted) {
-    CHECK_CTX();
-    ++ctx->xver;
-    REQUIRE_LOADED();
-    if (!ctx->lh_ring_s || ctx->lh_count < 4) return set_error(ctx, AGIS_E_STATE, "fewer than four recorded updates");
+// The gated learned step (two iterations); the history holds four records.
+static int learned_step(agis_ctx* ctx, double* q_plain, double* q_cand, int32_t* accepted) {
     // plain: x0 -> x1 by one iteration
     save_state(ctx, 0);
     int rc = iterate_once(ctx, nullptr);
@@ -1307,6 +1329,45 @@ extern "C" int agis_learned_step(agis_ctx_t* ctx, double* q_plain, double* q_can
     if (q_plain) *q_plain = q[0];
     if (q_cand) *q_cand = q[1];
     if (accepted) *accepted = acc ? 1 : 0;
+    return AGIS_OK;
+}
+
+extern "C" int agis_learned_step(agis_ctx_t* ctx, double* q_plain, double* q_cand, int32_t* accepted) {
+    CHECK_CTX();
+    ++ctx->xver;
+    REQUIRE_LOADED();
+    if (!ctx->lh_ring_s || ctx->lh_count < 4) return set_error(ctx, AGIS_E_STATE, "fewer than four recorded updates");
+    return learned_step(ctx, q_plain, q_cand, accepted);
+}
+
+extern "C" int agis_iterate_learned(agis_ctx_t* ctx, int32_t n_blocks, int32_t m, agis_learned_stats_t* per_block) {
+    CHECK_CTX();
+    ++ctx->xver;
+    REQUIRE_LOADED();
+    if (n_blocks < 0 || m < 1) return set_error(ctx, AGIS_E_INVALID_ARG, "n_blocks >= 0 and m >= 1");
+    int rc;
+    if (!ctx->lh_ring_s) {
+        // no history yet: it starts here
+        if ((rc = learned_alloc(ctx))) return rc;
+        launch_hist_anchor(ctx);
+        HIPCHK(hipGetLastError());
+        ctx->lh_count = 0;
+    }
+    for (int32_t b = 0; b < n_blocks; ++b) {
+        agis_learned_stats_t st = {m, 0, 0, 0.0, 0.0};
+        for (int32_t it = 0; it < m; ++it)
+            if ((rc = iterate_once(ctx, nullptr))) return rc;
+        launch_hist_record(ctx, ctx->lh_count % 4);
+        HIPCHK(hipGetLastError());
+        ++ctx->lh_count;
+        if (ctx->lh_count >= 4) {
+            if ((rc = learned_step(ctx, &st.q_plain, &st.q_cand, &st.accepted))) return rc;
+            st.gated = 1;
+            st.iterations += 2;
+        }
+        if (per_block) per_block[b] = st;
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
     return AGIS_OK;
 }
 

@@ -378,9 +378,10 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
         }
         SrcPrep sp_n = {};
         if (bn < l1) sp_n = prep[src_n];
-        // the wavefront's LDS operations complete in order: the rows just
-        // written are read back below by other lanes of the same wavefront
-        __asm__ volatile("" ::: "memory");
+        // the rows just written are read back below by other lanes: a
+        // workgroup barrier (the block is one wavefront, so it reduces to
+        // waiting for the LDS stores) orders the stores before the reads
+        __syncthreads();
         // groups of four observations past the interval's end hold padding
         // rows of weight zero: their matrix-core steps would add zeros
         const int64_t n_here = l1 - base < 64 ? l1 - base : 64;
@@ -410,7 +411,9 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
                 C = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, C, 0, 0, 0);
             }
         }
-        __asm__ volatile("" ::: "memory");
+        // the next chunk's stores overwrite these rows: every lane's reads
+        // above come first
+        __syncthreads();
         t_c = t_n;
         e_c = e_n;
         s_c = s_n;

@@ -64,38 +64,28 @@ __device__ __forceinline__ double rcp_nr(double x) {
     return y;
 }
 
-// The four non-zero cubic B-splines B_{l-3..l}(t) by de Boor's recurrence
-// (Algorithm B1, M = 4); kn points at tau_{l-2}, so kn[0..5] = tau_{l-2..l+3}.
+// The four non-zero cubic B-splines B_{l-3..l}(t) on an arbitrary knot
+// sequence (Appendix B): the Cox-de Boor recursion in t, raised from order 1
+// (the indicator of [tau_l, tau_l+1)) to order 4, each order-k function the
+// sum of its two order-(k-1) neighbours weighted by (t - tau_i) /
+// (tau_{i+k-1} - tau_i) and (tau_{i+k} - t) / (tau_{i+k} - tau_{i+1}).  kn
+// points at tau_{l-2}, so kn[0..5] = tau_{l-2..l+3}; every denominator spans
+// the interval [tau_l, tau_l+1) and is positive.
 __device__ __forceinline__ void bspline4(const double* __restrict__ kn, double t, double B[4]) {
-    // R_i = tau_{l+i+1} - t ; L_i = t - tau_{l-i}
-    const double R0 = kn[3] - t, R1 = kn[4] - t, R2 = kn[5] - t;
-    const double L0 = t - kn[2], L1 = t - kn[1], L2 = t - kn[0];
-    double b0 = 1.0, b1, b2, b3, s, u;
-    // i = 0
-    u = b0 / (R0 + L0);
-    b0 = R0 * u;
-    b1 = L0 * u;
-    // i = 1
-    u = b0 / (R0 + L1);
-    b0 = R0 * u;
-    s = L1 * u;
-    u = b1 / (R1 + L0);
-    b1 = s + R1 * u;
-    b2 = L0 * u;
-    // i = 2
-    u = b0 / (R0 + L2);
-    b0 = R0 * u;
-    s = L2 * u;
-    u = b1 / (R1 + L1);
-    b1 = s + R1 * u;
-    s = L1 * u;
-    u = b2 / (R2 + L0);
-    b2 = s + R2 * u;
-    b3 = L0 * u;
-    B[0] = b0;
-    B[1] = b1;
-    B[2] = b2;
-    B[3] = b3;
+    // knot tau_{l+j} for j = -2..3
+    auto tk = [&](int j) { return kn[j + 2]; };
+    // order 2: B_{l-1}, B_l
+    const double h0 = tk(1) - tk(0);
+    const double b2m1 = (tk(1) - t) / h0, b20 = (t - tk(0)) / h0;
+    // order 3: B_{l-2}, B_{l-1}, B_l
+    const double b3m2 = (tk(1) - t) / (tk(1) - tk(-1)) * b2m1;
+    const double b3m1 = (t - tk(-1)) / (tk(1) - tk(-1)) * b2m1 + (tk(2) - t) / (tk(2) - tk(0)) * b20;
+    const double b30 = (t - tk(0)) / (tk(2) - tk(0)) * b20;
+    // order 4: B_{l-3} .. B_l
+    B[0] = (tk(1) - t) / (tk(1) - tk(-2)) * b3m2;
+    B[1] = (t - tk(-2)) / (tk(1) - tk(-2)) * b3m2 + (tk(2) - t) / (tk(2) - tk(-1)) * b3m1;
+    B[2] = (t - tk(-1)) / (tk(2) - tk(-1)) * b3m1 + (tk(3) - t) / (tk(3) - tk(0)) * b30;
+    B[3] = (t - tk(0)) / (tk(3) - tk(0)) * b30;
 }
 
 // Attitude matrix A = S'C of a unit quaternion (eq:quat2mat), row-major.
@@ -159,7 +149,8 @@ struct ObsEval {
 //    the small angle d = Lrate (t - tau_l) (Taylor series to d^6);
 //  * on equally spaced knots the cubic B-splines in closed form
 //    ((1-u)^3, 3u^3 - 6u^2 + 4, -3u^3 + 3u^2 + 3u + 1, u^3) / 6 with
-//    u = (t - tau_l) / (tau_l+1 - tau_l), otherwise Algorithm B1;
+//    u = (t - tau_l) / (tau_l+1 - tau_l), otherwise the general recursion
+//    of bspline4;
 //  * the field angle as atan(y'/x') of the SRS direction rotated by the
 //    field's Gamma_c/2 (odd series to z^9 for |z| < 1e-2, atan2 otherwise);
 //  * normalisations by Newton-refined reciprocal square roots.
@@ -325,52 +316,59 @@ __device__ __forceinline__ void attitude_partial(const ObsEval& o, double g[4], 
     g[3] = s * (-(q[0] * n0 + q[1] * n1 + q[2] * n2));
 }
 
-// Modified Cholesky for a small dense symmetric system (Algorithms C1-C3
-// of Appendix C: zero pivots are skipped and counted, no pivoting).
-// small_chol_factor: U holds the upper triangle row-major n x n on entry and
-// the factor on exit; returns the rank-defect count.
+// Modified Cholesky factorisation U'U = N of a small dense symmetric
+// positive semidefinite system (Appendix C: Algorithm C1's rule that a
+// non-positive pivot makes its whole row of U zero and counts one rank
+// defect; no pivoting), in right-looking form: each pivot row, once formed,
+// is subtracted from the trailing rows as an outer product.  U holds the
+// upper triangle of N row-major on entry and the factor on exit; returns the
+// defect count.
 template <int NN>
 __device__ __forceinline__ int small_chol_factor(double U[NN * NN]) {
     int d = 0;
 #pragma unroll
-    for (int j = 0; j < NN; ++j) {
+    for (int p = 0; p < NN; ++p) {
+        const double piv = U[p * NN + p];
+        if (piv > 0.0) {
+            const double up = sqrt(piv);
+            U[p * NN + p] = up;
 #pragma unroll
-        for (int i = 0; i <= j; ++i) {
-            double s = 0.0;
+            for (int c = p + 1; c < NN; ++c) U[p * NN + c] /= up;
+            // trailing rows r > p, columns c >= r
 #pragma unroll
-            for (int kk = 0; kk < i; ++kk) s += U[kk * NN + i] * U[kk * NN + j];
-            if (i < j) {
-                U[i * NN + j] = U[i * NN + i] > 0.0 ? (U[i * NN + j] - s) / U[i * NN + i] : 0.0;
-            } else {
-                const double piv = U[j * NN + j] - s;
-                if (piv > 0.0) {
-                    U[j * NN + j] = sqrt(piv);
-                } else {
-                    U[j * NN + j] = 0.0;
-                    ++d;
-                }
-            }
+            for (int r = p + 1; r < NN; ++r)
+#pragma unroll
+                for (int c = r; c < NN; ++c) U[r * NN + c] -= U[p * NN + r] * U[p * NN + c];
+        } else {
+            ++d;
+#pragma unroll
+            for (int c = p; c < NN; ++c) U[p * NN + c] = 0.0;
         }
     }
     return d;
 }
 
-// Algorithms C2 and C3 with the factor of small_chol_factor.
+// Solves U'U x = b with the factor of small_chol_factor (Algorithms C2 and
+// C3: an unknown whose pivot is zero is set to zero), both triangular solves
+// column by column: a solved unknown is removed from the remaining
+// right-hand sides at once.  x holds b on entry.
 template <int NN>
 __device__ __forceinline__ void small_chol_subst(const double U[NN * NN], double x[NN]) {
+    // U' y = b
 #pragma unroll
-    for (int i = 0; i < NN; ++i) {
-        double s = 0.0;
+    for (int p = 0; p < NN; ++p) {
+        const double up = U[p * NN + p];
+        x[p] = up > 0.0 ? x[p] / up : 0.0;
 #pragma unroll
-        for (int kk = 0; kk < i; ++kk) s += U[kk * NN + i] * x[kk];
-        x[i] = U[i * NN + i] > 0.0 ? (x[i] - s) / U[i * NN + i] : 0.0;
+        for (int r = p + 1; r < NN; ++r) x[r] -= U[p * NN + r] * x[p];
     }
+    // U x = y
 #pragma unroll
-    for (int i = NN - 1; i >= 0; --i) {
-        double s = 0.0;
+    for (int p = NN - 1; p >= 0; --p) {
+        const double up = U[p * NN + p];
+        x[p] = up > 0.0 ? x[p] / up : 0.0;
 #pragma unroll
-        for (int kk = i + 1; kk < NN; ++kk) s += U[i * NN + kk] * x[kk];
-        x[i] = U[i * NN + i] > 0.0 ? (x[i] - s) / U[i * NN + i] : 0.0;
+        for (int r = 0; r < p; ++r) x[r] -= U[r * NN + p] * x[p];
     }
 }
 

@@ -174,6 +174,20 @@ def solve(ctx, w, m, n_iter, ref, mode, tol=1.0, log=None, asi_stride=16, asi_la
     dis = disagreement(state(ctx, w), ref)
     while it < n_iter and dis > tol:
         t0 = time.perf_counter()          # every library call below returns after its device work
+        if learned:
+            # m iterations, a record and (from the fourth record on) the gated step
+            r = agis.agis_iterate_learned(ctx, 1, m)[0]
+            it += r["iterations"]
+            if r["gated"]:
+                ratios.append(r["q_candidate"] / r["q_plain"])
+                acc += int(r["accepted"])
+                rej += int(not r["accepted"])
+            t_gpu += time.perf_counter() - t0
+            blocks += 1
+            dis = disagreement(state(ctx, w), ref)
+            if log and blocks % 20 == 0:
+                log(f"{mode} it {it}: disagreement {dis:.3f} uas, accepted {acc} rejected {rej}")
+            continue
         agis.agis_iterate(ctx, m, stats=False)
         agis.agis_learned_record(ctx)
         count += 1
@@ -182,15 +196,6 @@ def solve(ctx, w, m, n_iter, ref, mode, tol=1.0, log=None, asi_stride=16, asi_la
             r = agis.agis_asi_step(ctx, asi_stride, asi_lambda_max)
             ratios.append(r["lam"])
             if r["factor"] > 0:
-                acc += 1
-                count = 0
-            else:
-                rej += 1
-        if learned and count >= 4:
-            r = agis.agis_learned_step(ctx)
-            it += 2
-            ratios.append(r["q_candidate"] / r["q_plain"])
-            if r["accepted"]:
                 acc += 1
                 count = 0
             else:
@@ -385,7 +390,7 @@ def main(argv=None):
     for mode in args.modes.split(","):
         w, ctx = problem(args.world, args.eval_seed)
         for which in range(len(weights)):
-            agis.agis_mlp_set_weights(ctx, which, weights[which])
+            agis.agis_mlp_load(ctx, which, weights[which])
         out[mode] = solve(ctx, w, args.m, args.max_iter, ref, mode, tol=args.tol, log=log,
                           cg_restart=args.cg_restart)
         log(f"{mode}: {out[mode]}")

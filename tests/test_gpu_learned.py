@@ -170,8 +170,8 @@ def test_candidate_arithmetic(agis_mod, tiny):
         prev = cur
     b_s = np.array([0.5, -1.25, 2.0, 0.75])
     b_a = np.array([1.5, -0.5, 0.25, -2.0])
-    agis_mod.agis_mlp_set_weights(ctx, 0, _weights(0, b3=b_s, W1=np.ones((64, 22))))
-    agis_mod.agis_mlp_set_weights(ctx, 1, _weights(1, b3=b_a, W1=np.ones((64, 18))))
+    agis_mod.agis_mlp_load(ctx, 0, _weights(0, b3=b_s, W1=np.ones((64, 22))))
+    agis_mod.agis_mlp_load(ctx, 1, _weights(1, b3=b_a, W1=np.ones((64, 18))))
     s0, a0, c0 = _state(agis_mod, ctx, w)
     agis_mod.agis_learned_apply(ctx)
     s1, a1, c1 = _state(agis_mod, ctx, w)
@@ -213,8 +213,8 @@ def test_rejected_candidate_is_the_plain_iterate(agis_mod, tiny, b3):
     the plain iterate one iteration on, bit for bit."""
     w, eta = tiny
     ctx, twin = _twins(agis_mod, w, eta, 10, 5)
-    agis_mod.agis_mlp_set_weights(ctx, 0, _weights(0, b3=np.full(4, b3)))
-    agis_mod.agis_mlp_set_weights(ctx, 1, _weights(1, b3=np.full(4, b3)))
+    agis_mod.agis_mlp_load(ctx, 0, _weights(0, b3=np.full(4, b3)))
+    agis_mod.agis_mlp_load(ctx, 1, _weights(1, b3=np.full(4, b3)))
     r = agis_mod.agis_learned_step(ctx)
     agis_mod.agis_iterate(twin, 1, stats=False)
     print(r)
@@ -241,7 +241,7 @@ def test_linear_extrapolation_is_accepted(agis_mod, tiny):
     w, eta = tiny
     ctx, twin = _twins(agis_mod, w, eta, 2000, 20)
     for which in (0, 1):
-        agis_mod.agis_mlp_set_weights(ctx, which, _weights(which, b3=np.array([4.0, 0.0, 0.0, 0.0])))
+        agis_mod.agis_mlp_load(ctx, which, _weights(which, b3=np.array([4.0, 0.0, 0.0, 0.0])))
     q0 = agis_mod.agis_chi2(ctx)
     r = agis_mod.agis_learned_step(ctx)
     print(r, "chi2 before", q0)
@@ -250,7 +250,7 @@ def test_linear_extrapolation_is_accepted(agis_mod, tiny):
         agis_mod.agis_learned_features(ctx, 0)
     # the twin takes the same candidate without the gate, then one iteration
     for which in (0, 1):
-        agis_mod.agis_mlp_set_weights(twin, which, agis_mod.agis_mlp_get_weights(ctx, which))
+        agis_mod.agis_mlp_load(twin, which, agis_mod.agis_mlp_get_weights(ctx, which))
     agis_mod.agis_learned_apply(twin)
     agis_mod.agis_iterate(twin, 1, stats=False)
     for x, y in zip(_state(agis_mod, ctx, w), _state(agis_mod, twin, w)):
@@ -324,7 +324,7 @@ def test_learned_solve_beats_plain(agis_mod):
     for mode in ("learned", "plain"):
         w0, ctx = learned.problem("tiny", 0)
         for which in (0, 1):
-            agis_mod.agis_mlp_set_weights(ctx, which, weights[which])
+            agis_mod.agis_mlp_load(ctx, which, weights[which])
         agis_mod.agis_learned_reset(ctx)
         it, count, acc = 0, 0, 0
         if mode == "learned":
@@ -346,3 +346,114 @@ def test_learned_solve_beats_plain(agis_mod):
     print(chi2)
     assert chi2["learned"][2] > 0
     assert chi2["learned"][0] < chi2["plain"][0]
+
+
+def test_mlp_train_step(agis_mod, tiny):
+    """One Adam step on a whole batch: the returned loss is the batch loss at
+    the weights before the step (as agis_mlp_gradient gives it), and the
+    first Adam step moves every weight with a gradient well above Adam's
+    epsilon by lr against its gradient's sign (m_hat = g, v_hat = g^2)."""
+    w, eta = tiny
+    rng = np.random.default_rng(11)
+    X = rng.normal(size=(700, 22)).astype(np.float32)
+    T = rng.normal(size=(700, 5)).astype(np.float32)
+    ctx = _ctx(agis_mod, w, eta)
+    agis_mod.agis_mlp_init(ctx, 0, 21)
+    w0 = agis_mod.agis_mlp_get_weights(ctx, 0)
+    g, L = agis_mod.agis_mlp_gradient(ctx, 0, X, T)
+    lr = 1e-3
+    L1 = agis_mod.agis_mlp_train_step(ctx, 0, X, T, lr)
+    w1 = agis_mod.agis_mlp_get_weights(ctx, 0)
+    assert L1 == L
+    big = np.abs(g) > 1e-4
+    assert big.sum() > 1000
+    np.testing.assert_allclose(w1[big] - w0[big], -lr * np.sign(g[big]), rtol=2e-3, atol=2e-9)
+    assert np.all(np.abs(w1 - w0) <= lr * (1 + 1e-3))
+    agis_mod.agis_destroy(ctx)
+
+
+def test_iterate_learned_is_the_block_loop(agis_mod, tiny):
+    """agis_iterate_learned runs, per block, m iterations, a record and from
+    the fourth record on the gated step: the same state bit for bit as those
+    calls made one by one, with the same gate decisions (networks that
+    extrapolate along the newest update, whose candidates the gate keeps;
+    after a kept one the history needs four new records)."""
+    w, eta = tiny
+    m, n_blocks = 20, 9
+    weights = [_weights(which, b3=np.array([4.0, 0.0, 0.0, 0.0])) for which in (0, 1)]
+    ctx, twin = (_ctx(agis_mod, w, eta) for _ in range(2))
+    for c in (ctx, twin):
+        agis_mod.agis_iterate(c, 1000, stats=False)
+        for which in (0, 1):
+            agis_mod.agis_mlp_load(c, which, weights[which])
+    st = agis_mod.agis_iterate_learned(ctx, n_blocks, m)
+    agis_mod.agis_learned_reset(twin)
+    count, manual = 0, []
+    for b in range(n_blocks):
+        agis_mod.agis_iterate(twin, m, stats=False)
+        agis_mod.agis_learned_record(twin)
+        count += 1
+        if count >= 4:
+            r = agis_mod.agis_learned_step(twin)
+            manual.append((m + 2, True, r["accepted"], r["q_plain"], r["q_candidate"]))
+            if r["accepted"]:
+                count = 0
+        else:
+            manual.append((m, False, False, 0.0, 0.0))
+    got = [(x["iterations"], x["gated"], x["accepted"], x["q_plain"], x["q_candidate"]) for x in st]
+    print(got)
+    assert got == manual
+    assert sum(x[2] for x in got) >= 2 and sum(x[1] for x in got) >= 2
+    for x, y in zip(_state(agis_mod, ctx, w), _state(agis_mod, twin, w)):
+        assert np.array_equal(x, y)
+    with pytest.raises(RuntimeError):
+        agis_mod.agis_iterate_learned(ctx, 1, 0)
+    agis_mod.agis_destroy(ctx)
+    agis_mod.agis_destroy(twin)
+
+
+def test_asi_trajectory_parity(agis_mod, oracle_lib, tiny):
+    """Accelerated simple iteration (Sect. 4.7) from the start values: nine
+    records of two iterations with the frame rotator and an accelerated step
+    from every third record, on the GPU and in the oracle's own scheme
+    (oracle.asi, extended precision as the reference).  The same three
+    steps are taken with the same lambda, and every parameter ends within the
+    FP64-floor tolerance of the other parity tests, which here carries the
+    rounding of the recorded updates through factors lambda / (1 - lambda)
+    of up to ~16."""
+    from oracle.asi import AcceleratedIteration
+    from test_gpu_parity import check_floor, fp64_floor
+
+    w, eta = tiny
+    m, n_blocks, stride = 2, 9, 16
+
+    def run(pr):
+        acc = AcceleratedIteration(pr, w.src_true, stride=stride, lambda_max=0.99)
+        run.steps.append(acc.run(n_blocks, m))
+        return pr.s.copy(), pr.a.copy(), pr.c.copy()
+
+    run.steps = []
+    X, O, tol = fp64_floor(oracle_lib, w, eta, run)
+    steps_x, steps_o = run.steps[0], run.steps[1]
+    ctx = _ctx(agis_mod, w, eta)
+    agis_mod.agis_learned_reset(ctx)
+    count, steps_g = 0, []
+    for _ in range(n_blocks):
+        agis_mod.agis_iterate(ctx, m, stats=False)
+        agis_mod.agis_learned_record(ctx)
+        count += 1
+        if count >= 3:
+            r = agis_mod.agis_asi_step(ctx, stride, 0.99)
+            steps_g.append((r["lam"], r["factor"]))
+            if r["factor"] > 0:
+                count = 0
+    G = _state(agis_mod, ctx, w)
+    print("lambda (GPU, extended, FP64 oracle):", [(g[0], float(x[0]), o[0])
+                                                   for g, x, o in zip(steps_g, steps_x, steps_o)])
+    assert len(steps_g) == len(steps_x) == 3 and all(f > 0 for _, f in steps_g)
+    for g, x, o in zip(steps_g, steps_x, steps_o):
+        assert abs(g[0] - float(x[0])) <= max(1e-10, 10 * abs(o[0] - float(x[0])))
+    check_floor("ASI: sources", X[0], O[0], G[0], tol[0], 0)
+    check_floor("ASI: attitude", X[1], O[1], G[1], tol[1], 1)
+    check_floor("ASI: calibration", X[2], O[2], G[2], tol[2], 2)
+    agis_mod.agis_destroy(ctx)

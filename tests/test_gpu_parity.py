@@ -175,11 +175,6 @@ def test_residuals_match(agis_mod, small, oracle_lib):
     p.close()
 
 
-def _well_determined(w, defect_o, min_obs=20):
-    nobs = np.bincount(w.src, minlength=w.src_true.shape[0])
-    return (nobs >= min_obs) & (defect_o == 0)
-
-
 @pytest.mark.parametrize("world", ["small", "tiny"])
 def test_source_update_parity(agis_mod, oracle_lib, world, request):
     w, eta = request.getfixturevalue(world)

@@ -2,7 +2,7 @@
 
 Appendix A (quaternions), Appendix B (B-splines), Appendix C (Algorithms
 C1-C3).  Every expected value here comes from an independent textbook route
-(vector cross products, Rodrigues' formula, the Cox-de Boor recursion, the
+(vector cross products, Rodrigues' formula, SciPy's B-spline basis, the
 closed-form uniform cubic B-splines, LAPACK via NumPy), never from the oracle.
 """
 import numpy as np
@@ -77,18 +77,11 @@ def test_quat2mat_orthonormal_and_consistent(oracle_lib):
     np.testing.assert_allclose(A[0], [np.cos(th), np.sin(th), 0], atol=1e-15)
 
 
-def _cox_de_boor(knots, n, k, t):
-    """Textbook recursion B_{n,k} (order k) evaluated at t, half-open supports."""
-    if k == 1:
-        return 1.0 if knots[n] <= t < knots[n + 1] else 0.0
-    out = 0.0
-    d1 = knots[n + k - 1] - knots[n]
-    d2 = knots[n + k] - knots[n + 1]
-    if d1 > 0:
-        out += (t - knots[n]) / d1 * _cox_de_boor(knots, n, k - 1, t)
-    if d2 > 0:
-        out += (knots[n + k] - t) / d2 * _cox_de_boor(knots, n + 1, k - 1, t)
-    return out
+def _scipy_basis(knots, t):
+    """Values at t of all cubic B-splines on the knots, from SciPy's
+    B-spline design matrix (an independent library implementation)."""
+    from scipy.interpolate import BSpline
+    return BSpline.design_matrix(np.atleast_1d(t), knots, 3).toarray()[0]
 
 
 def _knots(K=12, dt=7.0, t0=-40.0):
@@ -106,16 +99,25 @@ def test_left_index(oracle_lib):
     assert oracle_lib.left_index(k, k[N]) == N - 1        # end of the spline interval
 
 
-def test_bspline_algorithm_b1(oracle_lib):
+def test_bspline_basis(oracle_lib):
+    """The four non-zero cubic B-splines equal SciPy's basis on a regular
+    sequence with 4-fold end knots and on an irregular one (a double knot
+    included); partition of unity; non-negative."""
+    rng_k = np.random.default_rng(3)
+    inner = np.cumsum(rng_k.uniform(0.5, 9.0, 14)) - 40.0
+    inner[6] = inner[5]                                   # a double knot
+    irregular = np.r_[np.full(3, inner[0]), inner, np.full(3, inner[-1])]
+    for k in (_knots(), irregular):
+        N = k.size - 4
+        for t in np.linspace(k[3], k[N] - 1e-9, 97):
+            ell = oracle_lib.left_index(k, t)
+            b = oracle_lib.bspline(k, ell, t)
+            assert np.all(b >= 0)
+            assert abs(b.sum() - 1) < 1e-15                    # partition of unity
+            ref = _scipy_basis(k, t)
+            np.testing.assert_allclose(b, ref[ell - 3:ell + 1], atol=4e-16)
+            assert np.abs(np.delete(ref, np.arange(ell - 3, ell + 1))).max(initial=0.0) == 0.0
     k = _knots()
-    N = k.size - 4
-    for t in np.linspace(k[3], k[N] - 1e-9, 97):
-        ell = oracle_lib.left_index(k, t)
-        b = oracle_lib.bspline(k, ell, t)
-        assert np.all(b >= 0)
-        assert abs(b.sum() - 1) < 1e-15                    # partition of unity
-        ref = [_cox_de_boor(k, ell - 3 + j, 4, t) for j in range(4)]
-        np.testing.assert_allclose(b, ref, atol=2e-16)
     # uniform interior interval: textbook cubic B-spline pieces
     for u in np.linspace(0, 1, 11)[:-1]:
         ell = 7
