@@ -258,9 +258,6 @@ class Problem:
         self.src = np.ascontiguousarray(src, dtype=np.int32)
         self.fov = np.ascontiguousarray(fov, dtype=np.int8)
         self.cell = np.ascontiguousarray(cell, dtype=np.int32)
-        if int(consts.get("robust", 0)) and self.cell.size and self.cell.min() < 0:
-            # the excess attitude noise would need its ACP and ACF components
-            raise ValueError("robust weighting with across-scan observations is not modelled")
         self.s = self._arr(s).copy()
         self.a = self._arr(a).copy()
         self.c = self._arr(c).copy()
@@ -275,8 +272,10 @@ class Problem:
                                  robust=int(consts.get("robust", 0)), eps_bucket=int(consts.get("eps_bucket", 8)))
         n_iv = self.knots.size - 7
         if self.world.robust:
+            # three components (along scan, across scan preceding and
+            # following field of view), n_buckets each
             nb = (n_iv + self.world.eps_bucket - 1) // self.world.eps_bucket
-            self.eps_a2 = self._arr(np.full(nb, float(consts.get("eps_a_init", 0.0)) ** 2))
+            self.eps_a2 = self._arr(np.full(3 * nb, float(consts.get("eps_a_init", 0.0)) ** 2))
         else:
             self.eps_a2 = self._zeros(0)
         # robust 2: excess source noise eps_i^2 and its significance D per source
@@ -297,7 +296,7 @@ class Problem:
                              cell=_p(self.cell, c_i32))
         self.state = self._State(n_src=self.s.shape[0], n_att=self.a.shape[0], n_cells=self.c.size,
                                  s=_p(self.s, cr), a=_p(self.a, cr), c=_p(self.c, cr),
-                                 n_buckets=self.eps_a2.size, eps_a2=_p(self.eps_a2, cr),
+                                 n_buckets=self.eps_a2.size // 3, eps_a2=_p(self.eps_a2, cr),
                                  src_eps2=_p(self.src_eps2, cr), src_D=_p(self.src_D, cr))
 
     def set_eta_obs(self, eta_obs):
@@ -443,12 +442,24 @@ def problem_from_world(world, eta_obs=None, state="start", precision="double"):
                    precision=precision)
 
 
-def observed_field_angles(world):
+def observed_field_angles(world, chunk=1 << 24):
     """eta_obs = eta(t | s_true, a_true) - c_true(cell) + noise (Sect. 3.5 at
     the truth); for an across-scan observation (cell < 0) zeta(t | s_true,
-    a_true) + noise (eq:resAC, no calibration term)."""
-    pr = problem_from_world(world, eta_obs=None, state="truth")
-    out = pr.observe()
-    ac = world.cell < 0
-    al = np.asarray(out["eta"]) - world.cal_true[np.where(ac, 0, world.cell)]
-    return np.where(ac, np.asarray(out["zeta"]), al) + world.eps
+    a_true) + noise (eq:resAC, no calibration term).  Evaluated over chunks
+    of at most `chunk` observations (memory: the model's outputs per
+    observation)."""
+    n = world.t.size
+    out = np.empty(n)
+    consts = dict(world.consts)
+    consts["robust"] = 0                       # the model alone; no robust state
+    for i0 in range(0, max(n, 1), chunk):
+        i1 = min(n, i0 + chunk)
+        sl = slice(i0, i1)
+        pr = Problem(consts, world.knots, world.t[sl], np.zeros(i1 - i0), world.sigma[sl], world.src[sl],
+                     world.fov[sl], world.cell[sl], world.src_true, world.att_true, world.cal_true)
+        o = pr.observe()
+        cell = world.cell[sl]
+        ac = cell < 0
+        al = np.asarray(o["eta"]) - world.cal_true[np.where(ac, 0, cell)]
+        out[sl] = np.where(ac, np.asarray(o["zeta"]), al) + world.eps[sl]
+    return out

@@ -440,12 +440,23 @@ double orc_quantile(const double* x, int64_t n, double p) {
  * excess-noise bucket. */
 static int64_t bucket_of(const orc_world_t* w, int64_t ell) { return (ell - (M_ORDER - 1)) / w->eps_bucket; }
 
-/* sigma~_l^2 = sigma_l^2 + eps_a^2(t_l) (eq:W with eps_i = 0). */
+/* The attitude component an observation measures (Sect. 3.6: three excess
+ * noise functions): along scan, or across scan in the preceding or in the
+ * following field of view.  eps_a2 holds n_buckets values per component,
+ * AL first, then ACP, then ACF. */
+static int64_t eps_slot(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, int64_t l,
+                        int64_t ell) {
+    int64_t comp = obs->cell[l] >= 0 ? 0 : (obs->fov[l] > 0 ? 1 : 2);
+    return comp * st->n_buckets + bucket_of(w, ell);
+}
+
+/* sigma~_l^2 = sigma_l^2 + eps_a^2(t_l) of the observation's component
+ * (eq:W with eps_i = 0). */
 static double sigma_tilde2(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, int64_t l,
                            int64_t ell) {
     double s = (double)obs->sigma[l];
     double v = s * s;
-    if (w->robust) v += st->eps_a2[bucket_of(w, ell)];
+    if (w->robust) v += st->eps_a2[eps_slot(w, obs, st, l, ell)];
     return v;
 }
 
@@ -466,9 +477,11 @@ static double weight(const orc_world_t* w, const orc_obs_t* obs, const orc_state
     return wl / v;
 }
 
+/* eq e09 for each component and bucket: the observations of the component
+ * in the bucket's knot intervals. */
 void orc_excess_attitude_noise(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st) {
     if (!w->robust || st->n_buckets <= 0) return;
-    int64_t nb = st->n_buckets;
+    int64_t nb = 3 * st->n_buckets;
     int64_t* cnt = (int64_t*)calloc((size_t)nb + 1, sizeof(int64_t));
     int64_t* bk = (int64_t*)malloc(sizeof(int64_t) * (size_t)(obs->n > 0 ? obs->n : 1));
     double* v = (double*)malloc(sizeof(double) * (size_t)(obs->n > 0 ? obs->n : 1));
@@ -478,7 +491,7 @@ void orc_excess_attitude_noise(const orc_world_t* w, const orc_obs_t* obs, orc_s
         orc_fwd_t o;
         forward_one(w, obs, st, l, &o);
         double s = (double)obs->sigma[l];
-        bk[l] = bucket_of(w, o.ell);
+        bk[l] = eps_slot(w, obs, st, l, o.ell);
         v[l] = o.R * o.R - s * s - source_eps2(w, obs, st, l);     /* e09 */
     }
     for (int64_t l = 0; l < obs->n; ++l) cnt[bk[l] + 1] += 1;
@@ -552,7 +565,7 @@ void orc_source_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* 
 #pragma omp parallel
     {
         int64_t cap = 0;
-        double *Ab = NULL, *hb = NULL, *Vb = NULL, *wb = NULL;
+        double *Ab = NULL, *hb = NULL, *Vb = NULL, *wb = NULL, *xb = NULL;
 #pragma omp for schedule(dynamic, 64)
         for (int64_t i = 0; i < st->n_src; ++i) {
             int64_t ni = off[i + 1] - off[i];
@@ -562,6 +575,7 @@ void orc_source_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* 
                 hb = (double*)realloc(hb, sizeof(double) * cap);
                 Vb = (double*)realloc(Vb, sizeof(double) * cap);
                 wb = (double*)realloc(wb, sizeof(double) * cap);
+                xb = (double*)realloc(xb, sizeof(double) * cap);
             }
             for (int64_t k = 0; k < ni; ++k) {
                 int64_t l = idx[off[i] + k];
@@ -574,9 +588,21 @@ void orc_source_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* 
             }
             int n_solve = 1;
             if (w->robust) {
+                /* initial downweights: varsigma_i from the source's residuals
+                 * of the observation's own kind (along scan, across scan),
+                 * whose scales differ by sigma_AC / sigma_AL */
                 n_solve = ORC_INNER_SOLVES;
-                double vs = 0.5 * (orc_quantile(hb, ni, 5.0 / 6.0) - orc_quantile(hb, ni, 1.0 / 6.0));
-                for (int64_t k = 0; k < ni; ++k) wb[k] = vs > 0.0 ? orc_weight_function(hb[k] / vs) : 1.0;
+                double vs[2];
+                for (int kind = 0; kind < 2; ++kind) {
+                    int64_t nk = 0;
+                    for (int64_t k = 0; k < ni; ++k)
+                        if ((obs->cell[idx[off[i] + k]] < 0) == kind) xb[nk++] = hb[k];
+                    vs[kind] = 0.5 * (orc_quantile(xb, nk, 5.0 / 6.0) - orc_quantile(xb, nk, 1.0 / 6.0));
+                }
+                for (int64_t k = 0; k < ni; ++k) {
+                    double v = vs[obs->cell[idx[off[i] + k]] < 0];
+                    wb[k] = v > 0.0 ? orc_weight_function(hb[k] / v) : 1.0;
+                }
             }
             double N[25], b[5];
             int def = 0;
@@ -644,7 +670,7 @@ void orc_source_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* 
             if (Q_out) Q_out[i] = Q;
             if (defect_out) defect_out[i] = def;
         }
-        free(Ab); free(hb); free(Vb); free(wb);
+        free(Ab); free(hb); free(Vb); free(wb); free(xb);
     }
     free(off);
     free(idx);

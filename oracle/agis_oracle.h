@@ -58,7 +58,8 @@ typedef struct {
     double* a;                /* [n_att][4] x, y, z, w */
     double* c;                /* [n_cells] */
     int64_t n_buckets;        /* ceil((N - 3) / eps_bucket) when robust, else 0 */
-    double* eps_a2;           /* [n_buckets] excess attitude variance eps_a^2 [rad^2] */
+    double* eps_a2;           /* [3][n_buckets] excess attitude variance eps_a^2 [rad^2] of the
+                                 AL, ACP and ACF components (Sect. 3.6) */
     double* src_eps2;         /* [n_src] excess source variance eps_i^2 of the last S update (robust 2; may be NULL) */
     double* src_D;            /* [n_src] its significance D of eq:D (robust 2; may be NULL) */
 } orc_state_t;
@@ -103,10 +104,12 @@ double orc_weight_function(double z);
 /* p-quantile of x[0..n-1] by linear interpolation between order statistics
  * at (n - 1) p (Hyndman-Fan type 7); n = 0 gives 0.  x is not modified. */
 double orc_quantile(const double* x, int64_t n, double p);
-/* Excess attitude noise (eq e09) per bucket from the residuals at the
- * current state: eps_a2[j] = max(0, F_0.68(R_l^2 - sigma_l^2)) over the
- * observations of bucket j (knot intervals [j B, (j + 1) B)); 0 for an empty
- * bucket.  Needs robust = 1. */
+/* Excess attitude noise (eq e09) per component and bucket from the
+ * residuals at the current state: eps_a2[a n_buckets + j] = max(0,
+ * F_0.68(R_l^2 - sigma_l^2 - eps_i^2)) over the observations of component a
+ * (0 along scan, 1 across scan in the preceding, 2 in the following field of
+ * view) in bucket j (knot intervals [j B, (j + 1) B)); 0 for an empty set.
+ * Needs robust >= 1. */
 void orc_excess_attitude_noise(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st);
 
 /* --- Sect. 5: update blocks ----------------------------------------------- */

@@ -232,6 +232,37 @@ def _sign_continuous_fast(q: np.ndarray) -> np.ndarray:
     return np.where(flips[:, None] == 1, -q, q)
 
 
+def _unit_norm_ends(knots: np.ndarray, a: np.ndarray, n_end: int = 6, n_iter: int = 8) -> np.ndarray:
+    """Rescale the first and last n_end coefficients so that the spline's
+    norm stays close to one over the end intervals too.  The closed-form
+    rescaling above assumes equally spaced knots; next to the 4-fold end
+    knots the B-spline weights differ, and so would the norm.  The scales
+    are fitted by Gauss-Newton to |q(t)|^2 = 1 on a dense sample of the
+    end intervals (SciPy's B-spline basis), the other coefficients held."""
+    from scipy.interpolate import BSpline
+    N = a.shape[0]
+    if N < 2 * n_end + 4:
+        return a
+    a = a.copy()
+    for side in (0, 1):
+        idx = np.arange(n_end) if side == 0 else np.arange(N - n_end, N)
+        t0, t1 = (knots[3], knots[3 + n_end - 2]) if side == 0 else (knots[N - n_end + 2], knots[N])
+        ts = np.linspace(t0, t1, 40 * n_end)
+        ts[-1] = np.nextafter(ts[-1], -np.inf) if side == 0 else ts[-1]
+        B = BSpline.design_matrix(ts, knots, 3).toarray()
+        sc = np.ones(n_end)
+        for _ in range(n_iter):
+            a_s = a.copy()
+            a_s[idx] *= sc[:, None]
+            q = B @ a_s                                   # (samples, 4)
+            res = 1.0 - (q * q).sum(axis=1)
+            # d|q|^2 / d sc_m = 2 q . (B_m a_m)
+            J = 2.0 * np.stack([(q * (B[:, m][:, None] * a[m])).sum(axis=1) for m in idx], axis=1)
+            sc += np.linalg.lstsq(J, res, rcond=None)[0]
+        a[idx] *= sc[:, None]
+    return a
+
+
 def make_world(spec: WorldSpec, law: dict | None = None, progress=None) -> World:
     """Generate one seeded synthetic workload (no observed field angles).
     progress(message), if given, is called at each stage."""
@@ -274,6 +305,7 @@ def make_world(spec: WorldSpec, law: dict | None = None, progress=None) -> World
     scale = np.ones(N)
     scale[1:-1] = 2.0 / 3.0 + (cosb[:-1] + cosb[1:]) / 6.0
     att_true = att_true / scale[:, None]
+    att_true = _unit_norm_ends(knots, att_true)
 
     n_days = int(np.ceil(T / DAY - 1e-9))
     n_cells = 2 * n_days

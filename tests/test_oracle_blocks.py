@@ -230,23 +230,6 @@ def test_first_iteration_independent_of_source_start(tiny_world, tiny_eta, oracl
     assert np.median(_rot_err(oracle_lib, pa.a, pb.a, idx)) < 0.5    # weak x/y axes amplify 2nd order
 
 
-def test_simple_iteration_converges_noise_free(tiny_world, tiny_eta, oracle_lib):
-    w = tiny_world
-    pr = oracle_lib.problem_from_world(w, tiny_eta, state="start")
-    nobs = np.bincount(w.src, minlength=w.src_true.shape[0])
-    good = nobs >= 30
-    idx = np.arange(40, w.n_att - 40, 11)
-    hist = []
-    for it in range(6):
-        pr.iterate(s_ref=w.src_true)
-        hist.append((np.median(_src_err(pr.s, w.src_true)[good]),
-                     np.median(_rot_err(oracle_lib, pr.a, w.att_true, idx)[:, 2])))
-    hs = np.array(hist)
-
-    assert np.all(np.diff(hs[1:, 0]) < 0) and np.all(np.diff(hs[1:, 1]) < 0)
-    assert hs[-1, 0] < 0.85 * hs[1, 0]
-
-
 def test_oracle_thread_count_invariance(tiny_world, tiny_eta, oracle_lib):
     w = tiny_world
     gomp = ctypes.CDLL("libgomp.so.1")

@@ -113,7 +113,9 @@ def test_excess_attitude_noise(oracle_lib, tiny_world):
                             w.cal_true)
     e2 = pr.excess_attitude_noise()
     R = pr.observe()["R"]
-    nb = e2.size
+    nb = e2.size // 3                                  # along scan; the across-scan components are empty here
+    assert np.all(e2[nb:] == 0.0)
+    e2 = e2[:nb]
     ref = np.zeros(nb)
     for j in np.unique(bucket):
         v = R[bucket == j] ** 2 - sig[bucket == j] ** 2
@@ -172,3 +174,92 @@ def test_robust_attitude_update_rejects_outliers(oracle_lib, outlier_world):
     assert np.median(e_rob) < 1.5 * np.median(e_clean) + 0.01
     assert np.percentile(e_rob, 99) < 1.5 * np.percentile(e_clean, 99) + 0.05
     assert np.median(e_plain) > 50 * np.median(e_rob)
+
+
+@pytest.fixture(scope="module")
+def ac_world(oracle_lib):
+    """Noise-free tiny world with one across-scan record per transit."""
+    w = C.make("tiny", noise=False, ac_obs=True)
+    return w, oracle_lib.observed_field_angles(w)
+
+
+def test_excess_attitude_noise_components(oracle_lib, ac_world):
+    """The three excess-noise functions (Sect. 3.6: along scan, across scan
+    in the preceding and in the following field of view), each by eq e09
+    over its own observations: every (component, bucket) equals NumPy's 68th
+    percentile of R^2 - sigma^2 over that set; an excess of 300 uas added to
+    the ACP records of buckets 100-159 and of 200 uas to the AL records of
+    buckets 300-359 is recovered in that component and bucket range only."""
+    w, eta = ac_world
+    rng = np.random.default_rng(31)
+    consts = dict(w.consts, robust=1, eps_a_init=0.0)
+    sig = w.sigma.astype(np.float64)
+    pr0 = oracle_lib.Problem(consts, w.knots, w.t, eta, w.sigma, w.src, w.fov, w.cell, w.src_true, w.att_true,
+                             w.cal_true)
+    bucket = (pr0.observe()["ell"] - 3) // 8
+    comp = np.where(w.cell >= 0, 0, np.where(w.fov > 0, 1, 2))
+    acp_win = (comp == 1) & (bucket >= 100) & (bucket < 160)
+    al_win = (comp == 0) & (bucket >= 300) & (bucket < 360)
+    eta2 = (eta + rng.normal(0, 1, w.n_obs) * sig + np.where(acp_win, rng.normal(0, 300 * UAS, w.n_obs), 0.0)
+            + np.where(al_win, rng.normal(0, 200 * UAS, w.n_obs), 0.0))
+    pr = oracle_lib.Problem(consts, w.knots, w.t, eta2, w.sigma, w.src, w.fov, w.cell, w.src_true, w.att_true,
+                            w.cal_true)
+    e2 = pr.excess_attitude_noise()
+    nb = e2.size // 3
+    R = pr.observe()["R"]
+    ref = np.zeros(3 * nb)
+    for a in range(3):
+        for j in np.unique(bucket[comp == a]):
+            sel = (comp == a) & (bucket == j)
+            ref[a * nb + j] = max(0.0, np.quantile(R[sel] ** 2 - sig[sel] ** 2, 0.68, method="linear"))
+    assert np.allclose(e2, ref, rtol=1e-12, atol=1e-30)
+    e = np.sqrt(e2.reshape(3, nb)) / UAS
+    s_ac = float(sig[comp == 1][0]) / UAS
+    exp_acp = np.sqrt(0.989 * (s_ac ** 2 + 300.0 ** 2) - s_ac ** 2)
+    exp_al = np.sqrt(0.989 * (100.0 ** 2 + 200.0 ** 2) - 100.0 ** 2)
+    print(f"ACP window {np.median(e[1, 100:160]):.1f} uas (expected {exp_acp:.1f}); AL window "
+          f"{np.median(e[0, 300:360]):.1f} (expected {exp_al:.1f}); elsewhere AL {np.median(e[0, :100]):.1f}, "
+          f"ACP {np.median(e[1, 200:300]):.1f}, ACF {np.median(e[2]):.1f} uas")
+    assert abs(np.median(e[1, 100:160]) / exp_acp - 1) < 0.15
+    assert abs(np.median(e[0, 300:360]) / exp_al - 1) < 0.1
+    assert np.median(e[1, 300:360]) < 0.3 * exp_acp and np.median(e[2, 100:160]) < 0.3 * exp_acp
+    assert np.median(e[0, 100:160]) < 0.3 * exp_al
+
+
+def test_inner_iteration_with_across_scan_records(oracle_lib, ac_world):
+    """Robust S update with along- and across-scan records of one source (a
+    scale ratio of 5.65 between their sigmas): the initial downweights take
+    varsigma from each kind's own residuals, so gross outliers of either
+    kind are rejected: the robust update on contaminated data equals the
+    plain update on the clean data to the influence the outliers keep
+    (across scan a 20 mas outlier is only 35 sigma, w = exp(-35/3) ~ 1e-5,
+    which moves a source by a few 1e-2 uas; along scan w ~ 1e-29), while the
+    plain update is pulled off by mas."""
+    w, eta = ac_world
+    rng = np.random.default_rng(33)
+    bad = rng.random(w.n_obs) < 0.01
+    eta_bad = eta + np.where(bad, rng.choice([-1.0, 1.0], w.n_obs) * rng.uniform(20, 100, w.n_obs) * MAS, 0.0)
+    s0 = w.src_true + rng.normal(0, 1.0, w.src_true.shape) * MAS
+    consts = dict(w.consts, robust=1, eps_a_init=0.0)
+
+    def run(robust, keep=slice(None)):
+        c = dict(consts, robust=int(robust))
+        p = oracle_lib.Problem(c, w.knots, w.t[keep], eta_bad[keep], w.sigma[keep], w.src[keep], w.fov[keep],
+                               w.cell[keep], s0, w.att_true, w.cal_true)
+        _, _, de = p.source_update()
+        return p.s, de
+
+    s_rob, de_r = run(True)
+    s_clean, de_c = run(False, ~bad)
+    s_plain, _ = run(False)
+    n_clean = np.bincount(w.src[~bad], minlength=w.src_true.shape[0])
+    n_bad = np.bincount(w.src[bad], minlength=w.src_true.shape[0])
+    n_ac_bad = np.bincount(w.src[bad & (w.cell < 0)], minlength=w.src_true.shape[0])
+    sel = (n_clean >= 20) & (n_bad >= 1) & (de_r == 0) & (de_c == 0)
+    assert sel.sum() > 500 and (sel & (n_ac_bad >= 1)).sum() > 100
+    d_rob = np.abs(_sdiff(s_rob, s_clean)).max(1)
+    print(f"robust - clean: AL-only outliers max {d_rob[sel & (n_ac_bad == 0)].max():.2e} uas, "
+          f"with AC outliers max {d_rob[sel & (n_ac_bad >= 1)].max():.2e} uas")
+    assert d_rob[sel & (n_ac_bad == 0)].max() < 1e-4
+    assert d_rob[sel].max() < 0.1
+    assert np.median(np.abs(_sdiff(s_plain, s_clean))[sel].max(1)) > 100.0
