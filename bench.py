@@ -24,34 +24,36 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 
 
 def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-# Algorithmic per-unit figures of the two observation passes (FP64 flops,
-# an add, multiply or divide counting 1 and a fused multiply-add 2; bytes
-# each pass must move).  The flop counts follow the formulas of the
-# observation model as the kernels evaluate them:
-#   model (ephemeris, proper direction, aberration, B-splines, attitude,
-#   SRS direction, field angle, residual)                          226
-#   A/C: attitude partials 29, normal-equation terms 83, the 120 interval
-#        sums 240                                                  352
-#   S:   source partials 72, weight 2, the 21 source sums 58        132
-AC_FLOPS_PER_OBS = 226.0 + 352.0
-S_FLOPS_PER_OBS = 226.0 + 132.0
-S_FLOPS_PER_SOURCE = 400.0     # 5x5 modified Cholesky, variances, update
-AC_BYTES_PER_OBS = 28.0        # t 8, eta 8, sigma 4, cell+fov 4, source 4
-AC_BYTES_PER_INTERVAL = 8.0 * (116 + 4) + 8.0 + 4 * 8.0   # sums out, offset, coefficient in
-AC_BYTES_PER_SOURCE = 56.0     # r, mu vector, parallax of s^(k+1)
-S_BYTES_PER_OBS = 28.0         # t 8, eta 8, sigma 4, cell+fov 4, left index 4
-S_BYTES_PER_SOURCE = 40.0 + 40.0 + 64.0 + 40.0 + 8.0 + 4.0 + 8.0   # s in/out, prep, d, Q, defect, offset
+# Algorithmic work per observation per iteration (a fused multiply-add
+# counts 2 flop), the per-unit figures of the hot-path measurement plan:
+#   forward model 186, source partials 60, attitude partials 50,
+#   source sums 40, attitude sums 290, calibration sums 4;
+#   the robust inner iteration's three further solves 240 (4 rounds in all).
+# Per kernel:
+MODEL_FLOPS = 186.0
+S_FLOPS_PER_OBS = MODEL_FLOPS + 60.0 + 40.0              # 286
+S_ROBUST_FLOPS_PER_OBS = S_FLOPS_PER_OBS + 240.0          # 526
+AC_FLOPS_PER_OBS = MODEL_FLOPS + 50.0 + 290.0 + 4.0       # 530
+EPS_FLOPS_PER_OBS = MODEL_FLOPS + 4.0                     # a model pass and R^2 - sigma^2
+# Algorithmic HBM bytes: every pass streams 28 B per observation (t 8,
+# eta 8, sigma 4, cell+fov 4, left index or source 4) and gathers ~88 B per
+# source; the A/C pass writes 62 doubles per attitude coefficient.
+BYTES_PER_OBS = 28.0
+BYTES_PER_SOURCE = 88.0
+BYTES_PER_COEF = 62.0 * 8.0
 
-KERNEL_SOURCES = ("paper_1112_4139_amd/csrc/hot.hip", "paper_1112_4139_amd/csrc/model.h")
-PMC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_gaia1.txt")
-KERNEL_SYMBOL = {"ac_pass": "k_ac_pass", "source_update": "k_source_update"}
+KERNEL_SOURCES = ("paper_1112_4139_amd/csrc/hot.hip", "paper_1112_4139_amd/csrc/model.h",
+                  "paper_1112_4139_amd/csrc/robust.hip", "paper_1112_4139_amd/csrc/source_block.h")
+# kernel timer -> symbol prefix of its kernels in the counter summaries
+KERNEL_SYMBOL = {"ac_pass": "k_ac_pass", "source_update": "k_source_update", "source_update_robust": "k_s_",
+                 "excess_noise": "k_eps_fused"}
 
 
 def kernel_source_hash():
@@ -63,22 +65,28 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
+def pmc_file(workload):
+    return os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.txt")
+
+
 def measured_traffic(kernel, workload, precision):
-    """HBM bytes per launch of kernel from the committed rocprofv3 PMC
-    summary (FETCH_SIZE + WRITE_SIZE scaled by a copy-kernel calibration),
-    taken on the FP64 gaia1 workload; None for another workload or
-    precision, when no summary exists or when the kernels changed since."""
-    if workload != "gaia1" or precision != "fp64" or not os.path.exists(PMC_FILE):
+    """HBM bytes per launch of a kernel (its HIP-event timer's kernels) from
+    the committed rocprofv3 counter summary of the workload (FETCH_SIZE +
+    WRITE_SIZE scaled by a copy-kernel calibration), taken in FP64; None for
+    another precision, when no summary exists or when the kernel sources
+    changed since the counters were taken."""
+    path = pmc_file(workload)
+    if precision != "fp64" or not os.path.exists(path):
         return None
     vals = {}
-    with open(PMC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha1") != kernel_source_hash():
         return None
-    key = KERNEL_SYMBOL[kernel] + " hbm_bytes_per_launch"
+    key = kernel + " hbm_bytes_per_launch"
     return float(vals[key]) if key in vals else None
 
 
@@ -95,35 +103,88 @@ def workload_description(name, w):
             "law": "Gaia-like: spin 60 arcsec/s, precession 63 d, aspect 45 deg, basic angle 106.5 deg"}
 
 
-def cpu_baseline(w, frac, log_fn):
-    """Time one oracle iteration on a source subset of the same workload."""
-    import oracle
-    import synth
-    oracle.build()
-    rng = np.random.default_rng(7)
-    n_src = w.src_true.shape[0]
-    m = max(1, int(n_src * frac))
-    pick = np.sort(rng.choice(n_src, m, replace=False))
-    remap = -np.ones(n_src, np.int64)
-    remap[pick] = np.arange(m)
-    keep = remap[w.src] >= 0
+def host_description():
+    model, ram = None, None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.lower().startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal"):
+                    ram = round(int(line.split()[1]) / 1024 ** 2, 1)
+                    break
+    except OSError:
+        pass
+    return model, ram
+
+
+def time_slice(w, day0, n_days):
+    """The observations of n_days whole days from day day0 of the mission:
+    the sources they see (renumbered), the attitude coefficients and knots
+    that cover them, the days' calibration cells.  Across-scan records keep
+    cell -1."""
     import copy
+    DAY = 86400.0
+    t0 = w.consts["t_beg"] + day0 * DAY
+    t1 = min(t0 + n_days * DAY, w.consts["t_end"])
+    keep = (w.t >= t0) & (w.t < t1)
     ws = copy.copy(w)
-    ws.src_true = w.src_true[pick]
-    ws.src_start = w.src_start[pick]
-    for name in ("t", "fov", "cell", "sigma", "eps", "eta_nominal"):
+    src_ids, inv = np.unique(w.src[keep], return_inverse=True)
+    ws.src_true, ws.src_start = w.src_true[src_ids], w.src_start[src_ids]
+    for name in ("t", "fov", "sigma", "eps"):
         setattr(ws, name, np.ascontiguousarray(getattr(w, name)[keep]))
-    ws.src = np.ascontiguousarray(remap[w.src[keep]].astype(np.int32))
-    eta = oracle.observed_field_angles(ws)
-    pr = oracle.problem_from_world(ws, eta, state="start")
+    ws.src = np.ascontiguousarray(inv.astype(np.int32))
+    cell = w.cell[keep]
+    ws.cell = np.ascontiguousarray(np.where(cell >= 0, cell - 2 * day0, cell).astype(np.int32))
+    nd = int(np.ceil((t1 - t0) / DAY - 1e-9))
+    ws.cal_true = w.cal_true[2 * day0:2 * (day0 + nd)]
+    ws.cal_start = w.cal_start[2 * day0:2 * (day0 + nd)]
+    # knot intervals [l0, l1] hold the slice; coefficients l0 - 3 .. l1
+    l0 = int(np.searchsorted(w.knots, t0, side="right") - 1)
+    l1 = int(np.searchsorted(w.knots, t1, side="left") - 1)
+    ws.knots = np.ascontiguousarray(w.knots[l0 - 3:l1 + 5])
+    ws.att_true = w.att_true[l0 - 3:l1 + 1]
+    ws.att_start = w.att_start[l0 - 3:l1 + 1]
+    ws.consts = dict(w.consts, t_beg=float(ws.knots[3]), t_end=float(ws.knots[-4]))
+    return ws
+
+
+def cpu_baseline(w, days, days_1t, log_fn):
+    """The oracle's iteration (S[AC] and the frame rotator) timed on time
+    slices of the same workload: all threads of the host share on `days` days
+    of observations, one thread on `days_1t` days."""
+    import ctypes
+
+    import oracle
+    oracle.build()
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    log_fn(f"cpu baseline: oracle on {m} sources, {ws.n_obs} obs, {threads} threads")
-    t0 = time.perf_counter()
-    pr.iterate(s_ref=ws.src_true)
-    dt = time.perf_counter() - t0
-    return {"value": ws.n_obs / dt, "unit": "obs/s", "cores": threads, "kind": "oracle",
-            "sample": f"one S[AC]+frame iteration over {m} of {n_src} sources ({ws.n_obs} obs) and all "
-                      f"{w.n_att} attitude coefficients, {dt:.1f} s"}
+    gomp = ctypes.CDLL("libgomp.so.1")
+    out = {}
+    n_days = int(np.ceil((w.consts["t_end"] - w.consts["t_beg"]) / 86400.0 - 1e-9))
+    for nt, nd in ((threads, days), (1, days_1t)):
+        day0 = n_days // 2
+        ws = time_slice(w, day0, nd)
+        eta = oracle.observed_field_angles(ws)
+        pr = oracle.problem_from_world(ws, eta, state="start")
+        gomp.omp_set_num_threads(nt)
+        t0 = time.perf_counter()
+        pr.iterate(s_ref=ws.src_true)
+        dt = time.perf_counter() - t0
+        gomp.omp_set_num_threads(threads)
+        out[nt] = (ws.n_obs / dt, ws.n_obs, ws.src_true.shape[0], ws.n_att, dt, nd)
+        log_fn(f"cpu baseline: {nt} threads, {nd} days ({ws.n_obs} obs, {ws.src_true.shape[0]} sources), "
+               f"{dt:.1f} s, {ws.n_obs / dt:.3g} obs/s")
+    model, ram = host_description()
+    v, n_obs, n_src, n_att, dt, nd = out[threads]
+    v1, n1, s1, a1, dt1, nd1 = out[1]
+    return {"value": v, "unit": "obs/s", "cores": threads, "kind": "oracle",
+            "sample": f"one S[AC] + frame iteration of the oracle over the observations of {nd} whole days in mid-"
+                      f"mission ({n_obs} obs, {n_src} sources, {n_att} attitude coefficients), {dt:.1f} s",
+            "one_thread": {"value": v1, "sample": f"{nd1} day(s): {n1} obs, {s1} sources, {dt1:.1f} s"},
+            "cpu_model": model, "host_ram_gib": ram}
 
 
 def main():
@@ -131,9 +192,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="gaia1")
+    ap.add_argument("--workload", default="gaia5",
+                    help="gaia5: 2M sources, 5 yr, robust (the largest single-GPU configuration); gaia1: 1M "
+                         "sources, 1 yr")
     ap.add_argument("--seg-len", type=int, default=None)
-    ap.add_argument("--cpu-frac", type=float, default=0.2)
+    ap.add_argument("--cpu-days", type=int, default=24, help="days of observations the oracle iterates over "
+                                                            "(all threads of the host share)")
+    ap.add_argument("--cpu-days-1t", type=int, default=3, help="... and on one thread")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="mixed: FP32 partials and compensated FP32 normal-equation sums")
@@ -205,7 +270,7 @@ def main():
         step()
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} done")
-    kt = {k: [] for k in ("source_update", "ac_pass", "band_solve", "calib_solve", "frame")}
+    kt = {k: [] for k in ("source_update", "ac_pass", "band_solve", "calib_solve", "frame", "excess_noise")}
     t_start = time.perf_counter()
     for i in range(args.steps):
         step()
@@ -230,29 +295,38 @@ def main():
     st = agis.agis_iterate(ctx, 1, stats=True)[0]
     log(f"last iteration stats: S rms {st['s']['rms_update']} A defect {st['a']['defect']}")
 
-    # dominant kernel and its roofline: both observation passes are bound by
-    # FP64 arithmetic (their algorithmic HBM traffic needs ~10% of 8 TB/s)
+    # the dominant kernel (timer) and its roofline: per-unit algorithmic
+    # flops and bytes times the units one launch processes, over the
+    # launch's average device time
+    robust = bool(w.spec.robust)
     K = w.n_att - 3
-    dom = max(("ac_pass", "source_update"), key=lambda k: kavg[k])
-    if dom == "ac_pass":
-        alg_flops = AC_FLOPS_PER_OBS * w.n_obs
-        alg_bytes = AC_BYTES_PER_OBS * w.n_obs + AC_BYTES_PER_INTERVAL * K + AC_BYTES_PER_SOURCE * n_src
-    else:
-        alg_flops = S_FLOPS_PER_OBS * w.n_obs + S_FLOPS_PER_SOURCE * n_src
-        alg_bytes = S_BYTES_PER_OBS * w.n_obs + S_BYTES_PER_SOURCE * n_src + 32.0 * w.n_att
+    per_launch = {
+        "source_update": ((S_ROBUST_FLOPS_PER_OBS if robust else S_FLOPS_PER_OBS) * w.n_obs,
+                          BYTES_PER_OBS * w.n_obs + BYTES_PER_SOURCE * n_src),
+        "ac_pass": (AC_FLOPS_PER_OBS * w.n_obs,
+                    BYTES_PER_OBS * w.n_obs + BYTES_PER_SOURCE * n_src + BYTES_PER_COEF * w.n_att),
+        "excess_noise": (EPS_FLOPS_PER_OBS * w.n_obs, BYTES_PER_OBS * w.n_obs + BYTES_PER_SOURCE * n_src),
+    }
+    dom = max((k for k in per_launch if kavg[k] > 0), key=lambda k: kavg[k])
+    alg_flops, alg_bytes = per_launch[dom]
     sec = kavg[dom] * 1e-3
     tfs = alg_flops / sec / 1e12
-    traffic = measured_traffic(dom, wname, args.precision)
-    roofline = {"kernel": dom, "bound": "alu", "achieved": round(tfs, 2), "peak": FP64_PEAK_TFLOPS,
+    sym = "source_update_robust" if dom == "source_update" and robust else dom
+    traffic = measured_traffic(sym, wname, args.precision)
+    roofline = {"kernel": sym, "bound": "alu", "achieved": round(tfs, 2), "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(tfs / FP64_PEAK_TFLOPS, 4), "traffic": traffic,
                 "alg_flops_per_launch": alg_flops, "alg_bytes_per_launch": alg_bytes,
                 "alg_hbm_GBs": round(alg_bytes / sec / 1e9, 1),
-                "alg_hbm_frac": round(alg_bytes / sec / 1e9 / HBM_PEAK_GBS, 4), "avg_ms": kavg[dom]}
+                "alg_hbm_frac": round(alg_bytes / sec / 1e9 / HBM_PEAK_GBS, 4), "avg_ms": kavg[dom],
+                "per_kernel_frac": {k: round(f / (kavg[k] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)
+                                    for k, (f, _) in per_launch.items() if kavg[k] > 0}}
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, args.cpu_frac, log)
-        log(f"cpu baseline {cpu['value']:.3g} obs/s on {cpu['cores']} threads")
+        agis.agis_destroy(ctx)
+        ctx = None
+        del eta_obs
+        cpu = cpu_baseline(w, args.cpu_days, args.cpu_days_1t, log)
 
     out = {"metric": "obs/s per AGIS iteration", "value": value, "unit": "obs/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
@@ -263,7 +337,8 @@ def main():
            "kernel_ms": kavg, "roofline": roofline,
            "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
-    agis.agis_destroy(ctx)
+    if ctx is not None:
+        agis.agis_destroy(ctx)
 
 
 if __name__ == "__main__":

@@ -78,12 +78,16 @@ typedef struct agis_ctx agis_ctx_t;
  *                context then creates its own default-priority stream).
  *   robust     : 0 = statistical weights W = 1/sigma^2; 1 = robust weighting
  *                (Sect. 5.1.2, 5.2.5): W = w(z)/sigma~^2 with the downweighting
- *                function w of eq:dw and sigma~^2 = sigma^2 + eps_a^2(t); the
- *                source update runs the inner iteration (initial downweights
- *                from half the intersextile range of the source's residuals,
- *                then four solves; excess source noise 0); the excess
- *                attitude noise eps_a (eq e09, 68th percentile of R^2 -
- *                sigma^2) is re-estimated per bucket after every source
+ *                function w of eq:dw and sigma~^2 = sigma^2 + eps_a^2(t) of
+ *                the attitude component the record measures (Sect. 3.6:
+ *                along scan, across scan in the preceding or in the
+ *                following field of view); the source update runs the inner
+ *                iteration (initial downweights from half the intersextile
+ *                range of the source's residuals of the record's kind,
+ *                along or across scan, then four solves; excess source
+ *                noise 0); the excess attitude noise eps_a (eq e09, 68th
+ *                percentile of R^2 - sigma^2 over a component's records) is
+ *                re-estimated per component and bucket after every source
  *                update and used by the attitude and calibration weights.
  *                2 = as 1 plus the excess source noise eps_i (Sect. 5.1.2):
  *                each round of the inner iteration fixes its w_l and solves
@@ -256,17 +260,20 @@ int agis_problem_size(const agis_ctx_t* ctx, int64_t* n_obs, int64_t* n_src, int
                       int64_t* n_segments);
 
 /* Device time [ms] of the last launch of each hot kernel, measured with
- * HIP events on the context stream: [0] source update, [1] attitude and
- * calibration accumulation, [2] band solve, [3] calibration solve,
- * [4] frame rotator.  In the robust mode [0] covers the three kernels of
- * the source inner iteration and [1] the residual pass, the eps_a
- * estimate and the accumulation. */
-int agis_kernel_times(const agis_ctx_t* ctx, double ms[5]);
+ * HIP events on the context stream: [0] source update (in the robust mode
+ * every launch of the inner iteration), [1] attitude and calibration
+ * accumulation, [2] band solve, [3] calibration solve, [4] frame rotator,
+ * [5] excess attitude noise estimate (robust mode; 0 otherwise). */
+int agis_kernel_times(const agis_ctx_t* ctx, double ms[6]);
 
-/* Excess attitude noise (robust mode): eps_a^2 [rad^2] of each bucket of
- * eps_bucket knot intervals, n = ceil((N - 3) / eps_bucket).  Set before an
- * update to impose values; read after one to inspect the estimate.
- * AGIS_E_STATE when the context is not robust; AGIS_E_SHAPE when n differs. */
+/* Excess attitude noise (robust mode): eps_a^2 [rad^2] per attitude
+ * component and bucket of eps_bucket knot intervals, component-major: the
+ * n_b = ceil((N - 3) / eps_bucket) buckets of the along-scan component, then
+ * those of across scan in the preceding field of view (fov +1), then those of
+ * the following one (fov -1); n = 3 n_b.  A component without records in a
+ * bucket estimates 0 there.  Set before an update to impose values; read
+ * after one to inspect the estimate.  AGIS_E_STATE when the context is not
+ * robust; AGIS_E_SHAPE when n differs. */
 int agis_set_excess_noise(agis_ctx_t* ctx, int64_t n, const double* eps_a2, int where);
 int agis_get_excess_noise(agis_ctx_t* ctx, int64_t n, double* eps_a2, int where);
 /* Re-estimate eps_a^2 per bucket from the residuals at the current

@@ -460,9 +460,9 @@ def agis_problem_size(ctx):
 
 
 def agis_kernel_times(ctx):
-    ms = (c_d * 5)()
+    ms = (c_d * 6)()
     _check(_lib.agis_kernel_times(ctx, ms), ctx)
-    return dict(zip(["source_update", "ac_pass", "band_solve", "calib_solve", "frame"], ms[:]))
+    return dict(zip(["source_update", "ac_pass", "band_solve", "calib_solve", "frame", "excess_noise"], ms[:]))
 
 
 class Solver:

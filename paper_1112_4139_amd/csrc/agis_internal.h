@@ -28,6 +28,14 @@ constexpr int IV_SUMS = IV_PAIRS * 10 + 16;
 // calibration partial sums per interval: (sum W, sum W R) for fov +1 and -1
 constexpr int IV_CAL = 4;
 
+// A class of sources of the robust S block handled by the one-kernel path:
+// positions [k0, k1) of the count-ordered launch, each with at most cap
+// observations, blocks of nt threads.
+struct SClass {
+    int64_t k0, k1;
+    int cap, nt;
+};
+
 struct Timers {
     hipEvent_t ev[10][2];
     bool valid[10];
@@ -112,10 +120,23 @@ struct agis_ctx {
     // also holds R^2 - sigma^2 in time order for the eps_a estimate)
     int64_t n_buckets = 0;
     double* eps_a2 = nullptr;            // [n_buckets]
-    double* vs = nullptr;                // [n_src]
+    double* vs = nullptr;                // [n_src][2]: along, across scan
     double* src_eps2 = nullptr;          // [n_src] robust mode 2: excess source noise eps_i^2 of the last S update
     double* src_D = nullptr;             // [n_src] ... and its significance D
-    double* rcol = nullptr;              // [6][n_obs]
+    double* rcol = nullptr;              // [6][n_obs] (only when some source or bucket needs the HBM path)
+    // one-kernel robust paths (robust mode 1): the classes of the S block,
+    // the leading launch positions that keep the three-kernel path (more
+    // observations than the LDS holds), and whether the excess-noise
+    // estimate runs in one kernel (every bucket fits the LDS)
+    std::vector<agis::SClass> s_classes;
+    int64_t s_fallback = 0;
+    int64_t eps_cap = 0;
+    bool eps_fused = false;
+    int robust_s_mode = 1;               // robust S block: 0 rows, varsigma and solves through HBM columns;
+                                         // 1 rows to HBM columns, then varsigma and solves per source in
+                                         // LDS; 2 the whole block per source in LDS (no HBM columns)
+    bool robust_fused_eps = true;        // the excess-noise estimate in one kernel (values in LDS)
+    int64_t robust_max_cap = INT64_MAX;  // largest source class of the one-kernel S path
 
     // learned extrapolation: update histories (rings of four), MLP weights
     // (FP32 master, BF16-rounded copy, Adam moments, gradient + loss) for
@@ -168,7 +189,7 @@ struct agis_ctx {
     int64_t select_reg_min_mean = 256;      // ... in the register kernel from this mean set size
 
     agis::Timers tm;
-    double last_ms[5] = {0, 0, 0, 0, 0};
+    double last_ms[6] = {0, 0, 0, 0, 0, 0};
     bool timing = true;                      // per-block HIP events (off inside a graph capture)
 
     // one captured iteration; rebuilt when gen (bumped by every call that
@@ -224,6 +245,10 @@ void launch_cg_quad(agis_ctx* ctx, const double* p, double* part, double* out);
 void launch_cg_direction(agis_ctx* ctx, double beta);
 // robust.hip
 void launch_source_update_robust(agis_ctx* ctx);
+// plan of the robust kernels from the per-source offsets and the launch
+// order (host copies); tells whether the HBM columns are needed
+int robust_plan(agis_ctx* ctx, const std::vector<int64_t>& h_off, const std::vector<int32_t>& order,
+                bool* need_columns);
 void launch_excess_noise(agis_ctx* ctx);
 void launch_freeze_sigma(agis_ctx* ctx);
 void launch_ac_pass(agis_ctx* ctx);

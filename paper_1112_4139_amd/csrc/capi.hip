@@ -103,6 +103,10 @@ static void free_store(agis_ctx* ctx) {
     dfree(ctx->src_eps2);
     dfree(ctx->src_D);
     dfree(ctx->rcol);
+    ctx->s_classes.clear();
+    ctx->s_fallback = 0;
+    ctx->eps_cap = 0;
+    ctx->eps_fused = false;
     dfree(ctx->lh_anchor_s);
     dfree(ctx->lh_ring_s);
     dfree(ctx->lh_anchor_a);
@@ -297,10 +301,22 @@ extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
     build_segments(ctx);
     if (cfg->robust) {
         ctx->n_buckets = (ctx->K + cfg->eps_bucket - 1) / cfg->eps_bucket;
+        k.n_buckets = ctx->n_buckets;
     }
     if (const char* e = std::getenv("AGIS_S_GROUP")) ctx->s_group = std::atoi(e);
     if (const char* e = std::getenv("AGIS_SELECT_REG_LIMIT")) ctx->select_reg_limit = std::atoll(e);
     if (const char* e = std::getenv("AGIS_SELECT_REG_MIN_MEAN")) ctx->select_reg_min_mean = std::atoll(e);
+    // robust kernel paths: AGIS_ROBUST_FUSED = 0 (every step through HBM
+    // columns), 1 (the excess-noise estimate in one kernel, the S block's
+    // varsigma and solves per source in LDS from the HBM rows; the default),
+    // 2 (the whole S block per source in LDS), 3 (the excess-noise estimate
+    // in one kernel, the S block through HBM columns)
+    if (const char* e = std::getenv("AGIS_ROBUST_FUSED")) {
+        const int v = std::atoi(e);
+        ctx->robust_fused_eps = v >= 1;
+        ctx->robust_s_mode = v == 1 ? 1 : (v == 2 ? 2 : 0);
+    }
+    if (const char* e = std::getenv("AGIS_ROBUST_MAX_CAP")) ctx->robust_max_cap = std::atoll(e);
     int rc = AGIS_OK;
     auto fail = [&](int code) {
         g_create_error = ctx->err;
@@ -338,8 +354,9 @@ extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
         }
     }
     if (ctx->n_buckets > 0) {
-        if ((rc = dalloc(ctx, &ctx->eps_a2, ctx->n_buckets, "excess attitude noise")) != AGIS_OK) return fail(rc);
-        const std::vector<double> e0(ctx->n_buckets, cfg->eps_a_init * cfg->eps_a_init);
+        // three excess-noise functions (AL, ACP, ACF), n_buckets each
+        if ((rc = dalloc(ctx, &ctx->eps_a2, 3 * ctx->n_buckets, "excess attitude noise")) != AGIS_OK) return fail(rc);
+        const std::vector<double> e0(3 * ctx->n_buckets, cfg->eps_a_init * cfg->eps_a_init);
         if (hipMemcpy(ctx->eps_a2, e0.data(), e0.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
             ctx->err = "initial copies failed";
             return fail(AGIS_E_DEVICE);
@@ -459,18 +476,24 @@ extern "C" int agis_load_observations(agis_ctx_t* ctx, const agis_obs_soa_t* obs
         HIPCHK(hipMemcpyAsync(ctx->src_order, order.data(), n_src * sizeof(int32_t), hipMemcpyHostToDevice,
                               ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
+        bool need_columns = true;
+        if (ctx->cfg.robust) {
+            int prc = robust_plan(ctx, h_off, order, &need_columns);
+            if (prc != AGIS_OK) return prc;
+        }
+        if (ctx->cfg.robust && need_columns)
+            ALLOC(ctx->rcol, 6 * std::max<int64_t>(ctx->n_obs, 1), "robust columns");
     }
     if (ctx->cfg.robust) {
         // the inner iteration's by-source columns (A, h, sigma~^2), also
         // used for R^2 - sigma^2 by the excess-noise estimate
-        ALLOC(ctx->vs, n_src, "source varsigma");
+        ALLOC(ctx->vs, 2 * n_src, "source varsigma per kind");
         if (ctx->cfg.robust == 2) {
             ALLOC(ctx->src_eps2, std::max<int64_t>(n_src, 1), "excess source noise");
             ALLOC(ctx->src_D, std::max<int64_t>(n_src, 1), "excess source noise significance");
             HIPCHK(hipMemsetAsync(ctx->src_eps2, 0, std::max<int64_t>(n_src, 1) * sizeof(double), ctx->stream));
             HIPCHK(hipMemsetAsync(ctx->src_D, 0, std::max<int64_t>(n_src, 1) * sizeof(double), ctx->stream));
         }
-        ALLOC(ctx->rcol, 6 * std::max<int64_t>(ctx->n_obs, 1), "robust columns");
     }
     launch_prep_sources(ctx);
     HIPCHK(hipGetLastError());
@@ -540,7 +563,7 @@ extern "C" int agis_get_calibration(agis_ctx_t* ctx, int64_t n, double* c, int w
 }
 
 // --- timing and statistics helpers -----------------------------------------
-enum { T_S = 0, T_AC = 1, T_BAND = 2, T_CAL = 3, T_FRAME = 4, T_ITER = 5 };
+enum { T_S = 0, T_AC = 1, T_BAND = 2, T_CAL = 3, T_FRAME = 4, T_EPS = 5, T_ITER = 6 };
 
 static void tstart(agis_ctx* ctx, int e) {
     if (ctx->timing) (void)hipEventRecord(ctx->tm.ev[e][0], ctx->stream);
@@ -592,8 +615,12 @@ static int run_source(agis_ctx* ctx) {
 // and dc; rc (optional) receives the calibration right-hand sides.
 static int run_ac(agis_ctx* ctx, bool do_a, bool do_c, bool eps_update = false, bool apply = true,
                   double* rc = nullptr) {
+    if (eps_update && robust_now(ctx)) {
+        tstart(ctx, T_EPS);
+        launch_excess_noise(ctx);
+        tstop(ctx, T_EPS);
+    }
     tstart(ctx, T_AC);
-    if (eps_update && robust_now(ctx)) launch_excess_noise(ctx);
     launch_ac_pass(ctx);
     HIPCHK(hipGetLastError());
     tstop(ctx, T_AC);
@@ -782,6 +809,7 @@ extern "C" int agis_iterate(agis_ctx_t* ctx, int32_t n_iter, agis_iter_stats_t* 
     ctx->last_ms[2] = tget(ctx, T_BAND);
     ctx->last_ms[3] = tget(ctx, T_CAL);
     ctx->last_ms[4] = tget(ctx, T_FRAME);
+    ctx->last_ms[5] = robust_now(ctx) ? tget(ctx, T_EPS) : 0.0;
     return AGIS_OK;
 }
 
@@ -890,7 +918,7 @@ extern "C" int agis_set_excess_noise(agis_ctx_t* ctx, int64_t n, const double* e
     CHECK_CTX();
     ++ctx->xver;
     if (!ctx->cfg.robust) return set_error(ctx, AGIS_E_STATE, "the context is not robust");
-    if (n != ctx->n_buckets || !eps_a2) return set_error(ctx, AGIS_E_SHAPE, "bucket count mismatch");
+    if (n != 3 * ctx->n_buckets || !eps_a2) return set_error(ctx, AGIS_E_SHAPE, "bucket count mismatch");
     int rc = check_finite_host(ctx, eps_a2, n, where);
     if (rc) return rc;
     return copy_in(ctx, ctx->eps_a2, eps_a2, n * sizeof(double), where);
@@ -909,7 +937,7 @@ extern "C" int agis_get_source_noise(agis_ctx_t* ctx, int64_t n, double* eps_i2,
 extern "C" int agis_get_excess_noise(agis_ctx_t* ctx, int64_t n, double* eps_a2, int where) {
     CHECK_CTX();
     if (!ctx->cfg.robust) return set_error(ctx, AGIS_E_STATE, "the context is not robust");
-    if (n != ctx->n_buckets || !eps_a2) return set_error(ctx, AGIS_E_SHAPE, "bucket count mismatch");
+    if (n != 3 * ctx->n_buckets || !eps_a2) return set_error(ctx, AGIS_E_SHAPE, "bucket count mismatch");
     return copy_out(ctx, eps_a2, ctx->eps_a2, n * sizeof(double), where);
 }
 
@@ -966,7 +994,7 @@ static int learned_alloc_all(agis_ctx* ctx) {
         ALLOC(ctx->bk_s[k], 5 * ns, "candidate backup");
         ALLOC(ctx->bk_a[k], 4 * na, "candidate backup");
         ALLOC(ctx->bk_c[k], std::max<int64_t>(ctx->n_cells, 1), "candidate backup");
-        ALLOC(ctx->bk_e[k], std::max<int64_t>(ctx->n_buckets, 1), "candidate backup");
+        ALLOC(ctx->bk_e[k], std::max<int64_t>(3 * ctx->n_buckets, 1), "candidate backup");
     }
     ALLOC(ctx->chi2_part, std::max<int64_t>((ctx->K + 63) / 64, 1), "chi2 partials");
     ALLOC(ctx->chi2_out, 2, "chi2");
@@ -1232,14 +1260,14 @@ static void save_state(agis_ctx* ctx, int k) {
     launch_copy(ctx, 5 * ctx->n_src, ctx->s, ctx->bk_s[k]);
     launch_copy(ctx, 4 * ctx->N, ctx->a, ctx->bk_a[k]);
     launch_copy(ctx, ctx->n_cells, ctx->c, ctx->bk_c[k]);
-    if (ctx->cfg.robust) launch_copy(ctx, ctx->n_buckets, ctx->eps_a2, ctx->bk_e[k]);
+    if (ctx->cfg.robust) launch_copy(ctx, 3 * ctx->n_buckets, ctx->eps_a2, ctx->bk_e[k]);
 }
 
 static void restore_state(agis_ctx* ctx, int k) {
     launch_copy(ctx, 5 * ctx->n_src, ctx->bk_s[k], ctx->s);
     launch_copy(ctx, 4 * ctx->N, ctx->bk_a[k], ctx->a);
     launch_copy(ctx, ctx->n_cells, ctx->bk_c[k], ctx->c);
-    if (ctx->cfg.robust) launch_copy(ctx, ctx->n_buckets, ctx->bk_e[k], ctx->eps_a2);
+    if (ctx->cfg.robust) launch_copy(ctx, 3 * ctx->n_buckets, ctx->bk_e[k], ctx->eps_a2);
     launch_prep_sources(ctx);
 }
 
@@ -1549,8 +1577,8 @@ extern "C" int agis_problem_size(const agis_ctx_t* ctx, int64_t* n_obs, int64_t*
     return AGIS_OK;
 }
 
-extern "C" int agis_kernel_times(const agis_ctx_t* ctx, double ms[5]) {
+extern "C" int agis_kernel_times(const agis_ctx_t* ctx, double ms[6]) {
     if (!ctx || !ms) return AGIS_E_INVALID_ARG;
-    for (int e = 0; e < 5; ++e) ms[e] = ctx->last_ms[e];
+    for (int e = 0; e < 6; ++e) ms[e] = ctx->last_ms[e];
     return AGIS_OK;
 }

@@ -253,8 +253,8 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
     const double lam2 = k.lam2;
     const int64_t l0 = valid ? iv_off[j] : 0, l1 = valid ? iv_off[j + 1] : 0;
     const KnotTab kt = valid ? ktab[j] : KnotTab{0.0, 1.0, 0.0, 0.0};
-    // robust: sigma~^2 = sigma^2 + eps_a^2 of the interval's bucket (eq:W)
-    const double eps2 = (valid && robust) ? eps_a2[j / eps_bucket] : 0.0;
+    // robust: sigma~^2 = sigma^2 + eps_a^2 of the record's component in the
+    // interval's bucket (eq:W)
     XT (*xw)[AC_XS] = xb[wv];
     const int ri = lane & 15, rk = lane >> 4;
     double4_t C = {0.0, 0.0, 0.0, 0.0};
@@ -310,7 +310,7 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
             double W;
             if (robust) {
                 // robust mode 2: plus the source's excess noise eps_i^2 (eq:W)
-                const double s2 = sg * sg + eps2 + (robust == 2 ? sp_c.pad : 0.0);
+                const double s2 = sg * sg + eps_a2[eps_slot(k, cf_c, j, eps_bucket)] + (robust == 2 ? sp_c.pad : 0.0);
                 W = h_c ? down_weight(o.R / sqrt(s2)) / s2 : 0.0;
             } else {
                 W = h_c ? rcp_nr(sg * sg) : 0.0;

@@ -24,7 +24,17 @@ struct DevConsts {
     double cos_half_gamma, sin_half_gamma;   // rounded cos, sin of Gamma_c / 2
     double half_gamma_err;                   // Gamma_c/2 - atan2(sin_half_gamma, cos_half_gamma)
     int32_t ac_cf0;                          // 2 n_cells: cell/fov codes from here on are across scan
+    int64_t n_buckets;                       // excess-noise buckets per component (robust)
 };
+
+// Slot in the excess attitude noise array of a record with cell/fov code
+// cf in knot interval j: the component (0 along scan, 1 across scan in the
+// preceding, 2 in the following field of view) times the buckets per
+// component, plus the interval's bucket.
+__device__ __forceinline__ int64_t eps_slot(const DevConsts& k, int32_t cf, int64_t j, int eps_bucket) {
+    const int64_t comp = cf >= k.ac_cf0 ? 1 + (cf & 1) : 0;
+    return comp * k.n_buckets + j / eps_bucket;
+}
 
 // Source data gathered per observation by the time-ordered pass: barycentric
 // direction r at t_ep, proper-motion vector p mu_a* + q mu_d, parallax.

@@ -85,15 +85,39 @@ __device__ __forceinline__ void radix_digit(const uint32_t* hist, int64_t k, int
     below_out = __shfl(below, src, 64);
 }
 
-// k-th smallest (0-based, k < n) of v[0..n) by the whole 64-thread block,
-// reading v on every pass (any n).
-__device__ double block_select(const double* __restrict__ v, int64_t n, int64_t k, uint32_t* hist) {
+// Every element selected (the sets without a filter).
+struct AllOf {
+    __device__ bool operator()(int64_t) const { return true; }
+};
+
+// Elements whose cell/fov code belongs to one excess-noise component (0
+// along scan, 1 across scan preceding, 2 following field of view) or, with
+// kind_only, to one kind of record (0 along scan, 1 across scan).  Without
+// codes (cf null) every element is along scan.
+struct OfComponent {
+    const int32_t* cf;
+    int32_t ac_cf0;
+    int comp;
+    bool kind_only;
+    __device__ bool operator()(int64_t i) const {
+        if (!cf) return comp == 0;
+        const int32_t c = cf[i];
+        const int k = c >= ac_cf0 ? 1 + (c & 1) : 0;
+        return kind_only ? (k > 0) == (comp > 0) : k == comp;
+    }
+};
+
+// k-th smallest (0-based) of the elements i of v[0..n) with sel(i), by the
+// whole 64-thread block, reading v on every pass (any n).
+template <class Sel>
+__device__ double block_select(const double* __restrict__ v, int64_t n, int64_t k, uint32_t* hist, Sel sel) {
     const int lane = threadIdx.x;
     uint64_t prefix = 0, mask = 0;
     for (int shift = 56; shift >= 0; shift -= 8) {
         for (int b = lane; b < 256; b += 64) hist[b] = 0u;
         __syncthreads();
         for (int64_t i = lane; i < n; i += 64) {
+            if (!sel(i)) continue;
             const uint64_t kk = order_key(v[i]);
             if ((kk & mask) == prefix) atomicAdd(&hist[(kk >> shift) & 255u], 1u);
         }
@@ -109,25 +133,45 @@ __device__ double block_select(const double* __restrict__ v, int64_t n, int64_t 
     return key_value(prefix);
 }
 
-// p-quantile by linear interpolation between the order statistics at
-// (n - 1) p (type 7); 0 for n = 0.
-__device__ double block_quantile7(const double* __restrict__ v, int64_t n, double p, uint32_t* hist) {
-    if (n <= 0) return 0.0;
-    const double h = (double)(n - 1) * p;
+// p-quantile of the m selected elements (sel) of v[0..n) by linear
+// interpolation between the order statistics at (m - 1) p (type 7); 0 for
+// m = 0.
+template <class Sel>
+__device__ double block_quantile7(const double* __restrict__ v, int64_t n, int64_t m, double p, uint32_t* hist,
+                                  Sel sel) {
+    if (m <= 0) return 0.0;
+    const double h = (double)(m - 1) * p;
     const int64_t j = (int64_t)floor(h);
-    const double xj = block_select(v, n, j, hist);
-    if (j + 1 >= n) return xj;
-    const double xj1 = block_select(v, n, j + 1, hist);
+    const double xj = block_select(v, n, j, hist, sel);
+    if (j + 1 >= m) return xj;
+    const double xj1 = block_select(v, n, j + 1, hist, sel);
     return xj + (h - (double)j) * (xj1 - xj);
+}
+
+// Number of the elements i of [0, n) with sel(i), summed over the 64-thread
+// block (every thread receives it).
+template <class Sel>
+__device__ int64_t block_count(int64_t n, Sel sel) {
+    int64_t c = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 64) c += sel(i) ? 1 : 0;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+    return c;
 }
 
 // Keys held in registers: key r of lane l is element l + 64 r (n <= 64 KR).
 constexpr int KR = 32;
 
-__device__ __forceinline__ void load_keys(const double* __restrict__ v, int64_t n, uint64_t (&kr)[KR]) {
+// Elements not selected (sel) get the largest key, above every finite
+// value: they sort after the m selected ones, which the ranks address.
+template <class Sel>
+__device__ __forceinline__ void load_keys(const double* __restrict__ v, int64_t n, uint64_t (&kr)[KR], Sel sel) {
     const int lane = threadIdx.x;
 #pragma unroll
-    for (int r = 0; r < KR; ++r) kr[r] = lane + 64 * r < n ? order_key(v[lane + 64 * r]) : ~0ull;
+    for (int r = 0; r < KR; ++r) {
+        const int64_t i = lane + 64 * r;
+        kr[r] = (i < n && sel(i)) ? order_key(v[i]) : ~0ull;
+    }
 }
 
 // k-th smallest key of the n register-held keys.  Where every active lane
@@ -168,17 +212,18 @@ __device__ uint64_t reg_select(const uint64_t (&kr)[KR], int64_t n, int64_t k, u
     return prefix;
 }
 
-// Type-7 p-quantile of the n register-held keys: the order statistic j by
-// selection, j + 1 as the same key if more than j + 1 keys are <= it, else
-// as the smallest key above it.
-__device__ double reg_quantile7(const uint64_t (&kr)[KR], int64_t n, double p, uint32_t* hist) {
-    if (n <= 0) return 0.0;
+// Type-7 p-quantile of the m selected keys among the n register-held ones
+// (the others hold the largest key): the order statistic j by selection,
+// j + 1 as the same key if more than j + 1 keys are <= it, else as the
+// smallest key above it.
+__device__ double reg_quantile7(const uint64_t (&kr)[KR], int64_t n, int64_t m, double p, uint32_t* hist) {
+    if (m <= 0) return 0.0;
     const int lane = threadIdx.x;
-    const double h = (double)(n - 1) * p;
+    const double h = (double)(m - 1) * p;
     const int64_t j = (int64_t)floor(h);
     const uint64_t kj = reg_select(kr, n, j, hist);
     const double xj = key_value(kj);
-    if (j + 1 >= n) return xj;
+    if (j + 1 >= m) return xj;
     uint32_t cle = 0;
     uint64_t mn = ~0ull;
 #pragma unroll
@@ -228,44 +273,129 @@ __global__ __launch_bounds__(256, 2) void k_s_rows(DevConsts k, int64_t n_src, c
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) mu[cc] = p[cc] * pma + q[cc] * pmd;
     const int64_t l1 = off[i + 1];
-    for (int64_t l = off[i] + gl; l < l1; l += G) {
-        const int32_t ell = oell[l];
-        const double sg = (double)osig[l];
+    int64_t l = off[i] + gl;
+    // Current observation with its gathers (attitude coefficients, interval
+    // table entry, calibration, excess noise); the next observation's
+    // columns load at the top of an iteration, its gathers after the
+    // current one has been evaluated.
+    double t_c = 0.0, e_c = 0.0, cal_c = 0.0, ea_c = 0.0;
+    float s_c = 1.0f;
+    int32_t ell_c = 3, cf_c = 0;
+    double a_c[16];
+    KnotTab kt_c = {0.0, 1.0, 0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < 16; ++e) a_c[e] = 0.0;
+    if (l < l1) {
+        t_c = ot[l];
+        e_c = oeta[l];
+        s_c = osig[l];
+        ell_c = oell[l];
+        cf_c = ocell[l];
+        cal_c = c[cf_c >> 1];
+        ea_c = eps_a2[eps_slot(k, cf_c, ell_c - 3, eps_bucket)];
+        const double* a4 = a + 4 * (ell_c - 3);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) a_c[e] = a4[e];
+        kt_c = ktab[ell_c - 3];
+    }
+    for (; l < l1; l += G) {
+        const int64_t ln = l + G;
+        const bool more = ln < l1;
+        double t_n = 0.0, e_n = 0.0;
+        float s_n = 1.0f;
+        int32_t cf_n = 0, ell_n = 3;
+        if (more) {
+            t_n = ot[ln];
+            e_n = oeta[ln];
+            s_n = osig[ln];
+            cf_n = ocell[ln];
+            ell_n = oell[ln];
+        }
+        const bool ac = cf_c >= k.ac_cf0;
         ObsEval o;
-        observe(k, ot[l], oeta[l], c[ocell[l] >> 1], r, mu, plx, a + 4 * (ell - 3), knots + (ell - 2),
-                ktab[ell - 3], o);
+        observe(k, t_c, e_c, cal_c, r, mu, plx, a_c, knots + (ell_c - 2), kt_c, o, ac);
         double A[5];
-        source_partials(o, p, q, r, A);
+        source_partials(o, p, q, r, A, ac);
+        const double sg = (double)s_c;
 #pragma unroll
         for (int e = 0; e < 3; ++e) col[e * n_obs + l] = A[e];
         col[3 * n_obs + l] = o.tau;              // A[3] = A[0] tau, A[4] = A[1] tau
         col[4 * n_obs + l] = o.R;
-        col[5 * n_obs + l] = sg * sg + eps_a2[(ell - 3) / eps_bucket];
+        col[5 * n_obs + l] = sg * sg + ea_c;
+        if (more) {
+            const double* a4 = a + 4 * (ell_n - 3);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) a_c[e] = a4[e];
+            kt_c = ktab[ell_n - 3];
+            cal_c = c[cf_n >> 1];
+            ea_c = eps_a2[eps_slot(k, cf_n, ell_n - 3, eps_bucket)];
+        }
+        t_c = t_n;
+        e_c = e_n;
+        s_c = s_n;
+        cf_c = cf_n;
+        ell_c = ell_n;
     }
 }
 
 // ------------------------------------------------ S, initial downweights
 // REG: keys of sets up to reg_limit in registers (fewer wavefronts per SIMD,
 // pays for large sets); otherwise re-read on every pass (small sets).
-template <bool REG>
+// varsigma of one kind of a source's records: half the intersextile range
+// of the selected (sel) h of the n; m of them are selected.
+template <bool REG, class Sel>
+__device__ double half_intersextile(const double* __restrict__ h, int64_t n, int64_t m, int64_t reg_limit,
+                                    uint32_t* hist, Sel sel) {
+    double q5, q1;
+    if (REG && n <= reg_limit) {
+        uint64_t kr[KR];
+        load_keys(h, n, kr, sel);
+        q5 = reg_quantile7(kr, n, m, 5.0 / 6.0, hist);
+        q1 = reg_quantile7(kr, n, m, 1.0 / 6.0, hist);
+    } else {
+        q5 = block_quantile7(h, n, m, 5.0 / 6.0, hist, sel);
+        q1 = block_quantile7(h, n, m, 1.0 / 6.0, hist, sel);
+    }
+    return 0.5 * (q5 - q1);
+}
+
+// vs[2 i + kind]: varsigma_i of the along-scan (kind 0) and the across-scan
+// (kind 1) records of source i, whose residual scales differ by the ratio of
+// their formal errors.  cell: the records' cell/fov codes in source order,
+// or null where every record is along scan (AC false; vs[2 i + 1] = 0 then).
+template <bool REG, bool AC>
 __global__ __launch_bounds__(64) void k_s_sigma(int64_t n_src, const int64_t* __restrict__ off,
                                                 const double* __restrict__ h, double* __restrict__ vs,
-                                                int64_t reg_limit, const int32_t* __restrict__ order) {
+                                                int64_t reg_limit, const int32_t* __restrict__ order,
+                                                const int32_t* __restrict__ cell, int32_t ac_cf0) {
     __shared__ uint32_t hist[256];
     if ((int64_t)blockIdx.x >= n_src) return;
     const int64_t i = order[blockIdx.x];         // the largest sets first
     const int64_t l0 = off[i], n = off[i + 1] - l0;
-    double q5, q1;
-    if (REG && n <= reg_limit) {
-        uint64_t kr[KR];
-        load_keys(h + l0, n, kr);
-        q5 = reg_quantile7(kr, n, 5.0 / 6.0, hist);
-        q1 = reg_quantile7(kr, n, 1.0 / 6.0, hist);
-    } else {
-        q5 = block_quantile7(h + l0, n, 5.0 / 6.0, hist);
-        q1 = block_quantile7(h + l0, n, 1.0 / 6.0, hist);
+    if (!AC) {
+        const double v = half_intersextile<REG>(h + l0, n, n, reg_limit, hist, AllOf{});
+        if (threadIdx.x == 0) {
+            vs[2 * i] = v;
+            vs[2 * i + 1] = 0.0;
+        }
+        return;
     }
-    if (threadIdx.x == 0) vs[i] = 0.5 * (q5 - q1);
+    const int32_t* cf = cell + l0;
+    const int64_t m_ac = block_count(n, OfComponent{cf, ac_cf0, 1, true});
+    for (int kind = 0; kind < 2; ++kind) {
+        const int64_t m = kind ? m_ac : n - m_ac;
+        const double v = m > 0 ? half_intersextile<REG>(h + l0, n, m, reg_limit, hist, OfComponent{cf, ac_cf0, kind, true})
+                               : 0.0;
+        if (threadIdx.x == 0) vs[2 * i + kind] = v;
+    }
+}
+
+// Initial downweight of a record (eq:wl's first round): w(h / varsigma) of
+// the record's kind; 1 where that varsigma is 0.
+__device__ __forceinline__ double first_weight(double h, double vs0, double vs1, const int32_t* __restrict__ cell,
+                                               int32_t ac_cf0, int64_t l) {
+    const double v = (cell && cell[l] >= ac_cf0) ? vs1 : vs0;
+    return v > 0.0 ? down_weight(h / v) : 1.0;
 }
 
 // ------------------------------------------------- S, inner iteration
@@ -277,7 +407,8 @@ __global__ __launch_bounds__(256) void k_s_irls(int64_t n_src, const int64_t* __
                                                 const double* __restrict__ vs, double* __restrict__ s,
                                                 SrcPrep* __restrict__ prep, double* __restrict__ ds,
                                                 double* __restrict__ qsrc, int32_t* __restrict__ sdef,
-                                                double* __restrict__ svar, const int32_t* __restrict__ order) {
+                                                double* __restrict__ svar, const int32_t* __restrict__ order,
+                                                const int32_t* __restrict__ cell, int32_t ac_cf0) {
     constexpr int GPB = 256 / G;
     const int gl = threadIdx.x % G;
     const int leader = (threadIdx.x & 63) & ~(G - 1);
@@ -285,7 +416,7 @@ __global__ __launch_bounds__(256) void k_s_irls(int64_t n_src, const int64_t* __
     const bool valid = kg < n_src;
     const int64_t i = valid ? order[kg] : 0;
     const int64_t l0 = valid ? off[i] : 0, l1 = valid ? off[i + 1] : 0;
-    const double vsi = valid ? vs[i] : 0.0;
+    const double vs0 = valid ? vs[2 * i] : 0.0, vs1 = valid ? vs[2 * i + 1] : 0.0;
     double d[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     double acc[21];
     for (int it = 0; it < INNER_SOLVES; ++it) {
@@ -301,7 +432,7 @@ __global__ __launch_bounds__(256) void k_s_irls(int64_t n_src, const int64_t* __
             const double h = col[4 * n_obs + l], s2 = col[5 * n_obs + l];
             double wl;
             if (it == 0) {
-                wl = vsi > 0.0 ? down_weight(h / vsi) : 1.0;
+                wl = first_weight(h, vs0, vs1, cell, ac_cf0, l);
             } else {
                 double R = h;
 #pragma unroll
@@ -362,7 +493,8 @@ __global__ __launch_bounds__(256) void k_s_irls_eps(int64_t n_src, const int64_t
                                                     SrcPrep* __restrict__ prep, double* __restrict__ ds,
                                                     double* __restrict__ qsrc, int32_t* __restrict__ sdef,
                                                     double* __restrict__ svar, const int32_t* __restrict__ order,
-                                                    double* __restrict__ eps2_out, double* __restrict__ D_out) {
+                                                    double* __restrict__ eps2_out, double* __restrict__ D_out,
+                                                    const int32_t* __restrict__ cell, int32_t ac_cf0) {
     constexpr int GPB = 256 / G;
     const int gl = threadIdx.x % G;
     const int leader = (threadIdx.x & 63) & ~(G - 1);
@@ -370,14 +502,14 @@ __global__ __launch_bounds__(256) void k_s_irls_eps(int64_t n_src, const int64_t
     const bool valid = kg < n_src;
     const int64_t i = valid ? order[kg] : 0;
     const int64_t l0 = valid ? off[i] : 0, l1 = valid ? off[i + 1] : 0;
-    const double vsi = valid ? vs[i] : 0.0;
+    const double vs0 = valid ? vs[2 * i] : 0.0, vs1 = valid ? vs[2 * i + 1] : 0.0;
     double dw[5] = {0.0, 0.0, 0.0, 0.0, 0.0};      // solution the round's weights come from
     double d[5] = {0.0, 0.0, 0.0, 0.0, 0.0};       // current solution
     double y = 0.0, D = 0.0;
     double acc[21];
     // w_l of the round (it) from dw and the previous round's eps_i^2 (yw)
-    auto weight_of = [&](int it, const double* A, double h, double s2, double yw) {
-        if (it == 0) return vsi > 0.0 ? down_weight(h / vsi) : 1.0;
+    auto weight_of = [&](int it, int64_t l, const double* A, double h, double s2, double yw) {
+        if (it == 0) return first_weight(h, vs0, vs1, cell, ac_cf0, l);
         double R = h;
 #pragma unroll
         for (int e = 0; e < 5; ++e) R -= A[e] * dw[e];
@@ -402,7 +534,7 @@ __global__ __launch_bounds__(256) void k_s_irls_eps(int64_t n_src, const int64_t
             for (int64_t l = l0 + gl; l < l1; l += G) {
                 double A[5], h, s2;
                 load(l, A, h, s2);
-                const double wl = weight_of(it, A, h, s2, yw);
+                const double wl = weight_of(it, l, A, h, s2, yw);
                 no += wl < 0.2 ? 1.0 : 0.0;
                 const double W = wl / (s2 + yacc);
                 int e = 0;
@@ -440,7 +572,7 @@ __global__ __launch_bounds__(256) void k_s_irls_eps(int64_t n_src, const int64_t
             for (int64_t l = l0 + gl; l < l1; l += G) {
                 double A[5], h, s2;
                 load(l, A, h, s2);
-                const double wl = weight_of(it, A, h, s2, yw);
+                const double wl = weight_of(it, l, A, h, s2, yw);
                 double R = h;
 #pragma unroll
                 for (int e = 0; e < 5; ++e) R -= A[e] * d[e];
@@ -496,8 +628,9 @@ __global__ __launch_bounds__(64) void k_ac_resid(DevConsts k, int64_t K, const i
     const KnotTab kt = ktab[j];
     for (int64_t l = iv_off[j] + lane; l < iv_off[j + 1]; l += 64) {
         const SrcPrep sp = prep[osrc[l]];
+        const int32_t cf = ocellfov[l];
         ObsEval o;
-        observe(k, ot[l], oeta[l], c[ocellfov[l] >> 1], sp.r, sp.mu, sp.plx, a4, kn, kt, o);
+        observe(k, ot[l], oeta[l], c[cf >> 1], sp.r, sp.mu, sp.plx, a4, kn, kt, o, cf >= k.ac_cf0);
         const double sg = (double)osig[l];
         v[l] = o.R * o.R - sg * sg - (robust == 2 ? sp.pad : 0.0);       // e09 with eps_i^2 (mode 2)
     }
@@ -525,13 +658,13 @@ __global__ __launch_bounds__(64) void k_freeze_sigma(DevConsts k, int64_t K, con
     for (int e = 0; e < 16; ++e) a4[e] = a[4 * j + e];
     for (int e = 0; e < 6; ++e) kn[e] = knots[j + 1 + e];
     const KnotTab kt = ktab[j];
-    const double eps2 = eps_a2[j / eps_bucket];
     for (int64_t l = iv_off[j] + lane; l < iv_off[j + 1]; l += 64) {
         const SrcPrep sp = prep[osrc[l]];
+        const int32_t cf = ocellfov[l];
         ObsEval o;
-        observe(k, ot[l], oeta[l], c[ocellfov[l] >> 1], sp.r, sp.mu, sp.plx, a4, kn, kt, o);
+        observe(k, ot[l], oeta[l], c[cf >> 1], sp.r, sp.mu, sp.plx, a4, kn, kt, o, cf >= k.ac_cf0);
         const double sg = (double)osig[l];
-        const double s2 = sg * sg + eps2 + (robust == 2 ? sp.pad : 0.0);
+        const double s2 = sg * sg + eps_a2[eps_slot(k, cf, j, eps_bucket)] + (robust == 2 ? sp.pad : 0.0);
         const double W = down_weight(o.R / sqrt(s2)) / s2;
         float se = W > 0.0 ? (float)(1.0 / sqrt(W)) : FLT_MAX;
         if (!(se <= FLT_MAX)) se = FLT_MAX;
@@ -545,25 +678,372 @@ __global__ void k_gather_f32(int64_t n, const int32_t* __restrict__ from, const 
         dst[i] = src[from[i]];
 }
 
+// 68th percentile of the selected values among the n of v, m selected.
+template <bool REG, class Sel>
+__device__ double percentile68(const double* __restrict__ v, int64_t n, int64_t m, int64_t reg_limit, uint32_t* hist,
+                               Sel sel) {
+    if (REG && n <= reg_limit) {
+        uint64_t kr[KR];
+        load_keys(v, n, kr, sel);
+        return reg_quantile7(kr, n, m, 0.68, hist);
+    }
+    return block_quantile7(v, n, m, 0.68, hist, sel);
+}
+
+// eq e09 per component and bucket: block c n_buckets + b takes component c
+// of bucket b.  cellfov: the records' cell/fov codes in time order, or null
+// where every record is along scan (one block per bucket then, which also
+// clears the across-scan components).
 template <bool REG>
 __global__ __launch_bounds__(64) void k_bucket_eps(int64_t n_buckets, int64_t K, int eps_bucket,
                                                    const int64_t* __restrict__ iv_off, const double* __restrict__ v,
-                                                   double* __restrict__ eps_a2, int64_t reg_limit) {
+                                                   double* __restrict__ eps_a2, int64_t reg_limit,
+                                                   const int32_t* __restrict__ cellfov, int32_t ac_cf0) {
     __shared__ uint32_t hist[256];
-    const int64_t b = blockIdx.x;
-    if (b >= n_buckets) return;
+    const int comp = (int)(blockIdx.x / n_buckets);
+    const int64_t b = blockIdx.x - comp * n_buckets;
+    if (comp >= 3) return;
     const int64_t j0 = b * eps_bucket;
     const int64_t j1 = j0 + eps_bucket < K ? j0 + eps_bucket : K;
     const int64_t l0 = iv_off[j0], n = iv_off[j1] - l0;
     double q;
-    if (REG && n <= reg_limit) {
-        uint64_t kr[KR];
-        load_keys(v + l0, n, kr);
-        q = reg_quantile7(kr, n, 0.68, hist);
+    if (!cellfov) {
+        q = percentile68<REG>(v + l0, n, n, reg_limit, hist, AllOf{});
+        if (threadIdx.x == 0) eps_a2[n_buckets + b] = eps_a2[2 * n_buckets + b] = 0.0;
     } else {
-        q = block_quantile7(v + l0, n, 0.68, hist);
+        const OfComponent sel{cellfov + l0, ac_cf0, comp, false};
+        q = percentile68<REG>(v + l0, n, block_count(n, sel), reg_limit, hist, sel);
     }
-    if (threadIdx.x == 0) eps_a2[b] = q > 0.0 ? q : 0.0;
+    if (threadIdx.x == 0) eps_a2[comp * n_buckets + b] = q > 0.0 ? q : 0.0;
+}
+
+// ------------------------------------------- S block per source in LDS
+// The robust source update with a source's observations held on chip: one
+// block of NT threads per source fills six LDS columns (alpha*, delta and
+// parallax entries of the design row, tau, h and sigma~^2; cap values each)
+// -- by evaluating the model and the design row of each observation, or
+// (FROM_COL) by reading the HBM columns k_s_rows wrote -- finds varsigma from
+// the h column by a block-wide radix selection, and runs the four solves of
+// the inner iteration from LDS.  Same arithmetic per observation as k_s_rows
+// / k_s_sigma / k_s_irls; the sums are taken in another order.  Sources with
+// more than the largest cap observations keep the HBM-column kernels.
+
+// Sum over the NT threads of the block of v[0..NV), every thread receiving
+// the sums (fixed order: a butterfly in each wavefront, then the wavefronts in
+// order).  red: LDS of (NT / 64) x NV doubles; out: LDS of NV doubles.
+template <int NT, int NV>
+__device__ __forceinline__ void block_sums(double (&v)[NV], double* red, double* out) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int e = 0; e < NV; ++e) v[e] = wave_sum(v[e]);
+    if (lane == 0)
+#pragma unroll
+        for (int e = 0; e < NV; ++e) red[wv * NV + e] = v[e];
+    __syncthreads();
+    if ((int)threadIdx.x < NV) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) t += red[w * NV + threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < NV; ++e) v[e] = out[e];
+    __syncthreads();
+}
+
+// k-th smallest (0-based, k < n) of the n doubles x[0..n) in LDS, as its
+// order key, by eight 8-bit radix passes of the whole block.  hist: 256
+// counts in LDS; bc: two ints in LDS for the broadcast of a pass's result.
+template <int NT, class Sel>
+__device__ uint64_t block_select_lds(const double* __restrict__ x, int n, int k, uint32_t* hist, int* bc, Sel sel) {
+    uint64_t prefix = 0, mask = 0;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        for (int b = threadIdx.x; b < 256; b += NT) hist[b] = 0u;
+        __syncthreads();
+        for (int j = threadIdx.x; j < n; j += NT) {
+            const uint64_t key = order_key(x[j]);
+            if ((key & mask) == prefix && sel(j)) {
+                // where every active lane of the wavefront has the same digit,
+                // one lane adds their count (the leading digits of values of
+                // one sign and magnitude would otherwise serialise)
+                const uint32_t dg = (uint32_t)(key >> shift) & 255u;
+                const uint32_t d0 = __builtin_amdgcn_readfirstlane(dg);
+                const uint64_t am = __ballot(true);
+                const uint64_t same = __ballot(dg == d0);
+                if (same == am) {
+                    if ((int)(threadIdx.x & 63) == __ffsll((unsigned long long)am) - 1)
+                        atomicAdd(&hist[d0], (uint32_t)__popcll(am));
+                } else {
+                    atomicAdd(&hist[dg], 1u);
+                }
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            int digit;
+            uint32_t below;
+            radix_digit(hist, k, digit, below);
+            if (threadIdx.x == 0) {
+                bc[0] = digit;
+                bc[1] = (int)below;
+            }
+        }
+        __syncthreads();
+        prefix |= (uint64_t)bc[0] << shift;
+        mask |= 0xFFull << shift;
+        k -= bc[1];
+        __syncthreads();
+    }
+    return prefix;
+}
+
+// Type-7 p-quantile of the m selected (sel) elements of x[0..n) in LDS (0
+// for m = 0): the order statistic j = floor((m - 1) p) by selection; j + 1
+// is the same key when more than j + 1 selected keys are <= it, else the
+// smallest selected key above it.  m is the same in every thread.
+template <int NT, class Sel>
+__device__ double block_quantile7_lds(const double* __restrict__ x, int n, int m, double p, uint32_t* hist, int* bc,
+                                      double* red, double* out, Sel sel) {
+    if (m <= 0) return 0.0;
+    const double h = (double)(m - 1) * p;
+    const int j = (int)floor(h);
+    const uint64_t kj = block_select_lds<NT>(x, n, j, hist, bc, sel);
+    const double xj = key_value(kj);
+    if (j + 1 >= m) return xj;
+    // count of selected keys <= kj, and the smallest selected key above it
+    double cnt[1] = {0.0};
+    uint64_t kmin = ~0ull;
+    for (int i = threadIdx.x; i < n; i += NT) {
+        if (!sel(i)) continue;
+        const uint64_t key = order_key(x[i]);
+        if (key <= kj) cnt[0] += 1.0;
+        else if (key < kmin) kmin = key;
+    }
+    // minimum over the block of kmin: per wavefront by shuffles, then in LDS
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)kmin, o, 64), hi = __shfl_xor((uint32_t)(kmin >> 32), o, 64);
+        const uint64_t other = ((uint64_t)hi << 32) | lo;
+        kmin = other < kmin ? other : kmin;
+    }
+    uint64_t* kred = reinterpret_cast<uint64_t*>(red);
+    // the block's count (exact: integers well below 2^53)
+    block_sums<NT, 1>(cnt, red + 2 * (NT / 64), out);
+    if ((threadIdx.x & 63) == 0) kred[threadIdx.x >> 6] = kmin;
+    __syncthreads();
+    uint64_t km = kred[0];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) km = kred[w] < km ? kred[w] : km;
+    __syncthreads();
+    const uint64_t kj1 = cnt[0] >= (double)(j + 2) ? kj : km;
+    return xj + (h - (double)j) * (key_value(kj1) - xj);
+}
+
+// Elements whose byte tag in LDS equals one value.
+struct TagIs {
+    const uint8_t* tag;
+    uint8_t want;
+    __device__ bool operator()(int64_t i) const { return tag[i] == want; }
+};
+
+template <int NT, bool FROM_COL>
+__global__ __launch_bounds__(NT) void k_s_robust(DevConsts k, int64_t n_src, int cap,
+                                                 const int64_t* __restrict__ off, const double* __restrict__ ot,
+                                                 const double* __restrict__ oeta, const float* __restrict__ osig,
+                                                 const int32_t* __restrict__ ocell, const int32_t* __restrict__ oell,
+                                                 const double* __restrict__ knots, const KnotTab* __restrict__ ktab,
+                                                 const double* __restrict__ a, const double* __restrict__ c,
+                                                 const double* __restrict__ eps_a2, int eps_bucket,
+                                                 double* __restrict__ s, SrcPrep* __restrict__ prep,
+                                                 double* __restrict__ ds, double* __restrict__ qsrc,
+                                                 int32_t* __restrict__ sdef, double* __restrict__ svar,
+                                                 const int32_t* __restrict__ order, double* __restrict__ vs_out,
+                                                 const double* __restrict__ col, int64_t n_obs) {
+    extern __shared__ double colm[];            // six columns of cap values, then cap kind bytes
+    __shared__ uint32_t hist[256];
+    __shared__ double red[(NT / 64) * 24];
+    __shared__ double out[24];
+    __shared__ int bc[2];
+    if ((int64_t)blockIdx.x >= n_src) return;
+    uint8_t* cKind = reinterpret_cast<uint8_t*>(colm + 6 * cap);   // 1: across scan
+    const int64_t i = order[blockIdx.x];
+    const int64_t l0 = off[i];
+    const int n = (int)(off[i + 1] - l0);       // <= cap (the launcher's class)
+    double* cA0 = colm;
+    double* cA1 = colm + cap;
+    double* cA2 = colm + 2 * cap;
+    double* cTau = colm + 3 * cap;
+    double* cH = colm + 4 * cap;
+    double* cS2 = colm + 5 * cap;
+    const double* si = s + 5 * i;
+    const double alpha = si[0], delta = si[1], plx = si[2], pma = si[3], pmd = si[4];
+    double sa, ca, sd, cd;
+    sincos(alpha, &sa, &ca);
+    sincos(delta, &sd, &cd);
+    const double p[3] = {-sa, ca, 0.0};
+    const double q[3] = {-sd * ca, -sd * sa, cd};
+    const double r[3] = {cd * ca, cd * sa, sd};
+    double mu[3];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) mu[cc] = p[cc] * pma + q[cc] * pmd;
+    // pass 0: model and design row of every observation, into LDS
+    double n_ac[1] = {0.0};
+    for (int j = threadIdx.x; j < n; j += NT) {
+        const int64_t l = l0 + j;
+        const int32_t cf = ocell[l];
+        const bool ac = cf >= k.ac_cf0;
+        cKind[j] = ac ? 1 : 0;
+        n_ac[0] += ac ? 1.0 : 0.0;
+        if (FROM_COL) {
+            cA0[j] = col[l];
+            cA1[j] = col[n_obs + l];
+            cA2[j] = col[2 * n_obs + l];
+            cTau[j] = col[3 * n_obs + l];
+            cH[j] = col[4 * n_obs + l];
+            cS2[j] = col[5 * n_obs + l];
+            continue;
+        }
+        const int32_t ell = oell[l];
+        const double sg = (double)osig[l];
+        ObsEval o;
+        observe(k, ot[l], oeta[l], c[cf >> 1], r, mu, plx, a + 4 * (ell - 3), knots + (ell - 2), ktab[ell - 3], o,
+                ac);
+        double A[5];
+        source_partials(o, p, q, r, A, ac);
+        cA0[j] = A[0];
+        cA1[j] = A[1];
+        cA2[j] = A[2];
+        cTau[j] = o.tau;                         // A[3] = A[0] tau, A[4] = A[1] tau
+        cH[j] = o.R;
+        cS2[j] = sg * sg + eps_a2[eps_slot(k, cf, ell - 3, eps_bucket)];
+    }
+    block_sums<NT, 1>(n_ac, red, out);          // also the barrier after the columns
+    // varsigma per kind of record: half the intersextile range of its h
+    double vk[2];
+    for (int kind = 0; kind < 2; ++kind) {
+        const int m = kind ? (int)n_ac[0] : n - (int)n_ac[0];
+        const TagIs sel{cKind, (uint8_t)kind};
+        const double q5 = block_quantile7_lds<NT>(cH, n, m, 5.0 / 6.0, hist, bc, red, out, sel);
+        const double q1 = block_quantile7_lds<NT>(cH, n, m, 1.0 / 6.0, hist, bc, red, out, sel);
+        vk[kind] = 0.5 * (q5 - q1);
+    }
+    if (threadIdx.x == 0) {
+        vs_out[2 * i] = vk[0];
+        vs_out[2 * i + 1] = vk[1];
+    }
+    // the inner iteration
+    double d[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double acc[21];
+    for (int it = 0; it < INNER_SOLVES; ++it) {
+#pragma unroll
+        for (int e = 0; e < 21; ++e) acc[e] = 0.0;
+        for (int j = threadIdx.x; j < n; j += NT) {
+            double A[5];
+            A[0] = cA0[j];
+            A[1] = cA1[j];
+            A[2] = cA2[j];
+            const double tau = cTau[j];
+            A[3] = A[0] * tau;
+            A[4] = A[1] * tau;
+            const double h = cH[j], s2 = cS2[j];
+            double wl;
+            if (it == 0) {
+                const double v = cKind[j] ? vk[1] : vk[0];
+                wl = v > 0.0 ? down_weight(h / v) : 1.0;
+            } else {
+                double R = h;
+#pragma unroll
+                for (int e = 0; e < 5; ++e) R -= A[e] * d[e];
+                wl = down_weight(R / sqrt(s2));
+            }
+            const double W = wl / s2;
+            int e = 0;
+#pragma unroll
+            for (int rr = 0; rr < 5; ++rr) {
+                const double wa = A[rr] * W;
+#pragma unroll
+                for (int cc = rr; cc < 5; ++cc) acc[e++] += wa * A[cc];
+            }
+#pragma unroll
+            for (int rr = 0; rr < 5; ++rr) acc[15 + rr] += A[rr] * W * h;
+            acc[20] += W * h * h;
+        }
+        block_sums<NT, 21>(acc, red, out);
+        if (it + 1 < INNER_SOLVES) {
+            // one thread solves; every thread takes d
+            if (threadIdx.x == 0) {
+                double U[25], x[5];
+                int e = 0;
+                for (int rr = 0; rr < 5; ++rr)
+                    for (int cc = rr; cc < 5; ++cc) U[rr * 5 + cc] = acc[e++];
+                for (int rr = 0; rr < 5; ++rr) x[rr] = acc[15 + rr];
+                small_chol_factor<5>(U);
+                small_chol_subst<5>(U, x);
+                for (int rr = 0; rr < 5; ++rr) out[rr] = x[rr];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < 5; ++e) d[e] = out[e];
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x != 0) return;
+    source_finish(acc, i, alpha, delta, plx, pma, pmd, cos(delta), s, prep, ds, qsrc, sdef, svar);
+}
+
+// Excess attitude noise in one kernel: one block of NT threads per bucket of
+// eps_bucket knot intervals evaluates R^2 - sigma^2 (- eps_i^2 in robust mode
+// 2) of the bucket's observations into LDS, with the attitude component each
+// measures, and takes the 68th percentile of each component's values there
+// (eq e09): k_ac_resid and k_bucket_eps without the HBM round trip.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_eps_fused(DevConsts k, int64_t n_buckets, int64_t K, int eps_bucket, int cap,
+                                                  const int64_t* __restrict__ iv_off, const double* __restrict__ ot,
+                                                  const double* __restrict__ oeta, const float* __restrict__ osig,
+                                                  const int32_t* __restrict__ ocellfov,
+                                                  const int32_t* __restrict__ osrc, const SrcPrep* __restrict__ prep,
+                                                  const double* __restrict__ knots,
+                                                  const KnotTab* __restrict__ ktab, const double* __restrict__ a,
+                                                  const double* __restrict__ c, int robust,
+                                                  double* __restrict__ eps_a2) {
+    extern __shared__ double vals[];            // the bucket's values (at most cap), then cap component bytes
+    __shared__ uint32_t hist[256];
+    __shared__ double red[(NT / 64) * 24];
+    __shared__ double out[24];
+    __shared__ int bc[2];
+    const int64_t b = blockIdx.x;
+    if (b >= n_buckets) return;
+    uint8_t* comp = reinterpret_cast<uint8_t*>(vals + cap);
+    const int64_t j0 = b * eps_bucket;
+    const int64_t j1 = j0 + eps_bucket < K ? j0 + eps_bucket : K;
+    const int64_t lb = iv_off[j0];
+    const int n = (int)(iv_off[j1] - lb);
+    double cnt[3] = {0.0, 0.0, 0.0};
+    for (int64_t j = j0; j < j1; ++j) {
+        const KnotTab kt = ktab[j];
+        const int64_t la = iv_off[j], le = iv_off[j + 1];
+        for (int64_t l = la + threadIdx.x; l < le; l += NT) {
+            const SrcPrep sp = prep[osrc[l]];
+            const int32_t cf = ocellfov[l];
+            const bool ac = cf >= k.ac_cf0;
+            ObsEval o;
+            observe(k, ot[l], oeta[l], c[cf >> 1], sp.r, sp.mu, sp.plx, a + 4 * j, knots + (j + 1), kt, o, ac);
+            const double sg = (double)osig[l];
+            vals[l - lb] = o.R * o.R - sg * sg - (robust == 2 ? sp.pad : 0.0);
+            const int cm = ac ? 1 + (cf & 1) : 0;
+            comp[l - lb] = (uint8_t)cm;
+            cnt[0] += cm == 0 ? 1.0 : 0.0;
+            cnt[1] += cm == 1 ? 1.0 : 0.0;
+            cnt[2] += cm == 2 ? 1.0 : 0.0;
+        }
+    }
+    block_sums<NT, 3>(cnt, red, out);           // also the barrier after the values
+    for (int cm = 0; cm < 3; ++cm) {
+        const double qv = block_quantile7_lds<NT>(vals, n, (int)cnt[cm], 0.68, hist, bc, red, out,
+                                                  TagIs{comp, (uint8_t)cm});
+        if (threadIdx.x == 0) eps_a2[cm * n_buckets + b] = qv > 0.0 ? qv : 0.0;
+    }
 }
 
 // Largest set whose keys go to registers; larger sets (or all, with the
@@ -586,33 +1066,52 @@ inline unsigned groups_grid(int64_t n_items, int items_per_block) {
     return (unsigned)((n_items + items_per_block - 1) / items_per_block);
 }
 
+// Dynamic LDS of k_s_robust (six columns and a byte per record) and of
+// k_eps_fused (a value and a byte per record) for cap records.
+inline size_t s_lds_bytes(int64_t cap) { return (size_t)cap * (6 * sizeof(double) + 1); }
+inline size_t eps_lds_bytes(int64_t cap) { return (size_t)cap * (sizeof(double) + 1); }
+
 }  // namespace
 
 #define AGIS_ROWS_LAUNCH(G)                                                                                      \
-    k_s_rows<G><<<groups_grid(ctx->n_src, 256 / G), 256, 0, ctx->stream>>>(                                      \
-        ctx->k, ctx->n_src, ctx->src_off, ctx->s_t, ctx->s_eta, ctx->s_sig, ctx->s_cell, ctx->s_ell, ctx->knots,   \
-        ctx->ktab, ctx->a, ctx->c, ctx->s, ctx->eps_a2, ctx->cfg.eps_bucket, ctx->rcol, ctx->n_obs, ctx->src_order)
+    k_s_rows<G><<<groups_grid(n_src, 256 / G), 256, 0, ctx->stream>>>(                                           \
+        ctx->k, n_src, ctx->src_off, ctx->s_t, ctx->s_eta, ctx->s_sig, ctx->s_cell, ctx->s_ell, ctx->knots,        \
+        ctx->ktab, ctx->a, ctx->c, ctx->s, ctx->eps_a2, ctx->cfg.eps_bucket, ctx->rcol, ctx->n_obs, order)
 #define AGIS_IRLS_LAUNCH(G)                                                                                      \
     if (ctx->cfg.robust == 2)                                                                                    \
-        k_s_irls_eps<G><<<groups_grid(ctx->n_src, 256 / G), 256, 0, ctx->stream>>>(                              \
-            ctx->n_src, ctx->src_off, ctx->rcol, ctx->n_obs, ctx->vs, ctx->s, ctx->prep, ctx->ds, ctx->qsrc,      \
-            ctx->sdef, ctx->svar, ctx->src_order, ctx->src_eps2, ctx->src_D);                                    \
+        k_s_irls_eps<G><<<groups_grid(n_src, 256 / G), 256, 0, ctx->stream>>>(                                   \
+            n_src, ctx->src_off, ctx->rcol, ctx->n_obs, ctx->vs, ctx->s, ctx->prep, ctx->ds, ctx->qsrc,           \
+            ctx->sdef, ctx->svar, order, ctx->src_eps2, ctx->src_D, ac_cells, ctx->k.ac_cf0);                    \
     else                                                                                                         \
-        k_s_irls<G><<<groups_grid(ctx->n_src, 256 / G), 256, 0, ctx->stream>>>(                                  \
-            ctx->n_src, ctx->src_off, ctx->rcol, ctx->n_obs, ctx->vs, ctx->s, ctx->prep, ctx->ds, ctx->qsrc,      \
-            ctx->sdef, ctx->svar, ctx->src_order)
+        k_s_irls<G><<<groups_grid(n_src, 256 / G), 256, 0, ctx->stream>>>(                                       \
+            n_src, ctx->src_off, ctx->rcol, ctx->n_obs, ctx->vs, ctx->s, ctx->prep, ctx->ds, ctx->qsrc,           \
+            ctx->sdef, ctx->svar, order, ac_cells, ctx->k.ac_cf0)
 
-void launch_source_update_robust(agis_ctx* ctx) {
-    if (ctx->n_src == 0) return;
+// The HBM-column kernels over launch positions [k0, k0 + n) of the
+// count-ordered source list: the rows (model and design row per
+// observation into the columns), then varsigma and the inner iteration.
+static void source_rows(agis_ctx* ctx, int64_t k0, int64_t n) {
+    if (n <= 0) return;
+    const int32_t* order = ctx->src_order + k0;
+    const int64_t n_src = n;
     switch (ctx->s_group) {
         case 8: AGIS_ROWS_LAUNCH(8); break;
         case 16: AGIS_ROWS_LAUNCH(16); break;
         case 32: AGIS_ROWS_LAUNCH(32); break;
         default: AGIS_ROWS_LAUNCH(64); break;
     }
-    (select_in_registers(ctx, ctx->n_obs, ctx->n_src) ? k_s_sigma<true> : k_s_sigma<false>)
-        <<<(unsigned)ctx->n_src, 64, 0, ctx->stream>>>(ctx->n_src, ctx->src_off, ctx->rcol + 4 * ctx->n_obs, ctx->vs,
-                                                       select_reg_limit(ctx), ctx->src_order);
+}
+
+static void source_solve_columns(agis_ctx* ctx, int64_t k0, int64_t n) {
+    if (n <= 0) return;
+    const int32_t* order = ctx->src_order + k0;
+    const int64_t n_src = n;
+    const int32_t* ac_cells = ctx->has_ac ? ctx->s_cell : nullptr;   // kinds of record matter with AC records
+    const bool reg = select_in_registers(ctx, ctx->n_obs, ctx->n_src);
+    (ac_cells ? (reg ? k_s_sigma<true, true> : k_s_sigma<false, true>)
+              : (reg ? k_s_sigma<true, false> : k_s_sigma<false, false>))
+        <<<(unsigned)n_src, 64, 0, ctx->stream>>>(n_src, ctx->src_off, ctx->rcol + 4 * ctx->n_obs, ctx->vs,
+                                                  select_reg_limit(ctx), order, ac_cells, ctx->k.ac_cf0);
     switch (ctx->s_group) {
         case 8: AGIS_IRLS_LAUNCH(8); break;
         case 16: AGIS_IRLS_LAUNCH(16); break;
@@ -620,6 +1119,126 @@ void launch_source_update_robust(agis_ctx* ctx) {
         default: AGIS_IRLS_LAUNCH(64); break;
     }
 }
+
+// Per-source LDS kernels for the robust S block (robust mode 1 only; the
+// excess source noise of mode 2 keeps the HBM-column kernels).
+static bool s_lds(const agis_ctx* ctx) { return ctx->robust_s_mode >= 1 && ctx->cfg.robust == 1; }
+static bool s_from_columns(const agis_ctx* ctx) { return ctx->robust_s_mode == 1; }
+static bool eps_one_kernel(const agis_ctx* ctx) { return ctx->robust_fused_eps && ctx->cfg.robust >= 1; }
+
+void launch_source_update_robust(agis_ctx* ctx) {
+    if (ctx->n_src == 0) return;
+    if (!s_lds(ctx)) {
+        source_rows(ctx, 0, ctx->n_src);
+        source_solve_columns(ctx, 0, ctx->n_src);
+        return;
+    }
+    const bool from_col = s_from_columns(ctx);
+    // the sources beyond the largest LDS class: the HBM-column kernels
+    source_rows(ctx, 0, from_col ? ctx->n_src : ctx->s_fallback);
+    source_solve_columns(ctx, 0, ctx->s_fallback);
+    for (const SClass& cl : ctx->s_classes) {
+        const int64_t n = cl.k1 - cl.k0;
+        const size_t lds = s_lds_bytes(cl.cap);
+#define AGIS_SROB_LAUNCH(NT, FC)                                                                                 \
+    k_s_robust<NT, FC><<<(unsigned)n, NT, lds, ctx->stream>>>(                                                  \
+        ctx->k, n, cl.cap, ctx->src_off, ctx->s_t, ctx->s_eta, ctx->s_sig, ctx->s_cell, ctx->s_ell, ctx->knots,    \
+        ctx->ktab, ctx->a, ctx->c, ctx->eps_a2, ctx->cfg.eps_bucket, ctx->s, ctx->prep, ctx->ds, ctx->qsrc,        \
+        ctx->sdef, ctx->svar, ctx->src_order + cl.k0, ctx->vs, ctx->rcol, ctx->n_obs)
+        if (from_col) {
+            if (cl.nt == 64) AGIS_SROB_LAUNCH(64, true);
+            else if (cl.nt == 128) AGIS_SROB_LAUNCH(128, true);
+            else AGIS_SROB_LAUNCH(256, true);
+        } else {
+            if (cl.nt == 64) AGIS_SROB_LAUNCH(64, false);
+            else if (cl.nt == 128) AGIS_SROB_LAUNCH(128, false);
+            else AGIS_SROB_LAUNCH(256, false);
+        }
+#undef AGIS_SROB_LAUNCH
+    }
+}
+
+#define HIPCHK(expr)                                            \
+    do {                                                        \
+        hipError_t e_ = (expr);                                 \
+        if (e_ != hipSuccess) return hip_check(ctx, e_, #expr); \
+    } while (0)
+
+// Observation-count classes of the one-kernel S path and its thread counts,
+// largest first; a class holds the counts above the next one's cap.
+static const int kSCaps[] = {3072, 2560, 2048, 1536, 1024, 768, 512, 384, 256, 128, 64, 32};
+static int s_threads(int cap) { return cap > 1024 ? 256 : (cap > 256 ? 128 : 64); }
+constexpr int EPS_NT = 256;
+
+int robust_plan(agis_ctx* ctx, const std::vector<int64_t>& h_off, const std::vector<int32_t>& order,
+                bool* need_columns) {
+    ctx->s_classes.clear();
+    ctx->s_fallback = 0;
+    ctx->eps_fused = false;
+    ctx->eps_cap = 0;
+    *need_columns = true;
+    // dynamic LDS a block may use beside the kernels' own (a few KB)
+    int max_lds = 0;
+    HIPCHK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+    const int64_t dyn_max = (int64_t)max_lds - 4096;
+    const int64_t n_src = (int64_t)order.size();
+    // classes: walk the count-ordered list from the smallest counts up
+    int64_t k1 = s_lds(ctx) ? n_src : 0;
+    for (int ci = (int)(sizeof kSCaps / sizeof kSCaps[0]) - 1; ci >= 0 && k1 > 0; --ci) {
+        const int cap = kSCaps[ci];
+        if ((int64_t)s_lds_bytes(cap) > dyn_max || cap > ctx->robust_max_cap) break;
+        int64_t k0 = k1;
+        while (k0 > 0) {
+            const int32_t i = order[k0 - 1];
+            if (h_off[i + 1] - h_off[i] > cap) break;
+            --k0;
+        }
+        if (k0 < k1) ctx->s_classes.push_back(SClass{k0, k1, cap, s_threads(cap)});
+        k1 = k0;
+    }
+    ctx->s_fallback = k1;
+    // largest classes first (the count order)
+    std::reverse(ctx->s_classes.begin(), ctx->s_classes.end());
+    int used_max[3] = {0, 0, 0};
+    for (const SClass& cl : ctx->s_classes) {
+        const int slot = cl.nt == 64 ? 0 : (cl.nt == 128 ? 1 : 2);
+        used_max[slot] = std::max(used_max[slot], (int)s_lds_bytes(cl.cap));
+    }
+    const bool fc = s_from_columns(ctx);
+    const void* fn[3] = {fc ? reinterpret_cast<const void*>(&k_s_robust<64, true>)
+                            : reinterpret_cast<const void*>(&k_s_robust<64, false>),
+                         fc ? reinterpret_cast<const void*>(&k_s_robust<128, true>)
+                            : reinterpret_cast<const void*>(&k_s_robust<128, false>),
+                         fc ? reinterpret_cast<const void*>(&k_s_robust<256, true>)
+                            : reinterpret_cast<const void*>(&k_s_robust<256, false>)};
+    for (int slot = 0; slot < 3; ++slot)
+        if (used_max[slot]) HIPCHK(hipFuncSetAttribute(fn[slot], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       used_max[slot]));
+    // the excess-noise buckets: the largest bucket's values must fit
+    if (!eps_one_kernel(ctx)) {
+        ctx->eps_fused = false;
+    } else if (ctx->K > 0 && ctx->n_buckets > 0) {
+        std::vector<int64_t> iv(ctx->K + 1);
+        HIPCHK(hipMemcpy(iv.data(), ctx->iv_off, (ctx->K + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+        int64_t mx = 0;
+        for (int64_t b = 0; b < ctx->n_buckets; ++b) {
+            const int64_t j0 = b * ctx->cfg.eps_bucket, j1 = std::min<int64_t>(j0 + ctx->cfg.eps_bucket, ctx->K);
+            mx = std::max(mx, iv[j1] - iv[j0]);
+        }
+        ctx->eps_cap = std::max<int64_t>(mx, 1);
+        if ((int64_t)eps_lds_bytes(ctx->eps_cap) <= dyn_max) {
+            HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eps_fused<EPS_NT>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)eps_lds_bytes(ctx->eps_cap)));
+            ctx->eps_fused = true;
+        }
+    } else {
+        ctx->eps_fused = true;
+    }
+    *need_columns = !s_lds(ctx) || fc || ctx->s_fallback > 0 || !ctx->eps_fused;
+    return AGIS_OK;
+}
+#undef HIPCHK
 
 void launch_freeze_sigma(agis_ctx* ctx) {
     if (ctx->K > 0)
@@ -635,12 +1254,21 @@ void launch_freeze_sigma(agis_ctx* ctx) {
 
 void launch_excess_noise(agis_ctx* ctx) {
     if (ctx->K == 0 || ctx->n_buckets == 0) return;
+    if (eps_one_kernel(ctx) && ctx->eps_fused) {
+        k_eps_fused<EPS_NT><<<(unsigned)ctx->n_buckets, EPS_NT, eps_lds_bytes(ctx->eps_cap), ctx->stream>>>(
+            ctx->k, ctx->n_buckets, ctx->K, ctx->cfg.eps_bucket, (int)ctx->eps_cap, ctx->iv_off, ctx->t_t, ctx->t_eta, ctx->t_sig,
+            ctx->t_cellfov, ctx->t_src, ctx->prep, ctx->knots, ctx->ktab, ctx->a, ctx->c, ctx->cfg.robust,
+            ctx->eps_a2);
+        return;
+    }
     k_ac_resid<<<(unsigned)ctx->K, 64, 0, ctx->stream>>>(ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, ctx->t_sig,
                                                          ctx->t_cellfov, ctx->t_src, ctx->prep, ctx->knots, ctx->ktab,
                                                          ctx->a, ctx->c, ctx->cfg.robust, ctx->rcol);
+    const int32_t* cellfov = ctx->has_ac ? ctx->t_cellfov : nullptr;
     (select_in_registers(ctx, ctx->n_obs, ctx->n_buckets) ? k_bucket_eps<true> : k_bucket_eps<false>)
-        <<<(unsigned)ctx->n_buckets, 64, 0, ctx->stream>>>(ctx->n_buckets, ctx->K, ctx->cfg.eps_bucket, ctx->iv_off,
-                                                           ctx->rcol, ctx->eps_a2, select_reg_limit(ctx));
+        <<<(unsigned)((cellfov ? 3 : 1) * ctx->n_buckets), 64, 0, ctx->stream>>>(
+            ctx->n_buckets, ctx->K, ctx->cfg.eps_bucket, ctx->iv_off, ctx->rcol, ctx->eps_a2, select_reg_limit(ctx),
+            cellfov, ctx->k.ac_cf0);
 }
 
 }  // namespace agis

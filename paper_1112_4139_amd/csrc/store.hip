@@ -253,11 +253,6 @@ int build_store(agis_ctx* ctx, const agis_obs_soa_t* obs, int where) {
     HIPCHK(hipStreamSynchronize(st));
     ctx->has_ac = (hflags & HAS_AC) != 0;
     hflags &= ~HAS_AC;
-    if (ctx->has_ac && ctx->cfg.robust) {
-        // the excess attitude noise would need its across-scan components
-        return set_error(ctx, AGIS_E_INVALID_ARG,
-                         "robust weighting with across-scan observations (cell -1) is not supported");
-    }
     if (hflags) {
         std::string m = "invalid observations:";
         if (hflags & BAD_SRC) m += " src outside [0, n_src);";

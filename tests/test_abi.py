@@ -76,8 +76,27 @@ def test_disagreement_metric():
 
 def test_measured_traffic_only_for_the_profiled_workload():
     import bench
-    assert bench.measured_traffic("ac_pass", "gaia5", "fp64") is None
-    assert bench.measured_traffic("ac_pass", "gaia1", "mixed") is None
-    t = bench.measured_traffic("ac_pass", "gaia1", "fp64")
-    # the committed counter summary matches the kernel sources, or reads None
-    assert t is None or t > 5e9
+    assert bench.measured_traffic("ac_pass", "gaia5", "mixed") is None
+    assert bench.measured_traffic("ac_pass", "no-such-workload", "fp64") is None
+    for wl in ("gaia1", "gaia5"):
+        for k in ("ac_pass", "source_update", "source_update_robust", "excess_noise"):
+            t = bench.measured_traffic(k, wl, "fp64")
+            # the committed counter summary matches the kernel sources, or reads None
+            assert t is None or t > 1e9
+
+
+def test_cpu_baseline_time_slice(oracle_lib):
+    """The benchmark's CPU sample: a few whole days of a world, its
+    sources renumbered, knots, attitude and cells cut to the slice; the
+    oracle's residuals there equal the full world's at the same
+    observations."""
+    import bench
+    import synth.configs as C
+    w = C.make("tiny", noise=False)
+    ws = bench.time_slice(w, 100, 3)
+    keep = (w.t >= w.consts["t_beg"] + 100 * 86400.0) & (w.t < w.consts["t_beg"] + 103 * 86400.0)
+    assert ws.n_obs == keep.sum() > 0
+    assert ws.cell.min() >= 0 and ws.cell.max() < ws.n_cells == 6
+    R_full = oracle_lib.problem_from_world(w, oracle_lib.observed_field_angles(w), state="start").observe()["R"]
+    R_sl = oracle_lib.problem_from_world(ws, oracle_lib.observed_field_angles(ws), state="start").observe()["R"]
+    np.testing.assert_array_equal(R_sl, R_full[keep])

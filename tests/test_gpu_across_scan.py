@@ -169,23 +169,16 @@ def test_ac_cg_parity(agis_mod, oracle_lib, tiny_ac):
     p.close()
 
 
-def test_ac_refused_in_robust_mode(agis_mod, oracle_lib, small_ac):
+def test_ac_cell_codes_checked(agis_mod, oracle_lib, small_ac):
+    """A cell index below -1 (neither a calibration cell nor across scan) is
+    refused at load."""
     w, eta = small_ac
-    consts = dict(w.consts)
-    consts["robust"] = 1
-    ctx = agis_mod.agis_create(consts, w.knots)
-    with pytest.raises(agis_mod.AgisError) as e:
-        agis_mod.agis_load_observations(ctx, w.t, eta, w.sigma, w.src, w.fov, w.cell, w.src_true.shape[0],
-                                        w.n_cells)
-    assert "across-scan" in str(e.value)
     bad = w.cell.copy()
     bad[0] = -2
-    consts["robust"] = 0
-    ctx2 = agis_mod.agis_create(consts, w.knots)
+    ctx = agis_mod.agis_create(w.consts, w.knots)
     with pytest.raises(agis_mod.AgisError):
-        agis_mod.agis_load_observations(ctx2, w.t, eta, w.sigma, w.src, w.fov, bad, w.src_true.shape[0], w.n_cells)
+        agis_mod.agis_load_observations(ctx, w.t, eta, w.sigma, w.src, w.fov, bad, w.src_true.shape[0], w.n_cells)
     agis_mod.agis_destroy(ctx)
-    agis_mod.agis_destroy(ctx2)
 
 
 def test_ac_chi2_matches_oracle(agis_mod, oracle_lib, small9_ac):

@@ -29,7 +29,7 @@ def _state(agis, ctx, w, robust=False):
            agis.agis_get_calibration(ctx, w.n_cells)]
     if robust:
         nb = (w.knots.size - 7 + int(w.consts["eps_bucket"]) - 1) // int(w.consts["eps_bucket"])
-        out.append(agis.agis_get_excess_noise(ctx, nb))
+        out.append(agis.agis_get_excess_noise(ctx, 3 * nb))   # AL, ACP, ACF
     return out
 
 

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import synth.configs as C
-from test_gpu_parity import DIFFS, Pair, fp64_floor, agis_mod  # noqa: F401
+from test_gpu_parity import Pair, check_floor, fp64_floor, agis_mod  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
@@ -45,22 +45,11 @@ def test_hybrid_parity(agis_mod, oracle_lib, tiny_robust):
     # The sequence compounds the rounding of the robust inner iterations, the
     # weights frozen from the residuals and the CG steps; the FP64 oracle
     # itself is then only 48% within 1e-3 uas for the across-scan attitude.
-    # Criterion: per class, the GPU's largest and RMS deviation from the
-    # extended-precision oracle at most twice the FP64 oracle's, and at least
-    # 99.5% of the parameters within the per-parameter FP64-floor tolerance
-    # (measured: single sources and coefficients reached 3x and 1.8x it).
+    # The criterion of every parity test applies: each parameter within its
+    # FP64-floor tolerance, per component an RMS at most twice the FP64
+    # oracle's.
     for name, which in (("sources", 0), ("attitude", 1), ("calibration", 2)):
-        f = DIFFS[which]
-        dg, do = np.abs(f(X[which], G[which])), np.abs(f(X[which], O[which]))
-        within = float(np.mean(dg <= tol[which]))
-        rms_g, rms_o = np.sqrt(np.mean(dg * dg, axis=0)), np.sqrt(np.mean(do * do, axis=0))
-        print(f"hybrid {name}: max |GPU - ext| {dg.max():.2e} (FP64 oracle {do.max():.2e}) uas, "
-              f"rms {np.array2string(np.atleast_1d(rms_g), precision=6)} "
-              f"(oracle {np.array2string(np.atleast_1d(rms_o), precision=6)}), "
-              f"{100 * within:.3f}% within tolerance, worst ratio {(dg / tol[which]).max():.2f}")
-        assert dg.max() <= 2.0 * do.max() + 1e-6
-        assert np.all(rms_g <= 2.0 * rms_o + 1e-6)
-        assert within >= 0.995
+        check_floor(f"hybrid: {name}", X[which], O[which], G[which], tol[which], which)
     p.close()
 
 
@@ -75,8 +64,8 @@ def test_thaw_returns_to_robust(agis_mod, oracle_lib, tiny_robust):
     for p in (a, b):
         agis_mod.agis_iterate(p.ctx, 2, stats=False)
     nb = (w.knots.size - 7 + int(w.consts["eps_bucket"]) - 1) // int(w.consts["eps_bucket"])
-    for x, y in zip(a.gpu_state() + (agis_mod.agis_get_excess_noise(a.ctx, nb),),
-                    b.gpu_state() + (agis_mod.agis_get_excess_noise(b.ctx, nb),)):
+    for x, y in zip(a.gpu_state() + (agis_mod.agis_get_excess_noise(a.ctx, 3 * nb),),
+                    b.gpu_state() + (agis_mod.agis_get_excess_noise(b.ctx, 3 * nb),)):
         assert np.array_equal(x, y)
     a.close()
     b.close()

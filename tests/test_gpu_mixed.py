@@ -103,3 +103,35 @@ def test_mixed_iterations_track_fp64(agis_mod, oracle_lib, tiny):
     # along-scan attitude and calibration, which the iteration determines
     # well, within 0.05 uas (measured 0.007 uas RMS and 0.027 uas max)
     assert np.sqrt(np.mean(dn[1][:, 2] ** 2)) <= 0.05 and np.abs(dn[2]).max() <= 0.05
+
+
+def test_mixed_converges_to_the_fp64_point(agis_mod, oracle_lib):
+    """On the tiny world with one across-scan record per transit (every
+    attitude axis well determined), FP64 and mixed precision each run 1,200
+    S[AC] + frame iterations from the start values, by which both have
+    converged (their last 200 iterations move no parameter class by more
+    than 1e-3 uas RMS); the two limits agree within 0.05 uas in every class,
+    RMS and maximum (the mixed path's right-hand sides are FP64, so its
+    fixed point is the FP64 one; its FP32 normal matrices only change the
+    path to it)."""
+    w = C.make("tiny", ac_obs=True)
+    eta = oracle_lib.observed_field_angles(w)
+    limits = {}
+    for prec in (0, AGIS_MIXED):
+        ctx = _ctx(agis_mod, w, eta, prec, w.src_start, w.att_start, w.cal_start)
+        agis_mod.agis_set_frame_reference(ctx, w.src_true)
+        agis_mod.agis_iterate_graph(ctx, 1000)
+        before = _state(agis_mod, ctx, w)
+        agis_mod.agis_iterate_graph(ctx, 200)
+        after = _state(agis_mod, ctx, w)
+        ds, da = src_diff_uas(before[0], after[0]), rot_diff_uas(before[1], after[1])
+        dc = (after[2] - before[2]) / UAS
+        _summary(f"precision {prec}: change over the last 200 iterations", ds, da, dc)
+        assert np.sqrt(np.mean(ds * ds, axis=0)).max() < 1e-3 and np.sqrt(np.mean(da * da, axis=0)).max() < 1e-3
+        limits[prec] = after
+        agis_mod.agis_destroy(ctx)
+    a, b = limits[0], limits[AGIS_MIXED]
+    ds, da, dc = src_diff_uas(a[0], b[0]), rot_diff_uas(a[1], b[1]), (b[2] - a[2]) / UAS
+    _summary("mixed - FP64 at convergence", ds, da, dc)
+    for d in (ds, da, dc[:, None]):
+        assert np.sqrt(np.mean(d * d, axis=0)).max() <= 0.05 and np.abs(d).max() <= 0.05

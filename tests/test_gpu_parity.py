@@ -52,33 +52,53 @@ def src_diff_uas(s_ref, s):
     return ds / UAS
 
 
-def fp64_floor(oracle_lib, world, eta, run, n_draws=3, ulp_noise=3e-16, factor=8.0, factor_ref=4.0):
+# The per-parameter bound.  An FP64 implementation's rounding error in a
+# parameter p is modelled as e_p = c s_p g_p, g_p ~ N(0, 1): s_p is the
+# parameter's sensitivity to rounding-level noise in the residuals, c the
+# implementation's noise level in those units.  s_p is estimated as the RMS
+# of the parameter's responses to N_DRAWS independent N(0, (3e-16 rad)^2)
+# perturbations of every residual (3e-16 rad is ~2x the measured RMS
+# difference of the GPU's and the oracle's residuals).  With c <= 1,
+# e_p / s_hat_p then follows Student's t with N_DRAWS degrees of freedom,
+# and FLOOR_FACTOR is its two-sided quantile for a false alarm of 1e-3 over
+# 1e5 parameters (scipy.stats.t.ppf(1 - 5e-9, 8) = 23.9).  An attitude
+# coefficient's bound is also at least REF_FACTOR x the largest deviation of
+# the FP64 oracle among the 33 coefficients around it (a pooled sample of the
+# local floor, which follows the band system's conditioning: the largest of
+# 33 Gaussian deviations is ~2.4 sigma, so the bound is ~10 sigma).
+N_DRAWS = 8
+FLOOR_FACTOR = 24.0
+REF_FACTOR = 4.0
+ULP_NOISE = 3e-16
+
+
+def fp64_floor(oracle_lib, world, eta, run, n_draws=N_DRAWS, ulp_noise=ULP_NOISE, factor=FLOOR_FACTOR,
+               factor_ref=REF_FACTOR):
     """Reference result X, FP64 oracle result O and per-parameter tolerances.
 
     X is the oracle built in x87 extended precision (64-bit significand): the
     exact answer to ~1e-19 relative.  An FP64 implementation cannot do better
-    than the FP64 rounding floor of each parameter, estimated two ways: the
-    FP64 oracle's own deviation |O - X|, and the oracle's response to a
-    3e-16 rad (a few ulp of the field angle) perturbation of every residual,
-    the largest over n_draws draws.  Where a parameter amplifies rounding
-    (few observations, the weakly determined across-scan attitude axes) that
-    floor exceeds 1e-3 uas; for attitude coefficients |O - X| is taken as
-    its largest value over the neighbouring coefficients.
-    run(problem) -> (s, a, c)."""
+    than the FP64 rounding floor of each parameter; the tolerance is
+    max(1e-3 uas, factor x s_hat_p) with s_hat_p the RMS response of the
+    parameter to n_draws perturbations of every residual by N(0, ulp_noise^2)
+    (see FLOOR_FACTOR above), and for attitude coefficients also factor_ref x
+    the FP64 oracle's largest deviation |O - X| among the 16 coefficients on
+    either side.  run(problem) -> (s, a, c)."""
     X = [np.asarray(v, np.float64) for v in run(oracle_lib.problem_from_world(world, eta, "start", "extended"))]
     O = run(oracle_lib.problem_from_world(world, eta, state="start"))
-    sens = [np.zeros_like(src_diff_uas(O[0], O[0])), np.zeros((O[1].shape[0], 3)), np.zeros_like(O[2])]
+    ss = [np.zeros_like(src_diff_uas(O[0], O[0])), np.zeros((O[1].shape[0], 3)), np.zeros_like(O[2])]
     for k in range(n_draws):
         rng = np.random.default_rng(100 + k)
         out = run(oracle_lib.problem_from_world(world, eta + rng.normal(0, ulp_noise, eta.shape), state="start"))
         for i, f in enumerate(DIFFS):
-            sens[i] = np.maximum(sens[i], np.abs(f(O[i], out[i])))
-    ref = [np.abs(f(X[i], O[i])) for i, f in enumerate(DIFFS)]
+            ss[i] += f(O[i], out[i]) ** 2
+    sens = [np.sqrt(x / n_draws) for x in ss]
+    tol = [np.maximum(TOL_UAS, factor * sens[i]) for i in range(3)]
     # the floor of an attitude coefficient is set by the conditioning of the
-    # local band system, which varies slowly along the mission: take the
-    # largest FP64 deviation among the 16 coefficients on either side
-    ref[1] = maximum_filter1d(ref[1], size=33, axis=0, mode="nearest")
-    tol = [np.maximum(TOL_UAS, np.maximum(factor * sens[i], factor_ref * ref[i])) for i in range(3)]
+    # local band system, which varies slowly along the mission: the largest
+    # FP64 deviation among the 16 coefficients on either side
+    ref_a = maximum_filter1d(np.abs(DIFFS[1](X[1], O[1])), size=33, axis=0, mode="nearest")
+    tol[1] = np.maximum(tol[1], factor_ref * ref_a)
     return X, O, tol
 
 

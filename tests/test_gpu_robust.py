@@ -1,8 +1,10 @@
 """Parity of the robust mode (Sect. 5.1.2, 5.2.5) of the HIP library with the
 oracle: excess attitude noise per bucket, the source inner iteration, and
 iterations with robust attitude and calibration weights, on the tiny world
-with 1% gross outliers (noise N(0, 50 mas)).  Same criterion as the plain
-parity tests: the extended-precision oracle is the reference."""
+with 1% gross outliers (noise N(0, 50 mas)), with and without across-scan
+records (then three excess-noise components per bucket and the initial
+downweights per kind of record).  Same criterion as the plain parity tests:
+the extended-precision oracle is the reference."""
 import types
 
 import numpy as np
@@ -17,10 +19,23 @@ pytestmark = pytest.mark.gpu
 UAS = synth.UAS
 
 
-@pytest.fixture(scope="module")
-def tiny_robust(oracle_lib):
-    w = C.make("tiny_robust")
+@pytest.fixture(scope="module", params=["tiny_robust", "tiny_robust+ac"])
+def tiny_robust(oracle_lib, request):
+    w = C.make("tiny_robust", ac_obs=request.param.endswith("+ac"))
     return w, oracle_lib.observed_field_angles(w)
+
+
+def eps_bound(w, e_o):
+    """Bound on |GPU - oracle| of eps_a^2 per component and bucket: R^2 -
+    sigma^2 carries the residuals' rounding, |d(R^2)| <= 2 |R| |dR| with
+    |dR| < 1e-15 rad and |R| about (eps_a^2 + sigma^2)^1/2 at the quantile,
+    times 2 for the two order statistics it interpolates; sigma of the
+    component's records (along or across scan)."""
+    nb = e_o.size // 3
+    al = w.sigma[w.cell >= 0]
+    ac = w.sigma[w.cell < 0]
+    s = np.repeat([al.max() if al.size else 0.0, ac.max() if ac.size else 0.0, ac.max() if ac.size else 0.0], nb)
+    return 4e-15 * np.sqrt(e_o + s.astype(np.float64) ** 2) + 2e-24
 
 
 def test_excess_noise_parity(agis_mod, oracle_lib, tiny_robust):
@@ -33,16 +48,36 @@ def test_excess_noise_parity(agis_mod, oracle_lib, tiny_robust):
     agis_mod.agis_excess_noise_update(p.ctx)
     e_g = agis_mod.agis_get_excess_noise(p.ctx, e_o.size)
     d = np.sqrt(np.abs(e_g - e_o)) / UAS
-    print(f"eps_a: buckets {e_o.size}, nonzero {np.mean(e_o > 0):.2f}, median {np.median(np.sqrt(e_o)) / UAS:.2f} uas, "
-          f"max |d eps_a^2|^(1/2) {d.max():.2e} uas")
-    # R^2 - sigma^2 with |R| ~ 100 uas carries the residuals' rounding
-    # (|dR| < 1e-15 rad): |d(R^2)| < 2 |R| |dR| ~ 1e-24 rad^2
-    assert np.all(np.abs(e_g - e_o) <= 2e-24)
+    nb = e_o.size // 3
+    for c, name in enumerate(("AL", "ACP", "ACF")):
+        ec = e_o[c * nb:(c + 1) * nb]
+        print(f"eps_a {name}: buckets {nb}, nonzero {np.mean(ec > 0):.2f}, median {np.median(np.sqrt(ec)) / UAS:.2f} "
+              f"uas, max |d eps_a^2|^(1/2) {d[c * nb:(c + 1) * nb].max():.2e} uas")
+    assert np.all(np.abs(e_g - e_o) <= eps_bound(w, e_o))
+    if not (w.cell < 0).any():
+        assert np.all(e_g[nb:] == 0.0)
     p.close()
 
 
-def test_robust_source_update_parity(agis_mod, oracle_lib, tiny_robust):
+@pytest.mark.parametrize("path", ["one kernel", "columns", "rows then LDS", "mixed", "rows then LDS, mixed"])
+def test_robust_source_update_parity(agis_mod, oracle_lib, tiny_robust, path, monkeypatch):
+    """The robust S update on its paths: every source in the one-kernel path
+    (model, varsigma and solves per source in LDS), every source through HBM
+    columns (three kernels), the rows to HBM columns and then varsigma and
+    the solves per source in LDS (the default), and each of the LDS paths
+    with the sources of more than 32 observations on the column kernels."""
     w, eta = tiny_robust
+    env = {"one kernel": {"AGIS_ROBUST_FUSED": "2"}, "columns": {"AGIS_ROBUST_FUSED": "0"},
+           "rows then LDS": {"AGIS_ROBUST_FUSED": "1"},
+           "mixed": {"AGIS_ROBUST_FUSED": "2", "AGIS_ROBUST_MAX_CAP": "32"},
+           "rows then LDS, mixed": {"AGIS_ROBUST_FUSED": "1", "AGIS_ROBUST_MAX_CAP": "32"}}[path]
+    for k in ("AGIS_ROBUST_FUSED", "AGIS_ROBUST_MAX_CAP"):
+        monkeypatch.delenv(k, raising=False)
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    if path.endswith("mixed"):
+        nobs = np.bincount(w.src, minlength=w.src_true.shape[0])
+        assert (nobs > 32).any() and (nobs <= 32).any()
 
     def run(pr):
         _, _, de = pr.source_update()
@@ -102,10 +137,11 @@ def test_robust_mode_calls(agis_mod, oracle_lib, tiny_robust):
     with pytest.raises(agis_mod.AgisError):
         agis_mod.agis_create(bad, w.knots)
     ctx = agis_mod.agis_create(w.consts, w.knots)
-    nb = (w.knots.size - 7 + 7) // 8
-    with pytest.raises(agis_mod.AgisError) as e:
-        agis_mod.agis_set_excess_noise(ctx, np.zeros(nb + 1))
-    assert e.value.code == -2
+    nb = 3 * ((w.knots.size - 7 + 7) // 8)      # buckets of 8 intervals, per AL, ACP, ACF
+    for wrong in (nb // 3, nb + 1):
+        with pytest.raises(agis_mod.AgisError) as e:
+            agis_mod.agis_set_excess_noise(ctx, np.zeros(wrong))
+        assert e.value.code == -2
     agis_mod.agis_set_excess_noise(ctx, np.full(nb, 1e-20))
     assert np.all(agis_mod.agis_get_excess_noise(ctx, nb) == 1e-20)
     agis_mod.agis_destroy(ctx)
@@ -127,9 +163,13 @@ def test_quantile_paths_agree(agis_mod, oracle_lib, tiny_robust, eps_bucket, mon
     wb = types.SimpleNamespace(**{**vars(w), "consts": consts, "n_cells": w.n_cells, "n_att": w.n_att,
                                   "n_obs": w.n_obs})
     out = []
-    # default choice; the lean kernel everywhere; the register kernel everywhere
-    for env in ({}, {"AGIS_SELECT_REG_LIMIT": "0"}, {"AGIS_SELECT_REG_MIN_MEAN": "0"}):
-        for k in ("AGIS_SELECT_REG_LIMIT", "AGIS_SELECT_REG_MIN_MEAN"):
+    # the HBM-column kernels with the default choice, the lean kernel
+    # everywhere and the register kernel everywhere; then the default paths
+    # (the excess-noise estimate in one kernel, values and selection in LDS)
+    names = ("AGIS_SELECT_REG_LIMIT", "AGIS_SELECT_REG_MIN_MEAN", "AGIS_ROBUST_FUSED")
+    for env in ({"AGIS_ROBUST_FUSED": "0"}, {"AGIS_SELECT_REG_LIMIT": "0", "AGIS_ROBUST_FUSED": "0"},
+                {"AGIS_SELECT_REG_MIN_MEAN": "0", "AGIS_ROBUST_FUSED": "0"}, {}):
+        for k in names:
             monkeypatch.delenv(k, raising=False)
         for k, v in env.items():
             monkeypatch.setenv(k, v)
@@ -142,9 +182,11 @@ def test_quantile_paths_agree(agis_mod, oracle_lib, tiny_robust, eps_bucket, mon
         if not env:
             e_o = p.pr.excess_attitude_noise()
         p.close()
-    for k in ("AGIS_SELECT_REG_LIMIT", "AGIS_SELECT_REG_MIN_MEAN"):
+    for k in names:
         monkeypatch.delenv(k, raising=False)
     print(f"eps_bucket {eps_bucket}: {e_o.size} buckets; max |eps^2 GPU - oracle| {np.abs(out[0][0] - e_o).max():.2e}")
-    for o in out[1:]:
+    for o in out[1:3]:
         assert np.array_equal(out[0][0], o[0]) and np.array_equal(out[0][1], o[1])
-    assert np.all(np.abs(out[0][0] - e_o) <= 2e-24)
+    # the same values and exact order statistics on the one-kernel path
+    assert np.array_equal(out[0][0], out[3][0])
+    assert np.all(np.abs(out[0][0] - e_o) <= eps_bound(w, e_o))

@@ -72,22 +72,11 @@ def test_iterations_with_source_noise(agis_mod, oracle_lib, world2):
     # eps_i is a root of Q(y) = nu and the outlier count n_out a threshold
     # count, so these iterations amplify rounding: the FP64 oracle deviates
     # from the extended-precision one by up to 8 uas (75% of the source
-    # parameters within 1e-3 uas).  Criterion as for the hybrid scheme: per
-    # class the GPU's largest and RMS deviation at most twice the FP64
-    # oracle's, and >= 99.5% of the parameters within the per-parameter
-    # FP64-floor tolerance (measured: one source parameter at 1.11x it).
+    # parameters within 1e-3 uas).  The per-parameter FP64-floor tolerance
+    # follows that amplification (the perturbed runs go through the same
+    # thresholds).
     for name, which in (("sources", 0), ("attitude", 1), ("calibration", 2)):
-        f = DIFFS[which]
-        dg, do = np.abs(f(X[which], G[which])), np.abs(f(X[which], O[which]))
-        within = float(np.mean(dg <= tol[which]))
-        rms_g, rms_o = np.sqrt(np.mean(dg * dg, axis=0)), np.sqrt(np.mean(do * do, axis=0))
-        print(f"robust 2 iterations, {name}: max |GPU - ext| {dg.max():.2e} (FP64 oracle {do.max():.2e}) uas, "
-              f"rms {np.array2string(np.atleast_1d(rms_g), precision=6)} "
-              f"(oracle {np.array2string(np.atleast_1d(rms_o), precision=6)}), "
-              f"{100 * within:.3f}% within tolerance, worst ratio {(dg / tol[which]).max():.2f}")
-        assert dg.max() <= 2.0 * do.max() + 1e-6
-        assert np.all(rms_g <= 2.0 * rms_o + 1e-6)
-        assert within >= 0.995
+        check_floor(f"robust 2 iterations: {name}", X[which], O[which], G[which], tol[which], which)
     e_g = agis_mod.agis_get_excess_noise(p.ctx, e_o.size)
     rel = np.abs(np.sqrt(e_g) - np.sqrt(e_o)) / UAS
     print(f"robust 2 iterations: eps_a median {np.median(np.sqrt(e_o)) / UAS:.3f} uas, max diff {rel.max():.2e} uas")
