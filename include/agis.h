@@ -432,13 +432,13 @@ int agis_cg_iterate(agis_ctx_t* ctx, int32_t n_eval, int32_t restart, agis_cg_st
  * needs a fixed normal matrix).  freeze != 0: at the current parameters and
  * excess attitude noise, every observation's weight of the A/C pass,
  * W = w(R / sigma~) / sigma~^2 with sigma~^2 = sigma^2 + eps_a^2 (eq:dw,
- * eq:W), is fixed as sigma_eff = 1 / sqrt(W) (FP32; W = 0 gives the
+ * eq:W), is fixed as sigma_eff = 1 / sqrt(W) (FP64; W = 0 gives the
  * largest finite float), and from then on the S, A and C blocks, the
  * iterations and agis_cg_iterate solve the plain weighted least-squares
  * problem with sigma_eff in place of sigma (no inner iteration, no
  * excess-noise update).  freeze == 0: back to the robust weighting.
  * Calling it again re-freezes at the current parameters.  Device memory:
- * 8 bytes per observation, allocated on the first freeze.  AGIS_E_STATE
+ * 16 bytes per observation (both orders), allocated on the first freeze.  AGIS_E_STATE
  * when the context is not robust.
  */
 int agis_freeze_weights(agis_ctx_t* ctx, int32_t freeze);

@@ -38,7 +38,7 @@ def _structs(c_r):
 
     class Obs(ctypes.Structure):
         _fields_ = [("n", c_i64), ("t", P(c_r)), ("eta_obs", P(c_r)), ("sigma", P(c_f)), ("src", P(c_i32)),
-                    ("fov", P(c_i8)), ("cell", P(c_i32))]
+                    ("fov", P(c_i8)), ("cell", P(c_i32)), ("sigma_eff", P(c_r))]
 
     class State(ctypes.Structure):
         _fields_ = [("n_src", c_i64), ("n_att", c_i64), ("n_cells", c_i64), ("s", P(c_r)), ("a", P(c_r)),
@@ -116,7 +116,7 @@ def lib(precision="double"):
         L.orc_normal_rhs.argtypes = [P(World), P(Obs), P(State), P(c_r), P(c_r), P(c_r)]
         L.orc_normal_quadratic.argtypes = [P(World), P(Obs), P(State), P(c_r)]
         L.orc_normal_quadratic.restype = c_r
-        L.orc_frozen_sigma.argtypes = [P(World), P(Obs), P(State), P(c_f)]
+        L.orc_frozen_sigma.argtypes = [P(World), P(Obs), P(State), P(c_r)]
         L.orc_frame_fit.argtypes = [P(World), P(State), P(c_r), P(c_r), P(c_r)]
         L.orc_frame_apply.argtypes = [P(World), P(State), P(c_r)]
         L.orc_weight_function.argtypes = [c_r]
@@ -246,7 +246,8 @@ class Problem:
     extended precision; arrays are then numpy longdouble).
     """
 
-    def __init__(self, consts, knots, t, eta_obs, sigma, src, fov, cell, s, a, c, precision="double"):
+    def __init__(self, consts, knots, t, eta_obs, sigma, src, fov, cell, s, a, c, precision="double",
+                 sigma_eff=None):
         self.precision = precision
         self._cr, self._dt = PRECISIONS[precision][0], PRECISIONS[precision][1]
         self._World, self._Obs, self._State = _STRUCTS[precision]
@@ -255,6 +256,8 @@ class Problem:
         self.t = self._arr(t)
         self.eta_obs = self._arr(eta_obs)
         self.sigma = np.ascontiguousarray(sigma, dtype=np.float32)
+        # the frozen sigma_eff of the hybrid scheme, replacing sigma (or None)
+        self.sigma_eff = None if sigma_eff is None else self._arr(sigma_eff).copy()
         self.src = np.ascontiguousarray(src, dtype=np.int32)
         self.fov = np.ascontiguousarray(fov, dtype=np.int8)
         self.cell = np.ascontiguousarray(cell, dtype=np.int32)
@@ -293,7 +296,7 @@ class Problem:
         cr = self._cr
         self.obs = self._Obs(n=self.t.size, t=_p(self.t, cr), eta_obs=_p(self.eta_obs, cr),
                              sigma=_p(self.sigma, c_f), src=_p(self.src, c_i32), fov=_p(self.fov, c_i8),
-                             cell=_p(self.cell, c_i32))
+                             cell=_p(self.cell, c_i32), sigma_eff=_p(self.sigma_eff, cr))
         self.state = self._State(n_src=self.s.shape[0], n_att=self.a.shape[0], n_cells=self.c.size,
                                  s=_p(self.s, cr), a=_p(self.a, cr), c=_p(self.c, cr),
                                  n_buckets=self.eps_a2.size // 3, eps_a2=_p(self.eps_a2, cr),
@@ -392,11 +395,11 @@ class Problem:
                                             ctypes.byref(self.state), _p(v, self._cr))
 
     def frozen_sigma(self):
-        """sigma_eff = 1 / sqrt(W) (float32, input order) of every observation
-        at the current state, W the A/C weight."""
-        out = np.zeros(self.t.size, np.float32)
+        """sigma_eff = 1 / sqrt(W) (the Problem's real type, input order) of
+        every observation at the current state, W the A/C weight."""
+        out = self._zeros(self.t.size)
         self._L.orc_frozen_sigma(ctypes.byref(self.world), ctypes.byref(self.obs), ctypes.byref(self.state),
-                                 _p(out, c_f))
+                                 _p(out, self._cr))
         return out
 
     def iterate_sac(self):

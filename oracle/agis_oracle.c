@@ -450,11 +450,17 @@ static int64_t eps_slot(const orc_world_t* w, const orc_obs_t* obs, const orc_st
     return comp * st->n_buckets + bucket_of(w, ell);
 }
 
+/* The observation's uncertainty: sigma_l, or the frozen sigma_eff that
+ * replaces it. */
+static double obs_sigma(const orc_obs_t* obs, int64_t l) {
+    return obs->sigma_eff ? obs->sigma_eff[l] : (double)obs->sigma[l];
+}
+
 /* sigma~_l^2 = sigma_l^2 + eps_a^2(t_l) of the observation's component
  * (eq:W with eps_i = 0). */
 static double sigma_tilde2(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, int64_t l,
                            int64_t ell) {
-    double s = (double)obs->sigma[l];
+    double s = obs_sigma(obs, l);
     double v = s * s;
     if (w->robust) v += st->eps_a2[eps_slot(w, obs, st, l, ell)];
     return v;
@@ -490,7 +496,7 @@ void orc_excess_attitude_noise(const orc_world_t* w, const orc_obs_t* obs, orc_s
     for (int64_t l = 0; l < obs->n; ++l) {
         orc_fwd_t o;
         forward_one(w, obs, st, l, &o);
-        double s = (double)obs->sigma[l];
+        double s = obs_sigma(obs, l);
         bk[l] = eps_slot(w, obs, st, l, o.ell);
         v[l] = o.R * o.R - s * s - source_eps2(w, obs, st, l);     /* e09 */
     }
@@ -955,16 +961,17 @@ double orc_normal_quadratic(const orc_world_t* w, const orc_obs_t* obs, const or
 
 /* Frozen weights (the switch of the hybrid scheme, Sect. 4.7): each
  * observation's A/C weight W_l at the current state, as sigma_eff =
- * 1 / sqrt(W_l) rounded to float (W_l = 0: the largest finite float), in
- * input order.  A problem with these in place of sigma and no robust
- * weighting is the fixed weighted least-squares problem CG then solves. */
-void orc_frozen_sigma(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, float* sig) {
+ * 1 / sqrt(W_l) (W_l = 0, or sigma_eff beyond it: the largest finite
+ * float), in input order.  A problem with these in place of sigma and no
+ * robust weighting is the fixed weighted least-squares problem CG then
+ * solves. */
+void orc_frozen_sigma(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, double* sig) {
     for (int64_t l = 0; l < obs->n; ++l) {
         orc_fwd_t o;
         forward_one(w, obs, st, l, &o);
         double W = weight(w, obs, st, l, &o);
-        float se = W > 0.0 ? (float)(1.0 / sqrt(W)) : FLT_MAX;
-        if (!(se <= FLT_MAX)) se = FLT_MAX;
+        double se = W > 0.0 ? 1.0 / sqrt(W) : (double)FLT_MAX;
+        if (!(se <= (double)FLT_MAX)) se = (double)FLT_MAX;
         sig[l] = se;
     }
 }

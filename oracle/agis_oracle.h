@@ -50,6 +50,8 @@ typedef struct {
     const int32_t* src;       /* source index */
     const int8_t* fov;        /* +1 preceding, -1 following */
     const int32_t* cell;      /* calibration cell; -1: across-scan observation (eq:resAC) */
+    const double* sigma_eff;  /* NULL, or the uncertainty that replaces sigma: the frozen
+                                 sigma_eff of the hybrid scheme (orc_frozen_sigma) [rad] */
 } orc_obs_t;
 
 typedef struct {
@@ -144,9 +146,9 @@ void orc_normal_rhs(const orc_world_t* w, const orc_obs_t* obs, const orc_state_
  * v holds the source, then the attitude, then the calibration unknowns. */
 double orc_normal_quadratic(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, const double* v);
 
-/* Frozen weights: sigma_eff = 1 / sqrt(W_l) (float) of every observation at the
+/* Frozen weights: sigma_eff = 1 / sqrt(W_l) of every observation at the
  * current state, W_l the A/C weight (eq:dw, eq:W); input order. */
-void orc_frozen_sigma(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, float* sig);
+void orc_frozen_sigma(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, double* sig);
 
 /* --- Sect. 6.1: frame rotator --------------------------------------------- */
 /* eps_omega = (eps_X, eps_Y, eps_Z [rad], omega_X, omega_Y, omega_Z [rad/yr]).

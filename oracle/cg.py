@@ -68,8 +68,8 @@ def freeze(pr):
     from oracle import Problem
     consts = dict(pr.consts)
     consts["robust"] = 0
-    out = Problem(consts, pr.knots, pr.t, pr.eta_obs, pr.frozen_sigma(), pr.src, pr.fov, pr.cell, pr.s, pr.a,
-                  pr.c, precision=pr.precision)
+    out = Problem(consts, pr.knots, pr.t, pr.eta_obs, pr.sigma, pr.src, pr.fov, pr.cell, pr.s, pr.a, pr.c,
+                  precision=pr.precision, sigma_eff=pr.frozen_sigma())
     if getattr(pr, "var", None) is not None:
         out.var = pr.var.copy()        # the frame rotator's weights from the last S update
     return out

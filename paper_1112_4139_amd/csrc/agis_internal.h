@@ -80,8 +80,8 @@ struct agis_ctx {
     // frozen robust weights: sigma_eff = 1 / sqrt(W) of every observation in
     // both orders; while frozen, the plain kernels run with these in place
     // of sigma (one fixed weighted least-squares problem)
-    float* s_sig_eff = nullptr;
-    float* t_sig_eff = nullptr;
+    double* s_sig_eff = nullptr;          // frozen sigma_eff = W^-1/2 (hybrid scheme), source order
+    double* t_sig_eff = nullptr;          // the same in time order
     bool frozen = false;
     int64_t* iv_off = nullptr;           // [K + 1]
     int32_t* iv_cell = nullptr;          // [K][2] cell of the fov +1 / -1 observations (-1: none)
@@ -132,7 +132,7 @@ struct agis_ctx {
     int64_t s_fallback = 0;
     int64_t eps_cap = 0;
     bool eps_fused = false;
-    int robust_s_mode = 1;               // robust S block: 0 rows, varsigma and solves through HBM columns;
+    int robust_s_mode = 0;               // robust S block: 0 rows, varsigma and solves through HBM columns;
                                          // 1 rows to HBM columns, then varsigma and solves per source in
                                          // LDS; 2 the whole block per source in LDS (no HBM columns)
     bool robust_fused_eps = true;        // the excess-noise estimate in one kernel (values in LDS)
@@ -187,6 +187,7 @@ struct agis_ctx {
     int s_group = 16;
     int64_t select_reg_limit = INT64_MAX;   // robust quantiles: register-held keys up to this count
     int64_t select_reg_min_mean = 256;      // ... in the register kernel from this mean set size
+    bool select_pair = true;                // ... both intersextile order statistics in one set of passes
 
     agis::Timers tm;
     double last_ms[6] = {0, 0, 0, 0, 0, 0};
@@ -202,9 +203,6 @@ namespace agis {
 
 // robust mode in effect: 0, 1 or 2 (0 while the weights are frozen)
 inline int robust_now(const agis_ctx* ctx) { return ctx->frozen ? 0 : ctx->cfg.robust; }
-// sigma columns the plain kernels read
-inline const float* s_sig_now(const agis_ctx* ctx) { return ctx->frozen ? ctx->s_sig_eff : ctx->s_sig; }
-inline const float* t_sig_now(const agis_ctx* ctx) { return ctx->frozen ? ctx->t_sig_eff : ctx->t_sig; }
 
 int set_error(agis_ctx* ctx, int code, const std::string& msg);
 int hip_check(agis_ctx* ctx, hipError_t e, const char* what);

@@ -306,15 +306,16 @@ extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
     if (const char* e = std::getenv("AGIS_S_GROUP")) ctx->s_group = std::atoi(e);
     if (const char* e = std::getenv("AGIS_SELECT_REG_LIMIT")) ctx->select_reg_limit = std::atoll(e);
     if (const char* e = std::getenv("AGIS_SELECT_REG_MIN_MEAN")) ctx->select_reg_min_mean = std::atoll(e);
+    if (const char* e = std::getenv("AGIS_SELECT_PAIR")) ctx->select_pair = std::atoi(e) != 0;
     // robust kernel paths: AGIS_ROBUST_FUSED = 0 (every step through HBM
-    // columns), 1 (the excess-noise estimate in one kernel, the S block's
-    // varsigma and solves per source in LDS from the HBM rows; the default),
-    // 2 (the whole S block per source in LDS), 3 (the excess-noise estimate
-    // in one kernel, the S block through HBM columns)
+    // columns), 1 (the excess-noise estimate in one kernel, the S block
+    // through HBM columns; the default), 2 (the whole S block per source in
+    // LDS), 3 (the S block's rows to HBM columns, then varsigma and the
+    // solves per source in LDS)
     if (const char* e = std::getenv("AGIS_ROBUST_FUSED")) {
         const int v = std::atoi(e);
         ctx->robust_fused_eps = v >= 1;
-        ctx->robust_s_mode = v == 1 ? 1 : (v == 2 ? 2 : 0);
+        ctx->robust_s_mode = v == 3 ? 1 : (v == 2 ? 2 : 0);
     }
     if (const char* e = std::getenv("AGIS_ROBUST_MAX_CAP")) ctx->robust_max_cap = std::atoll(e);
     int rc = AGIS_OK;

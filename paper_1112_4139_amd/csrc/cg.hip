@@ -150,9 +150,10 @@ __global__ __launch_bounds__(CG_THREADS) void k_cg_dot2(int64_t n, const double*
 // with J_R p = -A . p_src + sum_n B_n dR/dq . p_att(n) + p_cal (A the design
 // row -dR/ds of Sect. 5.1.3, dR/dq of eq:dfadq) and J_D p = sum_n -2 q~ B_n
 // . p_att(n) (eq:dDldan); the source's triad comes from its direction r.
+template <typename SigT>
 __global__ __launch_bounds__(64) void k_cg_quad(DevConsts k, int64_t K, const int64_t* __restrict__ iv_off,
                                                 const double* __restrict__ ot, const double* __restrict__ oeta,
-                                                const float* __restrict__ osig, const int32_t* __restrict__ ocellfov,
+                                                const SigT* __restrict__ osig, const int32_t* __restrict__ ocellfov,
                                                 const int32_t* __restrict__ osrc, const SrcPrep* __restrict__ prep,
                                                 const double* __restrict__ knots, const KnotTab* __restrict__ ktab,
                                                 const double* __restrict__ a, const double* __restrict__ c,
@@ -269,9 +270,14 @@ void launch_cg_quad(agis_ctx* ctx, const double* p, double* part, double* out) {
         k_cg_quad_sum<<<1, CG_THREADS, 0, ctx->stream>>>(0, part, out);
         return;
     }
-    k_cg_quad<<<(unsigned)nb, 64, 0, ctx->stream>>>(ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, t_sig_now(ctx),
-                                                    ctx->t_cellfov, ctx->t_src, ctx->prep, ctx->knots, ctx->ktab,
-                                                    ctx->a, ctx->c, p, ctx->n_src, ctx->N, part);
+    if (ctx->frozen)
+        k_cg_quad<double><<<(unsigned)nb, 64, 0, ctx->stream>>>(
+            ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, ctx->t_sig_eff, ctx->t_cellfov, ctx->t_src, ctx->prep,
+            ctx->knots, ctx->ktab, ctx->a, ctx->c, p, ctx->n_src, ctx->N, part);
+    else
+        k_cg_quad<float><<<(unsigned)nb, 64, 0, ctx->stream>>>(
+            ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, ctx->t_sig, ctx->t_cellfov, ctx->t_src, ctx->prep,
+            ctx->knots, ctx->ktab, ctx->a, ctx->c, p, ctx->n_src, ctx->N, part);
     k_cg_quad_sum<<<1, CG_THREADS, 0, ctx->stream>>>(nb, part, out);
 }
 

@@ -46,11 +46,13 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
 }
 
 // AC: the observations may include across-scan ones (cell/fov code from
-// k.ac_cf0 on); the along-scan-only instance is the plain pass.
-template <int G, bool MIXED, bool AC>
+// k.ac_cf0 on); the along-scan-only instance is the plain pass.  SigT: the
+// type of the sigma column (float: the input; double: the frozen sigma_eff
+// of the hybrid scheme).
+template <int G, bool MIXED, bool AC, typename SigT>
 __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n_src, const int64_t* __restrict__ off,
                                                        const double* __restrict__ ot, const double* __restrict__ oeta,
-                                                       const float* __restrict__ osig,
+                                                       const SigT* __restrict__ osig,
                                                        const int32_t* __restrict__ ocell,
                                                        const int32_t* __restrict__ oell,
                                                        const double* __restrict__ knots,
@@ -104,7 +106,7 @@ __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n
     // observation's columns load at the top of an iteration, its gathers
     // after the current observation has been evaluated.
     double t_c = 0.0, e_c = 0.0, cal_c = 0.0;
-    float s_c = 1.0f;
+    SigT s_c = 1;
     int32_t ell_c = 3;
     bool ac_c = false;
     double a_c[16];
@@ -128,7 +130,7 @@ __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n
         const int64_t ln = l + G;
         const bool more = ln < l1;
         double t_n = 0.0, e_n = 0.0;
-        float s_n = 1.0f;
+        SigT s_n = 1;
         int32_t c_n = 0, ell_n = 3;
         if (more) {
             t_n = ot[ln];
@@ -220,11 +222,11 @@ constexpr int AC_XS = 33;               // LDS row stride (doubles) of the trans
 // running sums, converted to FP64 for the band solve.
 // AC: across-scan observations present (cell/fov code from k.ac_cf0 on):
 // their rows carry the AC attitude partials and no calibration entries.
-template <bool MIXED, bool AC>
+template <bool MIXED, bool AC, typename SigT>
 __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t K, const int64_t* __restrict__ iv_off,
                                                            const double* __restrict__ ot,
                                                            const double* __restrict__ oeta,
-                                                           const float* __restrict__ osig,
+                                                           const SigT* __restrict__ osig,
                                                            const int32_t* __restrict__ ocellfov,
                                                            const int32_t* __restrict__ osrc,
                                                            const SrcPrep* __restrict__ prep,
@@ -272,7 +274,7 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
     // weight zero
     int64_t base = l0;
     double t_c = 0.0, e_c = 0.0;
-    float s_c = 1.0f;
+    SigT s_c = 1;
     int32_t cf_c = 0;
     bool h_c = false;
     SrcPrep sp_c = {};
@@ -288,7 +290,7 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
     for (; base < l1; base += 64) {
         const int64_t bn = base + 64;
         double t_n = 0.0, e_n = 0.0;
-        float s_n = 1.0f;
+        SigT s_n = 1;
         int32_t cf_n = 0, src_n = 0;
         bool h_n = false;
         if (bn < l1) {
@@ -670,13 +672,19 @@ inline int groups_grid(int64_t n_items, int items_per_block) {
 
 }  // namespace
 
+#define AGIS_S_KERNEL(G, T)                                                                                    \
+    (ctx->cfg.precision == AGIS_MIXED                                                                          \
+         ? (ctx->has_ac ? k_source_update<G, true, true, T> : k_source_update<G, true, false, T>)               \
+         : (ctx->has_ac ? k_source_update<G, false, true, T> : k_source_update<G, false, false, T>))
+#define AGIS_S_ARGS(SIG)                                                                                       \
+    ctx->k, ctx->n_src, ctx->src_off, ctx->s_t, ctx->s_eta, SIG, ctx->s_cell, ctx->s_ell, ctx->knots, ctx->ktab,   \
+        ctx->a, ctx->c, ctx->s, ctx->prep, ctx->ds, ctx->qsrc, ctx->sdef, ctx->svar, ctx->src_order, ctx->rhs_s_out
 #define AGIS_S_LAUNCH(G)                                                                                       \
-    (ctx->cfg.precision == AGIS_MIXED ? (ctx->has_ac ? k_source_update<G, true, true> : k_source_update<G, true, false>) \
-                                      : (ctx->has_ac ? k_source_update<G, false, true> : k_source_update<G, false, false>)) \
-        <<<groups_grid(ctx->n_src, 256 / G), 256, 0, ctx->stream>>>(                                           \
-        ctx->k, ctx->n_src, ctx->src_off, ctx->s_t, ctx->s_eta, s_sig_now(ctx), ctx->s_cell, ctx->s_ell, ctx->knots, \
-        ctx->ktab, ctx->a, ctx->c, ctx->s, ctx->prep, ctx->ds, ctx->qsrc, ctx->sdef, ctx->svar, ctx->src_order, \
-        ctx->rhs_s_out)
+    if (ctx->frozen)                                                                                           \
+        AGIS_S_KERNEL(G, double)<<<groups_grid(ctx->n_src, 256 / G), 256, 0, ctx->stream>>>(                  \
+            AGIS_S_ARGS(ctx->s_sig_eff));                                                                      \
+    else                                                                                                       \
+        AGIS_S_KERNEL(G, float)<<<groups_grid(ctx->n_src, 256 / G), 256, 0, ctx->stream>>>(AGIS_S_ARGS(ctx->s_sig))
 
 void launch_source_update(agis_ctx* ctx) {
     if (ctx->n_src == 0) return;
@@ -688,14 +696,21 @@ void launch_source_update(agis_ctx* ctx) {
     }
 }
 
+template <typename T>
+static void ac_pass_with(agis_ctx* ctx, const T* sig) {
+    (ctx->cfg.precision == AGIS_MIXED ? (ctx->has_ac ? k_ac_pass<true, true, T> : k_ac_pass<true, false, T>)
+                                      : (ctx->has_ac ? k_ac_pass<false, true, T> : k_ac_pass<false, false, T>))
+        <<<(unsigned)((ctx->K + AC_WAVES - 1) / AC_WAVES), 64 * AC_WAVES, 0, ctx->stream>>>(
+        ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, sig, ctx->t_cellfov, ctx->t_src, ctx->prep, ctx->knots,
+        ctx->ktab, ctx->a, ctx->c, ctx->eps_a2, ctx->cfg.eps_bucket, robust_now(ctx), ctx->iv_sums, ctx->iv_cal);
+}
+
 void launch_ac_pass(agis_ctx* ctx) {
     if (ctx->K == 0) return;
-    (ctx->cfg.precision == AGIS_MIXED ? (ctx->has_ac ? k_ac_pass<true, true> : k_ac_pass<true, false>)
-                                      : (ctx->has_ac ? k_ac_pass<false, true> : k_ac_pass<false, false>))
-        <<<(unsigned)((ctx->K + AC_WAVES - 1) / AC_WAVES), 64 * AC_WAVES, 0, ctx->stream>>>(
-        ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, t_sig_now(ctx), ctx->t_cellfov, ctx->t_src, ctx->prep,
-        ctx->knots, ctx->ktab, ctx->a, ctx->c, ctx->eps_a2, ctx->cfg.eps_bucket, robust_now(ctx), ctx->iv_sums,
-        ctx->iv_cal);
+    if (ctx->frozen)
+        ac_pass_with(ctx, ctx->t_sig_eff);
+    else
+        ac_pass_with(ctx, ctx->t_sig);
 }
 
 void launch_band_solve(agis_ctx* ctx) {

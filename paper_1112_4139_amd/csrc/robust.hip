@@ -244,6 +244,155 @@ __device__ double reg_quantile7(const uint64_t (&kr)[KR], int64_t n, int64_t m, 
     return xj + (h - (double)j) * (key_value(kj1) - xj);
 }
 
+// Adds the digits dg of the lanes with in set to the histogram h: where
+// every such lane of the wavefront has the same digit, one lane adds their
+// count.
+__device__ __forceinline__ void count_digits(uint32_t* h, uint32_t dg, bool in) {
+    if (!in) return;
+    const int lane = threadIdx.x & 63;
+    const uint32_t d0 = __builtin_amdgcn_readfirstlane(dg);
+    const uint64_t am = __ballot(true);
+    const uint64_t same = __ballot(dg == d0);
+    if (same == am) {
+        if (lane == __ffsll((unsigned long long)am) - 1) atomicAdd(&h[d0], (uint32_t)__popcll(am));
+    } else {
+        atomicAdd(&h[dg], 1u);
+    }
+}
+
+// The 64 keys of a wavefront sorted ascending over its lanes (bitonic
+// network; every lane of the wavefront takes part).
+__device__ __forceinline__ uint64_t wave_sort64(uint64_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t lo = __shfl_xor((uint32_t)v, j, 64), hi = __shfl_xor((uint32_t)(v >> 32), j, 64);
+            const uint64_t o = ((uint64_t)hi << 32) | lo;
+            const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+            v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
+        }
+    }
+    return v;
+}
+
+// Rank k among the c <= 64 register-held keys under prefix (mask): the keys
+// gathered in lane order into cand (LDS, 64 keys), sorted over the
+// wavefront, the k-th taken.  One wavefront.
+__device__ uint64_t reg_finish_select(const uint64_t (&kr)[KR], int64_t n, int nr, uint64_t mask, uint64_t prefix,
+                                      int64_t k, uint64_t* cand) {
+    const int lane = threadIdx.x;
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint32_t base = 0;
+#pragma unroll
+    for (int r = 0; r < KR; ++r) {
+        const bool in = r < nr && lane + 64 * r < n && (kr[r] & mask) == prefix;
+        const uint64_t b = __ballot(in);
+        if (in) cand[base + __popcll(b & below)] = kr[r];
+        base += (uint32_t)__popcll(b);
+    }
+    __syncthreads();
+    uint64_t v = lane < (int)base ? cand[lane] : ~0ull;
+    __syncthreads();
+    v = wave_sort64(v);
+    const uint32_t lo = __shfl((uint32_t)v, (int)k, 64), hi = __shfl((uint32_t)(v >> 32), (int)k, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Type-7 quantiles at pa and pb of the m selected keys among the n
+// register-held ones (the others hold the largest key), both order
+// statistics found in one set of radix passes: each pass counts the digits
+// of the keys under either prefix into a histogram of its own (hist: 512
+// counts); once at most 64 keys share a statistic's prefix, they are
+// gathered and sorted over the wavefront and the statistic is read off
+// (cand: 64 keys in LDS).  Then one sweep finds, for each, whether the next
+// order statistic is the same key or the smallest key above it.
+__device__ void reg_quantile7_pair(const uint64_t (&kr)[KR], int64_t n, int64_t m, double pa, double pb,
+                                   uint32_t* hist, uint64_t* cand, double& qa, double& qb) {
+    if (m <= 0) {
+        qa = qb = 0.0;
+        return;
+    }
+    const int lane = threadIdx.x;
+    const int nr = (int)((n + 63) / 64);
+    const double ha_ = (double)(m - 1) * pa, hb_ = (double)(m - 1) * pb;
+    const int64_t ja = (int64_t)floor(ha_), jb = (int64_t)floor(hb_);
+    int64_t ka = ja, kb = jb;
+    uint64_t prea = 0, preb = 0, mask = 0;
+    bool done_a = false, done_b = false;
+    uint32_t* hista = hist;
+    uint32_t* histb = hist + 256;
+    for (int shift = 56; shift >= 0 && !(done_a && done_b); shift -= 8) {
+        for (int b = lane; b < 512; b += 64) hist[b] = 0u;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < KR; ++r) {
+            if (r < nr && lane + 64 * r < n) {
+                const uint64_t key = kr[r];
+                const uint32_t dg = (uint32_t)(key >> shift) & 255u;
+                count_digits(hista, dg, !done_a && (key & mask) == prea);
+                count_digits(histb, dg, !done_b && (key & mask) == preb);
+            }
+        }
+        __syncthreads();
+        uint32_t ca = 65u, cb = 65u;
+        if (!done_a) {
+            int d;
+            uint32_t bel;
+            radix_digit(hista, ka, d, bel);
+            prea |= (uint64_t)d << shift;
+            ka -= (int64_t)bel;
+            ca = hista[d];
+        }
+        if (!done_b) {
+            int d;
+            uint32_t bel;
+            radix_digit(histb, kb, d, bel);
+            preb |= (uint64_t)d << shift;
+            kb -= (int64_t)bel;
+            cb = histb[d];
+        }
+        mask |= 0xFFull << shift;
+        __syncthreads();
+        if (shift > 0 && !done_a && ca <= 64u) {
+            prea = reg_finish_select(kr, n, nr, mask, prea, ka, cand);
+            done_a = true;
+        }
+        if (shift > 0 && !done_b && cb <= 64u) {
+            preb = reg_finish_select(kr, n, nr, mask, preb, kb, cand);
+            done_b = true;
+        }
+    }
+    uint32_t cla = 0, clb = 0;
+    uint64_t mna = ~0ull, mnb = ~0ull;
+#pragma unroll
+    for (int r = 0; r < KR; ++r) {
+        if (lane + 64 * r < n) {
+            const uint64_t key = kr[r];
+            cla += key <= prea ? 1u : 0u;
+            clb += key <= preb ? 1u : 0u;
+            if (key > prea && key < mna) mna = key;
+            if (key > preb && key < mnb) mnb = key;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        cla += __shfl_xor(cla, o, 64);
+        clb += __shfl_xor(clb, o, 64);
+        uint32_t lo = __shfl_xor((uint32_t)mna, o, 64), hi = __shfl_xor((uint32_t)(mna >> 32), o, 64);
+        uint64_t other = ((uint64_t)hi << 32) | lo;
+        mna = other < mna ? other : mna;
+        lo = __shfl_xor((uint32_t)mnb, o, 64);
+        hi = __shfl_xor((uint32_t)(mnb >> 32), o, 64);
+        other = ((uint64_t)hi << 32) | lo;
+        mnb = other < mnb ? other : mnb;
+    }
+    const double xa = key_value(prea), xb = key_value(preb);
+    qa = ja + 1 >= m ? xa : xa + (ha_ - (double)ja) * (key_value((int64_t)cla >= ja + 2 ? prea : mna) - xa);
+    qb = jb + 1 >= m ? xb : xb + (hb_ - (double)jb) * (key_value((int64_t)clb >= jb + 2 ? preb : mnb) - xb);
+}
+
 // ------------------------------------------------------------- S, pass 0
 template <int G>
 __global__ __launch_bounds__(256, 2) void k_s_rows(DevConsts k, int64_t n_src, const int64_t* __restrict__ off,
@@ -340,18 +489,24 @@ __global__ __launch_bounds__(256, 2) void k_s_rows(DevConsts k, int64_t n_src, c
 
 // ------------------------------------------------ S, initial downweights
 // REG: keys of sets up to reg_limit in registers (fewer wavefronts per SIMD,
-// pays for large sets); otherwise re-read on every pass (small sets).
+// pays for large sets), the two order statistics selected one after the
+// other (REG 1) or in one set of radix passes (REG 2); otherwise (REG 0)
+// re-read on every pass (small sets).
 // varsigma of one kind of a source's records: half the intersextile range
 // of the selected (sel) h of the n; m of them are selected.
-template <bool REG, class Sel>
+template <int REG, class Sel>
 __device__ double half_intersextile(const double* __restrict__ h, int64_t n, int64_t m, int64_t reg_limit,
-                                    uint32_t* hist, Sel sel) {
+                                    uint32_t* hist, uint64_t* cand, Sel sel) {
     double q5, q1;
     if (REG && n <= reg_limit) {
         uint64_t kr[KR];
         load_keys(h, n, kr, sel);
-        q5 = reg_quantile7(kr, n, m, 5.0 / 6.0, hist);
-        q1 = reg_quantile7(kr, n, m, 1.0 / 6.0, hist);
+        if (REG == 2) {
+            reg_quantile7_pair(kr, n, m, 5.0 / 6.0, 1.0 / 6.0, hist, cand, q5, q1);
+        } else {
+            q5 = reg_quantile7(kr, n, m, 5.0 / 6.0, hist);
+            q1 = reg_quantile7(kr, n, m, 1.0 / 6.0, hist);
+        }
     } else {
         q5 = block_quantile7(h, n, m, 5.0 / 6.0, hist, sel);
         q1 = block_quantile7(h, n, m, 1.0 / 6.0, hist, sel);
@@ -363,17 +518,18 @@ __device__ double half_intersextile(const double* __restrict__ h, int64_t n, int
 // (kind 1) records of source i, whose residual scales differ by the ratio of
 // their formal errors.  cell: the records' cell/fov codes in source order,
 // or null where every record is along scan (AC false; vs[2 i + 1] = 0 then).
-template <bool REG, bool AC>
+template <int REG, bool AC>
 __global__ __launch_bounds__(64) void k_s_sigma(int64_t n_src, const int64_t* __restrict__ off,
                                                 const double* __restrict__ h, double* __restrict__ vs,
                                                 int64_t reg_limit, const int32_t* __restrict__ order,
                                                 const int32_t* __restrict__ cell, int32_t ac_cf0) {
-    __shared__ uint32_t hist[256];
+    __shared__ uint32_t hist[512];
+    __shared__ uint64_t cand[64];
     if ((int64_t)blockIdx.x >= n_src) return;
     const int64_t i = order[blockIdx.x];         // the largest sets first
     const int64_t l0 = off[i], n = off[i + 1] - l0;
     if (!AC) {
-        const double v = half_intersextile<REG>(h + l0, n, n, reg_limit, hist, AllOf{});
+        const double v = half_intersextile<REG>(h + l0, n, n, reg_limit, hist, cand, AllOf{});
         if (threadIdx.x == 0) {
             vs[2 * i] = v;
             vs[2 * i + 1] = 0.0;
@@ -384,7 +540,8 @@ __global__ __launch_bounds__(64) void k_s_sigma(int64_t n_src, const int64_t* __
     const int64_t m_ac = block_count(n, OfComponent{cf, ac_cf0, 1, true});
     for (int kind = 0; kind < 2; ++kind) {
         const int64_t m = kind ? m_ac : n - m_ac;
-        const double v = m > 0 ? half_intersextile<REG>(h + l0, n, m, reg_limit, hist, OfComponent{cf, ac_cf0, kind, true})
+        const double v = m > 0 ? half_intersextile<REG>(h + l0, n, m, reg_limit, hist, cand,
+                                                          OfComponent{cf, ac_cf0, kind, true})
                                : 0.0;
         if (threadIdx.x == 0) vs[2 * i + kind] = v;
     }
@@ -637,9 +794,13 @@ __global__ __launch_bounds__(64) void k_ac_resid(DevConsts k, int64_t K, const i
 }
 
 // Frozen weights: the robust weight of the A/C pass, W = w(R / sigma~) /
-// sigma~^2 with sigma~^2 = sigma^2 + eps_a^2 of the interval's bucket
-// (eq:dw, eq:W), at the current parameters, stored as sigma_eff = 1 / sqrt(W)
-// in FP32 (W = 0: the largest finite float).
+// sigma~^2 with sigma~^2 = sigma^2 + eps_a^2 of the record's component and
+// bucket (eq:dw, eq:W), at the current parameters, stored as sigma_eff = 1 /
+// sqrt(W) in FP64 (W = 0, or sigma_eff beyond it: the largest finite float).
+// FP64 because the weight of an outlier, exp(-|z| / 3), moves by ~1e-7
+// relative for a rounding-level change of its residual: in FP32 that is a
+// whole ulp, and a source whose solution hangs on one such record would
+// move with it.
 __global__ __launch_bounds__(64) void k_freeze_sigma(DevConsts k, int64_t K, const int64_t* __restrict__ iv_off,
                                                      const double* __restrict__ ot, const double* __restrict__ oeta,
                                                      const float* __restrict__ osig,
@@ -650,7 +811,7 @@ __global__ __launch_bounds__(64) void k_freeze_sigma(DevConsts k, int64_t K, con
                                                      const KnotTab* __restrict__ ktab, const double* __restrict__ a,
                                                      const double* __restrict__ c,
                                                      const double* __restrict__ eps_a2, int eps_bucket, int robust,
-                                                     float* __restrict__ sig_eff) {
+                                                     double* __restrict__ sig_eff) {
     const int lane = threadIdx.x;
     const int64_t j = blockIdx.x;
     if (j >= K) return;
@@ -666,14 +827,14 @@ __global__ __launch_bounds__(64) void k_freeze_sigma(DevConsts k, int64_t K, con
         const double sg = (double)osig[l];
         const double s2 = sg * sg + eps_a2[eps_slot(k, cf, j, eps_bucket)] + (robust == 2 ? sp.pad : 0.0);
         const double W = down_weight(o.R / sqrt(s2)) / s2;
-        float se = W > 0.0 ? (float)(1.0 / sqrt(W)) : FLT_MAX;
-        if (!(se <= FLT_MAX)) se = FLT_MAX;
+        double se = W > 0.0 ? 1.0 / sqrt(W) : (double)FLT_MAX;
+        if (!(se <= (double)FLT_MAX)) se = (double)FLT_MAX;
         sig_eff[l] = se;
     }
 }
 
-__global__ void k_gather_f32(int64_t n, const int32_t* __restrict__ from, const float* __restrict__ src,
-                             float* __restrict__ dst) {
+__global__ void k_gather_f64(int64_t n, const int32_t* __restrict__ from, const double* __restrict__ src,
+                             double* __restrict__ dst) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         dst[i] = src[from[i]];
 }
@@ -752,11 +913,14 @@ __device__ __forceinline__ void block_sums(double (&v)[NV], double* red, double*
     __syncthreads();
 }
 
-// k-th smallest (0-based, k < n) of the n doubles x[0..n) in LDS, as its
-// order key, by eight 8-bit radix passes of the whole block.  hist: 256
-// counts in LDS; bc: two ints in LDS for the broadcast of a pass's result.
+// k-th smallest (0-based, k < n) of the selected doubles among x[0..n) in
+// LDS, as its order key, by 8-bit radix passes of the whole block; once at
+// most 64 keys share the prefix, they are gathered into cand (64 keys in
+// LDS), sorted over the first wavefront and the k-th is read off.  hist: 256
+// counts in LDS; bc: four ints in LDS (a pass's result, the gather count).
 template <int NT, class Sel>
-__device__ uint64_t block_select_lds(const double* __restrict__ x, int n, int k, uint32_t* hist, int* bc, Sel sel) {
+__device__ uint64_t block_select_lds(const double* __restrict__ x, int n, int k, uint32_t* hist, int* bc,
+                                     uint64_t* cand, Sel sel) {
     uint64_t prefix = 0, mask = 0;
     for (int shift = 56; shift >= 0; shift -= 8) {
         for (int b = threadIdx.x; b < 256; b += NT) hist[b] = 0u;
@@ -787,13 +951,37 @@ __device__ uint64_t block_select_lds(const double* __restrict__ x, int n, int k,
             if (threadIdx.x == 0) {
                 bc[0] = digit;
                 bc[1] = (int)below;
+                bc[2] = (int)hist[digit];
+                bc[3] = 0;
             }
         }
         __syncthreads();
         prefix |= (uint64_t)bc[0] << shift;
         mask |= 0xFFull << shift;
         k -= bc[1];
+        const int c = bc[2];
         __syncthreads();
+        if (shift > 0 && c <= 64) {
+            // gather (in any order: the sort makes the result independent of it)
+            for (int j = threadIdx.x; j < n; j += NT) {
+                const uint64_t key = order_key(x[j]);
+                if ((key & mask) == prefix && sel(j)) cand[atomicAdd(&bc[3], 1)] = key;
+            }
+            __syncthreads();
+            if (threadIdx.x < 64) {
+                uint64_t v = (int)threadIdx.x < c ? cand[threadIdx.x] : ~0ull;
+                v = wave_sort64(v);
+                const uint32_t lo = __shfl((uint32_t)v, k, 64), hi = __shfl((uint32_t)(v >> 32), k, 64);
+                if (threadIdx.x == 0) {
+                    bc[0] = (int)lo;
+                    bc[1] = (int)hi;
+                }
+            }
+            __syncthreads();
+            const uint64_t key = ((uint64_t)(uint32_t)bc[1] << 32) | (uint32_t)bc[0];
+            __syncthreads();
+            return key;
+        }
     }
     return prefix;
 }
@@ -804,11 +992,12 @@ __device__ uint64_t block_select_lds(const double* __restrict__ x, int n, int k,
 // smallest selected key above it.  m is the same in every thread.
 template <int NT, class Sel>
 __device__ double block_quantile7_lds(const double* __restrict__ x, int n, int m, double p, uint32_t* hist, int* bc,
+                                      uint64_t* cand,
                                       double* red, double* out, Sel sel) {
     if (m <= 0) return 0.0;
     const double h = (double)(m - 1) * p;
     const int j = (int)floor(h);
-    const uint64_t kj = block_select_lds<NT>(x, n, j, hist, bc, sel);
+    const uint64_t kj = block_select_lds<NT>(x, n, j, hist, bc, cand, sel);
     const double xj = key_value(kj);
     if (j + 1 >= m) return xj;
     // count of selected keys <= kj, and the smallest selected key above it
@@ -864,7 +1053,8 @@ __global__ __launch_bounds__(NT) void k_s_robust(DevConsts k, int64_t n_src, int
     __shared__ uint32_t hist[256];
     __shared__ double red[(NT / 64) * 24];
     __shared__ double out[24];
-    __shared__ int bc[2];
+    __shared__ int bc[4];
+    __shared__ uint64_t cand[64];
     if ((int64_t)blockIdx.x >= n_src) return;
     uint8_t* cKind = reinterpret_cast<uint8_t*>(colm + 6 * cap);   // 1: across scan
     const int64_t i = order[blockIdx.x];
@@ -924,8 +1114,8 @@ __global__ __launch_bounds__(NT) void k_s_robust(DevConsts k, int64_t n_src, int
     for (int kind = 0; kind < 2; ++kind) {
         const int m = kind ? (int)n_ac[0] : n - (int)n_ac[0];
         const TagIs sel{cKind, (uint8_t)kind};
-        const double q5 = block_quantile7_lds<NT>(cH, n, m, 5.0 / 6.0, hist, bc, red, out, sel);
-        const double q1 = block_quantile7_lds<NT>(cH, n, m, 1.0 / 6.0, hist, bc, red, out, sel);
+        const double q5 = block_quantile7_lds<NT>(cH, n, m, 5.0 / 6.0, hist, bc, cand, red, out, sel);
+        const double q1 = block_quantile7_lds<NT>(cH, n, m, 1.0 / 6.0, hist, bc, cand, red, out, sel);
         vk[kind] = 0.5 * (q5 - q1);
     }
     if (threadIdx.x == 0) {
@@ -1011,7 +1201,8 @@ __global__ __launch_bounds__(NT) void k_eps_fused(DevConsts k, int64_t n_buckets
     __shared__ uint32_t hist[256];
     __shared__ double red[(NT / 64) * 24];
     __shared__ double out[24];
-    __shared__ int bc[2];
+    __shared__ int bc[4];
+    __shared__ uint64_t cand[64];
     const int64_t b = blockIdx.x;
     if (b >= n_buckets) return;
     uint8_t* comp = reinterpret_cast<uint8_t*>(vals + cap);
@@ -1040,7 +1231,7 @@ __global__ __launch_bounds__(NT) void k_eps_fused(DevConsts k, int64_t n_buckets
     }
     block_sums<NT, 3>(cnt, red, out);           // also the barrier after the values
     for (int cm = 0; cm < 3; ++cm) {
-        const double qv = block_quantile7_lds<NT>(vals, n, (int)cnt[cm], 0.68, hist, bc, red, out,
+        const double qv = block_quantile7_lds<NT>(vals, n, (int)cnt[cm], 0.68, hist, bc, cand, red, out,
                                                   TagIs{comp, (uint8_t)cm});
         if (threadIdx.x == 0) eps_a2[cm * n_buckets + b] = qv > 0.0 ? qv : 0.0;
     }
@@ -1108,8 +1299,9 @@ static void source_solve_columns(agis_ctx* ctx, int64_t k0, int64_t n) {
     const int64_t n_src = n;
     const int32_t* ac_cells = ctx->has_ac ? ctx->s_cell : nullptr;   // kinds of record matter with AC records
     const bool reg = select_in_registers(ctx, ctx->n_obs, ctx->n_src);
-    (ac_cells ? (reg ? k_s_sigma<true, true> : k_s_sigma<false, true>)
-              : (reg ? k_s_sigma<true, false> : k_s_sigma<false, false>))
+    const bool pair = ctx->select_pair;
+    (ac_cells ? (reg ? (pair ? k_s_sigma<2, true> : k_s_sigma<1, true>) : k_s_sigma<0, true>)
+              : (reg ? (pair ? k_s_sigma<2, false> : k_s_sigma<1, false>) : k_s_sigma<0, false>))
         <<<(unsigned)n_src, 64, 0, ctx->stream>>>(n_src, ctx->src_off, ctx->rcol + 4 * ctx->n_obs, ctx->vs,
                                                   select_reg_limit(ctx), order, ac_cells, ctx->k.ac_cf0);
     switch (ctx->s_group) {
@@ -1247,7 +1439,7 @@ void launch_freeze_sigma(agis_ctx* ctx) {
             ctx->knots, ctx->ktab, ctx->a, ctx->c, ctx->eps_a2, ctx->cfg.eps_bucket, ctx->cfg.robust, ctx->t_sig_eff);
     if (ctx->n_obs > 0) {
         const int64_t b = std::min<int64_t>((ctx->n_obs + 255) / 256, 65536);
-        k_gather_f32<<<(unsigned)b, 256, 0, ctx->stream>>>(ctx->n_obs, ctx->s_from_t, ctx->t_sig_eff,
+        k_gather_f64<<<(unsigned)b, 256, 0, ctx->stream>>>(ctx->n_obs, ctx->s_from_t, ctx->t_sig_eff,
                                                            ctx->s_sig_eff);
     }
 }

@@ -9,6 +9,8 @@ eq:diffrot2-3, since the coefficients' scale is unobservable).  Sources whose 5x
 (too few observations) are compared through their defect flag only, because
 "any valid solution" is acceptable there (Appendix C.3).
 """
+import types
+
 import numpy as np
 import pytest
 from scipy.ndimage import maximum_filter1d
@@ -54,11 +56,17 @@ def src_diff_uas(s_ref, s):
 
 # The per-parameter bound.  An FP64 implementation's rounding error in a
 # parameter p is modelled as e_p = c s_p g_p, g_p ~ N(0, 1): s_p is the
-# parameter's sensitivity to rounding-level noise in the residuals, c the
-# implementation's noise level in those units.  s_p is estimated as the RMS
-# of the parameter's responses to N_DRAWS independent N(0, (3e-16 rad)^2)
-# perturbations of every residual (3e-16 rad is ~2x the measured RMS
-# difference of the GPU's and the oracle's residuals).  With c <= 1,
+# parameter's sensitivity to the two kinds of rounding in which FP64
+# implementations differ -- rounding-level noise in the residuals, and the
+# order in which the sums over observations are taken (which perturbs the
+# normal matrices in proportion to the update, so that it dominates for
+# ill-conditioned sources with large updates) -- and c the implementation's
+# noise level in those units.  s_p is estimated as the RMS of the
+# parameter's responses to N_DRAWS independent draws, each of which adds
+# N(0, (3e-16 rad)^2) to every residual (~2x the measured RMS difference of
+# the GPU's and the oracle's residuals) and feeds the oracle its
+# observations in a random order (the oracle sums a source's and a cell's
+# observations in input order).  With c <= 1,
 # e_p / s_hat_p then follows Student's t with N_DRAWS degrees of freedom,
 # and FLOOR_FACTOR is its two-sided quantile for a false alarm of 1e-3 over
 # 1e5 parameters (scipy.stats.t.ppf(1 - 5e-9, 8) = 23.9).  An attitude
@@ -80,8 +88,9 @@ def fp64_floor(oracle_lib, world, eta, run, n_draws=N_DRAWS, ulp_noise=ULP_NOISE
     exact answer to ~1e-19 relative.  An FP64 implementation cannot do better
     than the FP64 rounding floor of each parameter; the tolerance is
     max(1e-3 uas, factor x s_hat_p) with s_hat_p the RMS response of the
-    parameter to n_draws perturbations of every residual by N(0, ulp_noise^2)
-    (see FLOOR_FACTOR above), and for attitude coefficients also factor_ref x
+    parameter to n_draws perturbations of every residual by N(0, ulp_noise^2),
+    each with the observations in a random order (see FLOOR_FACTOR above),
+    and for attitude coefficients also factor_ref x
     the FP64 oracle's largest deviation |O - X| among the 16 coefficients on
     either side.  run(problem) -> (s, a, c)."""
     X = [np.asarray(v, np.float64) for v in run(oracle_lib.problem_from_world(world, eta, "start", "extended"))]
@@ -89,7 +98,9 @@ def fp64_floor(oracle_lib, world, eta, run, n_draws=N_DRAWS, ulp_noise=ULP_NOISE
     ss = [np.zeros_like(src_diff_uas(O[0], O[0])), np.zeros((O[1].shape[0], 3)), np.zeros_like(O[2])]
     for k in range(n_draws):
         rng = np.random.default_rng(100 + k)
-        out = run(oracle_lib.problem_from_world(world, eta + rng.normal(0, ulp_noise, eta.shape), state="start"))
+        noisy = eta + rng.normal(0, ulp_noise, eta.shape)
+        perm = rng.permutation(eta.size)
+        out = run(oracle_lib.problem_from_world(reordered(world, perm), noisy[perm], state="start"))
         for i, f in enumerate(DIFFS):
             ss[i] += f(O[i], out[i]) ** 2
     sens = [np.sqrt(x / n_draws) for x in ss]
@@ -100,6 +111,19 @@ def fp64_floor(oracle_lib, world, eta, run, n_draws=N_DRAWS, ulp_noise=ULP_NOISE
     ref_a = maximum_filter1d(np.abs(DIFFS[1](X[1], O[1])), size=33, axis=0, mode="nearest")
     tol[1] = np.maximum(tol[1], factor_ref * ref_a)
     return X, O, tol
+
+
+OBS_FIELDS = ("t", "src", "fov", "cell", "sigma", "eps")
+
+
+def reordered(w, perm):
+    """The world with its observations taken in the order perm (sources,
+    attitude, calibration, knots and constants unchanged)."""
+    out = types.SimpleNamespace(**{k: v for k, v in vars(w).items() if k not in OBS_FIELDS})
+    for k in OBS_FIELDS:
+        if getattr(w, k, None) is not None:
+            setattr(out, k, getattr(w, k)[perm])
+    return out
 
 
 def cal_diff_uas(c_ref, c):

@@ -63,14 +63,14 @@ def test_excess_noise_parity(agis_mod, oracle_lib, tiny_robust):
 def test_robust_source_update_parity(agis_mod, oracle_lib, tiny_robust, path, monkeypatch):
     """The robust S update on its paths: every source in the one-kernel path
     (model, varsigma and solves per source in LDS), every source through HBM
-    columns (three kernels), the rows to HBM columns and then varsigma and
-    the solves per source in LDS (the default), and each of the LDS paths
+    columns (three kernels; the default), the rows to HBM columns and then
+    varsigma and the solves per source in LDS, and each of the LDS paths
     with the sources of more than 32 observations on the column kernels."""
     w, eta = tiny_robust
     env = {"one kernel": {"AGIS_ROBUST_FUSED": "2"}, "columns": {"AGIS_ROBUST_FUSED": "0"},
-           "rows then LDS": {"AGIS_ROBUST_FUSED": "1"},
+           "rows then LDS": {"AGIS_ROBUST_FUSED": "3"},
            "mixed": {"AGIS_ROBUST_FUSED": "2", "AGIS_ROBUST_MAX_CAP": "32"},
-           "rows then LDS, mixed": {"AGIS_ROBUST_FUSED": "1", "AGIS_ROBUST_MAX_CAP": "32"}}[path]
+           "rows then LDS, mixed": {"AGIS_ROBUST_FUSED": "3", "AGIS_ROBUST_MAX_CAP": "32"}}[path]
     for k in ("AGIS_ROBUST_FUSED", "AGIS_ROBUST_MAX_CAP"):
         monkeypatch.delenv(k, raising=False)
     for k, v in env.items():

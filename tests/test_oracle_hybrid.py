@@ -2,8 +2,8 @@
 (Sect. 4.7; Problem.frozen_sigma, oracle.cg.freeze).
 
 * At the state where they are frozen, the fixed weights reproduce the robust
-  A and C updates (whose weights they are) to the FP32 rounding of
-  sigma_eff, and the robust weight function: sigma_eff = sigma~ for
+  A and C updates (whose weights they are) to the rounding of sigma_eff =
+  W^-1/2 (FP64), and the robust weight function: sigma_eff = sigma~ for
   residuals within 2 sigma~, much larger for gross outliers.
 * CG on the frozen problem lowers the frozen objective sum W R^2 below what
   the robust simple iteration reaches in the same number of evaluations.
@@ -28,10 +28,10 @@ def test_frozen_weights_reproduce_the_robust_ac_updates(oracle_lib, outlier_worl
     o = pr.observe()
     s2 = w.sigma.astype(np.float64) ** 2 + pr.eps_a2[(o["ell"] - 3) // int(pr.consts["eps_bucket"])]
     z = np.abs(o["R"]) / np.sqrt(s2)
-    sig = fr.sigma.astype(np.float64)
+    sig = fr.sigma_eff
     inlier = z <= 2.0                                  # eq:dw: w = 1
-    np.testing.assert_allclose(sig[inlier], np.sqrt(s2[inlier]), rtol=1.2e-7)
-    assert np.all(sig[~inlier] >= np.sqrt(s2[~inlier]) * (1 - 1.2e-7))
+    np.testing.assert_allclose(sig[inlier], np.sqrt(s2[inlier]), rtol=1e-15)
+    assert np.all(sig[~inlier] >= np.sqrt(s2[~inlier]) * (1 - 1e-15))
     assert np.median(sig[bad] / np.sqrt(s2[bad])) > 10.0
     # the A and C updates at the freezing state
     for name in ("attitude_update", "calibration_update"):
@@ -42,7 +42,7 @@ def test_frozen_weights_reproduce_the_robust_ac_updates(oracle_lib, outlier_worl
         d_got = d_got[0] if isinstance(d_got, tuple) else d_got
         rel = np.abs(d_got - d_ref).max() / np.abs(d_ref).max()
         print(f"{name}: max |frozen - robust| / max |update| = {rel:.1e}")
-        assert rel <= 1e-5
+        assert rel <= 1e-10
 
 
 def test_hybrid_lowers_the_frozen_objective(oracle_lib, outlier_world):
@@ -52,7 +52,7 @@ def test_hybrid_lowers_the_frozen_objective(oracle_lib, outlier_world):
     for _ in range(3):
         pr.iterate(w.src_true)
     fr = ocg.freeze(pr)
-    W = 1.0 / fr.sigma.astype(np.float64) ** 2
+    W = 1.0 / fr.sigma_eff ** 2
 
     def objective(p):
         return float(np.sum(W * p.observe()["R"] ** 2))
