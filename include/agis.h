@@ -341,6 +341,16 @@ int agis_mlp_train(agis_ctx_t* ctx, int32_t which, int64_t n, const float* X, co
                    int32_t steps, int32_t batch, float lr, uint64_t seed, float* loss_out);
 /* sum over observations of R^2 / sigma^2 at the current parameters. */
 int agis_chi2(agis_ctx_t* ctx, double* q);
+/* The same sum as agis_chi2, bit for bit, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc): it allocates nothing.  Its partial sums live in a
+ * per-GPU static scratch array of 1 MiB (131,072 doubles), so it handles at
+ * most 131,071 x 64 = 8,388,544 knot intervals (AGIS_E_SHAPE beyond).  *q
+ * is host memory (where = AGIS_HOST) or device memory of the context's GPU
+ * (AGIS_DEVICE).  Every call on one GPU shares that GPU's scratch array:
+ * calls that overlap on one GPU (two host threads, or two streams running
+ * at once) race and must be serialised by the caller. */
+int agis_chi2_noalloc(agis_ctx_t* ctx, double* q, int where);
 /* Ungated: x <- x + s MLP(features) for sources and coefficients, then a new
  * history starts from x.  AGIS_E_STATE with fewer than four records. */
 int agis_learned_apply(agis_ctx_t* ctx);

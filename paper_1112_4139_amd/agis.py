@@ -108,6 +108,7 @@ _sig = {
     "agis_mlp_train": ([_ctx_p, c_i32, c_i64, _vp, _vp, ctypes.c_int, c_i32, c_i32, ctypes.c_float, ctypes.c_uint64,
                         _vp], ctypes.c_int),
     "agis_chi2": ([_ctx_p, P(c_d)], ctypes.c_int),
+    "agis_chi2_noalloc": ([_ctx_p, _vp, ctypes.c_int], ctypes.c_int),
     "agis_learned_apply": ([_ctx_p], ctypes.c_int),
     "agis_asi_step": ([_ctx_p, ctypes.c_int32, c_d, P(c_d), P(c_d)], ctypes.c_int),
     "agis_cg_iterate": ([_ctx_p, c_i32, c_i32, P(agis_cg_stats_t)], ctypes.c_int),
@@ -402,6 +403,19 @@ def agis_chi2(ctx):
     q = c_d()
     _check(_lib.agis_chi2(ctx, ctypes.byref(q)), ctx)
     return q.value
+
+
+def agis_chi2_noalloc(ctx, out=None):
+    """chi^2 through the allocation-free entry point: returned as a float
+    (host), or written into out[0] when out is a float64 torch tensor on the
+    device."""
+    if out is None:
+        q = c_d()
+        _check(_lib.agis_chi2_noalloc(ctx, ctypes.byref(q), AGIS_HOST), ctx)
+        return q.value
+    p, where, keep = _ptr(out, np.float64)
+    _check(_lib.agis_chi2_noalloc(ctx, p, where), ctx)
+    return out
 
 
 def agis_learned_apply(ctx):

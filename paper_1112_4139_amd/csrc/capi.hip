@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "agis_internal.h"
@@ -26,6 +27,28 @@ int hip_check(agis_ctx* ctx, hipError_t e, const char* what) {
 using namespace agis;
 
 static std::string g_create_error;
+
+// Scratch of agis_chi2_noalloc: the per-block partial sums of chi^2 and
+// their total, in a file-scope device array of which each GPU holds its own
+// copy until the process ends.  Host code reaches a GPU's copy only through
+// the address hipGetSymbolAddress returns with that GPU current (resolved
+// once per device by agis_create), never through the array's name.
+constexpr int64_t kScratchDoubles = 131072;               // 1 MiB per GPU
+static __device__ __align__(256) double scratch[kScratchDoubles];
+static std::mutex g_scratch_mu;
+static std::vector<double*> g_scratch_dev;                // per device ordinal (null: not resolved)
+
+// Address of the current device's copy of scratch (device must be current).
+static double* scratch_address(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_dev.size() <= device) g_scratch_dev.resize(device + 1, nullptr);
+    if (!g_scratch_dev[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch_dev[device] = static_cast<double*>(p);
+    }
+    return g_scratch_dev[device];
+}
 
 #define HIPCHK(expr)                                            \
     do {                                                        \
@@ -263,6 +286,11 @@ extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
     ctx->device = cfg->device;
     if (hipSetDevice(ctx->device) != hipSuccess) {
         g_create_error = "hipSetDevice failed";
+        delete ctx;
+        return AGIS_E_DEVICE;
+    }
+    if (!scratch_address(ctx->device)) {
+        g_create_error = "hipGetSymbolAddress of the scratch array failed";
         delete ctx;
         return AGIS_E_DEVICE;
     }
@@ -1251,6 +1279,27 @@ extern "C" int agis_chi2(agis_ctx_t* ctx, double* q) {
     launch_chi2(ctx, ctx->chi2_part, ctx->chi2_out);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(q, ctx->chi2_out, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return AGIS_OK;
+}
+
+extern "C" int agis_chi2_noalloc(agis_ctx_t* ctx, double* q, int where) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    if (!q) return set_error(ctx, AGIS_E_INVALID_ARG, "null q");
+    if (where != AGIS_HOST && where != AGIS_DEVICE) return set_error(ctx, AGIS_E_INVALID_ARG, "bad 'where'");
+    const int64_t nb = (ctx->K + 63) / 64;              // partial sums (K >= 1)
+    if (nb + 1 > kScratchDoubles)
+        return set_error(ctx, AGIS_E_SHAPE, "agis_chi2_noalloc: more than " +
+                                                std::to_string((kScratchDoubles - 1) * 64) + " knot intervals");
+    double* sp = scratch_address(ctx->device);
+    if (!sp) return set_error(ctx, AGIS_E_DEVICE, "scratch array not resolved on this device");
+    // every partial and the total are written before they are read: nothing
+    // has to start at zero
+    launch_chi2(ctx, sp, sp + nb);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(q, sp + nb, sizeof(double),
+                          where == AGIS_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return AGIS_OK;
 }
