@@ -87,7 +87,7 @@ def measured_traffic(kernel, workload, precision):
     if vals.get("kernel_source_sha1") != kernel_source_hash():
         return None
     key = kernel + " hbm_bytes_per_launch"
-    return float(vals[key]) if key in vals else None
+    return float(vals[key].split()[0]) if key in vals else None
 
 
 def workload_description(name, w):
