@@ -1186,7 +1186,11 @@ __global__ __launch_bounds__(NT) void k_s_robust(DevConsts k, int64_t n_src, int
 // eps_bucket knot intervals evaluates R^2 - sigma^2 (- eps_i^2 in robust mode
 // 2) of the bucket's observations into LDS, with the attitude component each
 // measures, and takes the 68th percentile of each component's values there
-// (eq e09): k_ac_resid and k_bucket_eps without the HBM round trip.
+// (eq e09): k_ac_resid and k_bucket_eps without the HBM round trip.  The
+// threads stream the bucket's observations as one range (an interval holds
+// a few hundred, so a pass per interval would leave many threads idle); the
+// bucket's attitude coefficients, knots, interval tables and offsets sit in
+// LDS, and each observation finds its interval there by bisection.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_eps_fused(DevConsts k, int64_t n_buckets, int64_t K, int eps_bucket, int cap,
                                                   const int64_t* __restrict__ iv_off, const double* __restrict__ ot,
@@ -1197,7 +1201,11 @@ __global__ __launch_bounds__(NT) void k_eps_fused(DevConsts k, int64_t n_buckets
                                                   const KnotTab* __restrict__ ktab, const double* __restrict__ a,
                                                   const double* __restrict__ c, int robust,
                                                   double* __restrict__ eps_a2) {
-    extern __shared__ double vals[];            // the bucket's values (at most cap), then cap component bytes
+    // dynamic LDS: the bucket's values (cap doubles), its eps_bucket + 3
+    // attitude coefficients (4 doubles each), eps_bucket + 6 knots,
+    // eps_bucket interval tables and eps_bucket + 1 offsets, then cap
+    // component bytes
+    extern __shared__ double vals[];
     __shared__ uint32_t hist[256];
     __shared__ double red[(NT / 64) * 24];
     __shared__ double out[24];
@@ -1205,29 +1213,43 @@ __global__ __launch_bounds__(NT) void k_eps_fused(DevConsts k, int64_t n_buckets
     __shared__ uint64_t cand[64];
     const int64_t b = blockIdx.x;
     if (b >= n_buckets) return;
-    uint8_t* comp = reinterpret_cast<uint8_t*>(vals + cap);
+    double* sa = vals + cap;
+    double* sk = sa + 4 * (eps_bucket + 3);
+    KnotTab* st = reinterpret_cast<KnotTab*>(sk + eps_bucket + 6);
+    int64_t* so = reinterpret_cast<int64_t*>(st + eps_bucket);
+    uint8_t* comp = reinterpret_cast<uint8_t*>(so + eps_bucket + 1);
     const int64_t j0 = b * eps_bucket;
     const int64_t j1 = j0 + eps_bucket < K ? j0 + eps_bucket : K;
-    const int64_t lb = iv_off[j0];
-    const int n = (int)(iv_off[j1] - lb);
+    const int nj = (int)(j1 - j0);
+    for (int e = threadIdx.x; e < 4 * (nj + 3); e += NT) sa[e] = a[4 * j0 + e];
+    for (int e = threadIdx.x; e < nj + 6; e += NT) sk[e] = knots[j0 + 1 + e];
+    for (int e = threadIdx.x; e < nj; e += NT) st[e] = ktab[j0 + e];
+    for (int e = threadIdx.x; e <= nj; e += NT) so[e] = iv_off[j0 + e];
+    __syncthreads();
+    const int64_t lb = so[0];
+    const int n = (int)(so[nj] - lb);
     double cnt[3] = {0.0, 0.0, 0.0};
-    for (int64_t j = j0; j < j1; ++j) {
-        const KnotTab kt = ktab[j];
-        const int64_t la = iv_off[j], le = iv_off[j + 1];
-        for (int64_t l = la + threadIdx.x; l < le; l += NT) {
-            const SrcPrep sp = prep[osrc[l]];
-            const int32_t cf = ocellfov[l];
-            const bool ac = cf >= k.ac_cf0;
-            ObsEval o;
-            observe(k, ot[l], oeta[l], c[cf >> 1], sp.r, sp.mu, sp.plx, a + 4 * j, knots + (j + 1), kt, o, ac);
-            const double sg = (double)osig[l];
-            vals[l - lb] = o.R * o.R - sg * sg - (robust == 2 ? sp.pad : 0.0);
-            const int cm = ac ? 1 + (cf & 1) : 0;
-            comp[l - lb] = (uint8_t)cm;
-            cnt[0] += cm == 0 ? 1.0 : 0.0;
-            cnt[1] += cm == 1 ? 1.0 : 0.0;
-            cnt[2] += cm == 2 ? 1.0 : 0.0;
+    for (int i = threadIdx.x; i < n; i += NT) {
+        const int64_t l = lb + i;
+        // the interval: the largest jj with so[jj] <= l
+        int lo = 0, hi = nj - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (so[mid] <= l) lo = mid;
+            else hi = mid - 1;
         }
+        const SrcPrep sp = prep[osrc[l]];
+        const int32_t cf = ocellfov[l];
+        const bool ac = cf >= k.ac_cf0;
+        ObsEval o;
+        observe(k, ot[l], oeta[l], c[cf >> 1], sp.r, sp.mu, sp.plx, sa + 4 * lo, sk + lo, st[lo], o, ac);
+        const double sg = (double)osig[l];
+        vals[i] = o.R * o.R - sg * sg - (robust == 2 ? sp.pad : 0.0);
+        const int cm = ac ? 1 + (cf & 1) : 0;
+        comp[i] = (uint8_t)cm;
+        cnt[0] += cm == 0 ? 1.0 : 0.0;
+        cnt[1] += cm == 1 ? 1.0 : 0.0;
+        cnt[2] += cm == 2 ? 1.0 : 0.0;
     }
     block_sums<NT, 3>(cnt, red, out);           // also the barrier after the values
     for (int cm = 0; cm < 3; ++cm) {
@@ -1260,7 +1282,10 @@ inline unsigned groups_grid(int64_t n_items, int items_per_block) {
 // Dynamic LDS of k_s_robust (six columns and a byte per record) and of
 // k_eps_fused (a value and a byte per record) for cap records.
 inline size_t s_lds_bytes(int64_t cap) { return (size_t)cap * (6 * sizeof(double) + 1); }
-inline size_t eps_lds_bytes(int64_t cap) { return (size_t)cap * (sizeof(double) + 1); }
+inline size_t eps_lds_bytes(int64_t cap, int64_t eps_bucket) {
+    return (size_t)cap * (sizeof(double) + 1) +
+           (size_t)(4 * (eps_bucket + 3) + (eps_bucket + 6) + 4 * eps_bucket + (eps_bucket + 1)) * sizeof(double);
+}
 
 }  // namespace
 
@@ -1418,10 +1443,10 @@ int robust_plan(agis_ctx* ctx, const std::vector<int64_t>& h_off, const std::vec
             mx = std::max(mx, iv[j1] - iv[j0]);
         }
         ctx->eps_cap = std::max<int64_t>(mx, 1);
-        if ((int64_t)eps_lds_bytes(ctx->eps_cap) <= dyn_max) {
+        if ((int64_t)eps_lds_bytes(ctx->eps_cap, ctx->cfg.eps_bucket) <= dyn_max) {
             HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eps_fused<EPS_NT>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)eps_lds_bytes(ctx->eps_cap)));
+                                       (int)eps_lds_bytes(ctx->eps_cap, ctx->cfg.eps_bucket)));
             ctx->eps_fused = true;
         }
     } else {
@@ -1447,7 +1472,7 @@ void launch_freeze_sigma(agis_ctx* ctx) {
 void launch_excess_noise(agis_ctx* ctx) {
     if (ctx->K == 0 || ctx->n_buckets == 0) return;
     if (eps_one_kernel(ctx) && ctx->eps_fused) {
-        k_eps_fused<EPS_NT><<<(unsigned)ctx->n_buckets, EPS_NT, eps_lds_bytes(ctx->eps_cap), ctx->stream>>>(
+        k_eps_fused<EPS_NT><<<(unsigned)ctx->n_buckets, EPS_NT, eps_lds_bytes(ctx->eps_cap, ctx->cfg.eps_bucket), ctx->stream>>>(
             ctx->k, ctx->n_buckets, ctx->K, ctx->cfg.eps_bucket, (int)ctx->eps_cap, ctx->iv_off, ctx->t_t, ctx->t_eta, ctx->t_sig,
             ctx->t_cellfov, ctx->t_src, ctx->prep, ctx->knots, ctx->ktab, ctx->a, ctx->c, ctx->cfg.robust,
             ctx->eps_a2);
