@@ -51,11 +51,11 @@ WORKLOADS = {
     "gaia5": (gaia_law, WorldSpec(n_src=2_000_000, years=5.0, knot_dt=30.0, ccd_per_transit=9,
                                   seg_len=240, seg_overlap=12, lambda_reg=1e-2, outlier_frac=0.01,
                                   robust=True)),
-    # iteration-scheme comparisons beyond the tiny world: the Gaia law, 40 000
-    # stars, 1 yr, 9 AF observations and one across-scan record per transit
-    # (~7M records, about 20x tiny), 120 s knots (~263k coefficients, ~27
-    # records per interval)
-    "mid9_ac": (gaia_law, WorldSpec(n_src=40000, years=1.0, knot_dt=120.0, ccd_per_transit=9,
+    # iteration-scheme comparisons beyond the tiny world: the miniature law,
+    # 40 000 stars, 1 yr, 9 AF observations and one across-scan record per
+    # transit (~7M records, about 20x tiny), 1200 s knots (~26k coefficients,
+    # ~27 transits per interval)
+    "mid9_ac": (mini_law, WorldSpec(n_src=40000, years=1.0, knot_dt=1200.0, ccd_per_transit=9,
                                     seg_len=240, seg_overlap=12, lambda_reg=1e-2, min_transits=6,
                                     ac_obs=True)),
     # robust parity cases: the tiny and small worlds with 1% outliers
