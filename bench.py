@@ -196,9 +196,9 @@ def main():
                     help="gaia5: 2M sources, 5 yr, robust (the largest single-GPU configuration); gaia1: 1M "
                          "sources, 1 yr")
     ap.add_argument("--seg-len", type=int, default=None)
-    ap.add_argument("--cpu-days", type=int, default=24, help="days of observations the oracle iterates over "
+    ap.add_argument("--cpu-days", type=int, default=48, help="days of observations the oracle iterates over "
                                                             "(all threads of the host share)")
-    ap.add_argument("--cpu-days-1t", type=int, default=3, help="... and on one thread")
+    ap.add_argument("--cpu-days-1t", type=int, default=6, help="... and on one thread")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="mixed: FP32 partials and compensated FP32 normal-equation sums")
@@ -258,7 +258,8 @@ def main():
     log(f"store built: {sz}")
 
     s_group = agis.agis_autotune(ctx)
-    log(f"autotuned: {s_group} lanes per source")
+    tuning = agis.agis_get_tuning(ctx)
+    log(f"autotuned: {tuning}")
 
     def step():
         if args.scheme == "cg":
@@ -333,6 +334,8 @@ def main():
            "scaling": "weak", "vs_baseline": None,
            "dtype": "f64" if args.precision == "fp64" else "f64 model, f32 partials and sums", "data": "synthetic",
            "config": {**workload_description(wname, w), "lanes_per_source": s_group,
+                      **({"robust_s_path": ["hbm columns", "rows in hbm, solves in lds", "all in lds"][
+                          tuning["robust_s_path"]]} if w.spec.robust else {}),
                       **({"scheme": "conjugate gradients"} if args.scheme == "cg" else {})},
            "kernel_ms": kavg, "roofline": roofline,
            "cpu_baseline": cpu}

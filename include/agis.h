@@ -248,8 +248,19 @@ int agis_iterate_graph(agis_ctx_t* ctx, int32_t n_iter);
  * problem (twice each, from the current state, restored bit for bit
  * afterwards: sources, their derived data and variances) and keeps the
  * fastest; *s_group (may be NULL) receives it.  The default, 16, is the best
- * for ~160 observations per source. */
+ * for ~160 observations per source.  In robust mode 1 it then times the
+ * paths of the S block the same way (per-observation columns in HBM with
+ * the intersextile order statistics selected together or one after the
+ * other; the rows in HBM and the inner iteration per source in LDS; the
+ * whole block per source in LDS) and keeps the fastest; the paths give the
+ * same numbers up to the order of their sums. */
 int agis_autotune(agis_ctx_t* ctx, int32_t* s_group);
+/* The launch choices in effect: out[0] lanes per source of the S block,
+ * out[1] the robust S path (0 HBM columns, 1 rows in HBM then LDS, 2 all in
+ * LDS), out[2] 1 if the columns path selects both intersextile order
+ * statistics in one set of radix passes, out[3] 1 if the excess attitude
+ * noise is estimated in one kernel. */
+int agis_get_tuning(const agis_ctx_t* ctx, int32_t out[4]);
 
 /* Residuals R_l (eq:resAL) at the current parameters, in the input order of
  * agis_load_observations. */

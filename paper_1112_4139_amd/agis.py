@@ -89,6 +89,7 @@ _sig = {
     "agis_iterate": ([_ctx_p, c_i32, P(agis_iter_stats_t)], ctypes.c_int),
     "agis_iterate_graph": ([_ctx_p, ctypes.c_int32], ctypes.c_int),
     "agis_autotune": ([_ctx_p, P(c_i32)], ctypes.c_int),
+    "agis_get_tuning": ([_ctx_p, P(c_i32)], ctypes.c_int),
     "agis_residuals": ([_ctx_p, _vp, ctypes.c_int], ctypes.c_int),
     "agis_problem_size": ([_ctx_p, P(c_i64), P(c_i64), P(c_i64), P(c_i64), P(c_i64)], ctypes.c_int),
     "agis_kernel_times": ([_ctx_p, P(c_d)], ctypes.c_int),
@@ -291,6 +292,16 @@ def agis_autotune(ctx):
     g = c_i32()
     _check(_lib.agis_autotune(ctx, ctypes.byref(g)), ctx)
     return g.value
+
+
+def agis_get_tuning(ctx):
+    """The launch choices in effect: lanes per source, robust S path (0 HBM
+    columns, 1 rows then LDS, 2 all in LDS), paired quantile selection, fused
+    excess-noise estimate."""
+    out = (c_i32 * 4)()
+    _check(_lib.agis_get_tuning(ctx, out), ctx)
+    return dict(lanes_per_source=out[0], robust_s_path=out[1], paired_selection=bool(out[2]),
+                fused_excess_noise=bool(out[3]))
 
 
 def agis_residuals(ctx, out=None):

@@ -876,14 +876,10 @@ extern "C" int agis_autotune(agis_ctx_t* ctx, int32_t* s_group) {
         if (e == hipSuccess) e = hipMemcpyAsync(bs, ctx->s, 5 * ns * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(bv, ctx->svar, 5 * ns * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(bp, ctx->prep, ns * sizeof(agis::SrcPrep), hipMemcpyDeviceToDevice, ctx->stream);
-        // the source update for each group size, twice (the faster run
-        // counts), each from the saved state
-        const int cand[3] = {8, 16, 32};
-        int best = ctx->s_group;
-        float best_ms = 3.0e38f;
-        for (int ci = 0; ci < 3 && e == hipSuccess && rc == AGIS_OK; ++ci) {
+        // the faster of two source updates, each from the saved state
+        auto time_source = [&](float& best_ms) -> bool {
+            bool better = false;
             for (int rep = 0; rep < 2 && e == hipSuccess && rc == AGIS_OK; ++rep) {
-                ctx->s_group = cand[ci];
                 e = restore();
                 if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
                 if (e == hipSuccess) rc = run_source(ctx);
@@ -893,11 +889,52 @@ extern "C" int agis_autotune(agis_ctx_t* ctx, int32_t* s_group) {
                 if (e == hipSuccess && rc == AGIS_OK) e = hipEventElapsedTime(&ms, e0, e1);
                 if (e == hipSuccess && rc == AGIS_OK && ms < best_ms) {
                     best_ms = ms;
-                    best = cand[ci];
+                    better = true;
                 }
             }
+            return better;
+        };
+        // lanes per source
+        const int cand[3] = {8, 16, 32};
+        int best = ctx->s_group;
+        float best_ms = 3.0e38f;
+        for (int ci = 0; ci < 3 && e == hipSuccess && rc == AGIS_OK; ++ci) {
+            ctx->s_group = cand[ci];
+            if (time_source(best_ms)) best = cand[ci];
         }
         ctx->s_group = best;
+        // robust mode 1: the path of the S block (HBM columns, or the
+        // per-source LDS kernels after the rows or for the whole block), and
+        // for the columns the quantile kernel (both order statistics in one
+        // set of passes or one after the other); the same numbers up to the
+        // order of the sums (the quantiles bit for bit)
+        if (ctx->cfg.robust == 1 && ctx->rcol && e == hipSuccess && rc == AGIS_OK) {
+            std::vector<int64_t> h_off(ns + 1);
+            std::vector<int32_t> order(ns);
+            e = hipMemcpyAsync(h_off.data(), ctx->src_off, (ns + 1) * sizeof(int64_t), hipMemcpyDeviceToHost,
+                               ctx->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(order.data(), ctx->src_order, ns * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                   ctx->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+            struct Path { int mode; bool pair; };
+            const Path paths[4] = {{0, true}, {0, false}, {1, true}, {2, true}};
+            Path keep{ctx->robust_s_mode, ctx->select_pair};
+            float path_ms = 3.0e38f;
+            for (int pi = 0; pi < 4 && e == hipSuccess && rc == AGIS_OK; ++pi) {
+                ctx->robust_s_mode = paths[pi].mode;
+                ctx->select_pair = paths[pi].pair;
+                bool need = true;
+                rc = robust_plan(ctx, h_off, order, &need);
+                if (rc == AGIS_OK && time_source(path_ms)) keep = paths[pi];
+            }
+            ctx->robust_s_mode = keep.mode;
+            ctx->select_pair = keep.pair;
+            if (rc == AGIS_OK && e == hipSuccess) {
+                bool need = true;
+                rc = robust_plan(ctx, h_off, order, &need);
+            }
+        }
         ++ctx->gen;                      // launch shapes changed
         if (e == hipSuccess) e = restore();
         if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -906,6 +943,15 @@ extern "C" int agis_autotune(agis_ctx_t* ctx, int32_t* s_group) {
         if (e != hipSuccess) return hip_check(ctx, e, "autotuning");
     }
     if (s_group) *s_group = ctx->s_group;
+    return AGIS_OK;
+}
+
+extern "C" int agis_get_tuning(const agis_ctx_t* ctx, int32_t out[4]) {
+    if (!ctx || !out) return AGIS_E_INVALID_ARG;
+    out[0] = ctx->s_group;
+    out[1] = ctx->robust_s_mode;
+    out[2] = ctx->select_pair ? 1 : 0;
+    out[3] = ctx->eps_fused ? 1 : 0;
     return AGIS_OK;
 }
 

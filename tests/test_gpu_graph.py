@@ -133,3 +133,38 @@ def test_autotune_keeps_state(agis_mod, tiny, monkeypatch):
     assert _same(_state(agis_mod, ctx, w), _state(agis_mod, ref, w))
     agis_mod.agis_destroy(ctx)
     agis_mod.agis_destroy(ref)
+
+
+@pytest.mark.parametrize("ac", [False, True])
+def test_autotune_robust_path_keeps_state(agis_mod, oracle_lib, ac, monkeypatch):
+    """In robust mode 1 the autotuner also picks the S block's path: the
+    state is restored bit for bit, the choice is reported by
+    agis_get_tuning, and a following robust source update equals that of a
+    context fixed to the same lanes per source, path and quantile kernel."""
+    w = C.make("tiny_robust", ac_obs=ac)
+    eta = oracle_lib.observed_field_angles(w)
+    ctx = _ctx(agis_mod, w, eta)
+    agis_mod.agis_iterate(ctx, 2, stats=False)
+    before = _state(agis_mod, ctx, w, robust=True)
+    g = agis_mod.agis_autotune(ctx)
+    tun = agis_mod.agis_get_tuning(ctx)
+    print(f"autotuned (tiny_robust{'+ac' if ac else ''}): {tun}")
+    assert tun["lanes_per_source"] == g and tun["robust_s_path"] in (0, 1, 2)
+    assert _same(before, _state(agis_mod, ctx, w, robust=True))
+    env = {"AGIS_S_GROUP": str(g), "AGIS_SELECT_PAIR": "1" if tun["paired_selection"] else "0",
+           "AGIS_ROBUST_FUSED": {0: "1", 1: "3", 2: "2"}[tun["robust_s_path"]]}
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    ref = _ctx(agis_mod, w, eta)
+    for k in env:
+        monkeypatch.delenv(k)
+    assert agis_mod.agis_get_tuning(ref) == tun
+    for c in (ctx, ref):
+        agis_mod.agis_set_sources(c, before[0])
+        agis_mod.agis_set_attitude(c, before[1])
+        agis_mod.agis_set_calibration(c, before[2])
+        agis_mod.agis_set_excess_noise(c, before[3])
+        agis_mod.agis_source_update(c)
+    assert _same(_state(agis_mod, ctx, w), _state(agis_mod, ref, w))
+    agis_mod.agis_destroy(ctx)
+    agis_mod.agis_destroy(ref)
