@@ -34,16 +34,17 @@ def _structs(c_r):
         _fields_ = [("n_knots", c_i64), ("knots", P(c_r)), ("gamma_c", c_r), ("t_ep", c_r), ("t_fr", c_r),
                     ("lambda_reg", c_r), ("seg_len", c_i32), ("seg_overlap", c_i32), ("eph_radius_au", c_r),
                     ("eph_L0", c_r), ("eph_Lrate", c_r), ("eps_obl", c_r), ("au_m", c_r), ("c_mps", c_r),
-                    ("year_s", c_r), ("robust", c_i32), ("eps_bucket", c_i32)]
+                    ("year_s", c_r), ("robust", c_i32), ("eps_bucket", c_i32), ("geo_ccds", c_i32)]
 
     class Obs(ctypes.Structure):
         _fields_ = [("n", c_i64), ("t", P(c_r)), ("eta_obs", P(c_r)), ("sigma", P(c_f)), ("src", P(c_i32)),
-                    ("fov", P(c_i8)), ("cell", P(c_i32)), ("sigma_eff", P(c_r))]
+                    ("fov", P(c_i8)), ("cell", P(c_i32)), ("sigma_eff", P(c_r)), ("ccd", P(c_i8)),
+                    ("mu", P(c_f))]
 
     class State(ctypes.Structure):
         _fields_ = [("n_src", c_i64), ("n_att", c_i64), ("n_cells", c_i64), ("s", P(c_r)), ("a", P(c_r)),
                     ("c", P(c_r)), ("n_buckets", c_i64), ("eps_a2", P(c_r)), ("src_eps2", P(c_r)),
-                    ("src_D", P(c_r))]
+                    ("src_D", P(c_r)), ("geo", P(c_r))]
 
     return World, Obs, State
 
@@ -247,7 +248,7 @@ class Problem:
     """
 
     def __init__(self, consts, knots, t, eta_obs, sigma, src, fov, cell, s, a, c, precision="double",
-                 sigma_eff=None):
+                 sigma_eff=None, ccd=None, mu=None, geo=None):
         self.precision = precision
         self._cr, self._dt = PRECISIONS[precision][0], PRECISIONS[precision][1]
         self._World, self._Obs, self._State = _STRUCTS[precision]
@@ -258,6 +259,16 @@ class Problem:
         self.sigma = np.ascontiguousarray(sigma, dtype=np.float32)
         # the frozen sigma_eff of the hybrid scheme, replacing sigma (or None)
         self.sigma_eff = None if sigma_eff is None else self._arr(sigma_eff).copy()
+        # geometric calibration (consts geo_ccds > 0): CCD index and AC pixel
+        # coordinate per record, coefficients [n_cells][geo_ccds][3]
+        geo_ccds = int(consts.get("geo_ccds", 0) or 0)
+        if geo_ccds > 0:
+            self.ccd = np.ascontiguousarray(ccd, dtype=np.int8)
+            self.mu = np.ascontiguousarray(mu, dtype=np.float32)
+            self.geo = self._arr(np.reshape(geo, -1)).copy()
+            assert self.geo.size == np.size(c) * geo_ccds * 3
+        else:
+            self.ccd = self.mu = self.geo = None
         self.src = np.ascontiguousarray(src, dtype=np.int32)
         self.fov = np.ascontiguousarray(fov, dtype=np.int8)
         self.cell = np.ascontiguousarray(cell, dtype=np.int32)
@@ -272,7 +283,8 @@ class Problem:
                                  eph_radius_au=consts["eph_radius_au"], eph_L0=consts["eph_L0"],
                                  eph_Lrate=consts["eph_Lrate"], eps_obl=consts["eps_obl"], au_m=consts["au_m"],
                                  c_mps=consts["c_mps"], year_s=consts["year_s"],
-                                 robust=int(consts.get("robust", 0)), eps_bucket=int(consts.get("eps_bucket", 8)))
+                                 robust=int(consts.get("robust", 0)), eps_bucket=int(consts.get("eps_bucket", 8)),
+                                 geo_ccds=geo_ccds)
         n_iv = self.knots.size - 7
         if self.world.robust:
             # three components (along scan, across scan preceding and
@@ -296,17 +308,21 @@ class Problem:
         cr = self._cr
         self.obs = self._Obs(n=self.t.size, t=_p(self.t, cr), eta_obs=_p(self.eta_obs, cr),
                              sigma=_p(self.sigma, c_f), src=_p(self.src, c_i32), fov=_p(self.fov, c_i8),
-                             cell=_p(self.cell, c_i32), sigma_eff=_p(self.sigma_eff, cr))
+                             cell=_p(self.cell, c_i32), sigma_eff=_p(self.sigma_eff, cr),
+                             ccd=_p(self.ccd, c_i8), mu=_p(self.mu, c_f))
         self.state = self._State(n_src=self.s.shape[0], n_att=self.a.shape[0], n_cells=self.c.size,
                                  s=_p(self.s, cr), a=_p(self.a, cr), c=_p(self.c, cr),
                                  n_buckets=self.eps_a2.size // 3, eps_a2=_p(self.eps_a2, cr),
-                                 src_eps2=_p(self.src_eps2, cr), src_D=_p(self.src_D, cr))
+                                 src_eps2=_p(self.src_eps2, cr), src_D=_p(self.src_D, cr), geo=_p(self.geo, cr))
 
     def set_eta_obs(self, eta_obs):
         self.eta_obs = self._arr(eta_obs).copy()
         self._refresh()
 
-    def set_state(self, s=None, a=None, c=None, eps_a2=None):
+    def set_state(self, s=None, a=None, c=None, eps_a2=None, geo=None):
+        if geo is not None:
+            assert np.size(geo) == self.geo.size
+            self.geo = self._arr(np.reshape(geo, -1)).copy()
         if eps_a2 is not None:
             assert np.size(eps_a2) == self.eps_a2.size
             self.eps_a2 = self._arr(eps_a2).copy()
@@ -372,7 +388,9 @@ class Problem:
         return self.eps_a2.copy()
 
     def calibration_update(self):
-        d = np.zeros_like(self.c)
+        """The calibration update (per cell, or with the geometric model the
+        flat [n_cells][geo_ccds][3] coefficients), applied to the state."""
+        d = np.zeros_like(self.c if self.geo is None else self.geo)
         self._L.orc_calibration_update(ctypes.byref(self.world), ctypes.byref(self.obs), ctypes.byref(self.state),
                                        _p(d, self._cr))
         return d
@@ -439,10 +457,12 @@ def problem_from_world(world, eta_obs=None, state="start", precision="double"):
     eta = np.zeros(n) if eta_obs is None else eta_obs
     if state == "start":
         s, a, c = world.src_start, world.att_start, world.cal_start
+        geo = getattr(world, "geo_start", None)
     else:
         s, a, c = world.src_true, world.att_true, world.cal_true
+        geo = getattr(world, "geo_true", None)
     return Problem(world.consts, world.knots, world.t, eta, world.sigma, world.src, world.fov, world.cell, s, a, c,
-                   precision=precision)
+                   precision=precision, ccd=getattr(world, "ccd", None), mu=getattr(world, "mu", None), geo=geo)
 
 
 def observed_field_angles(world, chunk=1 << 24):
@@ -455,14 +475,20 @@ def observed_field_angles(world, chunk=1 << 24):
     out = np.empty(n)
     consts = dict(world.consts)
     consts["robust"] = 0                       # the model alone; no robust state
+    geo_ccds = int(consts.get("geo_ccds", 0) or 0)
     for i0 in range(0, max(n, 1), chunk):
         i1 = min(n, i0 + chunk)
         sl = slice(i0, i1)
         pr = Problem(consts, world.knots, world.t[sl], np.zeros(i1 - i0), world.sigma[sl], world.src[sl],
-                     world.fov[sl], world.cell[sl], world.src_true, world.att_true, world.cal_true)
+                     world.fov[sl], world.cell[sl], world.src_true, world.att_true, world.cal_true,
+                     ccd=None if geo_ccds == 0 else world.ccd[sl], mu=None if geo_ccds == 0 else world.mu[sl],
+                     geo=None if geo_ccds == 0 else world.geo_true)
         o = pr.observe()
         cell = world.cell[sl]
         ac = cell < 0
-        al = np.asarray(o["eta"]) - world.cal_true[np.where(ac, 0, cell)]
+        # the residual of eta_obs = 0 is the calibration minus the computed
+        # field angle (eq:resAL), so eta_obs = eta - calibration + noise
+        # makes it the noise at the truth
+        al = -np.asarray(o["R"])
         out[sl] = np.where(ac, np.asarray(o["zeta"]), al) + world.eps[sl]
     return out

@@ -278,6 +278,36 @@ typedef struct {
     int ac;                     /* 1: across-scan observation (cell < 0) */
 } orc_fwd_t;
 
+/* Shifted Legendre polynomial of degree r = 0, 1, 2, orthogonal on [0, 1]
+ * (eq:etazeta). */
+static double shifted_legendre(int r, double x) {
+    if (r == 0) return 1.0;
+    if (r == 1) return 2.0 * x - 1.0;
+    return 6.0 * x * x - 6.0 * x + 1.0;
+}
+
+/* Index of the first of the three geometric coefficients of an along-scan
+ * record: its cell and CCD. */
+static int64_t geo_index(const orc_world_t* w, const orc_obs_t* obs, int64_t l) {
+    return 3 * ((int64_t)obs->cell[l] * w->geo_ccds + obs->ccd[l]);
+}
+
+/* Argument of the shifted Legendre polynomials: the AC pixel coordinate
+ * mapped to [0, 1] (eq:etazeta). */
+static double geo_x(const orc_obs_t* obs, int64_t l) { return ((double)obs->mu[l] - 13.5) / 1966.0; }
+
+/* The large-scale AL geometric calibration of an along-scan record
+ * (eq:etazeta): sum over r of its cell and CCD's coefficients times
+ * L*_r(x); 0 without the geometric model or across scan. */
+static double geo_term(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, int64_t l) {
+    if (w->geo_ccds <= 0 || obs->cell[l] < 0) return 0.0;
+    const int64_t g = geo_index(w, obs, l);
+    const double x = geo_x(obs, l);
+    double v = 0.0;
+    for (int r = 0; r < 3; ++r) v += st->geo[g + r] * shifted_legendre(r, x);
+    return v;
+}
+
 /* Sect. 3.2-3.5: the computed field angles and the residual: eq:resAL for
  * an along-scan observation, eq:resAC (observed minus computed zeta, no
  * calibration term) for an across-scan one, marked by cell < 0. */
@@ -321,7 +351,7 @@ static void forward_one(const orc_world_t* w, const orc_obs_t* obs, const orc_st
     o->eta = o->phi - o->f * 0.5 * w->gamma_c;
     /* eq:resAL with the generic calibration model (eq:generic1); eq:resAC */
     o->ac = obs->cell[l] < 0;
-    o->R = o->ac ? obs->eta_obs[l] - o->zeta : obs->eta_obs[l] + st->c[obs->cell[l]] - o->eta;
+    o->R = o->ac ? obs->eta_obs[l] - o->zeta : obs->eta_obs[l] + geo_term(w, obs, st, l) + st->c[obs->cell[l]] - o->eta;
 }
 
 /* Sect. 5.1.3: design row -dR/ds for (alpha*, delta, parallax, mu_alpha*,
@@ -835,7 +865,72 @@ int64_t orc_attitude_update(const orc_world_t* w, const orc_obs_t* obs, orc_stat
  * goes through C1-C3; then the constraint projection eq:calCon with one
  * constraint per day, c_P + c_F = 0 (eq:cc1 for this model).
  * ====================================================================== */
+/* Number of calibration unknowns: one per cell, or with the geometric
+ * model three per cell and CCD. */
+static int64_t cal_size(const orc_world_t* w, const orc_state_t* st) {
+    return w->geo_ccds > 0 ? st->n_cells * w->geo_ccds * 3 : st->n_cells;
+}
+
+/* Geometric calibration (Sect. 5.3 with eq:etazeta): eq:normC for each
+ * group of three coefficients (cell and CCD), whose records share no
+ * coefficient with another group, W from the A/C weights; the 3x3 systems
+ * by C1-C3; then eq:calCon with the constraint eq:cc1 (for each day, the
+ * constant terms of its two cells and all CCDs sum to zero): the constant
+ * terms' mean over the day is subtracted. */
+static void calibration_solve_geo(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, double* d) {
+    const int64_t ng = st->n_cells * w->geo_ccds;
+    double* N = (double*)calloc((size_t)(9 * ng), sizeof(double));
+    double* b = (double*)calloc((size_t)(3 * ng), sizeof(double));
+    for (int64_t l = 0; l < obs->n; ++l) {
+        if (obs->cell[l] < 0) continue;              /* across scan: no calibration term */
+        orc_fwd_t o;
+        forward_one(w, obs, st, l, &o);
+        double W = weight(w, obs, st, l, &o);
+        const int64_t g = geo_index(w, obs, l) / 3;
+        const double x = geo_x(obs, l);
+        double L[3];
+        for (int r = 0; r < 3; ++r) L[r] = shifted_legendre(r, x);     /* dR/dc_r (eq:pdC) */
+        for (int r = 0; r < 3; ++r) {
+            for (int s = 0; s < 3; ++s) N[9 * g + 3 * r + s] += L[r] * W * L[s];
+            b[3 * g + r] -= L[r] * o.R * W;
+        }
+    }
+    for (int64_t g = 0; g < ng; ++g) {
+        double U[9], x[3];
+        memcpy(U, N + 9 * g, sizeof U);
+        memcpy(x, b + 3 * g, sizeof x);
+        orc_chol_c1(U, 3);
+        orc_chol_c2(U, 3, x);
+        orc_chol_c3(U, 3, x);
+        memcpy(d + 3 * g, x, sizeof x);
+    }
+    /* eq:calCon for eq:cc1: C has one column per day, with ones at the
+     * constant terms of the day's 2 geo_ccds groups; C'C = 2 geo_ccds I */
+    const int64_t per_day = 2 * w->geo_ccds;
+    for (int64_t j = 0; (j + 1) * per_day <= ng; ++j) {
+        double ctd = 0.0;
+        for (int64_t k = 0; k < per_day; ++k) ctd += d[3 * (j * per_day + k)];
+        const double z = ctd / (double)per_day;
+        for (int64_t k = 0; k < per_day; ++k) d[3 * (j * per_day + k)] -= z;
+    }
+    free(N);
+    free(b);
+}
+
+/* The calibration update d (cal_size entries) applied to the state. */
+static void apply_calibration(const orc_world_t* w, orc_state_t* st, const double* d) {
+    if (w->geo_ccds > 0) {
+        for (int64_t k = 0; k < cal_size(w, st); ++k) st->geo[k] += d[k];
+    } else {
+        for (int64_t c = 0; c < st->n_cells; ++c) st->c[c] += d[c];
+    }
+}
+
 static void calibration_solve(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, double* d) {
+    if (w->geo_ccds > 0) {
+        calibration_solve_geo(w, obs, st, d);
+        return;
+    }
     double* Nc = (double*)calloc((size_t)st->n_cells, sizeof(double));
     double* bc = (double*)calloc((size_t)st->n_cells, sizeof(double));
     for (int64_t l = 0; l < obs->n; ++l) {
@@ -867,10 +962,11 @@ static void calibration_solve(const orc_world_t* w, const orc_obs_t* obs, const 
 }
 
 void orc_calibration_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st, double* d_out) {
-    double* d = (double*)calloc((size_t)st->n_cells, sizeof(double));
+    const int64_t nc = cal_size(w, st);
+    double* d = (double*)calloc((size_t)nc, sizeof(double));
     calibration_solve(w, obs, st, d);
-    for (int64_t c = 0; c < st->n_cells; ++c) st->c[c] += d[c];
-    if (d_out) memcpy(d_out, d, sizeof(double) * (size_t)st->n_cells);
+    apply_calibration(w, st, d);
+    if (d_out) memcpy(d_out, d, sizeof(double) * (size_t)nc);
     free(d);
 }
 
@@ -882,11 +978,11 @@ void orc_iterate_sac(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st
     orc_source_update(w, obs, st, NULL, NULL, NULL, var);
     orc_excess_attitude_noise(w, obs, st);
     double* da = (double*)calloc((size_t)(4 * st->n_att), sizeof(double));
-    double* dc = (double*)calloc((size_t)st->n_cells, sizeof(double));
+    double* dc = (double*)calloc((size_t)cal_size(w, st), sizeof(double));
     attitude_solve(w, obs, st, da);
     calibration_solve(w, obs, st, dc);
     for (int64_t k = 0; k < 4 * st->n_att; ++k) st->a[k] += da[k];
-    for (int64_t c = 0; c < st->n_cells; ++c) st->c[c] += dc[c];
+    apply_calibration(w, st, dc);
     free(da);
     free(dc);
 }

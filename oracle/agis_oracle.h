@@ -39,6 +39,9 @@ typedef struct {
     int32_t robust;           /* 0: w_l = 1, eps = 0; 1: downweighting and excess attitude noise;
                                  2: also the excess source noise eps_i of eq:epsi */
     int32_t eps_bucket;       /* knot intervals per excess-attitude-noise bucket (robust) */
+    int32_t geo_ccds;         /* 0: one calibration offset per cell; n > 0: the large-scale AL
+                                 geometric calibration of eq:etazeta, three shifted-Legendre
+                                 coefficients per cell and CCD (n CCDs) in the AC pixel coordinate */
 } orc_world_t;
 
 typedef struct {
@@ -52,6 +55,8 @@ typedef struct {
     const int32_t* cell;      /* calibration cell; -1: across-scan observation (eq:resAC) */
     const double* sigma_eff;  /* NULL, or the uncertainty that replaces sigma: the frozen
                                  sigma_eff of the hybrid scheme (orc_frozen_sigma) [rad] */
+    const int8_t* ccd;        /* geometric calibration: CCD index of the record (else NULL) */
+    const float* mu;          /* geometric calibration: AC pixel coordinate, 13.5 .. 1979.5 */
 } orc_obs_t;
 
 typedef struct {
@@ -64,6 +69,8 @@ typedef struct {
                                  AL, ACP and ACF components (Sect. 3.6) */
     double* src_eps2;         /* [n_src] excess source variance eps_i^2 of the last S update (robust 2; may be NULL) */
     double* src_D;            /* [n_src] its significance D of eq:D (robust 2; may be NULL) */
+    double* geo;              /* [n_cells][geo_ccds][3] geometric calibration coefficients
+                                 (eq:etazeta, r = 0, 1, 2) [rad]; NULL when geo_ccds = 0 */
 } orc_state_t;
 
 /* --- Appendix A: quaternions -------------------------------------------- */
@@ -133,6 +140,8 @@ int64_t orc_attitude_segment(const orc_world_t* w, const orc_obs_t* obs, const o
                              int64_t K, double* d, int64_t* keep_lo, int64_t* keep_hi);
 int64_t orc_num_segments(const orc_world_t* w);
 /* C block; d[n_cells] receives the applied update (may be NULL). */
+/* d (may be NULL) receives the update: [n_cells], or with the geometric
+ * calibration [n_cells][geo_ccds][3]. */
 void orc_calibration_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st, double* d);
 /* S[AC]: S, then A and C from the same post-S residuals. */
 void orc_iterate_sac(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st, double* var);

@@ -80,6 +80,8 @@ class CG:
     state."""
 
     def __init__(self, pr, restart=40, s_ref=None):
+        if getattr(pr, "geo", None) is not None:
+            raise ValueError("conjugate gradients: the oracle's normal equations carry the cell offsets only")
         self.pr, self.restart, self.s_ref = pr, int(restart), s_ref
         self.k = 0                     # iterations done in the current cycle (0: a cycle starts next)
         self.r = self.z = self.p = None

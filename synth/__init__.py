@@ -113,6 +113,13 @@ class WorldSpec:
     robust: bool = False              # downweighting and excess attitude noise in the solvers
     eps_bucket: int = 8               # knot intervals per excess-attitude-noise bucket
     eps_a_init: float = 50.0 * MAS    # excess attitude noise assumed before the first attitude update
+    # large-scale AL geometric calibration (Sect. 3.4): per calibration cell
+    # (day and field of view) and CCD, three shifted-Legendre coefficients
+    # in the across-scan pixel coordinate, in place of one offset per cell;
+    # true coefficients N(0, geo_sd[r]), the constant terms summing to zero
+    # over the fields of view and CCDs of each day
+    geo_cal: bool = False
+    geo_sd: tuple = (1.0 * MAS, 0.3 * MAS, 0.1 * MAS)
 
 
 @dataclass
@@ -134,6 +141,12 @@ class World:
     eps: np.ndarray
     eta_nominal: np.ndarray           # the fiducial line eta0 of each observation [rad]
     extra: dict = field(default_factory=dict)
+    # geometric calibration worlds: CCD index and across-scan pixel coordinate
+    # of each record, and the coefficients [n_cells][n_ccd][3] (true, start)
+    ccd: np.ndarray | None = None
+    mu: np.ndarray | None = None
+    geo_true: np.ndarray | None = None
+    geo_start: np.ndarray | None = None
 
     @property
     def n_obs(self) -> int:
@@ -347,6 +360,15 @@ def make_world(spec: WorldSpec, law: dict | None = None, progress=None) -> World
     eta_nom = np.tile(eta0, tt.shape[0])
     keep = (t_obs >= t_beg) & (t_obs <= t_end)
     t_obs, fov, src_idx, eta_nom = t_obs[keep], fov[keep], src_idx[keep], eta_nom[keep]
+    ccd = mu = mu_tr = None
+    if spec.geo_cal:
+        # CCD index in the order the image crosses the lines; one across-scan
+        # pixel coordinate per transit, drawn uniformly over the 1966 pixel
+        # columns (a stand-in for the star's position across the field)
+        rng_g = np.random.default_rng([spec.seed_truth, 7])
+        mu_tr = rng_g.uniform(13.5, 1979.5, tt.shape[0]).astype(np.float32)
+        ccd = np.tile(np.arange(nc, dtype=np.int8), tt.shape[0])[keep]
+        mu = np.repeat(mu_tr, nc)[keep]
     day = np.floor((t_obs - t_beg) / DAY).astype(np.int64)
     day = np.minimum(day, n_days - 1)
     cell = (2 * day + (fov == -1)).astype(np.int32)
@@ -385,6 +407,9 @@ def make_world(spec: WorldSpec, law: dict | None = None, progress=None) -> World
         cell = np.concatenate([cell, np.full(t_ac.shape[0], -1, np.int32)])
         sigma = np.concatenate([sigma, sg_ac])
         eps = np.concatenate([eps, e_ac])
+        if spec.geo_cal:
+            ccd = np.concatenate([ccd, np.zeros(t_ac.shape[0], np.int8)])
+            mu = np.concatenate([mu, mu_tr[k_ac]])
 
     rng_s = np.random.default_rng(spec.seed_start)
     so = spec.start_offset
@@ -399,16 +424,32 @@ def make_world(spec: WorldSpec, law: dict | None = None, progress=None) -> World
     cal_start = cal_true.copy()
     cal_start[0::2] += dcal
     cal_start[1::2] -= dcal
+    geo_true = geo_start = None
+    if spec.geo_cal:
+        # the geometric coefficients replace the per-cell offsets, which
+        # stay zero; the constant terms sum to zero over each day's fields
+        # of view and CCDs (eq:cc1)
+        cal_true = np.zeros(n_cells)
+        cal_start = np.zeros(n_cells)
+        rng_g = np.random.default_rng([spec.seed_truth, 8])
+        geo_true = rng_g.normal(0.0, 1.0, (n_cells, nc, 3)) * np.asarray(spec.geo_sd)[None, None, :]
+        geo_start = geo_true + np.random.default_rng([spec.seed_start, 8]).normal(0.0, 0.5 * so, (n_cells, nc, 3))
+        for g in (geo_true, geo_start):
+            day_mean = g[:, :, 0].reshape(n_days, 2 * nc).mean(axis=1)
+            g[:, :, 0] -= np.repeat(day_mean, 2)[:, None]
 
     consts = dict(
         gamma_c=law["gamma"], t_ep=0.0, t_fr=0.0, lambda_reg=spec.lambda_reg,
         seg_len=spec.seg_len, seg_overlap=spec.seg_overlap,
         eph_radius_au=1.01, eph_L0=law["L0"], eph_Lrate=law["Lrate"], eps_obl=law["eps_obl"],
         au_m=AU_M, c_mps=C_MPS, year_s=YEAR, t_beg=t_beg, t_end=t_end, law=law,
-        robust=int(spec.robust), eps_bucket=spec.eps_bucket, eps_a_init=spec.eps_a_init)
+        robust=int(spec.robust), eps_bucket=spec.eps_bucket, eps_a_init=spec.eps_a_init,
+        geo_ccds=nc if spec.geo_cal else 0)
     return World(spec=spec, consts=consts, knots=knots, src_true=src_true, att_true=att_true,
                  cal_true=cal_true, src_start=src_start, att_start=att_start, cal_start=cal_start,
                  t=np.ascontiguousarray(t_obs), src=np.ascontiguousarray(src_idx),
                  fov=np.ascontiguousarray(fov), cell=np.ascontiguousarray(cell),
                  sigma=np.ascontiguousarray(sigma), eps=np.ascontiguousarray(eps),
-                 eta_nominal=np.ascontiguousarray(eta_nom))
+                 eta_nominal=np.ascontiguousarray(eta_nom),
+                 ccd=None if ccd is None else np.ascontiguousarray(ccd),
+                 mu=None if mu is None else np.ascontiguousarray(mu), geo_true=geo_true, geo_start=geo_start)
