@@ -100,6 +100,8 @@ def workload_description(name, w):
             "outlier_frac": sp.outlier_frac, "robust": bool(sp.robust),
             **({"ac_obs_per_transit": 1, "ac_observations": int((w.cell < 0).sum()),
                 "sigma_ac_uas": round(float(w.sigma[w.cell < 0][0]) / 4.8481368e-12, 1)} if sp.ac_obs else {}),
+            **({"calibration": "large-scale along-scan geometric: 3 shifted-Legendre coefficients per cell and CCD",
+                "calibration_groups": int(w.n_cells * w.consts["geo_ccds"])} if sp.geo_cal else {}),
             "law": "Gaia-like: spin 60 arcsec/s, precession 63 d, aspect 45 deg, basic angle 106.5 deg"}
 
 
@@ -207,6 +209,9 @@ def main():
                          "(cycles of 40 iterations; an iteration is one pass of the blocks plus p'N p)")
     ap.add_argument("--ac", action="store_true",
                     help="add one across-scan observation per transit (cell -1) to the workload")
+    ap.add_argument("--geo", action="store_true",
+                    help="the large-scale along-scan geometric calibration (3 coefficients per cell and CCD) in "
+                         "place of one offset per cell; no CPU baseline")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the timed steps, run one plain device copy of this many MiB (the reference "
                          "kernel for scaling HBM counters) and exit")
@@ -228,7 +233,10 @@ def main():
     over = {} if args.seg_len is None else {"seg_len": args.seg_len}
     if args.ac:
         over["ac_obs"] = True
-    wname = args.workload + ("+ac" if args.ac else "")
+    if args.geo:
+        over["geo_cal"] = True
+        args.no_cpu_baseline = True
+    wname = args.workload + ("+ac" if args.ac else "") + ("+geo" if args.geo else "")
     t0 = time.time()
     w = C.make(args.workload, progress=log, **over)
     log(f"workload {args.workload}: {w.src_true.shape[0]} sources, {w.n_obs} obs, {w.n_att} coefficients "
@@ -243,7 +251,10 @@ def main():
     agis.agis_set_sources(ctx, w.src_true)
     agis.agis_set_attitude(ctx, w.att_true)
     agis.agis_set_calibration(ctx, w.cal_true)
-    R = agis.agis_residuals(ctx)                   # = c_true - eta_true
+    if args.geo:
+        agis.agis_load_geometry(ctx, w.ccd, w.mu, int(w.consts["geo_ccds"]))
+        agis.agis_set_geo_calibration(ctx, w.geo_true)
+    R = agis.agis_residuals(ctx)                   # = c_true - eta_true (plus the true geometric terms)
     eta_obs = -R + w.eps
     del R, zeros
     if args.no_cpu_baseline:
@@ -253,6 +264,9 @@ def main():
     agis.agis_set_sources(ctx, w.src_start)
     agis.agis_set_attitude(ctx, w.att_start)
     agis.agis_set_calibration(ctx, w.cal_start)
+    if args.geo:
+        agis.agis_load_geometry(ctx, w.ccd, w.mu, int(w.consts["geo_ccds"]))
+        agis.agis_set_geo_calibration(ctx, w.geo_start)
     agis.agis_set_frame_reference(ctx, w.src_true)
     sz = agis.agis_problem_size(ctx)
     log(f"store built: {sz}")

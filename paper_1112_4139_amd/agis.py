@@ -79,6 +79,9 @@ _sig = {
     "agis_get_attitude": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
     "agis_set_calibration": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
     "agis_get_calibration": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
+    "agis_load_geometry": ([_ctx_p, c_i64, _vp, _vp, c_i32, ctypes.c_int], ctypes.c_int),
+    "agis_set_geo_calibration": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
+    "agis_get_geo_calibration": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
     "agis_source_update": ([_ctx_p, P(agis_block_stats_t)], ctypes.c_int),
     "agis_attitude_update": ([_ctx_p, P(agis_block_stats_t)], ctypes.c_int),
     "agis_calibration_update": ([_ctx_p, P(agis_block_stats_t)], ctypes.c_int),
@@ -228,6 +231,24 @@ def agis_set_calibration(ctx, c):
 
 def agis_get_calibration(ctx, n, out=None):
     return _get(_lib.agis_get_calibration, ctx, n, 1, out)
+
+
+def agis_load_geometry(ctx, ccd, mu, n_ccd):
+    """Enable the geometric calibration: CCD index (int8) and across-scan
+    pixel coordinate (float32) of every record, in input order."""
+    pc, wc, kc = _ptr(ccd, np.int8)
+    pm, wm, km = _ptr(mu, np.float32)
+    if wc != wm:
+        raise ValueError("ccd and mu must both be host arrays or both device tensors")
+    _check(_lib.agis_load_geometry(ctx, int(len(ccd)), pc, pm, int(n_ccd), wc), ctx)
+
+
+def agis_set_geo_calibration(ctx, c):
+    _set(_lib.agis_set_geo_calibration, ctx, np.size(c), np.reshape(c, -1) if isinstance(c, np.ndarray) else c)
+
+
+def agis_get_geo_calibration(ctx, n, out=None):
+    return _get(_lib.agis_get_geo_calibration, ctx, n, 1, out)
 
 
 def agis_source_update(ctx):

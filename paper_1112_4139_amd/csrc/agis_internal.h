@@ -104,6 +104,25 @@ struct agis_ctx {
     double* iv_cal = nullptr;            // [K][IV_CAL]
     double* da = nullptr;                // [N][4]
     double* dc = nullptr;                // [n_cells]
+    // large-scale AL geometric calibration (agis_load_geometry): three
+    // shifted-Legendre coefficients per cell and CCD in place of the cell
+    // offsets (held at zero); 0 CCDs: the cell offsets
+    int32_t geo_ccds = 0;
+    int64_t n_groups = 0;                // n_cells * geo_ccds
+    double* geo = nullptr;               // [n_groups][3]
+    double* dgeo = nullptr;              // [n_groups][3] the last update
+    double* geo_sums = nullptr;          // [n_groups][9] normal equations of the last C update
+    int32_t* t_geo_g = nullptr;          // time order: group of the record (-1 across scan)
+    int32_t* s_geo_g = nullptr;          // source order
+    float* t_geo_mu = nullptr;           // time order: across-scan pixel coordinate
+    float* s_geo_mu = nullptr;           // source order
+    double* t_eta0 = nullptr;            // time order: observed angles as loaded (t_eta adds the terms)
+    double* s_eta0 = nullptr;            // source order
+    double* geo_wr = nullptr;            // [n_al][2] W and W R of the last A/C pass (group order)
+    int32_t* geo_pos = nullptr;          // time order -> position in the group order (-1 across scan)
+    int64_t* geo_off = nullptr;          // [n_groups + 1] group ranges of the group order
+    float* geo_mu_g = nullptr;           // group order: across-scan pixel coordinate
+    int* geo_flags = nullptr;
     int32_t* seg_def = nullptr;          // [n_seg]
     std::vector<agis::SegDesc> h_segs;
     agis::SegDesc* segs = nullptr;
@@ -252,7 +271,12 @@ void launch_freeze_sigma(agis_ctx* ctx);
 void launch_ac_pass(agis_ctx* ctx);
 void launch_band_solve(agis_ctx* ctx);
 void launch_calib_solve(agis_ctx* ctx, double* rc = nullptr);   // rc: optional right-hand sides
+// geo.hip
+int load_geometry(agis_ctx* ctx, const int8_t* ccd, const float* mu, int32_t n_ccd, int where);
+void launch_geo_eta(agis_ctx* ctx);
+void launch_geo_solve(agis_ctx* ctx);
 void launch_apply_attitude(agis_ctx* ctx);
+void launch_apply_add(agis_ctx* ctx, int64_t n, double* x, const double* dx);   // x += dx
 void launch_apply_calibration(agis_ctx* ctx);
 void launch_frame_fit(agis_ctx* ctx);
 void launch_frame_apply(agis_ctx* ctx);

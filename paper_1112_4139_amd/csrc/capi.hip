@@ -110,6 +110,17 @@ static void free_store(agis_ctx* ctx) {
     dfree(ctx->s_sig_eff);
     dfree(ctx->t_sig_eff);
     ctx->frozen = false;
+    for (double** v : {&ctx->geo, &ctx->dgeo, &ctx->geo_sums, &ctx->t_eta0, &ctx->s_eta0, &ctx->geo_wr}) dfree(*v);
+    dfree(ctx->t_geo_g);
+    dfree(ctx->s_geo_g);
+    dfree(ctx->t_geo_mu);
+    dfree(ctx->s_geo_mu);
+    dfree(ctx->geo_flags);
+    dfree(ctx->geo_pos);
+    dfree(ctx->geo_off);
+    dfree(ctx->geo_mu_g);
+    ctx->geo_ccds = 0;
+    ctx->n_groups = 0;
     dfree(ctx->iv_off);
     dfree(ctx->iv_cell);
     dfree(ctx->cell_iv);
@@ -578,10 +589,50 @@ extern "C" int agis_set_calibration(agis_ctx_t* ctx, int64_t n, const double* c,
     CHECK_CTX();
     ++ctx->xver;
     REQUIRE_LOADED();
+    if (ctx->geo_ccds > 0)
+        return set_error(ctx, AGIS_E_STATE, "the geometric calibration replaces the cell offsets "
+                                            "(agis_set_geo_calibration)");
     if (n != ctx->n_cells || (!c && n > 0)) return set_error(ctx, AGIS_E_SHAPE, "cell count mismatch");
     int rc = check_finite_host(ctx, c, n, where);
     if (rc) return rc;
     return copy_in(ctx, ctx->c, c, n * sizeof(double), where);
+}
+
+extern "C" int agis_load_geometry(agis_ctx_t* ctx, int64_t n, const int8_t* ccd, const float* mu, int32_t n_ccd,
+                                  int where) {
+    CHECK_CTX();
+    ++ctx->xver;
+    REQUIRE_LOADED();
+    if (where != AGIS_HOST && where != AGIS_DEVICE) return set_error(ctx, AGIS_E_INVALID_ARG, "bad 'where'");
+    if (n != ctx->n_obs || ((!ccd || !mu) && n > 0)) return set_error(ctx, AGIS_E_SHAPE, "record count mismatch");
+    if (n_ccd < 1 || n_ccd > 127) return set_error(ctx, AGIS_E_INVALID_ARG, "n_ccd outside [1, 127]");
+    if (ctx->cfg.robust == 2) return set_error(ctx, AGIS_E_STATE, "the geometric calibration with robust mode 2");
+    const int rc = load_geometry(ctx, ccd, mu, n_ccd, where);
+    ++ctx->gen;                          // the captured iteration gains the geometric kernels
+    return rc;
+}
+
+extern "C" int agis_set_geo_calibration(agis_ctx_t* ctx, int64_t n, const double* c, int where) {
+    CHECK_CTX();
+    ++ctx->xver;
+    REQUIRE_LOADED();
+    if (ctx->geo_ccds <= 0) return set_error(ctx, AGIS_E_STATE, "agis_load_geometry first");
+    if (n != 3 * ctx->n_groups || (!c && n > 0)) return set_error(ctx, AGIS_E_SHAPE, "coefficient count mismatch");
+    int rc = check_finite_host(ctx, c, n, where);
+    if (rc) return rc;
+    if ((rc = copy_in(ctx, ctx->geo, c, n * sizeof(double), where))) return rc;
+    launch_geo_eta(ctx);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return AGIS_OK;
+}
+
+extern "C" int agis_get_geo_calibration(agis_ctx_t* ctx, int64_t n, double* c, int where) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    if (ctx->geo_ccds <= 0) return set_error(ctx, AGIS_E_STATE, "agis_load_geometry first");
+    if (n != 3 * ctx->n_groups || (!c && n > 0)) return set_error(ctx, AGIS_E_SHAPE, "coefficient count mismatch");
+    return copy_out(ctx, c, ctx->geo, n * sizeof(double), where);
 }
 
 extern "C" int agis_get_calibration(agis_ctx_t* ctx, int64_t n, double* c, int where) {
@@ -661,12 +712,20 @@ static int run_ac(agis_ctx* ctx, bool do_a, bool do_c, bool eps_update = false, 
     }
     if (do_c) {
         tstart(ctx, T_CAL);
-        launch_calib_solve(ctx, rc);
+        if (ctx->geo_ccds > 0) launch_geo_solve(ctx);
+        else launch_calib_solve(ctx, rc);
         HIPCHK(hipGetLastError());
         tstop(ctx, T_CAL);
     }
     if (do_a && apply) launch_apply_attitude(ctx);
-    if (do_c && apply) launch_apply_calibration(ctx);
+    if (do_c && apply) {
+        if (ctx->geo_ccds > 0) {
+            launch_apply_add(ctx, 3 * ctx->n_groups, ctx->geo, ctx->dgeo);
+            launch_geo_eta(ctx);
+        } else {
+            launch_apply_calibration(ctx);
+        }
+    }
     HIPCHK(hipGetLastError());
     return AGIS_OK;
 }
@@ -691,7 +750,9 @@ static int stats_a(agis_ctx* ctx, agis_block_stats_t* st) {
 }
 static int stats_c(agis_ctx* ctx, agis_block_stats_t* st) {
     if (!st) return AGIS_OK;
-    int rc = fill_stats(ctx, st, ctx->dc, ctx->n_cells, 1, nullptr, nullptr, ctx->n_obs, ctx->n_cells);
+    int rc = ctx->geo_ccds > 0
+                 ? fill_stats(ctx, st, ctx->dgeo, ctx->n_groups, 3, nullptr, nullptr, ctx->n_obs, ctx->n_groups)
+                 : fill_stats(ctx, st, ctx->dc, ctx->n_cells, 1, nullptr, nullptr, ctx->n_obs, ctx->n_cells);
     if (rc == AGIS_OK) st->ms = tget(ctx, T_CAL);
     return rc;
 }
@@ -1092,6 +1153,8 @@ static int check_which(agis_ctx* ctx, int32_t which) {
 extern "C" int agis_learned_reset(agis_ctx_t* ctx) {
     CHECK_CTX();
     REQUIRE_LOADED();
+    if (ctx->geo_ccds > 0)
+        return set_error(ctx, AGIS_E_STATE, "recorded updates and extrapolation: not with the geometric calibration");
     int rc = learned_alloc(ctx);
     if (rc) return rc;
     launch_hist_anchor(ctx);
@@ -1604,6 +1667,8 @@ extern "C" int agis_cg_iterate(agis_ctx_t* ctx, int32_t n_eval, int32_t restart,
     CHECK_CTX();
     REQUIRE_LOADED();
     if (n_eval < 0 || restart < 1) return set_error(ctx, AGIS_E_INVALID_ARG, "n_eval >= 0 and restart >= 1");
+    if (ctx->geo_ccds > 0)
+        return set_error(ctx, AGIS_E_STATE, "conjugate gradients: not with the geometric calibration");
     if (robust_now(ctx))
         return set_error(ctx, AGIS_E_STATE,
                          "conjugate gradients need fixed observation weights (robust mode: freeze them first)");

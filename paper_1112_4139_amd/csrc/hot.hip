@@ -236,7 +236,8 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
                                                            const double* __restrict__ c,
                                                            const double* __restrict__ eps_a2, int eps_bucket,
                                                            int robust, double* __restrict__ iv_sums,
-                                                           double* __restrict__ iv_cal) {
+                                                           double* __restrict__ iv_cal, double* __restrict__ wr_out,
+                                                           const int32_t* __restrict__ wr_pos) {
     using XT = typename std::conditional<MIXED, float, double>::type;
     __shared__ XT xb[AC_WAVES][64][AC_XS];
     __shared__ double sh_a[AC_WAVES][16];
@@ -316,6 +317,15 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
                 W = h_c ? down_weight(o.R / sqrt(s2)) / s2 : 0.0;
             } else {
                 W = h_c ? rcp_nr(sg * sg) : 0.0;
+            }
+            // geometric calibration: each along-scan record's W and W R for
+            // its C block, at its place in the group order
+            if (wr_out && h_c) {
+                const int32_t p = wr_pos[base + lane];
+                if (p >= 0) {
+                    wr_out[2 * (int64_t)p] = W;
+                    wr_out[2 * (int64_t)p + 1] = W * o.R;
+                }
             }
             XT* row = xw[lane];
             const int f = cf_c & 1;
@@ -702,7 +712,8 @@ static void ac_pass_with(agis_ctx* ctx, const T* sig) {
                                       : (ctx->has_ac ? k_ac_pass<false, true, T> : k_ac_pass<false, false, T>))
         <<<(unsigned)((ctx->K + AC_WAVES - 1) / AC_WAVES), 64 * AC_WAVES, 0, ctx->stream>>>(
         ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, sig, ctx->t_cellfov, ctx->t_src, ctx->prep, ctx->knots,
-        ctx->ktab, ctx->a, ctx->c, ctx->eps_a2, ctx->cfg.eps_bucket, robust_now(ctx), ctx->iv_sums, ctx->iv_cal);
+        ctx->ktab, ctx->a, ctx->c, ctx->eps_a2, ctx->cfg.eps_bucket, robust_now(ctx), ctx->iv_sums, ctx->iv_cal,
+        ctx->geo_ccds > 0 ? ctx->geo_wr : nullptr, ctx->geo_pos);
 }
 
 void launch_ac_pass(agis_ctx* ctx) {

@@ -364,6 +364,10 @@ void launch_prep_sources(agis_ctx* ctx) {
 
 
 
+void launch_apply_add(agis_ctx* ctx, int64_t n, double* x, const double* dx) {
+    if (n > 0) k_apply_add<<<grid_for(n), 256, 0, ctx->stream>>>(n, x, dx);
+}
+
 void launch_apply_attitude(agis_ctx* ctx) {
     k_apply_add<<<grid_for(4 * ctx->N), 256, 0, ctx->stream>>>(4 * ctx->N, ctx->a, ctx->da);
 }
