@@ -120,12 +120,14 @@ def test_ac_attitude_error_ratio(oracle_lib):
     assert abs(rms[True][2] / rms[False][2] - 1) < 0.1
 
 
-def test_robust_weighting_refuses_ac(oracle_lib, ac_world):
-    """The excess attitude noise is estimated for the AL component only, so a
-    robust problem with AC records is refused rather than mis-weighted."""
+def test_robust_weighting_takes_ac(oracle_lib, ac_world):
+    """A robust problem with AC records holds the three excess attitude
+    noise components of Sect. 3.6 (along scan, across scan in the preceding
+    and in the following field of view) per bucket of knot intervals."""
     w, eta = ac_world
     consts = dict(w.consts)
     consts["robust"] = 1
-    with pytest.raises(ValueError, match="across-scan"):
-        oracle_lib.Problem(consts, w.knots, w.t, eta, w.sigma, w.src, w.fov, w.cell, w.src_start, w.att_start,
-                           w.cal_start)
+    pr = oracle_lib.Problem(consts, w.knots, w.t, eta, w.sigma, w.src, w.fov, w.cell, w.src_start, w.att_start,
+                            w.cal_start)
+    nb = (w.n_att - 3 + consts["eps_bucket"] - 1) // consts["eps_bucket"]
+    assert pr.eps_a2.size == 3 * nb
