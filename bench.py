@@ -348,8 +348,12 @@ def main():
            "scaling": "weak", "vs_baseline": None,
            "dtype": "f64" if args.precision == "fp64" else "f64 model, f32 partials and sums", "data": "synthetic",
            "config": {**workload_description(wname, w), "lanes_per_source": s_group,
-                      **({"robust_s_path": ["hbm columns", "rows in hbm, solves in lds", "all in lds"][
-                          tuning["robust_s_path"]]} if w.spec.robust else {}),
+                      **({"robust_s_path": ["hbm columns", "rows in hbm, solves in lds", "all in lds",
+                                         "rows in registers"][
+                          tuning["robust_s_path"]],
+                          "inner_rounds": ["records re-read each round", "32 lanes per source, first 8 records in "
+                                           "registers", "64 lanes per source, first 8 records in registers"][
+                              tuning["irls_cache"]]} if w.spec.robust else {}),
                       **({"scheme": "conjugate gradients"} if args.scheme == "cg" else {})},
            "kernel_ms": kavg, "roofline": roofline,
            "cpu_baseline": cpu}

@@ -281,15 +281,21 @@ int agis_iterate_graph(agis_ctx_t* ctx, int32_t n_iter);
  * paths of the S block the same way (per-observation columns in HBM with
  * the intersextile order statistics selected together or one after the
  * other; the rows in HBM and the inner iteration per source in LDS; the
- * whole block per source in LDS) and keeps the fastest; the paths give the
- * same numbers up to the order of their sums. */
+ * whole block per source in LDS; the whole block per source with its rows
+ * in registers) and keeps the fastest; the paths give the same numbers up
+ * to the order of their sums (the register path forms the weights of the
+ * first three inner rounds from FP32 copies of the design row, which moves
+ * them by rounding of ~1e-7 relative in R). */
 int agis_autotune(agis_ctx_t* ctx, int32_t* s_group);
 /* The launch choices in effect: out[0] lanes per source of the S block,
  * out[1] the robust S path (0 HBM columns, 1 rows in HBM then LDS, 2 all in
- * LDS), out[2] 1 if the columns path selects both intersextile order
- * statistics in one set of radix passes, out[3] 1 if the excess attitude
- * noise is estimated in one kernel. */
-int agis_get_tuning(const agis_ctx_t* ctx, int32_t out[4]);
+ * LDS, 3 rows in registers), out[2] 1 if the columns path selects both
+ * intersextile order statistics in one set of radix passes, out[3] 1 if
+ * the excess attitude noise is estimated in one kernel, out[4] the inner
+ * rounds of the columns path: 0 every record re-read from the columns each
+ * round, 1 (2) 32 (64) lanes per source keeping their first 8 records in
+ * registers across the rounds.  out: 5 ints. */
+int agis_get_tuning(const agis_ctx_t* ctx, int32_t out[5]);
 
 /* Residuals R_l (eq:resAL) at the current parameters, in the input order of
  * agis_load_observations. */

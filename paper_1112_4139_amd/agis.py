@@ -317,12 +317,13 @@ def agis_autotune(ctx):
 
 def agis_get_tuning(ctx):
     """The launch choices in effect: lanes per source, robust S path (0 HBM
-    columns, 1 rows then LDS, 2 all in LDS), paired quantile selection, fused
-    excess-noise estimate."""
-    out = (c_i32 * 4)()
+    columns, 1 rows then LDS, 2 all in LDS, 3 rows in registers), paired
+    quantile selection, fused excess-noise estimate, register cache of the
+    column path's inner rounds (0 none, 1 / 2: 32 / 64 lanes per source)."""
+    out = (c_i32 * 5)()
     _check(_lib.agis_get_tuning(ctx, out), ctx)
     return dict(lanes_per_source=out[0], robust_s_path=out[1], paired_selection=bool(out[2]),
-                fused_excess_noise=bool(out[3]))
+                fused_excess_noise=bool(out[3]), irls_cache=out[4])
 
 
 def agis_residuals(ctx, out=None):

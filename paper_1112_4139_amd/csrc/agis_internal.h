@@ -153,7 +153,12 @@ struct agis_ctx {
     bool eps_fused = false;
     int robust_s_mode = 0;               // robust S block: 0 rows, varsigma and solves through HBM columns;
                                          // 1 rows to HBM columns, then varsigma and solves per source in
-                                         // LDS; 2 the whole block per source in LDS (no HBM columns)
+                                         // LDS; 2 the whole block per source in LDS (no HBM columns);
+                                         // 3 the whole block per source with its rows in registers
+    int sreg_rows = 4;                   // register path: rows per lane (at most 4)
+    int irls_cache = 0;                  // column path, mode 1: 0 the inner rounds re-read every record;
+                                         // 1 (2) 32 (64) lanes per source, each keeping its first records
+                                         // in registers across the rounds
     bool robust_fused_eps = true;        // the excess-noise estimate in one kernel (values in LDS)
     int64_t robust_max_cap = INT64_MAX;  // largest source class of the one-kernel S path
 

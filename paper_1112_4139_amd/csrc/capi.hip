@@ -350,13 +350,16 @@ extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
     // columns), 1 (the excess-noise estimate in one kernel, the S block
     // through HBM columns; the default), 2 (the whole S block per source in
     // LDS), 3 (the S block's rows to HBM columns, then varsigma and the
-    // solves per source in LDS)
+    // solves per source in LDS), 4 (the S block per source with its rows in
+    // registers)
     if (const char* e = std::getenv("AGIS_ROBUST_FUSED")) {
         const int v = std::atoi(e);
         ctx->robust_fused_eps = v >= 1;
-        ctx->robust_s_mode = v == 3 ? 1 : (v == 2 ? 2 : 0);
+        ctx->robust_s_mode = v == 4 ? 3 : (v == 3 ? 1 : (v == 2 ? 2 : 0));
     }
     if (const char* e = std::getenv("AGIS_ROBUST_MAX_CAP")) ctx->robust_max_cap = std::atoll(e);
+    if (const char* e = std::getenv("AGIS_SREG_ROWS")) ctx->sreg_rows = std::atoi(e);
+    if (const char* e = std::getenv("AGIS_IRLS_CACHE")) ctx->irls_cache = std::atoi(e);
     int rc = AGIS_OK;
     auto fail = [&](int code) {
         g_create_error = ctx->err;
@@ -964,8 +967,9 @@ extern "C" int agis_autotune(agis_ctx_t* ctx, int32_t* s_group) {
             if (time_source(best_ms)) best = cand[ci];
         }
         ctx->s_group = best;
-        // robust mode 1: the path of the S block (HBM columns, or the
-        // per-source LDS kernels after the rows or for the whole block), and
+        // robust mode 1: the path of the S block (HBM columns, the
+        // per-source LDS kernels after the rows or for the whole block, or
+        // the per-source kernel with the rows in registers), and
         // for the columns the quantile kernel (both order statistics in one
         // set of passes or one after the other); the same numbers up to the
         // order of the sums (the quantiles bit for bit)
@@ -978,19 +982,22 @@ extern "C" int agis_autotune(agis_ctx_t* ctx, int32_t* s_group) {
                 e = hipMemcpyAsync(order.data(), ctx->src_order, ns * sizeof(int32_t), hipMemcpyDeviceToHost,
                                    ctx->stream);
             if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-            struct Path { int mode; bool pair; };
-            const Path paths[4] = {{0, true}, {0, false}, {1, true}, {2, true}};
-            Path keep{ctx->robust_s_mode, ctx->select_pair};
+            struct Path { int mode; bool pair; int cache; };
+            const Path paths[7] = {{0, true, 0}, {0, false, 0}, {0, true, 1}, {0, true, 2},
+                                   {1, true, 0}, {2, true, 0}, {3, true, 0}};
+            Path keep{ctx->robust_s_mode, ctx->select_pair, ctx->irls_cache};
             float path_ms = 3.0e38f;
-            for (int pi = 0; pi < 4 && e == hipSuccess && rc == AGIS_OK; ++pi) {
+            for (int pi = 0; pi < 7 && e == hipSuccess && rc == AGIS_OK; ++pi) {
                 ctx->robust_s_mode = paths[pi].mode;
                 ctx->select_pair = paths[pi].pair;
+                ctx->irls_cache = paths[pi].cache;
                 bool need = true;
                 rc = robust_plan(ctx, h_off, order, &need);
                 if (rc == AGIS_OK && time_source(path_ms)) keep = paths[pi];
             }
             ctx->robust_s_mode = keep.mode;
             ctx->select_pair = keep.pair;
+            ctx->irls_cache = keep.cache;
             if (rc == AGIS_OK && e == hipSuccess) {
                 bool need = true;
                 rc = robust_plan(ctx, h_off, order, &need);
@@ -1007,12 +1014,13 @@ extern "C" int agis_autotune(agis_ctx_t* ctx, int32_t* s_group) {
     return AGIS_OK;
 }
 
-extern "C" int agis_get_tuning(const agis_ctx_t* ctx, int32_t out[4]) {
+extern "C" int agis_get_tuning(const agis_ctx_t* ctx, int32_t out[5]) {
     if (!ctx || !out) return AGIS_E_INVALID_ARG;
     out[0] = ctx->s_group;
     out[1] = ctx->robust_s_mode;
     out[2] = ctx->select_pair ? 1 : 0;
     out[3] = ctx->eps_fused ? 1 : 0;
+    out[4] = ctx->irls_cache;
     return AGIS_OK;
 }
 

@@ -46,9 +46,10 @@ __device__ __forceinline__ double key_value(uint64_t k) {
 
 // One radix step of the selection of the k-th smallest key: from the
 // 256-bin histogram of the current digit, the digit holding rank k and the
-// number of keys in the lower digits (every lane receives both).
+// number of keys in the lower digits (every lane of the calling wavefront
+// receives both; any wavefront of the block may call it).
 __device__ __forceinline__ void radix_digit(const uint32_t* hist, int64_t k, int& digit_out, uint32_t& below_out) {
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     // lane owns digits 4 lane .. 4 lane + 3
     const uint32_t c0 = hist[4 * lane], c1 = hist[4 * lane + 1], c2 = hist[4 * lane + 2];
     const uint32_t c3 = hist[4 * lane + 3];
@@ -558,7 +559,41 @@ __device__ __forceinline__ double first_weight(double h, double vs0, double vs1,
 // ------------------------------------------------- S, inner iteration
 constexpr int INNER_SOLVES = 4;
 
-template <int G>
+// The accumulation of one record into the 21 sums of a round: its weight
+// w(h / varsigma) of its kind in the first round, w(R / sigma~) from the
+// previous round's d after it (eq:dw, eq:wl, eq:W).
+__device__ __forceinline__ void irls_row(double (&acc)[21], const double (&A)[5], double h, double s2, int it,
+                                         const double (&d)[5], double vs0, double vs1, bool ac_row) {
+    double wl;
+    if (it == 0) {
+        const double v = ac_row ? vs1 : vs0;
+        wl = v > 0.0 ? down_weight(h / v) : 1.0;
+    } else {
+        double R = h;
+#pragma unroll
+        for (int e = 0; e < 5; ++e) R -= A[e] * d[e];
+        wl = down_weight(R / sqrt(s2));
+    }
+    const double W = wl / s2;
+    int e = 0;
+#pragma unroll
+    for (int rr = 0; rr < 5; ++rr) {
+        const double wa = A[rr] * W;
+#pragma unroll
+        for (int cc = rr; cc < 5; ++cc) acc[e++] += wa * A[cc];
+    }
+#pragma unroll
+    for (int rr = 0; rr < 5; ++rr) acc[15 + rr] += A[rr] * W * h;
+    acc[20] += W * h * h;
+}
+
+// RC > 0: each lane keeps its first RC records (alpha*, delta, parallax
+// entries, tau, h, sigma~^2 and the kind) in registers from the first round
+// on, so the later rounds re-read only the records beyond them from the
+// columns.  The sums take the records in the same order either way.
+constexpr int IRLS_RC = 8;
+
+template <int G, int RC = 0>
 __global__ __launch_bounds__(256) void k_s_irls(int64_t n_src, const int64_t* __restrict__ off,
                                                 const double* __restrict__ col, int64_t n_obs,
                                                 const double* __restrict__ vs, double* __restrict__ s,
@@ -576,37 +611,35 @@ __global__ __launch_bounds__(256) void k_s_irls(int64_t n_src, const int64_t* __
     const double vs0 = valid ? vs[2 * i] : 0.0, vs1 = valid ? vs[2 * i + 1] : 0.0;
     double d[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     double acc[21];
+    constexpr int NC = RC > 0 ? RC : 1;
+    double cA[NC][4], cH[NC], cS[NC];            // the lane's first RC records
+    uint32_t cAC = 0;                            // bit q: record q is across scan
     for (int it = 0; it < INNER_SOLVES; ++it) {
 #pragma unroll
         for (int e = 0; e < 21; ++e) acc[e] = 0.0;
-        for (int64_t l = l0 + gl; l < l1; l += G) {
+#pragma unroll
+        for (int q = 0; q < RC; ++q) {
+            const int64_t l = l0 + gl + (int64_t)q * G;
+            if (l < l1) {
+                if (it == 0) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) cA[q][e] = col[e * n_obs + l];
+                    cH[q] = col[4 * n_obs + l];
+                    cS[q] = col[5 * n_obs + l];
+                    if (cell && cell[l] >= ac_cf0) cAC |= 1u << q;
+                }
+                const double A[5] = {cA[q][0], cA[q][1], cA[q][2], cA[q][0] * cA[q][3], cA[q][1] * cA[q][3]};
+                irls_row(acc, A, cH[q], cS[q], it, d, vs0, vs1, (cAC >> q) & 1u);
+            }
+        }
+        for (int64_t l = l0 + gl + (int64_t)RC * G; l < l1; l += G) {
             double A[5];
 #pragma unroll
             for (int e = 0; e < 3; ++e) A[e] = col[e * n_obs + l];
             const double tau = col[3 * n_obs + l];
             A[3] = A[0] * tau;                   // as the design row forms them
             A[4] = A[1] * tau;
-            const double h = col[4 * n_obs + l], s2 = col[5 * n_obs + l];
-            double wl;
-            if (it == 0) {
-                wl = first_weight(h, vs0, vs1, cell, ac_cf0, l);
-            } else {
-                double R = h;
-#pragma unroll
-                for (int e = 0; e < 5; ++e) R -= A[e] * d[e];
-                wl = down_weight(R / sqrt(s2));
-            }
-            const double W = wl / s2;
-            int e = 0;
-#pragma unroll
-            for (int rr = 0; rr < 5; ++rr) {
-                const double wa = A[rr] * W;
-#pragma unroll
-                for (int cc = rr; cc < 5; ++cc) acc[e++] += wa * A[cc];
-            }
-#pragma unroll
-            for (int rr = 0; rr < 5; ++rr) acc[15 + rr] += A[rr] * W * h;
-            acc[20] += W * h * h;
+            irls_row(acc, A, col[4 * n_obs + l], col[5 * n_obs + l], it, d, vs0, vs1, cell && cell[l] >= ac_cf0);
         }
 #pragma unroll
         for (int e = 0; e < 21; ++e) acc[e] = group_sum<G>(acc[e]);
@@ -1182,6 +1215,416 @@ __global__ __launch_bounds__(NT) void k_s_robust(DevConsts k, int64_t n_src, int
     source_finish(acc, i, alpha, delta, plx, pma, pmd, cos(delta), s, prep, ds, qsrc, sdef, svar);
 }
 
+// ------------------------------------------ S, rows held in registers
+// The robust S block with each source's rows on chip in registers: a block
+// of W wavefronts per source, lane l of wavefront w holding the source's
+// rows 64 rows w + l + 64 q, q < rows <= SR_M, in FP64 (the design row's
+// alpha*, delta and parallax entries and tau, h, sigma~^2: 12 registers a
+// row).  The model pass evaluates each observation once; varsigma per kind
+// of record is selected from the register-held h across the block's
+// wavefronts (exact order statistics, as on the other paths); the four
+// rounds of the inner iteration sum over the registers.  Nothing goes
+// through HBM but the model's inputs.  (FP32 copies of the design row for
+// the first three rounds were tried: the 5x5 systems amplify their rounding
+// to ~0.1 uas in the solutions that set the next round's weights.)
+constexpr int SR_M = 4;
+constexpr int SR_WMAX = 8;
+
+// Sum over the block's W wavefronts of NV values per lane: a butterfly in
+// each wavefront (every lane gets the same total), then the wavefronts'
+// totals added in wavefront order by every thread.  red: W * NV doubles.
+template <int W, int NV>
+__device__ __forceinline__ void blk_sum(double (&v)[NV], double* red) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+        double x = v[e];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+        v[e] = x;
+    }
+    if (W == 1) return;
+    if (lane == 0) {
+#pragma unroll
+        for (int e = 0; e < NV; ++e) red[wv * NV + e] = v[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+        double t = red[e];
+        for (int w = 1; w < W; ++w) t += red[w * NV + e];
+        v[e] = t;
+    }
+    __syncthreads();
+}
+
+// Integer sum over the block (xi: W ints).
+template <int W>
+__device__ __forceinline__ int blk_count(int v, int* xi) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (W == 1) return v;
+    if (lane == 0) xi[wv] = v;
+    __syncthreads();
+    int t = 0;
+    for (int w = 0; w < W; ++w) t += xi[w];
+    __syncthreads();
+    return t;
+}
+
+// Rank k among the <= 64 keys of the block under prefix (mask): each
+// wavefront writes its keys after those of the wavefronts before it into
+// cand, and every wavefront sorts the same 64 slots and reads the k-th.
+// nw: the rows this wavefront holds.
+template <int W, int NK>
+__device__ __forceinline__ uint64_t blk_finish_select(const uint64_t (&kr)[NK], int nw, uint64_t mask, uint64_t prefix, int64_t k,
+                                      uint64_t* cand, int* xi) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int q = 0; q < NK; ++q) cnt += (uint32_t)__popcll(__ballot(lane + 64 * q < nw && (kr[q] & mask) == prefix));
+    uint32_t base = 0, total = cnt;
+    if (W > 1) {
+        if (lane == 0) xi[wv] = (int)cnt;
+        __syncthreads();
+        total = 0;
+        for (int w = 0; w < W; ++w) {
+            if (w < wv) base += (uint32_t)xi[w];
+            total += (uint32_t)xi[w];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NK; ++q) {
+        const bool in = lane + 64 * q < nw && (kr[q] & mask) == prefix;
+        const uint64_t b = __ballot(in);
+        if (in) cand[base + __popcll(b & below)] = kr[q];
+        base += (uint32_t)__popcll(b);
+    }
+    __syncthreads();
+    uint64_t v = lane < (int)total ? cand[lane] : ~0ull;
+    __syncthreads();
+    v = wave_sort64(v);
+    const uint32_t lo = __shfl((uint32_t)v, (int)k, 64), hi = __shfl((uint32_t)(v >> 32), (int)k, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// reg_quantile7_pair over the keys of all W wavefronts of the block: the
+// histograms are shared, every thread reads the same counts, so every
+// wavefront takes the same digits; the closing counts and minima are
+// combined over the wavefronts in a fixed order.  hist: 512 counts; cand:
+// 64 keys; xi: 2 W ints; xk: 2 W keys.
+template <int W, int NK>
+__device__ __forceinline__ void blk_quantile7_pair(const uint64_t (&kr)[NK], int nw, int64_t m, double pa, double pb,
+                                   uint32_t* hist, uint64_t* cand, int* xi, uint64_t* xk, double& qa, double& qb) {
+    if (m <= 0) {
+        qa = qb = 0.0;
+        return;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const double ha_ = (double)(m - 1) * pa, hb_ = (double)(m - 1) * pb;
+    const int64_t ja = (int64_t)floor(ha_), jb = (int64_t)floor(hb_);
+    int64_t ka = ja, kb = jb;
+    uint64_t prea = 0, preb = 0, mask = 0;
+    bool done_a = false, done_b = false;
+    uint32_t* hista = hist;
+    uint32_t* histb = hist + 256;
+    for (int shift = 56; shift >= 0 && !(done_a && done_b); shift -= 8) {
+        for (int b = threadIdx.x; b < 512; b += 64 * W) hist[b] = 0u;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NK; ++q) {
+            if (lane + 64 * q < nw) {
+                const uint64_t key = kr[q];
+                const uint32_t dg = (uint32_t)(key >> shift) & 255u;
+                count_digits(hista, dg, !done_a && (key & mask) == prea);
+                count_digits(histb, dg, !done_b && (key & mask) == preb);
+            }
+        }
+        __syncthreads();
+        uint32_t ca = 65u, cb = 65u;
+        if (!done_a) {
+            int d;
+            uint32_t bel;
+            radix_digit(hista, ka, d, bel);
+            prea |= (uint64_t)d << shift;
+            ka -= (int64_t)bel;
+            ca = hista[d];
+        }
+        if (!done_b) {
+            int d;
+            uint32_t bel;
+            radix_digit(histb, kb, d, bel);
+            preb |= (uint64_t)d << shift;
+            kb -= (int64_t)bel;
+            cb = histb[d];
+        }
+        mask |= 0xFFull << shift;
+        __syncthreads();
+        if (shift > 0 && !done_a && ca <= 64u) {
+            prea = blk_finish_select<W>(kr, nw, mask, prea, ka, cand, xi);
+            done_a = true;
+        }
+        if (shift > 0 && !done_b && cb <= 64u) {
+            preb = blk_finish_select<W>(kr, nw, mask, preb, kb, cand, xi);
+            done_b = true;
+        }
+    }
+    uint32_t cla = 0, clb = 0;
+    uint64_t mna = ~0ull, mnb = ~0ull;
+#pragma unroll
+    for (int q = 0; q < NK; ++q) {
+        if (lane + 64 * q < nw) {
+            const uint64_t key = kr[q];
+            cla += key <= prea ? 1u : 0u;
+            clb += key <= preb ? 1u : 0u;
+            if (key > prea && key < mna) mna = key;
+            if (key > preb && key < mnb) mnb = key;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        cla += __shfl_xor(cla, o, 64);
+        clb += __shfl_xor(clb, o, 64);
+        uint32_t lo = __shfl_xor((uint32_t)mna, o, 64), hi = __shfl_xor((uint32_t)(mna >> 32), o, 64);
+        uint64_t other = ((uint64_t)hi << 32) | lo;
+        mna = other < mna ? other : mna;
+        lo = __shfl_xor((uint32_t)mnb, o, 64);
+        hi = __shfl_xor((uint32_t)(mnb >> 32), o, 64);
+        other = ((uint64_t)hi << 32) | lo;
+        mnb = other < mnb ? other : mnb;
+    }
+    if (W > 1) {
+        if (lane == 0) {
+            xi[2 * wv] = (int)cla;
+            xi[2 * wv + 1] = (int)clb;
+            xk[2 * wv] = mna;
+            xk[2 * wv + 1] = mnb;
+        }
+        __syncthreads();
+        cla = clb = 0;
+        mna = mnb = ~0ull;
+        for (int w = 0; w < W; ++w) {
+            cla += (uint32_t)xi[2 * w];
+            clb += (uint32_t)xi[2 * w + 1];
+            mna = xk[2 * w] < mna ? xk[2 * w] : mna;
+            mnb = xk[2 * w + 1] < mnb ? xk[2 * w + 1] : mnb;
+        }
+        __syncthreads();
+    }
+    const double xa = key_value(prea), xb = key_value(preb);
+    qa = ja + 1 >= m ? xa : xa + (ha_ - (double)ja) * (key_value((int64_t)cla >= ja + 2 ? prea : mna) - xa);
+    qb = jb + 1 >= m ? xb : xb + (hb_ - (double)jb) * (key_value((int64_t)clb >= jb + 2 ? preb : mnb) - xb);
+}
+
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_s_regs(DevConsts k, int64_t n_src, const int64_t* __restrict__ off,
+                                                   const double* __restrict__ ot, const double* __restrict__ oeta,
+                                                   const float* __restrict__ osig, const int32_t* __restrict__ ocell,
+                                                   const int32_t* __restrict__ oell,
+                                                   const double* __restrict__ knots,
+                                                   const KnotTab* __restrict__ ktab, const double* __restrict__ a,
+                                                   const double* __restrict__ c, const double* __restrict__ eps_a2,
+                                                   int eps_bucket, double* __restrict__ s,
+                                                   SrcPrep* __restrict__ prep, double* __restrict__ ds,
+                                                   double* __restrict__ qsrc, int32_t* __restrict__ sdef,
+                                                   double* __restrict__ svar, const int32_t* __restrict__ order,
+                                                   double* __restrict__ vs_out, int rows) {
+    __shared__ uint32_t hist[512];
+    __shared__ uint64_t cand[64];
+    __shared__ double red[W * 21];
+    __shared__ int xi[2 * W];
+    __shared__ uint64_t xk[2 * W];
+    if ((int64_t)blockIdx.x >= n_src) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t i = order[blockIdx.x];
+    const int64_t l0 = off[i];
+    const int n = (int)(off[i + 1] - l0);        // <= 64 rows W (the launcher's class)
+    const int nw = min(max(n - 64 * rows * wv, 0), 64 * rows);
+    const int64_t lw = l0 + 64 * rows * wv;      // this wavefront's first observation
+    double p[3], q[3], r[3], mu[3], plx;
+    {
+        const double* si = s + 5 * i;
+        double sa, ca, sd, cd;
+        sincos(si[0], &sa, &ca);
+        sincos(si[1], &sd, &cd);
+        p[0] = -sa;
+        p[1] = ca;
+        p[2] = 0.0;
+        q[0] = -sd * ca;
+        q[1] = -sd * sa;
+        q[2] = cd;
+        r[0] = cd * ca;
+        r[1] = cd * sa;
+        r[2] = sd;
+        plx = si[2];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) mu[cc] = p[cc] * si[3] + q[cc] * si[4];
+    }
+    // the rows: design row (alpha*, delta, parallax entries and tau), h,
+    // sigma~^2; bit qq of acm: row qq is across scan
+    double af[SR_M][4], s2v[SR_M], hv[SR_M];
+    uint32_t acm = 0;
+#pragma unroll
+    for (int qq = 0; qq < SR_M; ++qq) {
+        af[qq][0] = af[qq][1] = af[qq][2] = af[qq][3] = 0.0;
+        s2v[qq] = 1.0;
+        hv[qq] = 0.0;
+    }
+    // model pass: the current row with its gathers; the next row's columns
+    // load at the top of a step, its gathers after the current row has been
+    // evaluated (lanes past the end repeat the wavefront's last row)
+    double t_c = 0.0, e_c = 0.0, cal_c = 0.0, ea_c = 0.0;
+    float s_c = 1.0f;
+    int32_t ell_c = 3, cf_c = 0;
+    double a_c[16];
+    KnotTab kt_c = {0.0, 1.0, 0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < 16; ++e) a_c[e] = 0.0;
+    if (nw > 0) {
+        const int64_t le = lw + (lane < nw ? lane : nw - 1);
+        t_c = ot[le];
+        e_c = oeta[le];
+        s_c = osig[le];
+        ell_c = oell[le];
+        cf_c = ocell[le];
+        cal_c = c[cf_c >> 1];
+        ea_c = eps_a2[eps_slot(k, cf_c, ell_c - 3, eps_bucket)];
+        const double* a4 = a + 4 * (ell_c - 3);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) a_c[e] = a4[e];
+        kt_c = ktab[ell_c - 3];
+    }
+    for (int qs = 0; qs < SR_M && 64 * qs < nw; ++qs) {
+        const int rn = 64 * (qs + 1) + lane;
+        const bool more = 64 * (qs + 1) < nw;    // the wavefront has a next step
+        double t_n = 0.0, e_n = 0.0;
+        float s_n = 1.0f;
+        int32_t cf_n = 0, ell_n = 3;
+        if (more) {
+            const int64_t le = lw + (rn < nw ? rn : nw - 1);
+            t_n = ot[le];
+            e_n = oeta[le];
+            s_n = osig[le];
+            cf_n = ocell[le];
+            ell_n = oell[le];
+        }
+        const bool ac = cf_c >= k.ac_cf0;
+        ObsEval o;
+        observe(k, t_c, e_c, cal_c, r, mu, plx, a_c, knots + (ell_c - 2), kt_c, o, ac);
+        double A[5];
+        source_partials(o, p, q, r, A, ac);
+        const double sg = (double)s_c;
+        const double s2 = sg * sg + ea_c;
+        if (ac && 64 * qs + lane < nw) acm |= 1u << qs;
+#pragma unroll
+        for (int qq = 0; qq < SR_M; ++qq) {
+            if (qq == qs) {
+                af[qq][0] = A[0];
+                af[qq][1] = A[1];
+                af[qq][2] = A[2];
+                af[qq][3] = o.tau;               // A[3] = A[0] tau, A[4] = A[1] tau
+                hv[qq] = o.R;
+                s2v[qq] = s2;
+            }
+        }
+        if (more) {
+            const double* a4 = a + 4 * (ell_n - 3);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) a_c[e] = a4[e];
+            kt_c = ktab[ell_n - 3];
+            cal_c = c[cf_n >> 1];
+            ea_c = eps_a2[eps_slot(k, cf_n, ell_n - 3, eps_bucket)];
+        }
+        t_c = t_n;
+        e_c = e_n;
+        s_c = s_n;
+        cf_c = cf_n;
+        ell_c = ell_n;
+    }
+    // varsigma per kind of record: half the intersextile range of its h
+    const int n_ac = blk_count<W>(__popc(acm), xi);
+    double vk0 = 0.0, vk1 = 0.0;
+    for (int kind = 0; kind < 2; ++kind) {
+        const int64_t m = kind ? n_ac : n - n_ac;
+        if (m <= 0) continue;
+        uint64_t kr[SR_M];
+#pragma unroll
+        for (int qq = 0; qq < SR_M; ++qq)
+            kr[qq] = (lane + 64 * qq < nw && (int)((acm >> qq) & 1u) == kind) ? order_key(hv[qq]) : ~0ull;
+        double q5, q1;
+        blk_quantile7_pair<W>(kr, nw, m, 5.0 / 6.0, 1.0 / 6.0, hist, cand, xi, xk, q5, q1);
+        if (kind == 0) vk0 = 0.5 * (q5 - q1);
+        else vk1 = 0.5 * (q5 - q1);
+    }
+    if (threadIdx.x == 0) {
+        vs_out[2 * i] = vk0;
+        vs_out[2 * i + 1] = vk1;
+    }
+    // the inner iteration
+    double d[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double acc[21];
+    for (int it = 0; it < INNER_SOLVES; ++it) {
+        const bool last = it + 1 == INNER_SOLVES;
+#pragma unroll
+        for (int e = 0; e < 21; ++e) acc[e] = 0.0;
+#pragma unroll
+        for (int qq = 0; qq < SR_M; ++qq) {
+            if (lane + 64 * qq < nw) {
+                double A[5];
+                const double h = hv[qq], s2 = s2v[qq];
+                A[0] = af[qq][0];
+                A[1] = af[qq][1];
+                A[2] = af[qq][2];
+                A[3] = A[0] * af[qq][3];         // as the design row forms them
+                A[4] = A[1] * af[qq][3];
+                double wl;
+                if (it == 0) {
+                    const double v = ((acm >> qq) & 1u) ? vk1 : vk0;
+                    wl = v > 0.0 ? down_weight(h / v) : 1.0;
+                } else {
+                    double R = h;
+#pragma unroll
+                    for (int e = 0; e < 5; ++e) R -= A[e] * d[e];
+                    wl = down_weight(R / sqrt(s2));
+                }
+                const double Wt = wl / s2;
+                int e = 0;
+#pragma unroll
+                for (int rr = 0; rr < 5; ++rr) {
+                    const double wa = A[rr] * Wt;
+#pragma unroll
+                    for (int cc = rr; cc < 5; ++cc) acc[e++] += wa * A[cc];
+                }
+#pragma unroll
+                for (int rr = 0; rr < 5; ++rr) acc[15 + rr] += A[rr] * Wt * h;
+                acc[20] += Wt * h * h;
+            }
+        }
+        blk_sum<W, 21>(acc, red);
+        if (!last) {
+            // lane 0 of each wavefront solves (the same numbers in each);
+            // every lane takes d
+            double x[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            if (lane == 0) {
+                double U[25];
+                int e = 0;
+                for (int rr = 0; rr < 5; ++rr)
+                    for (int cc = rr; cc < 5; ++cc) U[rr * 5 + cc] = acc[e++];
+                for (int rr = 0; rr < 5; ++rr) x[rr] = acc[15 + rr];
+                small_chol_factor<5>(U);
+                small_chol_subst<5>(U, x);
+            }
+#pragma unroll
+            for (int e = 0; e < 5; ++e) d[e] = __shfl(x[e], 0, 64);
+        }
+    }
+    if (threadIdx.x != 0) return;
+    const double* si = s + 5 * i;
+    source_finish(acc, i, si[0], si[1], si[2], si[3], si[4], cos(si[1]), s, prep, ds, qsrc, sdef, svar);
+}
+
 // Excess attitude noise in one kernel: one block of NT threads per bucket of
 // eps_bucket knot intervals evaluates R^2 - sigma^2 (- eps_i^2 in robust mode
 // 2) of the bucket's observations into LDS, with the attitude component each
@@ -1329,6 +1772,17 @@ static void source_solve_columns(agis_ctx* ctx, int64_t k0, int64_t n) {
               : (reg ? (pair ? k_s_sigma<2, false> : k_s_sigma<1, false>) : k_s_sigma<0, false>))
         <<<(unsigned)n_src, 64, 0, ctx->stream>>>(n_src, ctx->src_off, ctx->rcol + 4 * ctx->n_obs, ctx->vs,
                                                   select_reg_limit(ctx), order, ac_cells, ctx->k.ac_cf0);
+    if (ctx->cfg.robust == 1 && ctx->irls_cache > 0) {
+        // the lanes' first records cached in registers across the rounds
+#define AGIS_IRLS_CACHED(G)                                                                                      \
+    k_s_irls<G, IRLS_RC><<<groups_grid(n_src, 256 / G), 256, 0, ctx->stream>>>(                                  \
+        n_src, ctx->src_off, ctx->rcol, ctx->n_obs, ctx->vs, ctx->s, ctx->prep, ctx->ds, ctx->qsrc, ctx->sdef,    \
+        ctx->svar, order, ac_cells, ctx->k.ac_cf0)
+        if (ctx->irls_cache == 1) AGIS_IRLS_CACHED(32);
+        else AGIS_IRLS_CACHED(64);
+#undef AGIS_IRLS_CACHED
+        return;
+    }
     switch (ctx->s_group) {
         case 8: AGIS_IRLS_LAUNCH(8); break;
         case 16: AGIS_IRLS_LAUNCH(16); break;
@@ -1341,6 +1795,8 @@ static void source_solve_columns(agis_ctx* ctx, int64_t k0, int64_t n) {
 // excess source noise of mode 2 keeps the HBM-column kernels).
 static bool s_lds(const agis_ctx* ctx) { return ctx->robust_s_mode >= 1 && ctx->cfg.robust == 1; }
 static bool s_from_columns(const agis_ctx* ctx) { return ctx->robust_s_mode == 1; }
+static bool s_regs(const agis_ctx* ctx) { return ctx->robust_s_mode == 3; }
+static int sreg_rows(const agis_ctx* ctx) { return std::min(std::max(ctx->sreg_rows, 1), SR_M); }
 static bool eps_one_kernel(const agis_ctx* ctx) { return ctx->robust_fused_eps && ctx->cfg.robust >= 1; }
 
 void launch_source_update_robust(agis_ctx* ctx) {
@@ -1354,6 +1810,28 @@ void launch_source_update_robust(agis_ctx* ctx) {
     // the sources beyond the largest LDS class: the HBM-column kernels
     source_rows(ctx, 0, from_col ? ctx->n_src : ctx->s_fallback);
     source_solve_columns(ctx, 0, ctx->s_fallback);
+    if (s_regs(ctx)) {
+        for (const SClass& cl : ctx->s_classes) {
+            const int64_t n = cl.k1 - cl.k0;
+#define AGIS_SREG_LAUNCH(W)                                                                                      \
+    k_s_regs<W><<<(unsigned)n, 64 * W, 0, ctx->stream>>>(                                                        \
+        ctx->k, n, ctx->src_off, ctx->s_t, ctx->s_eta, ctx->s_sig, ctx->s_cell, ctx->s_ell, ctx->knots, ctx->ktab,  \
+        ctx->a, ctx->c, ctx->eps_a2, ctx->cfg.eps_bucket, ctx->s, ctx->prep, ctx->ds, ctx->qsrc, ctx->sdef,        \
+        ctx->svar, ctx->src_order + cl.k0, ctx->vs, sreg_rows(ctx))
+            switch (cl.nt / 64) {
+                case 1: AGIS_SREG_LAUNCH(1); break;
+                case 2: AGIS_SREG_LAUNCH(2); break;
+                case 3: AGIS_SREG_LAUNCH(3); break;
+                case 4: AGIS_SREG_LAUNCH(4); break;
+                case 5: AGIS_SREG_LAUNCH(5); break;
+                case 6: AGIS_SREG_LAUNCH(6); break;
+                case 7: AGIS_SREG_LAUNCH(7); break;
+                default: AGIS_SREG_LAUNCH(8); break;
+            }
+#undef AGIS_SREG_LAUNCH
+        }
+        return;
+    }
     for (const SClass& cl : ctx->s_classes) {
         const int64_t n = cl.k1 - cl.k0;
         const size_t lds = s_lds_bytes(cl.cap);
@@ -1401,6 +1879,24 @@ int robust_plan(agis_ctx* ctx, const std::vector<int64_t>& h_off, const std::vec
     const int64_t n_src = (int64_t)order.size();
     // classes: walk the count-ordered list from the smallest counts up
     int64_t k1 = s_lds(ctx) ? n_src : 0;
+    if (s_regs(ctx)) {
+        // register path: W wavefronts for up to 64 rows W rows
+        for (int W = 1; W <= SR_WMAX && k1 > 0; ++W) {
+            const int cap = 64 * sreg_rows(ctx) * W;
+            int64_t k0 = k1;
+            while (k0 > 0) {
+                const int32_t i = order[k0 - 1];
+                const int64_t cnt = h_off[i + 1] - h_off[i];
+                if (cnt > cap || cnt > ctx->robust_max_cap) break;
+                --k0;
+            }
+            if (k0 < k1) ctx->s_classes.push_back(SClass{k0, k1, cap, 64 * W});
+            k1 = k0;
+        }
+        ctx->s_fallback = k1;
+        std::reverse(ctx->s_classes.begin(), ctx->s_classes.end());
+        k1 = 0;                          // no LDS classes
+    }
     for (int ci = (int)(sizeof kSCaps / sizeof kSCaps[0]) - 1; ci >= 0 && k1 > 0; --ci) {
         const int cap = kSCaps[ci];
         if ((int64_t)s_lds_bytes(cap) > dyn_max || cap > ctx->robust_max_cap) break;
@@ -1413,11 +1909,14 @@ int robust_plan(agis_ctx* ctx, const std::vector<int64_t>& h_off, const std::vec
         if (k0 < k1) ctx->s_classes.push_back(SClass{k0, k1, cap, s_threads(cap)});
         k1 = k0;
     }
-    ctx->s_fallback = k1;
-    // largest classes first (the count order)
-    std::reverse(ctx->s_classes.begin(), ctx->s_classes.end());
+    if (!s_regs(ctx)) {
+        ctx->s_fallback = k1;
+        // largest classes first (the count order)
+        std::reverse(ctx->s_classes.begin(), ctx->s_classes.end());
+    }
     int used_max[3] = {0, 0, 0};
     for (const SClass& cl : ctx->s_classes) {
+        if (s_regs(ctx)) break;
         const int slot = cl.nt == 64 ? 0 : (cl.nt == 128 ? 1 : 2);
         used_max[slot] = std::max(used_max[slot], (int)s_lds_bytes(cl.cap));
     }

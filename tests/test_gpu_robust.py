@@ -59,19 +59,32 @@ def test_excess_noise_parity(agis_mod, oracle_lib, tiny_robust):
     p.close()
 
 
-@pytest.mark.parametrize("path", ["one kernel", "columns", "rows then LDS", "mixed", "rows then LDS, mixed"])
+PATH_ENV = {"one kernel": {"AGIS_ROBUST_FUSED": "2"}, "columns": {"AGIS_ROBUST_FUSED": "0"},
+            "rows then LDS": {"AGIS_ROBUST_FUSED": "3"}, "registers": {"AGIS_ROBUST_FUSED": "4"},
+            "mixed": {"AGIS_ROBUST_FUSED": "2", "AGIS_ROBUST_MAX_CAP": "32"},
+            "rows then LDS, mixed": {"AGIS_ROBUST_FUSED": "3", "AGIS_ROBUST_MAX_CAP": "32"},
+            "registers, mixed": {"AGIS_ROBUST_FUSED": "4", "AGIS_ROBUST_MAX_CAP": "32"},
+            "registers, one row per lane": {"AGIS_ROBUST_FUSED": "4", "AGIS_SREG_ROWS": "1",
+                                            "AGIS_ROBUST_MAX_CAP": "300"},
+            "columns, 32 lanes": {"AGIS_ROBUST_FUSED": "1", "AGIS_S_GROUP": "32"},
+            "columns, 32 lanes, cached": {"AGIS_ROBUST_FUSED": "1", "AGIS_IRLS_CACHE": "1"},
+            "columns, 64 lanes": {"AGIS_ROBUST_FUSED": "1", "AGIS_S_GROUP": "64"},
+            "columns, 64 lanes, cached": {"AGIS_ROBUST_FUSED": "1", "AGIS_IRLS_CACHE": "2"}}
+PATH_VARS = ("AGIS_ROBUST_FUSED", "AGIS_ROBUST_MAX_CAP", "AGIS_SREG_ROWS", "AGIS_S_GROUP", "AGIS_IRLS_CACHE")
+
+
+@pytest.mark.parametrize("path", ["one kernel", "columns", "rows then LDS", "registers", "mixed",
+                                  "rows then LDS, mixed", "registers, mixed"])
 def test_robust_source_update_parity(agis_mod, oracle_lib, tiny_robust, path, monkeypatch):
     """The robust S update on its paths: every source in the one-kernel path
     (model, varsigma and solves per source in LDS), every source through HBM
     columns (three kernels; the default), the rows to HBM columns and then
-    varsigma and the solves per source in LDS, and each of the LDS paths
-    with the sources of more than 32 observations on the column kernels."""
+    varsigma and the solves per source in LDS, every source with its rows
+    in registers, and each of the on-chip paths with the sources of more
+    than 32 observations on the column kernels."""
     w, eta = tiny_robust
-    env = {"one kernel": {"AGIS_ROBUST_FUSED": "2"}, "columns": {"AGIS_ROBUST_FUSED": "0"},
-           "rows then LDS": {"AGIS_ROBUST_FUSED": "3"},
-           "mixed": {"AGIS_ROBUST_FUSED": "2", "AGIS_ROBUST_MAX_CAP": "32"},
-           "rows then LDS, mixed": {"AGIS_ROBUST_FUSED": "3", "AGIS_ROBUST_MAX_CAP": "32"}}[path]
-    for k in ("AGIS_ROBUST_FUSED", "AGIS_ROBUST_MAX_CAP"):
+    env = PATH_ENV[path]
+    for k in PATH_VARS:
         monkeypatch.delenv(k, raising=False)
     for k, v in env.items():
         monkeypatch.setenv(k, v)
@@ -91,6 +104,69 @@ def test_robust_source_update_parity(agis_mod, oracle_lib, tiny_robust, path, mo
     agis_mod.agis_source_update(p.ctx)
     G = p.gpu_state()
     dg = check_floor("robust S update", X[0], O[0], G[0], tol[0], 0, mask=good)
+    assert np.mean(np.abs(dg) <= 1e-3) > 0.95
+    p.close()
+
+
+@pytest.fixture(scope="module")
+def small9_robust(oracle_lib):
+    w = C.make("small9", robust=True, outlier_frac=0.01, years=1.0, min_transits=6)
+    return w, oracle_lib.observed_field_angles(w)
+
+
+def test_irls_register_cache_is_bitwise(agis_mod, oracle_lib, small9_robust, monkeypatch):
+    """The inner rounds with each lane's first eight records kept in
+    registers take the records in the same order as the rounds that re-read
+    them: 32 and 64 lanes per source, cached and not, the same sources bit
+    for bit (the nine-CCD world: 54-351 records per source, so records
+    beyond the cache at 32 lanes)."""
+    w, eta = small9_robust
+    out = {}
+    for path in ("columns, 32 lanes", "columns, 32 lanes, cached", "columns, 64 lanes", "columns, 64 lanes, cached"):
+        for k in PATH_VARS:
+            monkeypatch.delenv(k, raising=False)
+        for k, v in PATH_ENV[path].items():
+            monkeypatch.setenv(k, v)
+        p = Pair(agis_mod, oracle_lib, w, eta)
+        agis_mod.agis_source_update(p.ctx)
+        out[path] = p.gpu_state()[0]
+        p.close()
+    for k in PATH_VARS:
+        monkeypatch.delenv(k, raising=False)
+    assert np.array_equal(out["columns, 32 lanes"], out["columns, 32 lanes, cached"])
+    assert np.array_equal(out["columns, 64 lanes"], out["columns, 64 lanes, cached"])
+
+
+@pytest.mark.parametrize("path", ["registers, one row per lane", "columns", "columns, 64 lanes, cached"])
+def test_robust_source_update_several_wavefronts(agis_mod, oracle_lib, small9_robust, path, monkeypatch):
+    """The register path with a source spread over several wavefronts
+    (one row per lane: 64 rows a wavefront; the nine-CCD world over one year
+    with 1% outliers, stars with at least six transits, has 54-351
+    observations per source, so up to five wavefronts a source, and the
+    sources above 300 observations on the column kernels): the block-wide
+    selection of varsigma and the block-wide sums of the inner rounds,
+    against the oracle; and the column path on the same world, with and
+    without the register cache of its inner rounds."""
+    w, eta = small9_robust
+    nobs = np.bincount(w.src, minlength=w.src_true.shape[0])
+    assert (nobs > 300).any() and (nobs > 256).sum() > 100 and (nobs <= 64).any()
+    for k in PATH_VARS:
+        monkeypatch.delenv(k, raising=False)
+    for k, v in PATH_ENV[path].items():
+        monkeypatch.setenv(k, v)
+
+    def run(pr):
+        _, _, de = pr.source_update()
+        run.defect = de
+        return pr.s.copy(), pr.a.copy(), pr.c.copy()
+
+    X, O, tol = fp64_floor(oracle_lib, w, eta, run)
+    run(oracle_lib.problem_from_world(w, eta, state="start"))
+    good = run.defect == 0
+    p = Pair(agis_mod, oracle_lib, w, eta)
+    agis_mod.agis_source_update(p.ctx)
+    G = p.gpu_state()
+    dg = check_floor(f"robust S update, {path}", X[0], O[0], G[0], tol[0], 0, mask=good)
     assert np.mean(np.abs(dg) <= 1e-3) > 0.95
     p.close()
 
