@@ -34,12 +34,13 @@ def _structs(c_r):
         _fields_ = [("n_knots", c_i64), ("knots", P(c_r)), ("gamma_c", c_r), ("t_ep", c_r), ("t_fr", c_r),
                     ("lambda_reg", c_r), ("seg_len", c_i32), ("seg_overlap", c_i32), ("eph_radius_au", c_r),
                     ("eph_L0", c_r), ("eph_Lrate", c_r), ("eps_obl", c_r), ("au_m", c_r), ("c_mps", c_r),
-                    ("year_s", c_r), ("robust", c_i32), ("eps_bucket", c_i32), ("geo_ccds", c_i32)]
+                    ("year_s", c_r), ("robust", c_i32), ("eps_bucket", c_i32), ("geo_ccds", c_i32),
+                    ("geo_ac_cells", c_i32)]
 
     class Obs(ctypes.Structure):
         _fields_ = [("n", c_i64), ("t", P(c_r)), ("eta_obs", P(c_r)), ("sigma", P(c_f)), ("src", P(c_i32)),
                     ("fov", P(c_i8)), ("cell", P(c_i32)), ("sigma_eff", P(c_r)), ("ccd", P(c_i8)),
-                    ("mu", P(c_f))]
+                    ("mu", P(c_f)), ("ac_cell", P(c_i32))]
 
     class State(ctypes.Structure):
         _fields_ = [("n_src", c_i64), ("n_att", c_i64), ("n_cells", c_i64), ("s", P(c_r)), ("a", P(c_r)),
@@ -248,7 +249,7 @@ class Problem:
     """
 
     def __init__(self, consts, knots, t, eta_obs, sigma, src, fov, cell, s, a, c, precision="double",
-                 sigma_eff=None, ccd=None, mu=None, geo=None):
+                 sigma_eff=None, ccd=None, mu=None, geo=None, ac_cell=None):
         self.precision = precision
         self._cr, self._dt = PRECISIONS[precision][0], PRECISIONS[precision][1]
         self._World, self._Obs, self._State = _STRUCTS[precision]
@@ -260,15 +261,19 @@ class Problem:
         # the frozen sigma_eff of the hybrid scheme, replacing sigma (or None)
         self.sigma_eff = None if sigma_eff is None else self._arr(sigma_eff).copy()
         # geometric calibration (consts geo_ccds > 0): CCD index and AC pixel
-        # coordinate per record, coefficients [n_cells][geo_ccds][3]
+        # coordinate per record, coefficients [n_cells][geo_ccds][3]; with
+        # ac_cell (the across-scan records' calibration cells) the AC term
+        # too, its coefficients after the AL ones
         geo_ccds = int(consts.get("geo_ccds", 0) or 0)
         if geo_ccds > 0:
             self.ccd = np.ascontiguousarray(ccd, dtype=np.int8)
             self.mu = np.ascontiguousarray(mu, dtype=np.float32)
+            self.ac_cell = None if ac_cell is None else np.ascontiguousarray(ac_cell, dtype=np.int32)
             self.geo = self._arr(np.reshape(geo, -1)).copy()
-            assert self.geo.size == np.size(c) * geo_ccds * 3
+            n_ac = 0 if ac_cell is None else int(consts.get("geo_ac_cells", 0) or 0)
+            assert self.geo.size == (np.size(c) + n_ac) * geo_ccds * 3
         else:
-            self.ccd = self.mu = self.geo = None
+            self.ccd = self.mu = self.geo = self.ac_cell = None
         self.src = np.ascontiguousarray(src, dtype=np.int32)
         self.fov = np.ascontiguousarray(fov, dtype=np.int8)
         self.cell = np.ascontiguousarray(cell, dtype=np.int32)
@@ -284,7 +289,7 @@ class Problem:
                                  eph_Lrate=consts["eph_Lrate"], eps_obl=consts["eps_obl"], au_m=consts["au_m"],
                                  c_mps=consts["c_mps"], year_s=consts["year_s"],
                                  robust=int(consts.get("robust", 0)), eps_bucket=int(consts.get("eps_bucket", 8)),
-                                 geo_ccds=geo_ccds)
+                                 geo_ccds=geo_ccds, geo_ac_cells=int(consts.get("geo_ac_cells", 0) or 0))
         n_iv = self.knots.size - 7
         if self.world.robust:
             # three components (along scan, across scan preceding and
@@ -309,7 +314,7 @@ class Problem:
         self.obs = self._Obs(n=self.t.size, t=_p(self.t, cr), eta_obs=_p(self.eta_obs, cr),
                              sigma=_p(self.sigma, c_f), src=_p(self.src, c_i32), fov=_p(self.fov, c_i8),
                              cell=_p(self.cell, c_i32), sigma_eff=_p(self.sigma_eff, cr),
-                             ccd=_p(self.ccd, c_i8), mu=_p(self.mu, c_f))
+                             ccd=_p(self.ccd, c_i8), mu=_p(self.mu, c_f), ac_cell=_p(self.ac_cell, c_i32))
         self.state = self._State(n_src=self.s.shape[0], n_att=self.a.shape[0], n_cells=self.c.size,
                                  s=_p(self.s, cr), a=_p(self.a, cr), c=_p(self.c, cr),
                                  n_buckets=self.eps_a2.size // 3, eps_a2=_p(self.eps_a2, cr),
@@ -455,20 +460,28 @@ def problem_from_world(world, eta_obs=None, state="start", precision="double"):
     """Build a Problem from a synth.World; eta_obs defaults to zeros."""
     n = world.t.size
     eta = np.zeros(n) if eta_obs is None else eta_obs
-    if state == "start":
-        s, a, c = world.src_start, world.att_start, world.cal_start
-        geo = getattr(world, "geo_start", None)
-    else:
-        s, a, c = world.src_true, world.att_true, world.cal_true
-        geo = getattr(world, "geo_true", None)
+    which = "start" if state == "start" else "true"
+    s, a, c = getattr(world, f"src_{which}"), getattr(world, f"att_{which}"), getattr(world, f"cal_{which}")
     return Problem(world.consts, world.knots, world.t, eta, world.sigma, world.src, world.fov, world.cell, s, a, c,
-                   precision=precision, ccd=getattr(world, "ccd", None), mu=getattr(world, "mu", None), geo=geo)
+                   precision=precision, ccd=getattr(world, "ccd", None), mu=getattr(world, "mu", None),
+                   geo=world_geo(world, which), ac_cell=getattr(world, "ac_cell", None))
+
+
+def world_geo(world, which="true"):
+    """The world's geometric coefficients (true or start), AL then AC; None
+    without the geometric model."""
+    g = getattr(world, f"geo_{which}", None)
+    if g is None:
+        return None
+    ga = getattr(world, f"geo_ac_{which}", None)
+    return np.reshape(g, -1) if ga is None else np.concatenate([np.reshape(g, -1), np.reshape(ga, -1)])
 
 
 def observed_field_angles(world, chunk=1 << 24):
     """eta_obs = eta(t | s_true, a_true) - c_true(cell) + noise (Sect. 3.5 at
     the truth); for an across-scan observation (cell < 0) zeta(t | s_true,
-    a_true) + noise (eq:resAC, no calibration term).  Evaluated over chunks
+    a_true) + noise (eq:resAC; minus the true AC geometric term where the
+    world has one).  Evaluated over chunks
     of at most `chunk` observations (memory: the model's outputs per
     observation)."""
     n = world.t.size
@@ -482,13 +495,11 @@ def observed_field_angles(world, chunk=1 << 24):
         pr = Problem(consts, world.knots, world.t[sl], np.zeros(i1 - i0), world.sigma[sl], world.src[sl],
                      world.fov[sl], world.cell[sl], world.src_true, world.att_true, world.cal_true,
                      ccd=None if geo_ccds == 0 else world.ccd[sl], mu=None if geo_ccds == 0 else world.mu[sl],
-                     geo=None if geo_ccds == 0 else world.geo_true)
+                     geo=None if geo_ccds == 0 else world_geo(world, "true"),
+                     ac_cell=None if getattr(world, "ac_cell", None) is None else world.ac_cell[sl])
         o = pr.observe()
-        cell = world.cell[sl]
-        ac = cell < 0
         # the residual of eta_obs = 0 is the calibration minus the computed
-        # field angle (eq:resAL), so eta_obs = eta - calibration + noise
-        # makes it the noise at the truth
-        al = -np.asarray(o["R"])
-        out[sl] = np.where(ac, np.asarray(o["zeta"]), al) + world.eps[sl]
+        # field angle (eq:resAL; eq:resAC across scan), so eta_obs = eta -
+        # calibration + noise makes it the noise at the truth
+        out[sl] = -np.asarray(o["R"]) + world.eps[sl]
     return out

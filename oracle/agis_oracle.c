@@ -286,22 +286,28 @@ static double shifted_legendre(int r, double x) {
     return 6.0 * x * x - 6.0 * x + 1.0;
 }
 
-/* Index of the first of the three geometric coefficients of an along-scan
- * record: its cell and CCD. */
-static int64_t geo_index(const orc_world_t* w, const orc_obs_t* obs, int64_t l) {
-    return 3 * ((int64_t)obs->cell[l] * w->geo_ccds + obs->ccd[l]);
+/* Index of the first of the three geometric coefficients of a record: an
+ * along-scan record's cell and CCD (the AL term of eq:etazeta); with the AC
+ * calibration an across-scan record's cell and CCD among the AC groups,
+ * which follow all the AL ones (the AC term); -1 for an across-scan record
+ * without it. */
+static int64_t geo_index(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, int64_t l) {
+    if (obs->cell[l] >= 0) return 3 * ((int64_t)obs->cell[l] * w->geo_ccds + obs->ccd[l]);
+    if (!obs->ac_cell) return -1;
+    return 3 * ((st->n_cells + (int64_t)obs->ac_cell[l]) * w->geo_ccds + obs->ccd[l]);   /* AC cells follow */
 }
 
 /* Argument of the shifted Legendre polynomials: the AC pixel coordinate
  * mapped to [0, 1] (eq:etazeta). */
 static double geo_x(const orc_obs_t* obs, int64_t l) { return ((double)obs->mu[l] - 13.5) / 1966.0; }
 
-/* The large-scale AL geometric calibration of an along-scan record
- * (eq:etazeta): sum over r of its cell and CCD's coefficients times
- * L*_r(x); 0 without the geometric model or across scan. */
+/* The large-scale geometric calibration of a record (eq:etazeta): sum over
+ * r of its group's coefficients times L*_r(x); 0 without the geometric
+ * model, or across scan without the AC calibration. */
 static double geo_term(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, int64_t l) {
-    if (w->geo_ccds <= 0 || obs->cell[l] < 0) return 0.0;
-    const int64_t g = geo_index(w, obs, l);
+    if (w->geo_ccds <= 0) return 0.0;
+    const int64_t g = geo_index(w, obs, st, l);
+    if (g < 0) return 0.0;
     const double x = geo_x(obs, l);
     double v = 0.0;
     for (int r = 0; r < 3; ++r) v += st->geo[g + r] * shifted_legendre(r, x);
@@ -351,7 +357,8 @@ static void forward_one(const orc_world_t* w, const orc_obs_t* obs, const orc_st
     o->eta = o->phi - o->f * 0.5 * w->gamma_c;
     /* eq:resAL with the generic calibration model (eq:generic1); eq:resAC */
     o->ac = obs->cell[l] < 0;
-    o->R = o->ac ? obs->eta_obs[l] - o->zeta : obs->eta_obs[l] + geo_term(w, obs, st, l) + st->c[obs->cell[l]] - o->eta;
+    o->R = o->ac ? obs->eta_obs[l] + geo_term(w, obs, st, l) - o->zeta
+                 : obs->eta_obs[l] + geo_term(w, obs, st, l) + st->c[obs->cell[l]] - o->eta;
 }
 
 /* Sect. 5.1.3: design row -dR/ds for (alpha*, delta, parallax, mu_alpha*,
@@ -866,27 +873,33 @@ int64_t orc_attitude_update(const orc_world_t* w, const orc_obs_t* obs, orc_stat
  * constraint per day, c_P + c_F = 0 (eq:cc1 for this model).
  * ====================================================================== */
 /* Number of calibration unknowns: one per cell, or with the geometric
- * model three per cell and CCD. */
-static int64_t cal_size(const orc_world_t* w, const orc_state_t* st) {
-    return w->geo_ccds > 0 ? st->n_cells * w->geo_ccds * 3 : st->n_cells;
+ * model three per cell and CCD, twice that with the AC calibration. */
+static int64_t cal_size(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st) {
+    if (w->geo_ccds <= 0) return st->n_cells;
+    return (st->n_cells + (obs->ac_cell ? (int64_t)w->geo_ac_cells : 0)) * w->geo_ccds * 3;
 }
 
 /* Geometric calibration (Sect. 5.3 with eq:etazeta): eq:normC for each
- * group of three coefficients (cell and CCD), whose records share no
- * coefficient with another group, W from the A/C weights; the 3x3 systems
- * by C1-C3; then eq:calCon with the constraint eq:cc1 (for each day, the
- * constant terms of its two cells and all CCDs sum to zero): the constant
- * terms' mean over the day is subtracted. */
+ * group of three coefficients (cell and CCD, along or across scan), whose
+ * records share no coefficient with another group, W from the A/C weights;
+ * the 3x3 systems by C1-C3; then eq:calCon with the constraints: eq:cc1
+ * (for each day, the AL constant terms of its two cells and all CCDs sum to
+ * zero) and, with the AC calibration, eq:cc3 (for each AC cell, i.e. field
+ * of view and long interval, the AC constant terms of its CCDs sum to zero); the
+ * constraint columns do not overlap, so each projection subtracts the mean
+ * constant term of its set. */
 static void calibration_solve_geo(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, double* d) {
-    const int64_t ng = st->n_cells * w->geo_ccds;
+    const int64_t ng_al = st->n_cells * w->geo_ccds;
+    const int64_t ng = cal_size(w, obs, st) / 3;
     double* N = (double*)calloc((size_t)(9 * ng), sizeof(double));
     double* b = (double*)calloc((size_t)(3 * ng), sizeof(double));
     for (int64_t l = 0; l < obs->n; ++l) {
-        if (obs->cell[l] < 0) continue;              /* across scan: no calibration term */
+        const int64_t g3 = geo_index(w, obs, st, l);
+        if (g3 < 0) continue;                        /* across scan without the AC calibration */
         orc_fwd_t o;
         forward_one(w, obs, st, l, &o);
         double W = weight(w, obs, st, l, &o);
-        const int64_t g = geo_index(w, obs, l) / 3;
+        const int64_t g = g3 / 3;
         const double x = geo_x(obs, l);
         double L[3];
         for (int r = 0; r < 3; ++r) L[r] = shifted_legendre(r, x);     /* dR/dc_r (eq:pdC) */
@@ -907,20 +920,29 @@ static void calibration_solve_geo(const orc_world_t* w, const orc_obs_t* obs, co
     /* eq:calCon for eq:cc1: C has one column per day, with ones at the
      * constant terms of the day's 2 geo_ccds groups; C'C = 2 geo_ccds I */
     const int64_t per_day = 2 * w->geo_ccds;
-    for (int64_t j = 0; (j + 1) * per_day <= ng; ++j) {
+    for (int64_t j = 0; (j + 1) * per_day <= ng_al; ++j) {
         double ctd = 0.0;
         for (int64_t k = 0; k < per_day; ++k) ctd += d[3 * (j * per_day + k)];
         const double z = ctd / (double)per_day;
         for (int64_t k = 0; k < per_day; ++k) d[3 * (j * per_day + k)] -= z;
+    }
+    /* eq:calCon for eq:cc3: one column per AC cell, with ones at the
+     * constant terms of the cell's geo_ccds AC groups; C'C = geo_ccds I */
+    for (int64_t c = 0; ng > ng_al && c < w->geo_ac_cells; ++c) {
+        const int64_t g0 = ng_al + c * w->geo_ccds;
+        double ctd = 0.0;
+        for (int64_t k = 0; k < w->geo_ccds; ++k) ctd += d[3 * (g0 + k)];
+        const double z = ctd / (double)w->geo_ccds;
+        for (int64_t k = 0; k < w->geo_ccds; ++k) d[3 * (g0 + k)] -= z;
     }
     free(N);
     free(b);
 }
 
 /* The calibration update d (cal_size entries) applied to the state. */
-static void apply_calibration(const orc_world_t* w, orc_state_t* st, const double* d) {
+static void apply_calibration(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st, const double* d) {
     if (w->geo_ccds > 0) {
-        for (int64_t k = 0; k < cal_size(w, st); ++k) st->geo[k] += d[k];
+        for (int64_t k = 0; k < cal_size(w, obs, st); ++k) st->geo[k] += d[k];
     } else {
         for (int64_t c = 0; c < st->n_cells; ++c) st->c[c] += d[c];
     }
@@ -962,10 +984,10 @@ static void calibration_solve(const orc_world_t* w, const orc_obs_t* obs, const 
 }
 
 void orc_calibration_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st, double* d_out) {
-    const int64_t nc = cal_size(w, st);
+    const int64_t nc = cal_size(w, obs, st);
     double* d = (double*)calloc((size_t)nc, sizeof(double));
     calibration_solve(w, obs, st, d);
-    apply_calibration(w, st, d);
+    apply_calibration(w, obs, st, d);
     if (d_out) memcpy(d_out, d, sizeof(double) * (size_t)nc);
     free(d);
 }
@@ -978,11 +1000,11 @@ void orc_iterate_sac(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st
     orc_source_update(w, obs, st, NULL, NULL, NULL, var);
     orc_excess_attitude_noise(w, obs, st);
     double* da = (double*)calloc((size_t)(4 * st->n_att), sizeof(double));
-    double* dc = (double*)calloc((size_t)cal_size(w, st), sizeof(double));
+    double* dc = (double*)calloc((size_t)cal_size(w, obs, st), sizeof(double));
     attitude_solve(w, obs, st, da);
     calibration_solve(w, obs, st, dc);
     for (int64_t k = 0; k < 4 * st->n_att; ++k) st->a[k] += da[k];
-    apply_calibration(w, st, dc);
+    apply_calibration(w, obs, st, dc);
     free(da);
     free(dc);
 }

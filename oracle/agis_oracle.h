@@ -42,6 +42,8 @@ typedef struct {
     int32_t geo_ccds;         /* 0: one calibration offset per cell; n > 0: the large-scale AL
                                  geometric calibration of eq:etazeta, three shifted-Legendre
                                  coefficients per cell and CCD (n CCDs) in the AC pixel coordinate */
+    int32_t geo_ac_cells;     /* with the AC term (obs ac_cell): its cells, each a field of view
+                                 and a long interval k of eq:etazeta */
 } orc_world_t;
 
 typedef struct {
@@ -57,6 +59,10 @@ typedef struct {
                                  sigma_eff of the hybrid scheme (orc_frozen_sigma) [rad] */
     const int8_t* ccd;        /* geometric calibration: CCD index of the record (else NULL) */
     const float* mu;          /* geometric calibration: AC pixel coordinate, 13.5 .. 1979.5 */
+    const int32_t* ac_cell;   /* NULL, or with the geometric calibration the AC calibration cell
+                                 (0 .. geo_ac_cells - 1) of each across-scan record (-1 for
+                                 along-scan ones): the large-scale AC term of eq:etazeta with
+                                 eq:cc3 */
 } orc_obs_t;
 
 typedef struct {
@@ -70,7 +76,8 @@ typedef struct {
     double* src_eps2;         /* [n_src] excess source variance eps_i^2 of the last S update (robust 2; may be NULL) */
     double* src_D;            /* [n_src] its significance D of eq:D (robust 2; may be NULL) */
     double* geo;              /* [n_cells][geo_ccds][3] geometric calibration coefficients
-                                 (eq:etazeta, r = 0, 1, 2) [rad]; NULL when geo_ccds = 0 */
+                                 (eq:etazeta, r = 0, 1, 2) [rad], followed with ac_cell by the
+                                 AC ones [geo_ac_cells][geo_ccds][3]; NULL when geo_ccds = 0 */
 } orc_state_t;
 
 /* --- Appendix A: quaternions -------------------------------------------- */
@@ -141,7 +148,8 @@ int64_t orc_attitude_segment(const orc_world_t* w, const orc_obs_t* obs, const o
 int64_t orc_num_segments(const orc_world_t* w);
 /* C block; d[n_cells] receives the applied update (may be NULL). */
 /* d (may be NULL) receives the update: [n_cells], or with the geometric
- * calibration [n_cells][geo_ccds][3]. */
+ * calibration [n_cells][geo_ccds][3] (followed by the AC groups' with
+ * ac_cell). */
 void orc_calibration_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st, double* d);
 /* S[AC]: S, then A and C from the same post-S residuals. */
 void orc_iterate_sac(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st, double* var);

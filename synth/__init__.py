@@ -120,6 +120,14 @@ class WorldSpec:
     # over the fields of view and CCDs of each day
     geo_cal: bool = False
     geo_sd: tuple = (1.0 * MAS, 0.3 * MAS, 0.1 * MAS)
+    # with geo_cal and ac_obs: the large-scale AC calibration too (three
+    # coefficients per AC cell and CCD for the across-scan records, an AC
+    # cell being a field of view and a 'long' interval of geo_ac_days days,
+    # whose constant terms sum to zero over the cell's CCDs, eq:cc3); each
+    # transit's AC record is then taken on one of its CCD lines, drawn
+    # uniformly, at that line's time
+    geo_ac: bool = False
+    geo_ac_days: int = 30
 
 
 @dataclass
@@ -147,6 +155,11 @@ class World:
     mu: np.ndarray | None = None
     geo_true: np.ndarray | None = None
     geo_start: np.ndarray | None = None
+    # geo_ac worlds: each record's AC calibration cell (-1 for along-scan
+    # records), and the AC coefficients [n_ac_cells][n_ccd][3]
+    ac_cell: np.ndarray | None = None
+    geo_ac_true: np.ndarray | None = None
+    geo_ac_start: np.ndarray | None = None
 
     @property
     def n_obs(self) -> int:
@@ -360,7 +373,7 @@ def make_world(spec: WorldSpec, law: dict | None = None, progress=None) -> World
     eta_nom = np.tile(eta0, tt.shape[0])
     keep = (t_obs >= t_beg) & (t_obs <= t_end)
     t_obs, fov, src_idx, eta_nom = t_obs[keep], fov[keep], src_idx[keep], eta_nom[keep]
-    ccd = mu = mu_tr = None
+    ccd = mu = mu_tr = ac_cell = None
     if spec.geo_cal:
         # CCD index in the order the image crosses the lines; one across-scan
         # pixel coordinate per transit, drawn uniformly over the 1966 pixel
@@ -389,7 +402,10 @@ def make_world(spec: WorldSpec, law: dict | None = None, progress=None) -> World
         # per transit at the time of its first CCD line, AC uncertainty in
         # the ratio of the paper's bright-star figures (520 / 92 uas), noise
         # from a stream of its own
-        t_ac = tt - eta0[0] / law["wspin"]
+        ccd_tr = np.zeros(tt.shape[0], np.int64)
+        if spec.geo_cal and spec.geo_ac:
+            ccd_tr = np.random.default_rng([spec.seed_truth, 9]).integers(0, nc, tt.shape[0])
+        t_ac = tt - eta0[ccd_tr] / law["wspin"]
         src_tr = np.repeat(np.arange(n, dtype=np.int32), ntr)
         k_ac = (t_ac >= t_beg) & (t_ac <= t_end)
         t_ac, f_ac, s_ac = t_ac[k_ac], ff[k_ac], src_tr[k_ac]
@@ -403,13 +419,20 @@ def make_world(spec: WorldSpec, law: dict | None = None, progress=None) -> World
         t_obs = np.concatenate([t_obs, t_ac])
         fov = np.concatenate([fov, f_ac])
         src_idx = np.concatenate([src_idx, s_ac])
-        eta_nom = np.concatenate([eta_nom, np.full(t_ac.shape[0], eta0[0])])
+        eta_nom = np.concatenate([eta_nom, eta0[ccd_tr[k_ac]]])
+        n_al = cell.shape[0]
         cell = np.concatenate([cell, np.full(t_ac.shape[0], -1, np.int32)])
         sigma = np.concatenate([sigma, sg_ac])
         eps = np.concatenate([eps, e_ac])
         if spec.geo_cal:
-            ccd = np.concatenate([ccd, np.zeros(t_ac.shape[0], np.int8)])
+            ccd = np.concatenate([ccd, ccd_tr[k_ac].astype(np.int8)])
             mu = np.concatenate([mu, mu_tr[k_ac]])
+        if spec.geo_cal and spec.geo_ac:
+            # the AC record's calibration cell: its long interval and field
+            # of view
+            day_ac = np.minimum(np.floor((t_ac - t_beg) / DAY).astype(np.int64), n_days - 1)
+            ac_cell = np.full(t_obs.shape[0], -1, np.int32)
+            ac_cell[n_al:] = (2 * (day_ac // spec.geo_ac_days) + (f_ac == -1)).astype(np.int32)
 
     rng_s = np.random.default_rng(spec.seed_start)
     so = spec.start_offset
@@ -437,6 +460,16 @@ def make_world(spec: WorldSpec, law: dict | None = None, progress=None) -> World
         for g in (geo_true, geo_start):
             day_mean = g[:, :, 0].reshape(n_days, 2 * nc).mean(axis=1)
             g[:, :, 0] -= np.repeat(day_mean, 2)[:, None]
+    geo_ac_true = geo_ac_start = None
+    n_ac_cells = 0
+    if spec.geo_cal and spec.geo_ac and spec.ac_obs:
+        n_ac_cells = 2 * ((n_days + spec.geo_ac_days - 1) // spec.geo_ac_days)
+        rng_g = np.random.default_rng([spec.seed_truth, 10])
+        geo_ac_true = rng_g.normal(0.0, 1.0, (n_ac_cells, nc, 3)) * np.asarray(spec.geo_sd)[None, None, :]
+        geo_ac_start = geo_ac_true + np.random.default_rng([spec.seed_start, 10]).normal(0.0, 0.5 * so,
+                                                                                         (n_ac_cells, nc, 3))
+        for g in (geo_ac_true, geo_ac_start):
+            g[:, :, 0] -= g[:, :, 0].mean(axis=1)[:, None]          # eq:cc3 per cell
 
     consts = dict(
         gamma_c=law["gamma"], t_ep=0.0, t_fr=0.0, lambda_reg=spec.lambda_reg,
@@ -444,7 +477,7 @@ def make_world(spec: WorldSpec, law: dict | None = None, progress=None) -> World
         eph_radius_au=1.01, eph_L0=law["L0"], eph_Lrate=law["Lrate"], eps_obl=law["eps_obl"],
         au_m=AU_M, c_mps=C_MPS, year_s=YEAR, t_beg=t_beg, t_end=t_end, law=law,
         robust=int(spec.robust), eps_bucket=spec.eps_bucket, eps_a_init=spec.eps_a_init,
-        geo_ccds=nc if spec.geo_cal else 0)
+        geo_ccds=nc if spec.geo_cal else 0, geo_ac_cells=int(n_ac_cells))
     return World(spec=spec, consts=consts, knots=knots, src_true=src_true, att_true=att_true,
                  cal_true=cal_true, src_start=src_start, att_start=att_start, cal_start=cal_start,
                  t=np.ascontiguousarray(t_obs), src=np.ascontiguousarray(src_idx),
@@ -452,4 +485,6 @@ def make_world(spec: WorldSpec, law: dict | None = None, progress=None) -> World
                  sigma=np.ascontiguousarray(sigma), eps=np.ascontiguousarray(eps),
                  eta_nominal=np.ascontiguousarray(eta_nom),
                  ccd=None if ccd is None else np.ascontiguousarray(ccd),
-                 mu=None if mu is None else np.ascontiguousarray(mu), geo_true=geo_true, geo_start=geo_start)
+                 mu=None if mu is None else np.ascontiguousarray(mu), geo_true=geo_true, geo_start=geo_start,
+                 ac_cell=None if ac_cell is None else np.ascontiguousarray(ac_cell), geo_ac_true=geo_ac_true,
+                 geo_ac_start=geo_ac_start)

@@ -17,6 +17,13 @@ in place of one offset per cell; one pixel coordinate per transit.
   and CCD the weighted least-squares fit of -R on (L*_0, L*_1, L*_2) over
   its records (numpy.linalg.lstsq), then eq:calCon for eq:cc1, i.e. each
   day's mean constant term removed; the constraint then holds.
+* The across-scan term (the AC half of eq:etazeta, constraint eq:cc3), on
+  the nine-CCD world with one AC record per transit on a CCD line drawn per
+  transit: a unit AC coefficient moves exactly its group's AC residuals, by
+  L*_r(x); the AC residuals vanish at the truth; one update from zero
+  coefficients recovers both terms' truth; with noise the AC part of the
+  update is the per-group weighted least squares followed by each cell's
+  mean AC constant term removed (eq:calCon for eq:cc3), which then holds.
 * The simple iteration S[AC] recovers the coefficients on a noise-free world
   (the tiny workload with one across-scan record per transit and the
   geometric model on its single CCD line; the sparse nine-CCD parity world
@@ -135,3 +142,92 @@ def test_iterations_recover_the_calibration(oracle_lib):
     errs = np.array(errs)
     print("geometric calibration RMS error (r = 0, 1, 2) every 4 iterations [uas]:\n", np.round(errs[::4], 2))
     assert np.all(errs[-1] < 0.05 * errs[0])
+
+
+@pytest.fixture(scope="module")
+def geo_ac_world(oracle_lib):
+    w = C.make("small9", geo_cal=True, ac_obs=True, geo_ac=True, noise=False)
+    return w, oracle_lib.observed_field_angles(w)
+
+
+def test_ac_term_moves_its_group_only(oracle_lib, geo_ac_world):
+    """Against the definition: a unit coefficient r of one AC group adds
+    L*_r(x) to the residuals of that group's AC records and nothing to any
+    other record."""
+    w, eta = geo_ac_world
+    base = oracle_lib.problem_from_world(w, eta, state="truth")
+    R0 = np.asarray(base.observe()["R"])
+    n_al = w.geo_true.size
+    ac = np.flatnonzero(w.cell < 0)
+    l = ac[len(ac) // 2]
+    gi = int(w.ac_cell[l]) * int(w.consts["geo_ccds"]) + int(w.ccd[l])
+    members = (w.cell < 0) & (w.ac_cell.astype(np.int64) * int(w.consts["geo_ccds"]) + w.ccd == gi)
+    assert members.sum() > 3
+    for r in range(3):
+        pr = oracle_lib.problem_from_world(w, eta, state="truth")
+        geo = pr.geo.copy()
+        geo[n_al + 3 * gi + r] += 1.0
+        pr.set_state(geo=geo)
+        dR = np.asarray(pr.observe()["R"]) - R0
+        np.testing.assert_allclose(dR[members], _legendre(r, _x(w)[members]), rtol=0, atol=1e-12)
+        assert np.all(dR[~members] == 0.0)
+
+
+def test_ac_residuals_vanish_and_update_recovers_both_terms(oracle_lib, geo_ac_world):
+    w, eta = geo_ac_world
+    pr = oracle_lib.problem_from_world(w, eta, state="truth")
+    R = np.asarray(pr.observe()["R"])
+    assert np.abs(R).max() < 1e-15
+    pr.set_state(geo=np.zeros_like(pr.geo))
+    pr.calibration_update()
+    d_al = (pr.geo[:w.geo_true.size].reshape(w.geo_true.shape) - w.geo_true) / UAS
+    d_ac = (pr.geo[w.geo_true.size:].reshape(w.geo_ac_true.shape) - w.geo_ac_true) / UAS
+    print(f"recovered AL / AC terms: max error {np.abs(d_al).max():.2e} / {np.abs(d_ac).max():.2e} uas")
+    assert np.abs(d_al).max() < 1e-6 and np.abs(d_ac).max() < 1e-6
+
+
+def test_ac_update_is_the_weighted_lstsq_with_cc3(oracle_lib):
+    w = C.make("small9", geo_cal=True, ac_obs=True, geo_ac=True)
+    eta = oracle_lib.observed_field_angles(w)
+    pr = oracle_lib.problem_from_world(w, eta, state="start")
+    R, x = np.asarray(pr.observe()["R"]), _x(w)
+    W = 1.0 / w.sigma.astype(np.float64) ** 2
+    n_ccd = int(w.consts["geo_ccds"])
+    ac = w.cell < 0
+    g = np.where(ac, w.ac_cell.astype(np.int64) * n_ccd + w.ccd, -1)
+    ref = np.zeros((int(w.consts["geo_ac_cells"]) * n_ccd, 3))
+    for gi in np.unique(g[ac]):
+        sel = g == gi
+        A = np.stack([_legendre(r, x[sel]) for r in range(3)], axis=1) * np.sqrt(W[sel])[:, None]
+        ref[gi] = np.linalg.lstsq(A, -R[sel] * np.sqrt(W[sel]), rcond=None)[0]
+    c0 = ref[:, 0].reshape(-1, n_ccd)
+    ref[:, 0] = (c0 - c0.mean(axis=1, keepdims=True)).reshape(-1)
+    d = pr.calibration_update()[w.geo_true.size:].reshape(-1, 3)
+    scale = np.abs(ref).max()
+    print(f"AC update vs weighted lstsq + eq:cc3: max |diff| {np.abs(d - ref).max() / UAS:.2e} uas "
+          f"(update up to {scale / UAS:.0f} uas)")
+    np.testing.assert_allclose(d, ref, rtol=0, atol=1e-9 * scale)
+    geo_ac = pr.geo[w.geo_true.size:].reshape(-1, 3)[:, 0].reshape(-1, n_ccd)
+    assert np.abs(geo_ac.sum(axis=1)).max() < 1e-12 * np.abs(geo_ac).max()
+
+
+def test_iterations_recover_both_terms(oracle_lib):
+    """The tiny world (one CCD line, so eq:cc3 holds every AC constant term at
+    zero) with AC records and both terms: noise-free iterations from start
+    values ~25 mas off bring every term of both below 5% of its start error."""
+    w = C.make("tiny", geo_cal=True, ac_obs=True, geo_ac=True, noise=False)
+    eta = oracle_lib.observed_field_angles(w)
+    pr = oracle_lib.problem_from_world(w, eta, state="start")
+    n_al = w.geo_true.size
+
+    def err():
+        e_al = (pr.geo[:n_al].reshape(w.geo_true.shape) - w.geo_true) / UAS
+        e_ac = (pr.geo[n_al:].reshape(w.geo_ac_true.shape) - w.geo_ac_true) / UAS
+        return np.array([np.sqrt(np.mean(e * e, axis=(0, 1))) for e in (e_al, e_ac)])    # [AL / AC][r]
+    e0 = err()
+    for _ in range(20):
+        pr.iterate(s_ref=w.src_true)
+    e1 = err()
+    print("RMS error [uas], AL and AC terms (r = 0, 1, 2): start\n", np.round(e0, 2), "\nafter 20\n", np.round(e1, 3))
+    live = e0 > 0
+    assert np.all(e1[live] < 0.05 * e0[live]) and np.all(e1[~live] < 1e-9)
