@@ -105,6 +105,14 @@ def workload_description(name, w):
             "law": "Gaia-like: spin 60 arcsec/s, precession 63 d, aspect 45 deg, basic angle 106.5 deg"}
 
 
+def geo_coefficients(w, which):
+    """The world's geometric coefficients, AL then AC (the layout
+    agis_set_geo_calibration takes)."""
+    g = getattr(w, f"geo_{which}")
+    ga = getattr(w, f"geo_ac_{which}", None)
+    return np.reshape(g, -1) if ga is None else np.concatenate([np.reshape(g, -1), np.reshape(ga, -1)])
+
+
 def host_description():
     model, ram = None, None
     try:
@@ -210,8 +218,8 @@ def main():
     ap.add_argument("--ac", action="store_true",
                     help="add one across-scan observation per transit (cell -1) to the workload")
     ap.add_argument("--geo", action="store_true",
-                    help="the large-scale along-scan geometric calibration (3 coefficients per cell and CCD) in "
-                         "place of one offset per cell; no CPU baseline")
+                    help="the large-scale geometric calibration (3 coefficients per cell and CCD) in place of one "
+                         "offset per cell; with --ac the across-scan term too; no CPU baseline")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the timed steps, run one plain device copy of this many MiB (the reference "
                          "kernel for scaling HBM counters) and exit")
@@ -235,6 +243,7 @@ def main():
         over["ac_obs"] = True
     if args.geo:
         over["geo_cal"] = True
+        over["geo_ac"] = args.ac            # with across-scan records: the AC term too
         args.no_cpu_baseline = True
     wname = args.workload + ("+ac" if args.ac else "") + ("+geo" if args.geo else "")
     t0 = time.time()
@@ -252,8 +261,9 @@ def main():
     agis.agis_set_attitude(ctx, w.att_true)
     agis.agis_set_calibration(ctx, w.cal_true)
     if args.geo:
-        agis.agis_load_geometry(ctx, w.ccd, w.mu, int(w.consts["geo_ccds"]))
-        agis.agis_set_geo_calibration(ctx, w.geo_true)
+        agis.agis_load_geometry(ctx, w.ccd, w.mu, int(w.consts["geo_ccds"]), w.ac_cell,
+                                int(w.consts.get("geo_ac_cells", 0)) if w.ac_cell is not None else 0)
+        agis.agis_set_geo_calibration(ctx, geo_coefficients(w, "true"))
     R = agis.agis_residuals(ctx)                   # = c_true - eta_true (plus the true geometric terms)
     eta_obs = -R + w.eps
     del R, zeros
@@ -265,8 +275,9 @@ def main():
     agis.agis_set_attitude(ctx, w.att_start)
     agis.agis_set_calibration(ctx, w.cal_start)
     if args.geo:
-        agis.agis_load_geometry(ctx, w.ccd, w.mu, int(w.consts["geo_ccds"]))
-        agis.agis_set_geo_calibration(ctx, w.geo_start)
+        agis.agis_load_geometry(ctx, w.ccd, w.mu, int(w.consts["geo_ccds"]), w.ac_cell,
+                                int(w.consts.get("geo_ac_cells", 0)) if w.ac_cell is not None else 0)
+        agis.agis_set_geo_calibration(ctx, geo_coefficients(w, "start"))
     agis.agis_set_frame_reference(ctx, w.src_true)
     sz = agis.agis_problem_size(ctx)
     log(f"store built: {sz}")

@@ -204,31 +204,40 @@ int agis_set_calibration(agis_ctx_t* ctx, int64_t n, const double* c, int where)
 int agis_get_calibration(agis_ctx_t* ctx, int64_t n, double* c, int where);
 
 /*
- * Large-scale along-scan geometric calibration (Sect. 3.4, eq:etazeta, its
- * AL large-scale terms with one gate): per calibration cell (day and field
- * of view) and CCD, three coefficients c_r of the shifted Legendre
- * polynomials L*_0..2 (orthogonal on [0, 1]) in x = (mu - 13.5) / 1966, mu
- * the record's across-scan pixel coordinate; an along-scan record's model
- * value is eta_obs + sum_r c_r L*_r(x) in place of eta_obs + c_cell.  The C
- * block then solves each (cell, CCD) group's 3x3 normal equations
- * (eq:normC with eq:pdC) by the modified Cholesky and applies eq:calCon for
- * eq:cc1: the constant terms of a day's two cells and all CCDs sum to zero.
+ * Large-scale geometric calibration (Sect. 3.4, eq:etazeta, its large-scale
+ * terms with one gate): per calibration cell (day and field of view) and
+ * CCD, three coefficients c_r of the shifted Legendre polynomials L*_0..2
+ * (orthogonal on [0, 1]) in x = (mu - 13.5) / 1966, mu the record's
+ * across-scan pixel coordinate; an along-scan record's model value is
+ * eta_obs + sum_r c_r L*_r(x) in place of eta_obs + c_cell.  Optionally the
+ * across-scan term too: per AC cell (a field of view and a long interval,
+ * numbered by the caller) and CCD three coefficients, an across-scan
+ * record's residual then being zeta_obs + sum_r c_r L*_r(x) - zeta.  The C
+ * block solves each group's 3x3 normal equations (eq:normC with eq:pdC) by
+ * the modified Cholesky and applies eq:calCon for eq:cc1 (the AL constant
+ * terms of a day's two cells and all CCDs sum to zero) and eq:cc3 (the AC
+ * constant terms of an AC cell's CCDs sum to zero).
  *
  * agis_load_geometry enables it after agis_load_observations: ccd [n] the
  * CCD index in [0, n_ccd) and mu [n] the pixel coordinate in [13.5, 1979.5]
  * of every record, in the input order of the observations (n = the loaded
- * count; across-scan records' values are ignored), host or device memory by
- * `where`; the coefficients start at zero and the cell offsets are held at
- * zero.  agis_set/get_geo_calibration: n = 3 n_cells n_ccd coefficients,
- * [n_cells][n_ccd][3] [rad].  AGIS_E_SHAPE on a count mismatch,
- * AGIS_E_INVALID_ARG on an index or coordinate out of range, AGIS_E_STATE for
- * the geometry in robust mode 2, for agis_set_calibration while it is on, and
- * for conjugate gradients and the recorded-update schemes (agis_learned_*,
- * agis_asi_step), which carry the cell offsets only.  Loading observations
- * again turns it off; so does a rejected agis_load_geometry (the context
- * then uses the cell offsets, which are zero if the model had been on).
+ * count); ac_cell [n] (NULL, or with n_ac_cells > 0) each across-scan
+ * record's AC cell in [0, n_ac_cells) (along-scan records' values are
+ * ignored, and so are across-scan records' ccd and mu without ac_cell);
+ * host or device memory by `where`; the coefficients start at zero and the
+ * cell offsets are held at zero.  agis_set/get_geo_calibration: n = 3
+ * (n_cells + n_ac_cells) n_ccd coefficients, [n_cells][n_ccd][3] AL then
+ * [n_ac_cells][n_ccd][3] AC [rad].  AGIS_E_SHAPE on a count mismatch,
+ * AGIS_E_INVALID_ARG on an index, cell or coordinate out of range,
+ * AGIS_E_STATE for the geometry in robust mode 2, for agis_set_calibration
+ * while it is on, and for conjugate gradients and the recorded-update
+ * schemes (agis_learned_*, agis_asi_step), which carry the cell offsets
+ * only.  Loading observations again turns it off; so does a rejected
+ * agis_load_geometry (the context then uses the cell offsets, which are
+ * zero if the model had been on).
  */
-int agis_load_geometry(agis_ctx_t* ctx, int64_t n, const int8_t* ccd, const float* mu, int32_t n_ccd, int where);
+int agis_load_geometry(agis_ctx_t* ctx, int64_t n, const int8_t* ccd, const float* mu, int32_t n_ccd,
+                       const int32_t* ac_cell, int32_t n_ac_cells, int where);
 int agis_set_geo_calibration(agis_ctx_t* ctx, int64_t n, const double* c, int where);
 int agis_get_geo_calibration(agis_ctx_t* ctx, int64_t n, double* c, int where);
 

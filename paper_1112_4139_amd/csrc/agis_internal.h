@@ -108,7 +108,8 @@ struct agis_ctx {
     // shifted-Legendre coefficients per cell and CCD in place of the cell
     // offsets (held at zero); 0 CCDs: the cell offsets
     int32_t geo_ccds = 0;
-    int64_t n_groups = 0;                // n_cells * geo_ccds
+    int32_t geo_ac_cells = 0;            // AC cells of the across-scan term (0: none)
+    int64_t n_groups = 0;                // (n_cells + geo_ac_cells) * geo_ccds: AL groups, then AC
     double* geo = nullptr;               // [n_groups][3]
     double* dgeo = nullptr;              // [n_groups][3] the last update
     double* geo_sums = nullptr;          // [n_groups][9] normal equations of the last C update
@@ -277,7 +278,8 @@ void launch_ac_pass(agis_ctx* ctx);
 void launch_band_solve(agis_ctx* ctx);
 void launch_calib_solve(agis_ctx* ctx, double* rc = nullptr);   // rc: optional right-hand sides
 // geo.hip
-int load_geometry(agis_ctx* ctx, const int8_t* ccd, const float* mu, int32_t n_ccd, int where);
+int load_geometry(agis_ctx* ctx, const int8_t* ccd, const float* mu, int32_t n_ccd, const int32_t* ac_cell,
+                  int32_t n_ac_cells, int where);
 void launch_geo_eta(agis_ctx* ctx);
 void launch_geo_solve(agis_ctx* ctx);
 void launch_apply_attitude(agis_ctx* ctx);

@@ -120,6 +120,7 @@ static void free_store(agis_ctx* ctx) {
     dfree(ctx->geo_off);
     dfree(ctx->geo_mu_g);
     ctx->geo_ccds = 0;
+    ctx->geo_ac_cells = 0;
     ctx->n_groups = 0;
     dfree(ctx->iv_off);
     dfree(ctx->iv_cell);
@@ -602,15 +603,17 @@ extern "C" int agis_set_calibration(agis_ctx_t* ctx, int64_t n, const double* c,
 }
 
 extern "C" int agis_load_geometry(agis_ctx_t* ctx, int64_t n, const int8_t* ccd, const float* mu, int32_t n_ccd,
-                                  int where) {
+                                  const int32_t* ac_cell, int32_t n_ac_cells, int where) {
     CHECK_CTX();
     ++ctx->xver;
     REQUIRE_LOADED();
     if (where != AGIS_HOST && where != AGIS_DEVICE) return set_error(ctx, AGIS_E_INVALID_ARG, "bad 'where'");
     if (n != ctx->n_obs || ((!ccd || !mu) && n > 0)) return set_error(ctx, AGIS_E_SHAPE, "record count mismatch");
     if (n_ccd < 1 || n_ccd > 127) return set_error(ctx, AGIS_E_INVALID_ARG, "n_ccd outside [1, 127]");
+    if (n_ac_cells < 0 || (n_ac_cells > 0 && !ac_cell && n > 0))
+        return set_error(ctx, AGIS_E_INVALID_ARG, "n_ac_cells < 0, or AC cells counted but not given");
     if (ctx->cfg.robust == 2) return set_error(ctx, AGIS_E_STATE, "the geometric calibration with robust mode 2");
-    const int rc = load_geometry(ctx, ccd, mu, n_ccd, where);
+    const int rc = load_geometry(ctx, ccd, mu, n_ccd, ac_cell, n_ac_cells, where);
     ++ctx->gen;                          // the captured iteration gains the geometric kernels
     return rc;
 }

@@ -1,23 +1,26 @@
-// Large-scale along-scan geometric calibration (Sect. 3.4, eq:etazeta, the
-// AL large-scale terms): per calibration cell (day and field of view) and
-// CCD three coefficients of the shifted Legendre polynomials L*_0..2 in the
+// Large-scale geometric calibration (Sect. 3.4, eq:etazeta, the large-scale
+// terms): per calibration cell (day and field of view) and CCD three
+// coefficients of the shifted Legendre polynomials L*_0..2 in the
 // across-scan pixel coordinate mu, x = (mu - 13.5) / 1966, in place of one
-// offset per cell.
+// offset per cell; optionally the across-scan term, three coefficients per
+// AC cell (field of view and long interval) and CCD.
 //
-// The term enters the residual additively (eq:resAL): R = eta_obs +
-// sum_r c_r L*_r(x) - eta.  The stored observed angles of both orders
-// therefore carry it -- eta = eta_obs + term, refreshed whenever the
-// coefficients change -- and every pass reads them unchanged, with the
-// per-cell offsets held at zero.  The C block (Sect. 5.3, eq:normC with
+// The term enters the residual additively (eq:resAL, eq:resAC): R = eta_obs
+// + sum_r c_r L*_r(x) - eta (zeta across scan).  The stored observed angles
+// of both orders therefore carry it -- eta = eta_obs + term, refreshed
+// whenever the coefficients change -- and every pass reads them unchanged,
+// with the per-cell offsets held at zero.  The C block (Sect. 5.3, eq:normC with
 // eq:pdC: dR/dc_r = L*_r(x)) is block-diagonal in groups of three
-// coefficients (a cell and a CCD).  The along-scan records are given a
+// coefficients (a cell and a CCD).  The records with a group are given a
 // second order at load, by group and time within a group (a stable radix
 // sort of the group indices); the A/C pass writes each record's W and W R
 // at its place in that order, so that one block per group sums W L_r L_s and
-// W R L_r over a contiguous range in a fixed order; one thread per day then
-// solves the day's 3x3 systems (the small modified Cholesky) and applies
-// eq:calCon for the constraint eq:cc1 (the constant terms of a day's two
-// cells and all CCDs sum to zero): their mean is removed.
+// W R L_r over a contiguous range in a fixed order; one thread per
+// constraint set then solves the set's 3x3 systems (the small modified
+// Cholesky) and applies eq:calCon for its constraint, eq:cc1 (the AL
+// constant terms of a day's two cells and all CCDs sum to zero) or eq:cc3
+// (the AC constant terms of an AC cell's CCDs sum to zero): their mean is
+// removed.
 #include <hipcub/hipcub.hpp>
 
 #include "agis_internal.h"
@@ -51,22 +54,32 @@ __device__ __forceinline__ double shifted_legendre(int r, double x) {
 __device__ __forceinline__ double geo_x(float mu) { return ((double)mu - 13.5) / 1966.0; }
 
 // Group index and pixel coordinate of every record in time order from the
-// input columns (t_perm: time index -> input index); across-scan records
-// get group -1.  Flags: 1 a CCD index out of range, 2 a coordinate not in
-// [13.5, 1979.5].
+// input columns (t_perm: time index -> input index): an along-scan record's
+// cell and CCD; with ac_cell an across-scan record's AC cell and CCD after
+// the n_cells n_ccd AL groups; -1 for an across-scan record without it.
+// Flags: 1 a CCD index out of range, 2 a coordinate not in [13.5, 1979.5],
+// 4 an AC cell out of range.
 __global__ void k_geo_index(int64_t n, const int32_t* __restrict__ t_perm, const int32_t* __restrict__ t_cellfov,
                             int32_t n_cells, const int8_t* __restrict__ ccd_in, const float* __restrict__ mu_in,
-                            int32_t n_ccd, int32_t* __restrict__ g_out, float* __restrict__ mu_out,
-                            int* __restrict__ flags) {
+                            const int32_t* __restrict__ ac_cell_in, int32_t n_ac_cells, int32_t n_ccd,
+                            int32_t* __restrict__ g_out, float* __restrict__ mu_out, int* __restrict__ flags) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t j = t_perm[i];
         const int32_t cell = t_cellfov[i] >> 1;
         const float mu = mu_in[j];
         int32_t g = -1;
+        int32_t base = -1;                       // the record's cell among the groups' cells
         if (cell < n_cells) {
+            base = cell;
+        } else if (ac_cell_in) {
+            const int32_t ac = ac_cell_in[j];
+            if (ac < 0 || ac >= n_ac_cells) atomicOr(flags, 4);
+            else base = n_cells + ac;
+        }
+        if (base >= 0 || (cell >= n_cells && ac_cell_in)) {
             const int c = ccd_in[j];
             if (c < 0 || c >= n_ccd) atomicOr(flags, 1);
-            else g = cell * n_ccd + c;
+            else if (base >= 0) g = base * n_ccd + c;
             if (!(mu >= 13.5f && mu <= 1979.5f)) atomicOr(flags, 2);
         }
         g_out[i] = g;
@@ -99,7 +112,7 @@ __global__ void k_geo_eta(int64_t n, const double* __restrict__ eta0, const int3
     }
 }
 
-// Sort keys of the group order: the group, or n_groups across scan (last).
+// Sort keys of the group order: the group, or n_groups without one (last).
 __global__ void k_geo_keys(int64_t n, const int32_t* __restrict__ g, int32_t n_groups, uint32_t* __restrict__ key,
                            int32_t* __restrict__ idx) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -109,15 +122,16 @@ __global__ void k_geo_keys(int64_t n, const int32_t* __restrict__ g, int32_t n_g
 }
 
 // From the sorted keys and time indices: each time-order record's place in
-// the group order (-1 across scan) and the group order's coordinates.
+// the group order (-1 for a record without a group) and the group order's
+// coordinates.
 __global__ void k_geo_order(int64_t n, const uint32_t* __restrict__ key, const int32_t* __restrict__ idx,
                             uint32_t n_groups, const float* __restrict__ t_mu, int32_t* __restrict__ pos,
                             float* __restrict__ mu_g) {
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
         const int32_t i = idx[k];
-        const bool al = key[k] < n_groups;
-        pos[i] = al ? (int32_t)k : -1;
-        if (al) mu_g[k] = t_mu[i];
+        const bool in = key[k] < n_groups;
+        pos[i] = in ? (int32_t)k : -1;
+        if (in) mu_g[k] = t_mu[i];
     }
 }
 
@@ -180,13 +194,15 @@ __global__ __launch_bounds__(GEO_NT) void k_geo_sums(int64_t n_groups, const int
     }
 }
 
-// One thread per day: the 3x3 solves of the day's 2 n_ccd groups, then
-// eq:calCon for eq:cc1 (the mean constant term of the day removed).
-__global__ void k_geo_solve(int64_t n_days, int32_t n_ccd, const double* __restrict__ sums,
+// One thread per constraint set of per_set consecutive groups from group
+// first: their 3x3 solves, then eq:calCon for its constraint (the set's
+// mean constant term removed).  AL: a day's 2 n_ccd groups (eq:cc1); AC: an
+// AC cell's n_ccd groups (eq:cc3).
+__global__ void k_geo_solve(int64_t n_sets, int64_t first, int32_t per_set, const double* __restrict__ sums,
                             double* __restrict__ dgeo) {
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n_days;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n_sets;
          j += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t g0 = j * 2 * n_ccd, per_day = 2 * (int64_t)n_ccd;
+        const int64_t g0 = first + j * per_set, per_day = per_set;
         double mean = 0.0;
         for (int64_t k = 0; k < per_day; ++k) {
             const double* s = sums + 9 * (g0 + k);
@@ -236,7 +252,10 @@ void launch_geo_solve(agis_ctx* ctx) {
     k_geo_sums<<<(unsigned)ctx->n_groups, GEO_NT, 0, ctx->stream>>>(ctx->n_groups, ctx->geo_off, ctx->geo_mu_g,
                                                                     ctx->geo_wr, ctx->geo_sums);
     const int64_t n_days = ctx->n_cells / 2;
-    k_geo_solve<<<grid_for(n_days), 256, 0, ctx->stream>>>(n_days, ctx->geo_ccds, ctx->geo_sums, ctx->dgeo);
+    k_geo_solve<<<grid_for(n_days), 256, 0, ctx->stream>>>(n_days, 0, 2 * ctx->geo_ccds, ctx->geo_sums, ctx->dgeo);
+    if (ctx->geo_ac_cells > 0)
+        k_geo_solve<<<grid_for(ctx->geo_ac_cells), 256, 0, ctx->stream>>>(
+            ctx->geo_ac_cells, ctx->n_cells * ctx->geo_ccds, ctx->geo_ccds, ctx->geo_sums, ctx->dgeo);
 }
 
 // The group order of the along-scan records (time order within a group):
@@ -275,34 +294,42 @@ static int build_group_order(agis_ctx* ctx) {
     return done(e == hipSuccess ? AGIS_OK : hip_check(ctx, e, "group order"));
 }
 
-int load_geometry(agis_ctx* ctx, const int8_t* ccd, const float* mu, int32_t n_ccd, int where) {
+int load_geometry(agis_ctx* ctx, const int8_t* ccd, const float* mu, int32_t n_ccd, const int32_t* ac_cell,
+                  int32_t n_ac_cells, int where) {
     const int64_t n = ctx->n_obs;
     hipStream_t st = ctx->stream;
     const int8_t* ccd_d = ccd;
     const float* mu_d = mu;
+    const int32_t* ac_d = n_ac_cells > 0 ? ac_cell : nullptr;
     int8_t* ccd_tmp = nullptr;
     float* mu_tmp = nullptr;
+    int32_t* ac_tmp = nullptr;
     auto release = [&]() {
         if (ccd_tmp) (void)hipFree(ccd_tmp);
         if (mu_tmp) (void)hipFree(mu_tmp);
+        if (ac_tmp) (void)hipFree(ac_tmp);
     };
     if (where == AGIS_HOST && n > 0) {
         int rc = dalloc(ctx, &ccd_tmp, (size_t)n, "geometry ccd");
         if (rc == AGIS_OK) rc = dalloc(ctx, &mu_tmp, (size_t)n, "geometry mu");
+        if (rc == AGIS_OK && ac_d) rc = dalloc(ctx, &ac_tmp, (size_t)n, "geometry AC cells");
         if (rc != AGIS_OK) {
             release();
             return rc;
         }
         hipError_t e = hipMemcpyAsync(ccd_tmp, ccd, n * sizeof(int8_t), hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(mu_tmp, mu, n * sizeof(float), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && ac_d) e = hipMemcpyAsync(ac_tmp, ac_cell, n * sizeof(int32_t), hipMemcpyHostToDevice, st);
         if (e != hipSuccess) {
             release();
             return hip_check(ctx, e, "geometry upload");
         }
         ccd_d = ccd_tmp;
         mu_d = mu_tmp;
+        if (ac_d) ac_d = ac_tmp;
     }
-    const int64_t ng = ctx->n_cells * n_ccd;
+    const int32_t n_ac = ac_d ? n_ac_cells : 0;
+    const int64_t ng = (ctx->n_cells + n_ac) * n_ccd;
     if (ng >= INT32_MAX || n > INT32_MAX) {
         release();
         return set_error(ctx, AGIS_E_INVALID_ARG, "agis_load_geometry: more than 2^31 - 1 records or groups");
@@ -325,7 +352,7 @@ int load_geometry(agis_ctx* ctx, const int8_t* ccd, const float* mu, int32_t n_c
     GALLOC(ctx->geo_mu_g, n, "group order mu");
     GALLOC(ctx->geo_flags, 1, "geometry flags");
 #undef GALLOC
-    if (ctx->geo_ccds != n_ccd || !ctx->geo) {
+    if (ctx->geo_ccds != n_ccd || ctx->geo_ac_cells != n_ac || !ctx->geo) {
         if (ctx->geo) {
             dfree(ctx->geo);
             dfree(ctx->dgeo);
@@ -345,7 +372,7 @@ int load_geometry(agis_ctx* ctx, const int8_t* ccd, const float* mu, int32_t n_c
     if (e != hipSuccess) return fail(hip_check(ctx, e, "geometry clear"));
     if (n > 0) {
         k_geo_index<<<grid_for(n), 256, 0, st>>>(n, ctx->t_perm, ctx->t_cellfov, (int32_t)ctx->n_cells, ccd_d, mu_d,
-                                                  n_ccd, ctx->t_geo_g, ctx->t_geo_mu, ctx->geo_flags);
+                                                  ac_d, n_ac, n_ccd, ctx->t_geo_g, ctx->t_geo_mu, ctx->geo_flags);
         k_geo_gather<int32_t><<<grid_for(n), 256, 0, st>>>(n, ctx->s_from_t, ctx->t_geo_g, ctx->s_geo_g);
         k_geo_gather<float><<<grid_for(n), 256, 0, st>>>(n, ctx->s_from_t, ctx->t_geo_mu, ctx->s_geo_mu);
     }
@@ -364,10 +391,12 @@ int load_geometry(agis_ctx* ctx, const int8_t* ccd, const float* mu, int32_t n_c
             HIPCHK(hipStreamSynchronize(st));
         }
         ctx->geo_ccds = 0;
+        ctx->geo_ac_cells = 0;
         ctx->n_groups = 0;
         std::string m = "agis_load_geometry:";
         if (flags & 1) m += " ccd index outside [0, n_ccd);";
-        if (flags & 2) m += " along-scan pixel coordinate outside [13.5, 1979.5];";
+        if (flags & 2) m += " across-scan pixel coordinate outside [13.5, 1979.5];";
+        if (flags & 4) m += " AC calibration cell outside [0, n_ac_cells);";
         return set_error(ctx, AGIS_E_INVALID_ARG, m);
     }
     // the observed angles as loaded (the first load of the geometry keeps
@@ -377,6 +406,7 @@ int load_geometry(agis_ctx* ctx, const int8_t* ccd, const float* mu, int32_t n_c
         HIPCHK(hipMemcpyAsync(ctx->s_eta0, ctx->s_eta, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     }
     ctx->geo_ccds = n_ccd;
+    ctx->geo_ac_cells = n_ac;
     ctx->n_groups = ng;
     if (n > 0 && (rc = build_group_order(ctx)) != AGIS_OK) {
         // back to the cell offsets and the observed angles as loaded
@@ -384,6 +414,7 @@ int load_geometry(agis_ctx* ctx, const int8_t* ccd, const float* mu, int32_t n_c
         (void)hipMemcpyAsync(ctx->s_eta, ctx->s_eta0, n * sizeof(double), hipMemcpyDeviceToDevice, st);
         (void)hipStreamSynchronize(st);
         ctx->geo_ccds = 0;
+        ctx->geo_ac_cells = 0;
         ctx->n_groups = 0;
         return rc;
     }

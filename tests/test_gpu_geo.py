@@ -1,6 +1,7 @@
-"""Parity of the large-scale along-scan geometric calibration (eq:etazeta,
-Sect. 3.4; the C block of Sect. 5.3 with eq:calCon for eq:cc1) of the HIP
-library with the oracle, through the C ABI.
+"""Parity of the large-scale geometric calibration (eq:etazeta, Sect. 3.4;
+the C block of Sect. 5.3 with eq:calCon for eq:cc1 and, with the across-scan
+term, eq:cc3) of the HIP library with the oracle, through the C ABI, on
+worlds with the along-scan term alone and with both terms.
 
 * Residuals at the start values with the geometric terms (the observed
   angles the library stores carry them): within the residual bound of the
@@ -31,16 +32,18 @@ def _ctx(agis, w, eta, pr):
     """A context holding the oracle problem pr's state, with the geometry."""
     ctx = agis.agis_create(w.consts, w.knots)
     agis.agis_load_observations(ctx, w.t, eta, w.sigma, w.src, w.fov, w.cell, w.src_true.shape[0], w.n_cells)
-    agis.agis_load_geometry(ctx, w.ccd, w.mu, int(w.consts["geo_ccds"]))
+    agis.agis_load_geometry(ctx, w.ccd, w.mu, int(w.consts["geo_ccds"]), w.ac_cell,
+                            int(w.consts.get("geo_ac_cells", 0)) if w.ac_cell is not None else 0)
     agis.agis_set_sources(ctx, pr.s)
     agis.agis_set_attitude(ctx, pr.a)
     agis.agis_set_geo_calibration(ctx, pr.geo)
     return ctx
 
 
-@pytest.fixture(scope="module")
-def small9_geo(oracle_lib):
-    w = C.make("small9", geo_cal=True)
+@pytest.fixture(scope="module", params=["AL term", "AL and AC terms"])
+def small9_geo(oracle_lib, request):
+    both = request.param == "AL and AC terms"
+    w = C.make("small9", geo_cal=True, ac_obs=both, geo_ac=both)
     return w, oracle_lib.observed_field_angles(w)
 
 
@@ -68,14 +71,19 @@ def test_geo_calibration_update_parity(agis_mod, oracle_lib, small9_geo):
     agis_mod.agis_calibration_update(ctx)
     G = agis_mod.agis_get_geo_calibration(ctx, pr.geo.size)
     check_floor("geometric C update", X[2], O[2], G, tol[2], 2)
-    per_day = 2 * int(w.consts["geo_ccds"])
-    c0 = G.reshape(-1, 3)[:, 0].reshape(-1, per_day)
-    assert np.abs(c0.sum(axis=1)).max() < 1e-12 * np.abs(c0).max()
+    n_ccd = int(w.consts["geo_ccds"])
+    n_al = w.geo_true.size // 3
+    c0 = G.reshape(-1, 3)[:n_al, 0].reshape(-1, 2 * n_ccd)
+    assert np.abs(c0.sum(axis=1)).max() < 1e-12 * np.abs(c0).max()              # eq:cc1
+    if w.ac_cell is not None:
+        a0 = G.reshape(-1, 3)[n_al:, 0].reshape(-1, n_ccd)
+        assert np.abs(a0.sum(axis=1)).max() < 1e-12 * np.abs(a0).max()          # eq:cc3
     agis_mod.agis_destroy(ctx)
 
 
-def test_geo_iterations_parity(agis_mod, oracle_lib):
-    w = C.make("tiny", geo_cal=True, ac_obs=True)
+@pytest.mark.parametrize("both", [False, True], ids=["AL term", "AL and AC terms"])
+def test_geo_iterations_parity(agis_mod, oracle_lib, both):
+    w = C.make("tiny", geo_cal=True, ac_obs=True, geo_ac=both)
     eta = oracle_lib.observed_field_angles(w)
     n_it = 2
 
@@ -152,6 +160,11 @@ def test_geo_refusals(agis_mod, oracle_lib, small9_geo):
     mu[np.flatnonzero(w.cell >= 0)[0]] = 2000.0
     with pytest.raises(agis_mod.AgisError):
         agis_mod.agis_load_geometry(ctx, w.ccd, mu, 9)
+    if w.ac_cell is not None:
+        ac = w.ac_cell.copy()
+        ac[np.flatnonzero(w.cell < 0)[0]] = int(w.consts["geo_ac_cells"])
+        with pytest.raises(agis_mod.AgisError):
+            agis_mod.agis_load_geometry(ctx, w.ccd, w.mu, 9, ac, int(w.consts["geo_ac_cells"]))
     # a rejected geometry leaves the cell offsets in use, at zero, and the
     # observed angles as loaded
     assert np.all(agis_mod.agis_get_calibration(ctx, w.n_cells) == 0.0)

@@ -113,7 +113,7 @@ def fp64_floor(oracle_lib, world, eta, run, n_draws=N_DRAWS, ulp_noise=ULP_NOISE
     return X, O, tol
 
 
-OBS_FIELDS = ("t", "src", "fov", "cell", "sigma", "eps", "ccd", "mu")
+OBS_FIELDS = ("t", "src", "fov", "cell", "sigma", "eps", "ccd", "mu", "ac_cell")
 
 
 def reordered(w, perm):
