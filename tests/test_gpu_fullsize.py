@@ -25,7 +25,7 @@ from test_gpu_parity import TOL_UAS, agis_mod, check_floor, fp64_floor  # noqa: 
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
-OBS_FIELDS = ("t", "src", "fov", "cell", "sigma", "eps")
+OBS_FIELDS = ("t", "src", "fov", "cell", "sigma", "eps", "ccd", "mu", "ac_cell")
 
 
 def subworld(w, idx):
@@ -33,7 +33,8 @@ def subworld(w, idx):
     attitude, calibration, knots and constants unchanged."""
     sub = types.SimpleNamespace(**{k: v for k, v in vars(w).items() if k not in OBS_FIELDS})
     for k in OBS_FIELDS:
-        setattr(sub, k, getattr(w, k)[idx])
+        v = getattr(w, k, None)
+        setattr(sub, k, None if v is None else v[idx])
     sub.n_obs, sub.n_att, sub.n_cells = idx.size, w.n_att, w.n_cells
     return sub
 
