@@ -35,7 +35,7 @@ def _structs(c_r):
                     ("lambda_reg", c_r), ("seg_len", c_i32), ("seg_overlap", c_i32), ("eph_radius_au", c_r),
                     ("eph_L0", c_r), ("eph_Lrate", c_r), ("eps_obl", c_r), ("au_m", c_r), ("c_mps", c_r),
                     ("year_s", c_r), ("robust", c_i32), ("eps_bucket", c_i32), ("geo_ccds", c_i32),
-                    ("geo_ac_cells", c_i32)]
+                    ("geo_ac_cells", c_i32), ("defl", c_r), ("ppn", c_i32)]
 
     class Obs(ctypes.Structure):
         _fields_ = [("n", c_i64), ("t", P(c_r)), ("eta_obs", P(c_r)), ("sigma", P(c_f)), ("src", P(c_i32)),
@@ -45,7 +45,7 @@ def _structs(c_r):
     class State(ctypes.Structure):
         _fields_ = [("n_src", c_i64), ("n_att", c_i64), ("n_cells", c_i64), ("s", P(c_r)), ("a", P(c_r)),
                     ("c", P(c_r)), ("n_buckets", c_i64), ("eps_a2", P(c_r)), ("src_eps2", P(c_r)),
-                    ("src_D", P(c_r)), ("geo", P(c_r))]
+                    ("src_D", P(c_r)), ("geo", P(c_r)), ("g0", c_r)]
 
     return World, Obs, State
 
@@ -115,6 +115,8 @@ def lib(precision="double"):
         L.orc_num_segments.restype = c_i64
         L.orc_calibration_update.argtypes = [P(World), P(Obs), P(State), P(c_r)]
         L.orc_iterate_sac.argtypes = [P(World), P(Obs), P(State), P(c_r)]
+        L.orc_global_update.argtypes = [P(World), P(Obs), P(State)]
+        L.orc_global_update.restype = c_r
         L.orc_normal_rhs.argtypes = [P(World), P(Obs), P(State), P(c_r), P(c_r), P(c_r)]
         L.orc_normal_quadratic.argtypes = [P(World), P(Obs), P(State), P(c_r)]
         L.orc_normal_quadratic.restype = c_r
@@ -249,7 +251,7 @@ class Problem:
     """
 
     def __init__(self, consts, knots, t, eta_obs, sigma, src, fov, cell, s, a, c, precision="double",
-                 sigma_eff=None, ccd=None, mu=None, geo=None, ac_cell=None):
+                 sigma_eff=None, ccd=None, mu=None, geo=None, ac_cell=None, g0=0.0):
         self.precision = precision
         self._cr, self._dt = PRECISIONS[precision][0], PRECISIONS[precision][1]
         self._World, self._Obs, self._State = _STRUCTS[precision]
@@ -289,7 +291,8 @@ class Problem:
                                  eph_Lrate=consts["eph_Lrate"], eps_obl=consts["eps_obl"], au_m=consts["au_m"],
                                  c_mps=consts["c_mps"], year_s=consts["year_s"],
                                  robust=int(consts.get("robust", 0)), eps_bucket=int(consts.get("eps_bucket", 8)),
-                                 geo_ccds=geo_ccds, geo_ac_cells=int(consts.get("geo_ac_cells", 0) or 0))
+                                 geo_ccds=geo_ccds, geo_ac_cells=int(consts.get("geo_ac_cells", 0) or 0),
+                                 defl=float(consts.get("defl", 0.0) or 0.0), ppn=int(consts.get("ppn", 0) or 0))
         n_iv = self.knots.size - 7
         if self.world.robust:
             # three components (along scan, across scan preceding and
@@ -301,7 +304,12 @@ class Problem:
         # robust 2: excess source noise eps_i^2 and its significance D per source
         self.src_eps2 = self._zeros(self.s.shape[0]) if self.world.robust == 2 else None
         self.src_D = self._zeros(self.s.shape[0]) if self.world.robust == 2 else None
+        self._g0 = g0                       # the global parameter of eq:gammaPPN (gamma = 1 + g0)
         self._refresh()
+
+    @property
+    def g0(self):
+        return float(self.state.g0)
 
     def _arr(self, x):
         return np.ascontiguousarray(x, dtype=self._dt)
@@ -311,6 +319,8 @@ class Problem:
 
     def _refresh(self):
         cr = self._cr
+        if hasattr(self, "state"):
+            self._g0 = self.state.g0            # kept across the struct's rebuild
         self.obs = self._Obs(n=self.t.size, t=_p(self.t, cr), eta_obs=_p(self.eta_obs, cr),
                              sigma=_p(self.sigma, c_f), src=_p(self.src, c_i32), fov=_p(self.fov, c_i8),
                              cell=_p(self.cell, c_i32), sigma_eff=_p(self.sigma_eff, cr),
@@ -318,13 +328,16 @@ class Problem:
         self.state = self._State(n_src=self.s.shape[0], n_att=self.a.shape[0], n_cells=self.c.size,
                                  s=_p(self.s, cr), a=_p(self.a, cr), c=_p(self.c, cr),
                                  n_buckets=self.eps_a2.size // 3, eps_a2=_p(self.eps_a2, cr),
-                                 src_eps2=_p(self.src_eps2, cr), src_D=_p(self.src_D, cr), geo=_p(self.geo, cr))
+                                 src_eps2=_p(self.src_eps2, cr), src_D=_p(self.src_D, cr), geo=_p(self.geo, cr),
+                                 g0=self._g0)
 
     def set_eta_obs(self, eta_obs):
         self.eta_obs = self._arr(eta_obs).copy()
         self._refresh()
 
-    def set_state(self, s=None, a=None, c=None, eps_a2=None, geo=None):
+    def set_state(self, s=None, a=None, c=None, eps_a2=None, geo=None, g0=None):
+        if g0 is not None:
+            self.state.g0 = g0
         if geo is not None:
             assert np.size(geo) == self.geo.size
             self.geo = self._arr(np.reshape(geo, -1)).copy()
@@ -400,6 +413,11 @@ class Problem:
                                        _p(d, self._cr))
         return d
 
+    def global_update(self):
+        """The update of g0 from eq:normG (Sect. 5.4), applied; returns it."""
+        return float(self._L.orc_global_update(ctypes.byref(self.world), ctypes.byref(self.obs),
+                                               ctypes.byref(self.state)))
+
     def normal_rhs(self):
         """Right-hand sides of the S, A and C normal equations at the current
         state: (rs [n_src][5], ra [n_att][4], rc [n_cells])."""
@@ -464,7 +482,8 @@ def problem_from_world(world, eta_obs=None, state="start", precision="double"):
     s, a, c = getattr(world, f"src_{which}"), getattr(world, f"att_{which}"), getattr(world, f"cal_{which}")
     return Problem(world.consts, world.knots, world.t, eta, world.sigma, world.src, world.fov, world.cell, s, a, c,
                    precision=precision, ccd=getattr(world, "ccd", None), mu=getattr(world, "mu", None),
-                   geo=world_geo(world, which), ac_cell=getattr(world, "ac_cell", None))
+                   geo=world_geo(world, which), ac_cell=getattr(world, "ac_cell", None),
+                   g0=getattr(world, f"g0_{which}", 0.0))
 
 
 def world_geo(world, which="true"):
@@ -496,7 +515,8 @@ def observed_field_angles(world, chunk=1 << 24):
                      world.fov[sl], world.cell[sl], world.src_true, world.att_true, world.cal_true,
                      ccd=None if geo_ccds == 0 else world.ccd[sl], mu=None if geo_ccds == 0 else world.mu[sl],
                      geo=None if geo_ccds == 0 else world_geo(world, "true"),
-                     ac_cell=None if getattr(world, "ac_cell", None) is None else world.ac_cell[sl])
+                     ac_cell=None if getattr(world, "ac_cell", None) is None else world.ac_cell[sl],
+                     g0=getattr(world, "g0_true", 0.0))
         o = pr.observe()
         # the residual of eta_obs = 0 is the calibration minus the computed
         # field angle (eq:resAL; eq:resAC across scan), so eta_obs = eta -

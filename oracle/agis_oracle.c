@@ -273,6 +273,7 @@ typedef struct {
     double bG[3], vG[3], vc[3];
     double tau;                 /* (t_B - t_ep) in years */
     double ubar[3], u[3], Su[3];
+    double dudg[3];             /* d(coordinate direction)/d g0 of the light deflection */
     double phi, zeta, eta, R;
     int f;
     int ac;                     /* 1: across-scan observation (cell < 0) */
@@ -343,10 +344,31 @@ static void forward_one(const orc_world_t* w, const orc_obs_t* obs, const orc_st
         ub[k] = o->r[k] + o->tau * (o->p[k] * s[3] + o->qv[k] * s[4]) - s[2] * o->bG[k];
     double nub = sqrt(dot3(ub, ub));
     for (int k = 0; k < 3; ++k) o->ubar[k] = ub[k] / nub;
+    /* light deflection by the Sun (eq:astro, with gamma = 1 + g0 of
+     * eq:gammaPPN), to first order in GM/(c^2 r) for a source at infinity:
+     * the coordinate direction moves by (1 + gamma) GM/(c^2 r) (e - (e.u)u) /
+     * (1 + e.u) towards e, the unit vector from the Sun to the observer at
+     * distance r (the Sun sits at the barycentre of the synthetic world) */
+    double ud[3];
+    for (int k = 0; k < 3; ++k) {
+        ud[k] = o->ubar[k];
+        o->dudg[k] = 0.0;
+    }
+    if (w->defl > 0.0) {
+        const double rb = sqrt(dot3(o->bG, o->bG));
+        double e[3];
+        for (int k = 0; k < 3; ++k) e[k] = o->bG[k] / rb;
+        const double eu = dot3(e, o->ubar);
+        const double f = w->defl / rb / (1.0 + eu);
+        for (int k = 0; k < 3; ++k) {
+            o->dudg[k] = f * (e[k] - eu * o->ubar[k]);
+            ud[k] = o->ubar[k] + (2.0 + st->g0) * o->dudg[k];
+        }
+    }
     /* eq:classAberr */
     for (int k = 0; k < 3; ++k) o->vc[k] = o->vG[k] * w->au_m / w->c_mps;
     double uu[3];
-    for (int k = 0; k < 3; ++k) uu[k] = o->ubar[k] + o->vc[k];
+    for (int k = 0; k < 3; ++k) uu[k] = ud[k] + o->vc[k];
     double nu = sqrt(dot3(uu, uu));
     for (int k = 0; k < 3; ++k) o->u[k] = uu[k] / nu;
     /* eq:srsprop, eq:srsprop1, eq:srspropeta */
@@ -387,6 +409,21 @@ static void source_partials(const orc_fwd_t* o, double A[5]) {
         orc_frame_rotate(o->q, du, dSu);
         A[j] = o->ac ? dot3(n, dSu) : dot3(m, dSu) / cz;
     }
+}
+
+/* Sect. 5.4: the global design entry -dR/dg0, in analogy with the source
+ * partials: the deflection's derivative d(ubar)/dg0 through the aberration
+ * (to first order in v/c) and the attitude into the field angle. */
+static double global_partial(const orc_fwd_t* o) {
+    const double ubv = dot3(o->ubar, o->vc);
+    const double vd = dot3(o->vc, o->dudg);
+    double du[3], dSu[3];
+    for (int k = 0; k < 3; ++k) du[k] = (1.0 - ubv) * o->dudg[k] - o->ubar[k] * vd;
+    orc_frame_rotate(o->q, du, dSu);
+    const double sp = sin(o->phi), cp = cos(o->phi), sz = sin(o->zeta), cz = cos(o->zeta);
+    const double m[3] = {-sp, cp, 0.0};
+    const double n[3] = {-sz * cp, -sz * sp, cz};
+    return o->ac ? dot3(n, dSu) : dot3(m, dSu) / cz;
 }
 
 /* Sect. 5.2.3: dR_AL/dq = -(eq:dfadq) = 2 sec(zeta) q {S'n, 0}; across
@@ -996,6 +1033,37 @@ void orc_calibration_update(const orc_world_t* w, const orc_obs_t* obs, orc_stat
  * s^{k+1}, a^k, c^k (the S[AC] variant of eq:precondS(CAG) without G).
  * Robust: the excess attitude noise is re-estimated from the residuals after
  * the source update and used by the A and C weights (Sect. 5.2.5). */
+/* Sect. 5.4, eq:normG for g = (g0, g1): g0 of eq:gammaPPN and the
+ * pseudo-parameter g1, a global shift of all parallaxes (its design entry is
+ * each observation's parallax entry), solved with g0 but never applied; the
+ * 2x2 system sum A_g W A_g' d = sum A_g W R (A_g = -dR/dg, W the A/C
+ * weights) by C1-C3.  Returns the update of g0. */
+static double global_solve(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st) {
+    double N[4] = {0.0, 0.0, 0.0, 0.0}, b[2] = {0.0, 0.0};
+    for (int64_t l = 0; l < obs->n; ++l) {
+        orc_fwd_t o;
+        forward_one(w, obs, st, l, &o);
+        const double W = weight(w, obs, st, l, &o);
+        double As[5];
+        source_partials(&o, As);
+        const double Ag[2] = {global_partial(&o), As[2]};
+        for (int r = 0; r < 2; ++r) {
+            for (int c = 0; c < 2; ++c) N[2 * r + c] += Ag[r] * W * Ag[c];
+            b[r] += Ag[r] * W * o.R;
+        }
+    }
+    orc_chol_c1(N, 2);
+    orc_chol_c2(N, 2, b);
+    orc_chol_c3(N, 2, b);
+    return b[0];
+}
+
+double orc_global_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st) {
+    const double d = global_solve(w, obs, st);
+    st->g0 += d;
+    return d;
+}
+
 void orc_iterate_sac(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st, double* var) {
     orc_source_update(w, obs, st, NULL, NULL, NULL, var);
     orc_excess_attitude_noise(w, obs, st);
@@ -1003,8 +1071,11 @@ void orc_iterate_sac(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st
     double* dc = (double*)calloc((size_t)cal_size(w, obs, st), sizeof(double));
     attitude_solve(w, obs, st, da);
     calibration_solve(w, obs, st, dc);
+    /* S[ACG]: the global update from the same residuals and weights */
+    const double dg = w->ppn ? global_solve(w, obs, st) : 0.0;
     for (int64_t k = 0; k < 4 * st->n_att; ++k) st->a[k] += da[k];
     apply_calibration(w, obs, st, dc);
+    st->g0 += dg;
     free(da);
     free(dc);
 }

@@ -44,6 +44,9 @@ typedef struct {
                                  coefficients per cell and CCD (n CCDs) in the AC pixel coordinate */
     int32_t geo_ac_cells;     /* with the AC term (obs ac_cell): its cells, each a field of view
                                  and a long interval k of eq:etazeta */
+    double defl;              /* 0: no light deflection; else GM_sun / (c^2 AU) [rad AU]: the Sun's
+                                 gravitational light deflection with gamma = 1 + g0 (eq:gammaPPN) */
+    int32_t ppn;              /* 1: the global block solves g0 (eq:normG) in each iteration */
 } orc_world_t;
 
 typedef struct {
@@ -78,6 +81,7 @@ typedef struct {
     double* geo;              /* [n_cells][geo_ccds][3] geometric calibration coefficients
                                  (eq:etazeta, r = 0, 1, 2) [rad], followed with ac_cell by the
                                  AC ones [geo_ac_cells][geo_ccds][3]; NULL when geo_ccds = 0 */
+    double g0;                /* global parameter of eq:gammaPPN: gamma = 1 + g0 */
 } orc_state_t;
 
 /* --- Appendix A: quaternions -------------------------------------------- */
@@ -153,6 +157,11 @@ int64_t orc_num_segments(const orc_world_t* w);
 void orc_calibration_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st, double* d);
 /* S[AC]: S, then A and C from the same post-S residuals. */
 void orc_iterate_sac(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st, double* var);
+/* Sect. 5.4: the global update of g0 from eq:normG at the current state
+ * (W from the A/C weights), solved jointly with the pseudo-parameter g1 (a
+ * global parallax shift, never applied), applied; returns the update (0
+ * without a pivot). */
+double orc_global_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st);
 
 /* Right-hand sides b - N x of the S, A and C normal equations at the current
  * state, summed over all observations (no robust weighting). */

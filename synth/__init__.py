@@ -45,6 +45,7 @@ DAY = 86400.0
 YEAR = 365.25 * DAY
 AU_M = 149597870700.0
 C_MPS = 299792458.0
+GM_SUN = 1.32712440018e20              # heliocentric gravitational constant [m^3 s^-2]
 
 
 class _Law(ctypes.Structure):
@@ -128,6 +129,11 @@ class WorldSpec:
     # uniformly, at that line's time
     geo_ac: bool = False
     geo_ac_days: int = 30
+    # the Sun's gravitational light deflection in the model, with the PPN
+    # parameter gamma = 1 + g0 (eq:gammaPPN) solved by the global block:
+    # true g0 = 0 (general relativity), start value g0_start
+    ppn: bool = False
+    g0_start: float = 1e-3
 
 
 @dataclass
@@ -160,6 +166,9 @@ class World:
     ac_cell: np.ndarray | None = None
     geo_ac_true: np.ndarray | None = None
     geo_ac_start: np.ndarray | None = None
+    # the global parameter g0 (true and start values)
+    g0_true: float = 0.0
+    g0_start: float = 0.0
 
     @property
     def n_obs(self) -> int:
@@ -477,7 +486,8 @@ def make_world(spec: WorldSpec, law: dict | None = None, progress=None) -> World
         eph_radius_au=1.01, eph_L0=law["L0"], eph_Lrate=law["Lrate"], eps_obl=law["eps_obl"],
         au_m=AU_M, c_mps=C_MPS, year_s=YEAR, t_beg=t_beg, t_end=t_end, law=law,
         robust=int(spec.robust), eps_bucket=spec.eps_bucket, eps_a_init=spec.eps_a_init,
-        geo_ccds=nc if spec.geo_cal else 0, geo_ac_cells=int(n_ac_cells))
+        geo_ccds=nc if spec.geo_cal else 0, geo_ac_cells=int(n_ac_cells),
+        defl=GM_SUN / (C_MPS ** 2 * AU_M) if spec.ppn else 0.0, ppn=int(spec.ppn))
     return World(spec=spec, consts=consts, knots=knots, src_true=src_true, att_true=att_true,
                  cal_true=cal_true, src_start=src_start, att_start=att_start, cal_start=cal_start,
                  t=np.ascontiguousarray(t_obs), src=np.ascontiguousarray(src_idx),
@@ -487,4 +497,4 @@ def make_world(spec: WorldSpec, law: dict | None = None, progress=None) -> World
                  ccd=None if ccd is None else np.ascontiguousarray(ccd),
                  mu=None if mu is None else np.ascontiguousarray(mu), geo_true=geo_true, geo_start=geo_start,
                  ac_cell=None if ac_cell is None else np.ascontiguousarray(ac_cell), geo_ac_true=geo_ac_true,
-                 geo_ac_start=geo_ac_start)
+                 geo_ac_start=geo_ac_start, g0_true=0.0, g0_start=float(spec.g0_start) if spec.ppn else 0.0)
