@@ -114,6 +114,8 @@ typedef struct {
     int32_t robust;
     int32_t eps_bucket;
     double eps_a_init;
+    double defl;            /* 0, or GM_sun / (c^2 AU) [rad AU]: the Sun's light deflection in the model */
+    int32_t ppn;            /* 1: the global block solves g0 (gamma = 1 + g0) in each iteration */
 } agis_config_t;
 
 /*
@@ -236,6 +238,29 @@ int agis_get_calibration(agis_ctx_t* ctx, int64_t n, double* c, int where);
  * agis_load_geometry (the context then uses the cell offsets, which are
  * zero if the model had been on).
  */
+/*
+ * Global block (Sect. 5.4, eq:normG) with the PPN parameter gamma = 1 + g0
+ * (eq:gammaPPN): with cfg.defl > 0 the model deflects the coordinate
+ * direction by the Sun's gravity, (1 + gamma) GM/(c^2 r) (e - (e.u)u) /
+ * (1 + e.u) to first order (e the unit vector from the Sun, taken at the
+ * barycentre, to the observer at distance r), before aberration; with
+ * cfg.ppn each agis_iterate also solves g = (g0, g1) from eq:normG with the
+ * A/C weights and residuals (S[ACG]) and applies the update of g0; g1 is
+ * the pseudo-parameter of a global parallax shift, solved with g0 and never
+ * applied.  agis_global_update: that solve and update alone at the current
+ * parameters (dg, may be NULL: the update of g0 and the value of g1);
+ * AGIS_E_STATE without cfg.ppn.  agis_set_global: g0 (0 at creation).
+ * agis_get_global: out[0] g0, out[1] the last update of g0, out[2] the last
+ * g1.  With the deflection (FP64 only; AGIS_E_INVALID_ARG at creation
+ * otherwise, and for ppn without it), conjugate gradients, the
+ * recorded-update schemes and frozen weights are refused (AGIS_E_STATE):
+ * they carry s, a and c and the plain model only; the robust S block takes
+ * the HBM-column path.
+ */
+int agis_global_update(agis_ctx_t* ctx, double dg[2]);
+int agis_set_global(agis_ctx_t* ctx, double g0);
+int agis_get_global(agis_ctx_t* ctx, double out[3]);
+
 int agis_load_geometry(agis_ctx_t* ctx, int64_t n, const int8_t* ccd, const float* mu, int32_t n_ccd,
                        const int32_t* ac_cell, int32_t n_ac_cells, int where);
 int agis_set_geo_calibration(agis_ctx_t* ctx, int64_t n, const double* c, int where);

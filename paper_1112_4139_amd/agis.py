@@ -31,7 +31,7 @@ class agis_config_t(ctypes.Structure):
                 ("lambda_reg", c_d), ("seg_len", c_i32), ("seg_overlap", c_i32), ("eph_radius_au", c_d),
                 ("eph_L0", c_d), ("eph_Lrate", c_d), ("eps_obl", c_d), ("au_m", c_d), ("c_mps", c_d),
                 ("year_s", c_d), ("precision", c_i32), ("device", c_i32), ("stream", ctypes.c_void_p),
-                ("robust", c_i32), ("eps_bucket", c_i32), ("eps_a_init", c_d)]
+                ("robust", c_i32), ("eps_bucket", c_i32), ("eps_a_init", c_d), ("defl", c_d), ("ppn", c_i32)]
 
 
 class agis_obs_soa_t(ctypes.Structure):
@@ -80,6 +80,9 @@ _sig = {
     "agis_set_calibration": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
     "agis_get_calibration": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
     "agis_load_geometry": ([_ctx_p, c_i64, _vp, _vp, c_i32, _vp, c_i32, ctypes.c_int], ctypes.c_int),
+    "agis_global_update": ([_ctx_p, P(c_d)], ctypes.c_int),
+    "agis_set_global": ([_ctx_p, c_d], ctypes.c_int),
+    "agis_get_global": ([_ctx_p, P(c_d)], ctypes.c_int),
     "agis_set_geo_calibration": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
     "agis_get_geo_calibration": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
     "agis_source_update": ([_ctx_p, P(agis_block_stats_t)], ctypes.c_int),
@@ -170,7 +173,8 @@ def agis_create(consts: dict, knots, precision=AGIS_FP64, device=0, stream=None)
                         c_mps=consts["c_mps"], year_s=consts["year_s"], precision=precision, device=device,
                         stream=stream, robust=int(consts.get("robust", 0)),
                         eps_bucket=int(consts.get("eps_bucket", 8)),
-                        eps_a_init=float(consts.get("eps_a_init", 0.0)))
+                        eps_a_init=float(consts.get("eps_a_init", 0.0)), defl=float(consts.get("defl", 0.0) or 0.0),
+                        ppn=int(consts.get("ppn", 0) or 0))
     ctx = _ctx_p()
     rc = _lib.agis_create(ctypes.byref(cfg), ctypes.byref(ctx))
     _check(rc, None)
@@ -244,6 +248,25 @@ def agis_load_geometry(ctx, ccd, mu, n_ccd, ac_cell=None, n_ac_cells=0):
     if wc != wm or wa != wc:
         raise ValueError("ccd, mu and ac_cell must all be host arrays or all device tensors")
     _check(_lib.agis_load_geometry(ctx, int(len(ccd)), pc, pm, int(n_ccd), pa, int(n_ac_cells), wc), ctx)
+
+
+def agis_global_update(ctx):
+    """The global block's solve and update of g0 at the current parameters;
+    returns (update of g0, g1)."""
+    out = (c_d * 2)()
+    _check(_lib.agis_global_update(ctx, out), ctx)
+    return out[0], out[1]
+
+
+def agis_set_global(ctx, g0):
+    _check(_lib.agis_set_global(ctx, float(g0)), ctx)
+
+
+def agis_get_global(ctx):
+    """(g0, the last update of g0, the last g1)."""
+    out = (c_d * 3)()
+    _check(_lib.agis_get_global(ctx, out), ctx)
+    return out[0], out[1], out[2]
 
 
 def agis_set_geo_calibration(ctx, c):

@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libagis.so")
-SOURCES = ["capi.hip", "store.hip", "kernels.hip", "hot.hip", "robust.hip", "learned.hip", "cg.hip", "geo.hip"]
+SOURCES = ["capi.hip", "store.hip", "kernels.hip", "hot.hip", "robust.hip", "learned.hip", "cg.hip", "geo.hip",
+           "global.hip"]
 ARCH = os.environ.get("AGIS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -90,6 +90,9 @@ struct agis_ctx {
     // parameters
     double* s = nullptr;                 // [n_src][5]
     double* a = nullptr;                 // [N][4]
+    double* gpar = nullptr;              // [2] global parameters: g0 (gamma = 1 + g0), g1 (held at zero)
+    double* dgpar = nullptr;             // [2] the last global solve: the update of g0, the value of g1
+    double* g_iv = nullptr;              // [K][5] per-interval sums of the global block (ppn only)
     double* c = nullptr;                 // [n_cells + 1]; entry n_cells (across scan) stays 0
     agis::SrcPrep* prep = nullptr;       // [n_src]
     double* s_ref = nullptr;             // [n_src][5] frame reference (optional)
@@ -283,6 +286,7 @@ int load_geometry(agis_ctx* ctx, const int8_t* ccd, const float* mu, int32_t n_c
 void launch_geo_eta(agis_ctx* ctx);
 void launch_geo_solve(agis_ctx* ctx);
 void launch_apply_attitude(agis_ctx* ctx);
+void launch_global_solve(agis_ctx* ctx);
 void launch_apply_add(agis_ctx* ctx, int64_t n, double* x, const double* dx);   // x += dx
 void launch_apply_calibration(agis_ctx* ctx);
 void launch_frame_fit(agis_ctx* ctx);

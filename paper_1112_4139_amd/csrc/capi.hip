@@ -283,6 +283,11 @@ extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
         g_create_error = "year_s, c_mps and au_m must be positive";
         return AGIS_E_INVALID_ARG;
     }
+    if (!(std::isfinite(cfg->defl) && cfg->defl >= 0.0) || (cfg->ppn && !(cfg->defl > 0.0)) ||
+        (cfg->defl > 0.0 && cfg->precision != AGIS_FP64)) {
+        g_create_error = "defl must be finite and >= 0, ppn needs defl > 0, and the deflection runs in FP64 only";
+        return AGIS_E_INVALID_ARG;
+    }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) {
         g_create_error = "no such HIP device";
@@ -338,6 +343,7 @@ extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
     k.half_gamma_err = (double)((long double)k.gamma_half -
                                 std::atan2((long double)k.sin_half_gamma, (long double)k.cos_half_gamma));
     k.ac_cf0 = INT32_MAX;                    // set by agis_load_observations
+    k.defl = cfg->defl > 0.0 ? cfg->defl : 0.0;
     build_segments(ctx);
     if (cfg->robust) {
         ctx->n_buckets = (ctx->K + cfg->eps_bucket - 1) / cfg->eps_bucket;
@@ -371,6 +377,15 @@ extern "C" int agis_create(const agis_config_t* cfg, agis_ctx_t** out) {
     if ((rc = dalloc(ctx, &ctx->ktab, ctx->K, "knot table")) != AGIS_OK) return fail(rc);
     if ((rc = dalloc(ctx, &ctx->a, 4 * ctx->N, "attitude")) != AGIS_OK) return fail(rc);
     if ((rc = dalloc(ctx, &ctx->da, 4 * ctx->N, "attitude update")) != AGIS_OK) return fail(rc);
+    if ((rc = dalloc(ctx, &ctx->gpar, 2, "global parameters")) != AGIS_OK ||
+        (rc = dalloc(ctx, &ctx->dgpar, 2, "global update")) != AGIS_OK)
+        return fail(rc);
+    if (ctx->cfg.ppn && (rc = dalloc(ctx, &ctx->g_iv, 5 * std::max<int64_t>(ctx->K, 1), "global sums")) != AGIS_OK)
+        return fail(rc);
+    if (hipMemset(ctx->gpar, 0, 2 * sizeof(double)) != hipSuccess ||
+        hipMemset(ctx->dgpar, 0, 2 * sizeof(double)) != hipSuccess)
+        return fail(set_error(ctx, AGIS_E_DEVICE, "global parameters: clear failed"));
+    ctx->k.gpar = ctx->gpar;
     if ((rc = dalloc(ctx, &ctx->iv_sums, (size_t)IV_SUMS * ctx->K, "interval sums")) != AGIS_OK) return fail(rc);
     if ((rc = dalloc(ctx, &ctx->iv_cal, (size_t)IV_CAL * ctx->K, "interval calibration sums")) != AGIS_OK)
         return fail(rc);
@@ -437,6 +452,9 @@ extern "C" void agis_destroy(agis_ctx_t* ctx) {
     dfree(ctx->ktab);
     dfree(ctx->a);
     dfree(ctx->da);
+    dfree(ctx->gpar);
+    dfree(ctx->dgpar);
+    dfree(ctx->g_iv);
     dfree(ctx->iv_sums);
     dfree(ctx->iv_cal);
     dfree(ctx->segs);
@@ -700,7 +718,7 @@ static int run_source(agis_ctx* ctx) {
 // see the same parameters (S[AC]).  apply = false leaves the updates in da
 // and dc; rc (optional) receives the calibration right-hand sides.
 static int run_ac(agis_ctx* ctx, bool do_a, bool do_c, bool eps_update = false, bool apply = true,
-                  double* rc = nullptr) {
+                  double* rc = nullptr, bool do_g = false) {
     if (eps_update && robust_now(ctx)) {
         tstart(ctx, T_EPS);
         launch_excess_noise(ctx);
@@ -723,6 +741,12 @@ static int run_ac(agis_ctx* ctx, bool do_a, bool do_c, bool eps_update = false, 
         HIPCHK(hipGetLastError());
         tstop(ctx, T_CAL);
     }
+    // the global block from the same parameters (S[ACG]; Sect. 5.4)
+    do_g = do_g && ctx->cfg.ppn;
+    if (do_g) {
+        launch_global_solve(ctx);
+        HIPCHK(hipGetLastError());
+    }
     if (do_a && apply) launch_apply_attitude(ctx);
     if (do_c && apply) {
         if (ctx->geo_ccds > 0) {
@@ -732,6 +756,7 @@ static int run_ac(agis_ctx* ctx, bool do_a, bool do_c, bool eps_update = false, 
             launch_apply_calibration(ctx);
         }
     }
+    if (do_g && apply) launch_apply_add(ctx, 1, ctx->gpar, ctx->dgpar);
     HIPCHK(hipGetLastError());
     return AGIS_OK;
 }
@@ -795,6 +820,39 @@ extern "C" int agis_calibration_update(agis_ctx_t* ctx, agis_block_stats_t* st) 
     if (rc) return rc;
     rc = stats_c(ctx, st);
     if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return AGIS_OK;
+}
+
+extern "C" int agis_global_update(agis_ctx_t* ctx, double dg[2]) {
+    CHECK_CTX();
+    ++ctx->xver;
+    REQUIRE_LOADED();
+    if (!ctx->cfg.ppn) return set_error(ctx, AGIS_E_STATE, "the global block needs ppn in the configuration");
+    if (ctx->K > 0) {
+        launch_global_solve(ctx);
+        launch_apply_add(ctx, 1, ctx->gpar, ctx->dgpar);
+        HIPCHK(hipGetLastError());
+    }
+    if (dg) HIPCHK(hipMemcpyAsync(dg, ctx->dgpar, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return AGIS_OK;
+}
+
+extern "C" int agis_set_global(agis_ctx_t* ctx, double g0) {
+    CHECK_CTX();
+    ++ctx->xver;
+    if (!std::isfinite(g0)) return set_error(ctx, AGIS_E_INVALID_ARG, "g0 not finite");
+    HIPCHK(hipMemcpyAsync(ctx->gpar, &g0, sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return AGIS_OK;
+}
+
+extern "C" int agis_get_global(agis_ctx_t* ctx, double out[3]) {
+    CHECK_CTX();
+    if (!out) return set_error(ctx, AGIS_E_INVALID_ARG, "null output");
+    HIPCHK(hipMemcpyAsync(out, ctx->gpar, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(out + 1, ctx->dgpar, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return AGIS_OK;
 }
@@ -865,7 +923,7 @@ static int iterate_once(agis_ctx* ctx, agis_iter_stats_t* st) {
     if (rc) return rc;
     if (st && (rc = stats_s(ctx, &st->s))) return rc;
     // robust: eps_a from the residuals after the source update (Sect. 5.2.5)
-    rc = run_ac(ctx, true, true, true);
+    rc = run_ac(ctx, true, true, true, true, nullptr, true);
     if (rc) return rc;
     if (st && (rc = stats_a(ctx, &st->a))) return rc;
     if (st && (rc = stats_c(ctx, &st->c))) return rc;
@@ -1166,6 +1224,8 @@ extern "C" int agis_learned_reset(agis_ctx_t* ctx) {
     REQUIRE_LOADED();
     if (ctx->geo_ccds > 0)
         return set_error(ctx, AGIS_E_STATE, "recorded updates and extrapolation: not with the geometric calibration");
+    if (ctx->k.defl > 0.0)
+        return set_error(ctx, AGIS_E_STATE, "recorded updates and extrapolation: not with the light deflection");
     int rc = learned_alloc(ctx);
     if (rc) return rc;
     launch_hist_anchor(ctx);
@@ -1680,6 +1740,7 @@ extern "C" int agis_cg_iterate(agis_ctx_t* ctx, int32_t n_eval, int32_t restart,
     if (n_eval < 0 || restart < 1) return set_error(ctx, AGIS_E_INVALID_ARG, "n_eval >= 0 and restart >= 1");
     if (ctx->geo_ccds > 0)
         return set_error(ctx, AGIS_E_STATE, "conjugate gradients: not with the geometric calibration");
+    if (ctx->k.defl > 0.0) return set_error(ctx, AGIS_E_STATE, "conjugate gradients: not with the light deflection");
     if (robust_now(ctx))
         return set_error(ctx, AGIS_E_STATE,
                          "conjugate gradients need fixed observation weights (robust mode: freeze them first)");
@@ -1704,6 +1765,7 @@ extern "C" int agis_freeze_weights(agis_ctx_t* ctx, int32_t freeze) {
     ++ctx->xver;
     REQUIRE_LOADED();
     if (!ctx->cfg.robust) return set_error(ctx, AGIS_E_STATE, "the context is not robust");
+    if (ctx->k.defl > 0.0) return set_error(ctx, AGIS_E_STATE, "frozen weights: not with the light deflection");
     if (!freeze) {
         if (ctx->frozen) {
             ctx->frozen = false;

@@ -49,7 +49,7 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
 // k.ac_cf0 on); the along-scan-only instance is the plain pass.  SigT: the
 // type of the sigma column (float: the input; double: the frozen sigma_eff
 // of the hybrid scheme).
-template <int G, bool MIXED, bool AC, typename SigT>
+template <int G, bool MIXED, bool AC, typename SigT, bool DEFL = false>
 __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n_src, const int64_t* __restrict__ off,
                                                        const double* __restrict__ ot, const double* __restrict__ oeta,
                                                        const SigT* __restrict__ osig,
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256, 2) void k_source_update(DevConsts k, int64_t n
             ell_n = oell[ln];
         }
         ObsEval o;
-        observe(k, t_c, e_c, cal_c, r, mu, plx, a_c, knots + (ell_c - 2), kt_c, o, ac_c);
+        observe<DEFL>(k, t_c, e_c, cal_c, r, mu, plx, a_c, knots + (ell_c - 2), kt_c, o, ac_c);
         double A[5];
         source_partials(o, p, q, r, A, ac_c);
         const double sg = (double)s_c;
@@ -222,7 +222,7 @@ constexpr int AC_XS = 33;               // LDS row stride (doubles) of the trans
 // running sums, converted to FP64 for the band solve.
 // AC: across-scan observations present (cell/fov code from k.ac_cf0 on):
 // their rows carry the AC attitude partials and no calibration entries.
-template <bool MIXED, bool AC, typename SigT>
+template <bool MIXED, bool AC, typename SigT, bool DEFL = false>
 __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t K, const int64_t* __restrict__ iv_off,
                                                            const double* __restrict__ ot,
                                                            const double* __restrict__ oeta,
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(64 * AC_WAVES) void k_ac_pass(DevConsts k, int64_t 
         {
             const bool ac = AC && cf_c >= k.ac_cf0;
             ObsEval o;
-            observe(k, t_c, e_c, c[cf_c >> 1], sp_c.r, sp_c.mu, sp_c.plx, sh_a[wv], sh_k[wv], kt, o, ac);
+            observe<DEFL>(k, t_c, e_c, c[cf_c >> 1], sp_c.r, sp_c.mu, sp_c.plx, sh_a[wv], sh_k[wv], kt, o, ac);
             double g[4];
             attitude_partial(o, g, ac);
             const double sg = (double)s_c;
@@ -690,7 +690,10 @@ inline int groups_grid(int64_t n_items, int items_per_block) {
     ctx->k, ctx->n_src, ctx->src_off, ctx->s_t, ctx->s_eta, SIG, ctx->s_cell, ctx->s_ell, ctx->knots, ctx->ktab,   \
         ctx->a, ctx->c, ctx->s, ctx->prep, ctx->ds, ctx->qsrc, ctx->sdef, ctx->svar, ctx->src_order, ctx->rhs_s_out
 #define AGIS_S_LAUNCH(G)                                                                                       \
-    if (ctx->frozen)                                                                                           \
+    if (ctx->k.defl > 0.0)                                                                                     \
+        (ctx->has_ac ? k_source_update<G, false, true, float, true> : k_source_update<G, false, false, float, true>) \
+            <<<groups_grid(ctx->n_src, 256 / G), 256, 0, ctx->stream>>>(AGIS_S_ARGS(ctx->s_sig));            \
+    else if (ctx->frozen)                                                                                      \
         AGIS_S_KERNEL(G, double)<<<groups_grid(ctx->n_src, 256 / G), 256, 0, ctx->stream>>>(                  \
             AGIS_S_ARGS(ctx->s_sig_eff));                                                                      \
     else                                                                                                       \
@@ -708,9 +711,15 @@ void launch_source_update(agis_ctx* ctx) {
 
 template <typename T>
 static void ac_pass_with(agis_ctx* ctx, const T* sig) {
-    (ctx->cfg.precision == AGIS_MIXED ? (ctx->has_ac ? k_ac_pass<true, true, T> : k_ac_pass<true, false, T>)
-                                      : (ctx->has_ac ? k_ac_pass<false, true, T> : k_ac_pass<false, false, T>))
-        <<<(unsigned)((ctx->K + AC_WAVES - 1) / AC_WAVES), 64 * AC_WAVES, 0, ctx->stream>>>(
+    auto kern = ctx->cfg.precision == AGIS_MIXED
+                    ? (ctx->has_ac ? k_ac_pass<true, true, T> : k_ac_pass<true, false, T>)
+                    : (ctx->has_ac ? k_ac_pass<false, true, T> : k_ac_pass<false, false, T>);
+    if constexpr (std::is_same<T, float>::value) {
+        // the model with the Sun's light deflection (FP64 only, as the
+        // global block requires)
+        if (ctx->k.defl > 0.0) kern = ctx->has_ac ? k_ac_pass<false, true, float, true> : k_ac_pass<false, false, float, true>;
+    }
+    kern<<<(unsigned)((ctx->K + AC_WAVES - 1) / AC_WAVES), 64 * AC_WAVES, 0, ctx->stream>>>(
         ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, sig, ctx->t_cellfov, ctx->t_src, ctx->prep, ctx->knots,
         ctx->ktab, ctx->a, ctx->c, ctx->eps_a2, ctx->cfg.eps_bucket, robust_now(ctx), ctx->iv_sums, ctx->iv_cal,
         ctx->geo_ccds > 0 ? ctx->geo_wr : nullptr, ctx->geo_pos);

@@ -275,6 +275,7 @@ __global__ __launch_bounds__(256) void k_frame_apply_attitude(DevConsts k, int64
 }
 
 // ------------------------------------------------------------ residuals
+template <bool DEFL>
 __global__ __launch_bounds__(256) void k_residuals(DevConsts k, int64_t K, const int64_t* __restrict__ iv_off,
                                                    const double* __restrict__ ot, const double* __restrict__ oeta,
                                                    const int32_t* __restrict__ ocellfov,
@@ -294,7 +295,7 @@ __global__ __launch_bounds__(256) void k_residuals(DevConsts k, int64_t K, const
         const SrcPrep sp = prep[osrc[l]];
         const int32_t cf = ocellfov[l];
         ObsEval o;
-        observe(k, ot[l], oeta[l], c[cf >> 1], sp.r, sp.mu, sp.plx, a4, kn, kt, o, cf >= k.ac_cf0);
+        observe<DEFL>(k, ot[l], oeta[l], c[cf >> 1], sp.r, sp.mu, sp.plx, a4, kn, kt, o, cf >= k.ac_cf0);
         R[operm[l]] = o.R;
     }
 }
@@ -397,7 +398,8 @@ void launch_frame_apply(agis_ctx* ctx) {
 
 void launch_residuals(agis_ctx* ctx, double* R) {
     if (ctx->K == 0) return;
-    k_residuals<<<waves_grid(ctx->K, 4), 256, 0, ctx->stream>>>(ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta,
+    (ctx->k.defl > 0.0 ? k_residuals<true> : k_residuals<false>)<<<waves_grid(ctx->K, 4), 256, 0, ctx->stream>>>(
+                                                                 ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta,
                                                                  ctx->t_cellfov, ctx->t_src, ctx->t_perm, ctx->prep,
                                                                  ctx->knots, ctx->ktab, ctx->a, ctx->c, R);
 }

@@ -25,6 +25,8 @@ struct DevConsts {
     double half_gamma_err;                   // Gamma_c/2 - atan2(sin_half_gamma, cos_half_gamma)
     int32_t ac_cf0;                          // 2 n_cells: cell/fov codes from here on are across scan
     int64_t n_buckets;                       // excess-noise buckets per component (robust)
+    double defl;                             // 0, or GM_sun / (c^2 AU) [rad AU]: the Sun's light deflection
+    const double* gpar;                      // device [2]: g0 (gamma = 1 + g0), g1 (held at zero)
 };
 
 // Slot in the excess attitude noise array of a record with cell/fov code
@@ -147,6 +149,7 @@ struct ObsEval {
     double D;          // 1 - |qraw|^2 (eq:Dl)
     double B[4];       // B_{l-3..l}(t)
     double A[9];       // attitude matrix
+    double dudg[3];    // d(coordinate direction)/d g0 of the light deflection (0 without it)
 };
 
 // Observation model (eq:roemer, eq:astro-standard, eq:classAberr,
@@ -168,6 +171,9 @@ struct ObsEval {
 // observation; eta_obs then holds the observed zeta, cal is zero and R is
 // zeta_obs - zeta, with zeta = atan(z / rho) (the same odd series for
 // |z / rho| < 1e-2, atan2 otherwise).
+// DEFL: with the Sun's light deflection (k.defl, gamma = 1 + k.gpar[0]);
+// the instances without it are the plain model.
+template <bool DEFL = false>
 __device__ __forceinline__ void observe(const DevConsts& k, double t, double eta_obs, double cal,
                                             const double r[3], const double mu[3], double plx,
                                             const double* __restrict__ a4, const double* __restrict__ kn,
@@ -206,9 +212,28 @@ __device__ __forceinline__ void observe(const DevConsts& k, double t, double eta
         o.ubar[c] = ub[c] * iub;
         o.vc[c] = v[c] * k.au_c;
     }
+    // the Sun's light deflection (gamma = 1 + g0), first order in GM/(c^2 r):
+    // the coordinate direction moves by (1 + gamma) GM/(c^2 r) (e - (e.u) u) /
+    // (1 + e.u), e the unit vector from the Sun (the barycentre here) to
+    // the observer at distance r
     double uu[3];
+    if constexpr (DEFL) {
+        const double ib = rsqrt_nr(dot3(o.b, o.b));
+        const double eu = dot3(o.b, o.ubar) * ib;
+        const double f = k.defl * ib / (1.0 + eu);
+        const double gam1 = 2.0 + k.gpar[0];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) uu[c] = o.ubar[c] + o.vc[c];
+        for (int c = 0; c < 3; ++c) {
+            o.dudg[c] = f * (o.b[c] * ib - eu * o.ubar[c]);
+            uu[c] = o.ubar[c] + gam1 * o.dudg[c] + o.vc[c];
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            o.dudg[c] = 0.0;
+            uu[c] = o.ubar[c] + o.vc[c];
+        }
+    }
     const double iuu = rsqrt_nr(dot3(uu, uu));
     double u[3];
 #pragma unroll
@@ -300,6 +325,37 @@ __device__ __forceinline__ void source_partials(const ObsEval& o, const double p
     Ad[2] = (f * dot3(m, dpl) - mu_ * dot3(o.vc, dpl)) * secz;
     Ad[3] = a0 * o.tau;
     Ad[4] = a1 * o.tau;
+}
+
+// The global design entries (Sect. 5.4): -dR/dg0, the light deflection's
+// derivative through the first-order aberration and the attitude, and the
+// parallax entry of the source row (the pseudo-parameter g1, a global
+// parallax shift); r: the source's direction.
+__device__ __forceinline__ void global_partials(const ObsEval& o, const double r[3], double& a_g0, double& a_plx,
+                                                bool ac = false) {
+    const double inv_rho = o.inv_rho;
+    double m[3];
+    double secz = inv_rho;
+    if (ac) {
+        const double ns0 = -o.Su[2] * o.Su[0] * inv_rho, ns1 = -o.Su[2] * o.Su[1] * inv_rho, ns2 = o.rho;
+        m[0] = o.A[0] * ns0 + o.A[3] * ns1 + o.A[6] * ns2;
+        m[1] = o.A[1] * ns0 + o.A[4] * ns1 + o.A[7] * ns2;
+        m[2] = o.A[2] * ns0 + o.A[5] * ns1 + o.A[8] * ns2;
+        secz = 1.0;
+    } else {
+        const double ms0 = -o.Su[1] * inv_rho, ms1 = o.Su[0] * inv_rho;
+        m[0] = o.A[0] * ms0 + o.A[3] * ms1;
+        m[1] = o.A[1] * ms0 + o.A[4] * ms1;
+        m[2] = o.A[2] * ms0 + o.A[5] * ms1;
+    }
+    const double f = 1.0 - dot3(o.ubar, o.vc);
+    const double mu_ = dot3(m, o.ubar);
+    const double rb = dot3(r, o.b);
+    double dpl[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dpl[c] = -(o.b[c] - r[c] * rb);
+    a_plx = (f * dot3(m, dpl) - mu_ * dot3(o.vc, dpl)) * secz;
+    a_g0 = (f * dot3(m, o.dudg) - mu_ * dot3(o.vc, o.dudg)) * secz;
 }
 
 // dR/dq = 2 sec(zeta) q {S'n, 0} (eq:dfadq), n of eq:srspqr; across scan

@@ -395,7 +395,7 @@ __device__ void reg_quantile7_pair(const uint64_t (&kr)[KR], int64_t n, int64_t 
 }
 
 // ------------------------------------------------------------- S, pass 0
-template <int G>
+template <int G, bool DEFL = false>
 __global__ __launch_bounds__(256, 2) void k_s_rows(DevConsts k, int64_t n_src, const int64_t* __restrict__ off,
                                                    const double* __restrict__ ot, const double* __restrict__ oeta,
                                                    const float* __restrict__ osig, const int32_t* __restrict__ ocell,
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(256, 2) void k_s_rows(DevConsts k, int64_t n_src, c
         }
         const bool ac = cf_c >= k.ac_cf0;
         ObsEval o;
-        observe(k, t_c, e_c, cal_c, r, mu, plx, a_c, knots + (ell_c - 2), kt_c, o, ac);
+        observe<DEFL>(k, t_c, e_c, cal_c, r, mu, plx, a_c, knots + (ell_c - 2), kt_c, o, ac);
         double A[5];
         source_partials(o, p, q, r, A, ac);
         const double sg = (double)s_c;
@@ -801,6 +801,7 @@ __global__ __launch_bounds__(256) void k_s_irls_eps(int64_t n_src, const int64_t
 }
 
 // ------------------------------------------------ excess attitude noise
+template <bool DEFL>
 __global__ __launch_bounds__(64) void k_ac_resid(DevConsts k, int64_t K, const int64_t* __restrict__ iv_off,
                                                  const double* __restrict__ ot, const double* __restrict__ oeta,
                                                  const float* __restrict__ osig,
@@ -820,7 +821,7 @@ __global__ __launch_bounds__(64) void k_ac_resid(DevConsts k, int64_t K, const i
         const SrcPrep sp = prep[osrc[l]];
         const int32_t cf = ocellfov[l];
         ObsEval o;
-        observe(k, ot[l], oeta[l], c[cf >> 1], sp.r, sp.mu, sp.plx, a4, kn, kt, o, cf >= k.ac_cf0);
+        observe<DEFL>(k, ot[l], oeta[l], c[cf >> 1], sp.r, sp.mu, sp.plx, a4, kn, kt, o, cf >= k.ac_cf0);
         const double sg = (double)osig[l];
         v[l] = o.R * o.R - sg * sg - (robust == 2 ? sp.pad : 0.0);       // e09 with eps_i^2 (mode 2)
     }
@@ -1634,7 +1635,7 @@ __global__ __launch_bounds__(64 * W) void k_s_regs(DevConsts k, int64_t n_src, c
 // a few hundred, so a pass per interval would leave many threads idle); the
 // bucket's attitude coefficients, knots, interval tables and offsets sit in
 // LDS, and each observation finds its interval there by bisection.
-template <int NT>
+template <int NT, bool DEFL = false>
 __global__ __launch_bounds__(NT) void k_eps_fused(DevConsts k, int64_t n_buckets, int64_t K, int eps_bucket, int cap,
                                                   const int64_t* __restrict__ iv_off, const double* __restrict__ ot,
                                                   const double* __restrict__ oeta, const float* __restrict__ osig,
@@ -1685,7 +1686,7 @@ __global__ __launch_bounds__(NT) void k_eps_fused(DevConsts k, int64_t n_buckets
         const int32_t cf = ocellfov[l];
         const bool ac = cf >= k.ac_cf0;
         ObsEval o;
-        observe(k, ot[l], oeta[l], c[cf >> 1], sp.r, sp.mu, sp.plx, sa + 4 * lo, sk + lo, st[lo], o, ac);
+        observe<DEFL>(k, ot[l], oeta[l], c[cf >> 1], sp.r, sp.mu, sp.plx, sa + 4 * lo, sk + lo, st[lo], o, ac);
         const double sg = (double)osig[l];
         vals[i] = o.R * o.R - sg * sg - (robust == 2 ? sp.pad : 0.0);
         const int cm = ac ? 1 + (cf & 1) : 0;
@@ -1733,7 +1734,7 @@ inline size_t eps_lds_bytes(int64_t cap, int64_t eps_bucket) {
 }  // namespace
 
 #define AGIS_ROWS_LAUNCH(G)                                                                                      \
-    k_s_rows<G><<<groups_grid(n_src, 256 / G), 256, 0, ctx->stream>>>(                                           \
+    (ctx->k.defl > 0.0 ? k_s_rows<G, true> : k_s_rows<G, false>)<<<groups_grid(n_src, 256 / G), 256, 0, ctx->stream>>>( \
         ctx->k, n_src, ctx->src_off, ctx->s_t, ctx->s_eta, ctx->s_sig, ctx->s_cell, ctx->s_ell, ctx->knots,        \
         ctx->ktab, ctx->a, ctx->c, ctx->s, ctx->eps_a2, ctx->cfg.eps_bucket, ctx->rcol, ctx->n_obs, order)
 #define AGIS_IRLS_LAUNCH(G)                                                                                      \
@@ -1793,7 +1794,9 @@ static void source_solve_columns(agis_ctx* ctx, int64_t k0, int64_t n) {
 
 // Per-source LDS kernels for the robust S block (robust mode 1 only; the
 // excess source noise of mode 2 keeps the HBM-column kernels).
-static bool s_lds(const agis_ctx* ctx) { return ctx->robust_s_mode >= 1 && ctx->cfg.robust == 1; }
+static bool s_lds(const agis_ctx* ctx) {
+    return ctx->robust_s_mode >= 1 && ctx->cfg.robust == 1 && !(ctx->k.defl > 0.0);   // on-chip paths: plain model
+}
 static bool s_from_columns(const agis_ctx* ctx) { return ctx->robust_s_mode == 1; }
 static bool s_regs(const agis_ctx* ctx) { return ctx->robust_s_mode == 3; }
 static int sreg_rows(const agis_ctx* ctx) { return std::min(std::max(ctx->sreg_rows, 1), SR_M); }
@@ -1943,7 +1946,8 @@ int robust_plan(agis_ctx* ctx, const std::vector<int64_t>& h_off, const std::vec
         }
         ctx->eps_cap = std::max<int64_t>(mx, 1);
         if ((int64_t)eps_lds_bytes(ctx->eps_cap, ctx->cfg.eps_bucket) <= dyn_max) {
-            HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eps_fused<EPS_NT>),
+            HIPCHK(hipFuncSetAttribute(ctx->k.defl > 0.0 ? reinterpret_cast<const void*>(&k_eps_fused<EPS_NT, true>)
+                                                         : reinterpret_cast<const void*>(&k_eps_fused<EPS_NT, false>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)eps_lds_bytes(ctx->eps_cap, ctx->cfg.eps_bucket)));
             ctx->eps_fused = true;
@@ -1971,13 +1975,15 @@ void launch_freeze_sigma(agis_ctx* ctx) {
 void launch_excess_noise(agis_ctx* ctx) {
     if (ctx->K == 0 || ctx->n_buckets == 0) return;
     if (eps_one_kernel(ctx) && ctx->eps_fused) {
-        k_eps_fused<EPS_NT><<<(unsigned)ctx->n_buckets, EPS_NT, eps_lds_bytes(ctx->eps_cap, ctx->cfg.eps_bucket), ctx->stream>>>(
+        (ctx->k.defl > 0.0 ? k_eps_fused<EPS_NT, true> : k_eps_fused<EPS_NT, false>)
+            <<<(unsigned)ctx->n_buckets, EPS_NT, eps_lds_bytes(ctx->eps_cap, ctx->cfg.eps_bucket), ctx->stream>>>(
             ctx->k, ctx->n_buckets, ctx->K, ctx->cfg.eps_bucket, (int)ctx->eps_cap, ctx->iv_off, ctx->t_t, ctx->t_eta, ctx->t_sig,
             ctx->t_cellfov, ctx->t_src, ctx->prep, ctx->knots, ctx->ktab, ctx->a, ctx->c, ctx->cfg.robust,
             ctx->eps_a2);
         return;
     }
-    k_ac_resid<<<(unsigned)ctx->K, 64, 0, ctx->stream>>>(ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, ctx->t_sig,
+    (ctx->k.defl > 0.0 ? k_ac_resid<true> : k_ac_resid<false>)<<<(unsigned)ctx->K, 64, 0, ctx->stream>>>(
+                                                         ctx->k, ctx->K, ctx->iv_off, ctx->t_t, ctx->t_eta, ctx->t_sig,
                                                          ctx->t_cellfov, ctx->t_src, ctx->prep, ctx->knots, ctx->ktab,
                                                          ctx->a, ctx->c, ctx->cfg.robust, ctx->rcol);
     const int32_t* cellfov = ctx->has_ac ? ctx->t_cellfov : nullptr;
