@@ -35,7 +35,7 @@ def _structs(c_r):
                     ("lambda_reg", c_r), ("seg_len", c_i32), ("seg_overlap", c_i32), ("eph_radius_au", c_r),
                     ("eph_L0", c_r), ("eph_Lrate", c_r), ("eps_obl", c_r), ("au_m", c_r), ("c_mps", c_r),
                     ("year_s", c_r), ("robust", c_i32), ("eps_bucket", c_i32), ("geo_ccds", c_i32),
-                    ("geo_ac_cells", c_i32), ("defl", c_r), ("ppn", c_i32)]
+                    ("geo_ac_cells", c_i32), ("defl", c_r), ("ppn", c_i32), ("geo_small_days", c_i32)]
 
     class Obs(ctypes.Structure):
         _fields_ = [("n", c_i64), ("t", P(c_r)), ("eta_obs", P(c_r)), ("sigma", P(c_f)), ("src", P(c_i32)),
@@ -265,7 +265,8 @@ class Problem:
         # geometric calibration (consts geo_ccds > 0): CCD index and AC pixel
         # coordinate per record, coefficients [n_cells][geo_ccds][3]; with
         # ac_cell (the across-scan records' calibration cells) the AC term
-        # too, its coefficients after the AL ones
+        # too, its coefficients after the AL ones; with consts geo_small_days
+        # the small-scale AL term, [K][geo_ccds][1966] coefficients last
         geo_ccds = int(consts.get("geo_ccds", 0) or 0)
         if geo_ccds > 0:
             self.ccd = np.ascontiguousarray(ccd, dtype=np.int8)
@@ -273,7 +274,9 @@ class Problem:
             self.ac_cell = None if ac_cell is None else np.ascontiguousarray(ac_cell, dtype=np.int32)
             self.geo = self._arr(np.reshape(geo, -1)).copy()
             n_ac = 0 if ac_cell is None else int(consts.get("geo_ac_cells", 0) or 0)
-            assert self.geo.size == (np.size(c) + n_ac) * geo_ccds * 3
+            sd = int(consts.get("geo_small_days", 0) or 0)
+            n_k = (np.size(c) // 2 + sd - 1) // sd if sd > 0 else 0
+            assert self.geo.size == (np.size(c) + n_ac) * geo_ccds * 3 + n_k * geo_ccds * 1966
         else:
             self.ccd = self.mu = self.geo = self.ac_cell = None
         self.src = np.ascontiguousarray(src, dtype=np.int32)
@@ -292,7 +295,8 @@ class Problem:
                                  c_mps=consts["c_mps"], year_s=consts["year_s"],
                                  robust=int(consts.get("robust", 0)), eps_bucket=int(consts.get("eps_bucket", 8)),
                                  geo_ccds=geo_ccds, geo_ac_cells=int(consts.get("geo_ac_cells", 0) or 0),
-                                 defl=float(consts.get("defl", 0.0) or 0.0), ppn=int(consts.get("ppn", 0) or 0))
+                                 defl=float(consts.get("defl", 0.0) or 0.0), ppn=int(consts.get("ppn", 0) or 0),
+                                 geo_small_days=int(consts.get("geo_small_days", 0) or 0) if geo_ccds > 0 else 0)
         n_iv = self.knots.size - 7
         if self.world.robust:
             # three components (along scan, across scan preceding and
@@ -487,13 +491,14 @@ def problem_from_world(world, eta_obs=None, state="start", precision="double"):
 
 
 def world_geo(world, which="true"):
-    """The world's geometric coefficients (true or start), AL then AC; None
-    without the geometric model."""
+    """The world's geometric coefficients (true or start): AL, then AC and
+    small-scale where the world has them; None without the geometric model."""
     g = getattr(world, f"geo_{which}", None)
     if g is None:
         return None
-    ga = getattr(world, f"geo_ac_{which}", None)
-    return np.reshape(g, -1) if ga is None else np.concatenate([np.reshape(g, -1), np.reshape(ga, -1)])
+    parts = [g] + [x for x in (getattr(world, f"geo_ac_{which}", None), getattr(world, f"geo_small_{which}", None))
+                   if x is not None]
+    return np.concatenate([np.reshape(x, -1) for x in parts])
 
 
 def observed_field_angles(world, chunk=1 << 24):

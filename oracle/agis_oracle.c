@@ -302,9 +302,42 @@ static int64_t geo_index(const orc_world_t* w, const orc_obs_t* obs, const orc_s
  * mapped to [0, 1] (eq:etazeta). */
 static double geo_x(const orc_obs_t* obs, int64_t l) { return ((double)obs->mu[l] - 13.5) / 1966.0; }
 
-/* The large-scale geometric calibration of a record (eq:etazeta): sum over
- * r of its group's coefficients times L*_r(x); 0 without the geometric
- * model, or across scan without the AC calibration. */
+/* Pixel columns of the small-scale AL term (eq:etazeta): m = 14 .. 1979. */
+#define GEO_COLS 1966
+
+/* Number of long intervals k of the small-scale AL term: the days of the
+ * cells (two cells a day) in runs of geo_small_days; 0 without the term. */
+static int64_t small_intervals(const orc_world_t* w, const orc_state_t* st) {
+    if (w->geo_ccds <= 0 || w->geo_small_days <= 0) return 0;
+    return (st->n_cells / 2 + w->geo_small_days - 1) / w->geo_small_days;
+}
+
+/* First small-scale coefficient: after the AL groups and, with ac_cell,
+ * the AC groups. */
+static int64_t small_base(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st) {
+    return (st->n_cells + (obs->ac_cell ? (int64_t)w->geo_ac_cells : 0)) * w->geo_ccds * 3;
+}
+
+/* The nearest pixel column m = round(mu) of eq:etazeta as 0 .. 1965 (a
+ * coordinate of exactly 1979.5 stays on the last column). */
+static int64_t geo_column(const orc_obs_t* obs, int64_t l) {
+    int64_t m = (int64_t)floor((double)obs->mu[l] + 0.5);
+    if (m > 1979) m = 1979;
+    return m - 14;
+}
+
+/* Index of an along-scan record's small-scale coefficient (its long
+ * interval, CCD and column), or -1 (across scan, or no small-scale term). */
+static int64_t small_index(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, int64_t l) {
+    if (small_intervals(w, st) == 0 || obs->cell[l] < 0) return -1;
+    const int64_t k = (obs->cell[l] / 2) / w->geo_small_days;
+    return small_base(w, obs, st) + (k * w->geo_ccds + obs->ccd[l]) * GEO_COLS + geo_column(obs, l);
+}
+
+/* The geometric calibration of a record (eq:etazeta): sum over r of its
+ * group's coefficients times L*_r(x), plus along scan the small-scale
+ * coefficient of its column when the world has that term; 0 without the
+ * geometric model, or across scan without the AC calibration. */
 static double geo_term(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, int64_t l) {
     if (w->geo_ccds <= 0) return 0.0;
     const int64_t g = geo_index(w, obs, st, l);
@@ -312,6 +345,8 @@ static double geo_term(const orc_world_t* w, const orc_obs_t* obs, const orc_sta
     const double x = geo_x(obs, l);
     double v = 0.0;
     for (int r = 0; r < 3; ++r) v += st->geo[g + r] * shifted_legendre(r, x);
+    const int64_t q = small_index(w, obs, st, l);
+    if (q >= 0) v += st->geo[q];
     return v;
 }
 
@@ -913,7 +948,108 @@ int64_t orc_attitude_update(const orc_world_t* w, const orc_obs_t* obs, orc_stat
  * model three per cell and CCD, twice that with the AC calibration. */
 static int64_t cal_size(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st) {
     if (w->geo_ccds <= 0) return st->n_cells;
-    return (st->n_cells + (obs->ac_cell ? (int64_t)w->geo_ac_cells : 0)) * w->geo_ccds * 3;
+    return small_base(w, obs, st) + small_intervals(w, st) * w->geo_ccds * GEO_COLS;
+}
+
+/* Solves A x = b (n x n, row-major, overwritten) by Gaussian elimination
+ * with partial pivoting (the largest remaining entry of the column; the
+ * first of equal ones), then back substitution.  Entries that are exactly
+ * zero take no part in a row operation (they would leave it unchanged). */
+static void solve_gauss_pp(double* A, double* b, int64_t n, double* x) {
+    int64_t* cols = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t p = k;
+        for (int64_t i = k + 1; i < n; ++i)
+            if (fabs(A[i * n + k]) > fabs(A[p * n + k])) p = i;
+        if (p != k) {
+            for (int64_t j = 0; j < n; ++j) {
+                const double t = A[k * n + j];
+                A[k * n + j] = A[p * n + j];
+                A[p * n + j] = t;
+            }
+            const double t = b[k];
+            b[k] = b[p];
+            b[p] = t;
+        }
+        int64_t nz = 0;
+        for (int64_t j = k + 1; j < n; ++j)
+            if (A[k * n + j] != 0.0) cols[nz++] = j;
+        for (int64_t i = k + 1; i < n; ++i) {
+            if (A[i * n + k] == 0.0) continue;
+            const double f = A[i * n + k] / A[k * n + k];
+            for (int64_t t = 0; t < nz; ++t) A[i * n + cols[t]] -= f * A[k * n + cols[t]];
+            b[i] -= f * b[k];
+            A[i * n + k] = 0.0;
+        }
+    }
+    for (int64_t i = n - 1; i >= 0; --i) {
+        double s = b[i];
+        for (int64_t j = i + 1; j < n; ++j) s -= A[i * n + j] * x[j];
+        x[i] = s / A[i * n + i];
+    }
+    free(cols);
+}
+
+/* The C update of one CCD n and long interval k with the small-scale term:
+ * the unknowns are the small-scale coefficients of the 1966 columns
+ * (dR/d delta-eta = 1) and the large-scale AL coefficients of the interval's
+ * cells of that CCD (dR/dc_r = L*_r(x)), which share records and, through
+ * the constant (exactly) and the two other polynomials (up to the rounding
+ * of mu to m), an almost degenerate direction.  eq:normC over the interval's
+ * AL records of that CCD, with the A/C weights, is solved subject to the
+ * three constraints of eq:cc2 (sum over m of the update times L*_r at the
+ * column centre, r = 0, 1, 2) by the Lagrange (KKT) system
+ *     [N  C] [d ]   [b]
+ *     [C' 0] [nu] = [0],
+ * the constrained least-squares update.  An unknown without records (a
+ * column or cell that no record of the block reaches) is held at zero.
+ * Unknown order: the columns, the cells' coefficients, the multipliers.
+ * R and W: each record's residual and weight, from the caller. */
+static void small_block_solve(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, int64_t k,
+                              int32_t n, const double* R, const double* W, double* d) {
+    const int64_t D = w->geo_small_days;
+    const int64_t c0 = 2 * k * D, c1 = (2 * (k + 1) * D < st->n_cells) ? 2 * (k + 1) * D : st->n_cells;
+    const int64_t nc = c1 - c0, ne = 3 * nc, nu = GEO_COLS + ne, nk = nu + 3;
+    double* A = (double*)calloc((size_t)(nk * nk), sizeof(double));
+    double* b = (double*)calloc((size_t)nk, sizeof(double));
+    double* x = (double*)calloc((size_t)nk, sizeof(double));
+    int64_t* cnt = (int64_t*)calloc((size_t)nu, sizeof(int64_t));
+    for (int64_t l = 0; l < obs->n; ++l) {
+        if (obs->cell[l] < c0 || obs->cell[l] >= c1 || obs->ccd[l] != n) continue;
+        const double xl = geo_x(obs, l);
+        int64_t idx[4];
+        double p[4];
+        idx[0] = geo_column(obs, l);
+        p[0] = 1.0;
+        for (int r = 0; r < 3; ++r) {
+            idx[1 + r] = GEO_COLS + 3 * (obs->cell[l] - c0) + r;
+            p[1 + r] = shifted_legendre(r, xl);
+        }
+        for (int a = 0; a < 4; ++a) {
+            for (int e = 0; e < 4; ++e) A[idx[a] * nk + idx[e]] += p[a] * W[l] * p[e];
+            b[idx[a]] -= p[a] * R[l] * W[l];
+            cnt[idx[a]] += 1;
+        }
+    }
+    for (int64_t m = 0; m < GEO_COLS; ++m) {
+        if (cnt[m] == 0) continue;
+        const double xm = ((double)(m + 14) - 13.5) / 1966.0;
+        for (int r = 0; r < 3; ++r) {
+            A[(nu + r) * nk + m] = shifted_legendre(r, xm);
+            A[m * nk + nu + r] = shifted_legendre(r, xm);
+        }
+    }
+    for (int64_t i = 0; i < nu; ++i)
+        if (cnt[i] == 0) A[i * nk + i] = 1.0;        /* held at zero: b_i = 0 */
+    solve_gauss_pp(A, b, nk, x);
+    const int64_t q0 = small_base(w, obs, st) + (k * w->geo_ccds + n) * GEO_COLS;
+    for (int64_t m = 0; m < GEO_COLS; ++m) d[q0 + m] = x[m];
+    for (int64_t c = c0; c < c1; ++c)
+        for (int r = 0; r < 3; ++r) d[3 * (c * w->geo_ccds + n) + r] = x[GEO_COLS + 3 * (c - c0) + r];
+    free(A);
+    free(b);
+    free(x);
+    free(cnt);
 }
 
 /* Geometric calibration (Sect. 5.3 with eq:etazeta): eq:normC for each
@@ -924,10 +1060,16 @@ static int64_t cal_size(const orc_world_t* w, const orc_obs_t* obs, const orc_st
  * zero) and, with the AC calibration, eq:cc3 (for each AC cell, i.e. field
  * of view and long interval, the AC constant terms of its CCDs sum to zero); the
  * constraint columns do not overlap, so each projection subtracts the mean
- * constant term of its set. */
+ * constant term of its set.  With the small-scale AL term the AL groups of a
+ * CCD and long interval share records with its small-scale coefficients, and
+ * each such block is solved together under eq:cc2 (small_block_solve)
+ * before the eq:cc1 projection. */
 static void calibration_solve_geo(const orc_world_t* w, const orc_obs_t* obs, const orc_state_t* st, double* d) {
     const int64_t ng_al = st->n_cells * w->geo_ccds;
-    const int64_t ng = cal_size(w, obs, st) / 3;
+    const int64_t ng = small_base(w, obs, st) / 3;
+    const int64_t K = small_intervals(w, st);
+    double* Rl = K > 0 ? (double*)calloc((size_t)(obs->n > 0 ? obs->n : 1), sizeof(double)) : NULL;
+    double* Wl = K > 0 ? (double*)calloc((size_t)(obs->n > 0 ? obs->n : 1), sizeof(double)) : NULL;
     double* N = (double*)calloc((size_t)(9 * ng), sizeof(double));
     double* b = (double*)calloc((size_t)(3 * ng), sizeof(double));
     for (int64_t l = 0; l < obs->n; ++l) {
@@ -936,6 +1078,10 @@ static void calibration_solve_geo(const orc_world_t* w, const orc_obs_t* obs, co
         orc_fwd_t o;
         forward_one(w, obs, st, l, &o);
         double W = weight(w, obs, st, l, &o);
+        if (K > 0) {
+            Rl[l] = o.R;
+            Wl[l] = W;
+        }
         const int64_t g = g3 / 3;
         const double x = geo_x(obs, l);
         double L[3];
@@ -945,7 +1091,7 @@ static void calibration_solve_geo(const orc_world_t* w, const orc_obs_t* obs, co
             b[3 * g + r] -= L[r] * o.R * W;
         }
     }
-    for (int64_t g = 0; g < ng; ++g) {
+    for (int64_t g = (K > 0 ? ng_al : 0); g < ng; ++g) {     /* AL groups: below, with the small scale */
         double U[9], x[3];
         memcpy(U, N + 9 * g, sizeof U);
         memcpy(x, b + 3 * g, sizeof x);
@@ -954,6 +1100,12 @@ static void calibration_solve_geo(const orc_world_t* w, const orc_obs_t* obs, co
         orc_chol_c3(U, 3, x);
         memcpy(d + 3 * g, x, sizeof x);
     }
+    /* with the small-scale term, the AL groups and the small-scale
+     * coefficients by CCD and long interval (eq:cc2 inside) */
+    for (int64_t k = 0; k < K; ++k)
+        for (int32_t n = 0; n < w->geo_ccds; ++n) small_block_solve(w, obs, st, k, n, Rl, Wl, d);
+    free(Rl);
+    free(Wl);
     /* eq:calCon for eq:cc1: C has one column per day, with ones at the
      * constant terms of the day's 2 geo_ccds groups; C'C = 2 geo_ccds I */
     const int64_t per_day = 2 * w->geo_ccds;

@@ -47,6 +47,10 @@ typedef struct {
     double defl;              /* 0: no light deflection; else GM_sun / (c^2 AU) [rad AU]: the Sun's
                                  gravitational light deflection with gamma = 1 + g0 (eq:gammaPPN) */
     int32_t ppn;              /* 1: the global block solves g0 (eq:normG) in each iteration */
+    int32_t geo_small_days;   /* with the geometric calibration, 0 or the days of a long interval k
+                                 of the small-scale AL term delta-eta of eq:etazeta: one value per
+                                 CCD, long interval and pixel column m = round(mu) (1966), under
+                                 eq:cc2 */
 } orc_world_t;
 
 typedef struct {
@@ -80,7 +84,9 @@ typedef struct {
     double* src_D;            /* [n_src] its significance D of eq:D (robust 2; may be NULL) */
     double* geo;              /* [n_cells][geo_ccds][3] geometric calibration coefficients
                                  (eq:etazeta, r = 0, 1, 2) [rad], followed with ac_cell by the
-                                 AC ones [geo_ac_cells][geo_ccds][3]; NULL when geo_ccds = 0 */
+                                 AC ones [geo_ac_cells][geo_ccds][3], then with geo_small_days the
+                                 small-scale ones [K][geo_ccds][1966], K = ceil(n_cells / 2 /
+                                 geo_small_days); NULL when geo_ccds = 0 */
     double g0;                /* global parameter of eq:gammaPPN: gamma = 1 + g0 */
 } orc_state_t;
 
@@ -153,7 +159,7 @@ int64_t orc_num_segments(const orc_world_t* w);
 /* C block; d[n_cells] receives the applied update (may be NULL). */
 /* d (may be NULL) receives the update: [n_cells], or with the geometric
  * calibration [n_cells][geo_ccds][3] (followed by the AC groups' with
- * ac_cell). */
+ * ac_cell, then the small-scale coefficients with geo_small_days). */
 void orc_calibration_update(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st, double* d);
 /* S[AC]: S, then A and C from the same post-S residuals. */
 void orc_iterate_sac(const orc_world_t* w, const orc_obs_t* obs, orc_state_t* st, double* var);

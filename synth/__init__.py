@@ -129,6 +129,13 @@ class WorldSpec:
     # uniformly, at that line's time
     geo_ac: bool = False
     geo_ac_days: int = 30
+    # with geo_cal: the small-scale AL calibration too, one value per CCD,
+    # long interval of geo_small_days days and pixel column m = round(mu);
+    # true values N(0, geo_small_sd) less their least-squares quadratic in
+    # the column centre (eq:cc2) per CCD and interval, start values zero
+    geo_small: bool = False
+    geo_small_days: int = 30
+    geo_small_sd: float = 0.2 * MAS
     # the Sun's gravitational light deflection in the model, with the PPN
     # parameter gamma = 1 + g0 (eq:gammaPPN) solved by the global block:
     # true g0 = 0 (general relativity), start value g0_start
@@ -166,6 +173,9 @@ class World:
     ac_cell: np.ndarray | None = None
     geo_ac_true: np.ndarray | None = None
     geo_ac_start: np.ndarray | None = None
+    # geo_small worlds: the small-scale coefficients [K][n_ccd][1966]
+    geo_small_true: np.ndarray | None = None
+    geo_small_start: np.ndarray | None = None
     # the global parameter g0 (true and start values)
     g0_true: float = 0.0
     g0_start: float = 0.0
@@ -479,6 +489,15 @@ def make_world(spec: WorldSpec, law: dict | None = None, progress=None) -> World
                                                                                          (n_ac_cells, nc, 3))
         for g in (geo_ac_true, geo_ac_start):
             g[:, :, 0] -= g[:, :, 0].mean(axis=1)[:, None]          # eq:cc3 per cell
+    geo_small_true = geo_small_start = None
+    if spec.geo_cal and spec.geo_small:
+        n_k = (n_days + spec.geo_small_days - 1) // spec.geo_small_days
+        xm = (np.arange(14, 1980) - 13.5) / 1966.0
+        Lm = np.stack([np.ones_like(xm), 2.0 * xm - 1.0, 6.0 * xm * xm - 6.0 * xm + 1.0], axis=1)
+        v = np.random.default_rng([spec.seed_truth, 11]).normal(0.0, spec.geo_small_sd, (n_k, nc, 1966))
+        coef = np.linalg.lstsq(Lm, v.reshape(-1, 1966).T, rcond=None)[0]
+        geo_small_true = v - (Lm @ coef).T.reshape(n_k, nc, 1966)
+        geo_small_start = np.zeros_like(geo_small_true)
 
     consts = dict(
         gamma_c=law["gamma"], t_ep=0.0, t_fr=0.0, lambda_reg=spec.lambda_reg,
@@ -487,6 +506,7 @@ def make_world(spec: WorldSpec, law: dict | None = None, progress=None) -> World
         au_m=AU_M, c_mps=C_MPS, year_s=YEAR, t_beg=t_beg, t_end=t_end, law=law,
         robust=int(spec.robust), eps_bucket=spec.eps_bucket, eps_a_init=spec.eps_a_init,
         geo_ccds=nc if spec.geo_cal else 0, geo_ac_cells=int(n_ac_cells),
+        geo_small_days=spec.geo_small_days if spec.geo_cal and spec.geo_small else 0,
         defl=GM_SUN / (C_MPS ** 2 * AU_M) if spec.ppn else 0.0, ppn=int(spec.ppn))
     return World(spec=spec, consts=consts, knots=knots, src_true=src_true, att_true=att_true,
                  cal_true=cal_true, src_start=src_start, att_start=att_start, cal_start=cal_start,
@@ -497,4 +517,5 @@ def make_world(spec: WorldSpec, law: dict | None = None, progress=None) -> World
                  ccd=None if ccd is None else np.ascontiguousarray(ccd),
                  mu=None if mu is None else np.ascontiguousarray(mu), geo_true=geo_true, geo_start=geo_start,
                  ac_cell=None if ac_cell is None else np.ascontiguousarray(ac_cell), geo_ac_true=geo_ac_true,
-                 geo_ac_start=geo_ac_start, g0_true=0.0, g0_start=float(spec.g0_start) if spec.ppn else 0.0)
+                 geo_ac_start=geo_ac_start, geo_small_true=geo_small_true, geo_small_start=geo_small_start,
+                 g0_true=0.0, g0_start=float(spec.g0_start) if spec.ppn else 0.0)

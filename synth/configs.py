@@ -41,6 +41,11 @@ WORKLOADS = {
                                   seg_len=240, seg_overlap=12, lambda_reg=1e-2, min_transits=6)),
     "small9": (mini_law, WorldSpec(n_src=3000, years=0.5, knot_dt=1200.0, ccd_per_transit=9,
                                    seg_len=100, seg_overlap=12, lambda_reg=1e-2)),
+    # the small-scale geometric calibration needs many records per pixel
+    # column: 20 000 stars over 60 days (two 30-day long intervals), 9 AF
+    # observations per transit (~15 records per column, CCD and interval)
+    "geo9": (mini_law, WorldSpec(n_src=20000, years=60.0 / 365.25, knot_dt=1200.0, ccd_per_transit=9,
+                                 seg_len=100, seg_overlap=12, lambda_reg=1e-2, geo_cal=True)),
     # 1M stars, 1 yr, 9 AF observations per transit (~160M obs), 30 s knots;
     # segments of 130 intervals: 8,092 band systems, four per wavefront, all
     # resident on the chip at once
