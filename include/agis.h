@@ -218,7 +218,16 @@ int agis_get_calibration(agis_ctx_t* ctx, int64_t n, double* c, int where);
  * block solves each group's 3x3 normal equations (eq:normC with eq:pdC) by
  * the modified Cholesky and applies eq:calCon for eq:cc1 (the AL constant
  * terms of a day's two cells and all CCDs sum to zero) and eq:cc3 (the AC
- * constant terms of an AC cell's CCDs sum to zero).
+ * constant terms of an AC cell's CCDs sum to zero).  Optionally the
+ * small-scale AL term delta-eta too: with small_days > 0 (at most 30) one
+ * value per CCD, long interval k (runs of small_days days from the first
+ * cell's day) and pixel column m = round(mu) in 14..1979, added to an
+ * along-scan record's model value.  It shares the records of the AL groups
+ * of its CCD and interval, which makes them one block: eq:normC over the
+ * block's AL groups and 1966 values is solved exactly under eq:cc2 (for r =
+ * 0, 1, 2 the update's values times L*_r((m - 13.5) / 1966) sum to zero),
+ * the constrained least-squares update; a column or cell without records
+ * keeps a zero update; then eq:cc1 as above.
  *
  * agis_load_geometry enables it after agis_load_observations: ccd [n] the
  * CCD index in [0, n_ccd) and mu [n] the pixel coordinate in [13.5, 1979.5]
@@ -226,17 +235,22 @@ int agis_get_calibration(agis_ctx_t* ctx, int64_t n, double* c, int where);
  * count); ac_cell [n] (NULL, or with n_ac_cells > 0) each across-scan
  * record's AC cell in [0, n_ac_cells) (along-scan records' values are
  * ignored, and so are across-scan records' ccd and mu without ac_cell);
- * host or device memory by `where`; the coefficients start at zero and the
+ * host or device memory by `where`; small_days: 0, or the long interval of
+ * the small-scale term [days]; the coefficients start at zero and the
  * cell offsets are held at zero.  agis_set/get_geo_calibration: n = 3
- * (n_cells + n_ac_cells) n_ccd coefficients, [n_cells][n_ccd][3] AL then
- * [n_ac_cells][n_ccd][3] AC [rad].  AGIS_E_SHAPE on a count mismatch,
- * AGIS_E_INVALID_ARG on an index, cell or coordinate out of range,
+ * (n_cells + n_ac_cells) n_ccd + K n_ccd 1966 values, [n_cells][n_ccd][3] AL,
+ * [n_ac_cells][n_ccd][3] AC, then [K][n_ccd][1966] small-scale with K =
+ * ceil(n_cells / 2 / small_days) (0 without it) [rad].  AGIS_E_SHAPE on a
+ * count mismatch, AGIS_E_INVALID_ARG on an index, cell or coordinate out of
+ * range, on small_days < 0 or above 30, or on 2^21 or more groups with it,
  * AGIS_E_STATE for the geometry in robust mode 2, for agis_set_calibration
  * while it is on, and for conjugate gradients and the recorded-update
  * schemes (agis_learned_*, agis_asi_step), which carry the cell offsets
- * only.  Loading observations again turns it off; so does a rejected
- * agis_load_geometry (the context then uses the cell offsets, which are
- * zero if the model had been on).
+ * only.  Loading observations again turns it off; so does an
+ * agis_load_geometry rejected for a record's index, cell or coordinate (the
+ * context then uses the cell offsets, which are zero if the model had been
+ * on); a call refused for its arguments (n_ccd, n_ac_cells, small_days, the
+ * group count) changes nothing.
  */
 /*
  * Global block (Sect. 5.4, eq:normG) with the PPN parameter gamma = 1 + g0
@@ -262,7 +276,7 @@ int agis_set_global(agis_ctx_t* ctx, double g0);
 int agis_get_global(agis_ctx_t* ctx, double out[3]);
 
 int agis_load_geometry(agis_ctx_t* ctx, int64_t n, const int8_t* ccd, const float* mu, int32_t n_ccd,
-                       const int32_t* ac_cell, int32_t n_ac_cells, int where);
+                       const int32_t* ac_cell, int32_t n_ac_cells, int32_t small_days, int where);
 int agis_set_geo_calibration(agis_ctx_t* ctx, int64_t n, const double* c, int where);
 int agis_get_geo_calibration(agis_ctx_t* ctx, int64_t n, double* c, int where);
 

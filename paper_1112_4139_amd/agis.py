@@ -79,7 +79,7 @@ _sig = {
     "agis_get_attitude": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
     "agis_set_calibration": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
     "agis_get_calibration": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
-    "agis_load_geometry": ([_ctx_p, c_i64, _vp, _vp, c_i32, _vp, c_i32, ctypes.c_int], ctypes.c_int),
+    "agis_load_geometry": ([_ctx_p, c_i64, _vp, _vp, c_i32, _vp, c_i32, c_i32, ctypes.c_int], ctypes.c_int),
     "agis_global_update": ([_ctx_p, P(c_d)], ctypes.c_int),
     "agis_set_global": ([_ctx_p, c_d], ctypes.c_int),
     "agis_get_global": ([_ctx_p, P(c_d)], ctypes.c_int),
@@ -237,17 +237,19 @@ def agis_get_calibration(ctx, n, out=None):
     return _get(_lib.agis_get_calibration, ctx, n, 1, out)
 
 
-def agis_load_geometry(ctx, ccd, mu, n_ccd, ac_cell=None, n_ac_cells=0):
+def agis_load_geometry(ctx, ccd, mu, n_ccd, ac_cell=None, n_ac_cells=0, small_days=0):
     """Enable the geometric calibration: CCD index (int8) and across-scan
     pixel coordinate (float32) of every record, in input order; with
     ac_cell (int32, each across-scan record's AC cell) and n_ac_cells the
-    across-scan term too."""
+    across-scan term too; with small_days > 0 the small-scale AL term per
+    CCD, long interval of that many days and pixel column."""
     pc, wc, kc = _ptr(ccd, np.int8)
     pm, wm, km = _ptr(mu, np.float32)
     pa, wa, ka = (None, wc, None) if ac_cell is None else _ptr(ac_cell, np.int32)
     if wc != wm or wa != wc:
         raise ValueError("ccd, mu and ac_cell must all be host arrays or all device tensors")
-    _check(_lib.agis_load_geometry(ctx, int(len(ccd)), pc, pm, int(n_ccd), pa, int(n_ac_cells), wc), ctx)
+    _check(_lib.agis_load_geometry(ctx, int(len(ccd)), pc, pm, int(n_ccd), pa, int(n_ac_cells), int(small_days), wc),
+           ctx)
 
 
 def agis_global_update(ctx):

@@ -127,6 +127,13 @@ struct agis_ctx {
     int64_t* geo_off = nullptr;          // [n_groups + 1] group ranges of the group order
     float* geo_mu_g = nullptr;           // group order: across-scan pixel coordinate
     int* geo_flags = nullptr;
+    // small-scale AL term (eq:cc2): days of a long interval (0: none), its
+    // values [K][geo_ccds][1966] after the groups' coefficients in geo and dgeo
+    int32_t geo_small_days = 0;
+    int64_t n_small = 0;
+    int32_t* geo_coff = nullptr;         // [n_cells geo_ccds][1967] column ranges of the AL groups
+    double* geo_colsum = nullptr;        // [n_cells geo_ccds][1966][4] column sums of the last C update
+    double* geo_dcol = nullptr;          // [K geo_ccds][1966][2] block diagonal and right-hand side
     int32_t* seg_def = nullptr;          // [n_seg]
     std::vector<agis::SegDesc> h_segs;
     agis::SegDesc* segs = nullptr;
@@ -282,7 +289,7 @@ void launch_band_solve(agis_ctx* ctx);
 void launch_calib_solve(agis_ctx* ctx, double* rc = nullptr);   // rc: optional right-hand sides
 // geo.hip
 int load_geometry(agis_ctx* ctx, const int8_t* ccd, const float* mu, int32_t n_ccd, const int32_t* ac_cell,
-                  int32_t n_ac_cells, int where);
+                  int32_t n_ac_cells, int32_t small_days, int where);
 void launch_geo_eta(agis_ctx* ctx);
 void launch_geo_solve(agis_ctx* ctx);
 void launch_apply_attitude(agis_ctx* ctx);

@@ -119,8 +119,13 @@ static void free_store(agis_ctx* ctx) {
     dfree(ctx->geo_pos);
     dfree(ctx->geo_off);
     dfree(ctx->geo_mu_g);
+    dfree(ctx->geo_coff);
+    dfree(ctx->geo_colsum);
+    dfree(ctx->geo_dcol);
     ctx->geo_ccds = 0;
     ctx->geo_ac_cells = 0;
+    ctx->geo_small_days = 0;
+    ctx->n_small = 0;
     ctx->n_groups = 0;
     dfree(ctx->iv_off);
     dfree(ctx->iv_cell);
@@ -621,7 +626,7 @@ extern "C" int agis_set_calibration(agis_ctx_t* ctx, int64_t n, const double* c,
 }
 
 extern "C" int agis_load_geometry(agis_ctx_t* ctx, int64_t n, const int8_t* ccd, const float* mu, int32_t n_ccd,
-                                  const int32_t* ac_cell, int32_t n_ac_cells, int where) {
+                                  const int32_t* ac_cell, int32_t n_ac_cells, int32_t small_days, int where) {
     CHECK_CTX();
     ++ctx->xver;
     REQUIRE_LOADED();
@@ -631,7 +636,8 @@ extern "C" int agis_load_geometry(agis_ctx_t* ctx, int64_t n, const int8_t* ccd,
     if (n_ac_cells < 0 || (n_ac_cells > 0 && !ac_cell && n > 0))
         return set_error(ctx, AGIS_E_INVALID_ARG, "n_ac_cells < 0, or AC cells counted but not given");
     if (ctx->cfg.robust == 2) return set_error(ctx, AGIS_E_STATE, "the geometric calibration with robust mode 2");
-    const int rc = load_geometry(ctx, ccd, mu, n_ccd, ac_cell, n_ac_cells, where);
+    if (small_days < 0) return set_error(ctx, AGIS_E_INVALID_ARG, "small_days < 0");
+    const int rc = load_geometry(ctx, ccd, mu, n_ccd, ac_cell, n_ac_cells, small_days, where);
     ++ctx->gen;                          // the captured iteration gains the geometric kernels
     return rc;
 }
@@ -641,7 +647,8 @@ extern "C" int agis_set_geo_calibration(agis_ctx_t* ctx, int64_t n, const double
     ++ctx->xver;
     REQUIRE_LOADED();
     if (ctx->geo_ccds <= 0) return set_error(ctx, AGIS_E_STATE, "agis_load_geometry first");
-    if (n != 3 * ctx->n_groups || (!c && n > 0)) return set_error(ctx, AGIS_E_SHAPE, "coefficient count mismatch");
+    if (n != 3 * ctx->n_groups + ctx->n_small || (!c && n > 0))
+        return set_error(ctx, AGIS_E_SHAPE, "coefficient count mismatch");
     int rc = check_finite_host(ctx, c, n, where);
     if (rc) return rc;
     if ((rc = copy_in(ctx, ctx->geo, c, n * sizeof(double), where))) return rc;
@@ -655,7 +662,8 @@ extern "C" int agis_get_geo_calibration(agis_ctx_t* ctx, int64_t n, double* c, i
     CHECK_CTX();
     REQUIRE_LOADED();
     if (ctx->geo_ccds <= 0) return set_error(ctx, AGIS_E_STATE, "agis_load_geometry first");
-    if (n != 3 * ctx->n_groups || (!c && n > 0)) return set_error(ctx, AGIS_E_SHAPE, "coefficient count mismatch");
+    if (n != 3 * ctx->n_groups + ctx->n_small || (!c && n > 0))
+        return set_error(ctx, AGIS_E_SHAPE, "coefficient count mismatch");
     return copy_out(ctx, c, ctx->geo, n * sizeof(double), where);
 }
 
@@ -750,7 +758,7 @@ static int run_ac(agis_ctx* ctx, bool do_a, bool do_c, bool eps_update = false, 
     if (do_a && apply) launch_apply_attitude(ctx);
     if (do_c && apply) {
         if (ctx->geo_ccds > 0) {
-            launch_apply_add(ctx, 3 * ctx->n_groups, ctx->geo, ctx->dgeo);
+            launch_apply_add(ctx, 3 * ctx->n_groups + ctx->n_small, ctx->geo, ctx->dgeo);
             launch_geo_eta(ctx);
         } else {
             launch_apply_calibration(ctx);

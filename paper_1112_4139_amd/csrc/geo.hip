@@ -21,6 +21,19 @@
 // constant terms of a day's two cells and all CCDs sum to zero) or eq:cc3
 // (the AC constant terms of an AC cell's CCDs sum to zero): their mean is
 // removed.
+//
+// The small-scale AL term (eq:etazeta's delta-eta with eq:cc2) adds one
+// value per CCD, long interval k (a run of `days` days) and pixel column
+// m = round(mu), 1966 a block.  It shares every record with the AL groups
+// of its CCD and interval, so a block (CCD, interval) is solved as one
+// system: the along-scan groups' records are ordered by column within a
+// group as well; one thread per group and column sums W, W L_1, W L_2 and
+// -W R over its records; one thread per block and column adds the block's
+// cells; one workgroup per block eliminates the diagonal small-scale part
+// and the three eq:cc2 multipliers in closed form and solves the remaining
+// system of the cells' 3 n_cells coefficients (at most 180) by the modified
+// Cholesky in LDS, then the small-scale values by back substitution.  The
+// eq:cc1 projection follows as without the term.
 #include <hipcub/hipcub.hpp>
 
 #include "agis_internal.h"
@@ -52,6 +65,16 @@ __device__ __forceinline__ double shifted_legendre(int r, double x) {
 }
 
 __device__ __forceinline__ double geo_x(float mu) { return ((double)mu - 13.5) / 1966.0; }
+
+constexpr int DG_COLS = 1966;       // pixel columns m = 14 .. 1979
+constexpr int DG_SHIFT = 11;        // column bits of the group-order keys with the small-scale term
+
+// The nearest pixel column m = round(mu) as 0 .. 1965 (1979.5 stays on the
+// last column).
+__device__ __forceinline__ int geo_column(float mu) {
+    int m = (int)floor((double)mu + 0.5);
+    return (m > 1979 ? 1979 : m) - 14;
+}
 
 // Group index and pixel coordinate of every record in time order from the
 // input columns (t_perm: time index -> input index): an along-scan record's
@@ -95,9 +118,12 @@ __global__ void k_geo_gather(int64_t n, const int32_t* __restrict__ from, const 
 }
 
 // eta = eta_obs + sum_r c_r L*_r(x) of the record's group (nothing across
-// scan), the sum taken from r = 0 up.
+// scan), the sum taken from r = 0 up, plus along scan the small-scale value
+// of the record's CCD, long interval and column when days > 0 (groups below
+// n_al are along scan: cell * n_ccd + CCD; small: the first small-scale value).
 __global__ void k_geo_eta(int64_t n, const double* __restrict__ eta0, const int32_t* __restrict__ g,
-                          const float* __restrict__ mu, const double* __restrict__ geo, double* __restrict__ eta) {
+                          const float* __restrict__ mu, const double* __restrict__ geo, int32_t n_al, int32_t n_ccd,
+                          int32_t days, int64_t small, double* __restrict__ eta) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t gi = g[i];
         double v = 0.0;
@@ -107,46 +133,73 @@ __global__ void k_geo_eta(int64_t n, const double* __restrict__ eta0, const int3
             v = c[0] * shifted_legendre(0, x);
             v += c[1] * shifted_legendre(1, x);
             v += c[2] * shifted_legendre(2, x);
+            if (days > 0 && gi < n_al) {
+                const int32_t cell = gi / n_ccd, ccd = gi - cell * n_ccd;
+                const int64_t blk = (int64_t)((cell >> 1) / days) * n_ccd + ccd;
+                v += geo[small + blk * DG_COLS + geo_column(mu[i])];
+            }
         }
         eta[i] = eta0[i] + v;
     }
 }
 
-// Sort keys of the group order: the group, or n_groups without one (last).
-__global__ void k_geo_keys(int64_t n, const int32_t* __restrict__ g, int32_t n_groups, uint32_t* __restrict__ key,
-                           int32_t* __restrict__ idx) {
+// Sort keys of the group order: the group, or n_groups without one (last);
+// shifted left by `shift` bits with the record's pixel column below.
+__global__ void k_geo_keys(int64_t n, const int32_t* __restrict__ g, const float* __restrict__ mu, int32_t n_groups,
+                           int shift, uint32_t* __restrict__ key, int32_t* __restrict__ idx) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        key[i] = g[i] >= 0 ? (uint32_t)g[i] : (uint32_t)n_groups;
+        key[i] = g[i] >= 0 ? ((uint32_t)g[i] << shift) | (shift ? (uint32_t)geo_column(mu[i]) : 0u)
+                           : (uint32_t)n_groups << shift;
         idx[i] = (int32_t)i;
     }
 }
 
 // From the sorted keys and time indices: each time-order record's place in
 // the group order (-1 for a record without a group) and the group order's
-// coordinates.
+// coordinates.  end: the key of "no group".
 __global__ void k_geo_order(int64_t n, const uint32_t* __restrict__ key, const int32_t* __restrict__ idx,
-                            uint32_t n_groups, const float* __restrict__ t_mu, int32_t* __restrict__ pos,
+                            uint32_t end, const float* __restrict__ t_mu, int32_t* __restrict__ pos,
                             float* __restrict__ mu_g) {
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
         const int32_t i = idx[k];
-        const bool in = key[k] < n_groups;
+        const bool in = key[k] < end;
         pos[i] = in ? (int32_t)k : -1;
         if (in) mu_g[k] = t_mu[i];
     }
 }
 
-// off[g] = the first place of group g in the sorted keys (g = 0..n_groups).
-__global__ void k_geo_offsets(int64_t n, const uint32_t* __restrict__ key, int64_t n_groups,
+// off[j] = the first place in the sorted keys with a key of at least j <<
+// shift (j = 0..n_out - 1): with shift 0 the group ranges, with the column
+// bits and j = group * 2^shift + column the column ranges.
+__global__ void k_geo_offsets(int64_t n, const uint32_t* __restrict__ key, int64_t n_out, int shift,
                               int64_t* __restrict__ off) {
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g <= n_groups;
-         g += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n_out; j += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t want = (uint64_t)j << shift;
         int64_t lo = 0, hi = n;
         while (lo < hi) {
             const int64_t mid = lo + (hi - lo) / 2;
-            if ((int64_t)key[mid] < g) lo = mid + 1;
+            if ((uint64_t)key[mid] < want) lo = mid + 1;
             else hi = mid;
         }
-        off[g] = lo;
+        off[j] = lo;
+    }
+}
+
+// Column ranges of the along-scan groups: coff[g * 1967 + c] = the first
+// place of group g's column c (c = 1966: the group's end).
+__global__ void k_geo_col_offsets(int64_t n, const uint32_t* __restrict__ key, int64_t n_al,
+                                  int32_t* __restrict__ coff) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n_al * (DG_COLS + 1);
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = j / (DG_COLS + 1), c = j - g * (DG_COLS + 1);
+        const uint64_t want = ((uint64_t)g << DG_SHIFT) + (uint64_t)c;
+        int64_t lo = 0, hi = n;
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if ((uint64_t)key[mid] < want) lo = mid + 1;
+            else hi = mid;
+        }
+        coff[j] = (int32_t)lo;
     }
 }
 
@@ -195,28 +248,302 @@ __global__ __launch_bounds__(GEO_NT) void k_geo_sums(int64_t n_groups, const int
 }
 
 // One thread per constraint set of per_set consecutive groups from group
-// first: their 3x3 solves, then eq:calCon for its constraint (the set's
-// mean constant term removed).  AL: a day's 2 n_ccd groups (eq:cc1); AC: an
-// AC cell's n_ccd groups (eq:cc3).
-__global__ void k_geo_solve(int64_t n_sets, int64_t first, int32_t per_set, const double* __restrict__ sums,
-                            double* __restrict__ dgeo) {
+// first: their 3x3 solves (unless solve is false: the updates are already in
+// dgeo), then eq:calCon for its constraint (the set's mean constant term
+// removed).  AL: a day's 2 n_ccd groups (eq:cc1); AC: an AC cell's n_ccd
+// groups (eq:cc3).
+__global__ void k_geo_solve(int64_t n_sets, int64_t first, int32_t per_set, bool solve,
+                            const double* __restrict__ sums, double* __restrict__ dgeo) {
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n_sets;
          j += (int64_t)gridDim.x * blockDim.x) {
         const int64_t g0 = first + j * per_set, per_day = per_set;
         double mean = 0.0;
         for (int64_t k = 0; k < per_day; ++k) {
-            const double* s = sums + 9 * (g0 + k);
-            double U[9] = {s[0], s[1], s[2], s[1], s[3], s[4], s[2], s[4], s[5]};
-            double x[3] = {s[6], s[7], s[8]};
-            small_chol_solve<3>(U, x);
             double* d = dgeo + 3 * (g0 + k);
-            d[0] = x[0];
-            d[1] = x[1];
-            d[2] = x[2];
-            mean += x[0];
+            if (solve) {
+                const double* s = sums + 9 * (g0 + k);
+                double U[9] = {s[0], s[1], s[2], s[1], s[3], s[4], s[2], s[4], s[5]};
+                double x[3] = {s[6], s[7], s[8]};
+                small_chol_solve<3>(U, x);
+                d[0] = x[0];
+                d[1] = x[1];
+                d[2] = x[2];
+            }
+            mean += d[0];
         }
         mean /= (double)per_day;
         for (int64_t k = 0; k < per_day; ++k) dgeo[3 * (g0 + k)] -= mean;
+    }
+}
+
+// Per along-scan group g and column c (one thread each): over the column's
+// records of the group order, in order, cs = {sum W, sum W L_1, sum W L_2,
+// -sum W R} at colsum[(g * 1966 + c) * 4].
+__global__ void k_dg_colsums(int64_t n_al, const int32_t* __restrict__ coff, const float* __restrict__ mu,
+                             const double* __restrict__ wr, double* __restrict__ colsum) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n_al * DG_COLS;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = j / DG_COLS, c = j - g * DG_COLS;
+        const int64_t l0 = coff[g * (DG_COLS + 1) + c], l1 = coff[g * (DG_COLS + 1) + c + 1];
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        for (int64_t l = l0; l < l1; ++l) {
+            const double W = wr[2 * l], WR = wr[2 * l + 1];
+            const double x = geo_x(mu[l]);
+            s0 += W;
+            s1 += W * shifted_legendre(1, x);
+            s2 += W * shifted_legendre(2, x);
+            s3 -= WR;
+        }
+        double* o = colsum + 4 * j;
+        o[0] = s0;
+        o[1] = s1;
+        o[2] = s2;
+        o[3] = s3;
+    }
+}
+
+// Per block (long interval k, CCD n; blk = k n_ccd + n) and column: the
+// diagonal D_m = sum W and the right-hand side -sum W R of the small-scale
+// value, over the interval's cells in order: dcol[(blk * 1966 + c) * 2].
+__global__ void k_dg_colred(int64_t n_blk, int32_t n_ccd, int32_t days, int64_t n_cells,
+                            const double* __restrict__ colsum, double* __restrict__ dcol) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n_blk * DG_COLS;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t blk = j / DG_COLS, c = j - blk * DG_COLS;
+        const int64_t k = blk / n_ccd, nn = blk - k * n_ccd;
+        const int64_t c0 = 2 * k * days, c1 = min<int64_t>(c0 + 2 * (int64_t)days, n_cells);
+        double d = 0.0, r = 0.0;
+        for (int64_t cell = c0; cell < c1; ++cell) {
+            const double* s = colsum + 4 * ((cell * n_ccd + nn) * DG_COLS + c);
+            d += s[0];
+            r += s[3];
+        }
+        dcol[2 * j] = d;
+        dcol[2 * j + 1] = r;
+    }
+}
+
+constexpr int DG_NT = 512;          // threads of the block solve
+constexpr int DG_T = 6;             // side of a thread's tile of the accumulated matrix
+constexpr int DG_CH = 8;            // columns staged in LDS at a time
+constexpr int DG_NE_MAX = 180;      // cells' coefficients of a block: 60 cells, 30 days
+constexpr int DG_NP_MAX = 186;      // with the three polynomials and the right-hand side, to a multiple of 6
+
+__host__ __device__ constexpr int dg_np(int ne) { return ((ne + 4 + DG_T - 1) / DG_T) * DG_T; }
+__host__ __device__ constexpr int64_t dg_packed(int np) { return (int64_t)np * (np + 1) / 2; }
+// dynamic LDS of the block solve: the packed matrix, then 3 Ne + 16 values
+__host__ __device__ constexpr size_t dg_lds_bytes(int ne) {
+    return (size_t)(dg_packed(dg_np(ne)) + 3 * ne + 16) * sizeof(double);
+}
+__device__ __forceinline__ int64_t pk(int i, int j) { return (int64_t)i * (i + 1) / 2 + j; }   // i >= j
+
+// The C update of one block (long interval k, CCD n; one workgroup each):
+// with z_m = [B_m, L*_0..2(x_m), b_m] / sqrt(D_m) over the active columns
+// (D_m > 0; B_m: the column's sums W L_r of each cell of the block, b_m: -sum
+// W R), Z = sum_m z_m z_m' (lower triangle, packed, in LDS) holds B'D^-1 B,
+// G = B'D^-1 C, H = C'D^-1 C, B'D^-1 b and C'D^-1 b.  Eliminating the
+// small-scale values d = D^-1 (b - B e - C nu) and the eq:cc2 multipliers
+// nu = H^-1 (C'D^-1 b - G'e) leaves, for the cells' coefficients e,
+//     (E - B'D^-1 B + G H^-1 G') e = b_e - B'D^-1 b + G H^-1 C'D^-1 b,
+// E and b_e the groups' 3x3 sums (k_geo_sums); a cell without records keeps
+// e = 0.  That system goes through the modified Cholesky (a pivot that is
+// not positive gives a zero column and a zero unknown) and two triangular
+// solves, then nu and d follow.  Writes the cells' three coefficients and the
+// block's 1966 small-scale values of dgeo (0 for a column without records).
+__global__ __launch_bounds__(DG_NT) void k_dg_block(int32_t n_ccd, int32_t days, int64_t n_cells,
+                                                    const int64_t* __restrict__ off,
+                                                    const double* __restrict__ colsum,
+                                                    const double* __restrict__ dcol,
+                                                    const double* __restrict__ sums, int64_t small,
+                                                    double* __restrict__ dgeo) {
+    extern __shared__ double lds[];
+    const int64_t blk = blockIdx.x;
+    const int64_t k = blk / n_ccd, nn = blk - k * n_ccd;
+    const int64_t c0 = 2 * k * days, c1 = min<int64_t>(c0 + 2 * (int64_t)days, n_cells);
+    const int nc = (int)(c1 - c0), ne = 3 * nc, np = dg_np(ne);
+    const int tid = threadIdx.x;
+    double* Z = lds;                                  // packed lower triangle, np x np
+    double* ex = lds + dg_packed(np);                 // the cells' right-hand side, then solution [ne]
+    double* act = ex + ne;                            // 1: the cell of row i has records [ne]
+    double* gw = act + ne;                            // spare [ne]
+    double* hs = gw + ne;                             // H^-1 [9], w = H^-1 C'D^-1 b [3], nu [3]
+    (void)gw;
+    const double* dc = dcol + 2 * blk * DG_COLS;
+    auto colv = [&](int i, int m) -> double {          // B_m entry of row i (< ne)
+        const int cell = i / 3, r = i - 3 * cell;
+        return colsum[4 * (((c0 + cell) * n_ccd + nn) * DG_COLS + m) + r];
+    };
+    // --- Z = sum_m z_m z_m', a 6x6 tile of the lower triangle per thread
+    const int ntile = np / DG_T;
+    int ti = 0;
+    while ((ti + 1) * (ti + 2) / 2 <= tid) ++ti;      // tile row of this thread
+    const int tj = tid - ti * (ti + 1) / 2;
+    const bool own = ti < ntile;
+    double acc[DG_T * DG_T];
+#pragma unroll
+    for (int e = 0; e < DG_T * DG_T; ++e) acc[e] = 0.0;
+    double* stage = lds;                              // DG_CH staged vectors (before Z is written)
+    for (int m0 = 0; m0 < DG_COLS; m0 += DG_CH) {
+        __syncthreads();
+        for (int e = tid; e < DG_CH * np; e += DG_NT) {
+            const int mm = e / np, i = e - mm * np, m = m0 + mm;
+            double v = 0.0;
+            if (m < DG_COLS) {
+                const double D = dc[2 * m];
+                if (D > 0.0) {
+                    const double s = 1.0 / sqrt(D);
+                    const double x = ((double)(m + 14) - 13.5) / 1966.0;
+                    if (i < ne) v = colv(i, m) * s;
+                    else if (i < ne + 3) v = shifted_legendre(i - ne, x) * s;
+                    else if (i == ne + 3) v = dc[2 * m + 1] * s;
+                }
+            }
+            stage[e] = v;
+        }
+        __syncthreads();
+        if (own) {
+#pragma unroll 2
+            for (int mm = 0; mm < DG_CH; ++mm) {
+                const double* z = stage + mm * np;
+                double a[DG_T], b[DG_T];
+#pragma unroll
+                for (int q = 0; q < DG_T; ++q) {
+                    a[q] = z[DG_T * ti + q];
+                    b[q] = z[DG_T * tj + q];
+                }
+#pragma unroll
+                for (int p = 0; p < DG_T; ++p)
+#pragma unroll
+                    for (int q = 0; q < DG_T; ++q) acc[p * DG_T + q] += a[p] * b[q];
+            }
+        }
+    }
+    __syncthreads();
+    if (own) {
+#pragma unroll
+        for (int p = 0; p < DG_T; ++p)
+#pragma unroll
+            for (int q = 0; q < DG_T; ++q) {
+                const int i = DG_T * ti + p, j = DG_T * tj + q;
+                if (i >= j) Z[pk(i, j)] = acc[p * DG_T + q];
+            }
+    }
+    for (int i = tid; i < ne; i += DG_NT) {
+        const int64_t g = (c0 + i / 3) * n_ccd + nn;
+        act[i] = off[g + 1] > off[g] ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // --- H^-1 (cofactors of the 3x3 SPD matrix) and w = H^-1 C'D^-1 b
+    if (tid == 0) {
+        const double h00 = Z[pk(ne, ne)], h10 = Z[pk(ne + 1, ne)], h11 = Z[pk(ne + 1, ne + 1)];
+        const double h20 = Z[pk(ne + 2, ne)], h21 = Z[pk(ne + 2, ne + 1)], h22 = Z[pk(ne + 2, ne + 2)];
+        const double a00 = h11 * h22 - h21 * h21, a01 = h20 * h21 - h10 * h22, a02 = h10 * h21 - h20 * h11;
+        const double det = h00 * a00 + h10 * a01 + h20 * a02;
+        const double inv = det != 0.0 ? 1.0 / det : 0.0;
+        const double a11 = h00 * h22 - h20 * h20, a12 = h10 * h20 - h00 * h21, a22 = h00 * h11 - h10 * h10;
+        const double Hi[9] = {a00 * inv, a01 * inv, a02 * inv, a01 * inv, a11 * inv,
+                              a12 * inv, a02 * inv, a12 * inv, a22 * inv};
+        for (int e = 0; e < 9; ++e) hs[e] = Hi[e];
+        for (int s = 0; s < 3; ++s) {
+            double v = 0.0;
+            for (int t = 0; t < 3; ++t) v += Hi[3 * s + t] * Z[pk(ne + 3, ne + t)];
+            hs[9 + s] = v;
+        }
+    }
+    __syncthreads();
+    // --- the reduced system in place: A = E - Z + G H^-1 G', right-hand side in ex
+    for (int e = tid; e < ne * ne; e += DG_NT) {
+        const int i = e / ne, j = e - i * ne;
+        if (j > i) continue;
+        double v;
+        if (act[i] == 0.0 || act[j] == 0.0) {
+            v = i == j ? 1.0 : 0.0;
+        } else {
+            double Ev = 0.0;
+            if (i / 3 == j / 3) {
+                const int a = j - 3 * (j / 3), b = i - 3 * (i / 3);           // a <= b
+                const int idx = a == 0 ? b : (a == 1 ? 2 + b : 5);
+                Ev = sums[9 * ((c0 + i / 3) * n_ccd + nn) + idx];
+            }
+            double gg = 0.0;
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                double t = 0.0;
+#pragma unroll
+                for (int u = 0; u < 3; ++u) t += hs[3 * s + u] * Z[pk(ne + u, j)];
+                gg += Z[pk(ne + s, i)] * t;
+            }
+            v = Ev - Z[pk(i, j)] + gg;
+        }
+        Z[pk(i, j)] = v;
+    }
+    for (int i = tid; i < ne; i += DG_NT) {
+        double v = 0.0;
+        if (act[i] != 0.0) {
+            const int cell = i / 3, r = i - 3 * cell;
+            v = sums[9 * ((c0 + cell) * n_ccd + nn) + 6 + r] - Z[pk(ne + 3, i)];
+#pragma unroll
+            for (int s = 0; s < 3; ++s) v += Z[pk(ne + s, i)] * hs[9 + s];
+        }
+        ex[i] = v;
+    }
+    __syncthreads();
+    // --- modified Cholesky A = L L' (right-looking, the factor over A's lower triangle)
+    for (int p = 0; p < ne; ++p) {
+        const double piv = Z[pk(p, p)];
+        const double d = piv > 0.0 ? sqrt(piv) : 0.0;
+        for (int i = p + 1 + tid; i < ne; i += DG_NT) Z[pk(i, p)] = d > 0.0 ? Z[pk(i, p)] / d : 0.0;
+        __syncthreads();
+        const int rem = ne - p - 1;
+        for (int e = tid; e < rem * rem; e += DG_NT) {
+            const int i = p + 1 + e / rem, j = p + 1 + (e - (e / rem) * rem);
+            if (j <= i) Z[pk(i, j)] -= Z[pk(i, p)] * Z[pk(j, p)];
+        }
+        if (tid == 0) Z[pk(p, p)] = d;
+        __syncthreads();
+    }
+    // --- L y = rhs, then L' e = y (a zero pivot gives a zero unknown)
+    for (int p = 0; p < ne; ++p) {
+        const double d = Z[pk(p, p)];
+        const double y = d > 0.0 ? ex[p] / d : 0.0;
+        __syncthreads();
+        if (tid == 0) ex[p] = y;
+        for (int i = p + 1 + tid; i < ne; i += DG_NT) ex[i] -= Z[pk(i, p)] * y;
+        __syncthreads();
+    }
+    for (int p = ne - 1; p >= 0; --p) {
+        const double d = Z[pk(p, p)];
+        const double x = d > 0.0 ? ex[p] / d : 0.0;
+        __syncthreads();
+        if (tid == 0) ex[p] = x;
+        for (int i = tid; i < p; i += DG_NT) ex[i] -= Z[pk(p, i)] * x;
+        __syncthreads();
+    }
+    // --- nu = H^-1 (C'D^-1 b - G'e)
+    if (tid == 0) {
+        double q[3];
+        for (int s = 0; s < 3; ++s) {
+            double v = Z[pk(ne + 3, ne + s)];
+            for (int i = 0; i < ne; ++i) v -= Z[pk(ne + s, i)] * ex[i];
+            q[s] = v;
+        }
+        for (int s = 0; s < 3; ++s) hs[12 + s] = hs[3 * s] * q[0] + hs[3 * s + 1] * q[1] + hs[3 * s + 2] * q[2];
+    }
+    __syncthreads();
+    // --- the cells' coefficients and the small-scale values
+    for (int i = tid; i < ne; i += DG_NT) dgeo[3 * ((c0 + i / 3) * n_ccd + nn) + (i - 3 * (i / 3))] = ex[i];
+    for (int m = tid; m < DG_COLS; m += DG_NT) {
+        const double D = dc[2 * m];
+        double v = 0.0;
+        if (D > 0.0) {
+            const double x = ((double)(m + 14) - 13.5) / 1966.0;
+            v = dc[2 * m + 1];
+            for (int i = 0; i < ne; ++i) v -= colv(i, m) * ex[i];
+#pragma unroll
+            for (int s = 0; s < 3; ++s) v -= shifted_legendre(s, x) * hs[12 + s];
+            v /= D;
+        }
+        dgeo[small + blk * DG_COLS + m] = v;
     }
 }
 
@@ -241,10 +568,14 @@ inline unsigned grid_for(int64_t n) {
 
 void launch_geo_eta(agis_ctx* ctx) {
     if (ctx->geo_ccds <= 0 || ctx->n_obs == 0) return;
+    const int32_t n_al = (int32_t)(ctx->n_cells * ctx->geo_ccds);
+    const int64_t small = 3 * ctx->n_groups;
     k_geo_eta<<<grid_for(ctx->n_obs), 256, 0, ctx->stream>>>(ctx->n_obs, ctx->t_eta0, ctx->t_geo_g, ctx->t_geo_mu,
-                                                             ctx->geo, ctx->t_eta);
+                                                             ctx->geo, n_al, ctx->geo_ccds, ctx->geo_small_days,
+                                                             small, ctx->t_eta);
     k_geo_eta<<<grid_for(ctx->n_obs), 256, 0, ctx->stream>>>(ctx->n_obs, ctx->s_eta0, ctx->s_geo_g, ctx->s_geo_mu,
-                                                             ctx->geo, ctx->s_eta);
+                                                             ctx->geo, n_al, ctx->geo_ccds, ctx->geo_small_days,
+                                                             small, ctx->s_eta);
 }
 
 void launch_geo_solve(agis_ctx* ctx) {
@@ -252,16 +583,31 @@ void launch_geo_solve(agis_ctx* ctx) {
     k_geo_sums<<<(unsigned)ctx->n_groups, GEO_NT, 0, ctx->stream>>>(ctx->n_groups, ctx->geo_off, ctx->geo_mu_g,
                                                                     ctx->geo_wr, ctx->geo_sums);
     const int64_t n_days = ctx->n_cells / 2;
-    k_geo_solve<<<grid_for(n_days), 256, 0, ctx->stream>>>(n_days, 0, 2 * ctx->geo_ccds, ctx->geo_sums, ctx->dgeo);
+    const bool small = ctx->geo_small_days > 0;
+    if (small) {
+        // the AL groups with the small-scale values, by block (eq:cc2 inside)
+        const int64_t n_al = ctx->n_cells * ctx->geo_ccds, n_blk = ctx->n_small / DG_COLS;
+        k_dg_colsums<<<grid_for(n_al * DG_COLS), 256, 0, ctx->stream>>>(n_al, ctx->geo_coff, ctx->geo_mu_g,
+                                                                       ctx->geo_wr, ctx->geo_colsum);
+        k_dg_colred<<<grid_for(n_blk * DG_COLS), 256, 0, ctx->stream>>>(n_blk, ctx->geo_ccds, ctx->geo_small_days,
+                                                                       ctx->n_cells, ctx->geo_colsum, ctx->geo_dcol);
+        k_dg_block<<<(unsigned)n_blk, DG_NT, dg_lds_bytes(3 * 2 * ctx->geo_small_days), ctx->stream>>>(
+            ctx->geo_ccds, ctx->geo_small_days, ctx->n_cells, ctx->geo_off, ctx->geo_colsum, ctx->geo_dcol,
+            ctx->geo_sums, 3 * ctx->n_groups, ctx->dgeo);
+    }
+    k_geo_solve<<<grid_for(n_days), 256, 0, ctx->stream>>>(n_days, 0, 2 * ctx->geo_ccds, !small, ctx->geo_sums,
+                                                           ctx->dgeo);
     if (ctx->geo_ac_cells > 0)
         k_geo_solve<<<grid_for(ctx->geo_ac_cells), 256, 0, ctx->stream>>>(
-            ctx->geo_ac_cells, ctx->n_cells * ctx->geo_ccds, ctx->geo_ccds, ctx->geo_sums, ctx->dgeo);
+            ctx->geo_ac_cells, ctx->n_cells * ctx->geo_ccds, ctx->geo_ccds, true, ctx->geo_sums, ctx->dgeo);
 }
 
-// The group order of the along-scan records (time order within a group):
-// geo_pos, geo_mu_g and geo_off from the time-order groups t_geo_g.
+// The group order of the records with a group (time order within a group,
+// or with the small-scale term column then time order): geo_pos, geo_mu_g,
+// geo_off (and geo_coff) from the time-order groups t_geo_g.
 static int build_group_order(agis_ctx* ctx) {
     const int64_t n = ctx->n_obs, ng = ctx->n_groups;
+    const int shift = ctx->geo_small_days > 0 ? DG_SHIFT : 0;
     hipStream_t st = ctx->stream;
     uint32_t *k_in = nullptr, *k_out = nullptr;
     int32_t *v_in = nullptr, *v_out = nullptr;
@@ -278,24 +624,27 @@ static int build_group_order(agis_ctx* ctx) {
     if ((rc = dalloc(ctx, &k_in, (size_t)n, "group order keys")) || (rc = dalloc(ctx, &k_out, (size_t)n, "group order keys")) ||
         (rc = dalloc(ctx, &v_in, (size_t)n, "group order")) || (rc = dalloc(ctx, &v_out, (size_t)n, "group order")))
         return done(rc);
-    const int end_bit = 32 - __builtin_clz((unsigned)ng);       // keys 0..ng
+    const int end_bit = 32 - __builtin_clz((unsigned)ng << shift);       // keys 0..ng << shift
     size_t tb = 0;
     hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, tb, k_in, k_out, v_in, v_out, (int)n, 0, end_bit, st);
     if (e != hipSuccess) return done(hip_check(ctx, e, "group order sort"));
     if ((rc = dalloc(ctx, &temp, tb, "group order sort"))) return done(rc);
-    k_geo_keys<<<grid_for(n), 256, 0, st>>>(n, ctx->t_geo_g, (int32_t)ng, k_in, v_in);
+    k_geo_keys<<<grid_for(n), 256, 0, st>>>(n, ctx->t_geo_g, ctx->t_geo_mu, (int32_t)ng, shift, k_in, v_in);
     e = hipcub::DeviceRadixSort::SortPairs(temp, tb, k_in, k_out, v_in, v_out, (int)n, 0, end_bit, st);
     if (e != hipSuccess) return done(hip_check(ctx, e, "group order sort"));
-    k_geo_order<<<grid_for(n), 256, 0, st>>>(n, k_out, v_out, (uint32_t)ng, ctx->t_geo_mu, ctx->geo_pos,
+    k_geo_order<<<grid_for(n), 256, 0, st>>>(n, k_out, v_out, (uint32_t)ng << shift, ctx->t_geo_mu, ctx->geo_pos,
                                              ctx->geo_mu_g);
-    k_geo_offsets<<<grid_for(ng + 1), 256, 0, st>>>(n, k_out, ng, ctx->geo_off);
+    k_geo_offsets<<<grid_for(ng + 1), 256, 0, st>>>(n, k_out, ng + 1, shift, ctx->geo_off);
+    if (shift)
+        k_geo_col_offsets<<<grid_for(ctx->n_cells * ctx->geo_ccds * (DG_COLS + 1)), 256, 0, st>>>(
+            n, k_out, ctx->n_cells * ctx->geo_ccds, ctx->geo_coff);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st);       // before the temporaries go
     return done(e == hipSuccess ? AGIS_OK : hip_check(ctx, e, "group order"));
 }
 
 int load_geometry(agis_ctx* ctx, const int8_t* ccd, const float* mu, int32_t n_ccd, const int32_t* ac_cell,
-                  int32_t n_ac_cells, int where) {
+                  int32_t n_ac_cells, int32_t small_days, int where) {
     const int64_t n = ctx->n_obs;
     hipStream_t st = ctx->stream;
     const int8_t* ccd_d = ccd;
@@ -334,6 +683,31 @@ int load_geometry(agis_ctx* ctx, const int8_t* ccd, const float* mu, int32_t n_c
         release();
         return set_error(ctx, AGIS_E_INVALID_ARG, "agis_load_geometry: more than 2^31 - 1 records or groups");
     }
+    // the small-scale term: blocks of 2 small_days cells, the group-order
+    // keys with 11 column bits, the block solve's LDS
+    const int64_t n_al = ctx->n_cells * n_ccd;
+    const int64_t n_k = small_days > 0 ? (ctx->n_cells / 2 + small_days - 1) / small_days : 0;
+    const int64_t n_small = n_k * n_ccd * DG_COLS;
+    if (small_days > 0) {
+        int dev = 0, lds_max = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        const size_t lds = dg_lds_bytes(6 * small_days);
+        std::string m;
+        if (6 * small_days > DG_NE_MAX) m = "small-scale long interval above 30 days";
+        else if (((ng + 1) << DG_SHIFT) > (int64_t)UINT32_MAX) m = "more than 2^21 - 1 groups with the small-scale term";
+        else if ((int64_t)lds > (int64_t)lds_max) m = "the small-scale block solve does not fit the device's LDS";
+        if (!m.empty()) {
+            release();
+            return set_error(ctx, AGIS_E_INVALID_ARG, "agis_load_geometry: " + m);
+        }
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dg_block),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) {
+            release();
+            return hip_check(ctx, e, "small-scale block solve LDS");
+        }
+    }
     auto fail = [&](int rc) {
         release();
         return rc;
@@ -352,22 +726,29 @@ int load_geometry(agis_ctx* ctx, const int8_t* ccd, const float* mu, int32_t n_c
     GALLOC(ctx->geo_mu_g, n, "group order mu");
     GALLOC(ctx->geo_flags, 1, "geometry flags");
 #undef GALLOC
-    if (ctx->geo_ccds != n_ccd || ctx->geo_ac_cells != n_ac || !ctx->geo) {
-        if (ctx->geo) {
-            dfree(ctx->geo);
-            dfree(ctx->dgeo);
-            dfree(ctx->geo_sums);
-            dfree(ctx->geo_off);
-        }
-        if ((rc = dalloc(ctx, &ctx->geo, (size_t)std::max<int64_t>(3 * ng, 1), "geometric calibration")) ||
-            (rc = dalloc(ctx, &ctx->dgeo, (size_t)std::max<int64_t>(3 * ng, 1), "geometric update")) ||
+    const int64_t n_coef = 3 * ng + n_small;
+    if (ctx->geo_ccds != n_ccd || ctx->geo_ac_cells != n_ac || ctx->geo_small_days != small_days || !ctx->geo) {
+        dfree(ctx->geo);
+        dfree(ctx->dgeo);
+        dfree(ctx->geo_sums);
+        dfree(ctx->geo_off);
+        dfree(ctx->geo_coff);
+        dfree(ctx->geo_colsum);
+        dfree(ctx->geo_dcol);
+        if ((rc = dalloc(ctx, &ctx->geo, (size_t)std::max<int64_t>(n_coef, 1), "geometric calibration")) ||
+            (rc = dalloc(ctx, &ctx->dgeo, (size_t)std::max<int64_t>(n_coef, 1), "geometric update")) ||
             (rc = dalloc(ctx, &ctx->geo_sums, (size_t)std::max<int64_t>(9 * ng, 1), "geometric sums")) ||
             (rc = dalloc(ctx, &ctx->geo_off, (size_t)(ng + 1), "group offsets")))
             return fail(rc);
+        if (small_days > 0 &&
+            ((rc = dalloc(ctx, &ctx->geo_coff, (size_t)(n_al * (DG_COLS + 1)), "column offsets")) ||
+             (rc = dalloc(ctx, &ctx->geo_colsum, (size_t)(4 * n_al * DG_COLS), "column sums")) ||
+             (rc = dalloc(ctx, &ctx->geo_dcol, (size_t)(2 * n_small), "small-scale diagonal"))))
+            return fail(rc);
     }
     hipError_t e = hipMemsetAsync(ctx->geo_flags, 0, sizeof(int), st);
-    if (e == hipSuccess) e = hipMemsetAsync(ctx->geo, 0, std::max<int64_t>(3 * ng, 1) * sizeof(double), st);
-    if (e == hipSuccess) e = hipMemsetAsync(ctx->dgeo, 0, std::max<int64_t>(3 * ng, 1) * sizeof(double), st);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->geo, 0, std::max<int64_t>(n_coef, 1) * sizeof(double), st);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->dgeo, 0, std::max<int64_t>(n_coef, 1) * sizeof(double), st);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->geo_off, 0, (ng + 1) * sizeof(int64_t), st);
     if (e != hipSuccess) return fail(hip_check(ctx, e, "geometry clear"));
     if (n > 0) {
@@ -392,6 +773,8 @@ int load_geometry(agis_ctx* ctx, const int8_t* ccd, const float* mu, int32_t n_c
         }
         ctx->geo_ccds = 0;
         ctx->geo_ac_cells = 0;
+        ctx->geo_small_days = 0;
+        ctx->n_small = 0;
         ctx->n_groups = 0;
         std::string m = "agis_load_geometry:";
         if (flags & 1) m += " ccd index outside [0, n_ccd);";
@@ -407,6 +790,8 @@ int load_geometry(agis_ctx* ctx, const int8_t* ccd, const float* mu, int32_t n_c
     }
     ctx->geo_ccds = n_ccd;
     ctx->geo_ac_cells = n_ac;
+    ctx->geo_small_days = small_days;
+    ctx->n_small = n_small;
     ctx->n_groups = ng;
     if (n > 0 && (rc = build_group_order(ctx)) != AGIS_OK) {
         // back to the cell offsets and the observed angles as loaded
@@ -415,6 +800,8 @@ int load_geometry(agis_ctx* ctx, const int8_t* ccd, const float* mu, int32_t n_c
         (void)hipStreamSynchronize(st);
         ctx->geo_ccds = 0;
         ctx->geo_ac_cells = 0;
+        ctx->geo_small_days = 0;
+        ctx->n_small = 0;
         ctx->n_groups = 0;
         return rc;
     }
