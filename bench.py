@@ -102,15 +102,17 @@ def workload_description(name, w):
                 "sigma_ac_uas": round(float(w.sigma[w.cell < 0][0]) / 4.8481368e-12, 1)} if sp.ac_obs else {}),
             **({"calibration": "large-scale along-scan geometric: 3 shifted-Legendre coefficients per cell and CCD",
                 "calibration_groups": int(w.n_cells * w.consts["geo_ccds"])} if sp.geo_cal else {}),
+            **({"small_scale": f"one value per CCD, {sp.geo_small_days}-day interval and pixel column (eq:cc2)",
+                "small_scale_values": int(w.geo_small_true.size)} if sp.geo_cal and sp.geo_small else {}),
             "law": "Gaia-like: spin 60 arcsec/s, precession 63 d, aspect 45 deg, basic angle 106.5 deg"}
 
 
 def geo_coefficients(w, which):
-    """The world's geometric coefficients, AL then AC (the layout
-    agis_set_geo_calibration takes)."""
-    g = getattr(w, f"geo_{which}")
-    ga = getattr(w, f"geo_ac_{which}", None)
-    return np.reshape(g, -1) if ga is None else np.concatenate([np.reshape(g, -1), np.reshape(ga, -1)])
+    """The world's geometric coefficients, AL, then AC and small-scale where
+    the world has them (the layout agis_set_geo_calibration takes)."""
+    parts = [getattr(w, f"geo_{which}")] + [x for x in (getattr(w, f"geo_ac_{which}", None),
+                                                         getattr(w, f"geo_small_{which}", None)) if x is not None]
+    return np.concatenate([np.reshape(x, -1) for x in parts])
 
 
 def host_description():
@@ -220,6 +222,9 @@ def main():
     ap.add_argument("--geo", action="store_true",
                     help="the large-scale geometric calibration (3 coefficients per cell and CCD) in place of one "
                          "offset per cell; with --ac the across-scan term too; no CPU baseline")
+    ap.add_argument("--geo-small", action="store_true",
+                    help="with --geo: the small-scale along-scan term too (one value per CCD, 30-day interval and "
+                         "pixel column)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the timed steps, run one plain device copy of this many MiB (the reference "
                          "kernel for scaling HBM counters) and exit")
@@ -244,8 +249,10 @@ def main():
     if args.geo:
         over["geo_cal"] = True
         over["geo_ac"] = args.ac            # with across-scan records: the AC term too
+        over["geo_small"] = args.geo_small
         args.no_cpu_baseline = True
-    wname = args.workload + ("+ac" if args.ac else "") + ("+geo" if args.geo else "")
+    wname = (args.workload + ("+ac" if args.ac else "") + ("+geo" if args.geo else "")
+             + ("+small" if args.geo and args.geo_small else ""))
     t0 = time.time()
     w = C.make(args.workload, progress=log, **over)
     log(f"workload {args.workload}: {w.src_true.shape[0]} sources, {w.n_obs} obs, {w.n_att} coefficients "
@@ -262,7 +269,8 @@ def main():
     agis.agis_set_calibration(ctx, w.cal_true)
     if args.geo:
         agis.agis_load_geometry(ctx, w.ccd, w.mu, int(w.consts["geo_ccds"]), w.ac_cell,
-                                int(w.consts.get("geo_ac_cells", 0)) if w.ac_cell is not None else 0)
+                                int(w.consts.get("geo_ac_cells", 0)) if w.ac_cell is not None else 0,
+                                small_days=int(w.consts.get("geo_small_days", 0)))
         agis.agis_set_geo_calibration(ctx, geo_coefficients(w, "true"))
     R = agis.agis_residuals(ctx)                   # = c_true - eta_true (plus the true geometric terms)
     eta_obs = -R + w.eps
@@ -276,7 +284,8 @@ def main():
     agis.agis_set_calibration(ctx, w.cal_start)
     if args.geo:
         agis.agis_load_geometry(ctx, w.ccd, w.mu, int(w.consts["geo_ccds"]), w.ac_cell,
-                                int(w.consts.get("geo_ac_cells", 0)) if w.ac_cell is not None else 0)
+                                int(w.consts.get("geo_ac_cells", 0)) if w.ac_cell is not None else 0,
+                                small_days=int(w.consts.get("geo_small_days", 0)))
         agis.agis_set_geo_calibration(ctx, geo_coefficients(w, "start"))
     agis.agis_set_frame_reference(ctx, w.src_true)
     sz = agis.agis_problem_size(ctx)

@@ -1010,6 +1010,16 @@ static void small_block_solve(const orc_world_t* w, const orc_obs_t* obs, const 
     const int64_t D = w->geo_small_days;
     const int64_t c0 = 2 * k * D, c1 = (2 * (k + 1) * D < st->n_cells) ? 2 * (k + 1) * D : st->n_cells;
     const int64_t nc = c1 - c0, ne = 3 * nc, nu = GEO_COLS + ne, nk = nu + 3;
+    const int64_t q0 = small_base(w, obs, st) + (k * w->geo_ccds + n) * GEO_COLS;
+    int64_t n_rec = 0;
+    for (int64_t l = 0; l < obs->n; ++l)
+        if (obs->cell[l] >= c0 && obs->cell[l] < c1 && obs->ccd[l] == n) ++n_rec;
+    if (n_rec == 0) {                                 /* every unknown held at zero */
+        for (int64_t m = 0; m < GEO_COLS; ++m) d[q0 + m] = 0.0;
+        for (int64_t c = c0; c < c1; ++c)
+            for (int r = 0; r < 3; ++r) d[3 * (c * w->geo_ccds + n) + r] = 0.0;
+        return;
+    }
     double* A = (double*)calloc((size_t)(nk * nk), sizeof(double));
     double* b = (double*)calloc((size_t)nk, sizeof(double));
     double* x = (double*)calloc((size_t)nk, sizeof(double));
@@ -1042,7 +1052,6 @@ static void small_block_solve(const orc_world_t* w, const orc_obs_t* obs, const 
     for (int64_t i = 0; i < nu; ++i)
         if (cnt[i] == 0) A[i * nk + i] = 1.0;        /* held at zero: b_i = 0 */
     solve_gauss_pp(A, b, nk, x);
-    const int64_t q0 = small_base(w, obs, st) + (k * w->geo_ccds + n) * GEO_COLS;
     for (int64_t m = 0; m < GEO_COLS; ++m) d[q0 + m] = x[m];
     for (int64_t c = c0; c < c1; ++c)
         for (int r = 0; r < 3; ++r) d[3 * (c * w->geo_ccds + n) + r] = x[GEO_COLS + 3 * (c - c0) + r];

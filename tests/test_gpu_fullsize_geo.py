@@ -1,18 +1,21 @@
-"""Parity at full size of the large-scale geometric calibration (eq:etazeta,
-Sect. 3.4; the C block of Sect. 5.3 with eq:calCon for eq:cc1 and eq:cc3):
+"""Parity at full size of the geometric calibration (eq:etazeta, Sect. 3.4;
+the C block of Sect. 5.3 with eq:calCon for eq:cc1 and eq:cc3, and eq:cc2):
 the 1M-source / 1-year / 9-CCD workload with one across-scan record per
-transit and both terms (3 coefficients per cell and CCD along scan, per AC
-cell of 30 days and CCD across scan; 178.8M records), loaded as the
-benchmark's --geo --ac run loads it, on sampled outputs.
+transit and all three terms (3 coefficients per cell and CCD along scan, the
+small-scale values per CCD, 30-day interval and pixel column, 3 coefficients
+per AC cell of 30 days and CCD across scan; 178.8M records), loaded as the
+benchmark's --geo --geo-small --ac run loads it, on sampled outputs.
 
 The oracle computes each sampled output from a sub-world that holds exactly
 the records it depends on: residuals at 4,096 sampled records; the C update
-at the start values of the AL groups of two sampled days (the records of the
-day's two cells) and of the AC groups of two sampled AC cells (the AC
-records of the cell).  With the plain weights W = 1 / sigma^2 a group's
-update depends on its own records only, and eq:cc1 (eq:cc3) couples only the
-groups of one day (AC cell).  Criterion: as in the small-world parity tests,
-the FP64 floor of the extended-precision oracle.
+at the start values of two sampled (CCD, interval) blocks (the block's
+along-scan records: its 1966 small-scale values and its cells' linear and
+quadratic coefficients, which eq:cc1's day means over all CCDs do not
+touch) and of the AC groups of two sampled AC cells (the AC records of the
+cell).  With the plain weights W = 1 / sigma^2 a block's (group's) update
+depends on its own records only, and eq:cc3 couples only the groups of one
+AC cell.  Criterion: as in the small-world parity tests, the FP64 floor of
+the extended-precision oracle.
 """
 import numpy as np
 import pytest
@@ -27,14 +30,15 @@ pytestmark = [pytest.mark.gpu, pytest.mark.timeout(1200)]
 
 @pytest.fixture(scope="module")
 def full_geo(oracle_lib, agis_mod):
-    w = C.make("gaia1", ac_obs=True, geo_cal=True, geo_ac=True)
-    print(f"gaia1+ac+geo: {w.n_obs} records, {w.n_cells} cells, {int(w.consts['geo_ac_cells'])} AC cells", flush=True)
+    w = C.make("gaia1", ac_obs=True, geo_cal=True, geo_ac=True, geo_small=True)
+    print(f"gaia1+ac+geo: {w.n_obs} records, {w.n_cells} cells, {int(w.consts['geo_ac_cells'])} AC cells, "
+          f"{w.geo_small_true.size} small-scale values", flush=True)
     eta = oracle_lib.observed_field_angles(w)
     print("gaia1+ac+geo: observed angles from the oracle's model", flush=True)
     ctx = agis_mod.agis_create(w.consts, w.knots)
     agis_mod.agis_load_observations(ctx, w.t, eta, w.sigma, w.src, w.fov, w.cell, w.src_true.shape[0], w.n_cells)
     agis_mod.agis_load_geometry(ctx, w.ccd, w.mu, int(w.consts["geo_ccds"]), w.ac_cell,
-                                int(w.consts["geo_ac_cells"]))
+                                int(w.consts["geo_ac_cells"]), small_days=int(w.consts["geo_small_days"]))
     w.eta_nominal = None
     yield w, eta, ctx
     agis_mod.agis_destroy(ctx)
@@ -65,23 +69,32 @@ def test_fullsize_geo_calibration_update(agis_mod, oracle_lib, full_geo):
     _start(agis_mod, ctx, w)
     agis_mod.agis_calibration_update(ctx)
     n_ccd, n_ac = int(w.consts["geo_ccds"]), int(w.consts["geo_ac_cells"])
-    G = agis_mod.agis_get_geo_calibration(ctx, 3 * (w.n_cells + n_ac) * n_ccd)
+    n_small = w.geo_small_true.size
+    G = agis_mod.agis_get_geo_calibration(ctx, 3 * (w.n_cells + n_ac) * n_ccd + n_small)
     n_al = 3 * w.n_cells * n_ccd
+    small0 = 3 * (w.n_cells + n_ac) * n_ccd
+    days = int(w.consts["geo_small_days"])
     rng = np.random.default_rng(19)
 
     def run(pr):
         pr.calibration_update()
         return pr.s.copy(), pr.a.copy(), pr.geo.copy()
 
-    # the AL groups of two sampled days
-    for day in sorted(rng.choice(np.arange(1, w.n_cells // 2 - 1), 2, replace=False)):
-        idx = np.flatnonzero((w.cell == 2 * day) | (w.cell == 2 * day + 1))
+    # eq:cc1 over every day
+    c0 = G[:n_al].reshape(-1, 2 * n_ccd, 3)[:, :, 0]
+    assert np.abs(c0.sum(axis=1)).max() < 1e-12 * np.abs(c0).max()
+    # two sampled (CCD, interval) blocks, whole intervals
+    n_k = (w.n_cells // 2) // days
+    for k, n in zip(sorted(rng.choice(np.arange(n_k), 2, replace=False)), rng.choice(n_ccd, 2, replace=False)):
+        c_lo, c_hi = 2 * days * k, 2 * days * (k + 1)
+        idx = np.flatnonzero((w.cell >= c_lo) & (w.cell < c_hi) & (w.ccd == n))
         X, O, tol = fp64_floor(oracle_lib, subworld(w, idx), eta[idx], run)
-        sel = np.arange(3 * 2 * day * n_ccd, 3 * (2 * day + 2) * n_ccd)
-        check_floor(f"AL geometric C update, day {day} ({idx.size} records, {sel.size} coefficients)",
+        sel = small0 + (k * n_ccd + n) * 1966 + np.arange(1966)
+        check_floor(f"small-scale C update, CCD {n}, interval {k} ({idx.size} records)",
                     X[2][sel], O[2][sel], G[sel], tol[2][sel], 2)
-        c0 = G[sel].reshape(-1, 3)[:, 0]
-        assert abs(c0.sum()) < 1e-12 * np.abs(c0).max()                       # eq:cc1
+        lq = (3 * (np.arange(c_lo, c_hi)[:, None] * n_ccd + n) + np.array([1, 2])[None, :]).reshape(-1)
+        check_floor(f"its cells' linear and quadratic coefficients ({lq.size})",
+                    X[2][lq], O[2][lq], G[lq], tol[2][lq], 2)
     # the AC groups of two sampled AC cells
     for cell in sorted(rng.choice(np.arange(1, n_ac - 1), 2, replace=False)):
         idx = np.flatnonzero(w.ac_cell == cell)
