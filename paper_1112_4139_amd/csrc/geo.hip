@@ -276,35 +276,53 @@ __global__ void k_geo_solve(int64_t n_sets, int64_t first, int32_t per_set, bool
     }
 }
 
-// Per along-scan group g and column c (one thread each): over the column's
-// records of the group order, in order, cs = {sum W, sum W L_1, sum W L_2,
-// -sum W R} at colsum[(g * 1966 + c) * 4].
+// Per along-scan group g and column c (DG_LPC lanes each, striding over
+// the column's records of the group order, so that a wave's loads cover
+// DG_LPC consecutive records of each of its columns; then a fixed-order
+// butterfly over the lanes): cs = {sum W, sum W L_1, sum W L_2, -sum W R}
+// at colsum[(g * 1966 + c) * 4].
+constexpr int DG_LPC = 8;
 __global__ void k_dg_colsums(int64_t n_al, const int32_t* __restrict__ coff, const float* __restrict__ mu,
                              const double* __restrict__ wr, double* __restrict__ colsum) {
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n_al * DG_COLS;
-         j += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t g = j / DG_COLS, c = j - g * DG_COLS;
-        const int64_t l0 = coff[g * (DG_COLS + 1) + c], l1 = coff[g * (DG_COLS + 1) + c + 1];
+    const int sub = threadIdx.x & (DG_LPC - 1);
+    const int64_t per = (int64_t)blockDim.x / DG_LPC;
+    for (int64_t j = blockIdx.x * per + threadIdx.x / DG_LPC; j - (threadIdx.x / DG_LPC) < n_al * DG_COLS;
+         j += (int64_t)gridDim.x * per) {
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        for (int64_t l = l0; l < l1; ++l) {
-            const double W = wr[2 * l], WR = wr[2 * l + 1];
-            const double x = geo_x(mu[l]);
-            s0 += W;
-            s1 += W * shifted_legendre(1, x);
-            s2 += W * shifted_legendre(2, x);
-            s3 -= WR;
+        const bool in = j < n_al * DG_COLS;
+        if (in) {
+            const int64_t g = j / DG_COLS, c = j - g * DG_COLS;
+            const int64_t l0 = coff[g * (DG_COLS + 1) + c], l1 = coff[g * (DG_COLS + 1) + c + 1];
+            for (int64_t l = l0 + sub; l < l1; l += DG_LPC) {
+                const double W = wr[2 * l], WR = wr[2 * l + 1];
+                const double x = geo_x(mu[l]);
+                s0 += W;
+                s1 += W * shifted_legendre(1, x);
+                s2 += W * shifted_legendre(2, x);
+                s3 -= WR;
+            }
         }
-        double* o = colsum + 4 * j;
-        o[0] = s0;
-        o[1] = s1;
-        o[2] = s2;
-        o[3] = s3;
+#pragma unroll
+        for (int m = DG_LPC / 2; m >= 1; m >>= 1) {
+            s0 += __shfl_xor(s0, m, DG_LPC);
+            s1 += __shfl_xor(s1, m, DG_LPC);
+            s2 += __shfl_xor(s2, m, DG_LPC);
+            s3 += __shfl_xor(s3, m, DG_LPC);
+        }
+        if (in && sub == 0) {
+            double* o = colsum + 4 * j;
+            o[0] = s0;
+            o[1] = s1;
+            o[2] = s2;
+            o[3] = s3;
+        }
     }
 }
 
 // Per block (long interval k, CCD n; blk = k n_ccd + n) and column: the
 // diagonal D_m = sum W and the right-hand side -sum W R of the small-scale
-// value, over the interval's cells in order: dcol[(blk * 1966 + c) * 2].
+// value, over the interval's cells in order, and the column's scale
+// 1 / sqrt(D_m) (0 for a column without records): dcol[(blk * 1966 + c) * 4].
 __global__ void k_dg_colred(int64_t n_blk, int32_t n_ccd, int32_t days, int64_t n_cells,
                             const double* __restrict__ colsum, double* __restrict__ dcol) {
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n_blk * DG_COLS;
@@ -318,14 +336,16 @@ __global__ void k_dg_colred(int64_t n_blk, int32_t n_ccd, int32_t days, int64_t 
             d += s[0];
             r += s[3];
         }
-        dcol[2 * j] = d;
-        dcol[2 * j + 1] = r;
+        dcol[4 * j] = d;
+        dcol[4 * j + 1] = r;
+        dcol[4 * j + 2] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+        dcol[4 * j + 3] = 0.0;
     }
 }
 
 constexpr int DG_NT = 512;          // threads of the block solve
 constexpr int DG_T = 6;             // side of a thread's tile of the accumulated matrix
-constexpr int DG_CH = 8;            // columns staged in LDS at a time
+constexpr int DG_CH = 32;           // columns staged in LDS at a time
 constexpr int DG_NE_MAX = 180;      // cells' coefficients of a block: 60 cells, 30 days
 constexpr int DG_NP_MAX = 186;      // with the three polynomials and the right-hand side, to a multiple of 6
 
@@ -368,7 +388,7 @@ __global__ __launch_bounds__(DG_NT) void k_dg_block(int32_t n_ccd, int32_t days,
     double* gw = act + ne;                            // spare [ne]
     double* hs = gw + ne;                             // H^-1 [9], w = H^-1 C'D^-1 b [3], nu [3]
     (void)gw;
-    const double* dc = dcol + 2 * blk * DG_COLS;
+    const double* dc = dcol + 4 * blk * DG_COLS;
     auto colv = [&](int i, int m) -> double {          // B_m entry of row i (< ne)
         const int cell = i / 3, r = i - 3 * cell;
         return colsum[4 * (((c0 + cell) * n_ccd + nn) * DG_COLS + m) + r];
@@ -383,24 +403,37 @@ __global__ __launch_bounds__(DG_NT) void k_dg_block(int32_t n_ccd, int32_t days,
 #pragma unroll
     for (int e = 0; e < DG_T * DG_T; ++e) acc[e] = 0.0;
     double* stage = lds;                              // DG_CH staged vectors (before Z is written)
+    // Staging: thread t fills entry i = t % np of the columns m0 + t / np,
+    // m0 + t / np + rows, ... (rows = DG_NT / np vectors at a time), so that
+    // its source is fixed: a cell's column sums (i < ne), a polynomial, or
+    // the right-hand side; loads without branches on the data.
+    const int rows = DG_NT / np, srow = tid / np, si = tid - srow * np;
+    const bool stager = srow < rows;
+    const int kind = si < ne ? 0 : (si < ne + 3 ? 1 : (si == ne + 3 ? 2 : 3));
+    const double* src = kind == 0 ? colsum + 4 * ((c0 + si / 3) * n_ccd + nn) * DG_COLS + (si - 3 * (si / 3))
+                                  : dc + 1;
+    auto zval = [&](int m) -> double {               // z_m[si] for column m (0 past the last column)
+        const int mc = m < DG_COLS ? m : DG_COLS - 1;
+        const double s = m < DG_COLS ? dc[4 * mc + 2] : 0.0;
+        const double x = ((double)(mc + 14) - 13.5) / 1966.0;
+        const double v = kind == 1 ? shifted_legendre(si - ne, x) : (kind == 3 ? 0.0 : src[4 * mc]);
+        return v * s;
+    };
+    constexpr int PF = (DG_CH + 1) / 2;               // vectors per stager: rows >= 2 (np <= 186)
+    double pf[PF];                                    // the next stage, loaded during the current one
+#pragma unroll
+    for (int q = 0; q < PF; ++q) pf[q] = stager && srow + q * rows < DG_CH ? zval(srow + q * rows) : 0.0;
     for (int m0 = 0; m0 < DG_COLS; m0 += DG_CH) {
         __syncthreads();
-        for (int e = tid; e < DG_CH * np; e += DG_NT) {
-            const int mm = e / np, i = e - mm * np, m = m0 + mm;
-            double v = 0.0;
-            if (m < DG_COLS) {
-                const double D = dc[2 * m];
-                if (D > 0.0) {
-                    const double s = 1.0 / sqrt(D);
-                    const double x = ((double)(m + 14) - 13.5) / 1966.0;
-                    if (i < ne) v = colv(i, m) * s;
-                    else if (i < ne + 3) v = shifted_legendre(i - ne, x) * s;
-                    else if (i == ne + 3) v = dc[2 * m + 1] * s;
-                }
-            }
-            stage[e] = v;
-        }
+#pragma unroll
+        for (int q = 0; q < PF; ++q)
+            if (stager && srow + q * rows < DG_CH) stage[(srow + q * rows) * np + si] = pf[q];
         __syncthreads();
+        if (m0 + DG_CH < DG_COLS) {
+#pragma unroll
+            for (int q = 0; q < PF; ++q)
+                pf[q] = stager && srow + q * rows < DG_CH ? zval(m0 + DG_CH + srow + q * rows) : 0.0;
+        }
         if (own) {
 #pragma unroll 2
             for (int mm = 0; mm < DG_CH; ++mm) {
@@ -488,37 +521,78 @@ __global__ __launch_bounds__(DG_NT) void k_dg_block(int32_t n_ccd, int32_t days,
         ex[i] = v;
     }
     __syncthreads();
-    // --- modified Cholesky A = L L' (right-looking, the factor over A's lower triangle)
+    // --- modified Cholesky A = L L' (right-looking over A's lower triangle):
+    // step p leaves column p as it is and updates the trailing entries by
+    // A_ij -= A_ip (A_jp / A_pp) when the pivot A_pp is positive (else column
+    // p is zero); afterwards each column is divided by the square root of
+    // its pivot, which gives L (a column with a pivot that is not positive
+    // becomes zero).  One barrier per step.
     for (int p = 0; p < ne; ++p) {
         const double piv = Z[pk(p, p)];
-        const double d = piv > 0.0 ? sqrt(piv) : 0.0;
-        for (int i = p + 1 + tid; i < ne; i += DG_NT) Z[pk(i, p)] = d > 0.0 ? Z[pk(i, p)] / d : 0.0;
-        __syncthreads();
-        const int rem = ne - p - 1;
-        for (int e = tid; e < rem * rem; e += DG_NT) {
-            const int i = p + 1 + e / rem, j = p + 1 + (e - (e / rem) * rem);
-            if (j <= i) Z[pk(i, j)] -= Z[pk(i, p)] * Z[pk(j, p)];
+        if (piv > 0.0) {
+            const double ip = 1.0 / piv;
+            const int rem = ne - p - 1, n_tri = rem * (rem + 1) / 2;
+            for (int t = tid; t < n_tri; t += DG_NT) {
+                // trailing entry t of the packed lower triangle: row a, column b <= a
+                int a = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+                if ((a + 1) * (a + 2) / 2 <= t) ++a;
+                if (a * (a + 1) / 2 > t) --a;
+                const int i = p + 1 + a, j = p + 1 + (t - a * (a + 1) / 2);
+                Z[pk(i, j)] -= Z[pk(i, p)] * (Z[pk(j, p)] * ip);
+            }
         }
-        if (tid == 0) Z[pk(p, p)] = d;
         __syncthreads();
     }
-    // --- L y = rhs, then L' e = y (a zero pivot gives a zero unknown)
-    for (int p = 0; p < ne; ++p) {
-        const double d = Z[pk(p, p)];
-        const double y = d > 0.0 ? ex[p] / d : 0.0;
-        __syncthreads();
-        if (tid == 0) ex[p] = y;
-        for (int i = p + 1 + tid; i < ne; i += DG_NT) ex[i] -= Z[pk(i, p)] * y;
-        __syncthreads();
+    for (int e = tid; e < ne * ne; e += DG_NT) {
+        const int i = e / ne, j = e - i * ne;
+        if (j >= i) continue;
+        const double piv = Z[pk(j, j)];
+        Z[pk(i, j)] = piv > 0.0 ? Z[pk(i, j)] / sqrt(piv) : 0.0;
     }
-    for (int p = ne - 1; p >= 0; --p) {
-        const double d = Z[pk(p, p)];
-        const double x = d > 0.0 ? ex[p] / d : 0.0;
-        __syncthreads();
-        if (tid == 0) ex[p] = x;
-        for (int i = tid; i < p; i += DG_NT) ex[i] -= Z[pk(p, i)] * x;
-        __syncthreads();
+    __syncthreads();
+    for (int p = tid; p < ne; p += DG_NT) {
+        const double piv = Z[pk(p, p)];
+        Z[pk(p, p)] = piv > 0.0 ? sqrt(piv) : 0.0;
     }
+    __syncthreads();
+    // --- L y = rhs, then L' e = y (a zero pivot gives a zero unknown): one
+    // wavefront, row i in lane i % 64, slot i / 64, of registers; the pivot
+    // row's value broadcast by a shuffle
+    if (tid < 64) {
+        double xr[3];
+#pragma unroll
+        for (int s = 0; s < 3; ++s) xr[s] = tid + 64 * s < ne ? ex[tid + 64 * s] : 0.0;
+        for (int p = 0; p < ne; ++p) {
+            const int slot = p >> 6;
+            const double mine = slot == 0 ? xr[0] : (slot == 1 ? xr[1] : xr[2]);
+            const double xp = __shfl(mine, p & 63, 64);
+            const double d = Z[pk(p, p)];
+            const double y = d > 0.0 ? xp / d : 0.0;
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                const int i = tid + 64 * s;
+                if (i == p) xr[s] = y;
+                else if (i > p && i < ne) xr[s] -= Z[pk(i, p)] * y;
+            }
+        }
+        for (int p = ne - 1; p >= 0; --p) {
+            const int slot = p >> 6;
+            const double mine = slot == 0 ? xr[0] : (slot == 1 ? xr[1] : xr[2]);
+            const double yp = __shfl(mine, p & 63, 64);
+            const double d = Z[pk(p, p)];
+            const double x = d > 0.0 ? yp / d : 0.0;
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                const int i = tid + 64 * s;
+                if (i == p) xr[s] = x;
+                else if (i < p) xr[s] -= Z[pk(p, i)] * x;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
+            if (tid + 64 * s < ne) ex[tid + 64 * s] = xr[s];
+    }
+    __syncthreads();
     // --- nu = H^-1 (C'D^-1 b - G'e)
     if (tid == 0) {
         double q[3];
@@ -533,12 +607,20 @@ __global__ __launch_bounds__(DG_NT) void k_dg_block(int32_t n_ccd, int32_t days,
     // --- the cells' coefficients and the small-scale values
     for (int i = tid; i < ne; i += DG_NT) dgeo[3 * ((c0 + i / 3) * n_ccd + nn) + (i - 3 * (i / 3))] = ex[i];
     for (int m = tid; m < DG_COLS; m += DG_NT) {
-        const double D = dc[2 * m];
+        const double D = dc[4 * m];
         double v = 0.0;
         if (D > 0.0) {
             const double x = ((double)(m + 14) - 13.5) / 1966.0;
-            v = dc[2 * m + 1];
-            for (int i = 0; i < ne; ++i) v -= colv(i, m) * ex[i];
+            // B_m e over the cells, each cell's column sums one 32-byte load,
+            // four partial sums
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+            for (int cell = 0; cell < nc; ++cell) {
+                const double4 b = *reinterpret_cast<const double4*>(
+                    colsum + 4 * (((c0 + cell) * n_ccd + nn) * DG_COLS + m));
+                acc[cell & 3] += b.x * ex[3 * cell] + b.y * ex[3 * cell + 1] + b.z * ex[3 * cell + 2];
+            }
+            v = dc[4 * m + 1] - ((acc[0] + acc[1]) + (acc[2] + acc[3]));
 #pragma unroll
             for (int s = 0; s < 3; ++s) v -= shifted_legendre(s, x) * hs[12 + s];
             v /= D;
@@ -587,8 +669,8 @@ void launch_geo_solve(agis_ctx* ctx) {
     if (small) {
         // the AL groups with the small-scale values, by block (eq:cc2 inside)
         const int64_t n_al = ctx->n_cells * ctx->geo_ccds, n_blk = ctx->n_small / DG_COLS;
-        k_dg_colsums<<<grid_for(n_al * DG_COLS), 256, 0, ctx->stream>>>(n_al, ctx->geo_coff, ctx->geo_mu_g,
-                                                                       ctx->geo_wr, ctx->geo_colsum);
+        k_dg_colsums<<<grid_for(n_al * DG_COLS * DG_LPC), 256, 0, ctx->stream>>>(n_al, ctx->geo_coff, ctx->geo_mu_g,
+                                                                                ctx->geo_wr, ctx->geo_colsum);
         k_dg_colred<<<grid_for(n_blk * DG_COLS), 256, 0, ctx->stream>>>(n_blk, ctx->geo_ccds, ctx->geo_small_days,
                                                                        ctx->n_cells, ctx->geo_colsum, ctx->geo_dcol);
         k_dg_block<<<(unsigned)n_blk, DG_NT, dg_lds_bytes(3 * 2 * ctx->geo_small_days), ctx->stream>>>(
@@ -743,7 +825,7 @@ int load_geometry(agis_ctx* ctx, const int8_t* ccd, const float* mu, int32_t n_c
         if (small_days > 0 &&
             ((rc = dalloc(ctx, &ctx->geo_coff, (size_t)(n_al * (DG_COLS + 1)), "column offsets")) ||
              (rc = dalloc(ctx, &ctx->geo_colsum, (size_t)(4 * n_al * DG_COLS), "column sums")) ||
-             (rc = dalloc(ctx, &ctx->geo_dcol, (size_t)(2 * n_small), "small-scale diagonal"))))
+             (rc = dalloc(ctx, &ctx->geo_dcol, (size_t)(4 * n_small), "small-scale diagonal"))))
             return fail(rc);
     }
     hipError_t e = hipMemsetAsync(ctx->geo_flags, 0, sizeof(int), st);
