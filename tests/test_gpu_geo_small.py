@@ -6,8 +6,9 @@ library with the oracle, through the C ABI, on the 60-day nine-CCD world
 * Residuals with non-zero small-scale values: within the residual bound of
   the plain parity test.
 * One C update from the start values (large-scale terms ~25 mas off,
-  small-scale values zero), with noise, with the along-scan terms and with
-  the across-scan term too: every coefficient within the FP64-floor
+  small-scale values zero), with noise, with the along-scan terms, with the
+  across-scan term too, and in robust mode with 1% outliers (the A/C
+  weights downweight them): every coefficient within the FP64-floor
   criterion of the other parity tests (extended-precision oracle as
   reference); eq:cc1 and eq:cc2 hold.
 * Two S[AC] iterations with the frame rotator, with across-scan records and
@@ -51,10 +52,11 @@ def _legendre_columns():
     return np.stack([np.ones_like(x), 2.0 * x - 1.0, 6.0 * x * x - 6.0 * x + 1.0], axis=1)
 
 
-@pytest.fixture(scope="module", params=["AL terms", "AL and AC terms"])
+@pytest.fixture(scope="module", params=["AL terms", "AL and AC terms", "robust, AL and AC terms"])
 def geo9_small(oracle_lib, request):
-    both = request.param == "AL and AC terms"
-    w = C.make("geo9", geo_small=True, ac_obs=both, geo_ac=both)
+    both = "AC" in request.param
+    robust = {"robust": True, "outlier_frac": 0.01} if request.param.startswith("robust") else {}
+    w = C.make("geo9", geo_small=True, ac_obs=both, geo_ac=both, **robust)
     return w, oracle_lib.observed_field_angles(w)
 
 
