@@ -133,6 +133,7 @@ struct agis_ctx {
     int64_t n_small = 0;
     int32_t* geo_coff = nullptr;         // [n_cells geo_ccds][1967] column ranges of the AL groups
     double* geo_colsum = nullptr;        // [n_cells geo_ccds][1966][4] column sums of the last C update
+    double* geo_zpart = nullptr;         // [K geo_ccds][parts][packed triangle] partial sums of the block solve
     double* geo_dcol = nullptr;          // [K geo_ccds][1966][4] block diagonal, right-hand side, 1 / sqrt(diagonal)
     int32_t* seg_def = nullptr;          // [n_seg]
     std::vector<agis::SegDesc> h_segs;

@@ -122,6 +122,7 @@ static void free_store(agis_ctx* ctx) {
     dfree(ctx->geo_coff);
     dfree(ctx->geo_colsum);
     dfree(ctx->geo_dcol);
+    dfree(ctx->geo_zpart);
     ctx->geo_ccds = 0;
     ctx->geo_ac_cells = 0;
     ctx->geo_small_days = 0;

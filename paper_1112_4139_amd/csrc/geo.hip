@@ -356,43 +356,25 @@ __host__ __device__ constexpr size_t dg_lds_bytes(int ne) {
     return (size_t)(dg_packed(dg_np(ne)) + 3 * ne + 16) * sizeof(double);
 }
 __device__ __forceinline__ int64_t pk(int i, int j) { return (int64_t)i * (i + 1) / 2 + j; }   // i >= j
+constexpr int DG_SPAN = 256;                                    // columns of an accumulation part
+constexpr int DG_PARTS = (DG_COLS + DG_SPAN - 1) / DG_SPAN;     // accumulation parts per block
+constexpr int64_t DG_PACK = dg_packed(DG_NP_MAX);               // stride of a part's packed triangle
 
-// The C update of one block (long interval k, CCD n; one workgroup each):
-// with z_m = [B_m, L*_0..2(x_m), b_m] / sqrt(D_m) over the active columns
-// (D_m > 0; B_m: the column's sums W L_r of each cell of the block, b_m: -sum
-// W R), Z = sum_m z_m z_m' (lower triangle, packed, in LDS) holds B'D^-1 B,
-// G = B'D^-1 C, H = C'D^-1 C, B'D^-1 b and C'D^-1 b.  Eliminating the
-// small-scale values d = D^-1 (b - B e - C nu) and the eq:cc2 multipliers
-// nu = H^-1 (C'D^-1 b - G'e) leaves, for the cells' coefficients e,
-//     (E - B'D^-1 B + G H^-1 G') e = b_e - B'D^-1 b + G H^-1 C'D^-1 b,
-// E and b_e the groups' 3x3 sums (k_geo_sums); a cell without records keeps
-// e = 0.  That system goes through the modified Cholesky (a pivot that is
-// not positive gives a zero column and a zero unknown) and two triangular
-// solves, then nu and d follow.  Writes the cells' three coefficients and the
-// block's 1966 small-scale values of dgeo (0 for a column without records).
-__global__ __launch_bounds__(DG_NT) void k_dg_block(int32_t n_ccd, int32_t days, int64_t n_cells,
-                                                    const int64_t* __restrict__ off,
+// The accumulation of the block solve, split over DG_PARTS workgroups per
+// block: workgroup (blk, part) sums z_m z_m' over the columns part * DG_SPAN
+// .. (part + 1) * DG_SPAN - 1 (z_m as in k_dg_block; 0 past the last column)
+// into zpart[(blk * DG_PARTS + part) * DG_PACK], the packed lower triangle.
+__global__ __launch_bounds__(DG_NT) void k_dg_accum(int32_t n_ccd, int32_t days, int64_t n_cells,
                                                     const double* __restrict__ colsum,
                                                     const double* __restrict__ dcol,
-                                                    const double* __restrict__ sums, int64_t small,
-                                                    double* __restrict__ dgeo) {
-    extern __shared__ double lds[];
-    const int64_t blk = blockIdx.x;
+                                                    double* __restrict__ zpart) {
+    const int64_t blk = blockIdx.x / DG_PARTS;
+    const int part = (int)(blockIdx.x - blk * DG_PARTS), mb = part * DG_SPAN;
     const int64_t k = blk / n_ccd, nn = blk - k * n_ccd;
     const int64_t c0 = 2 * k * days, c1 = min<int64_t>(c0 + 2 * (int64_t)days, n_cells);
     const int nc = (int)(c1 - c0), ne = 3 * nc, np = dg_np(ne);
     const int tid = threadIdx.x;
-    double* Z = lds;                                  // packed lower triangle, np x np
-    double* ex = lds + dg_packed(np);                 // the cells' right-hand side, then solution [ne]
-    double* act = ex + ne;                            // 1: the cell of row i has records [ne]
-    double* gw = act + ne;                            // spare [ne]
-    double* hs = gw + ne;                             // H^-1 [9], w = H^-1 C'D^-1 b [3], nu [3]
-    (void)gw;
     const double* dc = dcol + 4 * blk * DG_COLS;
-    auto colv = [&](int i, int m) -> double {          // B_m entry of row i (< ne)
-        const int cell = i / 3, r = i - 3 * cell;
-        return colsum[4 * (((c0 + cell) * n_ccd + nn) * DG_COLS + m) + r];
-    };
     // --- Z = sum_m z_m z_m', a 6x6 tile of the lower triangle per thread
     const int ntile = np / DG_T;
     int ti = 0;
@@ -402,7 +384,7 @@ __global__ __launch_bounds__(DG_NT) void k_dg_block(int32_t n_ccd, int32_t days,
     double acc[DG_T * DG_T];
 #pragma unroll
     for (int e = 0; e < DG_T * DG_T; ++e) acc[e] = 0.0;
-    double* stage = lds;                              // DG_CH staged vectors (before Z is written)
+    __shared__ double stage[DG_CH * DG_NP_MAX];      // DG_CH staged vectors
     // Staging: thread t fills entry i = t % np of the columns m0 + t / np,
     // m0 + t / np + rows, ... (rows = DG_NT / np vectors at a time), so that
     // its source is fixed: a cell's column sums (i < ne), a polynomial, or
@@ -422,14 +404,14 @@ __global__ __launch_bounds__(DG_NT) void k_dg_block(int32_t n_ccd, int32_t days,
     constexpr int PF = (DG_CH + 1) / 2;               // vectors per stager: rows >= 2 (np <= 186)
     double pf[PF];                                    // the next stage, loaded during the current one
 #pragma unroll
-    for (int q = 0; q < PF; ++q) pf[q] = stager && srow + q * rows < DG_CH ? zval(srow + q * rows) : 0.0;
-    for (int m0 = 0; m0 < DG_COLS; m0 += DG_CH) {
+    for (int q = 0; q < PF; ++q) pf[q] = stager && srow + q * rows < DG_CH ? zval(mb + srow + q * rows) : 0.0;
+    for (int m0 = mb; m0 < mb + DG_SPAN; m0 += DG_CH) {
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < PF; ++q)
             if (stager && srow + q * rows < DG_CH) stage[(srow + q * rows) * np + si] = pf[q];
         __syncthreads();
-        if (m0 + DG_CH < DG_COLS) {
+        if (m0 + DG_CH < mb + DG_SPAN) {
 #pragma unroll
             for (int q = 0; q < PF; ++q)
                 pf[q] = stager && srow + q * rows < DG_CH ? zval(m0 + DG_CH + srow + q * rows) : 0.0;
@@ -451,15 +433,57 @@ __global__ __launch_bounds__(DG_NT) void k_dg_block(int32_t n_ccd, int32_t days,
             }
         }
     }
-    __syncthreads();
     if (own) {
+        double* zp = zpart + ((int64_t)blk * DG_PARTS + part) * DG_PACK;
 #pragma unroll
         for (int p = 0; p < DG_T; ++p)
 #pragma unroll
             for (int q = 0; q < DG_T; ++q) {
                 const int i = DG_T * ti + p, j = DG_T * tj + q;
-                if (i >= j) Z[pk(i, j)] = acc[p * DG_T + q];
+                if (i >= j) zp[pk(i, j)] = acc[p * DG_T + q];
             }
+    }
+}
+
+// The C update of one block (long interval k, CCD n; one workgroup each):
+// with z_m = [B_m, L*_0..2(x_m), b_m] / sqrt(D_m) over the active columns
+// (D_m > 0; B_m: the column's sums W L_r of each cell of the block, b_m: -sum
+// W R), Z = sum_m z_m z_m' (lower triangle, packed, in LDS; the sum of
+// k_dg_accum's partial sums over column ranges) holds B'D^-1 B,
+// G = B'D^-1 C, H = C'D^-1 C, B'D^-1 b and C'D^-1 b.  Eliminating the
+// small-scale values d = D^-1 (b - B e - C nu) and the eq:cc2 multipliers
+// nu = H^-1 (C'D^-1 b - G'e) leaves, for the cells' coefficients e,
+//     (E - B'D^-1 B + G H^-1 G') e = b_e - B'D^-1 b + G H^-1 C'D^-1 b,
+// E and b_e the groups' 3x3 sums (k_geo_sums); a cell without records keeps
+// e = 0.  That system goes through the modified Cholesky (a pivot that is
+// not positive gives a zero column and a zero unknown) and two triangular
+// solves, then nu and d follow.  Writes the cells' three coefficients and the
+// block's 1966 small-scale values of dgeo (0 for a column without records).
+__global__ __launch_bounds__(DG_NT) void k_dg_block(int32_t n_ccd, int32_t days, int64_t n_cells,
+                                                    const int64_t* __restrict__ off,
+                                                    const double* __restrict__ colsum,
+                                                    const double* __restrict__ dcol,
+                                                    const double* __restrict__ zpart,
+                                                    const double* __restrict__ sums, int64_t small,
+                                                    double* __restrict__ dgeo) {
+    extern __shared__ double lds[];
+    const int64_t blk = blockIdx.x;
+    const int64_t k = blk / n_ccd, nn = blk - k * n_ccd;
+    const int64_t c0 = 2 * k * days, c1 = min<int64_t>(c0 + 2 * (int64_t)days, n_cells);
+    const int nc = (int)(c1 - c0), ne = 3 * nc, np = dg_np(ne);
+    const int tid = threadIdx.x;
+    double* Z = lds;                                  // packed lower triangle, np x np
+    double* ex = lds + dg_packed(np);                 // the cells' right-hand side, then solution [ne]
+    double* act = ex + ne;                            // 1: the cell of row i has records [ne]
+    double* gw = act + ne;                            // spare [ne]
+    double* hs = gw + ne;                             // H^-1 [9], w = H^-1 C'D^-1 b [3], nu [3]
+    (void)gw;
+    const double* dc = dcol + 4 * blk * DG_COLS;
+    // --- Z = sum_m z_m z_m' from the partial sums of k_dg_accum, in order
+    for (int64_t e = tid; e < dg_packed(np); e += DG_NT) {
+        double v = 0.0;
+        for (int part = 0; part < DG_PARTS; ++part) v += zpart[((int64_t)blk * DG_PARTS + part) * DG_PACK + e];
+        Z[e] = v;
     }
     for (int i = tid; i < ne; i += DG_NT) {
         const int64_t g = (c0 + i / 3) * n_ccd + nn;
@@ -673,9 +697,11 @@ void launch_geo_solve(agis_ctx* ctx) {
                                                                                 ctx->geo_wr, ctx->geo_colsum);
         k_dg_colred<<<grid_for(n_blk * DG_COLS), 256, 0, ctx->stream>>>(n_blk, ctx->geo_ccds, ctx->geo_small_days,
                                                                        ctx->n_cells, ctx->geo_colsum, ctx->geo_dcol);
+        k_dg_accum<<<(unsigned)(n_blk * DG_PARTS), DG_NT, 0, ctx->stream>>>(
+            ctx->geo_ccds, ctx->geo_small_days, ctx->n_cells, ctx->geo_colsum, ctx->geo_dcol, ctx->geo_zpart);
         k_dg_block<<<(unsigned)n_blk, DG_NT, dg_lds_bytes(3 * 2 * ctx->geo_small_days), ctx->stream>>>(
             ctx->geo_ccds, ctx->geo_small_days, ctx->n_cells, ctx->geo_off, ctx->geo_colsum, ctx->geo_dcol,
-            ctx->geo_sums, 3 * ctx->n_groups, ctx->dgeo);
+            ctx->geo_zpart, ctx->geo_sums, 3 * ctx->n_groups, ctx->dgeo);
     }
     k_geo_solve<<<grid_for(n_days), 256, 0, ctx->stream>>>(n_days, 0, 2 * ctx->geo_ccds, !small, ctx->geo_sums,
                                                            ctx->dgeo);
@@ -817,6 +843,7 @@ int load_geometry(agis_ctx* ctx, const int8_t* ccd, const float* mu, int32_t n_c
         dfree(ctx->geo_coff);
         dfree(ctx->geo_colsum);
         dfree(ctx->geo_dcol);
+        dfree(ctx->geo_zpart);
         if ((rc = dalloc(ctx, &ctx->geo, (size_t)std::max<int64_t>(n_coef, 1), "geometric calibration")) ||
             (rc = dalloc(ctx, &ctx->dgeo, (size_t)std::max<int64_t>(n_coef, 1), "geometric update")) ||
             (rc = dalloc(ctx, &ctx->geo_sums, (size_t)std::max<int64_t>(9 * ng, 1), "geometric sums")) ||
@@ -825,7 +852,9 @@ int load_geometry(agis_ctx* ctx, const int8_t* ccd, const float* mu, int32_t n_c
         if (small_days > 0 &&
             ((rc = dalloc(ctx, &ctx->geo_coff, (size_t)(n_al * (DG_COLS + 1)), "column offsets")) ||
              (rc = dalloc(ctx, &ctx->geo_colsum, (size_t)(4 * n_al * DG_COLS), "column sums")) ||
-             (rc = dalloc(ctx, &ctx->geo_dcol, (size_t)(4 * n_small), "small-scale diagonal"))))
+             (rc = dalloc(ctx, &ctx->geo_dcol, (size_t)(4 * n_small), "small-scale diagonal")) ||
+             (rc = dalloc(ctx, &ctx->geo_zpart, (size_t)(n_small / DG_COLS * DG_PARTS * DG_PACK),
+                          "small-scale partial sums"))))
             return fail(rc);
     }
     hipError_t e = hipMemsetAsync(ctx->geo_flags, 0, sizeof(int), st);
