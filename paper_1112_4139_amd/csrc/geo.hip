@@ -27,13 +27,14 @@
 // m = round(mu), 1966 a block.  It shares every record with the AL groups
 // of its CCD and interval, so a block (CCD, interval) is solved as one
 // system: the along-scan groups' records are ordered by column within a
-// group as well; one thread per group and column sums W, W L_1, W L_2 and
+// group as well; eight lanes per group and column sum W, W L_1, W L_2 and
 // -W R over its records; one thread per block and column adds the block's
-// cells; one workgroup per block eliminates the diagonal small-scale part
-// and the three eq:cc2 multipliers in closed form and solves the remaining
-// system of the cells' 3 n_cells coefficients (at most 180) by the modified
-// Cholesky in LDS, then the small-scale values by back substitution.  The
-// eq:cc1 projection follows as without the term.
+// cells; eight workgroups per block sum the reduced normal matrix over
+// column ranges; one workgroup per block adds them, eliminates the diagonal
+// small-scale part and the three eq:cc2 multipliers in closed form and
+// solves the remaining system of the cells' 3 n_cells coefficients (at most
+// 180) by the modified Cholesky in LDS, then the small-scale values by back
+// substitution.  The eq:cc1 projection follows as without the term.
 #include <hipcub/hipcub.hpp>
 
 #include "agis_internal.h"
