@@ -19,6 +19,8 @@ library with the oracle, through the C ABI, on the 60-day nine-CCD world
   coefficients within the criterion.
 * The graph-replayed iteration is bitwise the eager one (same world).
 * The arguments it refuses.
+* With the Sun's light deflection and the global block too: two S[ACG]
+  iterations on the same world, g0 included.
 """
 import numpy as np
 import pytest
@@ -163,3 +165,35 @@ def test_small_graph_bitwise_and_refusals(agis_mod, oracle_lib, tiny_small):
         agis_mod.agis_set_geo_calibration(e, np.zeros(pr.geo.size - COLS))
     for c in (e, g):
         agis_mod.agis_destroy(c)
+
+
+def test_small_with_global_block_parity(agis_mod, oracle_lib):
+    """All three geometric terms with the Sun's light deflection and the
+    global block (S[ACG], Sect. 5.4): two iterations with the frame rotator on
+    the 360-day tiny world; sources, attitude, coefficients and g0 within the
+    criterion (g0 by its per-parameter bound alone, as in the global-block
+    tests)."""
+    from test_gpu_ppn import check_g0
+    w = C.make("tiny", years=360 / 365.25, geo_cal=True, geo_small=True, ac_obs=True, geo_ac=True, ppn=True)
+    eta = oracle_lib.observed_field_angles(w)
+    n_it = 2
+
+    def run(pr):
+        for _ in range(n_it):
+            pr.iterate(s_ref=w.src_true)
+        return pr.s.copy(), pr.a.copy(), np.concatenate([pr.geo, [pr.g0]])
+
+    X, O, tol = fp64_floor(oracle_lib, w, eta, run)
+    pr = oracle_lib.problem_from_world(w, eta, state="start")
+    ctx = _ctx(agis_mod, w, eta, pr)
+    agis_mod.agis_set_global(ctx, w.g0_start)
+    agis_mod.agis_set_frame_reference(ctx, w.src_true)
+    agis_mod.agis_iterate(ctx, n_it, stats=False)
+    G = (agis_mod.agis_get_sources(ctx, w.src_true.shape[0]), agis_mod.agis_get_attitude(ctx, w.n_att),
+         agis_mod.agis_get_geo_calibration(ctx, pr.geo.size))
+    g0 = agis_mod.agis_get_global(ctx)[0]
+    check_floor("geometric terms with S[ACG]: sources", X[0], O[0], G[0], tol[0], 0)
+    check_floor("geometric terms with S[ACG]: attitude", X[1], O[1], G[1], tol[1], 1)
+    check_floor("geometric terms with S[ACG]: coefficients", X[2][:-1], O[2][:-1], G[2], tol[2][:-1], 2)
+    check_g0("geometric terms with S[ACG]: g0", float(X[2][-1]), float(O[2][-1]), g0, float(tol[2][-1]))
+    agis_mod.agis_destroy(ctx)
