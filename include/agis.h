@@ -279,6 +279,14 @@ int agis_load_geometry(agis_ctx_t* ctx, int64_t n, const int8_t* ccd, const floa
                        const int32_t* ac_cell, int32_t n_ac_cells, int32_t small_days, int where);
 int agis_set_geo_calibration(agis_ctx_t* ctx, int64_t n, const double* c, int where);
 int agis_get_geo_calibration(agis_ctx_t* ctx, int64_t n, double* c, int where);
+/* The basic-angle offset per short interval (day) j, a monitored quantity
+ * and not a parameter (Sect. 3.4, eq:DeltaGamma): the mean over the AF CCDs
+ * of the preceding field of view's AL constant term minus the following
+ * one's, (1/n_ccd) sum_n (c_0(P, n, j) - c_0(F, n, j)), which the paper
+ * writes with its 62 AF CCDs.  out [n_days] (n_days = n_cells / 2) [rad],
+ * host or device memory by `where`; AGIS_E_STATE without the geometric
+ * calibration, AGIS_E_SHAPE on a count mismatch. */
+int agis_basic_angle(agis_ctx_t* ctx, int64_t n_days, double* out, int where);
 
 /* S block (Sect. 5.1): per source, eq:normS with the design matrix of
  * eq:designS at the current (s, a, c), solved by Algorithms C1-C3;

@@ -490,6 +490,18 @@ def problem_from_world(world, eta_obs=None, state="start", precision="double"):
                    g0=getattr(world, f"g0_{which}", 0.0))
 
 
+def basic_angle(geo, n_cells, n_ccd):
+    """The basic-angle offset of each short interval (day), a monitored
+    quantity (Sect. 3.4, eq:DeltaGamma): over the AF CCDs, the sum of f times
+    the AL constant term of field of view f (f = +1 preceding, the day's even
+    cell; -1 following, its odd cell) divided by the number of AF CCDs (62 in
+    the paper, n_ccd here).  geo: the flat coefficients, AL groups first
+    ([n_cells][n_ccd][3])."""
+    c0 = np.asarray(geo, dtype=np.float64)[:3 * n_cells * n_ccd].reshape(n_cells // 2, 2, n_ccd, 3)[:, :, :, 0]
+    f = np.array([1.0, -1.0])
+    return np.einsum("f,jfn->j", f, c0) / n_ccd
+
+
 def world_geo(world, which="true"):
     """The world's geometric coefficients (true or start): AL, then AC and
     small-scale where the world has them; None without the geometric model."""

@@ -80,6 +80,7 @@ _sig = {
     "agis_set_calibration": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
     "agis_get_calibration": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
     "agis_load_geometry": ([_ctx_p, c_i64, _vp, _vp, c_i32, _vp, c_i32, c_i32, ctypes.c_int], ctypes.c_int),
+    "agis_basic_angle": ([_ctx_p, c_i64, _vp, ctypes.c_int], ctypes.c_int),
     "agis_global_update": ([_ctx_p, P(c_d)], ctypes.c_int),
     "agis_set_global": ([_ctx_p, c_d], ctypes.c_int),
     "agis_get_global": ([_ctx_p, P(c_d)], ctypes.c_int),
@@ -250,6 +251,14 @@ def agis_load_geometry(ctx, ccd, mu, n_ccd, ac_cell=None, n_ac_cells=0, small_da
         raise ValueError("ccd, mu and ac_cell must all be host arrays or all device tensors")
     _check(_lib.agis_load_geometry(ctx, int(len(ccd)), pc, pm, int(n_ccd), pa, int(n_ac_cells), int(small_days), wc),
            ctx)
+
+
+def agis_basic_angle(ctx, n_days):
+    """The basic-angle offset of each day from the AL constant terms
+    (eq:DeltaGamma) [rad]."""
+    out = np.empty(int(n_days), np.float64)
+    _check(_lib.agis_basic_angle(ctx, int(n_days), out.ctypes.data_as(_vp), 0), ctx)
+    return out
 
 
 def agis_global_update(ctx):

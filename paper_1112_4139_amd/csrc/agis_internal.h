@@ -293,6 +293,7 @@ int load_geometry(agis_ctx* ctx, const int8_t* ccd, const float* mu, int32_t n_c
                   int32_t n_ac_cells, int32_t small_days, int where);
 void launch_geo_eta(agis_ctx* ctx);
 void launch_geo_solve(agis_ctx* ctx);
+void launch_geo_basic_angle(agis_ctx* ctx, double* out);   // out: device [n_cells / 2]
 void launch_apply_attitude(agis_ctx* ctx);
 void launch_global_solve(agis_ctx* ctx);
 void launch_apply_add(agis_ctx* ctx, int64_t n, double* x, const double* dx);   // x += dx

@@ -668,6 +668,24 @@ extern "C" int agis_get_geo_calibration(agis_ctx_t* ctx, int64_t n, double* c, i
     return copy_out(ctx, c, ctx->geo, n * sizeof(double), where);
 }
 
+extern "C" int agis_basic_angle(agis_ctx_t* ctx, int64_t n_days, double* out, int where) {
+    CHECK_CTX();
+    REQUIRE_LOADED();
+    if (where != AGIS_HOST && where != AGIS_DEVICE) return set_error(ctx, AGIS_E_INVALID_ARG, "bad 'where'");
+    if (ctx->geo_ccds <= 0) return set_error(ctx, AGIS_E_STATE, "agis_load_geometry first");
+    if (n_days != ctx->n_cells / 2 || (!out && n_days > 0)) return set_error(ctx, AGIS_E_SHAPE, "day count mismatch");
+    if (n_days == 0) return AGIS_OK;
+    double* dst = out;
+    if (where == AGIS_HOST) HIPCHK(hipMalloc((void**)&dst, n_days * sizeof(double)));
+    launch_geo_basic_angle(ctx, dst);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && where == AGIS_HOST)
+        e = hipMemcpyAsync(out, dst, n_days * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (where == AGIS_HOST) (void)hipFree(dst);
+    return e == hipSuccess ? AGIS_OK : hip_check(ctx, e, "basic angle");
+}
+
 extern "C" int agis_get_calibration(agis_ctx_t* ctx, int64_t n, double* c, int where) {
     CHECK_CTX();
     REQUIRE_LOADED();

@@ -654,6 +654,22 @@ __global__ __launch_bounds__(DG_NT) void k_dg_block(int32_t n_ccd, int32_t days,
     }
 }
 
+// The basic-angle offset of each short interval (day) j (Sect. 3.4,
+// eq:DeltaGamma): the mean over the n_ccd AF CCDs of the preceding field of
+// view's AL constant term minus the following one's, (1/n_ccd) sum_n sum_f
+// f c_0(f, n, j), f = +1 preceding (cell 2j), -1 following (cell 2j + 1);
+// the CCDs summed in order.
+__global__ void k_geo_basic_angle(int64_t n_days, int32_t n_ccd, const double* __restrict__ geo,
+                                  double* __restrict__ out) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n_days;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int32_t n = 0; n < n_ccd; ++n)
+            s += geo[3 * ((2 * j) * n_ccd + n)] - geo[3 * ((2 * j + 1) * n_ccd + n)];
+        out[j] = s / (double)n_ccd;
+    }
+}
+
 inline unsigned grid_for(int64_t n) {
     const int64_t b = (n + 255) / 256;
     return (unsigned)(b < 1 ? 1 : (b > 65536 ? 65536 : b));
@@ -683,6 +699,12 @@ void launch_geo_eta(agis_ctx* ctx) {
     k_geo_eta<<<grid_for(ctx->n_obs), 256, 0, ctx->stream>>>(ctx->n_obs, ctx->s_eta0, ctx->s_geo_g, ctx->s_geo_mu,
                                                              ctx->geo, n_al, ctx->geo_ccds, ctx->geo_small_days,
                                                              small, ctx->s_eta);
+}
+
+void launch_geo_basic_angle(agis_ctx* ctx, double* out) {
+    const int64_t n_days = ctx->n_cells / 2;
+    if (ctx->geo_ccds <= 0 || n_days == 0) return;
+    k_geo_basic_angle<<<grid_for(n_days), 256, 0, ctx->stream>>>(n_days, ctx->geo_ccds, ctx->geo, out);
 }
 
 void launch_geo_solve(agis_ctx* ctx) {

@@ -15,6 +15,8 @@ worlds with the along-scan term alone and with both terms.
 * The graph-replayed iteration is bitwise the eager one, and device-memory
   inputs give the same residuals as host ones, bit for bit.
 * The calls it refuses, and a bad CCD index or coordinate.
+* The basic-angle monitor (eq:DeltaGamma) after a change of the basic
+  angle in the observations.
 """
 import numpy as np
 import pytest
@@ -173,4 +175,35 @@ def test_geo_refusals(agis_mod, oracle_lib, small9_geo):
     plain.set_state(c=np.zeros(w.n_cells), geo=np.zeros_like(pr.geo))
     R = agis_mod.agis_residuals(ctx)
     assert np.abs(R - np.asarray(plain.observe()["R"])).max() < 1e-15
+    agis_mod.agis_destroy(ctx)
+
+
+def test_basic_angle_monitor(agis_mod, oracle_lib):
+    """eq:DeltaGamma through the C ABI: observations made with the basic angle
+    Gamma_c + 1 mas, one C update by the library at the truth: the library's
+    monitor equals the oracle's formula applied to the library's own
+    coefficients (to rounding), and it moved by +1 mas on every day (to 1e-6,
+    as the oracle's pin)."""
+    import copy
+    w = C.make("small9", geo_cal=True, noise=False)
+    delta = 1.0 * synth.MAS
+    wd = copy.copy(w)
+    wd.consts = dict(w.consts, gamma_c=w.consts["gamma_c"] + delta)
+    eta = oracle_lib.observed_field_angles(wd)
+    pr = oracle_lib.problem_from_world(w, eta, state="true")
+    ctx = _ctx(agis_mod, w, eta, pr)
+    n_days, n_ccd = w.n_cells // 2, int(w.consts["geo_ccds"])
+    before = agis_mod.agis_basic_angle(ctx, n_days)
+    agis_mod.agis_calibration_update(ctx)
+    after = agis_mod.agis_basic_angle(ctx, n_days)
+    G = agis_mod.agis_get_geo_calibration(ctx, pr.geo.size)
+    ref = oracle_lib.basic_angle(G, w.n_cells, n_ccd)
+    print(f"monitor vs the formula on the library's coefficients: max diff {np.abs(after - ref).max():.2e} rad; "
+          f"moved by {np.mean(after - before) / synth.MAS:.9f} mas")
+    assert np.abs(after - ref).max() <= 1e-15 * max(np.abs(ref).max(), 1e-30)
+    seen = np.bincount(w.cell[w.cell >= 0] // 2, minlength=n_days) > 0
+    assert np.allclose((after - before)[seen], delta, rtol=1e-6, atol=0)
+    with pytest.raises(agis_mod.AgisError) as e:
+        agis_mod.agis_basic_angle(ctx, n_days + 1)
+    assert e.value.code == -2
     agis_mod.agis_destroy(ctx)

@@ -231,3 +231,32 @@ def test_iterations_recover_both_terms(oracle_lib):
     print("RMS error [uas], AL and AC terms (r = 0, 1, 2): start\n", np.round(e0, 2), "\nafter 20\n", np.round(e1, 3))
     live = e0 > 0
     assert np.all(e1[live] < 0.05 * e0[live]) and np.all(e1[~live] < 1e-9)
+
+
+def test_basic_angle_monitor_recovers_a_basic_angle_change(oracle_lib):
+    """eq:DeltaGamma: observations made with the basic angle Gamma_c + delta
+    (the true lines of sight further apart by delta), solved with the model's
+    conventional Gamma_c, sources and attitude at the truth and no noise: the
+    C update absorbs the change into the AL constant terms with opposite
+    signs in the two fields of view, and the monitored offset of every day
+    moves by +delta (the offset of the actual basic angle from Gamma_c), to
+    1e-6 of delta and the same on every day (the sign and the normalisation
+    are what this pins; the model's field angles are not exactly linear in
+    the basic angle, which leaves ~6e-9 of delta)."""
+    import copy
+    w = C.make("small9", geo_cal=True, noise=False)
+    delta = 1.0 * MAS
+    wd = copy.copy(w)
+    wd.consts = dict(w.consts, gamma_c=w.consts["gamma_c"] + delta)
+    eta = oracle_lib.observed_field_angles(wd)
+    pr = oracle_lib.problem_from_world(w, eta, state="true")
+    n_ccd = int(w.consts["geo_ccds"])
+    before = oracle_lib.basic_angle(pr.geo, w.n_cells, n_ccd)
+    pr.calibration_update()
+    moved = oracle_lib.basic_angle(pr.geo, w.n_cells, n_ccd) - before
+    seen = np.bincount(w.cell[w.cell >= 0] // 2, minlength=w.n_cells // 2) > 0
+    print(f"basic-angle offset moved by {moved[seen].mean() / MAS:.9f} mas (delta 1 mas), "
+          f"spread {np.ptp(moved[seen]) / UAS:.2e} uas over {seen.sum()} days")
+    assert np.allclose(moved[seen], delta, rtol=1e-6, atol=0)
+    assert np.ptp(moved[seen]) < 1e-9 * delta
+    assert np.all(moved[~seen] == 0.0)
