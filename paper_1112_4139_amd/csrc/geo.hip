@@ -352,10 +352,14 @@ constexpr int DG_NP_MAX = 186;      // with the three polynomials and the right-
 
 __host__ __device__ constexpr int dg_np(int ne) { return ((ne + 4 + DG_T - 1) / DG_T) * DG_T; }
 __host__ __device__ constexpr int64_t dg_packed(int np) { return (int64_t)np * (np + 1) / 2; }
-// dynamic LDS of the block solve: the packed matrix, then 3 Ne + 16 values
+// dynamic LDS of the block solve: the packed matrix, then the cells' right-hand
+// side and activity (2 Ne values) and 15 small values
 __host__ __device__ constexpr size_t dg_lds_bytes(int ne) {
-    return (size_t)(dg_packed(dg_np(ne)) + 3 * ne + 16) * sizeof(double);
+    return (size_t)(dg_packed(dg_np(ne)) + 2 * ne + 16) * sizeof(double);
 }
+static_assert(dg_np(DG_NE_MAX) == DG_NP_MAX, "the padded size of the largest block");
+static_assert((DG_NP_MAX / DG_T) * (DG_NP_MAX / DG_T + 1) / 2 <= DG_NT, "one tile of the lower triangle per thread");
+static_assert(DG_NT / DG_NP_MAX >= 2, "at least two staged vectors at a time (the prefetch count assumes it)");
 __device__ __forceinline__ int64_t pk(int i, int j) { return (int64_t)i * (i + 1) / 2 + j; }   // i >= j
 constexpr int DG_SPAN = 256;                                    // columns of an accumulation part
 constexpr int DG_PARTS = (DG_COLS + DG_SPAN - 1) / DG_SPAN;     // accumulation parts per block
@@ -476,9 +480,7 @@ __global__ __launch_bounds__(DG_NT) void k_dg_block(int32_t n_ccd, int32_t days,
     double* Z = lds;                                  // packed lower triangle, np x np
     double* ex = lds + dg_packed(np);                 // the cells' right-hand side, then solution [ne]
     double* act = ex + ne;                            // 1: the cell of row i has records [ne]
-    double* gw = act + ne;                            // spare [ne]
-    double* hs = gw + ne;                             // H^-1 [9], w = H^-1 C'D^-1 b [3], nu [3]
-    (void)gw;
+    double* hs = act + ne;                            // H^-1 [9], w = H^-1 C'D^-1 b [3], nu [3]
     const double* dc = dcol + 4 * blk * DG_COLS;
     // --- Z = sum_m z_m z_m' from the partial sums of k_dg_accum, in order
     for (int64_t e = tid; e < dg_packed(np); e += DG_NT) {
