@@ -21,6 +21,7 @@ library with the oracle, through the C ABI, on the 60-day nine-CCD world
 * The arguments it refuses.
 * With the Sun's light deflection and the global block too: two S[ACG]
   iterations on the same world, g0 included.
+* A mixed-precision context's C update equals the FP64 context's.
 """
 import numpy as np
 import pytest
@@ -197,3 +198,30 @@ def test_small_with_global_block_parity(agis_mod, oracle_lib):
     check_floor("geometric terms with S[ACG]: coefficients", X[2][:-1], O[2][:-1], G[2], tol[2][:-1], 2)
     check_g0("geometric terms with S[ACG]: g0", float(X[2][-1]), float(O[2][-1]), g0, float(tol[2][-1]))
     agis_mod.agis_destroy(ctx)
+
+
+def test_small_calibration_update_mixed_precision(agis_mod, oracle_lib):
+    """The mixed-precision mode forms the attitude sums of the A/C pass in
+    FP32 and keeps the model and the calibration's weights in FP64: one C
+    update with all three geometric terms in a mixed context equals the FP64
+    context's to rounding (1e-6 uas; the FP64 path itself is held to the
+    oracle by the tests above)."""
+    w = C.make("geo9", geo_small=True, ac_obs=True, geo_ac=True)
+    eta = oracle_lib.observed_field_angles(w)
+    pr = oracle_lib.problem_from_world(w, eta, state="start")
+    out = []
+    for prec in (agis_mod.AGIS_FP64, agis_mod.AGIS_MIXED):
+        ctx = agis_mod.agis_create(w.consts, w.knots, precision=prec)
+        agis_mod.agis_load_observations(ctx, w.t, eta, w.sigma, w.src, w.fov, w.cell, w.src_true.shape[0],
+                                        w.n_cells)
+        agis_mod.agis_load_geometry(ctx, w.ccd, w.mu, int(w.consts["geo_ccds"]), w.ac_cell,
+                                    int(w.consts["geo_ac_cells"]), small_days=int(w.consts["geo_small_days"]))
+        agis_mod.agis_set_sources(ctx, pr.s)
+        agis_mod.agis_set_attitude(ctx, pr.a)
+        agis_mod.agis_set_geo_calibration(ctx, pr.geo)
+        agis_mod.agis_calibration_update(ctx)
+        out.append(agis_mod.agis_get_geo_calibration(ctx, pr.geo.size))
+        agis_mod.agis_destroy(ctx)
+    d = np.abs(out[1] - out[0]).max() / synth.UAS
+    print(f"geometric C update, mixed vs FP64 context: max diff {d:.2e} uas")
+    assert d < 1e-6
